@@ -1,0 +1,109 @@
+"""Pins of the oracle's TR-BDF2 stepper against mathematics.
+
+* the scalar TR-BDF2 map of eq. trbdf2 is second order and L-stable with
+  gamma = 2 - sqrt(2) (the properties the paper states for it);
+* the full projection step converges at second order in time in the
+  Stokes regime (tiny amplitude, so the nonlinear terms vanish);
+* the full step converges in space to the exact Taylor-Green vortex;
+* the periodic Helmholtz step preserves the pressure mean exactly.
+"""
+import math
+
+import numpy as np
+import pytest
+
+import synthetic
+from oracle import BoxMesh, Discretization, TRBDF2, trbdf2_constants, trbdf2_scalar_step
+
+
+def test_scalar_trbdf2_order_and_l_stability():
+    errs = []
+    for z in (0.1, 0.05, 0.025):
+        errs.append(abs(trbdf2_scalar_step(z, 1.0, 1.0) - math.exp(z)))
+    # local error O(z^3): halving z divides it by ~8
+    assert 7.0 < errs[0] / errs[1] < 9.0 and 7.0 < errs[1] / errs[2] < 9.0
+    # L-stability: R(z) -> 0 as z -> -infinity, |R| <= 1 on the negative axis
+    assert abs(trbdf2_scalar_step(-1e12, 1.0, 1.0)) < 1e-10
+    for z in -np.logspace(-3, 6, 50):
+        assert abs(trbdf2_scalar_step(z, 1.0, 1.0)) <= 1.0
+    # A-stability along the imaginary axis
+    for y in np.logspace(-3, 4, 40):
+        assert abs(trbdf2_scalar_step(1j * y, 1.0, 1.0)) <= 1.0 + 1e-14
+
+
+def test_constants_consistency():
+    c = trbdf2_constants()
+    assert abs(c["gamma"] - (2 - math.sqrt(2))) < 1e-16
+    # stage-2 weights integrate a constant exactly
+    assert abs(c["a31"] + c["a32"] + c["a33"] - 1.0) < 1e-15
+    # both extrapolations reproduce constants
+    for e in (c["extrap1"], c["extrap2"]):
+        assert abs(e[0] + e[1] - 1.0) < 1e-15
+
+
+def _tg_run(N, k, nu, dt, nst, amp=1.0):
+    mesh = BoxMesh(2, (N, N), (0.0, 0.0), (1.0, 1.0), (True, True))
+    d = Discretization(mesh, k, nu=nu)
+    ts = TRBDF2(d, dt)
+    g = ts.cst["gamma"]
+    xu = d.node_coords("u")
+    xp = d.node_coords("p")
+    u = amp * synthetic.nodal_velocity(synthetic.taylor_green_2d_unit(xu, 0.0, nu)[0], 2, d.nbu)
+    hist = amp * synthetic.nodal_velocity(synthetic.taylor_green_2d_unit(xu, -(1 - g) * dt, nu)[0], 2, d.nbu)
+    p = amp * amp * synthetic.taylor_green_2d_unit(xp, 0.0, nu)[1]
+    t = 0.0
+    means = []
+    for _ in range(nst):
+        pm = float(ts.Mp.diagonal() @ p)
+        u, hist, p, _st = ts.step(u, hist, p, t)
+        means.append((pm, float(ts.Mp.diagonal() @ p)))
+        t += dt
+    return d, u, p, t, means
+
+
+def _shear_run(nst, T, nu=0.05):
+    """u = (sin 2 pi y, 0): discretely divergence free and free of advection,
+    so the projection step is exact and the stages reduce to TR-BDF2 for
+    the SIP heat equation; the exact decay is exp(-4 pi^2 nu t).
+
+    The explicit diffusion of the stage right-hand sides carries no penalty
+    (eq. rhs1), so it differs from the implicit SIP operator by terms in the
+    inter-element jumps; degree 4 keeps those jumps far below the time error
+    so that the order of the stage weights is visible."""
+    mesh = BoxMesh(2, (4, 4), (0.0, 0.0), (1.0, 1.0), (True, True))
+    d = Discretization(mesh, 4, nu=nu)
+    dt = T / nst
+    ts = TRBDF2(d, dt)
+    g = ts.cst["gamma"]
+    xu = d.node_coords("u")
+    def field(t):
+        v = np.stack([np.sin(2 * math.pi * xu[:, 1]), 0 * xu[:, 0]], 1) * math.exp(-4 * math.pi ** 2 * nu * t)
+        return synthetic.nodal_velocity(v, 2, d.nbu)
+    u, hist, p = field(0.0), field(-(1 - g) * dt), np.zeros(d.N_p)
+    t = 0.0
+    for _ in range(nst):
+        u, hist, p, _st = ts.step(u, hist, p, t)
+        t += dt
+    return u, p
+
+
+def test_shear_flow_second_order_in_time():
+    T = 0.4
+    sols = {n: _shear_run(n, T) for n in (4, 8, 16, 128)}
+    for n in sols:
+        assert np.ptp(sols[n][1]) < 1e-10          # no pressure gradient is generated
+    e = [np.linalg.norm(sols[n][0] - sols[128][0]) for n in (4, 8, 16)]
+    assert 3.5 < e[0] / e[1] < 4.6 and 3.5 < e[1] / e[2] < 4.6, e
+
+
+@pytest.mark.slow
+def test_taylor_green_space_convergence_and_mean():
+    nu = 0.01
+    errs = []
+    for N in (4, 8):
+        d, u, p, t, means = _tg_run(N, 3, nu, 0.002, 10)
+        eu, ru = d.l2_error(u, lambda x: synthetic.taylor_green_2d_unit(x, t, nu)[0])
+        errs.append(eu / ru)
+        for before, after in means:
+            assert abs(after - before) < 1e-12
+    assert errs[1] < 5e-3 and errs[0] / errs[1] > 6.0, errs
