@@ -1,0 +1,208 @@
+/*
+ * trbdg — matrix-free DG operators, stage solvers and the TR-BDF2 projection
+ * step of Orlando, Della Rocca, Barbante, Bonaventura, Parolini,
+ * "An efficient and accurate implicit DG solver for the incompressible
+ * Navier-Stokes equations" (arXiv 2107.07776), for AMD Instinct MI355X
+ * (gfx950).
+ *
+ * Conventions shared by every entry point
+ * ---------------------------------------
+ *  - Every array argument is a DEVICE pointer to contiguous float64 data,
+ *    owned by the caller, unless stated otherwise.  The library never frees
+ *    caller memory.  Input and output arrays of one call must not overlap
+ *    unless the call says so.
+ *  - Work is enqueued on the context's HIP stream and is asynchronous with
+ *    respect to the host unless stated otherwise (the solvers and the step
+ *    synchronise the stream to read their convergence scalars).
+ *  - Layouts: a velocity field is [cell][component][node] (N_u = dim *
+ *    N_cells * (k+1)^dim values); a scalar velocity-space field such as the
+ *    momentum diagonal is [cell][node]; a pressure field is [cell][node]
+ *    (N_p = N_cells * k^dim values).  Cells are numbered lexicographically
+ *    with x fastest; nodes are the tensor-product Gauss-Legendre points of
+ *    the reference cell, lexicographic with x fastest.
+ *  - Velocity space: Q_k per component, Lagrange basis at the k+1
+ *    Gauss-Legendre points, k+1 point Gauss quadrature (collocated, so the
+ *    velocity mass matrix is diagonal).  Pressure: Q_{k-1}, Lagrange at the
+ *    k Gauss points, k point quadrature in the pressure-only forms; forms
+ *    coupling velocity and pressure use the velocity quadrature (Sec. 3).
+ *  - Stage index s: 1 = TR stage (beta = gamma, theta = 1/2), 2 = BDF2-like
+ *    stage (beta = 1 - gamma, theta = a33 = 1/(2 - gamma)), eq. trbdf2.
+ *  - No exception or abort crosses this interface.  Every call returns a
+ *    tbdg_status; on failure a message is available from tbdg_last_error.
+ */
+#ifndef TRBDG_H
+#define TRBDG_H
+
+#include <stdint.h>
+
+#if defined(__GNUC__) || defined(__clang__)
+#define TBDG_API __attribute__((visibility("default")))
+#else
+#define TBDG_API
+#endif
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+    TBDG_OK = 0,
+    TBDG_EINVAL = -1,        /* invalid argument, descriptor or null pointer   */
+    TBDG_EDEVICE = -2,       /* a HIP runtime call failed                       */
+    TBDG_ENOMEM = -3,        /* device allocation failed                        */
+    TBDG_ENOTCONV = -4,      /* Krylov solver reached maxiter above tolerance   */
+    TBDG_EBREAKDOWN = -5,    /* Krylov breakdown (zero or negative curvature)   */
+    TBDG_ENAN = -6,          /* a non-finite residual was detected              */
+    TBDG_EUNSUPPORTED = -7   /* valid request outside what this build supports  */
+} tbdg_status;
+
+typedef struct tbdg_ctx tbdg_ctx;
+
+/* Structured box mesh T_h (Sec. 3).  dim 2 or 3; n_cells[a] >= 1;
+ * lo < hi per direction; periodic[a] != 0 wraps direction a.  mapping 0 is
+ * the affine box; other mappings are reserved (TBDG_EUNSUPPORTED).          */
+typedef struct {
+    int dim;
+    int n_cells[3];
+    double lo[3], hi[3];
+    int periodic[3];
+    int mapping;
+    double map_amp;
+} tbdg_mesh_desc;
+
+/* Discretisation parameters.  k_u: velocity degree k >= 1 (pressure k-1);
+ * supported: dim 2 with k <= 5, dim 3 with k <= 3.  nu = 1/Re.  c: the
+ * artificial sound speed of eq. ns_artcomp (> 0).  dt > 0.  gamma: 0 selects
+ * 2 - sqrt(2).  pen_u, pen_p: multipliers of the SIP penalties
+ * sigma^u = (k+1)^2 |Gamma|/|K| and sigma^p = k^2 |Gamma|/|K| (eq. penconst1
+ * and its pressure analogue, with diam(Gamma)/diam(K) read as the ratio of
+ * face to cell measure); 0 selects 1.                                      */
+typedef struct {
+    int k_u;
+    double nu, c, dt, gamma;
+    double pen_u, pen_p;
+} tbdg_disc_desc;
+
+/* Create a context: validates the descriptors, builds the 1D Gauss tables,
+ * the neighbour structure and the operator diagonals that do not depend on
+ * the advecting field, and allocates all solver workspaces.  hip_stream is
+ * a hipStream_t (NULL: the default stream).  On success *out owns the
+ * device memory until tbdg_destroy.  On failure *out is NULL.                */
+TBDG_API tbdg_status tbdg_create(const tbdg_mesh_desc* mesh, const tbdg_disc_desc* disc,
+                        void* hip_stream, tbdg_ctx** out);
+TBDG_API void tbdg_destroy(tbdg_ctx* ctx);
+TBDG_API const char* tbdg_last_error(const tbdg_ctx* ctx);
+TBDG_API tbdg_status tbdg_set_stream(tbdg_ctx* ctx, void* hip_stream);
+
+/* Host outputs: total velocity DoFs (all components), pressure DoFs, cells. */
+TBDG_API tbdg_status tbdg_sizes(const tbdg_ctx* ctx, int64_t* n_u, int64_t* n_p, int64_t* n_cells);
+
+/* Physical node coordinates, field 0 = velocity nodes, 1 = pressure nodes,
+ * written as [cell][node][dim] into a device array of (N_cells * nodes) * dim. */
+TBDG_API tbdg_status tbdg_node_coords(const tbdg_ctx* ctx, int field, double* xyz);
+
+/* Advecting velocity of stage s (Sec. 2 after eq. first_stage and
+ * eq. second_stage): w = e0 u_new + e1 u_old with (e0, e1) =
+ * (1 + gamma/(2(1-gamma)), -gamma/(2(1-gamma))) for s = 1 (u_new = u^n,
+ * u_old = u^{n-1+gamma}) and (1 + (1-gamma)/gamma, -(1-gamma)/gamma) for
+ * s = 2 (u_new = u^{n+gamma}, u_old = u^n).  All arrays N_u.                */
+TBDG_API tbdg_status tbdg_extrapolate(tbdg_ctx* ctx, int stage, const double* u_new,
+                             const double* u_old, double* w);
+
+/* Momentum operator of stage s applied to u (algebraic systems at the end of
+ * Sec. 3): y = m_s M u + theta_s (nu A u + C(w) u), with A the SIP form of
+ * eq. bilin_diff and C(w) the local Lax-Friedrichs form of eq. trilinear,
+ * applied to each component.  w, u, y: N_u.                                 */
+TBDG_API tbdg_status tbdg_apply_momentum(tbdg_ctx* ctx, int stage, const double* w,
+                                const double* u, double* y);
+
+/* Pressure Helmholtz operator of stage s: y = alpha_s M^p p + K p with
+ * alpha_s = 1/(c^2 beta_s^2 dt^2) and K the SIP form a_p.  p, y: N_p.       */
+TBDG_API tbdg_status tbdg_apply_pressure(tbdg_ctx* ctx, int stage, const double* p, double* y);
+
+/* Exact diagonals (Jacobi preconditioners).  Momentum: diag is N_u/dim in
+ * the [cell][node] layout, identical for every component.  Pressure: N_p.   */
+TBDG_API tbdg_status tbdg_diag_momentum(tbdg_ctx* ctx, int stage, const double* w, double* diag);
+TBDG_API tbdg_status tbdg_diag_pressure(tbdg_ctx* ctx, int stage, double* diag);
+
+/* Right-hand side of the momentum predictor: rhs = m_s M u_prev + F_u^(s)
+ * (eq. rhs1 for s = 1 with u_prev = u_n and advecting field w; the stage-2
+ * functional for s = 2 with u_prev = u_g = u^{n+gamma}, which uses
+ * u_g (x) u_g and u_n (x) u_n in the explicit advection).  p_prev is p^n
+ * (s = 1) or p^{n+gamma} (s = 2).  u_g may be NULL for s = 1.               */
+TBDG_API tbdg_status tbdg_rhs_momentum(tbdg_ctx* ctx, int stage, const double* u_n,
+                              const double* u_g, const double* w,
+                              const double* p_prev, double* rhs);
+
+/* gu = M^{-1} P p: the broken pressure gradient projected into V_h (end of
+ * Sec. 3); with collocated quadrature it is grad p at the velocity nodes.
+ * p: N_p, gu: N_u.                                                         */
+TBDG_API tbdg_status tbdg_grad_p(tbdg_ctx* ctx, const double* p, double* gu);
+
+/* y = x + a * M^{-1} P p (velocity update of the projection, Sec. 3); y may
+ * alias x.                                                                 */
+TBDG_API tbdg_status tbdg_add_grad_p(tbdg_ctx* ctx, const double* x, double a,
+                            const double* p, double* y);
+
+/* Helmholtz right-hand side: rhs = alpha_s M^p p_prev + F_p^(s)(u_ss) with
+ * F_p(q) = (1/(beta_s dt)) [ sum_K int u_ss . grad q - sum_E int {{u_ss}}.[[q]] ].
+ * u_ss: N_u, p_prev, rhs: N_p.                                             */
+TBDG_API tbdg_status tbdg_rhs_pressure(tbdg_ctx* ctx, int stage, const double* u_ss,
+                              const double* p_prev, double* rhs);
+
+/* Krylov options.  tol: relative true residual ||b - A x||_2 <= tol ||b||_2.
+ * maxiter: total iterations (GMRES: over all restarts).  restart: GMRES
+ * basis size m (<= 60).  precond: 0 = Jacobi.  guess: 0 = use the content
+ * of x_inout.                                                              */
+typedef struct {
+    double tol;
+    int maxiter;
+    int restart;
+    int precond;
+    int guess;
+} tbdg_solver_opts;
+
+typedef struct {
+    int iters;
+    double res0;        /* ||b - A x0||_2 / ||b||_2                          */
+    double res_final;   /* ||b - A x||_2 / ||b||_2, recomputed at the end    */
+    int guess_used;
+} tbdg_solve_info;
+
+/* Momentum predictor solve (right-preconditioned restarted GMRES with CGS2
+ * orthogonalisation, Jacobi preconditioner, all components in one Krylov
+ * space): V_s(w) u = rhs.  u_inout: initial guess in, solution out (the
+ * best iterate is written even when the solve fails).                      */
+TBDG_API tbdg_status tbdg_solve_momentum(tbdg_ctx* ctx, int stage, const double* w,
+                                const double* rhs, double* u_inout,
+                                const tbdg_solver_opts* opts, tbdg_solve_info* info);
+
+/* Helmholtz solve (Jacobi-preconditioned CG): (alpha_s M^p + K) p = rhs.     */
+TBDG_API tbdg_status tbdg_solve_pressure(tbdg_ctx* ctx, int stage, const double* rhs,
+                                double* p_inout, const tbdg_solver_opts* opts,
+                                tbdg_solve_info* info);
+
+/* TR-BDF2 state: u = u^n, u_hist = u^{n-1+gamma} (history level of the
+ * stage-1 extrapolation), p = p^n; t and n are host values.                 */
+typedef struct {
+    double* u;
+    double* u_hist;
+    double* p;
+    double t;
+    int64_t n;
+} tbdg_state;
+
+/* One TR-BDF2 projection step (Sec. 2 and the algebraic form of Sec. 3):
+ * per stage, extrapolate, momentum right-hand side, GMRES, projection,
+ * Helmholtz right-hand side, CG, velocity correction.  info[0..3] receive
+ * the momentum and pressure solves of stages 1 and 2.  The state is updated
+ * only when all four solves succeed; otherwise it is left untouched and the
+ * first failing status is returned.                                        */
+TBDG_API tbdg_status tbdg_step(tbdg_ctx* ctx, tbdg_state* state, const tbdg_solver_opts* mom,
+                      const tbdg_solver_opts* prs, tbdg_solve_info info[4]);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* TRBDG_H */

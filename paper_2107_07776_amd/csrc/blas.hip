@@ -1,0 +1,279 @@
+// Vector kernels and deterministic reductions for the Krylov solvers.
+//
+// Reductions are two-pass: a fixed grid of work-groups writes one partial sum
+// each (wave64 shuffles, then LDS across the four waves), and a single
+// work-group adds the partials in a fixed order.  The grid size does not
+// depend on timing, so results are bitwise reproducible run to run.
+#include "internal.hpp"
+
+namespace trbdg {
+namespace {
+
+constexpr int BS = 256;
+
+inline unsigned grid_for(int64_t n) {
+    int64_t g = (n + BS - 1) / BS;
+    if (g < 1) g = 1;
+    if (g > 65535) g = 65535;
+    return (unsigned)g;
+}
+
+__device__ inline double wave_sum(double v) {
+    for (int off = 32; off > 0; off >>= 1) v += __shfl_down(v, off, 64);
+    return v;
+}
+
+// Block-wide sum; valid in thread 0.
+__device__ inline double block_sum(double v) {
+    __shared__ double s_part[BS / 64];
+    v = wave_sum(v);
+    const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+    if (lane == 0) s_part[wv] = v;
+    __syncthreads();
+    double r = 0.0;
+    if (threadIdx.x == 0)
+        for (int i = 0; i < BS / 64; ++i) r += s_part[i];
+    __syncthreads();
+    return r;
+}
+
+__global__ __launch_bounds__(BS) void k_axpby(int64_t n, double a, const double* x, double b,
+                                              const double* y, double* out) {
+    for (int64_t i = (int64_t)blockIdx.x * BS + threadIdx.x; i < n; i += (int64_t)gridDim.x * BS)
+        out[i] = a * x[i] + (y ? b * y[i] : 0.0);
+}
+
+__global__ __launch_bounds__(BS) void k_div(int64_t n, const double* x, const double* d,
+                                            double* out) {
+    for (int64_t i = (int64_t)blockIdx.x * BS + threadIdx.x; i < n; i += (int64_t)gridDim.x * BS)
+        out[i] = x[i] / d[i];
+}
+
+__device__ inline int64_t diag_index(int64_t i, int dim, int64_t nb) {
+    return (i / (dim * nb)) * nb + (i % nb);
+}
+
+__global__ __launch_bounds__(BS) void k_div_diag_u(int64_t n, int dim, int64_t nb,
+                                                   const double* x, const double* d,
+                                                   double* out) {
+    for (int64_t i = (int64_t)blockIdx.x * BS + threadIdx.x; i < n; i += (int64_t)gridDim.x * BS)
+        out[i] = x[i] / d[diag_index(i, dim, nb)];
+}
+
+__global__ __launch_bounds__(BS) void k_add_div_diag_u(int64_t n, int dim, int64_t nb,
+                                                       const double* gz, const double* d,
+                                                       double* x) {
+    for (int64_t i = (int64_t)blockIdx.x * BS + threadIdx.x; i < n; i += (int64_t)gridDim.x * BS)
+        x[i] += gz[i] / d[diag_index(i, dim, nb)];
+}
+
+// partial[j * G + b] = sum over block b's slice of V_j . w
+__global__ __launch_bounds__(BS) void k_dot_many(int64_t n, const double* V, int64_t ldv,
+                                                 const double* w, double* partial) {
+    const int j = blockIdx.y;
+    const double* v = V + (int64_t)j * ldv;
+    double acc = 0.0;
+    for (int64_t i = (int64_t)blockIdx.x * BS + threadIdx.x; i < n; i += (int64_t)gridDim.x * BS)
+        acc += v[i] * w[i];
+    acc = block_sum(acc);
+    if (threadIdx.x == 0) partial[(int64_t)j * gridDim.x + blockIdx.x] = acc;
+}
+
+// out[j] = sum_b partial[j * G + b]
+__global__ __launch_bounds__(BS) void k_finish(const double* partial, int G, double* out) {
+    const int j = blockIdx.x;
+    double acc = 0.0;
+    for (int b = threadIdx.x; b < G; b += BS) acc += partial[(int64_t)j * G + b];
+    acc = block_sum(acc);
+    if (threadIdx.x == 0) out[j] = acc;
+}
+
+__global__ __launch_bounds__(BS) void k_sub_combo(int64_t n, int k, const double* V, int64_t ldv,
+                                                  const double* h, double* w) {
+    for (int64_t i = (int64_t)blockIdx.x * BS + threadIdx.x; i < n; i += (int64_t)gridDim.x * BS) {
+        double s = 0.0;
+        for (int j = 0; j < k; ++j) s += h[j] * V[(int64_t)j * ldv + i];
+        w[i] -= s;
+    }
+}
+
+__global__ __launch_bounds__(BS) void k_add_combo(int64_t n, int k, const double* V, int64_t ldv,
+                                                  const double* y, double* x) {
+    for (int64_t i = (int64_t)blockIdx.x * BS + threadIdx.x; i < n; i += (int64_t)gridDim.x * BS) {
+        double s = 0.0;
+        for (int j = 0; j < k; ++j) s += y[j] * V[(int64_t)j * ldv + i];
+        x[i] += s;
+    }
+}
+
+// ---- CG -------------------------------------------------------------------
+// sc: [0] rz, [1] pAp, [2] rr, [3] rz_new, [4] alpha, [5] beta, [6] breakdown
+__global__ void k_cg_alpha_finish(const double* partial, int G, double* sc) {
+    double acc = 0.0;
+    for (int b = threadIdx.x; b < G; b += BS) acc += partial[b];
+    acc = block_sum(acc);
+    if (threadIdx.x == 0) {
+        sc[1] = acc;
+        if (!(acc > 0.0)) {
+            sc[6] = 1.0;
+            sc[4] = 0.0;
+        } else {
+            sc[4] = sc[0] / acc;
+        }
+    }
+}
+
+__global__ __launch_bounds__(BS) void k_cg_update(int64_t n, const double* diag, double* x,
+                                                  double* r, const double* p, const double* q,
+                                                  const double* sc, double* partial) {
+    const double alpha = sc[4];
+    double rz = 0.0, rr = 0.0;
+    for (int64_t i = (int64_t)blockIdx.x * BS + threadIdx.x; i < n; i += (int64_t)gridDim.x * BS) {
+        x[i] += alpha * p[i];
+        const double ri = r[i] - alpha * q[i];
+        r[i] = ri;
+        rz += ri * ri / diag[i];
+        rr += ri * ri;
+    }
+    rz = block_sum(rz);
+    rr = block_sum(rr);
+    if (threadIdx.x == 0) {
+        partial[blockIdx.x] = rz;
+        partial[gridDim.x + blockIdx.x] = rr;
+    }
+}
+
+__global__ void k_cg_beta_finish(const double* partial, int G, double* sc, int first) {
+    double rz = 0.0, rr = 0.0;
+    for (int b = threadIdx.x; b < G; b += BS) {
+        rz += partial[b];
+        rr += partial[G + b];
+    }
+    rz = block_sum(rz);
+    rr = block_sum(rr);
+    if (threadIdx.x == 0) {
+        sc[2] = rr;
+        sc[3] = rz;
+        sc[5] = first ? 0.0 : rz / sc[0];
+        sc[0] = rz;
+    }
+}
+
+__global__ __launch_bounds__(BS) void k_cg_direction(int64_t n, const double* diag,
+                                                     const double* r, double* p,
+                                                     const double* sc) {
+    const double beta = sc[5];
+    for (int64_t i = (int64_t)blockIdx.x * BS + threadIdx.x; i < n; i += (int64_t)gridDim.x * BS)
+        p[i] = r[i] / diag[i] + beta * p[i];
+}
+
+__global__ __launch_bounds__(BS) void k_cg_init_partials(int64_t n, const double* diag,
+                                                         const double* r, double* p,
+                                                         double* partial) {
+    double rz = 0.0, rr = 0.0;
+    for (int64_t i = (int64_t)blockIdx.x * BS + threadIdx.x; i < n; i += (int64_t)gridDim.x * BS) {
+        const double ri = r[i];
+        const double zi = ri / diag[i];
+        p[i] = zi;
+        rz += ri * zi;
+        rr += ri * ri;
+    }
+    rz = block_sum(rz);
+    rr = block_sum(rr);
+    if (threadIdx.x == 0) {
+        partial[blockIdx.x] = rz;
+        partial[gridDim.x + blockIdx.x] = rr;
+    }
+}
+
+}  // namespace
+
+int reduce_grid(int64_t n, int cap) {
+    int64_t g = (n + BS - 1) / BS;
+    if (g > cap) g = cap;
+    if (g < 1) g = 1;
+    return (int)g;
+}
+
+void vec_axpby(hipStream_t s, int64_t n, double a, const double* x, double b, const double* y,
+               double* out) {
+    hipLaunchKernelGGL(k_axpby, dim3(grid_for(n)), dim3(BS), 0, s, n, a, x, b, y, out);
+    TBDG_HIP(hipGetLastError());
+}
+
+void vec_scale_copy(hipStream_t s, int64_t n, double a, const double* x, double* out) {
+    vec_axpby(s, n, a, x, 0.0, nullptr, out);
+}
+
+void vec_div(hipStream_t s, int64_t n, const double* x, const double* d, double* out) {
+    hipLaunchKernelGGL(k_div, dim3(grid_for(n)), dim3(BS), 0, s, n, x, d, out);
+    TBDG_HIP(hipGetLastError());
+}
+
+void vec_div_diag_u(hipStream_t s, int64_t n, int dim, int64_t nb, const double* x,
+                    const double* d, double* out) {
+    hipLaunchKernelGGL(k_div_diag_u, dim3(grid_for(n)), dim3(BS), 0, s, n, dim, nb, x, d, out);
+    TBDG_HIP(hipGetLastError());
+}
+
+void vec_add_div_diag_u(hipStream_t s, int64_t n, int dim, int64_t nb, const double* gz,
+                        const double* d, double* x) {
+    hipLaunchKernelGGL(k_add_div_diag_u, dim3(grid_for(n)), dim3(BS), 0, s, n, dim, nb, gz, d, x);
+    TBDG_HIP(hipGetLastError());
+}
+
+void dot_many(tbdg_ctx* c, int64_t n, int k, const double* V, int64_t ldv, const double* w,
+              double* dev_out) {
+    const int G = reduce_grid(n, c->red_blocks / (k > 0 ? k : 1) < 1024 ? c->red_blocks / (k > 0 ? k : 1) : 1024);
+    hipLaunchKernelGGL(k_dot_many, dim3(G, k), dim3(BS), 0, c->stream, n, V, ldv, w, c->red_part);
+    hipLaunchKernelGGL(k_finish, dim3(k), dim3(BS), 0, c->stream, c->red_part, G, dev_out);
+    TBDG_HIP(hipGetLastError());
+}
+
+void dot2(tbdg_ctx* c, int64_t n, const double* a, const double* b, double* dev_out) {
+    dot_many(c, n, 1, a, 0, b, dev_out);
+}
+
+void vec_sub_combo(hipStream_t s, int64_t n, int k, const double* V, int64_t ldv,
+                   const double* h, double* w) {
+    hipLaunchKernelGGL(k_sub_combo, dim3(grid_for(n)), dim3(BS), 0, s, n, k, V, ldv, h, w);
+    TBDG_HIP(hipGetLastError());
+}
+
+void vec_add_combo(hipStream_t s, int64_t n, int k, const double* V, int64_t ldv,
+                   const double* y, double* x) {
+    hipLaunchKernelGGL(k_add_combo, dim3(grid_for(n)), dim3(BS), 0, s, n, k, V, ldv, y, x);
+    TBDG_HIP(hipGetLastError());
+}
+
+void cg_alpha(tbdg_ctx* c, int64_t n, const double* p, const double* q, double* sc) {
+    const int G = reduce_grid(n, 1024);
+    hipLaunchKernelGGL(k_dot_many, dim3(G, 1), dim3(BS), 0, c->stream, n, p, 0, q, c->red_part);
+    hipLaunchKernelGGL(k_cg_alpha_finish, dim3(1), dim3(BS), 0, c->stream, c->red_part, G, sc);
+    TBDG_HIP(hipGetLastError());
+}
+
+void cg_update(tbdg_ctx* c, int64_t n, const double* diag, double* x, double* r, const double* p,
+               const double* q, double* sc) {
+    const int G = reduce_grid(n, 1024);
+    hipLaunchKernelGGL(k_cg_update, dim3(G), dim3(BS), 0, c->stream, n, diag, x, r, p, q, sc,
+                       c->red_part);
+    hipLaunchKernelGGL(k_cg_beta_finish, dim3(1), dim3(BS), 0, c->stream, c->red_part, G, sc, 0);
+    TBDG_HIP(hipGetLastError());
+}
+
+void cg_direction(hipStream_t s, int64_t n, const double* diag, const double* r, double* p,
+                  const double* sc) {
+    hipLaunchKernelGGL(k_cg_direction, dim3(grid_for(n)), dim3(BS), 0, s, n, diag, r, p, sc);
+    TBDG_HIP(hipGetLastError());
+}
+
+void cg_init(tbdg_ctx* c, int64_t n, const double* diag, const double* r, double* p, double* sc) {
+    const int G = reduce_grid(n, 1024);
+    hipLaunchKernelGGL(k_cg_init_partials, dim3(G), dim3(BS), 0, c->stream, n, diag, r, p,
+                       c->red_part);
+    hipLaunchKernelGGL(k_cg_beta_finish, dim3(1), dim3(BS), 0, c->stream, c->red_part, G, sc, 1);
+    TBDG_HIP(hipGetLastError());
+}
+
+}  // namespace trbdg

@@ -1,0 +1,387 @@
+// extern "C" entry points of libtrbdg: argument validation, context life
+// cycle and translation of C++ errors into status codes.
+#include <cmath>
+#include <cstring>
+#include <new>
+
+#include "internal.hpp"
+
+namespace trbdg {
+void build_tables(tbdg_ctx* c);
+tbdg_status solve_momentum(tbdg_ctx* c, int s, const double* w, const double* b, double* x,
+                           const tbdg_solver_opts& o, tbdg_solve_info* info);
+tbdg_status solve_pressure(tbdg_ctx* c, int s, const double* b, double* x,
+                           const tbdg_solver_opts& o, tbdg_solve_info* info);
+void extrapolate(tbdg_ctx* c, int s, const double* u_new, const double* u_old, double* w);
+void rhs_momentum(tbdg_ctx* c, int s, const double* u_n, const double* u_g, const double* w,
+                  const double* p, double* rhs);
+void rhs_pressure(tbdg_ctx* c, int s, const double* u_ss, const double* p_prev, double* rhs);
+tbdg_status step(tbdg_ctx* c, tbdg_state* S, const tbdg_solver_opts& mo,
+                 const tbdg_solver_opts& po, tbdg_solve_info info[4]);
+}  // namespace trbdg
+
+using trbdg::Error;
+
+namespace {
+
+constexpr int GMRES_MAX = 60;
+
+template <class F>
+tbdg_status guarded(tbdg_ctx* c, F&& f) {
+    try {
+        return f();
+    } catch (const Error& e) {
+        if (c) c->last_error = e.what();
+        return e.status;
+    } catch (const std::bad_alloc&) {
+        if (c) c->last_error = "host allocation failed";
+        return TBDG_ENOMEM;
+    } catch (const std::exception& e) {
+        if (c) c->last_error = e.what();
+        return TBDG_EINVAL;
+    }
+}
+
+void require(bool ok, const char* msg) {
+    if (!ok) throw Error(TBDG_EINVAL, msg);
+}
+
+void check_stage(int s) { require(s == 1 || s == 2, "stage must be 1 or 2"); }
+
+double* dalloc(int64_t n) {
+    void* p = nullptr;
+    const hipError_t e = hipMalloc(&p, sizeof(double) * (size_t)(n > 0 ? n : 1));
+    if (e != hipSuccess) throw Error(TBDG_ENOMEM, std::string("hipMalloc: ") + hipGetErrorString(e));
+    return static_cast<double*>(p);
+}
+
+void dfree(double*& p) {
+    if (p) (void)hipFree(p);
+    p = nullptr;
+}
+
+void free_all(tbdg_ctx* c) {
+    for (auto& d : c->diag_p) dfree(d);
+    dfree(c->diag_u);
+    dfree(c->V);
+    dfree(c->gv);
+    dfree(c->gz);
+    dfree(c->cr);
+    dfree(c->cp);
+    dfree(c->cq);
+    dfree(c->red_part);
+    dfree(c->red_out);
+    if (c->host_out) (void)hipHostFree(c->host_out);
+    c->host_out = nullptr;
+    dfree(c->s_w);
+    dfree(c->s_rhs);
+    dfree(c->s_ustar);
+    dfree(c->s_ug);
+    dfree(c->s_u1);
+    dfree(c->s_pb);
+    dfree(c->s_pg);
+    dfree(c->s_p1);
+    dfree(c->s_pv);
+}
+
+tbdg_solver_opts defaults(const tbdg_solver_opts* o) {
+    tbdg_solver_opts d{1e-8, 1000, 30, 0, 0};
+    if (!o) return d;
+    tbdg_solver_opts r = *o;
+    require(r.tol > 0.0 && std::isfinite(r.tol), "solver tol must be positive");
+    require(r.maxiter > 0, "solver maxiter must be positive");
+    require(r.restart >= 0 && r.restart <= GMRES_MAX, "GMRES restart must be in [0, 60]");
+    require(r.precond == 0, "only the Jacobi preconditioner (0) is available");
+    return r;
+}
+
+}  // namespace
+
+extern "C" {
+
+tbdg_status tbdg_create(const tbdg_mesh_desc* mesh, const tbdg_disc_desc* disc, void* stream,
+                        tbdg_ctx** out) {
+    if (!out) return TBDG_EINVAL;
+    *out = nullptr;
+    if (!mesh || !disc) return TBDG_EINVAL;
+    tbdg_ctx* c = new (std::nothrow) tbdg_ctx();
+    if (!c) return TBDG_ENOMEM;
+    const tbdg_status st = guarded(c, [&]() -> tbdg_status {
+        require(mesh->dim == 2 || mesh->dim == 3, "dim must be 2 or 3");
+        c->dim = mesh->dim;
+        c->Nc = 1;
+        for (int a = 0; a < 3; ++a) {
+            if (a < c->dim) {
+                require(mesh->n_cells[a] >= 1, "n_cells must be >= 1");
+                require(mesh->hi[a] > mesh->lo[a], "hi must exceed lo");
+                c->geom.nc[a] = mesh->n_cells[a];
+                c->geom.h[a] = (mesh->hi[a] - mesh->lo[a]) / mesh->n_cells[a];
+                c->geom.lo[a] = mesh->lo[a];
+                c->periodic_flags[a] = mesh->periodic[a] ? 1 : 0;
+                c->Nc *= mesh->n_cells[a];
+            } else {
+                c->geom.nc[a] = 1;
+                c->geom.h[a] = 1.0;
+                c->geom.lo[a] = 0.0;
+                c->periodic_flags[a] = 1;
+            }
+        }
+        if (mesh->mapping != 0) throw Error(TBDG_EUNSUPPORTED, "only the affine box (mapping 0) is built");
+        for (int a = 0; a < c->dim; ++a)
+            if (!c->periodic_flags[a])
+                throw Error(TBDG_EUNSUPPORTED, "non-periodic (Dirichlet) directions are not built");
+        require(disc->k_u >= 2, "velocity degree k_u must be >= 2");
+        const int kmax = c->dim == 2 ? 5 : 3;
+        if (disc->k_u > kmax) throw Error(TBDG_EUNSUPPORTED, "velocity degree too high for this dim");
+        require(std::isfinite(disc->nu) && disc->nu >= 0.0, "nu must be finite and >= 0");
+        require(disc->c > 0.0, "c must be > 0");
+        require(std::isfinite(disc->dt) && disc->dt > 0.0, "dt must be > 0");
+        require(disc->gamma >= 0.0 && disc->gamma < 1.0, "gamma must be in [0,1)");
+        c->k = disc->k_u;
+        c->n = c->k + 1;
+        c->np = c->k;
+        c->nu = disc->nu;
+        c->c = disc->c;
+        c->dt = disc->dt;
+        c->gamma = disc->gamma > 0.0 ? disc->gamma : 2.0 - std::sqrt(2.0);
+        c->pen_u = disc->pen_u > 0.0 ? disc->pen_u : 1.0;
+        c->pen_p = disc->pen_p > 0.0 ? disc->pen_p : 1.0;
+        const double g = c->gamma;
+        c->a31 = (1.0 - g) / (2.0 * (2.0 - g));
+        c->a32 = c->a31;
+        c->a33 = 1.0 / (2.0 - g);
+        c->beta[1] = g;
+        c->beta[2] = 1.0 - g;
+        c->theta[1] = 0.5;
+        c->theta[2] = c->a33;
+        int64_t nbu = 1, nbp = 1;
+        for (int a = 0; a < c->dim; ++a) {
+            nbu *= c->n;
+            nbp *= c->np;
+        }
+        c->nbu = nbu;
+        c->nbp = nbp;
+        c->Ns = c->Nc * nbu;
+        c->Nu = c->Ns * c->dim;
+        c->Np = c->Nc * nbp;
+        c->geom.vol = 1.0;
+        for (int a = 0; a < c->dim; ++a) c->geom.vol *= c->geom.h[a];
+        // uniform mesh: C = sigma_{Gamma,K} = deg^2 |Gamma| / |K| = deg^2 / h_a
+        for (int a = 0; a < 3; ++a) {
+            c->sig_u[a] = (c->k + 1.0) * (c->k + 1.0) * c->pen_u / c->geom.h[a];
+            c->sig_p[a] = (double)c->k * c->k * c->pen_p / c->geom.h[a];
+        }
+        c->stream = static_cast<hipStream_t>(stream);
+        trbdg::build_tables(c);
+        // workspaces
+        c->gm_m = GMRES_MAX;
+        c->diag_p[1] = dalloc(c->Np);
+        c->diag_p[2] = dalloc(c->Np);
+        c->diag_u = dalloc(c->Ns);
+        c->V = dalloc((int64_t)(c->gm_m + 1) * c->Nu);
+        c->gv = dalloc(c->Nu);
+        c->gz = dalloc(c->Nu);
+        c->cr = dalloc(c->Np);
+        c->cp = dalloc(c->Np);
+        c->cq = dalloc(c->Np);
+        c->red_blocks = 64 * 1024;
+        c->red_part = dalloc(c->red_blocks);
+        c->red_out = dalloc(128);
+        void* h = nullptr;
+        TBDG_HIP(hipHostMalloc(&h, sizeof(double) * 128, hipHostMallocDefault));
+        c->host_out = static_cast<double*>(h);
+        c->s_w = dalloc(c->Nu);
+        c->s_rhs = dalloc(c->Nu);
+        c->s_ustar = dalloc(c->Nu);
+        c->s_ug = dalloc(c->Nu);
+        c->s_u1 = dalloc(c->Nu);
+        c->s_pb = dalloc(c->Np);
+        c->s_pg = dalloc(c->Np);
+        c->s_p1 = dalloc(c->Np);
+        c->s_pv = dalloc(c->Ns);
+        trbdg::launch_diag_pressure(c, c->alpha(1), c->diag_p[1]);
+        trbdg::launch_diag_pressure(c, c->alpha(2), c->diag_p[2]);
+        TBDG_HIP(hipStreamSynchronize(c->stream));
+        return TBDG_OK;
+    });
+    if (st != TBDG_OK) {
+        free_all(c);
+        delete c;
+        return st;
+    }
+    *out = c;
+    return TBDG_OK;
+}
+
+void tbdg_destroy(tbdg_ctx* c) {
+    if (!c) return;
+    (void)hipStreamSynchronize(c->stream);
+    free_all(c);
+    delete c;
+}
+
+const char* tbdg_last_error(const tbdg_ctx* c) {
+    if (!c) return "null context";
+    return c->last_error.c_str();
+}
+
+tbdg_status tbdg_set_stream(tbdg_ctx* c, void* stream) {
+    if (!c) return TBDG_EINVAL;
+    c->stream = static_cast<hipStream_t>(stream);
+    return TBDG_OK;
+}
+
+tbdg_status tbdg_sizes(const tbdg_ctx* c, int64_t* n_u, int64_t* n_p, int64_t* n_cells) {
+    if (!c) return TBDG_EINVAL;
+    if (n_u) *n_u = c->Nu;
+    if (n_p) *n_p = c->Np;
+    if (n_cells) *n_cells = c->Nc;
+    return TBDG_OK;
+}
+
+tbdg_status tbdg_node_coords(const tbdg_ctx* cc, int field, double* xyz) {
+    tbdg_ctx* c = const_cast<tbdg_ctx*>(cc);
+    if (!c) return TBDG_EINVAL;
+    return guarded(c, [&]() {
+        require(field == 0 || field == 1, "field must be 0 (velocity) or 1 (pressure)");
+        require(xyz != nullptr, "null output");
+        trbdg::launch_node_coords(c, field, xyz);
+        return TBDG_OK;
+    });
+}
+
+tbdg_status tbdg_extrapolate(tbdg_ctx* c, int stage, const double* u_new, const double* u_old,
+                             double* w) {
+    if (!c) return TBDG_EINVAL;
+    return guarded(c, [&]() {
+        check_stage(stage);
+        require(u_new && u_old && w, "null pointer");
+        trbdg::extrapolate(c, stage, u_new, u_old, w);
+        return TBDG_OK;
+    });
+}
+
+tbdg_status tbdg_apply_momentum(tbdg_ctx* c, int stage, const double* w, const double* u, double* y) {
+    if (!c) return TBDG_EINVAL;
+    return guarded(c, [&]() {
+        check_stage(stage);
+        require(w && u && y, "null pointer");
+        require(u != y && w != y, "output must not alias an input");
+        trbdg::launch_apply_momentum(c, c->mcoef(stage), c->theta[stage], w, u, y);
+        return TBDG_OK;
+    });
+}
+
+tbdg_status tbdg_apply_pressure(tbdg_ctx* c, int stage, const double* p, double* y) {
+    if (!c) return TBDG_EINVAL;
+    return guarded(c, [&]() {
+        check_stage(stage);
+        require(p && y, "null pointer");
+        require(p != y, "output must not alias the input");
+        trbdg::launch_apply_pressure(c, c->alpha(stage), p, y);
+        return TBDG_OK;
+    });
+}
+
+tbdg_status tbdg_diag_momentum(tbdg_ctx* c, int stage, const double* w, double* diag) {
+    if (!c) return TBDG_EINVAL;
+    return guarded(c, [&]() {
+        check_stage(stage);
+        require(w && diag, "null pointer");
+        trbdg::launch_diag_momentum(c, c->mcoef(stage), c->theta[stage], w, diag);
+        return TBDG_OK;
+    });
+}
+
+tbdg_status tbdg_diag_pressure(tbdg_ctx* c, int stage, double* diag) {
+    if (!c) return TBDG_EINVAL;
+    return guarded(c, [&]() {
+        check_stage(stage);
+        require(diag != nullptr, "null pointer");
+        trbdg::launch_diag_pressure(c, c->alpha(stage), diag);
+        return TBDG_OK;
+    });
+}
+
+tbdg_status tbdg_rhs_momentum(tbdg_ctx* c, int stage, const double* u_n, const double* u_g,
+                              const double* w, const double* p_prev, double* rhs) {
+    if (!c) return TBDG_EINVAL;
+    return guarded(c, [&]() {
+        check_stage(stage);
+        require(u_n && w && p_prev && rhs, "null pointer");
+        require(stage == 1 || u_g != nullptr, "stage 2 needs u_g");
+        trbdg::rhs_momentum(c, stage, u_n, u_g, w, p_prev, rhs);
+        return TBDG_OK;
+    });
+}
+
+tbdg_status tbdg_grad_p(tbdg_ctx* c, const double* p, double* gu) {
+    if (!c) return TBDG_EINVAL;
+    return guarded(c, [&]() {
+        require(p && gu, "null pointer");
+        trbdg::launch_add_grad_p(c, nullptr, 1.0, p, gu);
+        return TBDG_OK;
+    });
+}
+
+tbdg_status tbdg_add_grad_p(tbdg_ctx* c, const double* x, double a, const double* p, double* y) {
+    if (!c) return TBDG_EINVAL;
+    return guarded(c, [&]() {
+        require(x && p && y, "null pointer");
+        trbdg::launch_add_grad_p(c, x, a, p, y);
+        return TBDG_OK;
+    });
+}
+
+tbdg_status tbdg_rhs_pressure(tbdg_ctx* c, int stage, const double* u_ss, const double* p_prev,
+                              double* rhs) {
+    if (!c) return TBDG_EINVAL;
+    return guarded(c, [&]() {
+        check_stage(stage);
+        require(u_ss && p_prev && rhs, "null pointer");
+        trbdg::rhs_pressure(c, stage, u_ss, p_prev, rhs);
+        return TBDG_OK;
+    });
+}
+
+tbdg_status tbdg_solve_momentum(tbdg_ctx* c, int stage, const double* w, const double* rhs,
+                                double* u_inout, const tbdg_solver_opts* opts,
+                                tbdg_solve_info* info) {
+    if (!c) return TBDG_EINVAL;
+    return guarded(c, [&]() {
+        check_stage(stage);
+        require(w && rhs && u_inout, "null pointer");
+        const tbdg_solver_opts o = defaults(opts);
+        const tbdg_status s = trbdg::solve_momentum(c, stage, w, rhs, u_inout, o, info);
+        if (s != TBDG_OK) c->last_error = "momentum GMRES did not converge";
+        return s;
+    });
+}
+
+tbdg_status tbdg_solve_pressure(tbdg_ctx* c, int stage, const double* rhs, double* p_inout,
+                                const tbdg_solver_opts* opts, tbdg_solve_info* info) {
+    if (!c) return TBDG_EINVAL;
+    return guarded(c, [&]() {
+        check_stage(stage);
+        require(rhs && p_inout, "null pointer");
+        const tbdg_solver_opts o = defaults(opts);
+        const tbdg_status s = trbdg::solve_pressure(c, stage, rhs, p_inout, o, info);
+        if (s != TBDG_OK) c->last_error = "pressure CG did not converge";
+        return s;
+    });
+}
+
+tbdg_status tbdg_step(tbdg_ctx* c, tbdg_state* state, const tbdg_solver_opts* mom,
+                      const tbdg_solver_opts* prs, tbdg_solve_info info[4]) {
+    if (!c) return TBDG_EINVAL;
+    return guarded(c, [&]() {
+        require(state && state->u && state->u_hist && state->p, "null state");
+        const tbdg_solver_opts mo = defaults(mom);
+        const tbdg_solver_opts po = defaults(prs);
+        const tbdg_status s = trbdg::step(c, state, mo, po, info);
+        if (s != TBDG_OK && c->last_error.empty()) c->last_error = "a stage solve failed";
+        return s;
+    });
+}
+
+}  // extern "C"

@@ -1,0 +1,332 @@
+// Krylov solvers and the TR-BDF2 step (host orchestration of device kernels).
+//
+// GMRES (momentum predictor): restarted, right-preconditioned with the exact
+// Jacobi diagonal, classical Gram-Schmidt applied twice (CGS2) through
+// multi-vector dot and update kernels, Givens rotations on the host.
+// CG (Helmholtz): Jacobi-preconditioned; all scalars stay on the device; the
+// host reads the residual norm every few iterations.
+// Both stop on the relative residual and confirm with a freshly computed
+// true residual ||b - A x|| before returning.
+#include <cmath>
+#include <cstring>
+#include <vector>
+
+#include "internal.hpp"
+
+namespace trbdg {
+
+namespace {
+
+double host_scalar(tbdg_ctx* c, const double* dev, int k = 1) {
+    TBDG_HIP(hipMemcpyAsync(c->host_out, dev, sizeof(double) * k, hipMemcpyDeviceToHost, c->stream));
+    TBDG_HIP(hipStreamSynchronize(c->stream));
+    return c->host_out[0];
+}
+
+double norm2(tbdg_ctx* c, int64_t n, const double* x) {
+    dot2(c, n, x, x, c->red_out + 63);
+    return std::sqrt(host_scalar(c, c->red_out + 63));
+}
+
+struct MomentumOp {
+    tbdg_ctx* c;
+    double m, th;
+    const double* w;
+    void operator()(const double* x, double* y) const { launch_apply_momentum(c, m, th, w, x, y); }
+};
+
+}  // namespace
+
+// ---------------------------------------------------------------------------
+tbdg_status solve_momentum(tbdg_ctx* c, int s, const double* w, const double* b, double* x,
+                           const tbdg_solver_opts& o, tbdg_solve_info* info) {
+    const int64_t n = c->Nu;
+    const int m = std::min(o.restart > 0 ? o.restart : 30, c->gm_m);
+    MomentumOp A{c, c->mcoef(s), c->theta[s], w};
+    launch_diag_momentum(c, c->mcoef(s), c->theta[s], w, c->diag_u);
+    const double bnorm = norm2(c, n, b);
+    tbdg_solve_info inf{0, 0.0, 0.0, 0};
+    if (bnorm == 0.0) {
+        TBDG_HIP(hipMemsetAsync(x, 0, sizeof(double) * n, c->stream));
+        if (info) *info = inf;
+        return TBDG_OK;
+    }
+    if (!std::isfinite(bnorm)) {
+        if (info) *info = inf;
+        return TBDG_ENAN;
+    }
+    double* V = c->V;
+    const int64_t ld = n;
+    std::vector<double> H((m + 1) * m), cs(m), sn(m), g(m + 1), y(m);
+    int total = 0;
+    tbdg_status st = TBDG_ENOTCONV;
+    // initial residual r = b - A x into V_0
+    A(x, c->gv);
+    vec_axpby(c->stream, n, 1.0, b, -1.0, c->gv, V);
+    double beta = norm2(c, n, V);
+    inf.res0 = beta / bnorm;
+    while (true) {
+        if (!std::isfinite(beta)) {
+            st = TBDG_ENAN;
+            break;
+        }
+        if (beta <= o.tol * bnorm) {
+            st = TBDG_OK;
+            break;
+        }
+        if (total >= o.maxiter) {
+            st = TBDG_ENOTCONV;
+            break;
+        }
+        vec_scale_copy(c->stream, n, 1.0 / beta, V, V);
+        std::fill(g.begin(), g.end(), 0.0);
+        g[0] = beta;
+        int j = 0;
+        double resid = beta;
+        bool breakdown = false;
+        for (; j < m && total < o.maxiter; ++j) {
+            ++total;
+            double* vj = V + (int64_t)j * ld;
+            double* vn = V + (int64_t)(j + 1) * ld;
+            vec_div_diag_u(c->stream, n, c->dim, c->nbu, vj, c->diag_u, c->gz);
+            A(c->gz, vn);
+            // CGS2
+            std::vector<double> h(j + 1, 0.0);
+            for (int pass = 0; pass < 2; ++pass) {
+                dot_many(c, n, j + 1, V, ld, vn, c->red_out);
+                TBDG_HIP(hipMemcpyAsync(c->host_out, c->red_out, sizeof(double) * (j + 1),
+                                        hipMemcpyDeviceToHost, c->stream));
+                vec_sub_combo(c->stream, n, j + 1, V, ld, c->red_out, vn);
+                TBDG_HIP(hipStreamSynchronize(c->stream));
+                for (int i = 0; i <= j; ++i) h[i] += c->host_out[i];
+            }
+            const double hn = norm2(c, n, vn);
+            for (int i = 0; i <= j; ++i) H[i * m + j] = h[i];
+            H[(j + 1) * m + j] = hn;
+            // apply previous rotations
+            for (int i = 0; i < j; ++i) {
+                const double t1 = cs[i] * H[i * m + j] + sn[i] * H[(i + 1) * m + j];
+                const double t2 = -sn[i] * H[i * m + j] + cs[i] * H[(i + 1) * m + j];
+                H[i * m + j] = t1;
+                H[(i + 1) * m + j] = t2;
+            }
+            const double a = H[j * m + j], bb = H[(j + 1) * m + j];
+            const double r = std::hypot(a, bb);
+            if (r == 0.0 || !std::isfinite(r)) {
+                breakdown = true;
+                break;
+            }
+            cs[j] = a / r;
+            sn[j] = bb / r;
+            H[j * m + j] = r;
+            H[(j + 1) * m + j] = 0.0;
+            g[j + 1] = -sn[j] * g[j];
+            g[j] = cs[j] * g[j];
+            resid = std::fabs(g[j + 1]);
+            if (hn > 0.0) vec_scale_copy(c->stream, n, 1.0 / hn, vn, vn);
+            if (resid <= o.tol * bnorm || hn == 0.0) {
+                ++j;
+                break;
+            }
+        }
+        // y = R^{-1} g, x += D^{-1} V y
+        const int k = j;
+        for (int i = k - 1; i >= 0; --i) {
+            double s2 = g[i];
+            for (int q = i + 1; q < k; ++q) s2 -= H[i * m + q] * y[q];
+            y[i] = s2 / H[i * m + i];
+        }
+        if (k > 0) {
+            std::memcpy(c->host_out, y.data(), sizeof(double) * k);
+            TBDG_HIP(hipMemcpyAsync(c->red_out, c->host_out, sizeof(double) * k,
+                                    hipMemcpyHostToDevice, c->stream));
+            TBDG_HIP(hipMemsetAsync(c->gz, 0, sizeof(double) * n, c->stream));
+            vec_add_combo(c->stream, n, k, V, ld, c->red_out, c->gz);
+            vec_add_div_diag_u(c->stream, n, c->dim, c->nbu, c->gz, c->diag_u, x);
+        }
+        // true residual
+        A(x, c->gv);
+        vec_axpby(c->stream, n, 1.0, b, -1.0, c->gv, V);
+        beta = norm2(c, n, V);
+        if (breakdown && beta > o.tol * bnorm) {
+            st = TBDG_EBREAKDOWN;
+            break;
+        }
+    }
+    inf.iters = total;
+    inf.res_final = beta / bnorm;
+    if (info) *info = inf;
+    return st;
+}
+
+// ---------------------------------------------------------------------------
+tbdg_status solve_pressure(tbdg_ctx* c, int s, const double* b, double* x,
+                           const tbdg_solver_opts& o, tbdg_solve_info* info) {
+    const int64_t n = c->Np;
+    const double alpha = c->alpha(s);
+    const double* diag = c->diag_p[s];
+    double* r = c->cr;
+    double* p = c->cp;
+    double* q = c->cq;
+    double* sc = c->red_out + 64;   // CG scalars
+    tbdg_solve_info inf{0, 0.0, 0.0, 0};
+    const double bnorm = norm2(c, n, b);
+    if (bnorm == 0.0) {
+        TBDG_HIP(hipMemsetAsync(x, 0, sizeof(double) * n, c->stream));
+        if (info) *info = inf;
+        return TBDG_OK;
+    }
+    if (!std::isfinite(bnorm)) {
+        if (info) *info = inf;
+        return TBDG_ENAN;
+    }
+    TBDG_HIP(hipMemsetAsync(sc, 0, sizeof(double) * 8, c->stream));
+    tbdg_status st = TBDG_ENOTCONV;
+    int total = 0;
+    const int check = 8;
+    bool first_cycle = true;
+    while (true) {
+        // (re)start from the true residual
+        launch_apply_pressure(c, alpha, x, q);
+        vec_axpby(c->stream, n, 1.0, b, -1.0, q, r);
+        cg_init(c, n, diag, r, p, sc);
+        TBDG_HIP(hipMemcpyAsync(c->host_out, sc, sizeof(double) * 8, hipMemcpyDeviceToHost, c->stream));
+        TBDG_HIP(hipStreamSynchronize(c->stream));
+        double rr = c->host_out[2];
+        if (first_cycle) inf.res0 = std::sqrt(rr) / bnorm;
+        first_cycle = false;
+        if (!std::isfinite(rr)) {
+            st = TBDG_ENAN;
+            break;
+        }
+        if (std::sqrt(rr) <= o.tol * bnorm) {
+            st = TBDG_OK;
+            break;
+        }
+        if (total >= o.maxiter) break;
+        bool converged = false, broke = false;
+        while (total < o.maxiter) {
+            launch_apply_pressure(c, alpha, p, q);
+            cg_alpha(c, n, p, q, sc);
+            cg_update(c, n, diag, x, r, p, q, sc);
+            cg_direction(c->stream, n, diag, r, p, sc);
+            ++total;
+            if (total % check == 0 || total >= o.maxiter) {
+                TBDG_HIP(hipMemcpyAsync(c->host_out, sc, sizeof(double) * 8, hipMemcpyDeviceToHost,
+                                        c->stream));
+                TBDG_HIP(hipStreamSynchronize(c->stream));
+                rr = c->host_out[2];
+                if (c->host_out[6] != 0.0) {
+                    broke = true;
+                    break;
+                }
+                if (!std::isfinite(rr)) break;
+                if (std::sqrt(rr) <= o.tol * bnorm) {
+                    converged = true;
+                    break;
+                }
+            }
+        }
+        if (broke) {
+            st = TBDG_EBREAKDOWN;
+            break;
+        }
+        if (!converged && !std::isfinite(rr)) {
+            st = TBDG_ENAN;
+            break;
+        }
+        if (!converged && total >= o.maxiter) {
+            // final true residual below
+            st = TBDG_ENOTCONV;
+            break;
+        }
+        // converged on the recurrence: loop back to confirm with the true residual
+    }
+    // final true residual
+    launch_apply_pressure(c, alpha, x, q);
+    vec_axpby(c->stream, n, 1.0, b, -1.0, q, r);
+    const double rt = norm2(c, n, r);
+    inf.iters = total;
+    inf.res_final = rt / bnorm;
+    if (st == TBDG_ENOTCONV && rt <= o.tol * bnorm) st = TBDG_OK;
+    if (info) *info = inf;
+    return st;
+}
+
+// ---------------------------------------------------------------------------
+void extrapolate(tbdg_ctx* c, int s, const double* u_new, const double* u_old, double* w) {
+    const double g = c->gamma;
+    double e0, e1;
+    if (s == 1) {
+        e1 = -g / (2.0 * (1.0 - g));
+        e0 = 1.0 - e1;
+    } else {
+        e1 = -(1.0 - g) / g;
+        e0 = 1.0 - e1;
+    }
+    vec_axpby(c->stream, c->Nu, e0, u_new, e1, u_old, w);
+}
+
+void rhs_momentum(tbdg_ctx* c, int s, const double* u_n, const double* u_g, const double* w,
+                  const double* p, double* rhs) {
+    if (s == 1) {
+        const double th = c->theta[1];
+        launch_rhs_momentum(c, c->mcoef(1), u_n, u_n, w, th * c->nu, th, nullptr, nullptr, 0.0,
+                            0.0, p, rhs);
+    } else {
+        launch_rhs_momentum(c, c->mcoef(2), u_g, u_g, u_g, c->a32 * c->nu, c->a32, u_n, u_n,
+                            c->a31 * c->nu, c->a31, p, rhs);
+    }
+}
+
+void rhs_pressure(tbdg_ctx* c, int s, const double* u_ss, const double* p_prev, double* rhs) {
+    launch_rhs_pressure(c, c->alpha(s), 1.0 / (c->beta[s] * c->dt), u_ss, p_prev, rhs);
+}
+
+tbdg_status step(tbdg_ctx* c, tbdg_state* S, const tbdg_solver_opts& mo,
+                 const tbdg_solver_opts& po, tbdg_solve_info info[4]) {
+    const int64_t Nu = c->Nu, Np = c->Np;
+    hipStream_t st = c->stream;
+    tbdg_solve_info loc[4];
+    tbdg_status rc;
+    const size_t bu = sizeof(double) * Nu, bp = sizeof(double) * Np;
+    // ---- stage 1 ----
+    extrapolate(c, 1, S->u, S->u_hist, c->s_w);
+    rhs_momentum(c, 1, S->u, nullptr, c->s_w, S->p, c->s_rhs);
+    TBDG_HIP(hipMemcpyAsync(c->s_ustar, S->u, bu, hipMemcpyDeviceToDevice, st));
+    rc = solve_momentum(c, 1, c->s_w, c->s_rhs, c->s_ustar, mo, &loc[0]);
+    if (info) info[0] = loc[0];
+    if (rc != TBDG_OK) return rc;
+    const double b1 = c->beta[1] * c->dt;
+    launch_add_grad_p(c, c->s_ustar, b1, S->p, c->s_ustar);          // u**
+    rhs_pressure(c, 1, c->s_ustar, S->p, c->s_pb);
+    TBDG_HIP(hipMemcpyAsync(c->s_pg, S->p, bp, hipMemcpyDeviceToDevice, st));
+    rc = solve_pressure(c, 1, c->s_pb, c->s_pg, po, &loc[1]);
+    if (info) info[1] = loc[1];
+    if (rc != TBDG_OK) return rc;
+    launch_add_grad_p(c, c->s_ustar, -b1, c->s_pg, c->s_ug);          // u^{n+gamma}
+    // ---- stage 2 ----
+    extrapolate(c, 2, c->s_ug, S->u, c->s_w);
+    rhs_momentum(c, 2, S->u, c->s_ug, c->s_w, c->s_pg, c->s_rhs);
+    TBDG_HIP(hipMemcpyAsync(c->s_ustar, c->s_ug, bu, hipMemcpyDeviceToDevice, st));
+    rc = solve_momentum(c, 2, c->s_w, c->s_rhs, c->s_ustar, mo, &loc[2]);
+    if (info) info[2] = loc[2];
+    if (rc != TBDG_OK) return rc;
+    const double b2 = c->beta[2] * c->dt;
+    launch_add_grad_p(c, c->s_ustar, b2, c->s_pg, c->s_ustar);
+    rhs_pressure(c, 2, c->s_ustar, c->s_pg, c->s_pb);
+    TBDG_HIP(hipMemcpyAsync(c->s_p1, c->s_pg, bp, hipMemcpyDeviceToDevice, st));
+    rc = solve_pressure(c, 2, c->s_pb, c->s_p1, po, &loc[3]);
+    if (info) info[3] = loc[3];
+    if (rc != TBDG_OK) return rc;
+    launch_add_grad_p(c, c->s_ustar, -b2, c->s_p1, c->s_u1);
+    // ---- commit ----
+    TBDG_HIP(hipMemcpyAsync(S->u_hist, c->s_ug, bu, hipMemcpyDeviceToDevice, st));
+    TBDG_HIP(hipMemcpyAsync(S->u, c->s_u1, bu, hipMemcpyDeviceToDevice, st));
+    TBDG_HIP(hipMemcpyAsync(S->p, c->s_p1, bp, hipMemcpyDeviceToDevice, st));
+    S->t += c->dt;
+    S->n += 1;
+    return TBDG_OK;
+}
+
+}  // namespace trbdg

@@ -1,0 +1,276 @@
+"""ctypes binding of libtrbdg (argument marshalling only).
+
+Every computation runs in the HIP library; this module checks tensor device,
+dtype, size and contiguity, passes raw device pointers and turns non-zero
+status codes into ``TrbdgError``.  PyTorch provides device memory and the
+stream.  Loading fails loudly when the library has not been built.
+"""
+import ctypes
+import math
+import os
+
+import torch
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libtrbdg.so")
+
+STATUS = {0: "OK", -1: "EINVAL", -2: "EDEVICE", -3: "ENOMEM", -4: "ENOTCONV",
+          -5: "EBREAKDOWN", -6: "ENAN", -7: "EUNSUPPORTED"}
+
+# Symbols declared in include/trbdg.h
+EXPORTED = [
+    "tbdg_create", "tbdg_destroy", "tbdg_last_error", "tbdg_set_stream", "tbdg_sizes",
+    "tbdg_node_coords", "tbdg_extrapolate", "tbdg_apply_momentum", "tbdg_apply_pressure",
+    "tbdg_diag_momentum", "tbdg_diag_pressure", "tbdg_rhs_momentum", "tbdg_grad_p",
+    "tbdg_add_grad_p", "tbdg_rhs_pressure", "tbdg_solve_momentum", "tbdg_solve_pressure",
+    "tbdg_step",
+]
+
+
+class TrbdgError(RuntimeError):
+    def __init__(self, status, msg):
+        super().__init__(f"{STATUS.get(status, status)}: {msg}")
+        self.status = status
+
+
+class MeshDesc(ctypes.Structure):
+    _fields_ = [("dim", ctypes.c_int), ("n_cells", ctypes.c_int * 3),
+                ("lo", ctypes.c_double * 3), ("hi", ctypes.c_double * 3),
+                ("periodic", ctypes.c_int * 3), ("mapping", ctypes.c_int),
+                ("map_amp", ctypes.c_double)]
+
+
+class DiscDesc(ctypes.Structure):
+    _fields_ = [("k_u", ctypes.c_int), ("nu", ctypes.c_double), ("c", ctypes.c_double),
+                ("dt", ctypes.c_double), ("gamma", ctypes.c_double),
+                ("pen_u", ctypes.c_double), ("pen_p", ctypes.c_double)]
+
+
+class SolverOpts(ctypes.Structure):
+    _fields_ = [("tol", ctypes.c_double), ("maxiter", ctypes.c_int), ("restart", ctypes.c_int),
+                ("precond", ctypes.c_int), ("guess", ctypes.c_int)]
+
+
+class SolveInfo(ctypes.Structure):
+    _fields_ = [("iters", ctypes.c_int), ("res0", ctypes.c_double),
+                ("res_final", ctypes.c_double), ("guess_used", ctypes.c_int)]
+
+    def as_dict(self):
+        return dict(iters=self.iters, res0=self.res0, res_final=self.res_final,
+                    guess_used=self.guess_used)
+
+
+class State(ctypes.Structure):
+    _fields_ = [("u", ctypes.c_void_p), ("u_hist", ctypes.c_void_p), ("p", ctypes.c_void_p),
+                ("t", ctypes.c_double), ("n", ctypes.c_int64)]
+
+
+_lib = None
+
+
+def load_library(path=LIB_PATH):
+    """Load libtrbdg.so; raises if it has not been built."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(path):
+        raise RuntimeError(f"{path} is missing: build it with `python -m paper_2107_07776_amd.build`")
+    lib = ctypes.CDLL(path)
+    vp, i, d, i64 = ctypes.c_void_p, ctypes.c_int, ctypes.c_double, ctypes.c_int64
+    P = ctypes.POINTER
+    sig = {
+        "tbdg_create": ([P(MeshDesc), P(DiscDesc), vp, P(vp)], i),
+        "tbdg_destroy": ([vp], None),
+        "tbdg_last_error": ([vp], ctypes.c_char_p),
+        "tbdg_set_stream": ([vp, vp], i),
+        "tbdg_sizes": ([vp, P(i64), P(i64), P(i64)], i),
+        "tbdg_node_coords": ([vp, i, vp], i),
+        "tbdg_extrapolate": ([vp, i, vp, vp, vp], i),
+        "tbdg_apply_momentum": ([vp, i, vp, vp, vp], i),
+        "tbdg_apply_pressure": ([vp, i, vp, vp], i),
+        "tbdg_diag_momentum": ([vp, i, vp, vp], i),
+        "tbdg_diag_pressure": ([vp, i, vp], i),
+        "tbdg_rhs_momentum": ([vp, i, vp, vp, vp, vp, vp], i),
+        "tbdg_grad_p": ([vp, vp, vp], i),
+        "tbdg_add_grad_p": ([vp, vp, d, vp, vp], i),
+        "tbdg_rhs_pressure": ([vp, i, vp, vp, vp], i),
+        "tbdg_solve_momentum": ([vp, i, vp, vp, vp, P(SolverOpts), P(SolveInfo)], i),
+        "tbdg_solve_pressure": ([vp, i, vp, vp, P(SolverOpts), P(SolveInfo)], i),
+        "tbdg_step": ([vp, P(State), P(SolverOpts), P(SolverOpts), P(SolveInfo)], i),
+    }
+    for name, (args, res) in sig.items():
+        fn = getattr(lib, name)
+        fn.argtypes = args
+        fn.restype = res
+    _lib = lib
+    return lib
+
+
+def _ptr(t):
+    return ctypes.c_void_p(t.data_ptr()) if t is not None else ctypes.c_void_p(0)
+
+
+def solver_opts(tol=1e-8, maxiter=1000, restart=30):
+    return SolverOpts(float(tol), int(maxiter), int(restart), 0, 0)
+
+
+class Context:
+    """One mesh + discretisation on the current HIP device and stream."""
+
+    def __init__(self, dim, n_cells, lo, hi, k, nu, dt, c=1.0e3, periodic=None,
+                 gamma=0.0, pen_u=1.0, pen_p=1.0, stream=None, device="cuda"):
+        self.lib = load_library()
+        self.device = torch.device(device)
+        if self.device.type != "cuda" or not torch.cuda.is_available():
+            raise RuntimeError("trbdg needs a ROCm GPU device")
+        periodic = periodic if periodic is not None else (1,) * dim
+        m = MeshDesc()
+        m.dim = dim
+        for a in range(3):
+            m.n_cells[a] = int(n_cells[a]) if a < dim else 1
+            m.lo[a] = float(lo[a]) if a < dim else 0.0
+            m.hi[a] = float(hi[a]) if a < dim else 1.0
+            m.periodic[a] = int(bool(periodic[a])) if a < dim else 1
+        m.mapping = 0
+        m.map_amp = 0.0
+        dd = DiscDesc(int(k), float(nu), float(c), float(dt), float(gamma), float(pen_u), float(pen_p))
+        self.stream = stream if stream is not None else torch.cuda.current_stream(self.device)
+        h = ctypes.c_void_p()
+        st = self.lib.tbdg_create(ctypes.byref(m), ctypes.byref(dd),
+                                  ctypes.c_void_p(self.stream.cuda_stream), ctypes.byref(h))
+        if st != 0:
+            raise TrbdgError(st, "tbdg_create failed (invalid or unsupported descriptor)")
+        self.h = h
+        nu_, np_, nc_ = ctypes.c_int64(), ctypes.c_int64(), ctypes.c_int64()
+        self._check(self.lib.tbdg_sizes(self.h, ctypes.byref(nu_), ctypes.byref(np_), ctypes.byref(nc_)))
+        self.dim, self.k = dim, k
+        self.N_u, self.N_p, self.N_c = nu_.value, np_.value, nc_.value
+        self.nbu = (k + 1) ** dim
+        self.nbp = k ** dim
+        self.dt = dt
+        self.gamma = float(gamma) if gamma > 0.0 else 2.0 - math.sqrt(2.0)
+
+    # -- plumbing ----------------------------------------------------------
+    def _check(self, st):
+        if st != 0:
+            msg = self.lib.tbdg_last_error(self.h)
+            raise TrbdgError(st, msg.decode() if msg else "")
+
+    def _vec(self, t, n, name):
+        if not isinstance(t, torch.Tensor):
+            raise TypeError(f"{name} must be a torch tensor")
+        if t.device.type != "cuda" or t.dtype != torch.float64 or not t.is_contiguous():
+            raise ValueError(f"{name} must be a contiguous float64 CUDA tensor")
+        if t.numel() != n:
+            raise ValueError(f"{name} has {t.numel()} entries, expected {n}")
+        return t
+
+    def empty_u(self):
+        return torch.empty(self.N_u, dtype=torch.float64, device=self.device)
+
+    def empty_p(self):
+        return torch.empty(self.N_p, dtype=torch.float64, device=self.device)
+
+    def close(self):
+        if getattr(self, "h", None):
+            self.lib.tbdg_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    # -- entry points ---------------------------------------------------------
+    def node_coords(self, field=0):
+        nb = self.nbu if field == 0 else self.nbp
+        out = torch.empty(self.N_c * nb * self.dim, dtype=torch.float64, device=self.device)
+        self._check(self.lib.tbdg_node_coords(self.h, field, _ptr(out)))
+        return out.view(-1, self.dim)
+
+    def extrapolate(self, stage, u_new, u_old, out=None):
+        out = self.empty_u() if out is None else self._vec(out, self.N_u, "out")
+        self._check(self.lib.tbdg_extrapolate(self.h, stage, _ptr(self._vec(u_new, self.N_u, "u_new")),
+                                              _ptr(self._vec(u_old, self.N_u, "u_old")), _ptr(out)))
+        return out
+
+    def apply_momentum(self, stage, w, u, out=None):
+        out = self.empty_u() if out is None else self._vec(out, self.N_u, "out")
+        self._check(self.lib.tbdg_apply_momentum(self.h, stage, _ptr(self._vec(w, self.N_u, "w")),
+                                                 _ptr(self._vec(u, self.N_u, "u")), _ptr(out)))
+        return out
+
+    def apply_pressure(self, stage, p, out=None):
+        out = self.empty_p() if out is None else self._vec(out, self.N_p, "out")
+        self._check(self.lib.tbdg_apply_pressure(self.h, stage, _ptr(self._vec(p, self.N_p, "p")), _ptr(out)))
+        return out
+
+    def diag_momentum(self, stage, w):
+        out = torch.empty(self.N_u // self.dim, dtype=torch.float64, device=self.device)
+        self._check(self.lib.tbdg_diag_momentum(self.h, stage, _ptr(self._vec(w, self.N_u, "w")), _ptr(out)))
+        return out
+
+    def diag_pressure(self, stage):
+        out = self.empty_p()
+        self._check(self.lib.tbdg_diag_pressure(self.h, stage, _ptr(out)))
+        return out
+
+    def rhs_momentum(self, stage, u_n, u_g, w, p_prev):
+        out = self.empty_u()
+        ug = None if u_g is None else self._vec(u_g, self.N_u, "u_g")
+        self._check(self.lib.tbdg_rhs_momentum(self.h, stage, _ptr(self._vec(u_n, self.N_u, "u_n")), _ptr(ug),
+                                               _ptr(self._vec(w, self.N_u, "w")),
+                                               _ptr(self._vec(p_prev, self.N_p, "p_prev")), _ptr(out)))
+        return out
+
+    def grad_p(self, p):
+        out = self.empty_u()
+        self._check(self.lib.tbdg_grad_p(self.h, _ptr(self._vec(p, self.N_p, "p")), _ptr(out)))
+        return out
+
+    def add_grad_p(self, x, a, p, out=None):
+        out = self.empty_u() if out is None else self._vec(out, self.N_u, "out")
+        self._check(self.lib.tbdg_add_grad_p(self.h, _ptr(self._vec(x, self.N_u, "x")), float(a),
+                                             _ptr(self._vec(p, self.N_p, "p")), _ptr(out)))
+        return out
+
+    def rhs_pressure(self, stage, u_ss, p_prev):
+        out = self.empty_p()
+        self._check(self.lib.tbdg_rhs_pressure(self.h, stage, _ptr(self._vec(u_ss, self.N_u, "u_ss")),
+                                               _ptr(self._vec(p_prev, self.N_p, "p_prev")), _ptr(out)))
+        return out
+
+    def solve_momentum(self, stage, w, rhs, u_inout, tol=1e-8, maxiter=1000, restart=30, check=True):
+        o = solver_opts(tol, maxiter, restart)
+        info = SolveInfo()
+        st = self.lib.tbdg_solve_momentum(self.h, stage, _ptr(self._vec(w, self.N_u, "w")),
+                                          _ptr(self._vec(rhs, self.N_u, "rhs")),
+                                          _ptr(self._vec(u_inout, self.N_u, "u")), ctypes.byref(o),
+                                          ctypes.byref(info))
+        if check:
+            self._check(st)
+        return info.as_dict() | {"status": st}
+
+    def solve_pressure(self, stage, rhs, p_inout, tol=1e-8, maxiter=5000, check=True):
+        o = solver_opts(tol, maxiter, 0)
+        info = SolveInfo()
+        st = self.lib.tbdg_solve_pressure(self.h, stage, _ptr(self._vec(rhs, self.N_p, "rhs")),
+                                          _ptr(self._vec(p_inout, self.N_p, "p")), ctypes.byref(o),
+                                          ctypes.byref(info))
+        if check:
+            self._check(st)
+        return info.as_dict() | {"status": st}
+
+    def step(self, u, u_hist, p, t=0.0, n=0, mom_tol=1e-8, prs_tol=1e-8, mom_maxiter=1000,
+             prs_maxiter=5000, restart=30, check=True):
+        """One TR-BDF2 step in place on (u, u_hist, p); returns per-solve info."""
+        S = State(_ptr(self._vec(u, self.N_u, "u")), _ptr(self._vec(u_hist, self.N_u, "u_hist")),
+                  _ptr(self._vec(p, self.N_p, "p")), float(t), int(n))
+        mo = solver_opts(mom_tol, mom_maxiter, restart)
+        po = solver_opts(prs_tol, prs_maxiter, 0)
+        infos = (SolveInfo * 4)()
+        st = self.lib.tbdg_step(self.h, ctypes.byref(S), ctypes.byref(mo), ctypes.byref(po), infos)
+        if check:
+            self._check(st)
+        return [infos[i].as_dict() for i in range(4)], st
