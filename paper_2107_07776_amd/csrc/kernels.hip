@@ -182,10 +182,19 @@ __global__ __launch_bounds__(256) void k_diag_pressure(Geom g, Periodic per, Tab
         acc += g.vol * inv_h * inv_h * wt * s2sum;
         const double dS = g.vol * inv_h * wt;
         for (int s = 0; s < 2; ++s) {
-            if (neighbor<DIM>(g, per.p, cell, a, s) < 0) continue;
+            const int64_t nb = neighbor<DIM>(g, per.p, cell, a, s);
+            if (nb < 0) continue;
+            const double sg = s ? 1.0 : -1.0;
             const double L = s ? t.L1p[ia] : t.L0p[ia];
-            const double dL = (s ? 1.0 : -1.0) * (s ? t.dL1p[ia] : t.dL0p[ia]) * inv_h;
+            const double dL = sg * (s ? t.dL1p[ia] : t.dL0p[ia]) * inv_h;
             acc += dS * (-dL * L + sig[a] * L * L);
+            if (nb == cell) {
+                // a single cell across a periodic direction is its own neighbour:
+                // the neighbour-trace coupling then lands on the diagonal too
+                const double Ln = s ? t.L0p[ia] : t.L1p[ia];
+                const double dLn = sg * (s ? t.dL0p[ia] : t.dL1p[ia]) * inv_h;
+                acc += dS * (-0.5 * dLn * L + 0.5 * Ln * dL - sig[a] * Ln * L);
+            }
         }
     }
     d[gid] = acc;
@@ -344,6 +353,12 @@ __global__ __launch_bounds__(256) void k_diag_momentum(Geom g, Periodic per, Tab
             const double L = Ls[ia];
             const double dL = sg * (s ? t.dL1u[ia] : t.dL0u[ia]) * inv_h;
             acc += dS * (tnu * (-dL * L + sig[a] * L * L) + th * 0.5 * (wo + lam) * L * L);
+            if (nb == cell) {
+                const double Lo = Ln[ia];
+                const double dLo = sg * (s ? t.dL0u[ia] : t.dL1u[ia]) * inv_h;
+                acc += dS * (tnu * (-0.5 * dLo * L + 0.5 * Lo * dL - sig[a] * Lo * L) +
+                             th * 0.5 * (wn - lam) * Lo * L);
+            }
         }
     }
     d[gid] = acc;
