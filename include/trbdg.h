@@ -201,6 +201,17 @@ typedef struct {
 TBDG_API tbdg_status tbdg_step(tbdg_ctx* ctx, tbdg_state* state, const tbdg_solver_opts* mom,
                       const tbdg_solver_opts* prs, tbdg_solve_info info[4]);
 
+/* Measurement hook.  While enabled, every launch of the pressure operator
+ * kernel (which = 0: tbdg_apply_pressure and the CG iterations) and of the
+ * momentum operator kernel (which = 1: tbdg_apply_momentum and the GMRES
+ * iterations) is bracketed by a pair of HIP events on the context's stream.
+ * tbdg_profile_read synchronises on the recorded events, returns the summed
+ * kernel time in milliseconds and the number of launches for `which` since
+ * the previous read, and resets those counters.                           */
+TBDG_API tbdg_status tbdg_profile_enable(tbdg_ctx* ctx, int enable);
+TBDG_API tbdg_status tbdg_profile_read(tbdg_ctx* ctx, int which, double* total_ms,
+                                       int64_t* launches);
+
 #ifdef __cplusplus
 }
 #endif

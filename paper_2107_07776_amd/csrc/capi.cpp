@@ -216,6 +216,7 @@ tbdg_status tbdg_create(const tbdg_mesh_desc* mesh, const tbdg_disc_desc* disc, 
 void tbdg_destroy(tbdg_ctx* c) {
     if (!c) return;
     (void)hipStreamSynchronize(c->stream);
+    trbdg::timer_release(c);
     free_all(c);
     delete c;
 }
@@ -381,6 +382,28 @@ tbdg_status tbdg_step(tbdg_ctx* c, tbdg_state* state, const tbdg_solver_opts* mo
         const tbdg_status s = trbdg::step(c, state, mo, po, info);
         if (s != TBDG_OK && c->last_error.empty()) c->last_error = "a stage solve failed";
         return s;
+    });
+}
+
+tbdg_status tbdg_profile_enable(tbdg_ctx* c, int enable) {
+    if (!c) return TBDG_EINVAL;
+    return guarded(c, [&]() {
+        trbdg::timer_collect(c);
+        c->timer.on = enable != 0;
+        return TBDG_OK;
+    });
+}
+
+tbdg_status tbdg_profile_read(tbdg_ctx* c, int which, double* total_ms, int64_t* launches) {
+    if (!c) return TBDG_EINVAL;
+    return guarded(c, [&]() {
+        require(which == 0 || which == 1, "which must be 0 (pressure) or 1 (momentum)");
+        trbdg::timer_collect(c);
+        if (total_ms) *total_ms = c->timer.total_ms[which];
+        if (launches) *launches = c->timer.count[which];
+        c->timer.total_ms[which] = 0.0;
+        c->timer.count[which] = 0;
+        return TBDG_OK;
     });
 }
 

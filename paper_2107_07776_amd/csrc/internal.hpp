@@ -49,9 +49,13 @@ struct Error : std::runtime_error {
                                  hipGetErrorString(e_));                        \
     } while (0)
 
-struct DevBuf {
-    double* p = nullptr;
-    size_t n = 0;
+// Event-bracketed timing of the operator kernels (measurement hook).
+struct KTimer {
+    bool on = false;
+    std::vector<std::pair<hipEvent_t, hipEvent_t>> pending[2];
+    std::vector<hipEvent_t> pool;
+    double total_ms[2] = {0.0, 0.0};
+    int64_t count[2] = {0, 0};
 };
 
 }  // namespace trbdg
@@ -68,6 +72,7 @@ struct tbdg_ctx {
     int periodic_flags[3] = {1, 1, 1};
     hipStream_t stream = nullptr;
     std::string last_error;
+    mutable trbdg::KTimer timer;
 
     // persistent device workspaces
     double* diag_p[3] = {nullptr, nullptr, nullptr};   // pressure diagonals, stage 1/2
@@ -119,6 +124,19 @@ void launch_add_grad_p(const tbdg_ctx* c, const double* x, double a, const doubl
 void launch_rhs_pressure(const tbdg_ctx* c, double alpha, double fcoef, const double* u_ss,
                          const double* p_prev, double* rhs);
 void launch_node_coords(const tbdg_ctx* c, int field, double* xyz);
+
+// Brackets one launch with events when the context's timer is on.
+class TimedLaunch {
+  public:
+    TimedLaunch(const tbdg_ctx* c, int which);
+    ~TimedLaunch();
+  private:
+    const tbdg_ctx* c_;
+    int which_;
+    hipEvent_t e1_ = nullptr;
+};
+void timer_collect(const tbdg_ctx* c);
+void timer_release(const tbdg_ctx* c);
 
 // ---- vector kernels implemented in blas.hip -------------------------------------
 void vec_axpby(hipStream_t s, int64_t n, double a, const double* x, double b, const double* y, double* out);

@@ -694,6 +694,7 @@ inline Periodic periodic_of(const tbdg_ctx* c) {
     } while (0)
 
 void launch_apply_pressure(const tbdg_ctx* c, double alpha, const double* p, double* y) {
+    TimedLaunch tl(c, 0);
 #define L_(D, N)                                                                          \
     {                                                                                     \
         using Lay = Layout<D, N - 1>;                                                     \
@@ -719,6 +720,7 @@ void launch_diag_pressure(const tbdg_ctx* c, double alpha, double* d) {
 
 void launch_apply_momentum(const tbdg_ctx* c, double mcoef, double theta, const double* w,
                            const double* u, double* y) {
+    TimedLaunch tl(c, 1);
 #define L_(D, N)                                                                          \
     {                                                                                     \
         using Lay = Layout<D, N>;                                                         \

@@ -1,0 +1,67 @@
+// Event-bracketed kernel timing used by the benchmark: per-launch durations
+// of the operator kernels measured on the stream they run on.
+#include "internal.hpp"
+
+namespace trbdg {
+
+namespace {
+hipEvent_t take(const tbdg_ctx* c) {
+    auto& pool = c->timer.pool;
+    if (!pool.empty()) {
+        hipEvent_t e = pool.back();
+        pool.pop_back();
+        return e;
+    }
+    hipEvent_t e = nullptr;
+    TBDG_HIP(hipEventCreate(&e));
+    return e;
+}
+}  // namespace
+
+TimedLaunch::TimedLaunch(const tbdg_ctx* c, int which) : c_(c), which_(which) {
+    if (!c_->timer.on) return;
+    e1_ = take(c_);
+    TBDG_HIP(hipEventRecord(e1_, c_->stream));
+}
+
+TimedLaunch::~TimedLaunch() {
+    if (!e1_) return;
+    hipEvent_t e2 = nullptr;
+    try {
+        e2 = take(c_);
+    } catch (...) {
+        return;
+    }
+    if (hipEventRecord(e2, c_->stream) != hipSuccess) return;
+    c_->timer.pending[which_].emplace_back(e1_, e2);
+    if (c_->timer.pending[which_].size() >= 4096) timer_collect(c_);
+}
+
+void timer_collect(const tbdg_ctx* c) {
+    for (int w = 0; w < 2; ++w) {
+        for (auto& pr : c->timer.pending[w]) {
+            TBDG_HIP(hipEventSynchronize(pr.second));
+            float ms = 0.0f;
+            TBDG_HIP(hipEventElapsedTime(&ms, pr.first, pr.second));
+            c->timer.total_ms[w] += ms;
+            c->timer.count[w] += 1;
+            c->timer.pool.push_back(pr.first);
+            c->timer.pool.push_back(pr.second);
+        }
+        c->timer.pending[w].clear();
+    }
+}
+
+void timer_release(const tbdg_ctx* c) {
+    for (int w = 0; w < 2; ++w) {
+        for (auto& pr : c->timer.pending[w]) {
+            (void)hipEventDestroy(pr.first);
+            (void)hipEventDestroy(pr.second);
+        }
+        c->timer.pending[w].clear();
+    }
+    for (hipEvent_t e : c->timer.pool) (void)hipEventDestroy(e);
+    c->timer.pool.clear();
+}
+
+}  // namespace trbdg

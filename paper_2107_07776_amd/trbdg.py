@@ -23,7 +23,7 @@ EXPORTED = [
     "tbdg_node_coords", "tbdg_extrapolate", "tbdg_apply_momentum", "tbdg_apply_pressure",
     "tbdg_diag_momentum", "tbdg_diag_pressure", "tbdg_rhs_momentum", "tbdg_grad_p",
     "tbdg_add_grad_p", "tbdg_rhs_pressure", "tbdg_solve_momentum", "tbdg_solve_pressure",
-    "tbdg_step",
+    "tbdg_step", "tbdg_profile_enable", "tbdg_profile_read",
 ]
 
 
@@ -97,6 +97,8 @@ def load_library(path=LIB_PATH):
         "tbdg_solve_momentum": ([vp, i, vp, vp, vp, P(SolverOpts), P(SolveInfo)], i),
         "tbdg_solve_pressure": ([vp, i, vp, vp, P(SolverOpts), P(SolveInfo)], i),
         "tbdg_step": ([vp, P(State), P(SolverOpts), P(SolverOpts), P(SolveInfo)], i),
+        "tbdg_profile_enable": ([vp, i], i),
+        "tbdg_profile_read": ([vp, i, P(d), P(i64)], i),
     }
     for name, (args, res) in sig.items():
         fn = getattr(lib, name)
@@ -274,3 +276,14 @@ class Context:
         if check:
             self._check(st)
         return [infos[i].as_dict() for i in range(4)], st
+
+    def profile(self, enable):
+        """Bracket every operator-kernel launch with HIP events (measurement)."""
+        self._check(self.lib.tbdg_profile_enable(self.h, int(bool(enable))))
+
+    def profile_read(self, which):
+        """(total kernel ms, launches) since the last read; which 0 = pressure
+        operator, 1 = momentum operator."""
+        ms, n = ctypes.c_double(), ctypes.c_int64()
+        self._check(self.lib.tbdg_profile_read(self.h, int(which), ctypes.byref(ms), ctypes.byref(n)))
+        return ms.value, n.value
