@@ -72,8 +72,13 @@ class TRBDF2:
     (unused on fully periodic meshes).
     """
 
-    def __init__(self, disc, dt, gamma=None, uD=None, extrap1="stage"):
+    def __init__(self, disc, dt, gamma=None, uD=None, extrap1="stage", rows=None):
+        """``rows``: optional list of cells; when given, every operator is
+        assembled only for the test functions of those cells (results are
+        valid on those cells' entries only), which keeps large meshes cheap
+        for sampled comparisons."""
         self.disc = disc
+        self.rows = rows
         self.dt = float(dt)
         self.cst = trbdf2_constants(gamma)
         self.uD = uD
@@ -82,20 +87,23 @@ class TRBDF2:
         self.beta = {1: g, 2: 1.0 - g}
         self.theta = {1: 0.5, 2: self.cst["a33"]}
         d = disc
-        self.M = d.mass_u()
-        self.Mv = d.mass_u_vector()
-        self.Mp = d.mass_p()
-        self.L = d.sip_u()
-        self.K = d.sip_p()
-        self.L0 = d.explicit_diffusion()
-        self.Gw = d.weak_gradient()
-        self.D = d.divergence()
-        self.P = d.projection()
+        r = rows
+        self.M = d.mass_u(r)
+        self.Mv = d.mass_u_vector(r)
+        self.Mp = d.mass_p(r)
+        self.L = d.sip_u(r)
+        self.K = d.sip_p(r)
+        self.L0 = d.explicit_diffusion(r)
+        self.Gw = d.weak_gradient(r)
+        self.D = d.divergence(r)
+        self.P = d.projection(r)
         mdiag = self.Mv.diagonal()
         if abs(sp.linalg.norm(self.Mv - sp.diags(mdiag))) > 0.0:
             raise AssertionError("velocity mass matrix is expected to be diagonal")
         # M^{-1} P: the projection of the broken pressure gradient into V_h
-        self.G = sp.diags(1.0 / mdiag) @ self.P
+        inv = np.zeros_like(mdiag)
+        inv[mdiag != 0.0] = 1.0 / mdiag[mdiag != 0.0]
+        self.G = sp.diags(inv) @ self.P
 
     # -- coefficients ------------------------------------------------------
     def m(self, s):
@@ -123,7 +131,7 @@ class TRBDF2:
     # -- operators -----------------------------------------------------------
     def momentum_scalar(self, s, w, t_stage=None):
         """m_s M + theta_s (nu A + C(w)) for one component."""
-        C = self.disc.lf_advection(w, self._uD_face(t_stage))
+        C = self.disc.lf_advection(w, self._uD_face(t_stage), self.rows)
         return (self.m(s) * self.M + self.theta[s] * (self.disc.nu * self.L + C)).tocsr()
 
     def pressure_matrix(self, s):
@@ -161,7 +169,7 @@ class TRBDF2:
         nu = d.nu
         if s == 1:
             th = self.theta[1]
-            A0 = d.explicit_advection(w)
+            A0 = d.explicit_advection(w, self.rows)
             F = (-th * nu * self.per_component(self.L0, u_n)
                  + th * self.per_component(A0, u_n))
             u_prev = u_n
@@ -169,8 +177,8 @@ class TRBDF2:
             a31, a32 = self.cst["a31"], self.cst["a32"]
             F = (-nu * a32 * self.per_component(self.L0, u_g)
                  - nu * a31 * self.per_component(self.L0, u_n)
-                 + a32 * self.per_component(d.explicit_advection(u_g), u_g)
-                 + a31 * self.per_component(d.explicit_advection(u_n), u_n))
+                 + a32 * self.per_component(d.explicit_advection(u_g, self.rows), u_g)
+                 + a31 * self.per_component(d.explicit_advection(u_n, self.rows), u_n))
             u_prev = u_g
         F = F + self.Gw @ p_prev
         if self.uD is not None and any(f[0] == "B" for f in d.faces()):

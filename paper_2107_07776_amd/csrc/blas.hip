@@ -5,6 +5,7 @@
 // work-group adds the partials in a fixed order.  The grid size does not
 // depend on timing, so results are bitwise reproducible run to run.
 #include "internal.hpp"
+#include "reduce.hpp"
 
 namespace trbdg {
 namespace {
@@ -18,24 +19,7 @@ inline unsigned grid_for(int64_t n) {
     return (unsigned)g;
 }
 
-__device__ inline double wave_sum(double v) {
-    for (int off = 32; off > 0; off >>= 1) v += __shfl_down(v, off, 64);
-    return v;
-}
-
-// Block-wide sum; valid in thread 0.
-__device__ inline double block_sum(double v) {
-    __shared__ double s_part[BS / 64];
-    v = wave_sum(v);
-    const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
-    if (lane == 0) s_part[wv] = v;
-    __syncthreads();
-    double r = 0.0;
-    if (threadIdx.x == 0)
-        for (int i = 0; i < BS / 64; ++i) r += s_part[i];
-    __syncthreads();
-    return r;
-}
+using red::block_sum;
 
 __global__ __launch_bounds__(BS) void k_axpby(int64_t n, double a, const double* x, double b,
                                               const double* y, double* out) {
@@ -156,6 +140,7 @@ __global__ void k_cg_beta_finish(const double* partial, int G, double* sc, int f
         sc[3] = rz;
         sc[5] = first ? 0.0 : rz / sc[0];
         sc[0] = rz;
+        if (first) sc[6] = 0.0;   // clear the breakdown flag of a previous solve
     }
 }
 
@@ -184,6 +169,111 @@ __global__ __launch_bounds__(BS) void k_cg_init_partials(int64_t n, const double
         partial[blockIdx.x] = rz;
         partial[gridDim.x + blockIdx.x] = rr;
     }
+}
+
+
+__global__ __launch_bounds__(BS) void k_recip(int64_t n, const double* d, double* out) {
+    for (int64_t i = (int64_t)blockIdx.x * BS + threadIdx.x; i < n; i += (int64_t)gridDim.x * BS)
+        out[i] = 1.0 / d[i];
+}
+
+// CG direction: p = r * invd + beta p   (beta = sc[5], 0 on the first iteration)
+__global__ __launch_bounds__(BS) void k_cg_dir(int64_t n, const double* invd, const double* r,
+                                               double* p, const double* sc) {
+    const double beta = sc[5];
+    for (int64_t i = (int64_t)blockIdx.x * BS + threadIdx.x; i < n; i += (int64_t)gridDim.x * BS)
+        p[i] = r[i] * invd[i] + beta * p[i];
+}
+
+// CG update with fused partial sums: x += alpha p, r -= alpha q,
+// partial rz = r.(invd r), rr = r.r (beta is formed by k_cg_beta_finish).
+__global__ __launch_bounds__(BS) void k_cg_upd(int64_t n, const double* invd, double* x, double* r,
+                                               const double* p, const double* q, const double* sc,
+                                               double* partial) {
+    const double alpha = sc[4];
+    double rz = 0.0, rr = 0.0;
+    for (int64_t i = (int64_t)blockIdx.x * BS + threadIdx.x; i < n; i += (int64_t)gridDim.x * BS) {
+        x[i] += alpha * p[i];
+        const double ri = r[i] - alpha * q[i];
+        r[i] = ri;
+        rz += ri * ri * invd[i];
+        rr += ri * ri;
+    }
+    rz = block_sum(rz);
+    rr = block_sum(rr);
+    if (threadIdx.x == 0) {
+        partial[blockIdx.x] = rz;
+        partial[gridDim.x + blockIdx.x] = rr;
+    }
+}
+
+// first CG direction: p = invd r, partial rz and rr
+__global__ __launch_bounds__(BS) void k_cg_start(int64_t n, const double* invd, const double* r,
+                                                 double* p, double* partial) {
+    double rz = 0.0, rr = 0.0;
+    for (int64_t i = (int64_t)blockIdx.x * BS + threadIdx.x; i < n; i += (int64_t)gridDim.x * BS) {
+        const double ri = r[i];
+        const double zi = ri * invd[i];
+        p[i] = zi;
+        rz += ri * zi;
+        rr += ri * ri;
+    }
+    rz = block_sum(rz);
+    rr = block_sum(rr);
+    if (threadIdx.x == 0) {
+        partial[blockIdx.x] = rz;
+        partial[gridDim.x + blockIdx.x] = rr;
+    }
+}
+
+// GMRES: V_j *= s; z = V_j * invd (velocity layout, invd per scalar node)
+__global__ __launch_bounds__(BS) void k_scale_precond(int64_t n, int dim, int64_t nb, double s,
+                                                      double* v, const double* invd, double* z) {
+    for (int64_t i = (int64_t)blockIdx.x * BS + threadIdx.x; i < n; i += (int64_t)gridDim.x * BS) {
+        const double vi = v[i] * s;
+        v[i] = vi;
+        z[i] = vi * invd[diag_index(i, dim, nb)];
+    }
+}
+
+// GMRES multi-dot: partial[j*G + b] = V_j . w over block b's slice for the
+// 8 vectors of group blockIdx.y; group 0 also sums w.w into slot k.
+__global__ __launch_bounds__(BS) void k_mdot8(int64_t n, int k, const double* V, int64_t ldv,
+                                              const double* w, double* partial) {
+    const int j0 = blockIdx.y * 8;
+    const int jn = min(8, k - j0);
+    const int G = gridDim.x;
+    double acc[8] = {0, 0, 0, 0, 0, 0, 0, 0};
+    double ww = 0.0;
+    for (int64_t i = (int64_t)blockIdx.x * BS + threadIdx.x; i < n; i += (int64_t)G * BS) {
+        const double wi = w[i];
+        if (blockIdx.y == 0) ww += wi * wi;
+#pragma unroll
+        for (int jj = 0; jj < 8; ++jj)
+            if (jj < jn) acc[jj] += V[(int64_t)(j0 + jj) * ldv + i] * wi;
+    }
+    for (int jj = 0; jj < 8; ++jj) {
+        const double s = block_sum(acc[jj]);
+        if (threadIdx.x == 0 && jj < jn) partial[(size_t)(j0 + jj) * G + blockIdx.x] = s;
+    }
+    if (blockIdx.y == 0) {
+        const double s = block_sum(ww);
+        if (threadIdx.x == 0) partial[(size_t)k * G + blockIdx.x] = s;
+    }
+}
+
+// GMRES update with fused norm partials: w -= sum_j h_j V_j, partial |w|^2
+__global__ __launch_bounds__(BS) void k_update_norm(int64_t n, int k, const double* V, int64_t ldv,
+                                                    const double* h, double* w, double* partial) {
+    double nn = 0.0;
+    for (int64_t i = (int64_t)blockIdx.x * BS + threadIdx.x; i < n; i += (int64_t)gridDim.x * BS) {
+        double s = w[i];
+        for (int j = 0; j < k; ++j) s -= h[j] * V[(int64_t)j * ldv + i];
+        w[i] = s;
+        nn += s * s;
+    }
+    nn = block_sum(nn);
+    if (threadIdx.x == 0) partial[blockIdx.x] = nn;
 }
 
 }  // namespace
@@ -246,6 +336,62 @@ void vec_add_combo(hipStream_t s, int64_t n, int k, const double* V, int64_t ldv
     TBDG_HIP(hipGetLastError());
 }
 
+void vec_recip(hipStream_t s, int64_t n, const double* d, double* out) {
+    hipLaunchKernelGGL(k_recip, dim3(grid_for(n)), dim3(BS), 0, s, n, d, out);
+    TBDG_HIP(hipGetLastError());
+}
+
+void cg_start(tbdg_ctx* c, int64_t n, const double* invd, const double* r, double* p, double* sc) {
+    const int G = reduce_grid(n, 4096);
+    hipLaunchKernelGGL(k_cg_start, dim3(G), dim3(BS), 0, c->stream, n, invd, r, p, c->red_part);
+    hipLaunchKernelGGL(k_cg_beta_finish, dim3(1), dim3(BS), 0, c->stream, c->red_part, G, sc, 1);
+    TBDG_HIP(hipGetLastError());
+}
+
+void cg_alpha_finish(const tbdg_ctx* c, int G, const double* partial, double* sc) {
+    hipLaunchKernelGGL(k_cg_alpha_finish, dim3(1), dim3(BS), 0, c->stream, partial, G, sc);
+    TBDG_HIP(hipGetLastError());
+}
+
+void cg_dir(tbdg_ctx* c, int64_t n, const double* invd, const double* r, double* p, const double* sc) {
+    hipLaunchKernelGGL(k_cg_dir, dim3(grid_for(n)), dim3(BS), 0, c->stream, n, invd, r, p, sc);
+    TBDG_HIP(hipGetLastError());
+}
+
+void cg_upd(tbdg_ctx* c, int64_t n, const double* invd, double* x, double* r, const double* p,
+            const double* q, double* sc) {
+    const int G = reduce_grid(n, 4096);
+    hipLaunchKernelGGL(k_cg_upd, dim3(G), dim3(BS), 0, c->stream, n, invd, x, r, p, q, sc,
+                       c->red_part);
+    hipLaunchKernelGGL(k_cg_beta_finish, dim3(1), dim3(BS), 0, c->stream, c->red_part, G, sc, 0);
+    TBDG_HIP(hipGetLastError());
+}
+
+void gm_scale_precond(tbdg_ctx* c, int64_t n, double s, double* v, const double* invd, double* z) {
+    hipLaunchKernelGGL(k_scale_precond, dim3(grid_for(n)), dim3(BS), 0, c->stream, n, c->dim,
+                       c->nbu, s, v, invd, z);
+    TBDG_HIP(hipGetLastError());
+}
+
+void gm_dots(tbdg_ctx* c, int64_t n, int k, const double* V, int64_t ldv, const double* w,
+             double* dev_out) {
+    const int groups = (k + 7) / 8;
+    const int G = reduce_grid(n, 4096);   // (k + 1) * G <= 62 * 4096 partial slots
+    hipLaunchKernelGGL(k_mdot8, dim3(G, groups), dim3(BS), 0, c->stream, n, k, V, ldv, w,
+                       c->red_part);
+    hipLaunchKernelGGL(k_finish, dim3(k + 1), dim3(BS), 0, c->stream, c->red_part, G, dev_out);
+    TBDG_HIP(hipGetLastError());
+}
+
+void gm_update_norm(tbdg_ctx* c, int64_t n, int k, const double* V, int64_t ldv, const double* h,
+                    double* w, double* dev_out) {
+    const int G = reduce_grid(n, 4096);
+    double* part = c->red_part + 62 * 4096;
+    hipLaunchKernelGGL(k_update_norm, dim3(G), dim3(BS), 0, c->stream, n, k, V, ldv, h, w, part);
+    hipLaunchKernelGGL(k_finish, dim3(1), dim3(BS), 0, c->stream, part, G, dev_out);
+    TBDG_HIP(hipGetLastError());
+}
+
 void cg_alpha(tbdg_ctx* c, int64_t n, const double* p, const double* q, double* sc) {
     const int G = reduce_grid(n, 1024);
     hipLaunchKernelGGL(k_dot_many, dim3(G, 1), dim3(BS), 0, c->stream, n, p, 0, q, c->red_part);
@@ -255,7 +401,7 @@ void cg_alpha(tbdg_ctx* c, int64_t n, const double* p, const double* q, double* 
 
 void cg_update(tbdg_ctx* c, int64_t n, const double* diag, double* x, double* r, const double* p,
                const double* q, double* sc) {
-    const int G = reduce_grid(n, 1024);
+    const int G = reduce_grid(n, 4096);
     hipLaunchKernelGGL(k_cg_update, dim3(G), dim3(BS), 0, c->stream, n, diag, x, r, p, q, sc,
                        c->red_part);
     hipLaunchKernelGGL(k_cg_beta_finish, dim3(1), dim3(BS), 0, c->stream, c->red_part, G, sc, 0);

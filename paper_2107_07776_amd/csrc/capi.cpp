@@ -8,6 +8,7 @@
 
 namespace trbdg {
 void build_tables(tbdg_ctx* c);
+void build_line_operators(tbdg_ctx* c);
 tbdg_status solve_momentum(tbdg_ctx* c, int s, const double* w, const double* b, double* x,
                            const tbdg_solver_opts& o, tbdg_solve_info* info);
 tbdg_status solve_pressure(tbdg_ctx* c, int s, const double* b, double* x,
@@ -69,8 +70,15 @@ void free_all(tbdg_ctx* c) {
     dfree(c->cr);
     dfree(c->cp);
     dfree(c->cq);
+    dfree(c->cp2);
     dfree(c->red_part);
     dfree(c->red_out);
+    dfree(c->invd_u);
+    dfree(c->red_op);
+    dfree(c->invd_p[1]);
+    dfree(c->invd_p[2]);
+    if (c->counters) (void)hipFree(c->counters);
+    c->counters = nullptr;
     if (c->host_out) (void)hipHostFree(c->host_out);
     c->host_out = nullptr;
     dfree(c->s_w);
@@ -173,6 +181,7 @@ tbdg_status tbdg_create(const tbdg_mesh_desc* mesh, const tbdg_disc_desc* disc, 
         }
         c->stream = static_cast<hipStream_t>(stream);
         trbdg::build_tables(c);
+        trbdg::build_line_operators(c);
         // workspaces
         c->gm_m = GMRES_MAX;
         c->diag_p[1] = dalloc(c->Np);
@@ -184,9 +193,21 @@ tbdg_status tbdg_create(const tbdg_mesh_desc* mesh, const tbdg_disc_desc* disc, 
         c->cr = dalloc(c->Np);
         c->cp = dalloc(c->Np);
         c->cq = dalloc(c->Np);
-        c->red_blocks = 64 * 1024;
+        c->cp2 = dalloc(c->Np);
+        c->red_blocks = 64 * 4096;
         c->red_part = dalloc(c->red_blocks);
         c->red_out = dalloc(128);
+        {
+            void* cp = nullptr;
+            TBDG_HIP(hipMalloc(&cp, sizeof(unsigned) * 16));
+            c->counters = static_cast<unsigned*>(cp);
+            TBDG_HIP(hipMemsetAsync(c->counters, 0, sizeof(unsigned) * 16, c->stream));
+        }
+        c->red_op_len = c->Nc + 1;   // at least one slot per block of any operator kernel
+        c->red_op = dalloc(c->red_op_len);
+        c->invd_u = dalloc(c->Ns);
+        c->invd_p[1] = dalloc(c->Np);
+        c->invd_p[2] = dalloc(c->Np);
         void* h = nullptr;
         TBDG_HIP(hipHostMalloc(&h, sizeof(double) * 128, hipHostMallocDefault));
         c->host_out = static_cast<double*>(h);
@@ -201,6 +222,8 @@ tbdg_status tbdg_create(const tbdg_mesh_desc* mesh, const tbdg_disc_desc* disc, 
         c->s_pv = dalloc(c->Ns);
         trbdg::launch_diag_pressure(c, c->alpha(1), c->diag_p[1]);
         trbdg::launch_diag_pressure(c, c->alpha(2), c->diag_p[2]);
+        trbdg::vec_recip(c->stream, c->Np, c->diag_p[1], c->invd_p[1]);
+        trbdg::vec_recip(c->stream, c->Np, c->diag_p[2], c->invd_p[2]);
         TBDG_HIP(hipStreamSynchronize(c->stream));
         return TBDG_OK;
     });

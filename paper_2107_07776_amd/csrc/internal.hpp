@@ -36,6 +36,25 @@ struct Geom {
     double vol;     // |K|
 };
 
+// Element matrices of the one-dimensional SIP form on a reference cell of
+// unit length (row i = test function, column j = trial function, stride n):
+// A = cell stiffness + self terms of both end faces; F0/F1 = self terms of
+// the left/right end face (subtracted where that face is a boundary);
+// Lm/Rm = coupling to the left/right neighbour's basis.
+// WD[m*n + i] = W_m l_i'(x_m) (volume advection weights).
+struct Line1D {
+    double A[NMAX * NMAX], F0[NMAX * NMAX], F1[NMAX * NMAX], Lm[NMAX * NMAX], Rm[NMAX * NMAX];
+    double WD[NMAX * NMAX];
+};
+
+// Per-direction scale factors of the line operators on the affine box:
+// sdiff[a] = |K| / h_a^2 (SIP), sadv[a] = |K| / h_a (advection).
+struct LineGeom {
+    int periodic[3];
+    double sdiff[3], sadv[3];
+    double inv_nc[3];   // 1 / cells per direction (fast index division)
+};
+
 struct Error : std::runtime_error {
     tbdg_status status;
     Error(tbdg_status s, const std::string& m) : std::runtime_error(m), status(s) {}
@@ -65,10 +84,13 @@ struct tbdg_ctx {
     int64_t Nc = 0, nbu = 0, nbp = 0, Nu = 0, Np = 0, Ns = 0;  // Ns = Nu / dim
     trbdg::Geom geom{};
     trbdg::Tables tab{};
+    trbdg::LineGeom lgeom{};
+    trbdg::Line1D line_u{}, line_p{};
     double nu = 0, c = 0, dt = 0, gamma = 0, pen_u = 1, pen_p = 1;
     double a31 = 0, a32 = 0, a33 = 0;
     double beta[3] = {0, 0, 0}, theta[3] = {0, 0, 0};
     double sig_u[3] = {0, 0, 0}, sig_p[3] = {0, 0, 0};   // penalties per face direction
+    double cr_u = 0, cr_p = 0;   // reference-cell penalties (k+1)^2 pen_u, k^2 pen_p
     int periodic_flags[3] = {1, 1, 1};
     hipStream_t stream = nullptr;
     std::string last_error;
@@ -86,10 +108,16 @@ struct tbdg_ctx {
     double* cr = nullptr;
     double* cp = nullptr;
     double* cq = nullptr;
+    double* cp2 = nullptr;      // second CG direction buffer (ping-pong)
     // reductions
     double* red_part = nullptr;     // partial sums
     int red_blocks = 0;
     double* red_out = nullptr;      // device scalars
+    unsigned* counters = nullptr;   // last-block tickets (zero between launches)
+    double* red_op = nullptr;       // per-block partials of operator kernels (one slot per block)
+    int64_t red_op_len = 0;
+    double* invd_u = nullptr;       // 1 / momentum diagonal (Ns)
+    double* invd_p[3] = {nullptr, nullptr, nullptr};
     double* host_out = nullptr;     // pinned host mirror
     // step scratch
     double* s_w = nullptr;
@@ -125,15 +153,19 @@ void launch_rhs_pressure(const tbdg_ctx* c, double alpha, double fcoef, const do
                          const double* p_prev, double* rhs);
 void launch_node_coords(const tbdg_ctx* c, int field, double* xyz);
 
-// Brackets one launch with events when the context's timer is on.
+// Start/stop events for one kernel launched with hipExtLaunchKernelGGL when
+// the context's timer is on (the runtime timestamps the dispatch itself, so
+// the interval is the kernel's execution); null events otherwise.
 class TimedLaunch {
   public:
     TimedLaunch(const tbdg_ctx* c, int which);
     ~TimedLaunch();
+    hipEvent_t start() const { return e1_; }
+    hipEvent_t stop() const { return e2_; }
   private:
     const tbdg_ctx* c_;
     int which_;
-    hipEvent_t e1_ = nullptr;
+    hipEvent_t e1_ = nullptr, e2_ = nullptr;
 };
 void timer_collect(const tbdg_ctx* c);
 void timer_release(const tbdg_ctx* c);
@@ -165,6 +197,21 @@ void cg_update(tbdg_ctx* c, int64_t n, const double* diag, double* x, double* r,
 void cg_direction(hipStream_t s, int64_t n, const double* diag, const double* r, double* p,
                   const double* sc);
 void cg_init(tbdg_ctx* c, int64_t n, const double* diag, const double* r, double* p, double* sc);
+void vec_recip(hipStream_t s, int64_t n, const double* d, double* out);
+void cg_start(tbdg_ctx* c, int64_t n, const double* invd, const double* r, double* p, double* sc);
+void cg_dir(tbdg_ctx* c, int64_t n, const double* invd, const double* r, double* p, const double* sc);
+void cg_upd(tbdg_ctx* c, int64_t n, const double* invd, double* x, double* r, const double* p,
+            const double* q, double* sc);
+void cg_alpha_finish(const tbdg_ctx* c, int G, const double* partial, double* sc);
+// One fused CG operator step: p_new = r invd + sc[5] p_old, q = H p_new and
+// the step length sc[4] = sc[0] / (p_new . q).  p_new must not alias p_old.
+void launch_cg_apply(const tbdg_ctx* c, double alpha, const double* r, const double* invd,
+                     const double* p_old, double* p_new, double* q, double* sc);
+void gm_scale_precond(tbdg_ctx* c, int64_t n, double s, double* v, const double* invd, double* z);
+void gm_dots(tbdg_ctx* c, int64_t n, int k, const double* V, int64_t ldv, const double* w,
+             double* dev_out);
+void gm_update_norm(tbdg_ctx* c, int64_t n, int k, const double* V, int64_t ldv, const double* h,
+                    double* w, double* dev_out);
 // x += gz / diag (velocity layout)
 void vec_add_div_diag_u(hipStream_t s, int64_t n, int dim, int64_t nb, const double* gz,
                         const double* d, double* x);

@@ -83,288 +83,6 @@ struct Periodic {
 };
 
 // ============================================================================
-// Pressure: y = alpha M^p p + K p  (K: SIP form a_p, interior faces only)
-// ============================================================================
-template <int DIM, int NP>
-__global__ __launch_bounds__(256) void k_apply_pressure(Geom g, Periodic per, Tables t,
-                                                         double alpha, double s0, double s1,
-                                                         double s2, const double* __restrict__ p,
-                                                         double* __restrict__ y, int64_t Nc) {
-    using Lay = Layout<DIM, NP>;
-    constexpr int NB = Lay::NB, NF = Lay::NF, CPB = Lay::CPB;
-    __shared__ double s_p[CPB * NB];
-    __shared__ double s_f[DIM][CPB * NB];
-    __shared__ double s_face[CPB][2 * DIM][NF][2];
-    const double sig[3] = {s0, s1, s2};
-    const int tid = threadIdx.x;
-    const int lc = tid / NB, nd = tid % NB;
-    const int64_t cell = (int64_t)blockIdx.x * CPB + lc;
-    const bool active = cell < Nc;
-    const double* D = t.Dp;
-    s_p[tid] = active ? p[cell * NB + nd] : 0.0;
-    __syncthreads();
-    double acc = 0.0;
-    const double Wi = node_weight<DIM, NP>(t.Wp, nd);
-    // volume: stiffness fluxes at the quadrature (= node) points
-    for (int a = 0; a < DIM; ++a) {
-        const int ia = Lay::coord(nd, a), tt = Lay::tang(nd, a);
-        double ga = 0.0;
-#pragma unroll
-        for (int m = 0; m < NP; ++m) ga += D[ia * NP + m] * s_p[lc * NB + Lay::node(a, m, tt)];
-        s_f[a][tid] = g.vol * Wi * ga / (g.h[a] * g.h[a]);
-    }
-    acc += alpha * g.vol * Wi * s_p[tid];
-    // face fluxes, one item per (face, tangential point)
-    for (int it = nd; it < 2 * DIM * NF; it += NB) {
-        const int a = it / (2 * NF), s = (it / NF) % 2, tt = it % NF;
-        double v0 = 0, d0 = 0, v1 = 0, d1 = 0;
-        const double* Ls = s ? t.L1p : t.L0p;
-        const double* dLs = s ? t.dL1p : t.dL0p;
-        const double* Ln = s ? t.L0p : t.L1p;
-        const double* dLn = s ? t.dL0p : t.dL1p;
-        const double sg = s ? 1.0 : -1.0;
-        double val = 0.0, grd = 0.0;
-        const int64_t nb = active ? neighbor<DIM>(g, per.p, cell, a, s) : -1;
-        if (nb >= 0) {
-#pragma unroll
-            for (int m = 0; m < NP; ++m) {
-                const double po = s_p[lc * NB + Lay::node(a, m, tt)];
-                const double pn = p[nb * NB + Lay::node(a, m, tt)];
-                v0 += Ls[m] * po;
-                d0 += dLs[m] * po;
-                v1 += Ln[m] * pn;
-                d1 += dLn[m] * pn;
-            }
-            const double inv_h = 1.0 / g.h[a];
-            const double jump = v0 - v1;
-            const double gavg = 0.5 * sg * (d0 + d1) * inv_h;
-            const double dS = g.vol * inv_h * tang_weight<DIM, NP>(t.Wp, tt);
-            val = (-gavg + sig[a] * jump) * dS;
-            grd = -0.5 * jump * dS;
-        }
-        s_face[lc][a * 2 + s][tt][0] = val;
-        s_face[lc][a * 2 + s][tt][1] = grd;
-    }
-    __syncthreads();
-    for (int a = 0; a < DIM; ++a) {
-        const int ia = Lay::coord(nd, a), tt = Lay::tang(nd, a);
-        double sum = 0.0;
-#pragma unroll
-        for (int m = 0; m < NP; ++m) sum += D[m * NP + ia] * s_f[a][lc * NB + Lay::node(a, m, tt)];
-        acc += sum;
-        const double inv_h = 1.0 / g.h[a];
-        acc += s_face[lc][a * 2][tt][0] * t.L0p[ia] - s_face[lc][a * 2][tt][1] * t.dL0p[ia] * inv_h;
-        acc += s_face[lc][a * 2 + 1][tt][0] * t.L1p[ia] + s_face[lc][a * 2 + 1][tt][1] * t.dL1p[ia] * inv_h;
-    }
-    if (active) y[cell * NB + nd] = acc;
-}
-
-template <int DIM, int NP>
-__global__ __launch_bounds__(256) void k_diag_pressure(Geom g, Periodic per, Tables t,
-                                                        double alpha, double s0, double s1,
-                                                        double s2, double* __restrict__ d,
-                                                        int64_t Nc) {
-    using Lay = Layout<DIM, NP>;
-    constexpr int NB = Lay::NB;
-    const double sig[3] = {s0, s1, s2};
-    const int64_t gid = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (gid >= Nc * NB) return;
-    const int64_t cell = gid / NB;
-    const int nd = (int)(gid % NB);
-    const double* D = t.Dp;
-    double acc = alpha * g.vol * node_weight<DIM, NP>(t.Wp, nd);
-    for (int a = 0; a < DIM; ++a) {
-        const int ia = Lay::coord(nd, a), tt = Lay::tang(nd, a);
-        double s2sum = 0.0;
-        for (int m = 0; m < NP; ++m) s2sum += t.Wp[m] * D[m * NP + ia] * D[m * NP + ia];
-        const double inv_h = 1.0 / g.h[a];
-        const double wt = tang_weight<DIM, NP>(t.Wp, tt);
-        acc += g.vol * inv_h * inv_h * wt * s2sum;
-        const double dS = g.vol * inv_h * wt;
-        for (int s = 0; s < 2; ++s) {
-            const int64_t nb = neighbor<DIM>(g, per.p, cell, a, s);
-            if (nb < 0) continue;
-            const double sg = s ? 1.0 : -1.0;
-            const double L = s ? t.L1p[ia] : t.L0p[ia];
-            const double dL = sg * (s ? t.dL1p[ia] : t.dL0p[ia]) * inv_h;
-            acc += dS * (-dL * L + sig[a] * L * L);
-            if (nb == cell) {
-                // a single cell across a periodic direction is its own neighbour:
-                // the neighbour-trace coupling then lands on the diagonal too
-                const double Ln = s ? t.L0p[ia] : t.L1p[ia];
-                const double dLn = sg * (s ? t.dL0p[ia] : t.dL1p[ia]) * inv_h;
-                acc += dS * (-0.5 * dLn * L + 0.5 * Ln * dL - sig[a] * Ln * L);
-            }
-        }
-    }
-    d[gid] = acc;
-}
-
-// ============================================================================
-// Momentum: y_c = m M u_c + theta (nu A u_c + C(w) u_c), every component c
-// ============================================================================
-template <int DIM, int N>
-__global__ __launch_bounds__(256) void k_apply_momentum(Geom g, Periodic per, Tables t,
-                                                         double mcoef, double tnu, double th,
-                                                         double s0, double s1, double s2,
-                                                         const double* __restrict__ w,
-                                                         const double* __restrict__ u,
-                                                         double* __restrict__ y, int64_t Nc) {
-    using Lay = Layout<DIM, N>;
-    constexpr int NB = Lay::NB, NF = Lay::NF, CPB = Lay::CPB;
-    __shared__ double s_w[DIM][CPB * NB];
-    __shared__ double s_u[DIM][CPB * NB];
-    __shared__ double s_f[DIM][CPB * NB];
-    __shared__ double s_wf[CPB][2 * DIM][NF][3];
-    __shared__ double s_face[CPB][2 * DIM][NF][2];
-    const double sig[3] = {s0, s1, s2};
-    const int tid = threadIdx.x;
-    const int lc = tid / NB, nd = tid % NB;
-    const int64_t cell = (int64_t)blockIdx.x * CPB + lc;
-    const bool active = cell < Nc;
-    const double* D = t.Du;
-    for (int c = 0; c < DIM; ++c) {
-        s_w[c][tid] = active ? w[(cell * DIM + c) * NB + nd] : 0.0;
-        s_u[c][tid] = active ? u[(cell * DIM + c) * NB + nd] : 0.0;
-    }
-    __syncthreads();
-    // normal advecting speeds and LF speed at every face point
-    for (int it = nd; it < 2 * DIM * NF; it += NB) {
-        const int a = it / (2 * NF), s = (it / NF) % 2, tt = it % NF;
-        const double* Ls = s ? t.L1u : t.L0u;
-        const double* Ln = s ? t.L0u : t.L1u;
-        const double sg = s ? 1.0 : -1.0;
-        const int64_t nb = active ? neighbor<DIM>(g, per.p, cell, a, s) : -1;
-        double wo = 0.0, wn = 0.0;
-#pragma unroll
-        for (int m = 0; m < N; ++m) wo += Ls[m] * s_w[a][lc * NB + Lay::node(a, m, tt)];
-        if (nb >= 0) {
-#pragma unroll
-            for (int m = 0; m < N; ++m) wn += Ln[m] * w[(nb * DIM + a) * NB + Lay::node(a, m, tt)];
-        }
-        wo *= sg;
-        wn *= sg;
-        s_wf[lc][a * 2 + s][tt][0] = wo;
-        s_wf[lc][a * 2 + s][tt][1] = wn;
-        s_wf[lc][a * 2 + s][tt][2] = fmax(fabs(wo), fabs(wn));
-    }
-    const double Wi = node_weight<DIM, N>(t.Wu, nd);
-    for (int c = 0; c < DIM; ++c) {
-        const double uc = s_u[c][tid];
-        for (int a = 0; a < DIM; ++a) {
-            const int ia = Lay::coord(nd, a), tt = Lay::tang(nd, a);
-            double ga = 0.0;
-#pragma unroll
-            for (int m = 0; m < N; ++m) ga += D[ia * N + m] * s_u[c][lc * NB + Lay::node(a, m, tt)];
-            const double inv_h = 1.0 / g.h[a];
-            s_f[a][tid] = g.vol * Wi * inv_h * (tnu * ga * inv_h - th * uc * s_w[a][tid]);
-        }
-        double acc = mcoef * g.vol * Wi * uc;
-        __syncthreads();
-        for (int it = nd; it < 2 * DIM * NF; it += NB) {
-            const int a = it / (2 * NF), s = (it / NF) % 2, tt = it % NF;
-            const double* Ls = s ? t.L1u : t.L0u;
-            const double* dLs = s ? t.dL1u : t.dL0u;
-            const double* Ln = s ? t.L0u : t.L1u;
-            const double* dLn = s ? t.dL0u : t.dL1u;
-            const double sg = s ? 1.0 : -1.0;
-            const int64_t nb = active ? neighbor<DIM>(g, per.p, cell, a, s) : -1;
-            double val = 0.0, grd = 0.0;
-            if (nb >= 0) {
-                double v0 = 0, d0 = 0, v1 = 0, d1 = 0;
-#pragma unroll
-                for (int m = 0; m < N; ++m) {
-                    const double uo = s_u[c][lc * NB + Lay::node(a, m, tt)];
-                    const double un = u[(nb * DIM + c) * NB + Lay::node(a, m, tt)];
-                    v0 += Ls[m] * uo;
-                    d0 += dLs[m] * uo;
-                    v1 += Ln[m] * un;
-                    d1 += dLn[m] * un;
-                }
-                const double inv_h = 1.0 / g.h[a];
-                const double jump = v0 - v1;
-                const double gavg = 0.5 * sg * (d0 + d1) * inv_h;
-                const double wo = s_wf[lc][a * 2 + s][tt][0];
-                const double wn = s_wf[lc][a * 2 + s][tt][1];
-                const double lam = s_wf[lc][a * 2 + s][tt][2];
-                const double flf = 0.5 * (v0 * wo + v1 * wn) + 0.5 * lam * jump;
-                const double dS = g.vol * inv_h * tang_weight<DIM, N>(t.Wu, tt);
-                val = (tnu * (-gavg + sig[a] * jump) + th * flf) * dS;
-                grd = -0.5 * tnu * jump * dS;
-            }
-            s_face[lc][a * 2 + s][tt][0] = val;
-            s_face[lc][a * 2 + s][tt][1] = grd;
-        }
-        __syncthreads();
-        for (int a = 0; a < DIM; ++a) {
-            const int ia = Lay::coord(nd, a), tt = Lay::tang(nd, a);
-            double sum = 0.0;
-#pragma unroll
-            for (int m = 0; m < N; ++m) sum += D[m * N + ia] * s_f[a][lc * NB + Lay::node(a, m, tt)];
-            acc += sum;
-            const double inv_h = 1.0 / g.h[a];
-            acc += s_face[lc][a * 2][tt][0] * t.L0u[ia] - s_face[lc][a * 2][tt][1] * t.dL0u[ia] * inv_h;
-            acc += s_face[lc][a * 2 + 1][tt][0] * t.L1u[ia] + s_face[lc][a * 2 + 1][tt][1] * t.dL1u[ia] * inv_h;
-        }
-        if (active) y[(cell * DIM + c) * NB + nd] = acc;
-        __syncthreads();
-    }
-}
-
-template <int DIM, int N>
-__global__ __launch_bounds__(256) void k_diag_momentum(Geom g, Periodic per, Tables t,
-                                                        double mcoef, double tnu, double th,
-                                                        double s0, double s1, double s2,
-                                                        const double* __restrict__ w,
-                                                        double* __restrict__ d, int64_t Nc) {
-    using Lay = Layout<DIM, N>;
-    constexpr int NB = Lay::NB;
-    const double sig[3] = {s0, s1, s2};
-    const int64_t gid = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (gid >= Nc * NB) return;
-    const int64_t cell = gid / NB;
-    const int nd = (int)(gid % NB);
-    const double* D = t.Du;
-    const double Wi = node_weight<DIM, N>(t.Wu, nd);
-    double acc = mcoef * g.vol * Wi;
-    for (int a = 0; a < DIM; ++a) {
-        const int ia = Lay::coord(nd, a), tt = Lay::tang(nd, a);
-        const double inv_h = 1.0 / g.h[a];
-        const double wt = tang_weight<DIM, N>(t.Wu, tt);
-        double s2sum = 0.0;
-        for (int m = 0; m < N; ++m) s2sum += t.Wu[m] * D[m * N + ia] * D[m * N + ia];
-        acc += tnu * g.vol * inv_h * inv_h * wt * s2sum;
-        acc -= th * g.vol * Wi * w[(cell * DIM + a) * NB + nd] * D[ia * N + ia] * inv_h;
-        const double dS = g.vol * inv_h * wt;
-        for (int s = 0; s < 2; ++s) {
-            const int64_t nb = neighbor<DIM>(g, per.p, cell, a, s);
-            if (nb < 0) continue;
-            const double* Ls = s ? t.L1u : t.L0u;
-            const double* Ln = s ? t.L0u : t.L1u;
-            const double sg = s ? 1.0 : -1.0;
-            double wo = 0.0, wn = 0.0;
-            for (int m = 0; m < N; ++m) {
-                wo += Ls[m] * w[(cell * DIM + a) * NB + Lay::node(a, m, tt)];
-                wn += Ln[m] * w[(nb * DIM + a) * NB + Lay::node(a, m, tt)];
-            }
-            wo *= sg;
-            wn *= sg;
-            const double lam = fmax(fabs(wo), fabs(wn));
-            const double L = Ls[ia];
-            const double dL = sg * (s ? t.dL1u[ia] : t.dL0u[ia]) * inv_h;
-            acc += dS * (tnu * (-dL * L + sig[a] * L * L) + th * 0.5 * (wo + lam) * L * L);
-            if (nb == cell) {
-                const double Lo = Ln[ia];
-                const double dLo = sg * (s ? t.dL0u[ia] : t.dL1u[ia]) * inv_h;
-                acc += dS * (tnu * (-0.5 * dLo * L + 0.5 * Lo * dL - sig[a] * Lo * L) +
-                             th * 0.5 * (wn - lam) * Lo * L);
-            }
-        }
-    }
-    d[gid] = acc;
-}
-
-// ============================================================================
 // Pressure interpolated to the velocity nodes (exact: Q_{k-1} is contained in
 // the span of the velocity Lagrange basis).  pv: [cell][velocity node].
 // ============================================================================
@@ -692,58 +410,6 @@ inline Periodic periodic_of(const tbdg_ctx* c) {
         else if (d_ == 3 && n_ == 4) { FN(3, 4); }                                        \
         else throw Error(TBDG_EUNSUPPORTED, "unsupported (dim, degree)");                 \
     } while (0)
-
-void launch_apply_pressure(const tbdg_ctx* c, double alpha, const double* p, double* y) {
-    TimedLaunch tl(c, 0);
-#define L_(D, N)                                                                          \
-    {                                                                                     \
-        using Lay = Layout<D, N - 1>;                                                     \
-        hipLaunchKernelGGL((k_apply_pressure<D, N - 1>), dim3(nblocks(c->Nc, Lay::CPB)),  \
-                           dim3(Lay::THREADS), 0, c->stream, c->geom, periodic_of(c),     \
-                           c->tab, alpha, c->sig_p[0], c->sig_p[1], c->sig_p[2], p, y,    \
-                           c->Nc);                                                        \
-    }
-    TBDG_DISPATCH(c, L_);
-#undef L_
-    TBDG_HIP(hipGetLastError());
-}
-
-void launch_diag_pressure(const tbdg_ctx* c, double alpha, double* d) {
-#define L_(D, N)                                                                          \
-    hipLaunchKernelGGL((k_diag_pressure<D, N - 1>), dim3(nblocks(c->Np, 256)), dim3(256), \
-                       0, c->stream, c->geom, periodic_of(c), c->tab, alpha, c->sig_p[0], \
-                       c->sig_p[1], c->sig_p[2], d, c->Nc);
-    TBDG_DISPATCH(c, L_);
-#undef L_
-    TBDG_HIP(hipGetLastError());
-}
-
-void launch_apply_momentum(const tbdg_ctx* c, double mcoef, double theta, const double* w,
-                           const double* u, double* y) {
-    TimedLaunch tl(c, 1);
-#define L_(D, N)                                                                          \
-    {                                                                                     \
-        using Lay = Layout<D, N>;                                                         \
-        hipLaunchKernelGGL((k_apply_momentum<D, N>), dim3(nblocks(c->Nc, Lay::CPB)),      \
-                           dim3(Lay::THREADS), 0, c->stream, c->geom, periodic_of(c),     \
-                           c->tab, mcoef, theta * c->nu, theta, c->sig_u[0], c->sig_u[1], \
-                           c->sig_u[2], w, u, y, c->Nc);                                  \
-    }
-    TBDG_DISPATCH(c, L_);
-#undef L_
-    TBDG_HIP(hipGetLastError());
-}
-
-void launch_diag_momentum(const tbdg_ctx* c, double mcoef, double theta, const double* w,
-                          double* d) {
-#define L_(D, N)                                                                          \
-    hipLaunchKernelGGL((k_diag_momentum<D, N>), dim3(nblocks(c->Ns, 256)), dim3(256), 0,  \
-                       c->stream, c->geom, periodic_of(c), c->tab, mcoef, theta * c->nu,  \
-                       theta, c->sig_u[0], c->sig_u[1], c->sig_u[2], w, d, c->Nc);
-    TBDG_DISPATCH(c, L_);
-#undef L_
-    TBDG_HIP(hipGetLastError());
-}
 
 void launch_rhs_momentum(const tbdg_ctx* c, double mcoef, const double* u_prev,
                          const double* u1, const double* w1, double cd1, double ca1,

@@ -1,0 +1,700 @@
+// Line-structured operator kernels for affine Cartesian boxes.
+//
+// With a Lagrange basis collocated at the Gauss points, the tangential mass
+// of every volume and face integral is diagonal, so on a box with cell size
+// h_a per direction every form of Sec. 3 splits into a sum over directions a
+// of one-dimensional operators acting along the grid line through a node:
+//
+//   SIP (eq. bilin_diff, a_p):  sum_a |K|/h_a^2 * Wt_a(node) *
+//                               [ A p(own line) + Lm p(left line) + Rm p(right line) ]
+//   LF advection (eq. trilinear): sum_a |K|/h_a * Wt_a(node) *
+//       [ -sum_m W_m u(m) w_a(m) l_i'(x_m) + l_i(0) F_left + l_i(1) F_right ]
+//
+// where A, Lm, Rm are the n x n element matrices of the 1D SIP form (cell
+// stiffness plus the self and neighbour terms of the two end faces, reference
+// cell of unit length), Wt_a is the product of the Gauss weights in the
+// directions other than a, and F are the local Lax-Friedrichs fluxes at the
+// two ends of the line.  Each thread owns one node and evaluates its row of
+// every 1D operator directly: no face buffer, no block-wide exchange beyond
+// the staging of its own cell.
+#include "internal.hpp"
+#include "reduce.hpp"
+
+#include <hip/hip_ext.h>
+
+namespace trbdg {
+namespace {
+
+constexpr int ipow(int b, int e) { return e == 0 ? 1 : b * ipow(b, e - 1); }
+
+template <int DIM, int N>
+struct Lay {
+    static constexpr int NB = ipow(N, DIM);
+    static constexpr int CPB = (256 / NB) > 0 ? (256 / NB) : 1;
+    static constexpr int THREADS = CPB * NB;
+    __device__ static inline int node(int a, int m, int t) {
+        if (DIM == 2) return a == 0 ? m + N * t : t + N * m;
+        if (a == 0) return m + N * t;
+        if (a == 1) return (t % N) + N * m + N * N * (t / N);
+        return t + N * N * m;
+    }
+    __device__ static inline int coord(int nd, int a) {
+        return a == 0 ? nd % N : (a == 1 ? (nd / N) % N : nd / (N * N));
+    }
+    __device__ static inline int tang(int nd, int a) {
+        if (DIM == 2) return a == 0 ? nd / N : nd % N;
+        if (a == 0) return nd / N;
+        if (a == 1) return (nd % N) + N * (nd / (N * N));
+        return nd % (N * N);
+    }
+    __device__ static inline double wtan(const double* W, int t) {
+        return DIM == 2 ? W[t] : W[t % N] * W[t / N];
+    }
+    __device__ static inline double wnode(const double* W, int nd) {
+        double w = 1.0;
+        for (int a = 0; a < DIM; ++a) w *= W[coord(nd, a)];
+        return w;
+    }
+};
+
+// q = r / n for 0 <= r < 2^31 from a double reciprocal, corrected to exact.
+__device__ inline int div_fast(int r, int n, double inv_n) {
+    int q = (int)((double)r * inv_n);
+    if (q * n > r) --q;
+    else if ((q + 1) * n <= r) ++q;
+    return q;
+}
+
+// Cell coordinates and the two neighbours of a cell along every direction.
+template <int DIM>
+struct Nbrs {
+    int left[3], right[3];
+    __device__ Nbrs(const Geom& g, const LineGeom& lg, int cell) {
+        int r = cell;
+        int stride = 1;
+        for (int a = 0; a < DIM; ++a) {
+            const int n = g.nc[a];
+            const int q = div_fast(r, n, lg.inv_nc[a]);
+            const int ca = r - q * n;
+            r = q;
+            left[a] = ca > 0 ? cell - stride : (lg.periodic[a] ? cell + (n - 1) * stride : -1);
+            right[a] = ca < n - 1 ? cell + stride : (lg.periodic[a] ? cell - (n - 1) * stride : -1);
+            stride *= n;
+        }
+    }
+};
+
+// ============================================================================
+// Pressure Helmholtz operator y = alpha M^p p + K p
+// ============================================================================
+// MODE 0: y = H p; MODE 1: y = diag(H); MODE 2: y = H p and, fused, one
+// partial sum of p . y per block (the CG step length is formed by a separate
+// one-block kernel: a grid-wide fence per block costs more than a launch on
+// a multi-XCD device).
+template <int DIM, int NP, int MODE>
+__global__ __launch_bounds__(256) void k_pressure_line(Geom g, LineGeom lg, Line1D lt, Tables t,
+                                                        double cm, const double* __restrict__ p,
+                                                        double* __restrict__ y, int Nc,
+                                                        double* partial) {
+    using L = Lay<DIM, NP>;
+    constexpr int NB = L::NB;
+    constexpr int NN = NP * NP;
+    constexpr bool DIAG = MODE == 1;
+    // the 1D element matrices are indexed by the thread's own node: stage
+    // them in LDS rather than gathering from the kernel-argument segment
+    __shared__ double s_m[5 * NN + NP];
+    for (int i = threadIdx.x; i < 5 * NN + NP; i += blockDim.x) {
+        const int mtx = i / NN, e = i % NN;
+        s_m[i] = mtx == 0 ? lt.A[e] : mtx == 1 ? lt.F0[e] : mtx == 2 ? lt.F1[e] : mtx == 3 ? lt.Lm[e]
+               : mtx == 4 ? lt.Rm[e] : t.Wp[e];
+    }
+    __syncthreads();
+    const double* Wp = s_m + 5 * NN;
+    const double* A = s_m;
+    const double* F0 = s_m + NN;
+    const double* F1 = s_m + 2 * NN;
+    const double* Lm = s_m + 3 * NN;
+    const double* Rm = s_m + 4 * NN;
+    const int gid = blockIdx.x * 256 + threadIdx.x;
+    if (MODE != 2 && gid >= Nc * NB) return;
+    const bool active = gid < Nc * NB;
+    const int cell = active ? gid / NB : 0, nd = active ? gid % NB : 0;
+    const Nbrs<DIM> nb(g, lg, cell);
+    double acc = cm * L::wnode(Wp, nd) * (DIAG ? 1.0 : (active ? p[gid] : 0.0));
+    for (int a = 0; a < DIM; ++a) {
+        const int ia = L::coord(nd, a), tt = L::tang(nd, a);
+        const int lf = nb.left[a], rt = nb.right[a];
+        double s = 0.0;
+        if (!active) {
+        } else if (DIAG) {
+            s = A[ia * NP + ia];
+            if (lf < 0) s -= F0[ia * NP + ia];
+            if (rt < 0) s -= F1[ia * NP + ia];
+            if (lf == cell) s += Lm[ia * NP + ia];
+            if (rt == cell) s += Rm[ia * NP + ia];
+        } else {
+#pragma unroll
+            for (int j = 0; j < NP; ++j) {
+                const int idx = L::node(a, j, tt);
+                double c = A[ia * NP + j];
+                if (lf < 0) c -= F0[ia * NP + j];
+                if (rt < 0) c -= F1[ia * NP + j];
+                s += c * p[cell * NB + idx];
+                if (lf >= 0) s += Lm[ia * NP + j] * p[lf * NB + idx];
+                if (rt >= 0) s += Rm[ia * NP + j] * p[rt * NB + idx];
+            }
+        }
+        acc += lg.sdiff[a] * L::wtan(Wp, tt) * s;
+    }
+    if (active) y[gid] = acc;
+    if (MODE == 2) {
+        const double pq = red::block_sum(active ? acc * p[gid] : 0.0);
+        if (threadIdx.x == 0) partial[blockIdx.x] = pq;
+    }
+}
+
+// ============================================================================
+// Momentum operator y_c = m M u_c + theta (nu A u_c + C(w) u_c), all c
+// ============================================================================
+template <int DIM, int N, bool DIAG>
+__global__ __launch_bounds__(256) void k_momentum_line(Geom g, LineGeom lg, Line1D lt, Tables t,
+                                                        double mc, double tnu, double th,
+                                                        const double* __restrict__ w,
+                                                        const double* __restrict__ u,
+                                                        double* __restrict__ y, int Nc) {
+    using L = Lay<DIM, N>;
+    constexpr int NB = L::NB, CPB = L::CPB;
+    __shared__ double s_w[DIM][CPB * NB];
+    __shared__ double s_u[DIM][CPB * NB];
+    constexpr int NN = N * N;
+    __shared__ double s_m[6 * NN + 3 * N];
+    for (int i = threadIdx.x; i < 6 * NN + 3 * N; i += blockDim.x) {
+        double v;
+        if (i < 5 * NN) {
+            const int mtx = i / NN, e = i % NN;
+            v = mtx == 0 ? lt.A[e] : mtx == 1 ? lt.F0[e] : mtx == 2 ? lt.F1[e] : mtx == 3 ? lt.Lm[e] : lt.Rm[e];
+        } else if (i < 6 * NN) {
+            v = t.Du[i - 5 * NN];
+        } else {
+            const int e = i - 6 * NN;
+            v = e < N ? t.Wu[e] : (e < 2 * N ? t.L0u[e - N] : t.L1u[e - 2 * N]);
+        }
+        s_m[i] = v;
+    }
+    const double* mA = s_m;
+    const double* mF0 = s_m + NN;
+    const double* mF1 = s_m + 2 * NN;
+    const double* mLm = s_m + 3 * NN;
+    const double* mRm = s_m + 4 * NN;
+    const double* D = s_m + 5 * NN;
+    const double* Wv = s_m + 6 * NN;
+    const double* L0v = Wv + N;
+    const double* L1v = Wv + 2 * N;
+    const int tid = threadIdx.x;
+    const int lc = tid / NB, nd = tid % NB;
+    const int cell = blockIdx.x * CPB + lc;
+    const bool active = cell < Nc;
+    for (int c = 0; c < DIM; ++c) {
+        s_w[c][tid] = active ? w[((size_t)cell * DIM + c) * NB + nd] : 0.0;
+        if (!DIAG) s_u[c][tid] = active ? u[((size_t)cell * DIM + c) * NB + nd] : 0.0;
+    }
+    __syncthreads();
+    if (!active) return;
+    const Nbrs<DIM> nb(g, lg, cell);
+    const double Wi = L::wnode(Wv, nd);
+    double acc[DIM];
+    for (int c = 0; c < DIM; ++c) acc[c] = mc * Wi * (DIAG ? 1.0 : s_u[c][tid]);
+    const int base = lc * NB;
+    for (int a = 0; a < DIM; ++a) {
+        const int ia = L::coord(nd, a), tt = L::tang(nd, a);
+        const int lf = nb.left[a], rt = nb.right[a];
+        const double wt = L::wtan(Wv, tt);
+        // traces of the advecting component w_a at both ends of the line
+        double w0 = 0.0, w1 = 0.0, wl = 0.0, wr = 0.0;
+        double wline[N];
+#pragma unroll
+        for (int m = 0; m < N; ++m) {
+            const int idx = L::node(a, m, tt);
+            const double wo = s_w[a][base + idx];
+            wline[m] = wo;
+            w0 += t.L0u[m] * wo;
+            w1 += t.L1u[m] * wo;
+            if (lf >= 0) wl += t.L1u[m] * w[((size_t)lf * DIM + a) * NB + idx];
+            if (rt >= 0) wr += t.L0u[m] * w[((size_t)rt * DIM + a) * NB + idx];
+        }
+        const double lam0 = fmax(fabs(w0), fabs(wl));
+        const double lam1 = fmax(fabs(w1), fabs(wr));
+        const double sd = tnu * lg.sdiff[a] * wt;
+        const double sv = th * lg.sadv[a] * wt;
+        if (DIAG) {
+            double s = mA[ia * N + ia];
+            if (lf < 0) s -= mF0[ia * N + ia];
+            if (rt < 0) s -= mF1[ia * N + ia];
+            if (lf == cell) s += mLm[ia * N + ia];
+            if (rt == cell) s += mRm[ia * N + ia];
+            const double L0 = L0v[ia], L1 = L1v[ia];
+            double v = -Wv[ia] * wline[ia] * D[ia * N + ia];
+            if (lf >= 0) v += L0 * L0 * 0.5 * (-w0 + lam0);
+            if (rt >= 0) v += L1 * L1 * 0.5 * (w1 + lam1);
+            if (lf == cell) v += L0 * L1 * 0.5 * (-wl - lam0);
+            if (rt == cell) v += L1 * L0 * 0.5 * (wr - lam1);
+            acc[0] += sd * s + sv * v;
+            continue;
+        }
+        for (int c = 0; c < DIM; ++c) {
+            double s = 0.0, vol = 0.0;
+            double u0 = 0.0, u1 = 0.0, ul = 0.0, ur = 0.0;
+#pragma unroll
+            for (int j = 0; j < N; ++j) {
+                const int idx = L::node(a, j, tt);
+                const double uo = s_u[c][base + idx];
+                double cf = mA[ia * N + j];
+                if (lf < 0) cf -= mF0[ia * N + j];
+                if (rt < 0) cf -= mF1[ia * N + j];
+                s += cf * uo;
+                u0 += t.L0u[j] * uo;
+                u1 += t.L1u[j] * uo;
+                vol -= t.Wu[j] * uo * wline[j] * D[j * N + ia];
+                if (lf >= 0) {
+                    const double ulv = u[((size_t)lf * DIM + c) * NB + idx];
+                    s += mLm[ia * N + j] * ulv;
+                    ul += t.L1u[j] * ulv;
+                }
+                if (rt >= 0) {
+                    const double urv = u[((size_t)rt * DIM + c) * NB + idx];
+                    s += mRm[ia * N + j] * urv;
+                    ur += t.L0u[j] * urv;
+                }
+            }
+            double fl = 0.0, fr = 0.0;
+            if (lf >= 0) fl = 0.5 * (-u0 * w0 - ul * wl) + 0.5 * lam0 * (u0 - ul);
+            if (rt >= 0) fr = 0.5 * (u1 * w1 + ur * wr) + 0.5 * lam1 * (u1 - ur);
+            acc[c] += sd * s + sv * (vol + L0v[ia] * fl + L1v[ia] * fr);
+        }
+    }
+    if (DIAG) {
+        y[(size_t)cell * NB + nd] = acc[0];
+    } else {
+        for (int c = 0; c < DIM; ++c) y[((size_t)cell * DIM + c) * NB + nd] = acc[c];
+    }
+}
+
+// ============================================================================
+// Operator kernels (apply).  Three phases per block of CPB whole cells:
+//  1. stage the own cells in LDS and gather, for every face point of every
+//     own cell, the neighbour's trace value v and normal derivative d (the
+//     neighbour enters each 1D SIP coupling only through them:
+//       sum_j Lm[i][j] u_left(j) = l_i(0) (d_L/2 - Cr v_L) - l_i'(0) v_L/2,
+//     and symmetrically on the right) and, for the momentum operator, the
+//     neighbour's advecting-velocity trace;
+//  2. one work item per (cell, direction, [component,] grid line) applies the
+//     1D operators of that line to its n nodes with all per-line quantities
+//     (end traces, LF fluxes, the u w products) computed once, and stores the
+//     n results per direction in LDS;
+//  3. one thread per node adds the mass term and the directions and writes.
+// Blocks are mapped to cells XCD by XCD (the hardware hands consecutive
+// blocks to the 8 XCDs in turn), so each XCD sweeps a contiguous slab of
+// cells and the neighbour lines it gathers mostly hit its own L2.
+// ============================================================================
+// Blocks are always launched with 256 threads (four full waves, so the
+// wave-level shuffles of the block reductions never read an inactive lane);
+// threads beyond CPB whole cells idle in phases 1 and 3.
+template <int DIM, int N>
+struct FaceLay {
+    static constexpr int NB = ipow(N, DIM);
+    static constexpr int NF = ipow(N, DIM - 1);
+    static constexpr int CPB = (256 / NB) > 0 ? (256 / NB) : 1;
+    static constexpr int THREADS = 256;
+};
+
+__device__ inline int xcd_block(int b, int G) {
+    const int x = b & 7, i = b >> 3;
+    const int q = G >> 3, r = G & 7;
+    return x < r ? x * (q + 1) + i : r * (q + 1) + (x - r) * q + i;
+}
+
+template <int DIM, int N>
+__global__ __launch_bounds__(256) void k_momentum_face(Geom g, LineGeom lg, Line1D lt, Tables t,
+                                                        double Cr, double mc, double tnu, double th,
+                                                        const double* __restrict__ w,
+                                                        const double* __restrict__ u,
+                                                        double* __restrict__ y, int Nc) {
+    using L = Lay<DIM, N>;
+    using F = FaceLay<DIM, N>;
+    constexpr int NB = F::NB, NF = F::NF, CPB = F::CPB;
+    constexpr int REC = 2 * DIM + 1;
+    constexpr int NFACE = 2 * DIM * NF;
+    // per-cell node arrays padded by one slot per x-row: lanes walking
+    // x-lines then touch distinct LDS banks
+    constexpr int NBP = NB + NB / N;
+    __shared__ double s_w[DIM][CPB * NBP];
+    __shared__ double s_u[DIM][CPB * NBP];
+    __shared__ double s_y[DIM][CPB * NBP];
+    __shared__ double s_f[CPB * NFACE * REC];
+    __shared__ int s_nbr[CPB * 2 * DIM];
+    __shared__ double s_W[N];
+    const int tid = threadIdx.x;
+    if (tid < N) s_W[tid] = t.Wu[tid];
+    const int blk = xcd_block(blockIdx.x, gridDim.x);
+    const int lc = tid / NB, nd = tid % NB;
+    const int cell = blk * CPB + lc;
+    const bool active = lc < CPB && cell < Nc;
+    const int pi = lc * NBP + nd + nd / N;
+    if (lc < CPB) {
+#pragma unroll
+        for (int c = 0; c < DIM; ++c) {
+            s_w[c][pi] = active ? w[((size_t)cell * DIM + c) * NB + nd] : 0.0;
+            s_u[c][pi] = active ? u[((size_t)cell * DIM + c) * NB + nd] : 0.0;
+        }
+    }
+    if (lc < CPB && nd == 0) {
+        // neighbour table of the cell, written with constant indices
+        const Nbrs<DIM> nb(g, lg, active ? cell : 0);
+#pragma unroll
+        for (int a = 0; a < DIM; ++a) {
+            s_nbr[lc * 2 * DIM + 2 * a] = active ? nb.left[a] : -1;
+            s_nbr[lc * 2 * DIM + 2 * a + 1] = active ? nb.right[a] : -1;
+        }
+    }
+    __syncthreads();
+    // phase 1
+    {
+        for (int it = nd; lc < CPB && it < NFACE; it += NB) {
+            const int face = it / NF, tt = it % NF;
+            const int a = face >> 1, s = face & 1;
+            double rec[REC];
+#pragma unroll
+            for (int q = 0; q < REC; ++q) rec[q] = 0.0;
+            const int nbr = s_nbr[lc * 2 * DIM + face];
+            if (nbr >= 0) {
+#pragma unroll
+                for (int m = 0; m < N; ++m) {
+                    const int idx = L::node(a, m, tt);
+                    const double lo = s ? t.L0u[m] : t.L1u[m];
+                    const double dlo = s ? t.dL0u[m] : t.dL1u[m];
+                    rec[2 * DIM] += lo * w[((size_t)nbr * DIM + a) * NB + idx];
+#pragma unroll
+                    for (int c = 0; c < DIM; ++c) {
+                        const double uv = u[((size_t)nbr * DIM + c) * NB + idx];
+                        rec[2 * c] += lo * uv;
+                        rec[2 * c + 1] += dlo * uv;
+                    }
+                }
+            }
+            double* dst = s_f + (lc * NFACE + it) * REC;
+#pragma unroll
+            for (int q = 0; q < REC; ++q) dst[q] = rec[q];
+        }
+    }
+    __syncthreads();
+    // phase 2: one pass per direction, items (cell, component, line); each
+    // node receives exactly one contribution per pass
+    if (lc < CPB) {
+        const double Wi0 = L::wnode(s_W, nd);
+#pragma unroll
+        for (int c = 0; c < DIM; ++c) s_y[c][pi] = mc * Wi0 * s_u[c][pi];
+    }
+#pragma unroll
+    for (int a = 0; a < DIM; ++a) {
+        __syncthreads();
+        constexpr int ITEMS = CPB * DIM * NF;
+        for (int it = tid; it < ITEMS; it += 256) {
+            const int lc2 = it / (DIM * NF);
+            const int c = (it % (DIM * NF)) / NF, ln = it % NF;
+            if (blk * CPB + lc2 >= Nc) continue;
+            const int base = lc2 * NBP;
+            double uu[N], uw[N];
+            double u0 = 0.0, u1 = 0.0, w0 = 0.0, w1 = 0.0, q0 = 0.0, q1 = 0.0;
+#pragma unroll
+            for (int m = 0; m < N; ++m) {
+                const int nm = L::node(a, m, ln);
+                const int idx = base + nm + nm / N;
+                const double um = s_u[c][idx], wm = s_w[a][idx];
+                uu[m] = um;
+                uw[m] = um * wm;
+                u0 += t.L0u[m] * um;
+                u1 += t.L1u[m] * um;
+                w0 += t.L0u[m] * wm;
+                w1 += t.L1u[m] * wm;
+            }
+            const double* recl = s_f + (lc2 * NFACE + (2 * a) * NF + ln) * REC;
+            const double* recr = s_f + (lc2 * NFACE + (2 * a + 1) * NF + ln) * REC;
+            const bool hl = s_nbr[lc2 * 2 * DIM + 2 * a] >= 0;
+            const bool hr = s_nbr[lc2 * 2 * DIM + 2 * a + 1] >= 0;
+            double X0, Y0, X1, Y1, fl = 0.0, fr = 0.0;
+            if (hl) {
+                const double vL = recl[2 * c], dL = recl[2 * c + 1], wl = recl[2 * DIM];
+                const double lam = fmax(fabs(w0), fabs(wl));
+                X0 = 0.5 * dL - Cr * vL;
+                Y0 = 0.5 * vL;
+                fl = 0.5 * (-u0 * w0 - vL * wl) + 0.5 * lam * (u0 - vL);
+            } else {
+#pragma unroll
+                for (int m = 0; m < N; ++m) q0 += t.dL0u[m] * uu[m];
+                X0 = -0.5 * q0 - Cr * u0;
+                Y0 = 0.5 * u0;
+            }
+            if (hr) {
+                const double vR = recr[2 * c], dR = recr[2 * c + 1], wr = recr[2 * DIM];
+                const double lam = fmax(fabs(w1), fabs(wr));
+                X1 = -0.5 * dR - Cr * vR;
+                Y1 = 0.5 * vR;
+                fr = 0.5 * (u1 * w1 + vR * wr) + 0.5 * lam * (u1 - vR);
+            } else {
+#pragma unroll
+                for (int m = 0; m < N; ++m) q1 += t.dL1u[m] * uu[m];
+                X1 = 0.5 * q1 - Cr * u1;
+                Y1 = 0.5 * u1;
+            }
+            const double wt = L::wtan(s_W, ln);
+            const double sd = tnu * lg.sdiff[a] * wt;
+            const double sv = th * lg.sadv[a] * wt;
+            const double cl = sd * X0 + sv * fl, cr = sd * X1 + sv * fr;
+            const double dl = sd * Y0, dr = sd * Y1;
+#pragma unroll
+            for (int i = 0; i < N; ++i) {
+                double s = 0.0, vol = 0.0;
+#pragma unroll
+                for (int j = 0; j < N; ++j) {
+                    s += lt.A[i * N + j] * uu[j];
+                    vol -= lt.WD[j * N + i] * uw[j];
+                }
+                const double out = sd * s + sv * vol + t.L0u[i] * cl + t.L1u[i] * cr
+                                   - t.dL0u[i] * dl + t.dL1u[i] * dr;
+                const int ni = L::node(a, i, ln);
+                s_y[c][base + ni + ni / N] += out;
+            }
+        }
+    }
+    __syncthreads();
+    if (!active) return;
+#pragma unroll
+    for (int c = 0; c < DIM; ++c) y[((size_t)cell * DIM + c) * NB + nd] = s_y[c][pi];
+}
+
+// Pressure operator.  MODE 0: y = H p.  MODE 3: the CG direction update is
+// fused in front: the operator is applied to p_new = r * invd + beta * p
+// (beta = sc[5]), evaluated on the fly for the neighbour traces and stored to
+// p_out for the own cells (p_out must not alias p: other blocks still read
+// the old p), and one partial sum of p_new . y is written per block.
+template <int DIM, int NP, int MODE>
+__global__ __launch_bounds__(256) void k_pressure_face(Geom g, LineGeom lg, Line1D lt, Tables t,
+                                                        double Cr, double cm,
+                                                        const double* __restrict__ p,
+                                                        double* __restrict__ y, int Nc,
+                                                        double* partial,
+                                                        const double* __restrict__ r,
+                                                        const double* __restrict__ invd,
+                                                        const double* __restrict__ sc,
+                                                        double* __restrict__ p_out) {
+    using L = Lay<DIM, NP>;
+    using F = FaceLay<DIM, NP>;
+    constexpr int NB = F::NB, NF = F::NF, CPB = F::CPB;
+    constexpr int NFACE = 2 * DIM * NF;
+    __shared__ double s_p[256];
+    __shared__ double s_y[DIM][256];
+    __shared__ double s_f[CPB * NFACE * 2];
+    __shared__ int s_nbr[CPB * 2 * DIM];
+    __shared__ double s_W[NP];
+    const int tid = threadIdx.x;
+    if (tid < NP) s_W[tid] = t.Wp[tid];
+    const int blk = xcd_block(blockIdx.x, gridDim.x);
+    const int lc = tid / NB, nd = tid % NB;
+    const int cell = blk * CPB + lc;
+    const bool active = lc < CPB && cell < Nc;
+    const double beta = MODE == 3 ? sc[5] : 0.0;
+    double pown = 0.0;
+    if (active) {
+        const size_t gi = (size_t)cell * NB + nd;
+        pown = MODE == 3 ? r[gi] * invd[gi] + beta * p[gi] : p[gi];
+        if (MODE == 3) p_out[gi] = pown;
+    }
+    s_p[tid] = pown;
+    if (lc < CPB && nd == 0) {
+        const Nbrs<DIM> nb(g, lg, active ? cell : 0);
+#pragma unroll
+        for (int a = 0; a < DIM; ++a) {
+            s_nbr[lc * 2 * DIM + 2 * a] = active ? nb.left[a] : -1;
+            s_nbr[lc * 2 * DIM + 2 * a + 1] = active ? nb.right[a] : -1;
+        }
+    }
+    __syncthreads();
+    {
+        for (int it = nd; lc < CPB && it < NFACE; it += NB) {
+            const int face = it / NF, tt = it % NF;
+            const int a = face >> 1, s = face & 1;
+            double v = 0.0, d = 0.0;
+            const int nbr = s_nbr[lc * 2 * DIM + face];
+            if (nbr >= 0) {
+#pragma unroll
+                for (int m = 0; m < NP; ++m) {
+                    const size_t gi = (size_t)nbr * NB + L::node(a, m, tt);
+                    const double pv = MODE == 3 ? r[gi] * invd[gi] + beta * p[gi] : p[gi];
+                    v += (s ? t.L0p[m] : t.L1p[m]) * pv;
+                    d += (s ? t.dL0p[m] : t.dL1p[m]) * pv;
+                }
+            }
+            s_f[2 * (lc * NFACE + it)] = v;
+            s_f[2 * (lc * NFACE + it) + 1] = d;
+        }
+    }
+    __syncthreads();
+    constexpr int ITEMS = CPB * DIM * NF;
+    for (int it = tid; it < ITEMS; it += 256) {
+        const int lc2 = it / (DIM * NF);
+        const int a = (it % (DIM * NF)) / NF, ln = it % NF;
+        if (blk * CPB + lc2 >= Nc) continue;
+        const int base = lc2 * NB;
+        double pp[NP];
+        double p0 = 0.0, p1 = 0.0;
+#pragma unroll
+        for (int m = 0; m < NP; ++m) {
+            pp[m] = s_p[base + L::node(a, m, ln)];
+            p0 += t.L0p[m] * pp[m];
+            p1 += t.L1p[m] * pp[m];
+        }
+        const bool hl = s_nbr[lc2 * 2 * DIM + 2 * a] >= 0;
+        const bool hr = s_nbr[lc2 * 2 * DIM + 2 * a + 1] >= 0;
+        double X0, Y0, X1, Y1;
+        if (hl) {
+            const int rl = 2 * (lc2 * NFACE + (2 * a) * NF + ln);
+            X0 = 0.5 * s_f[rl + 1] - Cr * s_f[rl];
+            Y0 = 0.5 * s_f[rl];
+        } else {
+            double q0 = 0.0;
+#pragma unroll
+            for (int m = 0; m < NP; ++m) q0 += t.dL0p[m] * pp[m];
+            X0 = -0.5 * q0 - Cr * p0;
+            Y0 = 0.5 * p0;
+        }
+        if (hr) {
+            const int rr = 2 * (lc2 * NFACE + (2 * a + 1) * NF + ln);
+            X1 = -0.5 * s_f[rr + 1] - Cr * s_f[rr];
+            Y1 = 0.5 * s_f[rr];
+        } else {
+            double q1 = 0.0;
+#pragma unroll
+            for (int m = 0; m < NP; ++m) q1 += t.dL1p[m] * pp[m];
+            X1 = 0.5 * q1 - Cr * p1;
+            Y1 = 0.5 * p1;
+        }
+        const double sd = lg.sdiff[a] * L::wtan(s_W, ln);
+#pragma unroll
+        for (int i = 0; i < NP; ++i) {
+            double s = 0.0;
+#pragma unroll
+            for (int j = 0; j < NP; ++j) s += lt.A[i * NP + j] * pp[j];
+            s += t.L0p[i] * X0 - t.dL0p[i] * Y0 + t.L1p[i] * X1 + t.dL1p[i] * Y1;
+            s_y[a][base + L::node(a, i, ln)] = sd * s;
+        }
+    }
+    __syncthreads();
+    double acc = 0.0;
+    if (active) {
+        acc = cm * L::wnode(s_W, nd) * pown;
+#pragma unroll
+        for (int a = 0; a < DIM; ++a) acc += s_y[a][tid];
+        y[(size_t)cell * NB + nd] = acc;
+    }
+    if (MODE == 3) {
+        const double pq = red::block_sum(active ? acc * pown : 0.0);
+        if (threadIdx.x == 0) partial[blockIdx.x] = pq;
+    }
+}
+
+inline unsigned nblk(int64_t work, int per) { return (unsigned)((work + per - 1) / per); }
+
+}  // namespace
+
+#define TBDG_LINE_DISPATCH(ctx, FN)                                                       \
+    do {                                                                                  \
+        const int d_ = (ctx)->dim, n_ = (ctx)->n;                                         \
+        if (d_ == 2 && n_ == 3) { FN(2, 3); }                                             \
+        else if (d_ == 2 && n_ == 4) { FN(2, 4); }                                        \
+        else if (d_ == 2 && n_ == 5) { FN(2, 5); }                                        \
+        else if (d_ == 2 && n_ == 6) { FN(2, 6); }                                        \
+        else if (d_ == 3 && n_ == 3) { FN(3, 3); }                                        \
+        else if (d_ == 3 && n_ == 4) { FN(3, 4); }                                        \
+        else throw Error(TBDG_EUNSUPPORTED, "unsupported (dim, degree)");                 \
+    } while (0)
+
+void launch_apply_pressure(const tbdg_ctx* c, double alpha, const double* p, double* y) {
+#define L_(D, N)                                                                           \
+    {                                                                                      \
+        using FL = FaceLay<D, N - 1>;                                                      \
+        TimedLaunch tl(c, 0);                                                              \
+        hipExtLaunchKernelGGL((k_pressure_face<D, N - 1, 0>), dim3(nblk(c->Nc, FL::CPB)),  \
+                              dim3(FL::THREADS), 0, c->stream, tl.start(), tl.stop(), 0,   \
+                              c->geom, c->lgeom, c->line_p, c->tab, c->cr_p,               \
+                              alpha * c->geom.vol, p, y, (int)c->Nc, (double*)nullptr,     \
+                              (const double*)nullptr, (const double*)nullptr,              \
+                              (const double*)nullptr, (double*)nullptr);                   \
+    }
+    TBDG_LINE_DISPATCH(c, L_);
+#undef L_
+    TBDG_HIP(hipGetLastError());
+}
+
+void launch_diag_pressure(const tbdg_ctx* c, double alpha, double* d) {
+#define L_(D, N)                                                                           \
+    hipLaunchKernelGGL((k_pressure_line<D, N - 1, 1>), dim3(nblk(c->Np, 256)), dim3(256),   \
+                       0, c->stream, c->geom, c->lgeom, c->line_p, c->tab,                 \
+                       alpha * c->geom.vol, nullptr, d, (int)c->Nc, nullptr);
+    TBDG_LINE_DISPATCH(c, L_);
+#undef L_
+    TBDG_HIP(hipGetLastError());
+}
+
+void launch_cg_apply(const tbdg_ctx* c, double alpha, const double* r, const double* invd,
+                     const double* p_old, double* p_new, double* q, double* sc) {
+    int G = 0;
+#define L_(D, N)                                                                           \
+    {                                                                                      \
+        using FL = FaceLay<D, N - 1>;                                                      \
+        G = (int)nblk(c->Nc, FL::CPB);                                                     \
+        if (G > c->red_op_len) throw Error(TBDG_EINVAL, "operator partial buffer too small"); \
+        TimedLaunch tl(c, 0);                                                              \
+        hipExtLaunchKernelGGL((k_pressure_face<D, N - 1, 3>), dim3(G), dim3(FL::THREADS),  \
+                              0, c->stream, tl.start(), tl.stop(), 0, c->geom, c->lgeom,   \
+                              c->line_p, c->tab, c->cr_p, alpha * c->geom.vol, p_old, q,  \
+                              (int)c->Nc, c->red_op, r, invd, (const double*)sc, p_new);   \
+    }
+    TBDG_LINE_DISPATCH(c, L_);
+#undef L_
+    TBDG_HIP(hipGetLastError());
+    cg_alpha_finish(c, G, c->red_op, sc);
+}
+
+void launch_apply_momentum(const tbdg_ctx* c, double mcoef, double theta, const double* w,
+                           const double* u, double* y) {
+#define L_(D, N)                                                                           \
+    {                                                                                      \
+        using FL = FaceLay<D, N>;                                                          \
+        TimedLaunch tl(c, 1);                                                              \
+        hipExtLaunchKernelGGL((k_momentum_face<D, N>), dim3(nblk(c->Nc, FL::CPB)),         \
+                              dim3(FL::THREADS), 0, c->stream, tl.start(), tl.stop(), 0,   \
+                              c->geom, c->lgeom, c->line_u, c->tab, c->cr_u,               \
+                              mcoef * c->geom.vol, theta * c->nu, theta, w, u, y,          \
+                              (int)c->Nc);                                                 \
+    }
+    TBDG_LINE_DISPATCH(c, L_);
+#undef L_
+    TBDG_HIP(hipGetLastError());
+}
+
+void launch_diag_momentum(const tbdg_ctx* c, double mcoef, double theta, const double* w,
+                          double* d) {
+#define L_(D, N)                                                                           \
+    {                                                                                      \
+        using LL = Lay<D, N>;                                                              \
+        hipLaunchKernelGGL((k_momentum_line<D, N, true>), dim3(nblk(c->Nc, LL::CPB)),      \
+                           dim3(LL::THREADS), 0, c->stream, c->geom, c->lgeom, c->line_u,  \
+                           c->tab, mcoef * c->geom.vol, theta * c->nu, theta, w, nullptr,  \
+                           d, (int)c->Nc);                                                 \
+    }
+    TBDG_LINE_DISPATCH(c, L_);
+#undef L_
+    TBDG_HIP(hipGetLastError());
+}
+
+}  // namespace trbdg

@@ -96,6 +96,46 @@ void build_tables(tbdg_ctx* c) {
         }
 }
 
+namespace {
+
+// 1D SIP element matrices, reference cell [0,1], penalty Cr (times 1/h on
+// the physical cell, so every entry scales as 1/h).
+void line_matrices(int n, const double* W, const double* D, const double* L0, const double* L1,
+                   const double* dL0, const double* dL1, double Cr, Line1D& m) {
+    std::memset(&m, 0, sizeof(m));
+    for (int i = 0; i < n; ++i)
+        for (int j = 0; j < n; ++j) {
+            double a = 0.0;
+            for (int q = 0; q < n; ++q) a += W[q] * D[q * n + i] * D[q * n + j];
+            const double f0 = 0.5 * dL0[j] * L0[i] + 0.5 * L0[j] * dL0[i] + Cr * L0[i] * L0[j];
+            const double f1 = -0.5 * dL1[j] * L1[i] - 0.5 * L1[j] * dL1[i] + Cr * L1[i] * L1[j];
+            m.F0[i * n + j] = f0;
+            m.F1[i * n + j] = f1;
+            m.A[i * n + j] = a + f0 + f1;
+            m.Lm[i * n + j] = 0.5 * dL1[j] * L0[i] - 0.5 * L1[j] * dL0[i] - Cr * L0[i] * L1[j];
+            m.Rm[i * n + j] = -0.5 * dL0[j] * L1[i] + 0.5 * L0[j] * dL1[i] - Cr * L1[i] * L0[j];
+            m.WD[i * n + j] = W[i] * D[i * n + j];   // row m = i, column = test function j
+        }
+}
+
+}  // namespace
+
+void build_line_operators(tbdg_ctx* c) {
+    const Tables& t = c->tab;
+    c->cr_u = (c->k + 1.0) * (c->k + 1.0) * c->pen_u;
+    c->cr_p = (double)c->k * c->k * c->pen_p;
+    line_matrices(c->n, t.Wu, t.Du, t.L0u, t.L1u, t.dL0u, t.dL1u,
+                  (c->k + 1.0) * (c->k + 1.0) * c->pen_u, c->line_u);
+    line_matrices(c->np, t.Wp, t.Dp, t.L0p, t.L1p, t.dL0p, t.dL1p,
+                  (double)c->k * c->k * c->pen_p, c->line_p);
+    for (int a = 0; a < 3; ++a) {
+        c->lgeom.periodic[a] = c->periodic_flags[a];
+        c->lgeom.inv_nc[a] = 1.0 / c->geom.nc[a];
+        c->lgeom.sadv[a] = c->geom.vol / c->geom.h[a];
+        c->lgeom.sdiff[a] = c->geom.vol / (c->geom.h[a] * c->geom.h[a]);
+    }
+}
+
 }  // namespace trbdg
 
 double tbdg_ctx::alpha(int s) const {

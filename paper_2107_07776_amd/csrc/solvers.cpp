@@ -1,14 +1,19 @@
 // Krylov solvers and the TR-BDF2 step (host orchestration of device kernels).
 //
 // GMRES (momentum predictor): restarted, right-preconditioned with the exact
-// Jacobi diagonal, classical Gram-Schmidt applied twice (CGS2) through
-// multi-vector dot and update kernels, Givens rotations on the host.
-// CG (Helmholtz): Jacobi-preconditioned; all scalars stay on the device; the
-// host reads the residual norm every few iterations.
+// Jacobi diagonal; classical Gram-Schmidt through one multi-vector dot kernel
+// and one update kernel that also returns the new norm, repeated once when
+// the norm drops below 1/sqrt(2) of its value before orthogonalisation
+// (the "twice is enough" criterion); Givens rotations on the host.
+// CG (Helmholtz): Jacobi-preconditioned, three kernels per iteration
+// (direction, operator fused with p.q and the step length, update fused with
+// r.z, r.r and the next beta); all scalars stay on the device and the host
+// reads the residual norm every 16 iterations.
 // Both stop on the relative residual and confirm with a freshly computed
 // true residual ||b - A x|| before returning.
 #include <cmath>
 #include <cstring>
+#include <utility>
 #include <vector>
 
 #include "internal.hpp"
@@ -44,6 +49,7 @@ tbdg_status solve_momentum(tbdg_ctx* c, int s, const double* w, const double* b,
     const int m = std::min(o.restart > 0 ? o.restart : 30, c->gm_m);
     MomentumOp A{c, c->mcoef(s), c->theta[s], w};
     launch_diag_momentum(c, c->mcoef(s), c->theta[s], w, c->diag_u);
+    vec_recip(c->stream, c->Ns, c->diag_u, c->invd_u);
     const double bnorm = norm2(c, n, b);
     tbdg_solve_info inf{0, 0.0, 0.0, 0};
     if (bnorm == 0.0) {
@@ -57,7 +63,9 @@ tbdg_status solve_momentum(tbdg_ctx* c, int s, const double* w, const double* b,
     }
     double* V = c->V;
     const int64_t ld = n;
-    std::vector<double> H((m + 1) * m), cs(m), sn(m), g(m + 1), y(m);
+    double* hdev = c->red_out;        // h (j+1 entries) then w.w
+    double* nndev = c->red_out + 62;  // |w'|^2
+    std::vector<double> H((m + 1) * m), cs(m), sn(m), g(m + 1), y(m), h(m + 1);
     int total = 0;
     tbdg_status st = TBDG_ENOTCONV;
     // initial residual r = b - A x into V_0
@@ -78,32 +86,34 @@ tbdg_status solve_momentum(tbdg_ctx* c, int s, const double* w, const double* b,
             st = TBDG_ENOTCONV;
             break;
         }
-        vec_scale_copy(c->stream, n, 1.0 / beta, V, V);
         std::fill(g.begin(), g.end(), 0.0);
         g[0] = beta;
+        double pending = 1.0 / beta;   // V_j is stored unnormalised until its first use
         int j = 0;
-        double resid = beta;
         bool breakdown = false;
         for (; j < m && total < o.maxiter; ++j) {
             ++total;
             double* vj = V + (int64_t)j * ld;
             double* vn = V + (int64_t)(j + 1) * ld;
-            vec_div_diag_u(c->stream, n, c->dim, c->nbu, vj, c->diag_u, c->gz);
+            gm_scale_precond(c, n, pending, vj, c->invd_u, c->gz);
             A(c->gz, vn);
-            // CGS2
-            std::vector<double> h(j + 1, 0.0);
+            // classical Gram-Schmidt, repeated only when cancellation is large
+            std::fill(h.begin(), h.end(), 0.0);
+            double nn = 0.0;
             for (int pass = 0; pass < 2; ++pass) {
-                dot_many(c, n, j + 1, V, ld, vn, c->red_out);
-                TBDG_HIP(hipMemcpyAsync(c->host_out, c->red_out, sizeof(double) * (j + 1),
-                                        hipMemcpyDeviceToHost, c->stream));
-                vec_sub_combo(c->stream, n, j + 1, V, ld, c->red_out, vn);
+                gm_dots(c, n, j + 1, V, ld, vn, hdev);
+                gm_update_norm(c, n, j + 1, V, ld, hdev, vn, nndev);
+                TBDG_HIP(hipMemcpyAsync(c->host_out, hdev, sizeof(double) * 63, hipMemcpyDeviceToHost,
+                                        c->stream));
                 TBDG_HIP(hipStreamSynchronize(c->stream));
                 for (int i = 0; i <= j; ++i) h[i] += c->host_out[i];
+                const double ww = c->host_out[j + 1];
+                nn = c->host_out[62];
+                if (!(nn < 0.5 * ww)) break;   // |w'| >= |w| / sqrt(2): twice is not needed
             }
-            const double hn = norm2(c, n, vn);
+            const double hn = std::sqrt(nn);
             for (int i = 0; i <= j; ++i) H[i * m + j] = h[i];
             H[(j + 1) * m + j] = hn;
-            // apply previous rotations
             for (int i = 0; i < j; ++i) {
                 const double t1 = cs[i] * H[i * m + j] + sn[i] * H[(i + 1) * m + j];
                 const double t2 = -sn[i] * H[i * m + j] + cs[i] * H[(i + 1) * m + j];
@@ -122,14 +132,12 @@ tbdg_status solve_momentum(tbdg_ctx* c, int s, const double* w, const double* b,
             H[(j + 1) * m + j] = 0.0;
             g[j + 1] = -sn[j] * g[j];
             g[j] = cs[j] * g[j];
-            resid = std::fabs(g[j + 1]);
-            if (hn > 0.0) vec_scale_copy(c->stream, n, 1.0 / hn, vn, vn);
-            if (resid <= o.tol * bnorm || hn == 0.0) {
+            pending = hn > 0.0 ? 1.0 / hn : 1.0;
+            if (std::fabs(g[j + 1]) <= o.tol * bnorm || hn == 0.0) {
                 ++j;
                 break;
             }
         }
-        // y = R^{-1} g, x += D^{-1} V y
         const int k = j;
         for (int i = k - 1; i >= 0; --i) {
             double s2 = g[i];
@@ -144,7 +152,6 @@ tbdg_status solve_momentum(tbdg_ctx* c, int s, const double* w, const double* b,
             vec_add_combo(c->stream, n, k, V, ld, c->red_out, c->gz);
             vec_add_div_diag_u(c->stream, n, c->dim, c->nbu, c->gz, c->diag_u, x);
         }
-        // true residual
         A(x, c->gv);
         vec_axpby(c->stream, n, 1.0, b, -1.0, c->gv, V);
         beta = norm2(c, n, V);
@@ -164,7 +171,7 @@ tbdg_status solve_pressure(tbdg_ctx* c, int s, const double* b, double* x,
                            const tbdg_solver_opts& o, tbdg_solve_info* info) {
     const int64_t n = c->Np;
     const double alpha = c->alpha(s);
-    const double* diag = c->diag_p[s];
+    const double* invd = c->invd_p[s];
     double* r = c->cr;
     double* p = c->cp;
     double* q = c->cq;
@@ -183,13 +190,13 @@ tbdg_status solve_pressure(tbdg_ctx* c, int s, const double* b, double* x,
     TBDG_HIP(hipMemsetAsync(sc, 0, sizeof(double) * 8, c->stream));
     tbdg_status st = TBDG_ENOTCONV;
     int total = 0;
-    const int check = 8;
+    const int check = 16;
     bool first_cycle = true;
     while (true) {
         // (re)start from the true residual
         launch_apply_pressure(c, alpha, x, q);
         vec_axpby(c->stream, n, 1.0, b, -1.0, q, r);
-        cg_init(c, n, diag, r, p, sc);
+        cg_start(c, n, invd, r, p, sc);
         TBDG_HIP(hipMemcpyAsync(c->host_out, sc, sizeof(double) * 8, hipMemcpyDeviceToHost, c->stream));
         TBDG_HIP(hipStreamSynchronize(c->stream));
         double rr = c->host_out[2];
@@ -205,11 +212,14 @@ tbdg_status solve_pressure(tbdg_ctx* c, int s, const double* b, double* x,
         }
         if (total >= o.maxiter) break;
         bool converged = false, broke = false;
+        // cg_start left p = invd r and sc[5] = 0, so the first fused step
+        // recomputes the same direction
+        double* pa = p;
+        double* pb = c->cp2;
         while (total < o.maxiter) {
-            launch_apply_pressure(c, alpha, p, q);
-            cg_alpha(c, n, p, q, sc);
-            cg_update(c, n, diag, x, r, p, q, sc);
-            cg_direction(c->stream, n, diag, r, p, sc);
+            launch_cg_apply(c, alpha, r, invd, pa, pb, q, sc);
+            cg_upd(c, n, invd, x, r, pb, q, sc);
+            std::swap(pa, pb);
             ++total;
             if (total % check == 0 || total >= o.maxiter) {
                 TBDG_HIP(hipMemcpyAsync(c->host_out, sc, sizeof(double) * 8, hipMemcpyDeviceToHost,
@@ -236,13 +246,10 @@ tbdg_status solve_pressure(tbdg_ctx* c, int s, const double* b, double* x,
             break;
         }
         if (!converged && total >= o.maxiter) {
-            // final true residual below
             st = TBDG_ENOTCONV;
             break;
         }
-        // converged on the recurrence: loop back to confirm with the true residual
     }
-    // final true residual
     launch_apply_pressure(c, alpha, x, q);
     vec_axpby(c->stream, n, 1.0, b, -1.0, q, r);
     const double rt = norm2(c, n, r);

@@ -21,20 +21,18 @@ hipEvent_t take(const tbdg_ctx* c) {
 TimedLaunch::TimedLaunch(const tbdg_ctx* c, int which) : c_(c), which_(which) {
     if (!c_->timer.on) return;
     e1_ = take(c_);
-    TBDG_HIP(hipEventRecord(e1_, c_->stream));
+    e2_ = take(c_);
 }
 
 TimedLaunch::~TimedLaunch() {
     if (!e1_) return;
-    hipEvent_t e2 = nullptr;
-    try {
-        e2 = take(c_);
-    } catch (...) {
-        return;
+    c_->timer.pending[which_].emplace_back(e1_, e2_);
+    if (c_->timer.pending[which_].size() >= 4096) {
+        try {
+            timer_collect(c_);
+        } catch (...) {
+        }
     }
-    if (hipEventRecord(e2, c_->stream) != hipSuccess) return;
-    c_->timer.pending[which_].emplace_back(e1_, e2);
-    if (c_->timer.pending[which_].size() >= 4096) timer_collect(c_);
 }
 
 void timer_collect(const tbdg_ctx* c) {
