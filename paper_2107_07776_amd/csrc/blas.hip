@@ -185,12 +185,29 @@ __global__ __launch_bounds__(BS) void k_cg_dir(int64_t n, const double* invd, co
         p[i] = r[i] * invd[i] + beta * p[i];
 }
 
-// CG update with fused partial sums: x += alpha p, r -= alpha q,
-// partial rz = r.(invd r), rr = r.r (beta is formed by k_cg_beta_finish).
+// CG update: every block first adds the Ga partial sums p.q of the operator
+// kernel (same order in every block) and forms alpha = sc[slot] / p.q;
+// then x += alpha p, r -= alpha q and one partial (r.(invd r), r.r) per
+// block.  Block 0 records alpha (sc[4]), p.q (sc[1]) and a breakdown flag.
 __global__ __launch_bounds__(BS) void k_cg_upd(int64_t n, const double* invd, double* x, double* r,
-                                               const double* p, const double* q, const double* sc,
+                                               const double* p, const double* q, double* sc,
+                                               const double* pa, int Ga, int slot,
                                                double* partial) {
-    const double alpha = sc[4];
+    __shared__ double s_alpha;
+    double pq = 0.0;
+    for (int b = threadIdx.x; b < Ga; b += BS) pq += pa[b];
+    pq = block_sum(pq);
+    if (threadIdx.x == 0) {
+        const bool ok = pq > 0.0;
+        s_alpha = ok ? sc[slot] / pq : 0.0;
+        if (blockIdx.x == 0) {
+            sc[1] = pq;
+            sc[4] = s_alpha;
+            if (!ok) sc[6] = 1.0;
+        }
+    }
+    __syncthreads();
+    const double alpha = s_alpha;
     double rz = 0.0, rr = 0.0;
     for (int64_t i = (int64_t)blockIdx.x * BS + threadIdx.x; i < n; i += (int64_t)gridDim.x * BS) {
         x[i] += alpha * p[i];
@@ -341,10 +358,10 @@ void vec_recip(hipStream_t s, int64_t n, const double* d, double* out) {
     TBDG_HIP(hipGetLastError());
 }
 
-void cg_start(tbdg_ctx* c, int64_t n, const double* invd, const double* r, double* p, double* sc) {
-    const int G = reduce_grid(n, 4096);
-    hipLaunchKernelGGL(k_cg_start, dim3(G), dim3(BS), 0, c->stream, n, invd, r, p, c->red_part);
-    hipLaunchKernelGGL(k_cg_beta_finish, dim3(1), dim3(BS), 0, c->stream, c->red_part, G, sc, 1);
+void cg_start(tbdg_ctx* c, int64_t n, const double* invd, const double* r, double* p, double* sc,
+              double* up, int Gu) {
+    hipLaunchKernelGGL(k_cg_start, dim3(Gu), dim3(BS), 0, c->stream, n, invd, r, p, up);
+    hipLaunchKernelGGL(k_cg_beta_finish, dim3(1), dim3(BS), 0, c->stream, up, Gu, sc, 1);
     TBDG_HIP(hipGetLastError());
 }
 
@@ -359,11 +376,9 @@ void cg_dir(tbdg_ctx* c, int64_t n, const double* invd, const double* r, double*
 }
 
 void cg_upd(tbdg_ctx* c, int64_t n, const double* invd, double* x, double* r, const double* p,
-            const double* q, double* sc) {
-    const int G = reduce_grid(n, 4096);
-    hipLaunchKernelGGL(k_cg_upd, dim3(G), dim3(BS), 0, c->stream, n, invd, x, r, p, q, sc,
-                       c->red_part);
-    hipLaunchKernelGGL(k_cg_beta_finish, dim3(1), dim3(BS), 0, c->stream, c->red_part, G, sc, 0);
+            const double* q, double* sc, const double* pa, int Ga, int slot, double* up, int Gu) {
+    hipLaunchKernelGGL(k_cg_upd, dim3(Gu), dim3(BS), 0, c->stream, n, invd, x, r, p, q, sc, pa,
+                       Ga, slot, up);
     TBDG_HIP(hipGetLastError());
 }
 

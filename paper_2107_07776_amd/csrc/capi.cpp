@@ -196,7 +196,7 @@ tbdg_status tbdg_create(const tbdg_mesh_desc* mesh, const tbdg_disc_desc* disc, 
         c->cp2 = dalloc(c->Np);
         c->red_blocks = 64 * 4096;
         c->red_part = dalloc(c->red_blocks);
-        c->red_out = dalloc(128);
+        c->red_out = dalloc(128);   // [0..62] GMRES, [63] norms, [64..79] CG scalars
         {
             void* cp = nullptr;
             TBDG_HIP(hipMalloc(&cp, sizeof(unsigned) * 16));
@@ -209,7 +209,7 @@ tbdg_status tbdg_create(const tbdg_mesh_desc* mesh, const tbdg_disc_desc* disc, 
         c->invd_p[1] = dalloc(c->Np);
         c->invd_p[2] = dalloc(c->Np);
         void* h = nullptr;
-        TBDG_HIP(hipHostMalloc(&h, sizeof(double) * 128, hipHostMallocDefault));
+        TBDG_HIP(hipHostMalloc(&h, sizeof(double) * 512, hipHostMallocDefault));
         c->host_out = static_cast<double*>(h);
         c->s_w = dalloc(c->Nu);
         c->s_rhs = dalloc(c->Nu);

@@ -198,15 +198,18 @@ void cg_direction(hipStream_t s, int64_t n, const double* diag, const double* r,
                   const double* sc);
 void cg_init(tbdg_ctx* c, int64_t n, const double* diag, const double* r, double* p, double* sc);
 void vec_recip(hipStream_t s, int64_t n, const double* d, double* out);
-void cg_start(tbdg_ctx* c, int64_t n, const double* invd, const double* r, double* p, double* sc);
+void cg_start(tbdg_ctx* c, int64_t n, const double* invd, const double* r, double* p, double* sc,
+              double* up, int Gu);
 void cg_dir(tbdg_ctx* c, int64_t n, const double* invd, const double* r, double* p, const double* sc);
 void cg_upd(tbdg_ctx* c, int64_t n, const double* invd, double* x, double* r, const double* p,
-            const double* q, double* sc);
+            const double* q, double* sc, const double* pa, int Ga, int slot, double* up, int Gu);
 void cg_alpha_finish(const tbdg_ctx* c, int G, const double* partial, double* sc);
-// One fused CG operator step: p_new = r invd + sc[5] p_old, q = H p_new and
-// the step length sc[4] = sc[0] / (p_new . q).  p_new must not alias p_old.
-void launch_cg_apply(const tbdg_ctx* c, double alpha, const double* r, const double* invd,
-                     const double* p_old, double* p_new, double* q, double* sc);
+// One fused CG operator step (beta from the update kernel's partials `up`,
+// p_new = r invd + beta p_old, q = H p_new, per-block p_new . q partials in
+// c->red_op); returns the number of partials.  p_new must not alias p_old.
+int launch_cg_apply(const tbdg_ctx* c, double alpha, const double* r, const double* invd,
+                    const double* p_old, double* p_new, double* q, double* sc, const double* up,
+                    int Gu, int first, int slot, int slot_prev);
 void gm_scale_precond(tbdg_ctx* c, int64_t n, double s, double* v, const double* invd, double* z);
 void gm_dots(tbdg_ctx* c, int64_t n, int k, const double* V, int64_t ldv, const double* w,
              double* dev_out);

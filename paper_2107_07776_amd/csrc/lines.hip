@@ -472,11 +472,14 @@ __global__ __launch_bounds__(256) void k_momentum_face(Geom g, LineGeom lg, Line
     for (int c = 0; c < DIM; ++c) y[((size_t)cell * DIM + c) * NB + nd] = s_y[c][pi];
 }
 
-// Pressure operator.  MODE 0: y = H p.  MODE 3: the CG direction update is
-// fused in front: the operator is applied to p_new = r * invd + beta * p
-// (beta = sc[5]), evaluated on the fly for the neighbour traces and stored to
-// p_out for the own cells (p_out must not alias p: other blocks still read
-// the old p), and one partial sum of p_new . y is written per block.
+// Pressure operator.  MODE 0: y = H p.  MODE 3: one fused CG step: every
+// block first adds the Gu partial sums (r.z, r.r) left by the previous update
+// kernel (same order in every block, so all blocks agree bit for bit) and
+// forms beta = rz / rz_prev (0 on the first step); the operator is then
+// applied to p_new = r * invd + beta * p, evaluated on the fly for the
+// neighbour traces and stored to p_out for the own cells (p_out must not
+// alias p: other blocks still read the old p); one partial sum of p_new . y
+// is written per block.  Block 0 records rz in sc[slot] and r.r in sc[2].
 template <int DIM, int NP, int MODE>
 __global__ __launch_bounds__(256) void k_pressure_face(Geom g, LineGeom lg, Line1D lt, Tables t,
                                                         double Cr, double cm,
@@ -485,8 +488,10 @@ __global__ __launch_bounds__(256) void k_pressure_face(Geom g, LineGeom lg, Line
                                                         double* partial,
                                                         const double* __restrict__ r,
                                                         const double* __restrict__ invd,
-                                                        const double* __restrict__ sc,
-                                                        double* __restrict__ p_out) {
+                                                        double* __restrict__ sc,
+                                                        double* __restrict__ p_out,
+                                                        const double* __restrict__ up, int Gu,
+                                                        int first, int slot, int slot_prev) {
     using L = Lay<DIM, NP>;
     using F = FaceLay<DIM, NP>;
     constexpr int NB = F::NB, NF = F::NF, CPB = F::CPB;
@@ -502,7 +507,26 @@ __global__ __launch_bounds__(256) void k_pressure_face(Geom g, LineGeom lg, Line
     const int lc = tid / NB, nd = tid % NB;
     const int cell = blk * CPB + lc;
     const bool active = lc < CPB && cell < Nc;
-    const double beta = MODE == 3 ? sc[5] : 0.0;
+    double beta = 0.0;
+    if (MODE == 3) {
+        __shared__ double s_beta;
+        double rz = 0.0, rr = 0.0;
+        for (int b = tid; b < Gu; b += 256) {
+            rz += up[b];
+            rr += up[Gu + b];
+        }
+        rz = red::block_sum(rz);
+        rr = red::block_sum(rr);
+        if (tid == 0) {
+            s_beta = first ? 0.0 : rz / sc[slot_prev];
+            if (blockIdx.x == 0) {
+                sc[slot] = rz;
+                sc[2] = rr;
+            }
+        }
+        __syncthreads();
+        beta = s_beta;
+    }
     double pown = 0.0;
     if (active) {
         const size_t gi = (size_t)cell * NB + nd;
@@ -628,7 +652,8 @@ void launch_apply_pressure(const tbdg_ctx* c, double alpha, const double* p, dou
                               c->geom, c->lgeom, c->line_p, c->tab, c->cr_p,               \
                               alpha * c->geom.vol, p, y, (int)c->Nc, (double*)nullptr,     \
                               (const double*)nullptr, (const double*)nullptr,              \
-                              (const double*)nullptr, (double*)nullptr);                   \
+                              (double*)nullptr, (double*)nullptr, (const double*)nullptr,  \
+                              0, 0, 0, 0);                                                 \
     }
     TBDG_LINE_DISPATCH(c, L_);
 #undef L_
@@ -645,8 +670,9 @@ void launch_diag_pressure(const tbdg_ctx* c, double alpha, double* d) {
     TBDG_HIP(hipGetLastError());
 }
 
-void launch_cg_apply(const tbdg_ctx* c, double alpha, const double* r, const double* invd,
-                     const double* p_old, double* p_new, double* q, double* sc) {
+int launch_cg_apply(const tbdg_ctx* c, double alpha, const double* r, const double* invd,
+                    const double* p_old, double* p_new, double* q, double* sc, const double* up,
+                    int Gu, int first, int slot, int slot_prev) {
     int G = 0;
 #define L_(D, N)                                                                           \
     {                                                                                      \
@@ -657,12 +683,13 @@ void launch_cg_apply(const tbdg_ctx* c, double alpha, const double* r, const dou
         hipExtLaunchKernelGGL((k_pressure_face<D, N - 1, 3>), dim3(G), dim3(FL::THREADS),  \
                               0, c->stream, tl.start(), tl.stop(), 0, c->geom, c->lgeom,   \
                               c->line_p, c->tab, c->cr_p, alpha * c->geom.vol, p_old, q,  \
-                              (int)c->Nc, c->red_op, r, invd, (const double*)sc, p_new);   \
+                              (int)c->Nc, c->red_op, r, invd, sc, p_new, up, Gu, first,    \
+                              slot, slot_prev);                                            \
     }
     TBDG_LINE_DISPATCH(c, L_);
 #undef L_
     TBDG_HIP(hipGetLastError());
-    cg_alpha_finish(c, G, c->red_op, sc);
+    return G;
 }
 
 void launch_apply_momentum(const tbdg_ctx* c, double mcoef, double theta, const double* w,

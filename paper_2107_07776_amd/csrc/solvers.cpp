@@ -192,11 +192,14 @@ tbdg_status solve_pressure(tbdg_ctx* c, int s, const double* b, double* x,
     int total = 0;
     const int check = 16;
     bool first_cycle = true;
+    // partial sums of the update kernel (r.z then r.r), Gu blocks
+    const int Gu = 256;
+    double* up = c->red_part;
     while (true) {
         // (re)start from the true residual
         launch_apply_pressure(c, alpha, x, q);
         vec_axpby(c->stream, n, 1.0, b, -1.0, q, r);
-        cg_start(c, n, invd, r, p, sc);
+        cg_start(c, n, invd, r, p, sc, up, Gu);
         TBDG_HIP(hipMemcpyAsync(c->host_out, sc, sizeof(double) * 8, hipMemcpyDeviceToHost, c->stream));
         TBDG_HIP(hipStreamSynchronize(c->stream));
         double rr = c->host_out[2];
@@ -212,21 +215,27 @@ tbdg_status solve_pressure(tbdg_ctx* c, int s, const double* b, double* x,
         }
         if (total >= o.maxiter) break;
         bool converged = false, broke = false;
-        // cg_start left p = invd r and sc[5] = 0, so the first fused step
-        // recomputes the same direction
         double* pa = p;
         double* pb = c->cp2;
+        int k = 0;
         while (total < o.maxiter) {
-            launch_cg_apply(c, alpha, r, invd, pa, pb, q, sc);
-            cg_upd(c, n, invd, x, r, pb, q, sc);
+            ++k;
+            const int slot = 8 + (k & 1), slot_prev = 8 + ((k - 1) & 1);
+            const int Ga = launch_cg_apply(c, alpha, r, invd, pa, pb, q, sc, up, Gu, k == 1, slot,
+                                           slot_prev);
+            cg_upd(c, n, invd, x, r, pb, q, sc, c->red_op, Ga, slot, up, Gu);
             std::swap(pa, pb);
             ++total;
             if (total % check == 0 || total >= o.maxiter) {
-                TBDG_HIP(hipMemcpyAsync(c->host_out, sc, sizeof(double) * 8, hipMemcpyDeviceToHost,
+                // r.r after this update: add the update kernel's partials here
+                TBDG_HIP(hipMemcpyAsync(c->host_out, up + Gu, sizeof(double) * Gu,
+                                        hipMemcpyDeviceToHost, c->stream));
+                TBDG_HIP(hipMemcpyAsync(c->host_out + Gu, sc + 6, sizeof(double), hipMemcpyDeviceToHost,
                                         c->stream));
                 TBDG_HIP(hipStreamSynchronize(c->stream));
-                rr = c->host_out[2];
-                if (c->host_out[6] != 0.0) {
+                rr = 0.0;
+                for (int i = 0; i < Gu; ++i) rr += c->host_out[i];
+                if (c->host_out[Gu] != 0.0) {
                     broke = true;
                     break;
                 }

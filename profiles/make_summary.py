@@ -1,23 +1,25 @@
-"""Write a short text summary of a rocprofv3 kernel-trace database.
+"""Write a short text summary of a rocprofv3 kernel-statistics file.
 
-    python profiles/make_summary.py <results.db> <title> <command> > profiles/<name>.txt
+    python profiles/make_summary.py <kernel_stats.csv> <title> <command>
+
+Reads the CSV that `rocprofv3 --kernel-trace --stats --output-format csv`
+writes (`*_kernel_stats.csv`) and prints the 20 most expensive kernels.
 """
-import sqlite3
+import csv
 import sys
 
 
 def main():
-    db, title, cmd = sys.argv[1], sys.argv[2], sys.argv[3]
-    con = sqlite3.connect(db)
-    rows = con.execute("select name, total_calls, total_duration, average, percentage "
-                       "from top_kernels order by total_duration desc limit 20").fetchall()
+    path, title, cmd = sys.argv[1], sys.argv[2], sys.argv[3]
+    rows = list(csv.DictReader(open(path)))
     print(f"# {title}")
     print(f"# command: {cmd}")
-    print("# times in microseconds (rocprofv3 --kernel-trace --stats, top_kernels view)")
+    print("# rocprofv3 --kernel-trace --stats (kernel_stats.csv); times in microseconds")
     print(f"{'calls':>7} {'total_us':>12} {'avg_us':>10} {'pct':>6}  kernel")
-    for name, calls, tot, avg, pct in rows:
-        short = name.replace("trbdg::(anonymous namespace)::", "").replace("void ", "").split("(")[0]
-        print(f"{calls:>7} {tot:>12.1f} {avg:>10.3f} {pct:>6.2f}  {short}")
+    for r in rows[:20]:
+        name = r["Name"].replace("trbdg::(anonymous namespace)::", "").replace("void ", "").split("(")[0]
+        print(f"{int(r['Calls']):>7} {float(r['TotalDurationNs']) / 1e3:>12.1f} "
+              f"{float(r['AverageNs']) / 1e3:>10.3f} {float(r['Percentage']):>6.2f}  {name}")
 
 
 if __name__ == "__main__":
