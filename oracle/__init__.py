@@ -19,7 +19,9 @@ Navier-Stokes equations", arXiv 2107.07776):
 * ``stepper``  - the two TR-BDF2 stages in algebraic form (Sec. 2 eqs.
                  first_stage, helmholtz2a, second_stage, helmholtz3a and the
                  algebraic systems at the end of Sec. 3), solved directly.
-* ``exact``    - closed-form reference solutions used as pins.
+
+Closed-form reference fields (Taylor-Green, Kovasznay) live in the separate
+``synthetic`` package, which holds no arithmetic of the method.
 
 Every operator is an assembled sparse matrix: no sum factorisation, no
 fusion.  Readings of passages that are silent or garbled are listed in the
