@@ -105,6 +105,8 @@ def main():
     ap.add_argument("--workload", default="tgv32")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-profile", action="store_true")
+    ap.add_argument("--precond", default="jacobi", choices=["jacobi", "mg_fp32", "mg_bf16"])
+    ap.add_argument("--mg-degree", type=int, default=0)
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py: this build runs on exactly one GPU; --gpus {args.gpus} is not supported",
@@ -127,10 +129,17 @@ def main():
     H = torch.tensor(u0 if uh0 is None else uh0, device=dev)
     P = torch.tensor(p0, device=dev)
     tol = W["tol"]
+    if args.precond != "jacobi":
+        t_setup = time.perf_counter()
+        ctx.mg_setup(degree=args.mg_degree)
+        torch.cuda.synchronize()
+        log(f"[bench] multigrid set-up {time.perf_counter() - t_setup:.2f}s: "
+            f"{[(l['np'], l['cells'], l['dofs']) for l in ctx.mg_levels()]}")
     t = 0.0
     n = 0
     for i in range(args.warmup):
-        info, _ = ctx.step(U, H, P, t, n, mom_tol=tol, prs_tol=tol, prs_maxiter=20000)
+        info, _ = ctx.step(U, H, P, t, n, mom_tol=tol, prs_tol=tol, prs_maxiter=20000,
+                           precond=args.precond)
         t += W["dt"]
         n += 1
         log(f"[bench] warmup step {i + 1}/{args.warmup}: iterations {[x['iters'] for x in info]}")
@@ -143,7 +152,8 @@ def main():
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     for i in range(args.steps):
-        info, _ = ctx.step(U, H, P, t, n, mom_tol=tol, prs_tol=tol, prs_maxiter=20000)
+        info, _ = ctx.step(U, H, P, t, n, mom_tol=tol, prs_tol=tol, prs_maxiter=20000,
+                           precond=args.precond)
         t += W["dt"]
         n += 1
         iters.append([x["iters"] for x in info])

@@ -152,8 +152,13 @@ TBDG_API tbdg_status tbdg_rhs_pressure(tbdg_ctx* ctx, int stage, const double* u
 
 /* Krylov options.  tol: relative true residual ||b - A x||_2 <= tol ||b||_2.
  * maxiter: total iterations (GMRES: over all restarts).  restart: GMRES
- * basis size m (<= 60).  precond: 0 = Jacobi.  guess: 0 = use the content
- * of x_inout.                                                              */
+ * basis size m (<= 60).  precond: TBDG_PRECOND_*; the multigrid values apply
+ * to tbdg_solve_pressure only.  guess: 0 = use the content of x_inout.     */
+enum {
+    TBDG_PRECOND_JACOBI = 0,
+    TBDG_PRECOND_MG_FP32 = 1,   /* h/p-multigrid V-cycle in FP32 under FP64 flexible CG */
+    TBDG_PRECOND_MG_BF16 = 2    /* the same with BF16 storage on the finest level        */
+};
 typedef struct {
     double tol;
     int maxiter;
@@ -177,10 +182,57 @@ TBDG_API tbdg_status tbdg_solve_momentum(tbdg_ctx* ctx, int stage, const double*
                                 const double* rhs, double* u_inout,
                                 const tbdg_solver_opts* opts, tbdg_solve_info* info);
 
-/* Helmholtz solve (Jacobi-preconditioned CG): (alpha_s M^p + K) p = rhs.     */
+/* Helmholtz solve: (alpha_s M^p + K) p = rhs by CG with the Jacobi
+ * preconditioner, or by flexible CG (Polak-Ribiere beta) preconditioned with
+ * one multigrid V-cycle (tbdg_mg_setup; built with default parameters on
+ * first use).  Residuals, dot products, the recurrences and the coarsest
+ * solve are FP64 in every case.                                             */
 TBDG_API tbdg_status tbdg_solve_pressure(tbdg_ctx* ctx, int stage, const double* rhs,
                                 double* p_inout, const tbdg_solver_opts* opts,
                                 tbdg_solve_info* info);
+
+/* Multigrid preconditioner of the pressure Helmholtz operator.  The paper
+ * preconditions the pressure CG with a multigrid (Sec. 4) without details;
+ * this one is an h/p hierarchy on the periodic affine box: level 0 is
+ * Q_{k-1} on the mesh, then Q_1 on the same cells (when k-1 > 1), then Q_1
+ * on meshes with every direction halved while all directions have an even
+ * cell count and the level has more than coarse_cells cells.  Each level
+ * operator is rediscretised (alpha_s M^p + K with the level's SIP penalty
+ * (q+1)^2/h); prolongation evaluates the coarse polynomial at the fine
+ * nodes, restriction is its transpose; smoothing is `degree` steps of
+ * Chebyshev acceleration of the Jacobi-preconditioned level operator on
+ * [lam/range, safety*lam], lam the largest Ritz value of lanczos_steps
+ * Lanczos steps (FP64, start vector: SplitMix64 outputs from state 0, top
+ * 53 bits scaled to [0,1), minus 1/2) on D^{-1/2} H D^{-1/2}; the coarsest
+ * level is solved with the inverse formed from its FP64 Cholesky factor.
+ * V-cycle: zero initial guess, pre- and post-smoothing.  Smoother vectors
+ * are FP32 (BF16 storage on level 0 for TBDG_PRECOND_MG_BF16).             */
+typedef struct {
+    int degree;          /* Chebyshev steps per smoothing pass, 2..16 (0 => 4)   */
+    int lanczos_steps;   /* 0 => 15                                             */
+    double range;        /* 0 => 15                                             */
+    double safety;       /* 0 => 1.1                                            */
+    int coarse_cells;    /* 0 => 64 (3D) / 16 (2D)                              */
+    int max_coarse_dofs; /* largest coarsest level solved densely (0 => 2048)    */
+} tbdg_mg_desc;
+
+/* (Re)builds the hierarchy for both stages (desc NULL: defaults).  Fails
+ * with TBDG_EUNSUPPORTED when fewer than two levels result or the coarsest
+ * level exceeds max_coarse_dofs; allocates device memory held until
+ * tbdg_destroy or the next tbdg_mg_setup.                                  */
+TBDG_API tbdg_status tbdg_mg_setup(tbdg_ctx* ctx, const tbdg_mg_desc* desc);
+
+/* Hierarchy description (after tbdg_mg_setup): *n_levels; for level l < cap,
+ * desc[5l..5l+4] = nodes per direction, cells in x, y, z (1 if unused), DoFs;
+ * lambda[l] and lambda[cap + l] = eigenvalue estimates of stages 1 and 2
+ * (0 on the coarsest level).  Host arrays; desc or lambda may be NULL.     */
+TBDG_API tbdg_status tbdg_mg_levels(tbdg_ctx* ctx, int cap, int* n_levels, int64_t* desc,
+                                    double* lambda);
+
+/* z = B_s r: one V-cycle of the stage-s hierarchy (precision 1: FP32,
+ * 2: BF16 storage on level 0).  r, z: device, N_p, FP64; may not alias.     */
+TBDG_API tbdg_status tbdg_mg_apply(tbdg_ctx* ctx, int stage, int precision, const double* r,
+                                   double* z);
 
 /* TR-BDF2 state: u = u^n, u_hist = u^{n-1+gamma} (history level of the
  * stage-1 extrapolation), p = p^n; t and n are host values.                 */

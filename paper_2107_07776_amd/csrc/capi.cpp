@@ -90,6 +90,7 @@ void free_all(tbdg_ctx* c) {
     dfree(c->s_pg);
     dfree(c->s_p1);
     dfree(c->s_pv);
+    trbdg::mg_free(c);
 }
 
 tbdg_solver_opts defaults(const tbdg_solver_opts* o) {
@@ -99,7 +100,8 @@ tbdg_solver_opts defaults(const tbdg_solver_opts* o) {
     require(r.tol > 0.0 && std::isfinite(r.tol), "solver tol must be positive");
     require(r.maxiter > 0, "solver maxiter must be positive");
     require(r.restart >= 0 && r.restart <= GMRES_MAX, "GMRES restart must be in [0, 60]");
-    require(r.precond == 0, "only the Jacobi preconditioner (0) is available");
+    require(r.precond >= TBDG_PRECOND_JACOBI && r.precond <= TBDG_PRECOND_MG_BF16,
+            "unknown preconditioner");
     return r;
 }
 
@@ -376,6 +378,8 @@ tbdg_status tbdg_solve_momentum(tbdg_ctx* c, int stage, const double* w, const d
         check_stage(stage);
         require(w && rhs && u_inout, "null pointer");
         const tbdg_solver_opts o = defaults(opts);
+        if (o.precond != TBDG_PRECOND_JACOBI)
+            throw Error(TBDG_EUNSUPPORTED, "the momentum solve has only the Jacobi preconditioner");
         const tbdg_status s = trbdg::solve_momentum(c, stage, w, rhs, u_inout, o, info);
         if (s != TBDG_OK) c->last_error = "momentum GMRES did not converge";
         return s;
@@ -402,9 +406,54 @@ tbdg_status tbdg_step(tbdg_ctx* c, tbdg_state* state, const tbdg_solver_opts* mo
         require(state && state->u && state->u_hist && state->p, "null state");
         const tbdg_solver_opts mo = defaults(mom);
         const tbdg_solver_opts po = defaults(prs);
+        if (mo.precond != TBDG_PRECOND_JACOBI)
+            throw Error(TBDG_EUNSUPPORTED, "the momentum solve has only the Jacobi preconditioner");
         const tbdg_status s = trbdg::step(c, state, mo, po, info);
         if (s != TBDG_OK && c->last_error.empty()) c->last_error = "a stage solve failed";
         return s;
+    });
+}
+
+tbdg_status tbdg_mg_setup(tbdg_ctx* c, const tbdg_mg_desc* desc) {
+    if (!c) return TBDG_EINVAL;
+    return guarded(c, [&]() {
+        trbdg::mg_setup(c, desc);
+        return TBDG_OK;
+    });
+}
+
+tbdg_status tbdg_mg_levels(tbdg_ctx* c, int cap, int* n_levels, int64_t* desc, double* lambda) {
+    if (!c) return TBDG_EINVAL;
+    return guarded(c, [&]() {
+        require(n_levels != nullptr && cap >= 0, "null n_levels or negative cap");
+        if (!c->mg) throw Error(TBDG_EINVAL, "multigrid hierarchy not built (tbdg_mg_setup)");
+        const int nl = (int)c->mg->lv.size();
+        *n_levels = nl;
+        for (int l = 0; l < nl && l < cap; ++l) {
+            const trbdg::MGLevel& L = c->mg->lv[l];
+            if (desc) {
+                desc[5 * l] = L.np;
+                for (int a = 0; a < 3; ++a) desc[5 * l + 1 + a] = L.geom.nc[a];
+                desc[5 * l + 4] = L.N;
+            }
+            if (lambda) {
+                lambda[l] = L.lam[1];
+                lambda[cap + l] = L.lam[2];
+            }
+        }
+        return TBDG_OK;
+    });
+}
+
+tbdg_status tbdg_mg_apply(tbdg_ctx* c, int stage, int precision, const double* r, double* z) {
+    if (!c) return TBDG_EINVAL;
+    return guarded(c, [&]() {
+        check_stage(stage);
+        require(r && z, "null pointer");
+        require(r != z, "r and z may not alias");
+        require(precision == 1 || precision == 2, "precision must be 1 (FP32) or 2 (BF16)");
+        trbdg::mg_apply(c, stage, precision, r, z);
+        return TBDG_OK;
     });
 }
 

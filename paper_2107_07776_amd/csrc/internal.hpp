@@ -77,6 +77,60 @@ struct KTimer {
     int64_t count[2] = {0, 0};
 };
 
+// ---- multigrid hierarchy of the pressure operator ------------------------------
+constexpr int MG_MAXDEG = 16;     // largest Chebyshev degree
+// smoother step kinds of the fused level kernel
+enum { MG_PRE1 = 0, MG_STEP = 1, MG_LAST = 2, MG_RES = 3, MG_ZFIN = 4 };
+constexpr int MG_MAXLEVELS = 16;
+
+// FP32 1D tables of one level (row i = test function, column j = trial):
+// A = SIP element matrix with both end-face self terms, L0/L1/dL0/dL1 = basis
+// values/derivatives at the cell ends, W = Gauss weights; Cr = reference
+// penalty; cm[s] = alpha_s |K| per stage; sdiff[a] = |K| / h_a^2.
+struct LevelTabF {
+    float A[NMAX * NMAX];
+    float L0[NMAX], L1[NMAX], dL0[NMAX], dL1[NMAX], W[NMAX];
+    float Cr;
+    float cm[3];
+    float sdiff[3];
+};
+
+// 1D transfer matrices to the next coarser level: T[b][i][j] = coarse Q1
+// basis j at fine node i (b: child offset for an h-transfer, 0 for p).
+struct TransferTab {
+    float T[2][NMAX][2];
+};
+
+struct MGLevel {
+    int np = 0;                 // nodes per direction (degree + 1)
+    int64_t Nc = 0, N = 0;      // cells, DoFs
+    Geom geom{};
+    LineGeom lgeom{};
+    Line1D line{};              // FP64 element matrices (setup, eigenvalue estimate)
+    Tables tab{};               // FP64 pressure tables (only the *p entries are used)
+    double cr = 0.0;
+    LevelTabF tf{};
+    int transfer = 0;           // to the next coarser level: 1 = p, 2 = h, 0 = coarsest
+    TransferTab tt{};
+    float *b = nullptr, *x = nullptr, *r = nullptr, *d[2] = {nullptr, nullptr};
+    uint16_t *hb = nullptr, *hx = nullptr, *hr = nullptr, *hd[2] = {nullptr, nullptr};  // bf16 (level 0)
+    float* invd[3] = {nullptr, nullptr, nullptr};
+    double lam[3] = {0.0, 0.0, 0.0};      // eigenvalue estimate per stage
+    double theta[3] = {0.0, 0.0, 0.0};
+    double c1[3][MG_MAXDEG] = {}, c2[3][MG_MAXDEG] = {};
+};
+
+struct MGData {
+    int degree = 4, lanczos_steps = 15, coarse_cells = 0, max_coarse = 2048;
+    double range = 15.0, safety = 1.1;
+    std::vector<MGLevel> lv;
+    double* ainv[3] = {nullptr, nullptr, nullptr};   // coarse inverses per stage (device, row-major)
+    double* z = nullptr;        // FP64 preconditioned residual (N_p)
+    double* zpart = nullptr;    // partial sums z.r, z.q of the finest smoother step
+    double* rpart = nullptr;    // partial sums r.r of the FP64 update
+    std::vector<void*> allocs;
+};
+
 }  // namespace trbdg
 
 struct tbdg_ctx {
@@ -129,6 +183,7 @@ struct tbdg_ctx {
     double* s_pg = nullptr;
     double* s_p1 = nullptr;
     double* s_pv = nullptr;     // pressure interpolated to velocity nodes (Ns)
+    trbdg::MGData* mg = nullptr;    // multigrid hierarchy (built on first use)
 
     double alpha(int s) const;
     double mcoef(int s) const { return 1.0 / (beta[s] * dt); }
@@ -218,5 +273,56 @@ void gm_update_norm(tbdg_ctx* c, int64_t n, int k, const double* V, int64_t ldv,
 // x += gz / diag (velocity layout)
 void vec_add_div_diag_u(hipStream_t s, int64_t n, int dim, int64_t nb, const double* gz,
                         const double* d, double* x);
+
+
+// ---- pressure operator on any multigrid level (lines.hip) -------------------------
+void launch_pressure_level(hipStream_t s, int dim, int np, const Geom& g, const LineGeom& lg,
+                           const Line1D& lt, const Tables& t, double cr, double cm,
+                           const double* p, double* y, int64_t Nc);
+void launch_diag_pressure_level(hipStream_t s, int dim, int np, const Geom& g, const LineGeom& lg,
+                                const Line1D& lt, const Tables& t, double cm, double* d,
+                                int64_t Nc);
+// One fused flexible-CG operator step: p_new = z + sc[5] p_old, q = H p_new,
+// per-block p_new . q partials in c->red_op; returns the number of partials.
+int launch_fcg_apply(const tbdg_ctx* c, double alpha, const double* z, const double* p_old,
+                     double* p_new, double* q, double* sc);
+
+// ---- multigrid kernels (mg.hip) ---------------------------------------------------
+template <typename S>
+int launch_level_step(hipStream_t st, int dim, const MGLevel& L, int stage, int mode, float c1,
+                      float c2, const S* dop, S* x, S* r, const S* b, S* dout, double* z,
+                      const double* r64, const double* q64, double* partial);
+int level_blocks(int dim, const MGLevel& L);
+template <typename S>
+void launch_restrict(hipStream_t st, int dim, const MGLevel& F, const MGLevel& C, int stage,
+                     float c2, const S* rf, bool with_d0);
+template <typename S>
+void launch_prolong(hipStream_t st, int dim, const MGLevel& F, const MGLevel& C, S* xf,
+                    const float* dc);
+void launch_coarse(hipStream_t st, const double* Ainv, const float* b, float* x, int n);
+template <typename S>
+int launch_mg_prep(hipStream_t st, int64_t n, int update, const double* pa, int Ga, double* sc,
+                   int slot, double* x, double* r, const double* p, const double* q, S* b0, S* d0,
+                   const float* invd, float c2, double* partial);
+void launch_mg_beta(hipStream_t st, const double* partial, int G, double* sc, int first, int slot,
+                    int slot_prev);
+void vec_mul(hipStream_t st, int64_t n, const double* a, const double* b, double* out);
+void vec_unit(hipStream_t st, int64_t n, int64_t j, double* out);
+void vec_inv_sqrt(hipStream_t st, int64_t n, const double* d, double* out, float* invf);
+
+// ---- set-up helpers (setup.cpp) ---------------------------------------------------
+void gauss_legendre(int n, double* x, double* w);
+double lagrange_value(const double* z, int n, int j, double x);
+void build_line_matrix(int n, const double* W, const double* D, const double* L0, const double* L1,
+                       const double* dL0, const double* dL1, double Cr, Line1D& m);
+void level_tables(int np, double pen_p, Tables& t, Line1D& line, double& cr);
+
+// ---- multigrid host side (mg.cpp) ---------------------------------------------------
+void mg_setup(tbdg_ctx* c, const tbdg_mg_desc* desc);
+void mg_free(tbdg_ctx* c);
+// z = B r, one V-cycle (precision 1: FP32, 2: BF16 storage on the finest level)
+void mg_apply(tbdg_ctx* c, int stage, int precision, const double* r, double* z);
+tbdg_status solve_pressure_mg(tbdg_ctx* c, int s, const double* b, double* x,
+                              const tbdg_solver_opts& o, tbdg_solve_info* info);
 
 }  // namespace trbdg

@@ -18,6 +18,7 @@
 // every 1D operator directly: no face buffer, no block-wide exchange beyond
 // the staging of its own cell.
 #include "internal.hpp"
+#include "lines.hpp"
 #include "reduce.hpp"
 
 #include <hip/hip_ext.h>
@@ -25,64 +26,7 @@
 namespace trbdg {
 namespace {
 
-constexpr int ipow(int b, int e) { return e == 0 ? 1 : b * ipow(b, e - 1); }
-
-template <int DIM, int N>
-struct Lay {
-    static constexpr int NB = ipow(N, DIM);
-    static constexpr int CPB = (256 / NB) > 0 ? (256 / NB) : 1;
-    static constexpr int THREADS = CPB * NB;
-    __device__ static inline int node(int a, int m, int t) {
-        if (DIM == 2) return a == 0 ? m + N * t : t + N * m;
-        if (a == 0) return m + N * t;
-        if (a == 1) return (t % N) + N * m + N * N * (t / N);
-        return t + N * N * m;
-    }
-    __device__ static inline int coord(int nd, int a) {
-        return a == 0 ? nd % N : (a == 1 ? (nd / N) % N : nd / (N * N));
-    }
-    __device__ static inline int tang(int nd, int a) {
-        if (DIM == 2) return a == 0 ? nd / N : nd % N;
-        if (a == 0) return nd / N;
-        if (a == 1) return (nd % N) + N * (nd / (N * N));
-        return nd % (N * N);
-    }
-    __device__ static inline double wtan(const double* W, int t) {
-        return DIM == 2 ? W[t] : W[t % N] * W[t / N];
-    }
-    __device__ static inline double wnode(const double* W, int nd) {
-        double w = 1.0;
-        for (int a = 0; a < DIM; ++a) w *= W[coord(nd, a)];
-        return w;
-    }
-};
-
-// q = r / n for 0 <= r < 2^31 from a double reciprocal, corrected to exact.
-__device__ inline int div_fast(int r, int n, double inv_n) {
-    int q = (int)((double)r * inv_n);
-    if (q * n > r) --q;
-    else if ((q + 1) * n <= r) ++q;
-    return q;
-}
-
-// Cell coordinates and the two neighbours of a cell along every direction.
-template <int DIM>
-struct Nbrs {
-    int left[3], right[3];
-    __device__ Nbrs(const Geom& g, const LineGeom& lg, int cell) {
-        int r = cell;
-        int stride = 1;
-        for (int a = 0; a < DIM; ++a) {
-            const int n = g.nc[a];
-            const int q = div_fast(r, n, lg.inv_nc[a]);
-            const int ca = r - q * n;
-            r = q;
-            left[a] = ca > 0 ? cell - stride : (lg.periodic[a] ? cell + (n - 1) * stride : -1);
-            right[a] = ca < n - 1 ? cell + stride : (lg.periodic[a] ? cell - (n - 1) * stride : -1);
-            stride *= n;
-        }
-    }
-};
+using namespace lines;
 
 // ============================================================================
 // Pressure Helmholtz operator y = alpha M^p p + K p
@@ -296,22 +240,6 @@ __global__ __launch_bounds__(256) void k_momentum_line(Geom g, LineGeom lg, Line
 // blocks to the 8 XCDs in turn), so each XCD sweeps a contiguous slab of
 // cells and the neighbour lines it gathers mostly hit its own L2.
 // ============================================================================
-// Blocks are always launched with 256 threads (four full waves, so the
-// wave-level shuffles of the block reductions never read an inactive lane);
-// threads beyond CPB whole cells idle in phases 1 and 3.
-template <int DIM, int N>
-struct FaceLay {
-    static constexpr int NB = ipow(N, DIM);
-    static constexpr int NF = ipow(N, DIM - 1);
-    static constexpr int CPB = (256 / NB) > 0 ? (256 / NB) : 1;
-    static constexpr int THREADS = 256;
-};
-
-__device__ inline int xcd_block(int b, int G) {
-    const int x = b & 7, i = b >> 3;
-    const int q = G >> 3, r = G & 7;
-    return x < r ? x * (q + 1) + i : r * (q + 1) + (x - r) * q + i;
-}
 
 template <int DIM, int N>
 __global__ __launch_bounds__(256) void k_momentum_face(Geom g, LineGeom lg, Line1D lt, Tables t,
@@ -480,6 +408,8 @@ __global__ __launch_bounds__(256) void k_momentum_face(Geom g, LineGeom lg, Line
 // neighbour traces and stored to p_out for the own cells (p_out must not
 // alias p: other blocks still read the old p); one partial sum of p_new . y
 // is written per block.  Block 0 records rz in sc[slot] and r.r in sc[2].
+// MODE 4: the same step of flexible CG, with the preconditioned residual z
+// passed in `r` and beta already in sc[5]: p_new = z + beta p.
 template <int DIM, int NP, int MODE>
 __global__ __launch_bounds__(256) void k_pressure_face(Geom g, LineGeom lg, Line1D lt, Tables t,
                                                         double Cr, double cm,
@@ -508,6 +438,7 @@ __global__ __launch_bounds__(256) void k_pressure_face(Geom g, LineGeom lg, Line
     const int cell = blk * CPB + lc;
     const bool active = lc < CPB && cell < Nc;
     double beta = 0.0;
+    if (MODE == 4) beta = sc[5];
     if (MODE == 3) {
         __shared__ double s_beta;
         double rz = 0.0, rr = 0.0;
@@ -530,8 +461,8 @@ __global__ __launch_bounds__(256) void k_pressure_face(Geom g, LineGeom lg, Line
     double pown = 0.0;
     if (active) {
         const size_t gi = (size_t)cell * NB + nd;
-        pown = MODE == 3 ? r[gi] * invd[gi] + beta * p[gi] : p[gi];
-        if (MODE == 3) p_out[gi] = pown;
+        pown = MODE == 3 ? r[gi] * invd[gi] + beta * p[gi] : MODE == 4 ? r[gi] + beta * p[gi] : p[gi];
+        if (MODE >= 3) p_out[gi] = pown;
     }
     s_p[tid] = pown;
     if (lc < CPB && nd == 0) {
@@ -553,7 +484,9 @@ __global__ __launch_bounds__(256) void k_pressure_face(Geom g, LineGeom lg, Line
 #pragma unroll
                 for (int m = 0; m < NP; ++m) {
                     const size_t gi = (size_t)nbr * NB + L::node(a, m, tt);
-                    const double pv = MODE == 3 ? r[gi] * invd[gi] + beta * p[gi] : p[gi];
+                    const double pv = MODE == 3   ? r[gi] * invd[gi] + beta * p[gi]
+                                      : MODE == 4 ? r[gi] + beta * p[gi]
+                                                  : p[gi];
                     v += (s ? t.L0p[m] : t.L1p[m]) * pv;
                     d += (s ? t.dL0p[m] : t.dL1p[m]) * pv;
                 }
@@ -620,7 +553,7 @@ __global__ __launch_bounds__(256) void k_pressure_face(Geom g, LineGeom lg, Line
         for (int a = 0; a < DIM; ++a) acc += s_y[a][tid];
         y[(size_t)cell * NB + nd] = acc;
     }
-    if (MODE == 3) {
+    if (MODE >= 3) {
         const double pq = red::block_sum(active ? acc * pown : 0.0);
         if (threadIdx.x == 0) partial[blockIdx.x] = pq;
     }
@@ -685,6 +618,68 @@ int launch_cg_apply(const tbdg_ctx* c, double alpha, const double* r, const doub
                               c->line_p, c->tab, c->cr_p, alpha * c->geom.vol, p_old, q,  \
                               (int)c->Nc, c->red_op, r, invd, sc, p_new, up, Gu, first,    \
                               slot, slot_prev);                                            \
+    }
+    TBDG_LINE_DISPATCH(c, L_);
+#undef L_
+    TBDG_HIP(hipGetLastError());
+    return G;
+}
+
+// Pressure-type operator of one multigrid level (FP64): any node count np
+// per direction (2..5 in 2D, 2..3 in 3D) with the level's own geometry.
+#define TBDG_NP_DISPATCH(dim, np, FN)                                                    \
+    do {                                                                                  \
+        if ((dim) == 2 && (np) == 2) { FN(2, 2); }                                        \
+        else if ((dim) == 2 && (np) == 3) { FN(2, 3); }                                   \
+        else if ((dim) == 2 && (np) == 4) { FN(2, 4); }                                   \
+        else if ((dim) == 2 && (np) == 5) { FN(2, 5); }                                   \
+        else if ((dim) == 3 && (np) == 2) { FN(3, 2); }                                   \
+        else if ((dim) == 3 && (np) == 3) { FN(3, 3); }                                   \
+        else throw Error(TBDG_EUNSUPPORTED, "unsupported (dim, pressure nodes)");          \
+    } while (0)
+
+void launch_pressure_level(hipStream_t s, int dim, int np, const Geom& g, const LineGeom& lg,
+                           const Line1D& lt, const Tables& t, double cr, double cm,
+                           const double* p, double* y, int64_t Nc) {
+#define L_(D, NP)                                                                          \
+    {                                                                                      \
+        using FL = FaceLay<D, NP>;                                                         \
+        hipLaunchKernelGGL((k_pressure_face<D, NP, 0>), dim3(nblk(Nc, FL::CPB)),           \
+                           dim3(FL::THREADS), 0, s, g, lg, lt, t, cr, cm, p, y, (int)Nc,   \
+                           (double*)nullptr, (const double*)nullptr, (const double*)nullptr, \
+                           (double*)nullptr, (double*)nullptr, (const double*)nullptr, 0, \
+                           0, 0, 0);                                                       \
+    }
+    TBDG_NP_DISPATCH(dim, np, L_);
+#undef L_
+    TBDG_HIP(hipGetLastError());
+}
+
+void launch_diag_pressure_level(hipStream_t s, int dim, int np, const Geom& g, const LineGeom& lg,
+                                const Line1D& lt, const Tables& t, double cm, double* d,
+                                int64_t Nc) {
+#define L_(D, NP)                                                                          \
+    hipLaunchKernelGGL((k_pressure_line<D, NP, 1>), dim3(nblk(Nc * ipow(NP, D), 256)),     \
+                       dim3(256), 0, s, g, lg, lt, t, cm, nullptr, d, (int)Nc, nullptr);
+    TBDG_NP_DISPATCH(dim, np, L_);
+#undef L_
+    TBDG_HIP(hipGetLastError());
+}
+
+int launch_fcg_apply(const tbdg_ctx* c, double alpha, const double* z, const double* p_old,
+                     double* p_new, double* q, double* sc) {
+    int G = 0;
+#define L_(D, N)                                                                           \
+    {                                                                                      \
+        using FL = FaceLay<D, N - 1>;                                                      \
+        G = (int)nblk(c->Nc, FL::CPB);                                                     \
+        if (G > c->red_op_len) throw Error(TBDG_EINVAL, "operator partial buffer too small"); \
+        TimedLaunch tl(c, 0);                                                              \
+        hipExtLaunchKernelGGL((k_pressure_face<D, N - 1, 4>), dim3(G), dim3(FL::THREADS),  \
+                              0, c->stream, tl.start(), tl.stop(), 0, c->geom, c->lgeom,   \
+                              c->line_p, c->tab, c->cr_p, alpha * c->geom.vol, p_old, q,  \
+                              (int)c->Nc, c->red_op, z, (const double*)nullptr, sc, p_new, \
+                              (const double*)nullptr, 0, 0, 0, 0);                         \
     }
     TBDG_LINE_DISPATCH(c, L_);
 #undef L_

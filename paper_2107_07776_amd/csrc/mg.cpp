@@ -1,0 +1,561 @@
+// Multigrid preconditioner of the pressure Helmholtz operator: hierarchy
+// set-up (level geometry and tables, Jacobi diagonals, Lanczos eigenvalue
+// estimates, dense coarse inverse), the V-cycle and the FP64 flexible CG
+// that uses it.  The hierarchy, smoother and cycle are defined in the header
+// next to tbdg_mg_setup.
+#include <algorithm>
+#include <cmath>
+#include <cstring>
+#include <utility>
+#include <vector>
+
+#include "internal.hpp"
+
+namespace trbdg {
+
+namespace {
+
+template <typename T>
+T* mg_alloc(MGData* m, int64_t n) {
+    void* p = nullptr;
+    TBDG_HIP(hipMalloc(&p, sizeof(T) * (size_t)std::max<int64_t>(n, 1)));
+    m->allocs.push_back(p);
+    return static_cast<T*>(p);
+}
+
+// SplitMix64 (Steele, Lea and Flood 2014): state += golden gamma, then two
+// xor-shift-multiply rounds and a final xor-shift.
+uint64_t splitmix64_next(uint64_t& s) {
+    s += 0x9E3779B97F4A7C15ull;
+    uint64_t z = s;
+    z = (z ^ (z >> 30)) * 0xBF58476D1CE4E5B9ull;
+    z = (z ^ (z >> 27)) * 0x94D049BB133111EBull;
+    return z ^ (z >> 31);
+}
+
+// Number of eigenvalues below x of the symmetric tridiagonal matrix with
+// diagonal a and off-diagonal b (Sturm sequence of the LDL^T pivots).
+int sturm_count(const std::vector<double>& a, const std::vector<double>& b, double x) {
+    int cnt = 0;
+    double q = 1.0;
+    for (size_t i = 0; i < a.size(); ++i) {
+        const double off = i > 0 ? b[i - 1] * b[i - 1] : 0.0;
+        q = a[i] - x - (i > 0 ? off / q : 0.0);
+        if (q == 0.0) q = -1e-300;
+        if (q < 0.0) ++cnt;
+    }
+    return cnt;
+}
+
+// Largest eigenvalue of a symmetric tridiagonal matrix by bisection between
+// the Gershgorin bounds.
+double tridiag_max(const std::vector<double>& a, const std::vector<double>& b) {
+    const int n = (int)a.size();
+    double lo = a[0], hi = a[0];
+    for (int i = 0; i < n; ++i) {
+        const double r = (i > 0 ? std::fabs(b[i - 1]) : 0.0) + (i < n - 1 ? std::fabs(b[i]) : 0.0);
+        lo = std::min(lo, a[i] - r);
+        hi = std::max(hi, a[i] + r);
+    }
+    for (int it = 0; it < 200; ++it) {
+        const double mid = 0.5 * (lo + hi);
+        if (mid <= lo || mid >= hi) break;
+        if (sturm_count(a, b, mid) == n) hi = mid;
+        else lo = mid;
+    }
+    return hi;
+}
+
+double host_dot(tbdg_ctx* c, int64_t n, const double* a, const double* b) {
+    dot2(c, n, a, b, c->red_out + 63);
+    TBDG_HIP(hipMemcpyAsync(c->host_out, c->red_out + 63, sizeof(double), hipMemcpyDeviceToHost,
+                            c->stream));
+    TBDG_HIP(hipStreamSynchronize(c->stream));
+    return c->host_out[0];
+}
+
+void apply_level64(tbdg_ctx* c, const MGLevel& L, double alpha, const double* p, double* y) {
+    launch_pressure_level(c->stream, c->dim, L.np, L.geom, L.lgeom, L.line, L.tab, L.cr,
+                          alpha * L.geom.vol, p, y, L.Nc);
+}
+
+// Largest Ritz value of `steps` Lanczos steps on D^{-1/2} H D^{-1/2} (FP64).
+double lanczos(tbdg_ctx* c, const MGLevel& L, double alpha, const double* dis, int steps,
+               double* v, double* vp, double* w, double* t) {
+    const int64_t n = L.N;
+    std::vector<double> h(n);
+    uint64_t s = 0;
+    for (int64_t i = 0; i < n; ++i) h[i] = (double)(splitmix64_next(s) >> 11) * 0x1.0p-53 - 0.5;
+    TBDG_HIP(hipMemcpyAsync(v, h.data(), sizeof(double) * n, hipMemcpyHostToDevice, c->stream));
+    const double nv = std::sqrt(host_dot(c, n, v, v));
+    vec_scale_copy(c->stream, n, 1.0 / nv, v, v);
+    TBDG_HIP(hipMemsetAsync(vp, 0, sizeof(double) * n, c->stream));
+    steps = (int)std::min<int64_t>(steps, n);
+    std::vector<double> al, be;
+    double b_prev = 0.0;
+    for (int j = 0; j < steps; ++j) {
+        vec_mul(c->stream, n, dis, v, t);
+        apply_level64(c, L, alpha, t, w);
+        vec_mul(c->stream, n, dis, w, w);
+        const double a = host_dot(c, n, w, v);
+        vec_axpby(c->stream, n, 1.0, w, -a, v, w);
+        vec_axpby(c->stream, n, 1.0, w, -b_prev, vp, w);
+        al.push_back(a);
+        const double b = std::sqrt(host_dot(c, n, w, w));
+        if (j == steps - 1 || b == 0.0) break;
+        be.push_back(b);
+        std::swap(v, vp);                    // vp <- old v
+        vec_scale_copy(c->stream, n, 1.0 / b, w, v);
+        b_prev = b;
+    }
+    return tridiag_max(al, be);
+}
+
+// In-place Cholesky factor (lower) and the inverse of an SPD matrix.
+void spd_inverse(std::vector<double>& A, int n) {
+    std::vector<double> Lf(A);
+    for (int j = 0; j < n; ++j) {
+        double d = Lf[(size_t)j * n + j];
+        for (int k = 0; k < j; ++k) d -= Lf[(size_t)j * n + k] * Lf[(size_t)j * n + k];
+        if (!(d > 0.0)) throw Error(TBDG_EBREAKDOWN, "coarse multigrid matrix is not positive definite");
+        const double ljj = std::sqrt(d);
+        Lf[(size_t)j * n + j] = ljj;
+        for (int i = j + 1; i < n; ++i) {
+            double s = Lf[(size_t)i * n + j];
+            for (int k = 0; k < j; ++k) s -= Lf[(size_t)i * n + k] * Lf[(size_t)j * n + k];
+            Lf[(size_t)i * n + j] = s / ljj;
+        }
+    }
+    // W = L^{-1} (lower triangular), then A^{-1} = W^T W
+    std::vector<double> W((size_t)n * n, 0.0);
+    for (int col = 0; col < n; ++col) {
+        for (int i = col; i < n; ++i) {
+            double s = i == col ? 1.0 : 0.0;
+            for (int k = col; k < i; ++k) s -= Lf[(size_t)i * n + k] * W[(size_t)k * n + col];
+            W[(size_t)i * n + col] = s / Lf[(size_t)i * n + i];
+        }
+    }
+    for (int i = 0; i < n; ++i)
+        for (int j = 0; j <= i; ++j) {
+            double s = 0.0;
+            for (int k = i; k < n; ++k) s += W[(size_t)k * n + i] * W[(size_t)k * n + j];
+            A[(size_t)i * n + j] = s;
+            A[(size_t)j * n + i] = s;
+        }
+}
+
+MGLevel make_level(const tbdg_ctx* c, const int nc[3], int np) {
+    MGLevel L;
+    L.np = np;
+    L.Nc = 1;
+    L.geom.vol = 1.0;
+    for (int a = 0; a < 3; ++a) {
+        L.geom.nc[a] = nc[a];
+        L.geom.lo[a] = c->geom.lo[a];
+        L.geom.h[a] = a < c->dim ? c->geom.h[a] * c->geom.nc[a] / nc[a] : 1.0;
+        if (a < c->dim) {
+            L.Nc *= nc[a];
+            L.geom.vol *= L.geom.h[a];
+        }
+    }
+    int64_t nb = 1;
+    for (int a = 0; a < c->dim; ++a) nb *= np;
+    L.N = L.Nc * nb;
+    for (int a = 0; a < 3; ++a) {
+        L.lgeom.periodic[a] = c->periodic_flags[a];
+        L.lgeom.inv_nc[a] = 1.0 / nc[a];
+        L.lgeom.sadv[a] = L.geom.vol / L.geom.h[a];
+        L.lgeom.sdiff[a] = L.geom.vol / (L.geom.h[a] * L.geom.h[a]);
+    }
+    level_tables(np, c->pen_p, L.tab, L.line, L.cr);
+    LevelTabF& f = L.tf;
+    std::memset(&f, 0, sizeof(f));
+    for (int i = 0; i < np * np; ++i) f.A[i] = (float)L.line.A[i];
+    for (int i = 0; i < np; ++i) {
+        f.L0[i] = (float)L.tab.L0p[i];
+        f.L1[i] = (float)L.tab.L1p[i];
+        f.dL0[i] = (float)L.tab.dL0p[i];
+        f.dL1[i] = (float)L.tab.dL1p[i];
+        f.W[i] = (float)L.tab.Wp[i];
+    }
+    f.Cr = (float)L.cr;
+    for (int s = 1; s <= 2; ++s) f.cm[s] = (float)(c->alpha(s) * L.geom.vol);
+    for (int a = 0; a < 3; ++a) f.sdiff[a] = (float)L.lgeom.sdiff[a];
+    return L;
+}
+
+void set_transfer(MGLevel& F, int kind) {
+    F.transfer = kind;
+    std::memset(&F.tt, 0, sizeof(F.tt));
+    const double* zc = nullptr;
+    double z2[2], w2[2];
+    gauss_legendre(2, z2, w2);
+    zc = z2;
+    if (kind == 1) {
+        for (int i = 0; i < F.np; ++i)
+            for (int j = 0; j < 2; ++j) F.tt.T[0][i][j] = (float)lagrange_value(zc, 2, j, F.tab.xp[i]);
+    } else {
+        for (int b = 0; b < 2; ++b)
+            for (int i = 0; i < 2; ++i)
+                for (int j = 0; j < 2; ++j)
+                    F.tt.T[b][i][j] = (float)lagrange_value(zc, 2, j, 0.5 * (b + zc[i]));
+    }
+}
+
+template <typename S>
+struct LevelVecs {
+    S *b, *x, *r, *d0, *d1;
+};
+
+template <typename S>
+LevelVecs<S> vecs0(MGLevel& L);
+template <>
+LevelVecs<float> vecs0<float>(MGLevel& L) {
+    return {L.b, L.x, L.r, L.d[0], L.d[1]};
+}
+template <>
+LevelVecs<uint16_t> vecs0<uint16_t>(MGLevel& L) {
+    return {L.hb, L.hx, L.hr, L.hd[0], L.hd[1]};
+}
+
+// Smoothing passes of one level; the first direction d_0 is already in d0
+// (pre-smoothing) or is formed from the residual (post-smoothing).  Returns
+// the buffer holding the final direction, whose addition to x is left to the
+// consumer (prolongation or the finest level's z).
+template <typename S>
+void presmooth(tbdg_ctx* c, MGLevel& L, int s, LevelVecs<S> v) {
+    const int m = c->mg->degree;
+    S* d[2] = {v.d0, v.d1};
+    // k = 1: x = d0, r = b - H d0, d1
+    launch_level_step<S>(c->stream, c->dim, L, s, MG_PRE1, (float)L.c1[s][1], (float)L.c2[s][1],
+                         d[0], v.x, v.r, v.b, d[1], nullptr, nullptr, nullptr, nullptr);
+    for (int k = 2; k < m; ++k)
+        launch_level_step<S>(c->stream, c->dim, L, s, MG_STEP, (float)L.c1[s][k], (float)L.c2[s][k],
+                             d[(k - 1) & 1], v.x, v.r, v.b, d[k & 1], nullptr, nullptr, nullptr,
+                             nullptr);
+    launch_level_step<S>(c->stream, c->dim, L, s, MG_LAST, 0.0f, 0.0f, d[(m - 1) & 1], v.x, v.r,
+                         v.b, nullptr, nullptr, nullptr, nullptr, nullptr);
+}
+
+template <typename S>
+S* postsmooth(tbdg_ctx* c, MGLevel& L, int s, LevelVecs<S> v, double* z, const double* r64,
+              const double* q64, double* partial) {
+    const int m = c->mg->degree;
+    S* d[2] = {v.d0, v.d1};
+    launch_level_step<S>(c->stream, c->dim, L, s, MG_RES, 0.0f, (float)(1.0 / L.theta[s]), nullptr,
+                         v.x, v.r, v.b, d[0], nullptr, nullptr, nullptr, nullptr);
+    for (int k = 1; k < m; ++k) {
+        const bool fin = z != nullptr && k == m - 1;
+        launch_level_step<S>(c->stream, c->dim, L, s, fin ? MG_ZFIN : MG_STEP, (float)L.c1[s][k],
+                             (float)L.c2[s][k], d[(k - 1) & 1], v.x, v.r, v.b, d[k & 1], z, r64,
+                             q64, partial);
+    }
+    return d[(m - 1) & 1];
+}
+
+// One V-cycle below the finest level's right-hand side and first direction
+// (already in place).  The finest level's final step writes z = x + d and the
+// partial sums z.r64, z.q64 to mg->zpart.
+template <typename S>
+void vcycle(tbdg_ctx* c, int s, const double* r64, const double* q64) {
+    MGData& M = *c->mg;
+    const int nl = (int)M.lv.size();
+    // descent
+    for (int l = 0; l < nl - 1; ++l) {
+        MGLevel& L = M.lv[l];
+        MGLevel& C = M.lv[l + 1];
+        const bool coarsest = l + 1 == nl - 1;
+        if (l == 0) {
+            LevelVecs<S> v = vecs0<S>(L);
+            presmooth<S>(c, L, s, v);
+            launch_restrict<S>(c->stream, c->dim, L, C, s, coarsest ? 0.0f : (float)(1.0 / C.theta[s]),
+                               v.r, !coarsest);
+        } else {
+            LevelVecs<float> v = vecs0<float>(L);
+            presmooth<float>(c, L, s, v);
+            launch_restrict<float>(c->stream, c->dim, L, C, s,
+                                   coarsest ? 0.0f : (float)(1.0 / C.theta[s]), v.r, !coarsest);
+        }
+    }
+    MGLevel& LC = M.lv[nl - 1];
+    launch_coarse(c->stream, M.ainv[s], LC.b, LC.x, (int)LC.N);
+    // ascent
+    const float* pending = nullptr;   // final direction of the level below, not yet in its x
+    for (int l = nl - 2; l >= 0; --l) {
+        MGLevel& L = M.lv[l];
+        MGLevel& C = M.lv[l + 1];
+        if (l == 0) {
+            LevelVecs<S> v = vecs0<S>(L);
+            launch_prolong<S>(c->stream, c->dim, L, C, v.x, pending);
+            postsmooth<S>(c, L, s, v, M.z, r64, q64, M.zpart);
+        } else {
+            LevelVecs<float> v = vecs0<float>(L);
+            launch_prolong<float>(c->stream, c->dim, L, C, v.x, pending);
+            pending = postsmooth<float>(c, L, s, v, nullptr, nullptr, nullptr, nullptr);
+        }
+    }
+}
+
+void run_vcycle(tbdg_ctx* c, int s, int precision, const double* r64, const double* q64) {
+    if (precision == 2) vcycle<uint16_t>(c, s, r64, q64);
+    else vcycle<float>(c, s, r64, q64);
+}
+
+int prep(tbdg_ctx* c, int s, int precision, int update, const double* pa, int Ga, double* sc,
+         int slot, double* x, double* r, const double* p, const double* q) {
+    MGLevel& L = c->mg->lv[0];
+    const float c2 = (float)(1.0 / L.theta[s]);
+    if (precision == 2)
+        return launch_mg_prep<uint16_t>(c->stream, c->Np, update, pa, Ga, sc, slot, x, r, p, q,
+                                        L.hb, L.hd[0], L.invd[s], c2, c->mg->rpart);
+    return launch_mg_prep<float>(c->stream, c->Np, update, pa, Ga, sc, slot, x, r, p, q, L.b,
+                                 L.d[0], L.invd[s], c2, c->mg->rpart);
+}
+
+}  // namespace
+
+void mg_free(tbdg_ctx* c) {
+    if (!c->mg) return;
+    for (void* p : c->mg->allocs) (void)hipFree(p);
+    delete c->mg;
+    c->mg = nullptr;
+}
+
+void mg_setup(tbdg_ctx* c, const tbdg_mg_desc* desc) {
+    mg_free(c);
+    for (int a = 0; a < c->dim; ++a)
+        if (!c->periodic_flags[a]) throw Error(TBDG_EUNSUPPORTED, "multigrid is built for periodic boxes");
+    c->mg = new MGData();
+    MGData& M = *c->mg;
+    M.coarse_cells = c->dim == 3 ? 64 : 16;
+    if (desc) {
+        if (desc->degree) M.degree = desc->degree;
+        if (desc->lanczos_steps) M.lanczos_steps = desc->lanczos_steps;
+        if (desc->range > 0.0) M.range = desc->range;
+        if (desc->safety > 0.0) M.safety = desc->safety;
+        if (desc->coarse_cells) M.coarse_cells = desc->coarse_cells;
+        if (desc->max_coarse_dofs) M.max_coarse = desc->max_coarse_dofs;
+    }
+    if (M.degree < 2 || M.degree >= MG_MAXDEG) throw Error(TBDG_EINVAL, "multigrid degree must be in [2, 15]");
+    if (M.lanczos_steps < 1 || M.range <= 1.0 || M.safety < 1.0 || M.coarse_cells < 1)
+        throw Error(TBDG_EINVAL, "invalid multigrid parameters");
+    // ---- hierarchy ----
+    int nc[3] = {c->geom.nc[0], c->geom.nc[1], c->geom.nc[2]};
+    M.lv.push_back(make_level(c, nc, c->np));
+    if (c->np > 2) {
+        set_transfer(M.lv.back(), 1);
+        M.lv.push_back(make_level(c, nc, 2));
+    }
+    while ((int)M.lv.size() < MG_MAXLEVELS) {
+        const MGLevel& L = M.lv.back();
+        bool even = true;
+        for (int a = 0; a < c->dim; ++a) even = even && nc[a] % 2 == 0;
+        if (L.Nc <= M.coarse_cells || !even) break;
+        set_transfer(M.lv.back(), 2);
+        for (int a = 0; a < c->dim; ++a) nc[a] /= 2;
+        M.lv.push_back(make_level(c, nc, 2));
+    }
+    const int nl = (int)M.lv.size();
+    if (nl < 2) throw Error(TBDG_EUNSUPPORTED, "multigrid needs at least two levels on this mesh");
+    if (M.lv.back().N > M.max_coarse)
+        throw Error(TBDG_EUNSUPPORTED, "coarsest multigrid level too large for the dense solve");
+    // ---- vectors ----
+    for (int l = 0; l < nl; ++l) {
+        MGLevel& L = M.lv[l];
+        L.b = mg_alloc<float>(&M, L.N);
+        L.x = mg_alloc<float>(&M, L.N);
+        if (l < nl - 1) {
+            L.r = mg_alloc<float>(&M, L.N);
+            L.d[0] = mg_alloc<float>(&M, L.N);
+            L.d[1] = mg_alloc<float>(&M, L.N);
+            L.invd[1] = mg_alloc<float>(&M, L.N);
+            L.invd[2] = mg_alloc<float>(&M, L.N);
+        }
+        if (l == 0) {
+            L.hb = mg_alloc<uint16_t>(&M, L.N);
+            L.hx = mg_alloc<uint16_t>(&M, L.N);
+            L.hr = mg_alloc<uint16_t>(&M, L.N);
+            L.hd[0] = mg_alloc<uint16_t>(&M, L.N);
+            L.hd[1] = mg_alloc<uint16_t>(&M, L.N);
+        }
+    }
+    M.z = mg_alloc<double>(&M, c->Np);
+    M.zpart = mg_alloc<double>(&M, 2 * (int64_t)level_blocks(c->dim, M.lv[0]));
+    M.rpart = mg_alloc<double>(&M, 1024);
+    // ---- diagonals, eigenvalue estimates, Chebyshev coefficients ----
+    int64_t nmax = 0;
+    for (const MGLevel& L : M.lv) nmax = std::max(nmax, L.N);
+    double* dg = mg_alloc<double>(&M, nmax);
+    double* dis = mg_alloc<double>(&M, nmax);
+    double* w1 = mg_alloc<double>(&M, nmax);
+    double* w2 = mg_alloc<double>(&M, nmax);
+    double* w3 = mg_alloc<double>(&M, nmax);
+    double* w4 = mg_alloc<double>(&M, nmax);
+    for (int s = 1; s <= 2; ++s) {
+        const double alpha = c->alpha(s);
+        for (int l = 0; l < nl - 1; ++l) {
+            MGLevel& L = M.lv[l];
+            launch_diag_pressure_level(c->stream, c->dim, L.np, L.geom, L.lgeom, L.line, L.tab,
+                                       alpha * L.geom.vol, dg, L.Nc);
+            vec_inv_sqrt(c->stream, L.N, dg, dis, L.invd[s]);
+            const double lam = lanczos(c, L, alpha, dis, M.lanczos_steps, w1, w2, w3, w4);
+            if (!(lam > 0.0) || !std::isfinite(lam))
+                throw Error(TBDG_EBREAKDOWN, "multigrid eigenvalue estimate failed");
+            L.lam[s] = lam;
+            const double lo = lam / M.range, hi = M.safety * lam;
+            const double theta = 0.5 * (hi + lo), delta = 0.5 * (hi - lo), sigma = theta / delta;
+            L.theta[s] = theta;
+            double rho = 1.0 / sigma;
+            for (int k = 1; k < M.degree; ++k) {
+                const double rn = 1.0 / (2.0 * sigma - rho);
+                L.c1[s][k] = rn * rho;
+                L.c2[s][k] = 2.0 * rn / delta;
+                rho = rn;
+            }
+        }
+        // coarse operator by columns, then its inverse from the Cholesky factor
+        MGLevel& C = M.lv[nl - 1];
+        const int n = (int)C.N;
+        double* cols = mg_alloc<double>(&M, (int64_t)n * n);
+        for (int j = 0; j < n; ++j) {
+            vec_unit(c->stream, n, j, w1);
+            apply_level64(c, C, alpha, w1, cols + (size_t)j * n);
+        }
+        std::vector<double> A((size_t)n * n);
+        TBDG_HIP(hipMemcpyAsync(A.data(), cols, sizeof(double) * n * n, hipMemcpyDeviceToHost, c->stream));
+        TBDG_HIP(hipStreamSynchronize(c->stream));
+        for (int i = 0; i < n; ++i)
+            for (int j = 0; j < i; ++j) {
+                const double v = 0.5 * (A[(size_t)i * n + j] + A[(size_t)j * n + i]);
+                A[(size_t)i * n + j] = v;
+                A[(size_t)j * n + i] = v;
+            }
+        spd_inverse(A, n);
+        M.ainv[s] = cols;    // reuse the column buffer for the inverse
+        TBDG_HIP(hipMemcpyAsync(M.ainv[s], A.data(), sizeof(double) * n * n, hipMemcpyHostToDevice,
+                                c->stream));
+        TBDG_HIP(hipStreamSynchronize(c->stream));
+    }
+}
+
+void mg_apply(tbdg_ctx* c, int s, int precision, const double* r, double* z) {
+    if (!c->mg) mg_setup(c, nullptr);
+    double* sc = c->red_out + 64;
+    prep(c, s, precision, 0, nullptr, 0, sc, 0, nullptr, const_cast<double*>(r), nullptr, nullptr);
+    run_vcycle(c, s, precision, r, nullptr);
+    TBDG_HIP(hipMemcpyAsync(z, c->mg->z, sizeof(double) * c->Np, hipMemcpyDeviceToDevice, c->stream));
+}
+
+// Flexible CG (Polak-Ribiere beta) preconditioned by one V-cycle; FP64
+// residual, dot products, recurrences.  One host synchronisation per
+// iteration (the residual norm).
+tbdg_status solve_pressure_mg(tbdg_ctx* c, int s, const double* b, double* x,
+                              const tbdg_solver_opts& o, tbdg_solve_info* info) {
+    if (!c->mg) mg_setup(c, nullptr);
+    MGData& M = *c->mg;
+    const int prec = o.precond == TBDG_PRECOND_MG_BF16 ? 2 : 1;
+    const int64_t n = c->Np;
+    const double alpha = c->alpha(s);
+    double* r = c->cr;
+    double* q = c->cq;
+    double* pa = c->cp;
+    double* pb = c->cp2;
+    double* sc = c->red_out + 64;
+    tbdg_solve_info inf{0, 0.0, 0.0, 0};
+    dot2(c, n, b, b, c->red_out + 63);
+    TBDG_HIP(hipMemcpyAsync(c->host_out, c->red_out + 63, sizeof(double), hipMemcpyDeviceToHost, c->stream));
+    TBDG_HIP(hipStreamSynchronize(c->stream));
+    const double bnorm = std::sqrt(c->host_out[0]);
+    if (bnorm == 0.0) {
+        TBDG_HIP(hipMemsetAsync(x, 0, sizeof(double) * n, c->stream));
+        if (info) *info = inf;
+        return TBDG_OK;
+    }
+    if (!std::isfinite(bnorm)) {
+        if (info) *info = inf;
+        return TBDG_ENAN;
+    }
+    TBDG_HIP(hipMemsetAsync(sc, 0, sizeof(double) * 16, c->stream));
+    auto read_rr = [&](int G) {
+        TBDG_HIP(hipMemcpyAsync(c->host_out, M.rpart, sizeof(double) * G, hipMemcpyDeviceToHost, c->stream));
+        TBDG_HIP(hipMemcpyAsync(c->host_out + G, sc + 6, sizeof(double), hipMemcpyDeviceToHost, c->stream));
+        TBDG_HIP(hipStreamSynchronize(c->stream));
+        double rr = 0.0;
+        for (int i = 0; i < G; ++i) rr += c->host_out[i];
+        return rr;
+    };
+    tbdg_status st = TBDG_ENOTCONV;
+    int total = 0;
+    bool first_cycle = true;
+    const int G0 = level_blocks(c->dim, M.lv[0]);
+    while (true) {
+        // (re)start from the true residual
+        launch_apply_pressure(c, alpha, x, q);
+        vec_axpby(c->stream, n, 1.0, b, -1.0, q, r);
+        const int G = prep(c, s, prec, 0, nullptr, 0, sc, 0, x, r, nullptr, nullptr);
+        double rr = read_rr(G);
+        if (first_cycle) inf.res0 = std::sqrt(rr) / bnorm;
+        first_cycle = false;
+        if (!std::isfinite(rr)) {
+            st = TBDG_ENAN;
+            break;
+        }
+        if (std::sqrt(rr) <= o.tol * bnorm) {
+            st = TBDG_OK;
+            break;
+        }
+        if (total >= o.maxiter) break;
+        run_vcycle(c, s, prec, r, nullptr);
+        launch_mg_beta(c->stream, M.zpart, G0, sc, 1, 8, 9);
+        bool conv = false, broke = false, nan = false;
+        int k = 0;
+        while (total < o.maxiter) {
+            ++k;
+            ++total;
+            const int slot = 8 + ((k - 1) & 1);          // z.r of the current z
+            const int Ga = launch_fcg_apply(c, alpha, M.z, pa, pb, q, sc);
+            prep(c, s, prec, 1, c->red_op, Ga, sc, slot, x, r, pb, q);
+            std::swap(pa, pb);
+            rr = read_rr(G);
+            if (c->host_out[G] != 0.0) {
+                broke = true;
+                break;
+            }
+            if (!std::isfinite(rr)) {
+                nan = true;
+                break;
+            }
+            if (std::sqrt(rr) <= o.tol * bnorm) {
+                conv = true;
+                break;
+            }
+            if (total >= o.maxiter) break;
+            run_vcycle(c, s, prec, r, q);
+            launch_mg_beta(c->stream, M.zpart, G0, sc, 0, 8 + (k & 1), slot);
+        }
+        if (broke) {
+            st = TBDG_EBREAKDOWN;
+            break;
+        }
+        if (nan) {
+            st = TBDG_ENAN;
+            break;
+        }
+        if (!conv) {
+            st = TBDG_ENOTCONV;
+            break;
+        }
+        // converged on the recurrence: confirm on the true residual
+    }
+    launch_apply_pressure(c, alpha, x, q);
+    vec_axpby(c->stream, n, 1.0, b, -1.0, q, r);
+    dot2(c, n, r, r, c->red_out + 63);
+    TBDG_HIP(hipMemcpyAsync(c->host_out, c->red_out + 63, sizeof(double), hipMemcpyDeviceToHost, c->stream));
+    TBDG_HIP(hipStreamSynchronize(c->stream));
+    inf.iters = total;
+    inf.res_final = std::sqrt(c->host_out[0]) / bnorm;
+    if (info) *info = inf;
+    return st;
+}
+
+}  // namespace trbdg

@@ -96,11 +96,9 @@ void build_tables(tbdg_ctx* c) {
         }
 }
 
-namespace {
-
 // 1D SIP element matrices, reference cell [0,1], penalty Cr (times 1/h on
 // the physical cell, so every entry scales as 1/h).
-void line_matrices(int n, const double* W, const double* D, const double* L0, const double* L1,
+void build_line_matrix(int n, const double* W, const double* D, const double* L0, const double* L1,
                    const double* dL0, const double* dL1, double Cr, Line1D& m) {
     std::memset(&m, 0, sizeof(m));
     for (int i = 0; i < n; ++i)
@@ -118,15 +116,33 @@ void line_matrices(int n, const double* W, const double* D, const double* L0, co
         }
 }
 
-}  // namespace
+double lagrange_value(const double* z, int n, int j, double x) { return lagrange(z, n, j, x); }
+
+// Pressure-type tables of one multigrid level with np Gauss nodes per
+// direction: rule, derivative matrix, end values and derivatives, the 1D SIP
+// element matrices with the reference penalty np^2 pen_p.
+void level_tables(int np, double pen_p, Tables& t, Line1D& line, double& cr) {
+    std::memset(&t, 0, sizeof(t));
+    gauss_legendre(np, t.xp, t.Wp);
+    for (int i = 0; i < np; ++i)
+        for (int j = 0; j < np; ++j) t.Dp[i * np + j] = lagrange_d(t.xp, np, j, t.xp[i]);
+    for (int j = 0; j < np; ++j) {
+        t.L0p[j] = lagrange(t.xp, np, j, 0.0);
+        t.L1p[j] = lagrange(t.xp, np, j, 1.0);
+        t.dL0p[j] = lagrange_d(t.xp, np, j, 0.0);
+        t.dL1p[j] = lagrange_d(t.xp, np, j, 1.0);
+    }
+    cr = (double)np * np * pen_p;
+    build_line_matrix(np, t.Wp, t.Dp, t.L0p, t.L1p, t.dL0p, t.dL1p, cr, line);
+}
 
 void build_line_operators(tbdg_ctx* c) {
     const Tables& t = c->tab;
     c->cr_u = (c->k + 1.0) * (c->k + 1.0) * c->pen_u;
     c->cr_p = (double)c->k * c->k * c->pen_p;
-    line_matrices(c->n, t.Wu, t.Du, t.L0u, t.L1u, t.dL0u, t.dL1u,
+    build_line_matrix(c->n, t.Wu, t.Du, t.L0u, t.L1u, t.dL0u, t.dL1u,
                   (c->k + 1.0) * (c->k + 1.0) * c->pen_u, c->line_u);
-    line_matrices(c->np, t.Wp, t.Dp, t.L0p, t.L1p, t.dL0p, t.dL1p,
+    build_line_matrix(c->np, t.Wp, t.Dp, t.L0p, t.L1p, t.dL0p, t.dL1p,
                   (double)c->k * c->k * c->pen_p, c->line_p);
     for (int a = 0; a < 3; ++a) {
         c->lgeom.periodic[a] = c->periodic_flags[a];

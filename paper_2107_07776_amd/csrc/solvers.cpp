@@ -169,6 +169,8 @@ tbdg_status solve_momentum(tbdg_ctx* c, int s, const double* w, const double* b,
 // ---------------------------------------------------------------------------
 tbdg_status solve_pressure(tbdg_ctx* c, int s, const double* b, double* x,
                            const tbdg_solver_opts& o, tbdg_solve_info* info) {
+    if (o.precond == TBDG_PRECOND_MG_FP32 || o.precond == TBDG_PRECOND_MG_BF16)
+        return solve_pressure_mg(c, s, b, x, o, info);
     const int64_t n = c->Np;
     const double alpha = c->alpha(s);
     const double* invd = c->invd_p[s];

@@ -23,8 +23,11 @@ EXPORTED = [
     "tbdg_node_coords", "tbdg_extrapolate", "tbdg_apply_momentum", "tbdg_apply_pressure",
     "tbdg_diag_momentum", "tbdg_diag_pressure", "tbdg_rhs_momentum", "tbdg_grad_p",
     "tbdg_add_grad_p", "tbdg_rhs_pressure", "tbdg_solve_momentum", "tbdg_solve_pressure",
-    "tbdg_step", "tbdg_profile_enable", "tbdg_profile_read",
+    "tbdg_step", "tbdg_profile_enable", "tbdg_profile_read", "tbdg_mg_setup",
+    "tbdg_mg_levels", "tbdg_mg_apply",
 ]
+
+PRECOND = {"jacobi": 0, "mg_fp32": 1, "mg_bf16": 2}
 
 
 class TrbdgError(RuntimeError):
@@ -49,6 +52,12 @@ class DiscDesc(ctypes.Structure):
 class SolverOpts(ctypes.Structure):
     _fields_ = [("tol", ctypes.c_double), ("maxiter", ctypes.c_int), ("restart", ctypes.c_int),
                 ("precond", ctypes.c_int), ("guess", ctypes.c_int)]
+
+
+class MGDesc(ctypes.Structure):
+    _fields_ = [("degree", ctypes.c_int), ("lanczos_steps", ctypes.c_int), ("range", ctypes.c_double),
+                ("safety", ctypes.c_double), ("coarse_cells", ctypes.c_int),
+                ("max_coarse_dofs", ctypes.c_int)]
 
 
 class SolveInfo(ctypes.Structure):
@@ -99,6 +108,9 @@ def load_library(path=LIB_PATH):
         "tbdg_step": ([vp, P(State), P(SolverOpts), P(SolverOpts), P(SolveInfo)], i),
         "tbdg_profile_enable": ([vp, i], i),
         "tbdg_profile_read": ([vp, i, P(d), P(i64)], i),
+        "tbdg_mg_setup": ([vp, P(MGDesc)], i),
+        "tbdg_mg_levels": ([vp, i, P(i), P(i64), P(d)], i),
+        "tbdg_mg_apply": ([vp, i, i, vp, vp], i),
     }
     for name, (args, res) in sig.items():
         fn = getattr(lib, name)
@@ -112,8 +124,8 @@ def _ptr(t):
     return ctypes.c_void_p(t.data_ptr()) if t is not None else ctypes.c_void_p(0)
 
 
-def solver_opts(tol=1e-8, maxiter=1000, restart=30):
-    return SolverOpts(float(tol), int(maxiter), int(restart), 0, 0)
+def solver_opts(tol=1e-8, maxiter=1000, restart=30, precond="jacobi"):
+    return SolverOpts(float(tol), int(maxiter), int(restart), PRECOND[precond], 0)
 
 
 class Context:
@@ -254,8 +266,9 @@ class Context:
             self._check(st)
         return info.as_dict() | {"status": st}
 
-    def solve_pressure(self, stage, rhs, p_inout, tol=1e-8, maxiter=5000, check=True):
-        o = solver_opts(tol, maxiter, 0)
+    def solve_pressure(self, stage, rhs, p_inout, tol=1e-8, maxiter=5000, precond="jacobi",
+                       check=True):
+        o = solver_opts(tol, maxiter, 0, precond)
         info = SolveInfo()
         st = self.lib.tbdg_solve_pressure(self.h, stage, _ptr(self._vec(rhs, self.N_p, "rhs")),
                                           _ptr(self._vec(p_inout, self.N_p, "p")), ctypes.byref(o),
@@ -265,17 +278,42 @@ class Context:
         return info.as_dict() | {"status": st}
 
     def step(self, u, u_hist, p, t=0.0, n=0, mom_tol=1e-8, prs_tol=1e-8, mom_maxiter=1000,
-             prs_maxiter=5000, restart=30, check=True):
-        """One TR-BDF2 step in place on (u, u_hist, p); returns per-solve info."""
+             prs_maxiter=5000, restart=30, precond="jacobi", check=True):
+        """One TR-BDF2 step in place on (u, u_hist, p); returns per-solve info.
+        ``precond`` selects the pressure preconditioner."""
         S = State(_ptr(self._vec(u, self.N_u, "u")), _ptr(self._vec(u_hist, self.N_u, "u_hist")),
                   _ptr(self._vec(p, self.N_p, "p")), float(t), int(n))
         mo = solver_opts(mom_tol, mom_maxiter, restart)
-        po = solver_opts(prs_tol, prs_maxiter, 0)
+        po = solver_opts(prs_tol, prs_maxiter, 0, precond)
         infos = (SolveInfo * 4)()
         st = self.lib.tbdg_step(self.h, ctypes.byref(S), ctypes.byref(mo), ctypes.byref(po), infos)
         if check:
             self._check(st)
         return [infos[i].as_dict() for i in range(4)], st
+
+    def mg_setup(self, degree=0, lanczos_steps=0, range_=0.0, safety=0.0, coarse_cells=0,
+                 max_coarse_dofs=0):
+        """Build the pressure multigrid hierarchy (0 = library default)."""
+        d = MGDesc(int(degree), int(lanczos_steps), float(range_), float(safety), int(coarse_cells),
+                   int(max_coarse_dofs))
+        self._check(self.lib.tbdg_mg_setup(self.h, ctypes.byref(d)))
+
+    def mg_levels(self, cap=16):
+        """List of per-level dicts (nodes per direction, cells, DoFs, eigenvalue
+        estimates of stages 1 and 2)."""
+        n = ctypes.c_int()
+        desc = (ctypes.c_int64 * (5 * cap))()
+        lam = (ctypes.c_double * (2 * cap))()
+        self._check(self.lib.tbdg_mg_levels(self.h, cap, ctypes.byref(n), desc, lam))
+        return [dict(np=desc[5 * l], cells=tuple(desc[5 * l + 1:5 * l + 4]), dofs=desc[5 * l + 4],
+                     lam=(lam[l], lam[cap + l])) for l in range(min(n.value, cap))]
+
+    def mg_apply(self, stage, r, precision="fp32"):
+        """z = B r, one V-cycle of the stage's hierarchy."""
+        z = self.empty_p()
+        self._check(self.lib.tbdg_mg_apply(self.h, stage, 1 if precision == "fp32" else 2,
+                                           _ptr(self._vec(r, self.N_p, "r")), _ptr(z)))
+        return z
 
     def profile(self, enable):
         """Bracket every operator-kernel launch with HIP events (measurement)."""
