@@ -3,9 +3,12 @@
 Default workload (one step = both TR-BDF2 stages with all four implicit
 solves): 3D periodic Taylor-Green vortex on [0, 2 pi]^3, 32^3 hexahedra,
 velocity degree 3 / pressure degree 2 (6 291 456 + 884 736 DoFs), nu = 1/1600,
-dt = 2 pi / 96 (Courant number 1), Jacobi-preconditioned GMRES (momentum) and
-CG (Helmholtz) to a 1e-8 relative residual, FP64.  Synthetic data: the
-closed-form initial vortex.  Inputs are resident in HBM before timing starts.
+dt = 2 pi / 96 (Courant number 1), every solve to a 1e-8 relative FP64
+residual.  The timed solver uses the FP32 h/p-multigrid preconditioner for
+the pressure (flexible FP64 CG); the same steps with the plain FP64 solver
+(Jacobi CG) are timed beside it from the same initial state and the two
+final fields are compared ("equal error").  Synthetic data: the closed-form
+initial vortex.  Inputs are resident in HBM before timing starts.
 
 Prints one JSON line.  `--gpus N` with N > 1 is refused: this build runs on
 one GPU.
@@ -34,7 +37,12 @@ def workload(name):
         return dict(dim=3, n=(32, 32, 32), ext=(2 * math.pi,) * 3, k=3, nu=1.0 / 1600.0,
                     dt=2 * math.pi / 96.0, tol=1e-8,
                     label="3D periodic Taylor-Green vortex, 32^3 hexes, Q3-Q2, nu=1/1600, "
-                          "dt=2pi/96 (C=1), Jacobi-GMRES(30)/Jacobi-CG to 1e-8, FP64")
+                          "dt=2pi/96 (C=1), solves to 1e-8 relative FP64 residual")
+    if name == "tgv64":
+        return dict(dim=3, n=(64, 64, 64), ext=(2 * math.pi,) * 3, k=3, nu=1.0 / 1600.0,
+                    dt=2 * math.pi / 192.0, tol=1e-8,
+                    label="3D periodic Taylor-Green vortex, 64^3 hexes, Q3-Q2, nu=1/1600, "
+                          "dt=2pi/192 (C=1), solves to 1e-8 relative FP64 residual")
     if name == "tg2d":
         return dict(dim=2, n=(8, 8), ext=(1.0, 1.0), k=2, nu=0.01, dt=0.01, tol=1e-10,
                     label="2D periodic Taylor-Green, 8x8 quads, Q2-Q1, nu=0.01, dt=0.01, tol 1e-10")
@@ -97,6 +105,60 @@ def cpu_baseline(W, seconds_budget=20.0):
                       f"scaled by DoF ratio {scale:.3g}; setup {setup:.1f}s excluded"}
 
 
+def run_solver(ctx, W, precond, steps, warmup, profile, mg_degree=0):
+    """Fresh initial state, `warmup` untimed steps, `steps` timed steps with the
+    given pressure preconditioner.  Returns timing, iterations, final fields
+    and (with `profile`) the event-timed operator kernels."""
+    import numpy as np
+    import torch
+
+    dev = torch.device("cuda:0")
+    xu = ctx.node_coords(0).cpu().numpy()
+    xp = ctx.node_coords(1).cpu().numpy()
+    u0, p0, uh0 = initial_fields(W, xu, xp)
+    U = torch.tensor(u0, device=dev)
+    H = torch.tensor(u0 if uh0 is None else uh0, device=dev)
+    P = torch.tensor(p0, device=dev)
+    tol = W["tol"]
+    if precond != "jacobi":
+        t_setup = time.perf_counter()
+        ctx.mg_setup(degree=mg_degree)
+        torch.cuda.synchronize()
+        log(f"[bench] multigrid set-up {time.perf_counter() - t_setup:.2f}s: "
+            f"{[(l['np'], l['cells'], l['dofs']) for l in ctx.mg_levels()]}")
+    t = 0.0
+    n = 0
+    for i in range(warmup):
+        info, _ = ctx.step(U, H, P, t, n, mom_tol=tol, prs_tol=tol, prs_maxiter=20000, precond=precond)
+        t += W["dt"]
+        n += 1
+        log(f"[bench] {precond} warmup step {i + 1}/{warmup}: iterations {[x['iters'] for x in info]}")
+    torch.cuda.synchronize()
+    if profile:
+        ctx.profile(True)
+        ctx.profile_read(0)
+        ctx.profile_read(1)
+    iters = []
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for i in range(steps):
+        info, _ = ctx.step(U, H, P, t, n, mom_tol=tol, prs_tol=tol, prs_maxiter=20000, precond=precond)
+        t += W["dt"]
+        n += 1
+        iters.append([x["iters"] for x in info])
+        log(f"[bench] {precond} step {i + 1}/{steps}: iterations {iters[-1]}")
+    torch.cuda.synchronize()
+    elapsed = time.perf_counter() - t0
+    if not np.isfinite(U.abs().max().item()):
+        raise SystemExit("non-finite velocity")
+    res = dict(sps=steps / elapsed, ms=1e3 * elapsed / steps, elapsed=elapsed,
+               iters=[float(np.mean([it[j] for it in iters])) for j in range(4)], U=U, P=P)
+    if profile:
+        res["prof"] = (ctx.profile_read(0), ctx.profile_read(1))
+        ctx.profile(False)
+    return res
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -105,8 +167,11 @@ def main():
     ap.add_argument("--workload", default="tgv32")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-profile", action="store_true")
-    ap.add_argument("--precond", default="jacobi", choices=["jacobi", "mg_fp32", "mg_bf16"])
+    ap.add_argument("--precond", default="mg_fp32", choices=["jacobi", "mg_fp32", "mg_bf16"],
+                    help="pressure preconditioner of the timed solver")
     ap.add_argument("--mg-degree", type=int, default=0)
+    ap.add_argument("--no-compare", action="store_true",
+                    help="skip the plain FP64 (Jacobi) reference run")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py: this build runs on exactly one GPU; --gpus {args.gpus} is not supported",
@@ -119,62 +184,39 @@ def main():
     from paper_2107_07776_amd import Context
 
     W = workload(args.workload)
-    dev = torch.device("cuda:0")
     log(f"[bench] setting up {W['label']}")
     ctx = Context(W["dim"], W["n"], (0.0,) * W["dim"], W["ext"], k=W["k"], nu=W["nu"], dt=W["dt"])
-    xu = ctx.node_coords(0).cpu().numpy()
-    xp = ctx.node_coords(1).cpu().numpy()
-    u0, p0, uh0 = initial_fields(W, xu, xp)
-    U = torch.tensor(u0, device=dev)
-    H = torch.tensor(u0 if uh0 is None else uh0, device=dev)
-    P = torch.tensor(p0, device=dev)
-    tol = W["tol"]
-    if args.precond != "jacobi":
-        t_setup = time.perf_counter()
-        ctx.mg_setup(degree=args.mg_degree)
-        torch.cuda.synchronize()
-        log(f"[bench] multigrid set-up {time.perf_counter() - t_setup:.2f}s: "
-            f"{[(l['np'], l['cells'], l['dofs']) for l in ctx.mg_levels()]}")
-    t = 0.0
-    n = 0
-    for i in range(args.warmup):
-        info, _ = ctx.step(U, H, P, t, n, mom_tol=tol, prs_tol=tol, prs_maxiter=20000,
-                           precond=args.precond)
-        t += W["dt"]
-        n += 1
-        log(f"[bench] warmup step {i + 1}/{args.warmup}: iterations {[x['iters'] for x in info]}")
-    torch.cuda.synchronize()
-    if not args.no_profile:
-        ctx.profile(True)
-        ctx.profile_read(0)
-        ctx.profile_read(1)
-    iters = []
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    for i in range(args.steps):
-        info, _ = ctx.step(U, H, P, t, n, mom_tol=tol, prs_tol=tol, prs_maxiter=20000,
-                           precond=args.precond)
-        t += W["dt"]
-        n += 1
-        iters.append([x["iters"] for x in info])
-        log(f"[bench] step {i + 1}/{args.steps}: iterations {iters[-1]}")
-    torch.cuda.synchronize()
-    elapsed = time.perf_counter() - t0
-    if not np.isfinite(U.abs().max().item()):
-        raise SystemExit("non-finite velocity")
-    sps = args.steps / elapsed
-
-    out = {"metric": METRIC, "value": sps, "unit": "steps/s", "n_gpus": 1, "steps": args.steps,
-           "warmup": args.warmup, "ms_per_step": 1e3 * elapsed / args.steps,
+    plain = None
+    if not args.no_compare and args.precond != "jacobi":
+        plain = run_solver(ctx, W, "jacobi", args.steps, args.warmup, False)
+    main_run = run_solver(ctx, W, args.precond, args.steps, args.warmup, not args.no_profile,
+                          args.mg_degree)
+    solver = {"jacobi": "Jacobi-preconditioned FP64 CG",
+              "mg_fp32": "FP32 h/p-multigrid V-cycle (Chebyshev smoother) under FP64 flexible CG",
+              "mg_bf16": "h/p-multigrid V-cycle with BF16 storage on the finest level under FP64 "
+                         "flexible CG"}[args.precond]
+    out = {"metric": METRIC, "value": main_run["sps"], "unit": "steps/s", "n_gpus": 1,
+           "steps": args.steps, "warmup": args.warmup, "ms_per_step": main_run["ms"],
            "higher_is_better": True, "scaling": "strong", "vs_baseline": None, "dtype": "f64",
            "data": "synthetic (closed-form Taylor-Green initial field)",
-           "config": {"workload": W["label"], "cells": list(W["n"]), "degree": W["k"],
+           "config": {"workload": W["label"], "pressure_solver": solver,
+                      "momentum_solver": "Jacobi-preconditioned FP64 GMRES(30)",
+                      "tolerance": W["tol"], "cells": list(W["n"]), "degree": W["k"],
                       "velocity_dofs": ctx.N_u, "pressure_dofs": ctx.N_p,
-                      "mean_iterations_per_step": [float(np.mean([it[j] for it in iters])) for j in range(4)]}}
-    if not args.no_profile:
-        ms_p, n_p = ctx.profile_read(0)
-        ms_u, n_u = ctx.profile_read(1)
-        ctx.profile(False)
+                      "mean_iterations_per_step": main_run["iters"]}}
+    if args.precond != "jacobi":
+        out["preconditioner_dtype"] = "f32" if args.precond == "mg_fp32" else "bf16 storage, f32 arithmetic"
+    if plain is not None:
+        du = (main_run["U"] - plain["U"]).norm().item() / plain["U"].norm().item()
+        dp = (main_run["P"] - plain["P"]).norm().item() / plain["P"].norm().item()
+        out["plain_fp64"] = {"steps_per_s": plain["sps"], "ms_per_step": plain["ms"],
+                             "mean_iterations_per_step": plain["iters"],
+                             "pressure_solver": "Jacobi-preconditioned FP64 CG"}
+        out["speedup_vs_plain_fp64"] = main_run["sps"] / plain["sps"]
+        out["equal_error"] = {"u_rel_l2_diff_vs_plain": du, "p_rel_l2_diff_vs_plain": dp,
+                              "after_steps": args.steps + args.warmup}
+    if "prof" in main_run:
+        (ms_p, n_p), (ms_u, n_u) = main_run["prof"]
         bytes_p = 16.0 * ctx.N_p          # read p, write y
         bytes_u = 24.0 * ctx.N_u          # read u and w, write y
         kern = {
@@ -191,7 +233,8 @@ def main():
         out["roofline"] = {"bound": "hbm", "kernel": dom, "achieved": kd["gbs"], "peak": HBM_PEAK_GBS,
                            "unit": "GB/s", "frac": kd["gbs"] / HBM_PEAK_GBS, "traffic": None,
                            "algorithmic_bytes_per_launch": kd["bytes"], "avg_launch_us": kd["avg_us"],
-                           "launches": kd["n"], "share_of_step_time": kd["ms"] * 1e-3 / elapsed}
+                           "launches": kd["n"],
+                           "share_of_step_time": kd["ms"] * 1e-3 / main_run["elapsed"]}
         out["operator_gdofs"] = {k: round(v["gdofs"], 3) for k, v in kern.items()}
         out["operator_avg_us"] = {k: round(v["avg_us"], 3) for k, v in kern.items()}
     if not args.no_cpu_baseline:

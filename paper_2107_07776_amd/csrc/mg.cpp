@@ -477,8 +477,8 @@ tbdg_status solve_pressure_mg(tbdg_ctx* c, int s, const double* b, double* x,
     }
     TBDG_HIP(hipMemsetAsync(sc, 0, sizeof(double) * 16, c->stream));
     auto read_rr = [&](int G) {
-        TBDG_HIP(hipMemcpyAsync(c->host_out, M.rpart, sizeof(double) * G, hipMemcpyDeviceToHost, c->stream));
-        TBDG_HIP(hipMemcpyAsync(c->host_out + G, sc + 6, sizeof(double), hipMemcpyDeviceToHost, c->stream));
+        TBDG_HIP(hipMemcpyAsync(c->host_out, M.rpart, sizeof(double) * (G + 1), hipMemcpyDeviceToHost,
+                                c->stream));
         TBDG_HIP(hipStreamSynchronize(c->stream));
         double rr = 0.0;
         for (int i = 0; i < G; ++i) rr += c->host_out[i];

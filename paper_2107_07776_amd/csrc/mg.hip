@@ -308,7 +308,7 @@ __global__ __launch_bounds__(256) void k_coarse(const double* __restrict__ Ainv,
 // partials of p.q) (block 0 records it in sc[4], a non-positive p.q raises
 // sc[6]); x += alpha p; r -= alpha q.  Always: b0 = r rounded to the level-0
 // storage, d0 = c2 D^{-1} b0 (first smoother direction of the finest level),
-// and per-block partial sums of r.r.
+// per-block partial sums of r.r, and after them the breakdown flag sc[6].
 template <typename S>
 __global__ __launch_bounds__(256) void k_mg_prep(int64_t n, int update, const double* pa, int Ga,
                                                   double* sc, int slot, double* x, double* r,
@@ -347,7 +347,11 @@ __global__ __launch_bounds__(256) void k_mg_prep(int64_t n, int update, const do
         T::put(d0, i, c2 * invd[i] * bs);
     }
     rr = red::block_sum(rr);
-    if (threadIdx.x == 0) partial[blockIdx.x] = rr;
+    if (threadIdx.x == 0) {
+        partial[blockIdx.x] = rr;
+        // the breakdown flag travels with the partials (one host copy)
+        if (blockIdx.x == 0) partial[gridDim.x] = sc[6];
+    }
 }
 
 // beta of flexible CG from the z.r and z.q partials of the last smoother step:

@@ -89,3 +89,22 @@ def test_full_size_solves(full):
     ru = bu - ctx.apply_momentum(2, w, xu)
     assert info["res_final"] <= 1e-8
     assert h(ru.norm() / bu.norm()) <= 1.01e-8
+
+
+@pytest.mark.parametrize("precond", ["mg_fp32", "mg_bf16"])
+def test_full_size_multigrid_solves(full, precond):
+    """The benchmark's multigrid solve (5 levels down to 4^3 Q1) meets 1e-8 on
+    the recomputed FP64 residual, with the V-cycle built for both stages."""
+    ctx, disc, _ = full
+    ctx.mg_setup()
+    levels = ctx.mg_levels()
+    assert [l["dofs"] for l in levels] == [884736, 262144, 32768, 4096, 512]
+    for stage in (1, 2):
+        b = t(synthetic.random_vector(disc.N_p, 40 + stage))
+        x = torch.zeros_like(b)
+        info = ctx.solve_pressure(stage, b, x, tol=1e-8, maxiter=100, precond=precond)
+        r = b - ctx.apply_pressure(stage, x)
+        print(f"{precond} stage {stage}: {info['iters']} iterations")
+        assert info["res_final"] <= 1e-8
+        assert h(r.norm() / b.norm()) <= 1.01e-8
+        assert info["iters"] <= 30
