@@ -234,6 +234,44 @@ TBDG_API tbdg_status tbdg_mg_levels(tbdg_ctx* ctx, int cap, int* n_levels, int64
 TBDG_API tbdg_status tbdg_mg_apply(tbdg_ctx* ctx, int stage, int precision, const double* r,
                                    double* z);
 
+/* Learned initial guess of the pressure solves: a small 3D convolutional
+ * network on the cell grid (not part of the paper).  Layers 3 -> 32 -> 32 ->
+ * 32 -> 1, 3x3x3 kernels, circular padding, ReLU between layers; bf16
+ * weights and activations with FP32 accumulation (matrix cores), FP32
+ * master parameters and Adam.  Parameters are one flat FP32 vector
+ * [W0, b0, W1, b1, W2, b2, W3, b3], each W laid out [out][in][dz][dy][dx];
+ * the convolution is the cross-correlation
+ *   y[o](z,y,x) = b[o] + sum_{i,dz,dy,dx} W[o][i][dz+1][dy+1][dx+1]
+ *                        * x[i]((z+dz) mod nz, (y+dy) mod ny, (x+dx) mod nx).
+ * All arrays are device pointers; work is enqueued on the network's stream. */
+typedef struct tbdg_net tbdg_net;
+
+/* channels must be 32.  Weights He-uniform U(-a, a), a = sqrt(6 / (27 in)),
+ * drawn from SplitMix64 outputs from state `seed` (top 53 bits scaled to
+ * [0, 1)); biases zero; Adam moments zero.                                  */
+TBDG_API tbdg_status tbdg_net_create(int channels, uint64_t seed, void* hip_stream, tbdg_net** out);
+TBDG_API void tbdg_net_destroy(tbdg_net* net);
+TBDG_API const char* tbdg_net_last_error(const tbdg_net* net);
+TBDG_API tbdg_status tbdg_net_num_params(const tbdg_net* net, int64_t* n);
+/* Copy the FP32 master parameters in (resets Adam) / out; gradients out.      */
+TBDG_API tbdg_status tbdg_net_set_params(tbdg_net* net, const float* theta);
+TBDG_API tbdg_status tbdg_net_get_params(tbdg_net* net, float* theta);
+TBDG_API tbdg_status tbdg_net_get_grads(tbdg_net* net, float* grads);
+TBDG_API tbdg_status tbdg_net_zero_grad(tbdg_net* net);
+/* y = net(x): x FP32 [B][3][nz][ny][nx] (rounded to bf16), y FP32
+ * [B][nz][ny][nx].  nx <= 93.  Keeps the activations for tbdg_net_backward.  */
+TBDG_API tbdg_status tbdg_net_forward(tbdg_net* net, const float* x, float* y, int B, int nx, int ny,
+                                      int nz);
+/* Adds d(sum dy * y)/d(theta) of the last forward to the gradients; dy has
+ * the shape of y (rounded to bf16 on entry).                                 */
+TBDG_API tbdg_status tbdg_net_backward(tbdg_net* net, const float* dy);
+/* dy = 2 (yhat - target) / n; *loss (host, may be NULL) = mean squared error. */
+TBDG_API tbdg_status tbdg_net_mse(tbdg_net* net, const float* yhat, const float* target, int64_t n,
+                                  float* dy, double* loss);
+/* One Adam step (Kingma and Ba, with bias correction) on the master
+ * parameters from the accumulated gradients.                                */
+TBDG_API tbdg_status tbdg_net_adam_step(tbdg_net* net, float lr, float beta1, float beta2, float eps);
+
 /* TR-BDF2 state: u = u^n, u_hist = u^{n-1+gamma} (history level of the
  * stage-1 extrapolation), p = p^n; t and n are host values.                 */
 typedef struct {

@@ -75,14 +75,18 @@ def conv3d_grad(X, W, dY):
     return dX, dW, db
 
 
-def forward(params, X):
-    """Returns the output [B][1][nz][ny][nx] and the inputs of every layer."""
+def forward(params, X, act_round=None):
+    """Returns the output [B][1][nz][ny][nx] and the inputs of every layer.
+    ``act_round`` (e.g. bf16_round) is applied to every hidden activation,
+    modelling storage of the activations in a narrower format."""
     acts = [X]
     A = X
     for li, (W, b) in enumerate(params):
         Z = conv3d(A, W, b)
         A = np.maximum(Z, 0.0) if li < len(params) - 1 else Z
         if li < len(params) - 1:
+            if act_round is not None:
+                A = act_round(A)
             acts.append(A)
     return A, acts
 

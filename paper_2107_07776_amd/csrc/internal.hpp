@@ -131,6 +131,11 @@ struct MGData {
     std::vector<void*> allocs;
 };
 
+// Voxel grid of the guess network: nx * ny * nz voxels per sample, B samples.
+struct NetGeo {
+    int nx, ny, nz, nvox, B;
+};
+
 }  // namespace trbdg
 
 struct tbdg_ctx {
@@ -316,6 +321,23 @@ double lagrange_value(const double* z, int n, int j, double x);
 void build_line_matrix(int n, const double* W, const double* D, const double* L0, const double* L1,
                        const double* dL0, const double* dL1, double Cr, Line1D& m);
 void level_tables(int np, double pen_p, Tables& t, Line1D& line, double& cr);
+
+// ---- guess-network kernels (net.hip) -----------------------------------------------
+void net_conv(hipStream_t st, const NetGeo& g, int cin, int cout, int mode, const uint16_t* X,
+              const uint16_t* Wp, const float* bias, uint16_t* Yb, float* Yf, const uint16_t* mask);
+int net_wgrad(hipStream_t st, const NetGeo& g, int cin, int cout, int dys, const uint16_t* X,
+              const uint16_t* dY, float* partial, int rows_per_block);
+void net_wgrad_reduce(hipStream_t st, const float* partial, int G, int cout, int cin, int cin_real,
+                      float* grad, int64_t w_off, int64_t b_off);
+void net_pack_fwd(hipStream_t st, const float* theta, int64_t w_off, int cout_real, int cin_real,
+                  int cin, int cout, int S, uint16_t* Wp);
+void net_pack_bwd(hipStream_t st, const float* theta, int64_t w_off, int cout_real, int cin_real,
+                  int cin2, int S, uint16_t* Wt);
+void net_copy_bias(hipStream_t st, const float* theta, int64_t b_off, int n, float* b);
+void net_to_channel_last(hipStream_t st, const float* x, int B, int C, int nvox, int CP, uint16_t* out);
+int net_mse(hipStream_t st, const float* yhat, const float* y, int64_t n, float* dy, double* partial);
+void net_adam(hipStream_t st, int64_t n, float* theta, const float* g, float* m, float* v, float lr,
+              float b1, float b2, float eps, float c1, float c2);
 
 // ---- multigrid host side (mg.cpp) ---------------------------------------------------
 void mg_setup(tbdg_ctx* c, const tbdg_mg_desc* desc);

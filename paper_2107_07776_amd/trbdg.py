@@ -24,7 +24,10 @@ EXPORTED = [
     "tbdg_diag_momentum", "tbdg_diag_pressure", "tbdg_rhs_momentum", "tbdg_grad_p",
     "tbdg_add_grad_p", "tbdg_rhs_pressure", "tbdg_solve_momentum", "tbdg_solve_pressure",
     "tbdg_step", "tbdg_profile_enable", "tbdg_profile_read", "tbdg_mg_setup",
-    "tbdg_mg_levels", "tbdg_mg_apply",
+    "tbdg_mg_levels", "tbdg_mg_apply", "tbdg_net_create", "tbdg_net_destroy",
+    "tbdg_net_last_error", "tbdg_net_num_params", "tbdg_net_set_params", "tbdg_net_get_params",
+    "tbdg_net_get_grads", "tbdg_net_zero_grad", "tbdg_net_forward", "tbdg_net_backward",
+    "tbdg_net_mse", "tbdg_net_adam_step",
 ]
 
 PRECOND = {"jacobi": 0, "mg_fp32": 1, "mg_bf16": 2}
@@ -111,6 +114,18 @@ def load_library(path=LIB_PATH):
         "tbdg_mg_setup": ([vp, P(MGDesc)], i),
         "tbdg_mg_levels": ([vp, i, P(i), P(i64), P(d)], i),
         "tbdg_mg_apply": ([vp, i, i, vp, vp], i),
+        "tbdg_net_create": ([i, ctypes.c_uint64, vp, P(vp)], i),
+        "tbdg_net_destroy": ([vp], None),
+        "tbdg_net_last_error": ([vp], ctypes.c_char_p),
+        "tbdg_net_num_params": ([vp, P(i64)], i),
+        "tbdg_net_set_params": ([vp, vp], i),
+        "tbdg_net_get_params": ([vp, vp], i),
+        "tbdg_net_get_grads": ([vp, vp], i),
+        "tbdg_net_zero_grad": ([vp], i),
+        "tbdg_net_forward": ([vp, vp, vp, i, i, i, i], i),
+        "tbdg_net_backward": ([vp, vp], i),
+        "tbdg_net_mse": ([vp, vp, vp, i64, vp, P(d)], i),
+        "tbdg_net_adam_step": ([vp, ctypes.c_float, ctypes.c_float, ctypes.c_float, ctypes.c_float], i),
     }
     for name, (args, res) in sig.items():
         fn = getattr(lib, name)
@@ -325,3 +340,89 @@ class Context:
         ms, n = ctypes.c_double(), ctypes.c_int64()
         self._check(self.lib.tbdg_profile_read(self.h, int(which), ctypes.byref(ms), ctypes.byref(n)))
         return ms.value, n.value
+
+
+class Net:
+    """The learned pressure-guess network on the current HIP device and stream."""
+
+    def __init__(self, channels=32, seed=0, stream=None, device="cuda"):
+        self.lib = load_library()
+        self.device = torch.device(device)
+        if self.device.type != "cuda" or not torch.cuda.is_available():
+            raise RuntimeError("trbdg needs a ROCm GPU device")
+        self.stream = stream if stream is not None else torch.cuda.current_stream(self.device)
+        h = ctypes.c_void_p()
+        st = self.lib.tbdg_net_create(int(channels), ctypes.c_uint64(seed),
+                                      ctypes.c_void_p(self.stream.cuda_stream), ctypes.byref(h))
+        if st != 0:
+            raise TrbdgError(st, "tbdg_net_create failed")
+        self.h = h
+        n = ctypes.c_int64()
+        self._check(self.lib.tbdg_net_num_params(self.h, ctypes.byref(n)))
+        self.n_params = n.value
+        self.shape = None
+
+    def _check(self, st):
+        if st != 0:
+            raise TrbdgError(st, self.lib.tbdg_net_last_error(self.h).decode())
+
+    def _f32(self, t, n, name):
+        if not isinstance(t, torch.Tensor) or t.device.type != "cuda" or t.dtype != torch.float32 \
+                or not t.is_contiguous() or t.numel() != n:
+            raise ValueError(f"{name} must be a contiguous float32 CUDA tensor of {n} entries")
+        return t
+
+    def set_params(self, theta):
+        self._check(self.lib.tbdg_net_set_params(self.h, _ptr(self._f32(theta, self.n_params, "theta"))))
+
+    def params(self):
+        out = torch.empty(self.n_params, dtype=torch.float32, device=self.device)
+        self._check(self.lib.tbdg_net_get_params(self.h, _ptr(out)))
+        return out
+
+    def grads(self):
+        out = torch.empty(self.n_params, dtype=torch.float32, device=self.device)
+        self._check(self.lib.tbdg_net_get_grads(self.h, _ptr(out)))
+        return out
+
+    def zero_grad(self):
+        self._check(self.lib.tbdg_net_zero_grad(self.h))
+
+    def forward(self, x):
+        """x: float32 [B][3][nz][ny][nx] -> y: float32 [B][nz][ny][nx]."""
+        if x.dim() != 5 or x.shape[1] != 3:
+            raise ValueError("x must have shape [B][3][nz][ny][nx]")
+        B, _, nz, ny, nx = x.shape
+        self._f32(x, x.numel(), "x")
+        y = torch.empty((B, nz, ny, nx), dtype=torch.float32, device=self.device)
+        self._check(self.lib.tbdg_net_forward(self.h, _ptr(x), _ptr(y), B, nx, ny, nz))
+        self.shape = (B, nz, ny, nx)
+        return y
+
+    def backward(self, dy):
+        if self.shape is None or tuple(dy.shape) != self.shape:
+            raise ValueError("dy must have the shape of the last forward output")
+        self._check(self.lib.tbdg_net_backward(self.h, _ptr(self._f32(dy, dy.numel(), "dy"))))
+
+    def mse(self, yhat, target):
+        """(loss, dL/dyhat) with L = mean((yhat - target)^2)."""
+        dy = torch.empty_like(yhat)
+        loss = ctypes.c_double()
+        self._check(self.lib.tbdg_net_mse(self.h, _ptr(self._f32(yhat, yhat.numel(), "yhat")),
+                                          _ptr(self._f32(target, yhat.numel(), "target")),
+                                          yhat.numel(), _ptr(dy), ctypes.byref(loss)))
+        return loss.value, dy
+
+    def adam_step(self, lr, beta1=0.9, beta2=0.999, eps=1e-8):
+        self._check(self.lib.tbdg_net_adam_step(self.h, lr, beta1, beta2, eps))
+
+    def close(self):
+        if getattr(self, "h", None):
+            self.lib.tbdg_net_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
