@@ -155,6 +155,11 @@ TBDG_API tbdg_status tbdg_rhs_pressure(tbdg_ctx* ctx, int stage, const double* u
  * basis size m (<= 60).  precond: TBDG_PRECOND_*; the multigrid values apply
  * to tbdg_solve_pressure only.  guess: 0 = use the content of x_inout.     */
 enum {
+    TBDG_GUESS_GIVEN = 0,       /* the content of x_inout (in tbdg_step: the previous pressure) */
+    TBDG_GUESS_PREVIOUS = 1,    /* tbdg_step only: previous pressure + same stage's last increment */
+    TBDG_GUESS_LEARNED = 2      /* tbdg_step only: the guess network, TBDG_GUESS_PREVIOUS as fallback */
+};
+enum {
     TBDG_PRECOND_JACOBI = 0,
     TBDG_PRECOND_MG_FP32 = 1,   /* h/p-multigrid V-cycle in FP32 under FP64 flexible CG */
     TBDG_PRECOND_MG_BF16 = 2    /* the same with BF16 storage on the finest level        */
@@ -164,14 +169,14 @@ typedef struct {
     int maxiter;
     int restart;
     int precond;
-    int guess;
+    int guess;          /* TBDG_GUESS_*                                       */
 } tbdg_solver_opts;
 
 typedef struct {
     int iters;
     double res0;        /* ||b - A x0||_2 / ||b||_2                          */
     double res_final;   /* ||b - A x||_2 / ||b||_2, recomputed at the end    */
-    int guess_used;
+    int guess_used;     /* TBDG_GUESS_* actually used (tbdg_step)              */
 } tbdg_solve_info;
 
 /* Momentum predictor solve (right-preconditioned restarted GMRES with CGS2
@@ -271,6 +276,51 @@ TBDG_API tbdg_status tbdg_net_mse(tbdg_net* net, const float* yhat, const float*
 /* One Adam step (Kingma and Ba, with bias correction) on the master
  * parameters from the accumulated gradients.                                */
 TBDG_API tbdg_status tbdg_net_adam_step(tbdg_net* net, float lr, float beta1, float beta2, float eps);
+
+/* Initial guesses of the Helmholtz solves in tbdg_step (not part of the
+ * paper).  The context keeps the two newest pressure increments p_new - p_prev
+ * of its solves (inc_1 the newest, from the other stage; inc_2 from the same
+ * stage one step earlier) and their stage weights beta.  For the stage-s
+ * solve with right-hand side b and previous pressure p:
+ *   TBDG_GUESS_PREVIOUS: p + inc_2;
+ *   TBDG_GUESS_LEARNED:  per cell K the network input is
+ *     (f0 / s_inc, f1 / s_inc, div / s_div),  f0 = mean_K(inc_1) / (beta_1 dt),
+ *     f1 = mean_K(inc_2) / (beta_2 dt), div = -(beta_s dt / |K|) sum_{i in K}
+ *     (b_i - alpha_s (M^p p)_i) (cell average of div u** in flux form), mean_K
+ *     the Gauss-rule cell average, s_inc and s_div the RMS over cells of f0
+ *     and div (1 where zero); the network output y (cell averages of the
+ *     correction to TBDG_GUESS_PREVIOUS) gives the guess
+ *     p + inc_2 + beta_s dt s_inc I(y), I the multilinear interpolation of
+ *     the cell values from the cell centres (periodic) to the nodes; the
+ *     candidate with the smaller FP64 residual ||b - H x|| (learned or
+ *     TBDG_GUESS_PREVIOUS) is used.
+ * With fewer than two stored increments the previous pressure is used.  A
+ * failed step clears the history.                                           */
+
+/* Attach (net != NULL) or detach the guess network; it must use the
+ * context's stream.  The network is borrowed, not owned.  Clears the history. */
+TBDG_API tbdg_status tbdg_set_guess_net(tbdg_ctx* ctx, tbdg_net* net);
+/* Forget the stored increments (start of a new trajectory).                 */
+TBDG_API tbdg_status tbdg_guess_reset(tbdg_ctx* ctx);
+/* Record training samples: after each Helmholtz solve of tbdg_step that has
+ * two stored increments, sample k of buf (device, FP32, [capacity][4][N_c])
+ * receives the network input [3][N_c] and the target
+ * mean_K(p_new - p - inc_2) / (beta_s dt) / s_inc.  buf NULL stops
+ * recording; the history is cleared.                                        */
+TBDG_API tbdg_status tbdg_guess_record(tbdg_ctx* ctx, float* buf, int capacity);
+TBDG_API tbdg_status tbdg_guess_recorded(tbdg_ctx* ctx, int* count);
+/* ||b - H x|| of the learned and the fallback candidate of the last
+ * TBDG_GUESS_LEARNED decision (host outputs; 0 before the first).          */
+TBDG_API tbdg_status tbdg_guess_last(tbdg_ctx* ctx, double* r_learned, double* r_fallback);
+/* The network input for given vectors (device, N_p each): x FP32 [3][N_c];
+ * scales (host, may be NULL) = (s_inc, s_div).                              */
+TBDG_API tbdg_status tbdg_guess_features(tbdg_ctx* ctx, int stage, const double* b,
+                                         const double* p_prev, const double* inc1, double beta1,
+                                         const double* inc2, double beta2, float* x, double* scales);
+/* out = p_prev + inc2 + beta_s dt s_inc I(y) (y: FP32 [N_c], the rest N_p).  */
+TBDG_API tbdg_status tbdg_guess_inject(tbdg_ctx* ctx, int stage, const double* p_prev,
+                                       const double* inc2, const float* y, double s_inc,
+                                       double* out);
 
 /* TR-BDF2 state: u = u^n, u_hist = u^{n-1+gamma} (history level of the
  * stage-1 extrapolation), p = p^n; t and n are host values.                 */

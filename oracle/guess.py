@@ -1,9 +1,10 @@
 """Inputs, outputs and fallback of the learned pressure initial guess
 (oracle; TEST INFRASTRUCTURE ONLY).
 
-Not part of the paper.  For the Helmholtz solve of stage s, with beta_s,
-right-hand side b = alpha_s M^p p_prev + F_p(u**) and the two latest pressure
-increments (inc1 the newest, from a solve with beta1; inc2 with beta2):
+Not part of the paper.  For the Helmholtz solve of stage s (beta_s, right-hand
+side b = alpha_s M^p p_prev + F_p(u**)) with the two newest pressure
+increments inc1 (the newest, from the other stage, weight beta1) and inc2
+(the same stage one step earlier, weight beta2):
 
 * per cell K, f0 = mean_K(inc1) / (beta1 dt), f1 = mean_K(inc2) / (beta2 dt),
   where mean_K is the Gauss-rule cell average (sum of weight * nodal value);
@@ -12,10 +13,13 @@ increments (inc1 the newest, from a solve with beta1; inc2 with beta2):
   div u** in flux form (the test functions of K sum to one);
 * scales s_inc = RMS over cells of f0, s_div = RMS of div (1 where zero);
 * network input, cell-lexicographic: [f0 / s_inc, f1 / s_inc, div / s_div];
-* training target: mean_K(p_new - p_prev) / (beta_s dt) / s_inc;
-* learned guess: p_prev + beta_s dt s_inc y_K on every node of K;
-* fallback: p_prev + (beta_s / beta1) inc1, the newest increment rescaled to
-  the stage.
+* fallback: p_prev + inc2 (the pressures of the two stages carry different
+  offsets, so the other stage's increment predicts poorly);
+* the network predicts the cell averages of the correction to the fallback,
+  training target mean_K(p_new - p_prev - inc2) / (beta_s dt) / s_inc;
+* learned guess: fallback + beta_s dt s_inc I(y), I the multilinear
+  interpolation of the cell values from the cell centres (periodic) to the
+  nodes, so the correction is continuous.
 """
 import numpy as np
 
@@ -46,13 +50,42 @@ def features(ts, s, b, p_prev, inc1, beta1, inc2, beta2):
     return np.stack([f0 / s_inc, f1 / s_inc, div / s_div]), s_inc, s_div
 
 
-def target(ts, s, p_new, p_prev, s_inc):
-    return cell_average(ts.disc, p_new - p_prev) / (ts.beta[s] * ts.dt) / s_inc
+def target(ts, s, p_new, p_prev, inc2, s_inc):
+    return cell_average(ts.disc, p_new - p_prev - inc2) / (ts.beta[s] * ts.dt) / s_inc
 
 
-def inject(ts, s, p_prev, y, s_inc):
-    return p_prev + np.repeat(ts.beta[s] * ts.dt * s_inc * np.asarray(y), ts.disc.nbp)
+def interpolate_centres(disc, y):
+    """Multilinear interpolation of cell values (located at the cell centres,
+    periodic) to the pressure nodes, [cell][node] layout."""
+    mesh = disc.mesh
+    y = np.asarray(y, dtype=np.float64)
+    out = np.zeros(disc.N_p)
+    z = disc.zp
+    for c in range(disc.Nc):
+        ijk = mesh.cell_ijk(c)
+        for node in range(disc.nbp):
+            loc = [(node // disc.n_p ** a) % disc.n_p for a in range(disc.dim)]
+            lo, w = [], []
+            for a in range(disc.dim):
+                X = ijk[a] + z[loc[a]] - 0.5          # position in cell-centre units
+                i0 = int(np.floor(X))
+                lo.append(i0)
+                w.append(X - i0)
+            val = 0.0
+            for corner in range(2 ** disc.dim):
+                wt, idx = 1.0, []
+                for a in range(disc.dim):
+                    bit = (corner >> a) & 1
+                    wt *= w[a] if bit else 1.0 - w[a]
+                    idx.append((lo[a] + bit) % mesh.n_cells[a])
+                val += wt * y[mesh.cell_index(idx)]
+            out[c * disc.nbp + node] = val
+    return out
 
 
-def fallback(ts, s, p_prev, inc1, beta1):
-    return p_prev + (ts.beta[s] / beta1) * inc1
+def inject(ts, s, p_prev, inc2, y, s_inc):
+    return fallback(p_prev, inc2) + ts.beta[s] * ts.dt * s_inc * interpolate_centres(ts.disc, y)
+
+
+def fallback(p_prev, inc2):
+    return p_prev + inc2

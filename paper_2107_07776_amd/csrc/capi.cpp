@@ -91,6 +91,7 @@ void free_all(tbdg_ctx* c) {
     dfree(c->s_p1);
     dfree(c->s_pv);
     trbdg::mg_free(c);
+    trbdg::guess_free(c);
 }
 
 tbdg_solver_opts defaults(const tbdg_solver_opts* o) {
@@ -102,6 +103,7 @@ tbdg_solver_opts defaults(const tbdg_solver_opts* o) {
     require(r.restart >= 0 && r.restart <= GMRES_MAX, "GMRES restart must be in [0, 60]");
     require(r.precond >= TBDG_PRECOND_JACOBI && r.precond <= TBDG_PRECOND_MG_BF16,
             "unknown preconditioner");
+    require(r.guess >= TBDG_GUESS_GIVEN && r.guess <= TBDG_GUESS_LEARNED, "unknown initial guess");
     return r;
 }
 
@@ -393,6 +395,8 @@ tbdg_status tbdg_solve_pressure(tbdg_ctx* c, int stage, const double* rhs, doubl
         check_stage(stage);
         require(rhs && p_inout, "null pointer");
         const tbdg_solver_opts o = defaults(opts);
+        if (o.guess != TBDG_GUESS_GIVEN)
+            throw Error(TBDG_EINVAL, "initial-guess modes apply to the solves inside tbdg_step");
         const tbdg_status s = trbdg::solve_pressure(c, stage, rhs, p_inout, o, info);
         if (s != TBDG_OK) c->last_error = "pressure CG did not converge";
         return s;
@@ -453,6 +457,100 @@ tbdg_status tbdg_mg_apply(tbdg_ctx* c, int stage, int precision, const double* r
         require(r != z, "r and z may not alias");
         require(precision == 1 || precision == 2, "precision must be 1 (FP32) or 2 (BF16)");
         trbdg::mg_apply(c, stage, precision, r, z);
+        return TBDG_OK;
+    });
+}
+
+tbdg_status tbdg_set_guess_net(tbdg_ctx* c, tbdg_net* net) {
+    if (!c) return TBDG_EINVAL;
+    return guarded(c, [&]() {
+        if (net) {
+            require(trbdg::net_stream(net) == c->stream, "network and context must share one stream");
+            if (c->geom.nc[0] > 93)
+                throw Error(TBDG_EUNSUPPORTED, "the network takes at most 93 cells in x");
+        }
+        if (!c->gs && !net) return TBDG_OK;
+        trbdg::guess_reset(c);
+        trbdg::guess_ensure(c);
+        c->gs->net = net;
+        return TBDG_OK;
+    });
+}
+
+tbdg_status tbdg_guess_reset(tbdg_ctx* c) {
+    if (!c) return TBDG_EINVAL;
+    return guarded(c, [&]() {
+        trbdg::guess_reset(c);
+        return TBDG_OK;
+    });
+}
+
+tbdg_status tbdg_guess_record(tbdg_ctx* c, float* buf, int capacity) {
+    if (!c) return TBDG_EINVAL;
+    return guarded(c, [&]() {
+        require(buf == nullptr || capacity > 0, "capacity must be positive");
+        trbdg::guess_ensure(c);
+        trbdg::guess_reset(c);
+        c->gs->rec = buf;
+        c->gs->rec_cap = buf ? capacity : 0;
+        c->gs->rec_count = 0;
+        return TBDG_OK;
+    });
+}
+
+tbdg_status tbdg_guess_recorded(tbdg_ctx* c, int* count) {
+    if (!c) return TBDG_EINVAL;
+    return guarded(c, [&]() {
+        require(count != nullptr, "null pointer");
+        *count = c->gs ? c->gs->rec_count : 0;
+        return TBDG_OK;
+    });
+}
+
+tbdg_status tbdg_guess_last(tbdg_ctx* c, double* r_learned, double* r_fallback) {
+    if (!c) return TBDG_EINVAL;
+    return guarded(c, [&]() {
+        require(r_learned && r_fallback, "null pointer");
+        *r_learned = c->gs ? c->gs->last_r[0] : 0.0;
+        *r_fallback = c->gs ? c->gs->last_r[1] : 0.0;
+        return TBDG_OK;
+    });
+}
+
+tbdg_status tbdg_guess_features(tbdg_ctx* c, int stage, const double* b, const double* p_prev,
+                                const double* inc1, double beta1, const double* inc2, double beta2,
+                                float* x, double* scales) {
+    if (!c) return TBDG_EINVAL;
+    return guarded(c, [&]() {
+        check_stage(stage);
+        require(b && p_prev && inc1 && inc2 && x, "null pointer");
+        require(beta1 > 0.0 && beta2 > 0.0, "stage weights must be positive");
+        trbdg::guess_features(c, stage, b, p_prev, inc1, beta1, inc2, beta2);
+        TBDG_HIP(hipMemcpyAsync(x, c->gs->feat, sizeof(float) * 3 * c->Nc, hipMemcpyDeviceToDevice,
+                                c->stream));
+        if (scales) {
+            TBDG_HIP(hipMemcpyAsync(c->host_out, c->gs->sc, 2 * sizeof(double), hipMemcpyDeviceToHost,
+                                    c->stream));
+            TBDG_HIP(hipStreamSynchronize(c->stream));
+            scales[0] = c->host_out[0];
+            scales[1] = c->host_out[1];
+        }
+        return TBDG_OK;
+    });
+}
+
+tbdg_status tbdg_guess_inject(tbdg_ctx* c, int stage, const double* p_prev, const double* inc2,
+                              const float* y, double s_inc, double* out) {
+    if (!c) return TBDG_EINVAL;
+    return guarded(c, [&]() {
+        check_stage(stage);
+        require(p_prev && inc2 && y && out, "null pointer");
+        require(s_inc > 0.0 && std::isfinite(s_inc), "scale must be positive");
+        trbdg::guess_ensure(c);
+        c->host_out[0] = s_inc;
+        TBDG_HIP(hipMemcpyAsync(c->gs->sc, c->host_out, sizeof(double), hipMemcpyHostToDevice, c->stream));
+        trbdg::guess_inject(c, stage, p_prev, inc2, y, out);
+        TBDG_HIP(hipStreamSynchronize(c->stream));
         return TBDG_OK;
     });
 }

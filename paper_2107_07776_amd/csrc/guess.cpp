@@ -1,0 +1,135 @@
+// Initial guesses of the Helmholtz solves inside tbdg_step: the previous
+// pressure, the previous pressure plus the same stage's increment of the
+// previous step, or the learned guess of the network with that as fallback
+// (the guess with the smaller FP64 residual is used).  Also records (input, target) samples of
+// the network from the solver's own solves.
+#include <cmath>
+#include <utility>
+
+#include "internal.hpp"
+
+namespace trbdg {
+
+namespace {
+
+void ensure_state(tbdg_ctx* c) {
+    if (c->gs) return;
+    GuessState* g = new GuessState();
+    c->gs = g;
+    auto dal = [&](int64_t n) {
+        void* p = nullptr;
+        TBDG_HIP(hipMalloc(&p, sizeof(double) * (size_t)(n > 0 ? n : 1)));
+        g->allocs.push_back(p);
+        return static_cast<double*>(p);
+    };
+    auto fal = [&](int64_t n) {
+        void* p = nullptr;
+        TBDG_HIP(hipMalloc(&p, sizeof(float) * (size_t)(n > 0 ? n : 1)));
+        g->allocs.push_back(p);
+        return static_cast<float*>(p);
+    };
+    g->inc[0] = dal(c->Np);
+    g->inc[1] = dal(c->Np);
+    g->cells = dal(3 * c->Nc);
+    g->partial = dal(2 * ((c->Nc + 255) / 256));
+    g->sc = dal(8);
+    g->trial = dal(c->Np);
+    g->feat = fal(3 * c->Nc);
+    g->y = fal(c->Nc);
+}
+
+// ||b - H x||^2 into the device slot
+void residual_sq(tbdg_ctx* c, int s, const double* b, const double* x, double* slot) {
+    launch_apply_pressure(c, c->alpha(s), x, c->cq);
+    vec_axpby(c->stream, c->Np, 1.0, b, -1.0, c->cq, c->cr);
+    dot2(c, c->Np, c->cr, c->cr, slot);
+}
+
+}  // namespace
+
+void guess_ensure(tbdg_ctx* c) { ensure_state(c); }
+
+void guess_free(tbdg_ctx* c) {
+    if (!c->gs) return;
+    for (void* p : c->gs->allocs) (void)hipFree(p);
+    delete c->gs;
+    c->gs = nullptr;
+}
+
+void guess_reset(tbdg_ctx* c) {
+    if (c->gs) c->gs->n = 0;
+}
+
+void guess_features(tbdg_ctx* c, int s, const double* b, const double* p, const double* inc1,
+                    double beta1, const double* inc2, double beta2) {
+    ensure_state(c);
+    GuessState& g = *c->gs;
+    const int G = launch_guess_cells(c, inc1, inc2, b, p, 1.0 / (beta1 * c->dt), 1.0 / (beta2 * c->dt),
+                                     -c->beta[s] * c->dt, c->alpha(s), g.cells, g.partial);
+    launch_guess_feat(c, g.cells, g.partial, G, g.feat, g.sc);
+}
+
+void guess_inject(tbdg_ctx* c, int s, const double* p, const double* inc2, const float* y, double* out) {
+    ensure_state(c);
+    launch_guess_inject(c, p, inc2, y, c->beta[s] * c->dt, c->gs->sc, out);
+}
+
+int guess_prepare(tbdg_ctx* c, int s, int mode, const double* b, const double* p_prev, double* x) {
+    const int64_t bp = (int64_t)sizeof(double) * c->Np;
+    const bool recording = c->gs && c->gs->rec && c->gs->rec_count < c->gs->rec_cap;
+    if (mode == 0 && !recording) {
+        TBDG_HIP(hipMemcpyAsync(x, p_prev, bp, hipMemcpyDeviceToDevice, c->stream));
+        return 0;
+    }
+    ensure_state(c);
+    GuessState& g = *c->gs;
+    g.feat_valid = false;
+    const bool learned = mode == 2 && g.net != nullptr && g.n >= 2;
+    if (g.n >= 2 && (learned || recording)) {
+        guess_features(c, s, b, p_prev, g.inc[0], g.beta[0], g.inc[1], g.beta[1]);
+        g.feat_valid = true;
+    }
+    if (mode == 0 || g.n < 2) {
+        TBDG_HIP(hipMemcpyAsync(x, p_prev, bp, hipMemcpyDeviceToDevice, c->stream));
+        return 0;
+    }
+    // fallback: the increment of the same stage one step earlier (the two
+    // stages' pressures carry different offsets, so the other stage's
+    // increment is a poor predictor)
+    vec_axpby(c->stream, c->Np, 1.0, p_prev, 1.0, g.inc[1], x);
+    if (!learned) return 1;
+    net_infer(g.net, g.feat, g.y, c->geom.nc[0], c->geom.nc[1], c->geom.nc[2]);
+    guess_inject(c, s, p_prev, g.inc[1], g.y, g.trial);
+    residual_sq(c, s, b, g.trial, c->red_out + 60);
+    residual_sq(c, s, b, x, c->red_out + 61);
+    TBDG_HIP(hipMemcpyAsync(c->host_out, c->red_out + 60, 2 * sizeof(double), hipMemcpyDeviceToHost,
+                            c->stream));
+    TBDG_HIP(hipStreamSynchronize(c->stream));
+    const double rl = c->host_out[0], rf = c->host_out[1];
+    g.last_r[0] = std::sqrt(rl);
+    g.last_r[1] = std::sqrt(rf);
+    if (std::isfinite(rl) && rl < rf) {
+        TBDG_HIP(hipMemcpyAsync(x, g.trial, bp, hipMemcpyDeviceToDevice, c->stream));
+        return 2;
+    }
+    return 1;
+}
+
+void guess_after_solve(tbdg_ctx* c, int s, const double* p_new, const double* p_prev) {
+    if (!c->gs) return;
+    GuessState& g = *c->gs;
+    if (g.feat_valid && g.rec && g.rec_count < g.rec_cap) {
+        float* dst = g.rec + (int64_t)g.rec_count * 4 * c->Nc;
+        TBDG_HIP(hipMemcpyAsync(dst, g.feat, sizeof(float) * 3 * c->Nc, hipMemcpyDeviceToDevice, c->stream));
+        launch_guess_target(c, p_new, p_prev, g.inc[1], 1.0 / (c->beta[s] * c->dt), g.sc, dst + 3 * c->Nc);
+        ++g.rec_count;
+    }
+    g.feat_valid = false;
+    std::swap(g.inc[0], g.inc[1]);
+    g.beta[1] = g.beta[0];
+    vec_axpby(c->stream, c->Np, 1.0, p_new, -1.0, p_prev, g.inc[0]);
+    g.beta[0] = c->beta[s];
+    g.n = g.n < 2 ? g.n + 1 : 2;
+}
+
+}  // namespace trbdg

@@ -131,6 +131,25 @@ struct MGData {
     std::vector<void*> allocs;
 };
 
+// Learned / extrapolated initial guesses of the Helmholtz solves in a step.
+struct GuessState {
+    tbdg_net* net = nullptr;
+    double* inc[2] = {nullptr, nullptr};   // newest pressure increments (inc[0] newest)
+    double beta[2] = {0.0, 0.0};           // stage weights of those solves
+    int n = 0;                              // valid increments
+    double* cells = nullptr;               // f0, f1, div per cell [3][Nc]
+    double* partial = nullptr;
+    double* sc = nullptr;                   // s_inc, s_div
+    double* trial = nullptr;               // learned guess (N_p)
+    float* feat = nullptr;                  // network input [3][Nc]
+    float* y = nullptr;                     // network output [Nc]
+    bool feat_valid = false;
+    double last_r[2] = {0.0, 0.0};          // residual norms of the last learned / fallback guesses
+    float* rec = nullptr;                   // recorded samples [cap][4][Nc] (caller's memory)
+    int rec_cap = 0, rec_count = 0;
+    std::vector<void*> allocs;
+};
+
 // Voxel grid of the guess network: nx * ny * nz voxels per sample, B samples.
 struct NetGeo {
     int nx, ny, nz, nvox, B;
@@ -189,6 +208,7 @@ struct tbdg_ctx {
     double* s_p1 = nullptr;
     double* s_pv = nullptr;     // pressure interpolated to velocity nodes (Ns)
     trbdg::MGData* mg = nullptr;    // multigrid hierarchy (built on first use)
+    trbdg::GuessState* gs = nullptr;   // initial-guess history and network
 
     double alpha(int s) const;
     double mcoef(int s) const { return 1.0 / (beta[s] * dt); }
@@ -338,6 +358,30 @@ void net_to_channel_last(hipStream_t st, const float* x, int B, int C, int nvox,
 int net_mse(hipStream_t st, const float* yhat, const float* y, int64_t n, float* dy, double* partial);
 void net_adam(hipStream_t st, int64_t n, float* theta, const float* g, float* m, float* v, float lr,
               float b1, float b2, float eps, float c1, float c2);
+
+// ---- learned initial guess (guess.hip, guess.cpp, net.cpp) --------------------------
+int launch_guess_cells(const tbdg_ctx* c, const double* inc1, const double* inc2, const double* b,
+                       const double* p, double c0, double c1, double cdiv, double alpha,
+                       double* cells, double* partial);
+void launch_guess_feat(const tbdg_ctx* c, const double* cells, const double* partial, int G,
+                       float* feat, double* sc);
+void launch_guess_inject(const tbdg_ctx* c, const double* p, const double* inc2, const float* y,
+                         double bdt, const double* sc, double* out);
+void launch_guess_target(const tbdg_ctx* c, const double* pn, const double* p, const double* inc2,
+                         double inv_bdt, const double* sc, float* out);
+void guess_ensure(tbdg_ctx* c);
+void guess_free(tbdg_ctx* c);
+void guess_reset(tbdg_ctx* c);
+void guess_features(tbdg_ctx* c, int s, const double* b, const double* p, const double* inc1,
+                    double beta1, const double* inc2, double beta2);
+void guess_inject(tbdg_ctx* c, int s, const double* p, const double* inc2, const float* y, double* out);
+// writes the initial guess of the stage-s solve to x; returns 0 (previous
+// pressure), 1 (rescaled increment) or 2 (learned)
+int guess_prepare(tbdg_ctx* c, int s, int mode, const double* b, const double* p_prev, double* x);
+void guess_after_solve(tbdg_ctx* c, int s, const double* p_new, const double* p_prev);
+// forward pass of the network on one sample of the mesh's cell grid
+void net_infer(tbdg_net* net, const float* x, float* y, int nx, int ny, int nz);
+hipStream_t net_stream(const tbdg_net* net);
 
 // ---- multigrid host side (mg.cpp) ---------------------------------------------------
 void mg_setup(tbdg_ctx* c, const tbdg_mg_desc* desc);

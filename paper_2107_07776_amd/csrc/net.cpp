@@ -341,3 +341,14 @@ tbdg_status tbdg_net_adam_step(tbdg_net* n, float lr, float beta1, float beta2, 
 }
 
 }  // extern "C"
+
+namespace trbdg {
+
+hipStream_t net_stream(const tbdg_net* net) { return net->stream; }
+
+void net_infer(tbdg_net* net, const float* x, float* y, int nx, int ny, int nz) {
+    const tbdg_status st = tbdg_net_forward(net, x, y, 1, nx, ny, nz);
+    if (st != TBDG_OK) throw Error(st, std::string("guess network: ") + net->last_error);
+}
+
+}  // namespace trbdg

@@ -314,14 +314,22 @@ tbdg_status step(tbdg_ctx* c, tbdg_state* S, const tbdg_solver_opts& mo,
     TBDG_HIP(hipMemcpyAsync(c->s_ustar, S->u, bu, hipMemcpyDeviceToDevice, st));
     rc = solve_momentum(c, 1, c->s_w, c->s_rhs, c->s_ustar, mo, &loc[0]);
     if (info) info[0] = loc[0];
-    if (rc != TBDG_OK) return rc;
+    if (rc != TBDG_OK) {
+        guess_reset(c);
+        return rc;
+    }
     const double b1 = c->beta[1] * c->dt;
     launch_add_grad_p(c, c->s_ustar, b1, S->p, c->s_ustar);          // u**
     rhs_pressure(c, 1, c->s_ustar, S->p, c->s_pb);
-    TBDG_HIP(hipMemcpyAsync(c->s_pg, S->p, bp, hipMemcpyDeviceToDevice, st));
+    int used = guess_prepare(c, 1, po.guess, c->s_pb, S->p, c->s_pg);
     rc = solve_pressure(c, 1, c->s_pb, c->s_pg, po, &loc[1]);
+    loc[1].guess_used = used;
     if (info) info[1] = loc[1];
-    if (rc != TBDG_OK) return rc;
+    if (rc != TBDG_OK) {
+        guess_reset(c);
+        return rc;
+    }
+    guess_after_solve(c, 1, c->s_pg, S->p);
     launch_add_grad_p(c, c->s_ustar, -b1, c->s_pg, c->s_ug);          // u^{n+gamma}
     // ---- stage 2 ----
     extrapolate(c, 2, c->s_ug, S->u, c->s_w);
@@ -329,14 +337,22 @@ tbdg_status step(tbdg_ctx* c, tbdg_state* S, const tbdg_solver_opts& mo,
     TBDG_HIP(hipMemcpyAsync(c->s_ustar, c->s_ug, bu, hipMemcpyDeviceToDevice, st));
     rc = solve_momentum(c, 2, c->s_w, c->s_rhs, c->s_ustar, mo, &loc[2]);
     if (info) info[2] = loc[2];
-    if (rc != TBDG_OK) return rc;
+    if (rc != TBDG_OK) {
+        guess_reset(c);
+        return rc;
+    }
     const double b2 = c->beta[2] * c->dt;
     launch_add_grad_p(c, c->s_ustar, b2, c->s_pg, c->s_ustar);
     rhs_pressure(c, 2, c->s_ustar, c->s_pg, c->s_pb);
-    TBDG_HIP(hipMemcpyAsync(c->s_p1, c->s_pg, bp, hipMemcpyDeviceToDevice, st));
+    used = guess_prepare(c, 2, po.guess, c->s_pb, c->s_pg, c->s_p1);
     rc = solve_pressure(c, 2, c->s_pb, c->s_p1, po, &loc[3]);
+    loc[3].guess_used = used;
     if (info) info[3] = loc[3];
-    if (rc != TBDG_OK) return rc;
+    if (rc != TBDG_OK) {
+        guess_reset(c);
+        return rc;
+    }
+    guess_after_solve(c, 2, c->s_p1, c->s_pg);
     launch_add_grad_p(c, c->s_ustar, -b2, c->s_p1, c->s_u1);
     // ---- commit ----
     TBDG_HIP(hipMemcpyAsync(S->u_hist, c->s_ug, bu, hipMemcpyDeviceToDevice, st));

@@ -1,0 +1,104 @@
+"""Training and evaluation of the learned pressure initial guess.
+
+Samples come from the solver itself: ``tbdg_step`` runs from seeded initial
+states with sample recording on (network input and the converged increment
+of every Helmholtz solve).  The network is trained on the GPU by its own
+kernels (forward, backward, Adam through the C ABI); the evaluation runs
+held-out trajectories with the three initial-guess modes and reports the
+pressure-solve iterations.  Orchestration only: every computation happens in
+the library.
+"""
+import time
+
+import torch
+
+
+def generate(ctx, initial_state, seeds, steps, discard, precond="mg_fp32", tol=1e-8, maxiter=20000):
+    """Samples [S][4][N_c] (float32, device) from ``steps`` recorded steps per
+    seed after ``discard`` unrecorded ones.  ``initial_state(seed)`` returns
+    device tensors (u, u_hist, p)."""
+    cap = 2 * steps * len(seeds)
+    buf = torch.zeros((cap, 4, ctx.N_c), dtype=torch.float32, device=ctx.device)
+    total = 0
+    for seed in seeds:
+        u, uh, p = initial_state(seed)
+        ctx.guess_record(None)
+        ctx.guess_reset()
+        t = 0.0
+        for n in range(discard):
+            ctx.step(u, uh, p, t, n, mom_tol=tol, prs_tol=tol, prs_maxiter=maxiter, precond=precond,
+                     guess="previous")
+            t += ctx.dt
+        ctx.guess_record(buf[total:])
+        # recording clears the history: one step to refill it
+        for n in range(discard, discard + steps + 1):
+            ctx.step(u, uh, p, t, n, mom_tol=tol, prs_tol=tol, prs_maxiter=maxiter, precond=precond,
+                     guess="previous")
+            t += ctx.dt
+        total += ctx.guess_recorded()
+        ctx.guess_record(None)
+    return buf[:total]
+
+
+def train(net, samples, grid, epochs, batch=8, lr=1e-3, seed=0, log=None):
+    """Adam on the mean-squared error of the recorded targets; returns the
+    mean loss of every epoch.  ``grid`` = (nx, ny, nz) of the cell grid."""
+    nx, ny, nz = grid
+    S = samples.shape[0]
+    x_all = samples[:, :3].reshape(S, 3, nz, ny, nx)
+    y_all = samples[:, 3].reshape(S, nz, ny, nx)
+    gen = torch.Generator(device="cpu")
+    gen.manual_seed(seed)
+    losses = []
+    for ep in range(epochs):
+        perm = torch.randperm(S, generator=gen)
+        tot, cnt = 0.0, 0
+        for i in range(0, S, batch):
+            idx = perm[i:i + batch].to(samples.device)
+            x = x_all.index_select(0, idx).contiguous()
+            y = y_all.index_select(0, idx).contiguous()
+            yhat = net.forward(x)
+            loss, dy = net.mse(yhat, y)
+            net.zero_grad()
+            net.backward(dy)
+            net.adam_step(lr)
+            tot += loss * len(idx)
+            cnt += len(idx)
+        losses.append(tot / cnt)
+        if log:
+            log(f"epoch {ep + 1}/{epochs}: loss {losses[-1]:.4e}")
+    return losses
+
+
+def evaluate(ctx, initial_state, seeds, steps, discard, modes=("given", "previous", "learned"),
+             precond="mg_fp32", tol=1e-8, maxiter=20000):
+    """Mean pressure-solve iterations, fallback rate and steps/s per guess
+    mode over held-out trajectories (identical trajectories for every mode
+    up to the solver tolerance)."""
+    out = {}
+    for mode in modes:
+        iters, used, secs, nsteps = [], [], 0.0, 0
+        for seed in seeds:
+            u, uh, p = initial_state(seed)
+            ctx.guess_reset()
+            t = 0.0
+            for n in range(discard + steps):
+                torch.cuda.synchronize()
+                t0 = time.perf_counter()
+                info, _ = ctx.step(u, uh, p, t, n, mom_tol=tol, prs_tol=tol, prs_maxiter=maxiter,
+                                   precond=precond, guess=mode)
+                torch.cuda.synchronize()
+                t += ctx.dt
+                if n >= discard:
+                    secs += time.perf_counter() - t0
+                    nsteps += 1
+                    for j in (1, 3):
+                        iters.append(info[j]["iters"])
+                        used.append(info[j]["guess_used"])
+        res = {"mean_pressure_iterations": sum(iters) / len(iters), "steps_per_s": nsteps / secs,
+               "solves": len(iters)}
+        if mode == "learned":
+            res["learned_used_rate"] = sum(1 for g in used if g == 2) / len(used)
+            res["fallback_rate"] = 1.0 - res["learned_used_rate"]
+        out[mode] = res
+    return out

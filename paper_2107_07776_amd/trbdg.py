@@ -27,8 +27,12 @@ EXPORTED = [
     "tbdg_mg_levels", "tbdg_mg_apply", "tbdg_net_create", "tbdg_net_destroy",
     "tbdg_net_last_error", "tbdg_net_num_params", "tbdg_net_set_params", "tbdg_net_get_params",
     "tbdg_net_get_grads", "tbdg_net_zero_grad", "tbdg_net_forward", "tbdg_net_backward",
-    "tbdg_net_mse", "tbdg_net_adam_step",
+    "tbdg_net_mse", "tbdg_net_adam_step", "tbdg_set_guess_net", "tbdg_guess_reset",
+    "tbdg_guess_record", "tbdg_guess_recorded", "tbdg_guess_features", "tbdg_guess_inject",
+    "tbdg_guess_last",
 ]
+
+GUESS = {"given": 0, "previous": 1, "learned": 2}
 
 PRECOND = {"jacobi": 0, "mg_fp32": 1, "mg_bf16": 2}
 
@@ -126,6 +130,13 @@ def load_library(path=LIB_PATH):
         "tbdg_net_backward": ([vp, vp], i),
         "tbdg_net_mse": ([vp, vp, vp, i64, vp, P(d)], i),
         "tbdg_net_adam_step": ([vp, ctypes.c_float, ctypes.c_float, ctypes.c_float, ctypes.c_float], i),
+        "tbdg_set_guess_net": ([vp, vp], i),
+        "tbdg_guess_reset": ([vp], i),
+        "tbdg_guess_record": ([vp, vp, i], i),
+        "tbdg_guess_recorded": ([vp, P(i)], i),
+        "tbdg_guess_last": ([vp, P(d), P(d)], i),
+        "tbdg_guess_features": ([vp, i, vp, vp, vp, d, vp, d, vp, P(d)], i),
+        "tbdg_guess_inject": ([vp, i, vp, vp, vp, d, vp], i),
     }
     for name, (args, res) in sig.items():
         fn = getattr(lib, name)
@@ -139,8 +150,8 @@ def _ptr(t):
     return ctypes.c_void_p(t.data_ptr()) if t is not None else ctypes.c_void_p(0)
 
 
-def solver_opts(tol=1e-8, maxiter=1000, restart=30, precond="jacobi"):
-    return SolverOpts(float(tol), int(maxiter), int(restart), PRECOND[precond], 0)
+def solver_opts(tol=1e-8, maxiter=1000, restart=30, precond="jacobi", guess="given"):
+    return SolverOpts(float(tol), int(maxiter), int(restart), PRECOND[precond], GUESS[guess])
 
 
 class Context:
@@ -293,13 +304,15 @@ class Context:
         return info.as_dict() | {"status": st}
 
     def step(self, u, u_hist, p, t=0.0, n=0, mom_tol=1e-8, prs_tol=1e-8, mom_maxiter=1000,
-             prs_maxiter=5000, restart=30, precond="jacobi", check=True):
+             prs_maxiter=5000, restart=30, precond="jacobi", guess="given", check=True):
         """One TR-BDF2 step in place on (u, u_hist, p); returns per-solve info.
-        ``precond`` selects the pressure preconditioner."""
+        ``precond`` selects the pressure preconditioner, ``guess`` the initial
+        guess of the pressure solves ("given": previous pressure, "previous":
+        rescaled newest increment, "learned": the attached network)."""
         S = State(_ptr(self._vec(u, self.N_u, "u")), _ptr(self._vec(u_hist, self.N_u, "u_hist")),
                   _ptr(self._vec(p, self.N_p, "p")), float(t), int(n))
         mo = solver_opts(mom_tol, mom_maxiter, restart)
-        po = solver_opts(prs_tol, prs_maxiter, 0, precond)
+        po = solver_opts(prs_tol, prs_maxiter, 0, precond, guess)
         infos = (SolveInfo * 4)()
         st = self.lib.tbdg_step(self.h, ctypes.byref(S), ctypes.byref(mo), ctypes.byref(po), infos)
         if check:
@@ -329,6 +342,57 @@ class Context:
         self._check(self.lib.tbdg_mg_apply(self.h, stage, 1 if precision == "fp32" else 2,
                                            _ptr(self._vec(r, self.N_p, "r")), _ptr(z)))
         return z
+
+    def set_guess_net(self, net):
+        """Attach a Net (same stream) for guess="learned", or None to detach."""
+        self._net = net
+        self._check(self.lib.tbdg_set_guess_net(self.h, net.h if net is not None else None))
+
+    def guess_reset(self):
+        self._check(self.lib.tbdg_guess_reset(self.h))
+
+    def guess_record(self, buf):
+        """Record (input, target) samples of the pressure solves into buf
+        (float32 CUDA tensor [capacity][4][N_c]); None stops recording."""
+        if buf is None:
+            self._rec = None
+            self._check(self.lib.tbdg_guess_record(self.h, None, 0))
+            return
+        if buf.dtype != torch.float32 or buf.device.type != "cuda" or not buf.is_contiguous() \
+                or buf.dim() != 3 or buf.shape[1:] != (4, self.N_c):
+            raise ValueError("buf must be a contiguous float32 CUDA tensor [capacity][4][N_c]")
+        self._rec = buf
+        self._check(self.lib.tbdg_guess_record(self.h, _ptr(buf), buf.shape[0]))
+
+    def guess_recorded(self):
+        n = ctypes.c_int()
+        self._check(self.lib.tbdg_guess_recorded(self.h, ctypes.byref(n)))
+        return n.value
+
+    def guess_last(self):
+        """(||b - H x_learned||, ||b - H x_fallback||) of the last learned decision."""
+        a, b = ctypes.c_double(), ctypes.c_double()
+        self._check(self.lib.tbdg_guess_last(self.h, ctypes.byref(a), ctypes.byref(b)))
+        return a.value, b.value
+
+    def guess_features(self, stage, b, p_prev, inc1, beta1, inc2, beta2):
+        """(x [3][N_c] float32, (s_inc, s_div)) of the guess network."""
+        x = torch.empty((3, self.N_c), dtype=torch.float32, device=self.device)
+        sc = (ctypes.c_double * 2)()
+        self._check(self.lib.tbdg_guess_features(
+            self.h, stage, _ptr(self._vec(b, self.N_p, "b")), _ptr(self._vec(p_prev, self.N_p, "p_prev")),
+            _ptr(self._vec(inc1, self.N_p, "inc1")), float(beta1), _ptr(self._vec(inc2, self.N_p, "inc2")),
+            float(beta2), _ptr(x), sc))
+        return x, (sc[0], sc[1])
+
+    def guess_inject(self, stage, p_prev, inc2, y, s_inc):
+        out = self.empty_p()
+        if y.dtype != torch.float32 or y.numel() != self.N_c or not y.is_contiguous():
+            raise ValueError("y must be a contiguous float32 tensor of N_c entries")
+        self._check(self.lib.tbdg_guess_inject(self.h, stage, _ptr(self._vec(p_prev, self.N_p, "p_prev")),
+                                               _ptr(self._vec(inc2, self.N_p, "inc2")), _ptr(y),
+                                               float(s_inc), _ptr(out)))
+        return out
 
     def profile(self, enable):
         """Bracket every operator-kernel launch with HIP events (measurement)."""

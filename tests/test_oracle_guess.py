@@ -3,8 +3,10 @@
 * Gauss-rule cell averages are exact cell means for pressures the space holds;
 * the divergence feature of an interpolated polynomial velocity equals the
   exact cell mean of its divergence (interior cells of a periodic mesh);
-* the training target of an injected increment returns that increment;
-* the rescaled previous increment is exact for pressures linear in time.
+* the multilinear interpolation of cell-centre values reproduces linear data,
+  and the target of an injected correction returns it;
+* the same-stage increment of the previous step is exact for pressures that
+  are linear in time up to a constant offset per stage.
 """
 import numpy as np
 
@@ -57,29 +59,41 @@ def test_divergence_feature_is_cell_mean_of_divergence():
         assert np.allclose(x[0] * s_inc, 1.0 / (0.5 * ts.dt)) and np.allclose(x[1] * s_inc, 2.0 / (0.25 * ts.dt))
 
 
-def test_target_inverts_injection():
-    disc, ts = _setup()
+def test_interpolation_and_target_reproduce_linear_cell_data():
+    """Cell values linear in the cell index are reproduced exactly by the
+    multilinear interpolation away from the periodic seam, and the target of
+    the injected correction returns them (the cell mean of a linear function
+    is its centre value); a constant is reproduced everywhere."""
+    disc, ts = _setup(n=6)
     rng = np.random.default_rng(1)
-    p_prev = rng.standard_normal(disc.N_p)
-    y = rng.standard_normal(disc.Nc)
+    p_prev, inc2 = rng.standard_normal(disc.N_p), rng.standard_normal(disc.N_p)
+    n = disc.mesh.n_cells[0]
+    ij = np.array([disc.mesh.cell_ijk(c) for c in range(disc.Nc)])
+    y = 0.3 + 0.7 * ij[:, 0] - 0.2 * ij[:, 1]
+    inner = (ij[:, 0] > 0) & (ij[:, 0] < n - 1) & (ij[:, 1] > 0) & (ij[:, 1] < n - 1)
     for s in (1, 2):
-        p_new = guess.inject(ts, s, p_prev, y, 3.5)
-        assert np.allclose(guess.target(ts, s, p_new, p_prev, 3.5), y, atol=1e-12)
+        pg = guess.inject(ts, s, p_prev, inc2, y, 3.5)
+        tgt = guess.target(ts, s, pg, p_prev, inc2, 3.5)
+        assert np.allclose(tgt[inner], y[inner], atol=1e-12)
+        const = guess.inject(ts, s, p_prev, inc2, np.full(disc.Nc, 2.0), 3.5)
+        assert np.allclose(const - p_prev - inc2, ts.beta[s] * ts.dt * 3.5 * 2.0, atol=1e-13)
 
 
-def test_fallback_exact_for_linear_in_time_pressure():
+def test_fallback_exact_for_linear_in_time_pressure_with_stage_offsets():
+    """p = P(t) + o_s with P linear in time and a constant offset per stage:
+    the same-stage increment of the previous step predicts exactly."""
     disc, ts = _setup()
     rng = np.random.default_rng(2)
-    p0, q = rng.standard_normal(disc.N_p), rng.standard_normal(disc.N_p)
+    p0, q, o1, o2 = (rng.standard_normal(disc.N_p) for _ in range(4))
     g, dt = ts.cst["gamma"], ts.dt
 
-    def p(t):
-        return p0 + t * q
+    def p(t, o):
+        return p0 + t * q + o
 
     tn = 0.3
-    # stage 1 of step n: the newest increment came from stage 2 of step n-1
-    inc1 = p(tn) - p(tn - (1 - g) * dt)
-    assert np.allclose(guess.fallback(ts, 1, p(tn), inc1, 1 - g), p(tn + g * dt), atol=1e-13)
-    # stage 2: the newest increment came from stage 1 of the same step
-    inc1 = p(tn + g * dt) - p(tn)
-    assert np.allclose(guess.fallback(ts, 2, p(tn + g * dt), inc1, g), p(tn + dt), atol=1e-13)
+    # stage 1 of step n: p_prev = p^n (a stage-2 value), inc2 = p^{n-1+g} - p^{n-1}
+    inc2 = p(tn - (1 - g) * dt, o1) - p(tn - dt, o2)
+    assert np.allclose(guess.fallback(p(tn, o2), inc2), p(tn + g * dt, o1), atol=1e-13)
+    # stage 2: p_prev = p^{n+g}, inc2 = p^n - p^{n-1+g}
+    inc2 = p(tn, o2) - p(tn - (1 - g) * dt, o1)
+    assert np.allclose(guess.fallback(p(tn + g * dt, o1), inc2), p(tn + dt, o2), atol=1e-13)
