@@ -105,10 +105,11 @@ def cpu_baseline(W, seconds_budget=20.0):
                       f"scaled by DoF ratio {scale:.3g}; setup {setup:.1f}s excluded"}
 
 
-def run_solver(ctx, W, precond, steps, warmup, profile, mg_degree=0):
+def run_solver(ctx, W, precond, steps, warmup, profile, mg_degree=0, guess="given"):
     """Fresh initial state, `warmup` untimed steps, `steps` timed steps with the
-    given pressure preconditioner.  Returns timing, iterations, final fields
-    and (with `profile`) the event-timed operator kernels."""
+    given pressure preconditioner and initial guess.  Returns timing,
+    iterations, final fields and (with `profile`) the event-timed operator
+    kernels."""
     import numpy as np
     import torch
 
@@ -120,43 +121,82 @@ def run_solver(ctx, W, precond, steps, warmup, profile, mg_degree=0):
     H = torch.tensor(u0 if uh0 is None else uh0, device=dev)
     P = torch.tensor(p0, device=dev)
     tol = W["tol"]
-    if precond != "jacobi":
+    ctx.guess_reset()
+    if precond != "jacobi" and not getattr(ctx, "_mg_built", False):
         t_setup = time.perf_counter()
         ctx.mg_setup(degree=mg_degree)
+        ctx._mg_built = True
         torch.cuda.synchronize()
         log(f"[bench] multigrid set-up {time.perf_counter() - t_setup:.2f}s: "
             f"{[(l['np'], l['cells'], l['dofs']) for l in ctx.mg_levels()]}")
     t = 0.0
     n = 0
     for i in range(warmup):
-        info, _ = ctx.step(U, H, P, t, n, mom_tol=tol, prs_tol=tol, prs_maxiter=20000, precond=precond)
+        info, _ = ctx.step(U, H, P, t, n, mom_tol=tol, prs_tol=tol, prs_maxiter=20000, precond=precond,
+                           guess=guess)
         t += W["dt"]
         n += 1
-        log(f"[bench] {precond} warmup step {i + 1}/{warmup}: iterations {[x['iters'] for x in info]}")
+        log(f"[bench] {precond}/{guess} warmup step {i + 1}/{warmup}: iterations {[x['iters'] for x in info]}")
     torch.cuda.synchronize()
     if profile:
         ctx.profile(True)
         ctx.profile_read(0)
         ctx.profile_read(1)
-    iters = []
+    iters, used = [], []
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     for i in range(steps):
-        info, _ = ctx.step(U, H, P, t, n, mom_tol=tol, prs_tol=tol, prs_maxiter=20000, precond=precond)
+        info, _ = ctx.step(U, H, P, t, n, mom_tol=tol, prs_tol=tol, prs_maxiter=20000, precond=precond,
+                           guess=guess)
         t += W["dt"]
         n += 1
         iters.append([x["iters"] for x in info])
-        log(f"[bench] {precond} step {i + 1}/{steps}: iterations {iters[-1]}")
+        used += [info[1]["guess_used"], info[3]["guess_used"]]
+        log(f"[bench] {precond}/{guess} step {i + 1}/{steps}: iterations {iters[-1]}")
     torch.cuda.synchronize()
     elapsed = time.perf_counter() - t0
     if not np.isfinite(U.abs().max().item()):
         raise SystemExit("non-finite velocity")
     res = dict(sps=steps / elapsed, ms=1e3 * elapsed / steps, elapsed=elapsed,
-               iters=[float(np.mean([it[j] for it in iters])) for j in range(4)], U=U, P=P)
+               iters=[float(np.mean([it[j] for it in iters])) for j in range(4)], U=U, P=P,
+               learned_rate=sum(1 for g in used if g == 2) / max(len(used), 1))
     if profile:
         res["prof"] = (ctx.profile_read(0), ctx.profile_read(1))
         ctx.profile(False)
     return res
+
+
+def random_phase_state(ctx, W, seed, amplitude=0.25):
+    """Divergence-free random-phase field of the learned guess's training
+    data (8 Fourier modes, |kappa| <= 4, amplitudes N(0,1)/|kappa|^2, scaled
+    by `amplitude` so that the fields stay in the scheme's stable Courant
+    range at the workload's time step), zero pressure."""
+    import torch
+
+    import synthetic
+    xu = ctx.node_coords(0).cpu().numpy()
+    nbu = (W["k"] + 1) ** W["dim"]
+    u = amplitude * synthetic.random_phase_velocity(xu, seed)
+    u = torch.tensor(synthetic.nodal_velocity(u, W["dim"], nbu), device="cuda")
+    return u, u.clone(), torch.zeros(ctx.N_p, dtype=torch.float64, device="cuda")
+
+
+def train_guess(ctx, W, seeds=(0, 1, 2, 3), steps=20, discard=3, epochs=20):
+    """Generate samples with the solver, train the guess network on the GPU."""
+    from paper_2107_07776_amd import Net, learned_guess
+    t0 = time.perf_counter()
+    samples = learned_guess.generate(ctx, lambda s: random_phase_state(ctx, W, s), list(seeds), steps,
+                                     discard, precond="mg_fp32", tol=W["tol"])
+    t1 = time.perf_counter()
+    net = Net(32, seed=1)
+    nx, ny, nz = (list(W["n"]) + [1, 1])[:3]
+    losses = learned_guess.train(net, samples, (nx, ny, nz), epochs=epochs, batch=8, lr=1e-3)
+    t2 = time.perf_counter()
+    log(f"[bench] guess network: {samples.shape[0]} samples in {t1 - t0:.1f}s, {epochs} epochs in "
+        f"{t2 - t1:.1f}s, loss {losses[0]:.3e} -> {losses[-1]:.3e}")
+    return net, {"samples": int(samples.shape[0]), "generation_s": t1 - t0, "training_s": t2 - t1,
+                 "epochs": epochs, "loss_first_epoch": losses[0], "loss_last_epoch": losses[-1],
+                 "train_seeds": list(seeds)}
 
 
 def main():
@@ -172,6 +212,10 @@ def main():
     ap.add_argument("--mg-degree", type=int, default=0)
     ap.add_argument("--no-compare", action="store_true",
                     help="skip the plain FP64 (Jacobi) reference run")
+    ap.add_argument("--guess", default="previous", choices=["given", "previous", "learned"],
+                    help="initial guess of the timed solver's pressure solves")
+    ap.add_argument("--no-learned", action="store_true",
+                    help="skip training and timing the learned-guess variant")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py: this build runs on exactly one GPU; --gpus {args.gpus} is not supported",
@@ -189,8 +233,13 @@ def main():
     plain = None
     if not args.no_compare and args.precond != "jacobi":
         plain = run_solver(ctx, W, "jacobi", args.steps, args.warmup, False)
+    net = None
+    learned_info = None
+    if args.guess == "learned" or (not args.no_learned and args.precond != "jacobi"):
+        net, learned_info = train_guess(ctx, W)
+        ctx.set_guess_net(net)
     main_run = run_solver(ctx, W, args.precond, args.steps, args.warmup, not args.no_profile,
-                          args.mg_degree)
+                          args.mg_degree, args.guess)
     solver = {"jacobi": "Jacobi-preconditioned FP64 CG",
               "mg_fp32": "FP32 h/p-multigrid V-cycle (Chebyshev smoother) under FP64 flexible CG",
               "mg_bf16": "h/p-multigrid V-cycle with BF16 storage on the finest level under FP64 "
@@ -198,14 +247,28 @@ def main():
     out = {"metric": METRIC, "value": main_run["sps"], "unit": "steps/s", "n_gpus": 1,
            "steps": args.steps, "warmup": args.warmup, "ms_per_step": main_run["ms"],
            "higher_is_better": True, "scaling": "strong", "vs_baseline": None, "dtype": "f64",
-           "data": "synthetic (closed-form Taylor-Green initial field)",
+           "data": "synthetic (closed-form Taylor-Green initial field; seeded random-phase fields train the guess network)",
            "config": {"workload": W["label"], "pressure_solver": solver,
                       "momentum_solver": "Jacobi-preconditioned FP64 GMRES(30)",
                       "tolerance": W["tol"], "cells": list(W["n"]), "degree": W["k"],
                       "velocity_dofs": ctx.N_u, "pressure_dofs": ctx.N_p,
                       "mean_iterations_per_step": main_run["iters"]}}
+    out["config"]["pressure_initial_guess"] = {
+        "given": "previous pressure",
+        "previous": "previous pressure + the same stage's increment of the previous step",
+        "learned": "learned (3D CNN, bf16) correction of the same-stage increment, FP64 residual judge"}[args.guess]
     if args.precond != "jacobi":
         out["preconditioner_dtype"] = "f32" if args.precond == "mg_fp32" else "bf16 storage, f32 arithmetic"
+    if learned_info is not None and args.guess != "learned":
+        lr_run = run_solver(ctx, W, args.precond, args.steps, args.warmup, False, args.mg_degree, "learned")
+        learned_info.update({"steps_per_s": lr_run["sps"], "ms_per_step": lr_run["ms"],
+                             "mean_iterations_per_step": lr_run["iters"],
+                             "learned_used_rate": lr_run["learned_rate"],
+                             "fallback_rate": 1.0 - lr_run["learned_rate"]})
+    if learned_info is not None:
+        if args.guess == "learned":
+            learned_info["learned_used_rate"] = main_run["learned_rate"]
+        out["learned_guess"] = learned_info
     if plain is not None:
         du = (main_run["U"] - plain["U"]).norm().item() / plain["U"].norm().item()
         dp = (main_run["P"] - plain["P"]).norm().item() / plain["P"].norm().item()
@@ -240,6 +303,9 @@ def main():
     if not args.no_cpu_baseline:
         log("[bench] timing the CPU oracle on a bounded sample")
         out["cpu_baseline"] = cpu_baseline(W)
+    ctx.set_guess_net(None)
+    if net is not None:
+        net.close()
     ctx.close()
     print(json.dumps(out), flush=True)
 

@@ -13,10 +13,12 @@ import time
 import torch
 
 
-def generate(ctx, initial_state, seeds, steps, discard, precond="mg_fp32", tol=1e-8, maxiter=20000):
+def generate(ctx, initial_state, seeds, steps, discard, precond="mg_fp32", tol=1e-8, maxiter=20000,
+             log=None):
     """Samples [S][4][N_c] (float32, device) from ``steps`` recorded steps per
     seed after ``discard`` unrecorded ones.  ``initial_state(seed)`` returns
-    device tensors (u, u_hist, p)."""
+    device tensors (u, u_hist, p).  A trajectory whose step fails (a solve
+    that does not converge) ends there; its samples so far are kept."""
     cap = 2 * steps * len(seeds)
     buf = torch.zeros((cap, 4, ctx.N_c), dtype=torch.float32, device=ctx.device)
     total = 0
@@ -25,15 +27,16 @@ def generate(ctx, initial_state, seeds, steps, discard, precond="mg_fp32", tol=1
         ctx.guess_record(None)
         ctx.guess_reset()
         t = 0.0
-        for n in range(discard):
-            ctx.step(u, uh, p, t, n, mom_tol=tol, prs_tol=tol, prs_maxiter=maxiter, precond=precond,
-                     guess="previous")
-            t += ctx.dt
-        ctx.guess_record(buf[total:])
-        # recording clears the history: one step to refill it
-        for n in range(discard, discard + steps + 1):
-            ctx.step(u, uh, p, t, n, mom_tol=tol, prs_tol=tol, prs_maxiter=maxiter, precond=precond,
-                     guess="previous")
+        for n in range(discard + steps + 1):
+            if n == discard:
+                # recording clears the history: one more step refills it
+                ctx.guess_record(buf[total:])
+            _, st = ctx.step(u, uh, p, t, n, mom_tol=tol, prs_tol=tol, prs_maxiter=maxiter,
+                             precond=precond, guess="previous", check=False)
+            if st != 0:
+                if log:
+                    log(f"seed {seed}: step {n} failed with status {st}; trajectory ends")
+                break
             t += ctx.dt
         total += ctx.guess_recorded()
         ctx.guess_record(None)
