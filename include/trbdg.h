@@ -59,8 +59,10 @@ typedef enum {
 typedef struct tbdg_ctx tbdg_ctx;
 
 /* Structured box mesh T_h (Sec. 3).  dim 2 or 3; n_cells[a] >= 1;
- * lo < hi per direction; periodic[a] != 0 wraps direction a.  mapping 0 is
- * the affine box; other mappings are reserved (TBDG_EUNSUPPORTED).          */
+ * lo < hi per direction; periodic[a] != 0 wraps direction a, otherwise its
+ * two end faces are boundary faces with Dirichlet velocity data
+ * (tbdg_set_dirichlet).  mapping 0 is the affine box; other mappings are
+ * reserved (TBDG_EUNSUPPORTED).                                             */
 typedef struct {
     int dim;
     int n_cells[3];
@@ -106,6 +108,23 @@ TBDG_API tbdg_status tbdg_node_coords(const tbdg_ctx* ctx, int field, double* xy
  * (1 + gamma/(2(1-gamma)), -gamma/(2(1-gamma))) for s = 1 (u_new = u^n,
  * u_old = u^{n-1+gamma}) and (1 + (1-gamma)/gamma, -(1-gamma)/gamma) for
  * s = 2 (u_new = u^{n+gamma}, u_old = u^n).  All arrays N_u.                */
+/* Dirichlet velocity data (Sec. 3: the boundary E^B of the non-periodic
+ * directions; the pressure is natural, homogeneous Neumann, there).  The data
+ * enter the momentum operator only through the Lax-Friedrichs speed at the
+ * boundary, max(|w.n|, |(2 u_D - w).n|), and the momentum right-hand side
+ * through the boundary terms of eq. rhs1 (penalty 2C on boundary faces).
+ * Boundary points are the tangential velocity Gauss nodes of every boundary
+ * face: for each non-periodic direction a, side 0 (low) then 1 (high), the
+ * boundary cells in lexicographic order of their other coordinates, the
+ * points lexicographic (lower direction fastest).  tbdg_face_qpoints returns
+ * the count and, if xyz != NULL, the coordinates ([n][dim], device).        */
+TBDG_API tbdg_status tbdg_face_qpoints(const tbdg_ctx* ctx, int64_t* n, double* xyz);
+/* Dirichlet data at the boundary points ([n][dim], device, copied): slot 0
+ * for the stage-1 time t^n + gamma dt, slot 1 for t^{n+1}; both start zero.
+ * Stage s of tbdg_apply_momentum, tbdg_diag_momentum, tbdg_rhs_momentum,
+ * tbdg_solve_momentum and tbdg_step uses slot s - 1.                        */
+TBDG_API tbdg_status tbdg_set_dirichlet(tbdg_ctx* ctx, int slot, const double* uD);
+
 TBDG_API tbdg_status tbdg_extrapolate(tbdg_ctx* ctx, int stage, const double* u_new,
                              const double* u_old, double* w);
 
@@ -198,7 +217,7 @@ TBDG_API tbdg_status tbdg_solve_pressure(tbdg_ctx* ctx, int stage, const double*
 
 /* Multigrid preconditioner of the pressure Helmholtz operator.  The paper
  * preconditions the pressure CG with a multigrid (Sec. 4) without details;
- * this one is an h/p hierarchy on the periodic affine box: level 0 is
+ * this one is an h/p hierarchy on the affine box: level 0 is
  * Q_{k-1} on the mesh, then Q_1 on the same cells (when k-1 > 1), then Q_1
  * on meshes with every direction halved while all directions have an even
  * cell count and the level has more than coarse_cells cells.  Each level

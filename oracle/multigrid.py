@@ -191,7 +191,8 @@ def _prolongation(fine, coarse):
 
 
 class Multigrid:
-    """h/p-multigrid V-cycle for H = alpha M^p + K on a periodic box.
+    """h/p-multigrid V-cycle for H = alpha M^p + K on an affine box (periodic
+    directions wrap, the others carry the natural Neumann condition).
 
     ``disc`` gives the mesh and the velocity degree k (pressure degree k-1);
     ``alpha`` the mass coefficient of the stage."""
@@ -199,8 +200,8 @@ class Multigrid:
     def __init__(self, disc, alpha, degree=3, lanczos_steps=15, range_=15.0, safety=1.1,
                  coarse_cells=None, seed=0):
         mesh = disc.mesh
-        if not mesh.affine or not all(mesh.periodic):
-            raise ValueError("the multigrid hierarchy is defined on periodic affine boxes")
+        if not mesh.affine:
+            raise ValueError("the multigrid hierarchy is defined on affine boxes")
         if coarse_cells is None:
             coarse_cells = 64 if mesh.dim == 3 else 16
         self.degree = int(degree)

@@ -3,6 +3,7 @@
 #include <cmath>
 #include <cstring>
 #include <new>
+#include <vector>
 
 #include "internal.hpp"
 
@@ -92,6 +93,8 @@ void free_all(tbdg_ctx* c) {
     dfree(c->s_pv);
     trbdg::mg_free(c);
     trbdg::guess_free(c);
+    dfree(c->bnd_uD[0]);
+    dfree(c->bnd_uD[1]);
 }
 
 tbdg_solver_opts defaults(const tbdg_solver_opts* o) {
@@ -139,9 +142,6 @@ tbdg_status tbdg_create(const tbdg_mesh_desc* mesh, const tbdg_disc_desc* disc, 
             }
         }
         if (mesh->mapping != 0) throw Error(TBDG_EUNSUPPORTED, "only the affine box (mapping 0) is built");
-        for (int a = 0; a < c->dim; ++a)
-            if (!c->periodic_flags[a])
-                throw Error(TBDG_EUNSUPPORTED, "non-periodic (Dirichlet) directions are not built");
         require(disc->k_u >= 2, "velocity degree k_u must be >= 2");
         const int kmax = c->dim == 2 ? 5 : 3;
         if (disc->k_u > kmax) throw Error(TBDG_EUNSUPPORTED, "velocity degree too high for this dim");
@@ -224,6 +224,28 @@ tbdg_status tbdg_create(const tbdg_mesh_desc* mesh, const tbdg_disc_desc* disc, 
         c->s_pg = dalloc(c->Np);
         c->s_p1 = dalloc(c->Np);
         c->s_pv = dalloc(c->Ns);
+        // boundary faces of the non-periodic directions: point offsets and
+        // zero-initialised Dirichlet data for the two stage times
+        {
+            int64_t nf = 1;
+            for (int a = 0; a < c->dim - 1; ++a) nf *= c->n;
+            int64_t off = 0;
+            for (int a = 0; a < 3; ++a)
+                for (int sd = 0; sd < 2; ++sd) {
+                    if (a < c->dim && !c->periodic_flags[a]) {
+                        c->bnd_off[a][sd] = off;
+                        off += (c->Nc / c->geom.nc[a]) * nf;
+                    } else {
+                        c->bnd_off[a][sd] = -1;
+                    }
+                }
+            c->bnd_npts = off;
+            for (int k = 0; k < 2; ++k) {
+                c->bnd_uD[k] = dalloc(off * c->dim);
+                TBDG_HIP(hipMemsetAsync(c->bnd_uD[k], 0, sizeof(double) * (off > 0 ? off * c->dim : 1),
+                                        c->stream));
+            }
+        }
         trbdg::launch_diag_pressure(c, c->alpha(1), c->diag_p[1]);
         trbdg::launch_diag_pressure(c, c->alpha(2), c->diag_p[2]);
         trbdg::vec_recip(c->stream, c->Np, c->diag_p[1], c->invd_p[1]);
@@ -289,13 +311,69 @@ tbdg_status tbdg_extrapolate(tbdg_ctx* c, int stage, const double* u_new, const 
     });
 }
 
+tbdg_status tbdg_face_qpoints(const tbdg_ctx* c, int64_t* n, double* xyz) {
+    if (!c) return TBDG_EINVAL;
+    return guarded(const_cast<tbdg_ctx*>(c), [&]() {
+        require(n != nullptr, "null pointer");
+        *n = c->bnd_npts;
+        if (!xyz || c->bnd_npts == 0) return TBDG_OK;
+        const int d = c->dim, N = c->n;
+        int64_t nf = 1;
+        for (int a = 0; a < d - 1; ++a) nf *= N;
+        std::vector<double> pts((size_t)c->bnd_npts * d);
+        for (int a = 0; a < d; ++a) {
+            if (c->bnd_off[a][0] < 0) continue;
+            int oth[2] = {0, 0}, no = 0;
+            for (int b = 0; b < d; ++b)
+                if (b != a) oth[no++] = b;
+            const int64_t ncf = c->Nc / c->geom.nc[a];
+            for (int sd = 0; sd < 2; ++sd)
+                for (int64_t tc = 0; tc < ncf; ++tc) {
+                    int64_t ci[3] = {0, 0, 0};
+                    int64_t r = tc;
+                    for (int q = 0; q < no; ++q) {
+                        ci[oth[q]] = r % c->geom.nc[oth[q]];
+                        r /= c->geom.nc[oth[q]];
+                    }
+                    for (int64_t tt = 0; tt < nf; ++tt) {
+                        const int64_t pt = c->bnd_off[a][sd] + tc * nf + tt;
+                        int64_t rr = tt;
+                        for (int q = 0; q < no; ++q) {
+                            const int b = oth[q];
+                            const int ib = (int)(rr % N);
+                            rr /= N;
+                            pts[pt * d + b] = c->geom.lo[b] + (ci[b] + c->tab.xu[ib]) * c->geom.h[b];
+                        }
+                        pts[pt * d + a] = c->geom.lo[a] + (sd ? c->geom.nc[a] : 0) * c->geom.h[a];
+                    }
+                }
+        }
+        TBDG_HIP(hipMemcpyAsync(xyz, pts.data(), sizeof(double) * pts.size(), hipMemcpyHostToDevice,
+                                c->stream));
+        TBDG_HIP(hipStreamSynchronize(c->stream));
+        return TBDG_OK;
+    });
+}
+
+tbdg_status tbdg_set_dirichlet(tbdg_ctx* c, int slot, const double* uD) {
+    if (!c) return TBDG_EINVAL;
+    return guarded(c, [&]() {
+        require(slot == 0 || slot == 1, "slot must be 0 (stage-1 time) or 1 (stage-2 time)");
+        require(uD != nullptr || c->bnd_npts == 0, "null pointer");
+        if (c->bnd_npts == 0) return TBDG_OK;
+        TBDG_HIP(hipMemcpyAsync(c->bnd_uD[slot], uD, sizeof(double) * c->bnd_npts * c->dim,
+                                hipMemcpyDeviceToDevice, c->stream));
+        return TBDG_OK;
+    });
+}
+
 tbdg_status tbdg_apply_momentum(tbdg_ctx* c, int stage, const double* w, const double* u, double* y) {
     if (!c) return TBDG_EINVAL;
     return guarded(c, [&]() {
         check_stage(stage);
         require(w && u && y, "null pointer");
         require(u != y && w != y, "output must not alias an input");
-        trbdg::launch_apply_momentum(c, c->mcoef(stage), c->theta[stage], w, u, y);
+        trbdg::launch_apply_momentum(c, stage, w, u, y);
         return TBDG_OK;
     });
 }
@@ -316,7 +394,7 @@ tbdg_status tbdg_diag_momentum(tbdg_ctx* c, int stage, const double* w, double* 
     return guarded(c, [&]() {
         check_stage(stage);
         require(w && diag, "null pointer");
-        trbdg::launch_diag_momentum(c, c->mcoef(stage), c->theta[stage], w, diag);
+        trbdg::launch_diag_momentum(c, stage, w, diag);
         return TBDG_OK;
     });
 }

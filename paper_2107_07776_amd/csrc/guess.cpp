@@ -12,10 +12,22 @@ namespace trbdg {
 
 namespace {
 
+void fill_state(tbdg_ctx* c, GuessState* g);
+
 void ensure_state(tbdg_ctx* c) {
     if (c->gs) return;
     GuessState* g = new GuessState();
-    c->gs = g;
+    try {
+        fill_state(c, g);
+    } catch (...) {
+        for (void* p : g->allocs) (void)hipFree(p);
+        delete g;
+        throw;
+    }
+    c->gs = g;   // published only when complete
+}
+
+void fill_state(tbdg_ctx* c, GuessState* g) {
     auto dal = [&](int64_t n) {
         void* p = nullptr;
         TBDG_HIP(hipMalloc(&p, sizeof(double) * (size_t)(n > 0 ? n : 1)));

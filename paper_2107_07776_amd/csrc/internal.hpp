@@ -77,6 +77,27 @@ struct KTimer {
     int64_t count[2] = {0, 0};
 };
 
+// Dirichlet velocity data on the boundary faces of the box (the faces normal
+// to non-periodic directions).  Face points are the tangential Gauss nodes of
+// the velocity rule; face (a, side) holds one block per boundary cell, the
+// cells in lexicographic order of their remaining coordinates, the points in
+// the order of the line index of the operator kernels (lower direction
+// fastest).
+struct Bnd {
+    const double* uD;       // [points][dim] at the stage time (zeros until set)
+    int64_t off[3][2];      // first point of face (a, side); -1 for periodic directions
+};
+
+// Point index of the face point `tt` of boundary face (a, side) of `cell`.
+__host__ __device__ inline int64_t bnd_point(const Bnd& b, const Geom& g, int64_t cell, int a,
+                                             int side, int tt, int nf) {
+    const int64_t c0 = cell % g.nc[0], c1 = (cell / g.nc[0]) % g.nc[1],
+                  c2 = cell / ((int64_t)g.nc[0] * g.nc[1]);
+    const int64_t tc = a == 0 ? c1 + (int64_t)g.nc[1] * c2
+                     : (a == 1 ? c0 + (int64_t)g.nc[0] * c2 : c0 + (int64_t)g.nc[0] * c1);
+    return b.off[a][side] + tc * nf + tt;
+}
+
 // ---- multigrid hierarchy of the pressure operator ------------------------------
 constexpr int MG_MAXDEG = 16;     // largest Chebyshev degree
 // smoother step kinds of the fused level kernel
@@ -207,6 +228,16 @@ struct tbdg_ctx {
     double* s_pg = nullptr;
     double* s_p1 = nullptr;
     double* s_pv = nullptr;     // pressure interpolated to velocity nodes (Ns)
+    // Dirichlet data: slot 0 at the stage-1 time t^{n+gamma}, slot 1 at t^{n+1}
+    double* bnd_uD[2] = {nullptr, nullptr};
+    int64_t bnd_npts = 0;
+    int64_t bnd_off[3][2] = {{-1, -1}, {-1, -1}, {-1, -1}};
+    trbdg::Bnd bnd(int s) const {
+        trbdg::Bnd b{bnd_uD[s == 2 ? 1 : 0], {}};
+        for (int a = 0; a < 3; ++a)
+            for (int k = 0; k < 2; ++k) b.off[a][k] = bnd_off[a][k];
+        return b;
+    }
     trbdg::MGData* mg = nullptr;    // multigrid hierarchy (built on first use)
     trbdg::GuessState* gs = nullptr;   // initial-guess history and network
 
@@ -219,15 +250,16 @@ namespace trbdg {
 // ---- launchers implemented in kernels.hip -------------------------------------
 void launch_apply_pressure(const tbdg_ctx* c, double alpha, const double* p, double* y);
 void launch_diag_pressure(const tbdg_ctx* c, double alpha, double* d);
-void launch_apply_momentum(const tbdg_ctx* c, double mcoef, double theta, const double* w,
-                           const double* u, double* y);
-void launch_diag_momentum(const tbdg_ctx* c, double mcoef, double theta, const double* w,
-                          double* d);
+// momentum operator / diagonal of stage s (Dirichlet data of that stage)
+void launch_apply_momentum(const tbdg_ctx* c, int s, const double* w, const double* u, double* y);
+void launch_diag_momentum(const tbdg_ctx* c, int s, const double* w, double* d);
 // rhs = m M u_prev + sum_pairs [ -cd L0 u_i + ca A0(w_i) u_i ] + Gw p
 void launch_rhs_momentum(const tbdg_ctx* c, double mcoef, const double* u_prev,
                          const double* u1, const double* w1, double cd1, double ca1,
                          const double* u2, const double* w2, double cd2, double ca2,
                          const double* p, double* rhs);
+// rhs += Dirichlet-data terms of stage s on every boundary face (advector w)
+void launch_dirichlet_rhs(const tbdg_ctx* c, int s, const double* w, double* rhs);
 void launch_add_grad_p(const tbdg_ctx* c, const double* x, double a, const double* p, double* y);
 void launch_rhs_pressure(const tbdg_ctx* c, double alpha, double fcoef, const double* u_ss,
                          const double* p_prev, double* rhs);

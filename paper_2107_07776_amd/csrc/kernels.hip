@@ -244,6 +244,58 @@ __global__ __launch_bounds__(256) void k_rhs_momentum(
     }
 }
 
+// Dirichlet-data terms of the momentum functionals on the boundary faces
+// normal to direction a, per component c and face point (eq. rhs1 and its
+// stage-2 analogue with the stage's theta and data):
+//   -theta nu int u_D,c (n.grad v) + theta nu int 2 C u_D,c v
+//   - theta int u_D,c (w.n) v + theta int lambda u_D,c v,
+// lambda = max(|w.n|, |(2 u_D - w).n|).  One thread per (boundary cell of
+// the face, face point, component) handles both sides of its cell, so two
+// threads never add to the same entry; directions are separate launches.
+template <int DIM, int N>
+__global__ __launch_bounds__(256) void k_dirichlet_rhs(Geom g, Tables t, Bnd bd, int a, double tnu,
+                                                        double th, double two_c,
+                                                        const double* __restrict__ w,
+                                                        double* __restrict__ rhs, int64_t ncells_face) {
+    using Lay = Layout<DIM, N>;
+    constexpr int NB = Lay::NB, NF = Lay::NF;
+    const int64_t gid = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (gid >= ncells_face * NF * DIM) return;
+    const int c = (int)(gid % DIM);
+    const int tt = (int)((gid / DIM) % NF);
+    const int64_t tc = gid / (DIM * NF);
+    // coordinates of the boundary cell: tc enumerates the other directions
+    int64_t ci[3] = {0, 0, 0};
+    {
+        int64_t r = tc;
+        for (int b = 0; b < DIM; ++b) {
+            if (b == a) continue;
+            ci[b] = r % g.nc[b];
+            r /= g.nc[b];
+        }
+    }
+    const double inv_h = 1.0 / g.h[a];
+    const double wf = g.vol * inv_h * tang_weight<DIM, N>(t.Wu, tt);
+    for (int side = 0; side < 2; ++side) {
+        ci[a] = side ? g.nc[a] - 1 : 0;
+        const int64_t cell = ci[0] + (int64_t)g.nc[0] * (ci[1] + (int64_t)g.nc[1] * ci[2]);
+        const double* Ls = side ? t.L1u : t.L0u;
+        const double* dLs = side ? t.dL1u : t.dL0u;
+        const double sg = side ? 1.0 : -1.0;
+        double wa = 0.0;
+#pragma unroll
+        for (int m = 0; m < N; ++m) wa += Ls[m] * w[(cell * DIM + a) * NB + Lay::node(a, m, tt)];
+        const int64_t pt = bd.off[a][side] + tc * NF + tt;
+        const double uDa = bd.uD[pt * DIM + a], uDc = bd.uD[pt * DIM + c];
+        const double lam = fmax(fabs(wa), fabs(2.0 * uDa - wa));
+        const double cv = tnu * two_c - th * sg * wa + th * lam;    // multiplies v on the face
+        const double cg = -tnu * sg * inv_h;                        // multiplies l_m' at the face
+#pragma unroll
+        for (int m = 0; m < N; ++m)
+            rhs[(cell * DIM + c) * NB + Lay::node(a, m, tt)] += wf * uDc * (cv * Ls[m] + cg * dLs[m]);
+    }
+}
+
 template <int DIM, int N>
 __global__ __launch_bounds__(256) void k_interp_p(Tables t, const double* __restrict__ p,
                                                    double* __restrict__ pv, int64_t Nc) {
@@ -429,6 +481,25 @@ void launch_rhs_momentum(const tbdg_ctx* c, double mcoef, const double* u_prev,
     TBDG_DISPATCH(c, L_);
 #undef L_
     TBDG_HIP(hipGetLastError());
+}
+
+void launch_dirichlet_rhs(const tbdg_ctx* c, int s, const double* w, double* rhs) {
+    const Bnd bd = c->bnd(s);
+    for (int a = 0; a < c->dim; ++a) {
+        if (bd.off[a][0] < 0) continue;
+        const int64_t ncf = c->Nc / c->geom.nc[a];
+        const double two_c = 2.0 * c->cr_u / c->geom.h[a];
+#define L_(D, N)                                                                          \
+        {                                                                                 \
+            using Lay = Layout<D, N>;                                                     \
+            hipLaunchKernelGGL((k_dirichlet_rhs<D, N>), dim3(nblocks(ncf * Lay::NF * D, 256)), \
+                               dim3(256), 0, c->stream, c->geom, c->tab, bd, a,           \
+                               c->theta[s] * c->nu, c->theta[s], two_c, w, rhs, ncf);     \
+        }
+        TBDG_DISPATCH(c, L_);
+#undef L_
+        TBDG_HIP(hipGetLastError());
+    }
 }
 
 void launch_add_grad_p(const tbdg_ctx* c, const double* x, double a, const double* p, double* y) {

@@ -105,7 +105,7 @@ __global__ __launch_bounds__(256) void k_momentum_line(Geom g, LineGeom lg, Line
                                                         double mc, double tnu, double th,
                                                         const double* __restrict__ w,
                                                         const double* __restrict__ u,
-                                                        double* __restrict__ y, int Nc) {
+                                                        double* __restrict__ y, int Nc, Bnd bd) {
     using L = Lay<DIM, N>;
     constexpr int NB = L::NB, CPB = L::CPB;
     __shared__ double s_w[DIM][CPB * NB];
@@ -171,15 +171,25 @@ __global__ __launch_bounds__(256) void k_momentum_line(Geom g, LineGeom lg, Line
         const double sd = tnu * lg.sdiff[a] * wt;
         const double sv = th * lg.sadv[a] * wt;
         if (DIAG) {
+            // Dirichlet faces (no neighbour): the self term once more, and
+            // lambda u v with lambda from the mirrored state 2 u_D - w
             double s = mA[ia * N + ia];
-            if (lf < 0) s -= mF0[ia * N + ia];
-            if (rt < 0) s -= mF1[ia * N + ia];
+            if (lf < 0) s += mF0[ia * N + ia];
+            if (rt < 0) s += mF1[ia * N + ia];
             if (lf == cell) s += mLm[ia * N + ia];
             if (rt == cell) s += mRm[ia * N + ia];
             const double L0 = L0v[ia], L1 = L1v[ia];
             double v = -Wv[ia] * wline[ia] * D[ia * N + ia];
             if (lf >= 0) v += L0 * L0 * 0.5 * (-w0 + lam0);
             if (rt >= 0) v += L1 * L1 * 0.5 * (w1 + lam1);
+            if (lf < 0) {
+                const double uDa = bd.uD[bnd_point(bd, g, cell, a, 0, tt, L::NB / N) * DIM + a];
+                v += L0 * L0 * fmax(fabs(w0), fabs(2.0 * uDa - w0));
+            }
+            if (rt < 0) {
+                const double uDa = bd.uD[bnd_point(bd, g, cell, a, 1, tt, L::NB / N) * DIM + a];
+                v += L1 * L1 * fmax(fabs(w1), fabs(2.0 * uDa - w1));
+            }
             if (lf == cell) v += L0 * L1 * 0.5 * (-wl - lam0);
             if (rt == cell) v += L1 * L0 * 0.5 * (wr - lam1);
             acc[0] += sd * s + sv * v;
@@ -246,7 +256,7 @@ __global__ __launch_bounds__(256) void k_momentum_face(Geom g, LineGeom lg, Line
                                                         double Cr, double mc, double tnu, double th,
                                                         const double* __restrict__ w,
                                                         const double* __restrict__ u,
-                                                        double* __restrict__ y, int Nc) {
+                                                        double* __restrict__ y, int Nc, Bnd bd) {
     using L = Lay<DIM, N>;
     using F = FaceLay<DIM, N>;
     constexpr int NB = F::NB, NF = F::NF, CPB = F::CPB;
@@ -357,10 +367,15 @@ __global__ __launch_bounds__(256) void k_momentum_face(Geom g, LineGeom lg, Line
                 Y0 = 0.5 * vL;
                 fl = 0.5 * (-u0 * w0 - vL * wl) + 0.5 * lam * (u0 - vL);
             } else {
+                // Dirichlet face: SIP terms with twice the penalty (the self
+                // term once more) and the LF term lambda u v, lambda from the
+                // mirrored state 2 u_D - w
 #pragma unroll
                 for (int m = 0; m < N; ++m) q0 += t.dL0u[m] * uu[m];
-                X0 = -0.5 * q0 - Cr * u0;
-                Y0 = 0.5 * u0;
+                X0 = 0.5 * q0 + Cr * u0;
+                Y0 = -0.5 * u0;
+                const double uDa = bd.uD[bnd_point(bd, g, blk * CPB + lc2, a, 0, ln, NF) * DIM + a];
+                fl = fmax(fabs(w0), fabs(2.0 * uDa - w0)) * u0;
             }
             if (hr) {
                 const double vR = recr[2 * c], dR = recr[2 * c + 1], wr = recr[2 * DIM];
@@ -371,8 +386,10 @@ __global__ __launch_bounds__(256) void k_momentum_face(Geom g, LineGeom lg, Line
             } else {
 #pragma unroll
                 for (int m = 0; m < N; ++m) q1 += t.dL1u[m] * uu[m];
-                X1 = 0.5 * q1 - Cr * u1;
-                Y1 = 0.5 * u1;
+                X1 = -0.5 * q1 + Cr * u1;
+                Y1 = -0.5 * u1;
+                const double uDa = bd.uD[bnd_point(bd, g, blk * CPB + lc2, a, 1, ln, NF) * DIM + a];
+                fr = fmax(fabs(w1), fabs(2.0 * uDa - w1)) * u1;
             }
             const double wt = L::wtan(s_W, ln);
             const double sd = tnu * lg.sdiff[a] * wt;
@@ -687,8 +704,9 @@ int launch_fcg_apply(const tbdg_ctx* c, double alpha, const double* z, const dou
     return G;
 }
 
-void launch_apply_momentum(const tbdg_ctx* c, double mcoef, double theta, const double* w,
-                           const double* u, double* y) {
+void launch_apply_momentum(const tbdg_ctx* c, int st, const double* w, const double* u, double* y) {
+    const double mcoef = c->mcoef(st), theta = c->theta[st];
+    const Bnd bd = c->bnd(st);
 #define L_(D, N)                                                                           \
     {                                                                                      \
         using FL = FaceLay<D, N>;                                                          \
@@ -697,22 +715,23 @@ void launch_apply_momentum(const tbdg_ctx* c, double mcoef, double theta, const 
                               dim3(FL::THREADS), 0, c->stream, tl.start(), tl.stop(), 0,   \
                               c->geom, c->lgeom, c->line_u, c->tab, c->cr_u,               \
                               mcoef * c->geom.vol, theta * c->nu, theta, w, u, y,          \
-                              (int)c->Nc);                                                 \
+                              (int)c->Nc, bd);                                             \
     }
     TBDG_LINE_DISPATCH(c, L_);
 #undef L_
     TBDG_HIP(hipGetLastError());
 }
 
-void launch_diag_momentum(const tbdg_ctx* c, double mcoef, double theta, const double* w,
-                          double* d) {
+void launch_diag_momentum(const tbdg_ctx* c, int st, const double* w, double* d) {
+    const double mcoef = c->mcoef(st), theta = c->theta[st];
+    const Bnd bd = c->bnd(st);
 #define L_(D, N)                                                                           \
     {                                                                                      \
         using LL = Lay<D, N>;                                                              \
         hipLaunchKernelGGL((k_momentum_line<D, N, true>), dim3(nblk(c->Nc, LL::CPB)),      \
                            dim3(LL::THREADS), 0, c->stream, c->geom, c->lgeom, c->line_u,  \
                            c->tab, mcoef * c->geom.vol, theta * c->nu, theta, w, nullptr,  \
-                           d, (int)c->Nc);                                                 \
+                           d, (int)c->Nc, bd);                                             \
     }
     TBDG_LINE_DISPATCH(c, L_);
 #undef L_

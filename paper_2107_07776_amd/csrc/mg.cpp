@@ -321,12 +321,10 @@ void mg_free(tbdg_ctx* c) {
     c->mg = nullptr;
 }
 
-void mg_setup(tbdg_ctx* c, const tbdg_mg_desc* desc) {
-    mg_free(c);
-    for (int a = 0; a < c->dim; ++a)
-        if (!c->periodic_flags[a]) throw Error(TBDG_EUNSUPPORTED, "multigrid is built for periodic boxes");
-    c->mg = new MGData();
-    MGData& M = *c->mg;
+namespace {
+
+// Builds the whole hierarchy into M (allocations recorded in M.allocs).
+void mg_build(tbdg_ctx* c, MGData& M, const tbdg_mg_desc* desc) {
     M.coarse_cells = c->dim == 3 ? 64 : 16;
     if (desc) {
         if (desc->degree) M.degree = desc->degree;
@@ -436,6 +434,24 @@ void mg_setup(tbdg_ctx* c, const tbdg_mg_desc* desc) {
                                 c->stream));
         TBDG_HIP(hipStreamSynchronize(c->stream));
     }
+}
+
+}  // namespace
+
+// The context sees the hierarchy only once it is complete: a failed set-up
+// (too few levels, a coarse matrix that is not SPD, an allocation) leaves no
+// partial state behind that a later solve could use.
+void mg_setup(tbdg_ctx* c, const tbdg_mg_desc* desc) {
+    mg_free(c);
+    MGData* M = new MGData();
+    try {
+        mg_build(c, *M, desc);
+    } catch (...) {
+        for (void* p : M->allocs) (void)hipFree(p);
+        delete M;
+        throw;
+    }
+    c->mg = M;
 }
 
 void mg_apply(tbdg_ctx* c, int s, int precision, const double* r, double* z) {

@@ -35,9 +35,9 @@ double norm2(tbdg_ctx* c, int64_t n, const double* x) {
 
 struct MomentumOp {
     tbdg_ctx* c;
-    double m, th;
+    int s;
     const double* w;
-    void operator()(const double* x, double* y) const { launch_apply_momentum(c, m, th, w, x, y); }
+    void operator()(const double* x, double* y) const { launch_apply_momentum(c, s, w, x, y); }
 };
 
 }  // namespace
@@ -47,8 +47,8 @@ tbdg_status solve_momentum(tbdg_ctx* c, int s, const double* w, const double* b,
                            const tbdg_solver_opts& o, tbdg_solve_info* info) {
     const int64_t n = c->Nu;
     const int m = std::min(o.restart > 0 ? o.restart : 30, c->gm_m);
-    MomentumOp A{c, c->mcoef(s), c->theta[s], w};
-    launch_diag_momentum(c, c->mcoef(s), c->theta[s], w, c->diag_u);
+    MomentumOp A{c, s, w};
+    launch_diag_momentum(c, s, w, c->diag_u);
     vec_recip(c->stream, c->Ns, c->diag_u, c->invd_u);
     const double bnorm = norm2(c, n, b);
     tbdg_solve_info inf{0, 0.0, 0.0, 0};
@@ -295,6 +295,7 @@ void rhs_momentum(tbdg_ctx* c, int s, const double* u_n, const double* u_g, cons
         launch_rhs_momentum(c, c->mcoef(2), u_g, u_g, u_g, c->a32 * c->nu, c->a32, u_n, u_n,
                             c->a31 * c->nu, c->a31, p, rhs);
     }
+    if (c->bnd_npts > 0) launch_dirichlet_rhs(c, s, w, rhs);
 }
 
 void rhs_pressure(tbdg_ctx* c, int s, const double* u_ss, const double* p_prev, double* rhs) {

@@ -29,7 +29,7 @@ EXPORTED = [
     "tbdg_net_get_grads", "tbdg_net_zero_grad", "tbdg_net_forward", "tbdg_net_backward",
     "tbdg_net_mse", "tbdg_net_adam_step", "tbdg_set_guess_net", "tbdg_guess_reset",
     "tbdg_guess_record", "tbdg_guess_recorded", "tbdg_guess_features", "tbdg_guess_inject",
-    "tbdg_guess_last",
+    "tbdg_guess_last", "tbdg_face_qpoints", "tbdg_set_dirichlet",
 ]
 
 GUESS = {"given": 0, "previous": 1, "learned": 2}
@@ -135,6 +135,8 @@ def load_library(path=LIB_PATH):
         "tbdg_guess_record": ([vp, vp, i], i),
         "tbdg_guess_recorded": ([vp, P(i)], i),
         "tbdg_guess_last": ([vp, P(d), P(d)], i),
+        "tbdg_face_qpoints": ([vp, P(i64), vp], i),
+        "tbdg_set_dirichlet": ([vp, i, vp], i),
         "tbdg_guess_features": ([vp, i, vp, vp, vp, d, vp, d, vp, P(d)], i),
         "tbdg_guess_inject": ([vp, i, vp, vp, vp, d, vp], i),
     }
@@ -228,6 +230,25 @@ class Context:
         out = torch.empty(self.N_c * nb * self.dim, dtype=torch.float64, device=self.device)
         self._check(self.lib.tbdg_node_coords(self.h, field, _ptr(out)))
         return out.view(-1, self.dim)
+
+    def face_qpoints(self):
+        """Boundary face points [n][dim] (float64, device), empty if periodic."""
+        n = ctypes.c_int64()
+        self._check(self.lib.tbdg_face_qpoints(self.h, ctypes.byref(n), None))
+        out = torch.empty((n.value, self.dim), dtype=torch.float64, device=self.device)
+        if n.value:
+            self._check(self.lib.tbdg_face_qpoints(self.h, ctypes.byref(n), _ptr(out)))
+        return out
+
+    def set_dirichlet(self, slot, uD):
+        """Dirichlet data [n][dim] at the boundary points; slot 0: stage-1 time
+        t^n + gamma dt, slot 1: t^{n+1}."""
+        n = self.face_qpoints().shape[0] if not hasattr(self, "_nbp") else self._nbp
+        self._nbp = n
+        if uD.dtype != torch.float64 or uD.device.type != "cuda" or not uD.is_contiguous() \
+                or uD.numel() != n * self.dim:
+            raise ValueError(f"uD must be a contiguous float64 CUDA tensor of {n} x {self.dim}")
+        self._check(self.lib.tbdg_set_dirichlet(self.h, int(slot), _ptr(uD)))
 
     def extrapolate(self, stage, u_new, u_old, out=None):
         out = self.empty_u() if out is None else self._vec(out, self.N_u, "out")

@@ -123,6 +123,14 @@ def test_single_level_mesh_is_rejected():
     with pytest.raises(TrbdgError) as e:
         ctx.mg_setup()
     assert e.value.status == -7
+    # a failed set-up leaves nothing behind: every later multigrid solve on
+    # the same context fails the same way instead of running on a partial
+    # hierarchy
+    b = torch.ones(ctx.N_p, dtype=torch.float64, device="cuda")
+    for _ in range(2):
+        x = torch.zeros_like(b)
+        info = ctx.solve_pressure(1, b, x, tol=1e-8, maxiter=10, precond="mg_fp32", check=False)
+        assert info["status"] == -7
     ctx.close()
 
 
