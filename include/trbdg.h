@@ -351,6 +351,11 @@ typedef struct {
     int64_t n;
 } tbdg_state;
 
+/* Momentum initial guesses in tbdg_step (mom->guess): TBDG_GUESS_GIVEN
+ * starts stage 1 from u^n and stage 2 from u^{n+gamma}; TBDG_GUESS_PREVIOUS
+ * from their linear extrapolations to the stage times,
+ * (1 + e) u^n - e u^{n-1+gamma} with e = gamma / (1 - gamma), and the
+ * stage-2 advector.                                                          */
 /* One TR-BDF2 projection step (Sec. 2 and the algebraic form of Sec. 3):
  * per stage, extrapolate, momentum right-hand side, GMRES, projection,
  * Helmholtz right-hand side, CG, velocity correction.  info[0..3] receive
@@ -359,6 +364,22 @@ typedef struct {
  * first failing status is returned.                                        */
 TBDG_API tbdg_status tbdg_step(tbdg_ctx* ctx, tbdg_state* state, const tbdg_solver_opts* mom,
                       const tbdg_solver_opts* prs, tbdg_solve_info info[4]);
+
+/* Fully nonlinear momentum predictors (Sec. 2: the advecting velocity of
+ * each stage may be the stage unknown itself, found by fixed-point
+ * iteration).  max_solves = 1 (the default) is the linearised scheme with
+ * the extrapolated advecting velocity.  With max_solves > 1 every tbdg_step
+ * stage does up to max_solves momentum solves: the first advected by the
+ * extrapolated velocity, each later one by the previous solution (which is
+ * also its initial guess); the stage-1 explicit advection is advected by
+ * u^n.  A stage stops early once ||u*_j - u*_{j-1}||_2 <= tol ||u*_j||_2
+ * (tol = 0: always max_solves).  The momentum info of tbdg_step then sums
+ * the GMRES iterations of all solves of the stage.  Errors: TBDG_EINVAL
+ * for max_solves < 1 or tol < 0 or not finite.                             */
+TBDG_API tbdg_status tbdg_set_nonlinear(tbdg_ctx* ctx, int max_solves, double tol);
+/* solves[0..1] (host): momentum solves of stages 1 and 2 in the last
+ * tbdg_step (also of a failed one, up to the failing solve).               */
+TBDG_API tbdg_status tbdg_nonlinear_solves(tbdg_ctx* ctx, int* solves);
 
 /* Measurement hook.  While enabled, every launch of the pressure operator
  * kernel (which = 0: tbdg_apply_pressure and the CG iterations) and of the

@@ -29,6 +29,17 @@ Readings
   mirroring stage 2.  Stage-2 Helmholtz "given p^n" is read as p^{n+gamma}.
 * First step: the history level u^{-1+gamma} is supplied by the caller
   (the exact solution at t = -(1-gamma) dt when one is known).
+
+Fully nonlinear stages
+----------------------
+Sec. 2 also allows the advecting velocity of each momentum predictor to be
+the unknown itself, found by fixed-point iteration (stage 1: the implicit
+advection is advected by u^{n+gamma,*} and the explicit one by u^n).  With
+``nonlinear_iters`` = m > 1 a stage does up to m momentum solves: the first
+advected by the extrapolated velocity, each later one by the previous
+solution, stopping early once ||u*_j - u*_{j-1}||_2 <= nonlinear_tol ||u*_j||_2;
+the stage-1 explicit advection then uses u^n throughout.  m = 1 is the
+linearised scheme above.
 """
 import math
 
@@ -72,7 +83,8 @@ class TRBDF2:
     (unused on fully periodic meshes).
     """
 
-    def __init__(self, disc, dt, gamma=None, uD=None, extrap1="stage", rows=None):
+    def __init__(self, disc, dt, gamma=None, uD=None, extrap1="stage", rows=None,
+                 nonlinear_iters=1, nonlinear_tol=0.0):
         """``rows``: optional list of cells; when given, every operator is
         assembled only for the test functions of those cells (results are
         valid on those cells' entries only), which keeps large meshes cheap
@@ -83,6 +95,10 @@ class TRBDF2:
         self.cst = trbdf2_constants(gamma)
         self.uD = uD
         self.extrap1 = extrap1
+        if int(nonlinear_iters) < 1:
+            raise ValueError("nonlinear_iters must be >= 1")
+        self.nonlinear_iters = int(nonlinear_iters)
+        self.nonlinear_tol = float(nonlinear_tol)
         g = self.cst["gamma"]
         self.beta = {1: g, 2: 1.0 - g}
         self.theta = {1: 0.5, 2: self.cst["a33"]}
@@ -158,10 +174,11 @@ class TRBDF2:
         e = self.cst["extrap1"] if s == 1 else self.cst["extrap2"]
         return e[0] * u_new + e[1] * u_old
 
-    def rhs_momentum(self, s, u_n, u_g, w, p_prev, t_stage=None):
+    def rhs_momentum(self, s, u_n, u_g, w, p_prev, t_stage=None, w_explicit=None):
         """m_s M u_prev + F_u^(s) (eq. rhs1 and its stage-2 analogue).
 
-        Stage 1: u_prev = u_n, advecting field w.  Stage 2: u_prev = u_g
+        Stage 1: u_prev = u_n, advecting field w (``w_explicit``, when given,
+        replaces it in the explicit advection only).  Stage 2: u_prev = u_g
         (= u^{n+gamma}); the explicit advection uses u_g (x) u_g with a32 and
         u_n (x) u_n with a31; w enters only through the boundary terms.
         """
@@ -169,7 +186,7 @@ class TRBDF2:
         nu = d.nu
         if s == 1:
             th = self.theta[1]
-            A0 = d.explicit_advection(w, self.rows)
+            A0 = d.explicit_advection(w if w_explicit is None else w_explicit, self.rows)
             F = (-th * nu * self.per_component(self.L0, u_n)
                  + th * self.per_component(A0, u_n))
             u_prev = u_n
@@ -218,15 +235,29 @@ class TRBDF2:
             w = self.extrapolate(2, u_g, u_n)
             t_stage = t + self.dt
             u_prev = u_g
-        rhs = self.rhs_momentum(s, u_n, u_g, w, p_prev, t_stage)
-        u_star = self.solve_momentum(s, w, rhs, t_stage)
+        solves = 1
+        if self.nonlinear_iters == 1:
+            rhs = self.rhs_momentum(s, u_n, u_g, w, p_prev, t_stage)
+            u_star = self.solve_momentum(s, w, rhs, t_stage)
+        else:
+            w_ex = u_n if s == 1 else None
+            rhs = self.rhs_momentum(s, u_n, u_g, w, p_prev, t_stage, w_explicit=w_ex)
+            u_star = self.solve_momentum(s, w, rhs, t_stage)
+            while solves < self.nonlinear_iters:
+                w = u_star
+                rhs = self.rhs_momentum(s, u_n, u_g, w, p_prev, t_stage, w_explicit=w_ex)
+                u_star = self.solve_momentum(s, w, rhs, t_stage)
+                solves += 1
+                change = np.linalg.norm(u_star - w)
+                if change <= self.nonlinear_tol * np.linalg.norm(u_star):
+                    break
         bdt = self.beta[s] * self.dt
         u_ss = u_star + bdt * self.grad_p(p_prev)
         b = self.rhs_pressure(s, u_ss, p_prev)
         p_new = self.solve_pressure(s, b)
         u_new = u_ss - bdt * self.grad_p(p_new)
         return dict(w=w, rhs=rhs, u_star=u_star, u_ss=u_ss, b=b,
-                    p=p_new, u=u_new, u_prev=u_prev)
+                    p=p_new, u=u_new, u_prev=u_prev, solves=solves)
 
     def step(self, u_n, u_hist, p_n, t):
         """Advance (u^n, u^{n-1+gamma}, p^n) at time t by dt.

@@ -490,9 +490,31 @@ tbdg_status tbdg_step(tbdg_ctx* c, tbdg_state* state, const tbdg_solver_opts* mo
         const tbdg_solver_opts po = defaults(prs);
         if (mo.precond != TBDG_PRECOND_JACOBI)
             throw Error(TBDG_EUNSUPPORTED, "the momentum solve has only the Jacobi preconditioner");
+        require(mo.guess != TBDG_GUESS_LEARNED, "the momentum solve has no learned guess");
         const tbdg_status s = trbdg::step(c, state, mo, po, info);
         if (s != TBDG_OK && c->last_error.empty()) c->last_error = "a stage solve failed";
         return s;
+    });
+}
+
+tbdg_status tbdg_set_nonlinear(tbdg_ctx* c, int max_solves, double tol) {
+    if (!c) return TBDG_EINVAL;
+    return guarded(c, [&]() {
+        require(max_solves >= 1, "max_solves must be >= 1");
+        require(std::isfinite(tol) && tol >= 0.0, "tol must be finite and >= 0");
+        c->nl_max = max_solves;
+        c->nl_tol = tol;
+        return TBDG_OK;
+    });
+}
+
+tbdg_status tbdg_nonlinear_solves(tbdg_ctx* c, int* solves) {
+    if (!c) return TBDG_EINVAL;
+    return guarded(c, [&]() {
+        require(solves != nullptr, "null output");
+        solves[0] = c->nl_solves[0];
+        solves[1] = c->nl_solves[1];
+        return TBDG_OK;
     });
 }
 

@@ -238,6 +238,11 @@ struct tbdg_ctx {
             for (int k = 0; k < 2; ++k) b.off[a][k] = bnd_off[a][k];
         return b;
     }
+    // fully nonlinear stages: at most nl_max momentum solves per stage, early
+    // stop on the relative change nl_tol; solves used by the last step
+    int nl_max = 1;
+    double nl_tol = 0.0;
+    int nl_solves[2] = {0, 0};
     trbdg::MGData* mg = nullptr;    // multigrid hierarchy (built on first use)
     trbdg::GuessState* gs = nullptr;   // initial-guess history and network
 

@@ -285,22 +285,79 @@ void extrapolate(tbdg_ctx* c, int s, const double* u_new, const double* u_old, d
     vec_axpby(c->stream, c->Nu, e0, u_new, e1, u_old, w);
 }
 
-void rhs_momentum(tbdg_ctx* c, int s, const double* u_n, const double* u_g, const double* w,
-                  const double* p, double* rhs) {
+// stage-s momentum right-hand side without the boundary terms of the
+// advector; wx advects the stage-1 explicit advection
+void rhs_momentum_base(tbdg_ctx* c, int s, const double* u_n, const double* u_g, const double* wx,
+                       const double* p, double* rhs) {
     if (s == 1) {
         const double th = c->theta[1];
-        launch_rhs_momentum(c, c->mcoef(1), u_n, u_n, w, th * c->nu, th, nullptr, nullptr, 0.0,
+        launch_rhs_momentum(c, c->mcoef(1), u_n, u_n, wx, th * c->nu, th, nullptr, nullptr, 0.0,
                             0.0, p, rhs);
     } else {
         launch_rhs_momentum(c, c->mcoef(2), u_g, u_g, u_g, c->a32 * c->nu, c->a32, u_n, u_n,
                             c->a31 * c->nu, c->a31, p, rhs);
     }
+}
+
+void rhs_momentum(tbdg_ctx* c, int s, const double* u_n, const double* u_g, const double* w,
+                  const double* p, double* rhs) {
+    rhs_momentum_base(c, s, u_n, u_g, w, p, rhs);
     if (c->bnd_npts > 0) launch_dirichlet_rhs(c, s, w, rhs);
 }
 
 void rhs_pressure(tbdg_ctx* c, int s, const double* u_ss, const double* p_prev, double* rhs) {
     launch_rhs_pressure(c, c->alpha(s), 1.0 / (c->beta[s] * c->dt), u_ss, p_prev, rhs);
 }
+
+namespace {
+
+// Momentum predictor of stage s into c->s_ustar, which holds the initial
+// guess; c->s_w holds the extrapolated advector.  With c->nl_max > 1 the
+// fully nonlinear form of Sec. 2: the stage-1 explicit advection is advected
+// by u^n, and every solve after the first is advected by the previous
+// solution, until the relative change drops to c->nl_tol or c->nl_max
+// solves are done.  info sums the GMRES iterations of all solves.
+tbdg_status momentum_stage(tbdg_ctx* c, int s, const double* u_n, const double* u_g,
+                           const double* p, const tbdg_solver_opts& mo, tbdg_solve_info* info) {
+    c->nl_solves[s - 1] = 1;
+    if (c->nl_max <= 1) {
+        rhs_momentum(c, s, u_n, u_g, c->s_w, p, c->s_rhs);
+        return solve_momentum(c, s, c->s_w, c->s_rhs, c->s_ustar, mo, info);
+    }
+    const int64_t Nu = c->Nu;
+    hipStream_t st = c->stream;
+    const bool bnd = c->bnd_npts > 0;
+    rhs_momentum_base(c, s, u_n, u_g, u_n, p, c->s_rhs);
+    tbdg_solve_info acc{0, 0.0, 0.0, 0}, one{0, 0.0, 0.0, 0};
+    tbdg_status rc = TBDG_OK;
+    for (int solves = 1;; ++solves) {
+        const double* b = c->s_rhs;
+        if (bnd) {
+            // s_u1 is free until the end of stage 2
+            TBDG_HIP(hipMemcpyAsync(c->s_u1, c->s_rhs, sizeof(double) * Nu, hipMemcpyDeviceToDevice,
+                                    st));
+            launch_dirichlet_rhs(c, s, c->s_w, c->s_u1);
+            b = c->s_u1;
+        }
+        rc = solve_momentum(c, s, c->s_w, b, c->s_ustar, mo, &one);
+        if (solves == 1) acc.res0 = one.res0;
+        acc.iters += one.iters;
+        acc.res_final = one.res_final;
+        c->nl_solves[s - 1] = solves;
+        if (rc != TBDG_OK) break;
+        if (solves >= 2 && c->nl_tol > 0.0) {
+            vec_axpby(st, Nu, 1.0, c->s_ustar, -1.0, c->s_w, c->s_u1);
+            const double dn = norm2(c, Nu, c->s_u1);
+            if (dn <= c->nl_tol * norm2(c, Nu, c->s_ustar)) break;
+        }
+        if (solves >= c->nl_max) break;
+        TBDG_HIP(hipMemcpyAsync(c->s_w, c->s_ustar, sizeof(double) * Nu, hipMemcpyDeviceToDevice, st));
+    }
+    if (info) *info = acc;
+    return rc;
+}
+
+}  // namespace
 
 tbdg_status step(tbdg_ctx* c, tbdg_state* S, const tbdg_solver_opts& mo,
                  const tbdg_solver_opts& po, tbdg_solve_info info[4]) {
@@ -311,9 +368,14 @@ tbdg_status step(tbdg_ctx* c, tbdg_state* S, const tbdg_solver_opts& mo,
     const size_t bu = sizeof(double) * Nu, bp = sizeof(double) * Np;
     // ---- stage 1 ----
     extrapolate(c, 1, S->u, S->u_hist, c->s_w);
-    rhs_momentum(c, 1, S->u, nullptr, c->s_w, S->p, c->s_rhs);
-    TBDG_HIP(hipMemcpyAsync(c->s_ustar, S->u, bu, hipMemcpyDeviceToDevice, st));
-    rc = solve_momentum(c, 1, c->s_w, c->s_rhs, c->s_ustar, mo, &loc[0]);
+    if (mo.guess == TBDG_GUESS_PREVIOUS) {
+        // linear extrapolation of (u^{n-1+gamma}, u^n) to t^n + gamma dt
+        const double e = c->gamma / (1.0 - c->gamma);
+        vec_axpby(st, Nu, 1.0 + e, S->u, -e, S->u_hist, c->s_ustar);
+    } else {
+        TBDG_HIP(hipMemcpyAsync(c->s_ustar, S->u, bu, hipMemcpyDeviceToDevice, st));
+    }
+    rc = momentum_stage(c, 1, S->u, nullptr, S->p, mo, &loc[0]);
     if (info) info[0] = loc[0];
     if (rc != TBDG_OK) {
         guess_reset(c);
@@ -334,9 +396,11 @@ tbdg_status step(tbdg_ctx* c, tbdg_state* S, const tbdg_solver_opts& mo,
     launch_add_grad_p(c, c->s_ustar, -b1, c->s_pg, c->s_ug);          // u^{n+gamma}
     // ---- stage 2 ----
     extrapolate(c, 2, c->s_ug, S->u, c->s_w);
-    rhs_momentum(c, 2, S->u, c->s_ug, c->s_w, c->s_pg, c->s_rhs);
-    TBDG_HIP(hipMemcpyAsync(c->s_ustar, c->s_ug, bu, hipMemcpyDeviceToDevice, st));
-    rc = solve_momentum(c, 2, c->s_w, c->s_rhs, c->s_ustar, mo, &loc[2]);
+    // stage-2 initial guess: u^{n+gamma}, or its linear extrapolation with u^n
+    // to t^{n+1}, which is the stage-2 advector
+    TBDG_HIP(hipMemcpyAsync(c->s_ustar, mo.guess == TBDG_GUESS_PREVIOUS ? c->s_w : c->s_ug, bu,
+                            hipMemcpyDeviceToDevice, st));
+    rc = momentum_stage(c, 2, S->u, c->s_ug, c->s_pg, mo, &loc[2]);
     if (info) info[2] = loc[2];
     if (rc != TBDG_OK) {
         guess_reset(c);

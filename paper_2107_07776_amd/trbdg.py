@@ -29,7 +29,8 @@ EXPORTED = [
     "tbdg_net_get_grads", "tbdg_net_zero_grad", "tbdg_net_forward", "tbdg_net_backward",
     "tbdg_net_mse", "tbdg_net_adam_step", "tbdg_set_guess_net", "tbdg_guess_reset",
     "tbdg_guess_record", "tbdg_guess_recorded", "tbdg_guess_features", "tbdg_guess_inject",
-    "tbdg_guess_last", "tbdg_face_qpoints", "tbdg_set_dirichlet",
+    "tbdg_guess_last", "tbdg_face_qpoints", "tbdg_set_dirichlet", "tbdg_set_nonlinear",
+    "tbdg_nonlinear_solves",
 ]
 
 GUESS = {"given": 0, "previous": 1, "learned": 2}
@@ -137,6 +138,8 @@ def load_library(path=LIB_PATH):
         "tbdg_guess_last": ([vp, P(d), P(d)], i),
         "tbdg_face_qpoints": ([vp, P(i64), vp], i),
         "tbdg_set_dirichlet": ([vp, i, vp], i),
+        "tbdg_set_nonlinear": ([vp, i, d], i),
+        "tbdg_nonlinear_solves": ([vp, P(i)], i),
         "tbdg_guess_features": ([vp, i, vp, vp, vp, d, vp, d, vp, P(d)], i),
         "tbdg_guess_inject": ([vp, i, vp, vp, vp, d, vp], i),
     }
@@ -325,20 +328,31 @@ class Context:
         return info.as_dict() | {"status": st}
 
     def step(self, u, u_hist, p, t=0.0, n=0, mom_tol=1e-8, prs_tol=1e-8, mom_maxiter=1000,
-             prs_maxiter=5000, restart=30, precond="jacobi", guess="given", check=True):
+             prs_maxiter=5000, restart=30, precond="jacobi", guess="given", mom_guess="given",
+             check=True):
         """One TR-BDF2 step in place on (u, u_hist, p); returns per-solve info.
         ``precond`` selects the pressure preconditioner, ``guess`` the initial
         guess of the pressure solves ("given": previous pressure, "previous":
         rescaled newest increment, "learned": the attached network)."""
         S = State(_ptr(self._vec(u, self.N_u, "u")), _ptr(self._vec(u_hist, self.N_u, "u_hist")),
                   _ptr(self._vec(p, self.N_p, "p")), float(t), int(n))
-        mo = solver_opts(mom_tol, mom_maxiter, restart)
+        mo = solver_opts(mom_tol, mom_maxiter, restart, guess=mom_guess)
         po = solver_opts(prs_tol, prs_maxiter, 0, precond, guess)
         infos = (SolveInfo * 4)()
         st = self.lib.tbdg_step(self.h, ctypes.byref(S), ctypes.byref(mo), ctypes.byref(po), infos)
         if check:
             self._check(st)
-        return [infos[i].as_dict() for i in range(4)], st
+        out = [infos[i].as_dict() for i in range(4)]
+        solves = (ctypes.c_int * 2)()
+        self._check(self.lib.tbdg_nonlinear_solves(self.h, solves))
+        out[0]["solves"], out[2]["solves"] = solves[0], solves[1]
+        return out, st
+
+    def set_nonlinear(self, max_solves=1, tol=0.0):
+        """Fully nonlinear momentum predictors in step(): up to ``max_solves``
+        fixed-point solves per stage, early stop at relative change ``tol``
+        (1 = the linearised scheme with the extrapolated advector)."""
+        self._check(self.lib.tbdg_set_nonlinear(self.h, int(max_solves), float(tol)))
 
     def mg_setup(self, degree=0, lanczos_steps=0, range_=0.0, safety=0.0, coarse_cells=0,
                  max_coarse_dofs=0):

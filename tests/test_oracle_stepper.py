@@ -107,3 +107,74 @@ def test_taylor_green_space_convergence_and_mean():
         for before, after in means:
             assert abs(after - before) < 1e-12
     assert errs[1] < 5e-3 and errs[0] / errs[1] > 6.0, errs
+
+
+def _paper_tg(N, k, dt, m, T=3.2, Re=100.0):
+    """The 2D Taylor-Green convergence case of Sec. 4 (eq. greentaylor on
+    (0, 2 pi)^2, Re = 100, c = 1e3, t = 0 .. 3.2) with fully nonlinear stages
+    of at most m solves; returns the relative L2 errors of u and p (mean
+    removed) at T."""
+    mesh = BoxMesh(2, (N, N), (0.0, 0.0), (2 * math.pi,) * 2, (True, True))
+    d = Discretization(mesh, k, nu=1.0 / Re, c=1.0e3)
+    ts = TRBDF2(d, dt, nonlinear_iters=m)
+    g = ts.cst["gamma"]
+    xu, xp = d.node_coords("u"), d.node_coords("p")
+    U = lambda t: synthetic.nodal_velocity(synthetic.taylor_green_2d(xu, t, Re)[0], 2, d.nbu)
+    u, hist, p = U(0.0), U(-(1 - g) * dt), synthetic.taylor_green_2d(xp, 0.0, Re)[1]
+    t = 0.0
+    for _ in range(int(round(T / dt))):
+        u, hist, p, st = ts.step(u, hist, p, t)
+        assert st[0]["solves"] == m and st[1]["solves"] == m
+        t += dt
+    eu, ru = d.l2_error(u, lambda x: synthetic.taylor_green_2d(x, t, Re)[0])
+    ep, rp = d.l2_error(p, lambda x: synthetic.taylor_green_2d(x, t, Re)[1], "p", remove_mean=True)
+    return eu / ru, ep / rp
+
+
+def test_paper_taylor_green_table_coarsest():
+    """Coarsest row of the paper's Q2-Q1 Taylor-Green table at C = 1.63
+    (8 x 8 cells, dt = 0.64): printed relative L2 errors 0.38 (velocity) and
+    0.43 (pressure).  Reproduced to 25 % with three fixed-point solves per
+    stage; the readings of the quadrature and of the projection differ from
+    the paper's implementation, so the digits are not expected to agree."""
+    eu, ep = _paper_tg(8, 2, 0.64, 3)
+    assert abs(eu / 0.38 - 1.0) < 0.25, eu
+    assert abs(ep / 0.43 - 1.0) < 0.25, ep
+
+
+@pytest.mark.slow
+def test_paper_taylor_green_table_second_row_velocity():
+    """Second row (16 x 16, dt = 0.32): printed velocity error 0.095, i.e. a
+    rate near 2 from the first row.  The velocity is reproduced to 25 % and
+    the observed rate lies between 1.5 and 3."""
+    e8, _ = _paper_tg(8, 2, 0.64, 3)
+    e16, _ = _paper_tg(16, 2, 0.32, 3)
+    assert abs(e16 / 0.095 - 1.0) < 0.25, e16
+    assert 1.5 < math.log2(e8 / e16) < 3.0, (e8, e16)
+
+
+def test_nonlinear_stage_solves_the_nonlinear_equation():
+    """With enough fixed-point solves the stage-1 predictor satisfies the
+    trapezoidal stage equation of eq. first_stage with the advecting
+    velocity replaced by the unknown on the left and by u^n on the right:
+    [m M + (nu A + C(u*))/2] u* = m M u^n + (-nu A0 + A0_adv(u^n)) u^n / 2 + Gw p^n."""
+    mesh = BoxMesh(2, (4, 4), (0.0, 0.0), (1.0, 1.0), (True, True))
+    d = Discretization(mesh, 3, nu=0.01)
+    dt = 0.01
+    ts = TRBDF2(d, dt, nonlinear_iters=60, nonlinear_tol=1e-14)
+    g = ts.cst["gamma"]
+    xu, xp = d.node_coords("u"), d.node_coords("p")
+    u = synthetic.nodal_velocity(synthetic.taylor_green_2d_unit(xu, 0.0, 0.01)[0], 2, d.nbu)
+    hist = synthetic.nodal_velocity(synthetic.taylor_green_2d_unit(xu, -(1 - g) * dt, 0.01)[0], 2, d.nbu)
+    p = synthetic.taylor_green_2d_unit(xp, 0.0, 0.01)[1]
+    st1 = ts.stage(1, u, hist, None, p, 0.0)
+    assert st1["solves"] < 60
+    us = st1["u_star"]
+    lhs = (ts.per_component((1.0 / (g * dt)) * ts.M + 0.5 * (d.nu * ts.L + d.lf_advection(us)), us))
+    rhs = ((1.0 / (g * dt)) * (ts.Mv @ u) - 0.5 * d.nu * ts.per_component(ts.L0, u)
+           + 0.5 * ts.per_component(d.explicit_advection(u), u) + ts.Gw @ p)
+    assert np.linalg.norm(lhs - rhs) <= 1e-11 * np.linalg.norm(rhs)
+    # one solve is the linearised scheme
+    lin = TRBDF2(d, dt).stage(1, u, hist, None, p, 0.0)
+    one = TRBDF2(d, dt, nonlinear_iters=1).stage(1, u, hist, None, p, 0.0)
+    assert np.array_equal(lin["u"], one["u"]) and one["solves"] == 1
