@@ -223,6 +223,9 @@ def main():
     ap.add_argument("--restart", type=int, default=5, help="GMRES restart length of the timed solver")
     ap.add_argument("--mom-guess", default="previous", choices=["given", "previous"],
                     help="momentum initial guess of the timed solver")
+    ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
+                    help="before the run, copy a MIB-sized device buffer 5 times (a plain copy "
+                         "kernel of known size, the reference for hardware byte counters)")
     ap.add_argument("--nonlinear", type=int, default=0,
                     help="momentum solves per stage (fixed point; 0 = the workload's setting)")
     args = ap.parse_args()
@@ -236,6 +239,15 @@ def main():
 
     from paper_2107_07776_amd import Context
 
+    if args.copy_calibration > 0:
+        n = args.copy_calibration * (1 << 20) // 8
+        src = torch.ones(n, dtype=torch.float64, device="cuda")
+        dst = torch.empty_like(src)
+        for _ in range(5):
+            dst.copy_(src)
+        torch.cuda.synchronize()
+        log(f"[bench] copied {args.copy_calibration} MiB five times")
+        del src, dst
     W = workload(args.workload)
     log(f"[bench] setting up {W['label']}")
     if args.nonlinear > 0:

@@ -81,11 +81,12 @@ __global__ __launch_bounds__(BS) void k_sub_combo(int64_t n, int k, const double
     }
 }
 
+// x += sum_j y_j V_j, with y_j scaled by gsc[j] when gsc is set
 __global__ __launch_bounds__(BS) void k_add_combo(int64_t n, int k, const double* V, int64_t ldv,
-                                                  const double* y, double* x) {
+                                                  const double* y, const double* gsc, double* x) {
     for (int64_t i = (int64_t)blockIdx.x * BS + threadIdx.x; i < n; i += (int64_t)gridDim.x * BS) {
         double s = 0.0;
-        for (int j = 0; j < k; ++j) s += y[j] * V[(int64_t)j * ldv + i];
+        for (int j = 0; j < k; ++j) s += (gsc ? y[j] * gsc[j] : y[j]) * V[(int64_t)j * ldv + i];
         x[i] += s;
     }
 }
@@ -243,16 +244,6 @@ __global__ __launch_bounds__(BS) void k_cg_start(int64_t n, const double* invd, 
     }
 }
 
-// GMRES: V_j *= s; z = V_j * invd (velocity layout, invd per scalar node)
-__global__ __launch_bounds__(BS) void k_scale_precond(int64_t n, int dim, int64_t nb, double s,
-                                                      double* v, const double* invd, double* z) {
-    for (int64_t i = (int64_t)blockIdx.x * BS + threadIdx.x; i < n; i += (int64_t)gridDim.x * BS) {
-        const double vi = v[i] * s;
-        v[i] = vi;
-        z[i] = vi * invd[diag_index(i, dim, nb)];
-    }
-}
-
 // GMRES multi-dot: partial[j*G + b] = V_j . w over block b's slice for the
 // 8 vectors of group blockIdx.y; group 0 also sums w.w into slot k.
 __global__ __launch_bounds__(BS) void k_mdot8(int64_t n, int k, const double* V, int64_t ldv,
@@ -279,18 +270,46 @@ __global__ __launch_bounds__(BS) void k_mdot8(int64_t n, int k, const double* V,
     }
 }
 
-// GMRES update with fused norm partials: w -= sum_j h_j V_j, partial |w|^2
+// GMRES update with fused norm partials: w -= sum_j h_j gsc_j V_j (the V_j
+// unnormalised, gsc_j their inverse norms), partial |w|^2
 __global__ __launch_bounds__(BS) void k_update_norm(int64_t n, int k, const double* V, int64_t ldv,
-                                                    const double* h, double* w, double* partial) {
+                                                    const double* h, const double* gsc, double* w,
+                                                    double* partial) {
+    __shared__ double s_cf[64];
+    for (int j = threadIdx.x; j < k; j += BS) s_cf[j] = h[j] * gsc[j];
+    __syncthreads();
     double nn = 0.0;
     for (int64_t i = (int64_t)blockIdx.x * BS + threadIdx.x; i < n; i += (int64_t)gridDim.x * BS) {
         double s = w[i];
-        for (int j = 0; j < k; ++j) s -= h[j] * V[(int64_t)j * ldv + i];
+        for (int j = 0; j < k; ++j) s -= s_cf[j] * V[(int64_t)j * ldv + i];
         w[i] = s;
         nn += s * s;
     }
     nn = block_sum(nn);
     if (threadIdx.x == 0) partial[blockIdx.x] = nn;
+}
+
+// out[j] = gsc[j] * sum_b partial[j * G + b] for j < k; out[k] = the plain
+// sum of slot k (w . w)
+__global__ __launch_bounds__(BS) void k_finish_gs(const double* partial, int G, int k,
+                                                  const double* gsc, double* out) {
+    const int j = blockIdx.x;
+    double acc = 0.0;
+    for (int b = threadIdx.x; b < G; b += BS) acc += partial[(int64_t)j * G + b];
+    acc = block_sum(acc);
+    if (threadIdx.x == 0) out[j] = j < k ? gsc[j] * acc : acc;
+}
+
+// nn = sum of the partials; inv = 1 / sqrt(nn) (1 when nn is not positive)
+__global__ __launch_bounds__(BS) void k_finish_inv_norm(const double* partial, int G, double* nn,
+                                                        double* inv) {
+    double acc = 0.0;
+    for (int b = threadIdx.x; b < G; b += BS) acc += partial[b];
+    acc = block_sum(acc);
+    if (threadIdx.x == 0) {
+        if (nn) nn[0] = acc;
+        inv[0] = acc > 0.0 ? 1.0 / sqrt(acc) : 1.0;
+    }
 }
 
 }  // namespace
@@ -348,8 +367,8 @@ void vec_sub_combo(hipStream_t s, int64_t n, int k, const double* V, int64_t ldv
 }
 
 void vec_add_combo(hipStream_t s, int64_t n, int k, const double* V, int64_t ldv,
-                   const double* y, double* x) {
-    hipLaunchKernelGGL(k_add_combo, dim3(grid_for(n)), dim3(BS), 0, s, n, k, V, ldv, y, x);
+                   const double* y, const double* gsc, double* x) {
+    hipLaunchKernelGGL(k_add_combo, dim3(grid_for(n)), dim3(BS), 0, s, n, k, V, ldv, y, gsc, x);
     TBDG_HIP(hipGetLastError());
 }
 
@@ -382,28 +401,40 @@ void cg_upd(tbdg_ctx* c, int64_t n, const double* invd, double* x, double* r, co
     TBDG_HIP(hipGetLastError());
 }
 
-void gm_scale_precond(tbdg_ctx* c, int64_t n, double s, double* v, const double* invd, double* z) {
-    hipLaunchKernelGGL(k_scale_precond, dim3(grid_for(n)), dim3(BS), 0, c->stream, n, c->dim,
-                       c->nbu, s, v, invd, z);
-    TBDG_HIP(hipGetLastError());
-}
-
 void gm_dots(tbdg_ctx* c, int64_t n, int k, const double* V, int64_t ldv, const double* w,
-             double* dev_out) {
+             const double* gsc, double* dev_out) {
     const int groups = (k + 7) / 8;
     const int G = reduce_grid(n, 4096);   // (k + 1) * G <= 62 * 4096 partial slots
     hipLaunchKernelGGL(k_mdot8, dim3(G, groups), dim3(BS), 0, c->stream, n, k, V, ldv, w,
                        c->red_part);
-    hipLaunchKernelGGL(k_finish, dim3(k + 1), dim3(BS), 0, c->stream, c->red_part, G, dev_out);
+    hipLaunchKernelGGL(k_finish_gs, dim3(k + 1), dim3(BS), 0, c->stream, c->red_part, G, k, gsc,
+                       dev_out);
+    TBDG_HIP(hipGetLastError());
+}
+
+void gm_finish_dots(tbdg_ctx* c, int G, int k, const double* part, const double* gsc,
+                    double* dev_out) {
+    hipLaunchKernelGGL(k_finish_gs, dim3(k + 1), dim3(BS), 0, c->stream, part, G, k, gsc, dev_out);
     TBDG_HIP(hipGetLastError());
 }
 
 void gm_update_norm(tbdg_ctx* c, int64_t n, int k, const double* V, int64_t ldv, const double* h,
-                    double* w, double* dev_out) {
+                    const double* gsc, double* w, double* dev_nn, double* gsc_next) {
     const int G = reduce_grid(n, 4096);
     double* part = c->red_part + 62 * 4096;
-    hipLaunchKernelGGL(k_update_norm, dim3(G), dim3(BS), 0, c->stream, n, k, V, ldv, h, w, part);
-    hipLaunchKernelGGL(k_finish, dim3(1), dim3(BS), 0, c->stream, part, G, dev_out);
+    hipLaunchKernelGGL(k_update_norm, dim3(G), dim3(BS), 0, c->stream, n, k, V, ldv, h, gsc, w,
+                       part);
+    hipLaunchKernelGGL(k_finish_inv_norm, dim3(1), dim3(BS), 0, c->stream, part, G, dev_nn,
+                       gsc_next);
+    TBDG_HIP(hipGetLastError());
+}
+
+void gm_norm_inv(tbdg_ctx* c, int64_t n, const double* v, double* dev_nn, double* inv) {
+    const int G = reduce_grid(n, 1024);
+    hipLaunchKernelGGL(k_dot_many, dim3(G, 1), dim3(BS), 0, c->stream, n, v, (int64_t)0, v,
+                       c->red_part);
+    hipLaunchKernelGGL(k_finish_inv_norm, dim3(1), dim3(BS), 0, c->stream, c->red_part, G, dev_nn,
+                       inv);
     TBDG_HIP(hipGetLastError());
 }
 

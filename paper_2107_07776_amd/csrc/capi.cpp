@@ -66,6 +66,8 @@ void free_all(tbdg_ctx* c) {
     for (auto& d : c->diag_p) dfree(d);
     dfree(c->diag_u);
     dfree(c->V);
+    dfree(c->gsc);
+    dfree(c->gm_part);
     dfree(c->gv);
     dfree(c->gz);
     dfree(c->cr);
@@ -194,6 +196,9 @@ tbdg_status tbdg_create(const tbdg_mesh_desc* mesh, const tbdg_disc_desc* disc, 
         c->V = dalloc((int64_t)(c->gm_m + 1) * c->Nu);
         c->gv = dalloc(c->Nu);
         c->gz = dalloc(c->Nu);
+        c->gsc = dalloc(GMRES_MAX + 2);
+        c->gm_part_len = (c->Nc + 1) * (trbdg::MOM_FUSE_MAX_DOTS + 1);
+        c->gm_part = dalloc(c->gm_part_len);
         c->cr = dalloc(c->Np);
         c->cp = dalloc(c->Np);
         c->cq = dalloc(c->Np);

@@ -88,6 +88,23 @@ struct Bnd {
     int64_t off[3][2];      // first point of face (a, side); -1 for periodic directions
 };
 
+// Optional work fused into the momentum operator kernel for GMRES.  With
+// invd set the operand is gsc[0] * invd (per scalar node) * u, the Jacobi-
+// preconditioned Krylov vector, and the output is shifted:
+// y = A (gsc[0] invd u) - shift gsc[0] u.  With ndot > 0 every block also
+// writes the partial sums of y . V_i (i < ndot, stride ldv) and y . y to
+// part[i * gridDim.x + block], i = 0 .. ndot.
+struct MomFuse {
+    const double* invd;
+    const double* gsc;
+    double shift;
+    const double* V;
+    int64_t ldv;
+    int ndot;
+    double* part;
+};
+constexpr int MOM_FUSE_MAX_DOTS = 8;
+
 // Point index of the face point `tt` of boundary face (a, side) of `cell`.
 __host__ __device__ inline int64_t bnd_point(const Bnd& b, const Geom& g, int64_t cell, int a,
                                              int side, int tt, int nf) {
@@ -203,6 +220,9 @@ struct tbdg_ctx {
     double* V = nullptr;        // (m+1) * Nu basis
     double* gv = nullptr;       // Nu scratch
     double* gz = nullptr;       // Nu scratch
+    double* gsc = nullptr;      // inverse norms of the Krylov vectors (gm_m + 1)
+    double* gm_part = nullptr;  // partials of the fused operator dots
+    int64_t gm_part_len = 0;
     // CG
     double* cr = nullptr;
     double* cp = nullptr;
@@ -257,6 +277,9 @@ void launch_apply_pressure(const tbdg_ctx* c, double alpha, const double* p, dou
 void launch_diag_pressure(const tbdg_ctx* c, double alpha, double* d);
 // momentum operator / diagonal of stage s (Dirichlet data of that stage)
 void launch_apply_momentum(const tbdg_ctx* c, int s, const double* w, const double* u, double* y);
+// the same with fused GMRES work; returns the grid size (partials per dot)
+int launch_apply_momentum_fused(const tbdg_ctx* c, int s, const double* w, const double* u,
+                                double* y, const MomFuse& fz);
 void launch_diag_momentum(const tbdg_ctx* c, int s, const double* w, double* d);
 // rhs = m M u_prev + sum_pairs [ -cd L0 u_i + ca A0(w_i) u_i ] + Gw p
 void launch_rhs_momentum(const tbdg_ctx* c, double mcoef, const double* u_prev,
@@ -303,7 +326,7 @@ void vec_sub_combo(hipStream_t s, int64_t n, int k, const double* V, int64_t ldv
                    const double* h, double* w);
 // x += V y (y on device)
 void vec_add_combo(hipStream_t s, int64_t n, int k, const double* V, int64_t ldv,
-                   const double* y, double* x);
+                   const double* y, const double* gsc, double* x);
 
 // ---- CG building blocks (blas.hip) --------------------------------------------
 // CG scalars on the device, sc[0] = rz, sc[1] = pAp, sc[2] = rr, sc[3] = rz_new,
@@ -327,11 +350,19 @@ void cg_alpha_finish(const tbdg_ctx* c, int G, const double* partial, double* sc
 int launch_cg_apply(const tbdg_ctx* c, double alpha, const double* r, const double* invd,
                     const double* p_old, double* p_new, double* q, double* sc, const double* up,
                     int Gu, int first, int slot, int slot_prev);
-void gm_scale_precond(tbdg_ctx* c, int64_t n, double s, double* v, const double* invd, double* z);
+// GMRES with unnormalised Krylov vectors V_i and their inverse norms gsc[i]
+// kept on the device.  gm_dots: dev_out[i] = gsc_i (V_i . w), i < k, and
+// dev_out[k] = w . w; gm_finish_dots: the same from the partials of the fused
+// operator kernel.  gm_update_norm: w -= sum_i dev h_i gsc_i V_i, dev_nn =
+// |w|^2, gsc_next = 1 / |w| (1 if zero).  gm_norm_inv: dev_nn = |v|^2 and
+// inv = 1 / |v|.
 void gm_dots(tbdg_ctx* c, int64_t n, int k, const double* V, int64_t ldv, const double* w,
-             double* dev_out);
+             const double* gsc, double* dev_out);
+void gm_finish_dots(tbdg_ctx* c, int G, int k, const double* part, const double* gsc,
+                    double* dev_out);
 void gm_update_norm(tbdg_ctx* c, int64_t n, int k, const double* V, int64_t ldv, const double* h,
-                    double* w, double* dev_out);
+                    const double* gsc, double* w, double* dev_nn, double* gsc_next);
+void gm_norm_inv(tbdg_ctx* c, int64_t n, const double* v, double* dev_nn, double* inv);
 // x += gz / diag (velocity layout)
 void vec_add_div_diag_u(hipStream_t s, int64_t n, int dim, int64_t nb, const double* gz,
                         const double* d, double* x);

@@ -256,19 +256,23 @@ __global__ __launch_bounds__(256) void k_momentum_face(Geom g, LineGeom lg, Line
                                                         double Cr, double mc, double tnu, double th,
                                                         const double* __restrict__ w,
                                                         const double* __restrict__ u,
-                                                        double* __restrict__ y, int Nc, Bnd bd) {
+                                                        double* __restrict__ y, int Nc, Bnd bd,
+                                                        MomFuse fz) {
     using L = Lay<DIM, N>;
     using F = FaceLay<DIM, N>;
     constexpr int NB = F::NB, NF = F::NF, CPB = F::CPB;
     constexpr int REC = 2 * DIM + 1;
-    constexpr int NFACE = 2 * DIM * NF;
+    const double us = fz.invd ? fz.gsc[0] : 1.0;
+    double uraw[DIM];
+#pragma unroll
+    for (int c = 0; c < DIM; ++c) uraw[c] = 0.0;
     // per-cell node arrays padded by one slot per x-row: lanes walking
     // x-lines then touch distinct LDS banks
     constexpr int NBP = NB + NB / N;
     __shared__ double s_w[DIM][CPB * NBP];
     __shared__ double s_u[DIM][CPB * NBP];
     __shared__ double s_y[DIM][CPB * NBP];
-    __shared__ double s_f[CPB * NFACE * REC];
+    __shared__ double s_f[CPB * 2 * NF * REC];   // face records of one direction
     __shared__ int s_nbr[CPB * 2 * DIM];
     __shared__ double s_W[N];
     const int tid = threadIdx.x;
@@ -284,6 +288,14 @@ __global__ __launch_bounds__(256) void k_momentum_face(Geom g, LineGeom lg, Line
             s_w[c][pi] = active ? w[((size_t)cell * DIM + c) * NB + nd] : 0.0;
             s_u[c][pi] = active ? u[((size_t)cell * DIM + c) * NB + nd] : 0.0;
         }
+        if (fz.invd && active) {
+            const double sc = us * fz.invd[(size_t)cell * NB + nd];
+#pragma unroll
+            for (int c = 0; c < DIM; ++c) {
+                uraw[c] = s_u[c][pi];
+                s_u[c][pi] *= sc;
+            }
+        }
     }
     if (lc < CPB && nd == 0) {
         // neighbour table of the cell, written with constant indices
@@ -295,38 +307,9 @@ __global__ __launch_bounds__(256) void k_momentum_face(Geom g, LineGeom lg, Line
         }
     }
     __syncthreads();
-    // phase 1
-    {
-        for (int it = nd; lc < CPB && it < NFACE; it += NB) {
-            const int face = it / NF, tt = it % NF;
-            const int a = face >> 1, s = face & 1;
-            double rec[REC];
-#pragma unroll
-            for (int q = 0; q < REC; ++q) rec[q] = 0.0;
-            const int nbr = s_nbr[lc * 2 * DIM + face];
-            if (nbr >= 0) {
-#pragma unroll
-                for (int m = 0; m < N; ++m) {
-                    const int idx = L::node(a, m, tt);
-                    const double lo = s ? t.L0u[m] : t.L1u[m];
-                    const double dlo = s ? t.dL0u[m] : t.dL1u[m];
-                    rec[2 * DIM] += lo * w[((size_t)nbr * DIM + a) * NB + idx];
-#pragma unroll
-                    for (int c = 0; c < DIM; ++c) {
-                        const double uv = u[((size_t)nbr * DIM + c) * NB + idx];
-                        rec[2 * c] += lo * uv;
-                        rec[2 * c + 1] += dlo * uv;
-                    }
-                }
-            }
-            double* dst = s_f + (lc * NFACE + it) * REC;
-#pragma unroll
-            for (int q = 0; q < REC; ++q) dst[q] = rec[q];
-        }
-    }
-    __syncthreads();
-    // phase 2: one pass per direction, items (cell, component, line); each
-    // node receives exactly one contribution per pass
+    // phase 2 (with phase 1 per direction): one pass per direction, items
+    // (cell, component, line); each node receives exactly one contribution
+    // per pass
     if (lc < CPB) {
         const double Wi0 = L::wnode(s_W, nd);
 #pragma unroll
@@ -334,6 +317,33 @@ __global__ __launch_bounds__(256) void k_momentum_face(Geom g, LineGeom lg, Line
     }
 #pragma unroll
     for (int a = 0; a < DIM; ++a) {
+        // phase 1 for direction a: the two faces of every own cell
+        for (int it = tid; it < CPB * 2 * NF; it += 256) {
+            const int lc1 = it / (2 * NF), s = (it / NF) & 1, tt = it % NF;
+            double rec[REC];
+#pragma unroll
+            for (int q = 0; q < REC; ++q) rec[q] = 0.0;
+            const int nbr = s_nbr[lc1 * 2 * DIM + 2 * a + s];
+            if (nbr >= 0) {
+#pragma unroll
+                for (int m = 0; m < N; ++m) {
+                    const int idx = L::node(a, m, tt);
+                    const double lo = s ? t.L0u[m] : t.L1u[m];
+                    const double dlo = s ? t.dL0u[m] : t.dL1u[m];
+                    rec[2 * DIM] += lo * w[((size_t)nbr * DIM + a) * NB + idx];
+                    const double sc = fz.invd ? us * fz.invd[(size_t)nbr * NB + idx] : 1.0;
+#pragma unroll
+                    for (int c = 0; c < DIM; ++c) {
+                        const double uv = sc * u[((size_t)nbr * DIM + c) * NB + idx];
+                        rec[2 * c] += lo * uv;
+                        rec[2 * c + 1] += dlo * uv;
+                    }
+                }
+            }
+            double* dst = s_f + it * REC;
+#pragma unroll
+            for (int q = 0; q < REC; ++q) dst[q] = rec[q];
+        }
         __syncthreads();
         constexpr int ITEMS = CPB * DIM * NF;
         for (int it = tid; it < ITEMS; it += 256) {
@@ -355,8 +365,8 @@ __global__ __launch_bounds__(256) void k_momentum_face(Geom g, LineGeom lg, Line
                 w0 += t.L0u[m] * wm;
                 w1 += t.L1u[m] * wm;
             }
-            const double* recl = s_f + (lc2 * NFACE + (2 * a) * NF + ln) * REC;
-            const double* recr = s_f + (lc2 * NFACE + (2 * a + 1) * NF + ln) * REC;
+            const double* recl = s_f + ((lc2 * 2) * NF + ln) * REC;
+            const double* recr = s_f + ((lc2 * 2 + 1) * NF + ln) * REC;
             const bool hl = s_nbr[lc2 * 2 * DIM + 2 * a] >= 0;
             const bool hr = s_nbr[lc2 * 2 * DIM + 2 * a + 1] >= 0;
             double X0, Y0, X1, Y1, fl = 0.0, fr = 0.0;
@@ -410,11 +420,43 @@ __global__ __launch_bounds__(256) void k_momentum_face(Geom g, LineGeom lg, Line
                 s_y[c][base + ni + ni / N] += out;
             }
         }
+        // the next direction's gathers overwrite s_f and its items touch
+        // other nodes of s_y
+        __syncthreads();
     }
-    __syncthreads();
-    if (!active) return;
+    double yv[DIM];
+    const double ysh = fz.invd ? fz.shift * us : 0.0;
 #pragma unroll
-    for (int c = 0; c < DIM; ++c) y[((size_t)cell * DIM + c) * NB + nd] = s_y[c][pi];
+    for (int c = 0; c < DIM; ++c) yv[c] = active ? s_y[c][pi] - ysh * uraw[c] : 0.0;
+    if (active) {
+#pragma unroll
+        for (int c = 0; c < DIM; ++c) y[((size_t)cell * DIM + c) * NB + nd] = yv[c];
+    }
+    if (fz.ndot > 0) {
+        // partial sums of y . V_i and y . y over the block's nodes: one wave
+        // sum per value, then one thread per value adds the four waves
+        __shared__ double s_red[MOM_FUSE_MAX_DOTS + 1][4];
+        const int lane = tid & 63, wv = tid >> 6;
+#pragma unroll
+        for (int i = 0; i <= MOM_FUSE_MAX_DOTS; ++i) {
+            if (i > fz.ndot) break;
+            double v = 0.0;
+            if (active) {
+#pragma unroll
+                for (int c = 0; c < DIM; ++c) {
+                    const size_t gi = ((size_t)cell * DIM + c) * NB + nd;
+                    v += yv[c] * (i < fz.ndot ? fz.V[(size_t)i * fz.ldv + gi] : yv[c]);
+                }
+            }
+            v = red::wave_sum(v);
+            if (lane == 0) s_red[i][wv] = v;
+        }
+        __syncthreads();
+        if (tid <= fz.ndot) {
+            const double r = s_red[tid][0] + s_red[tid][1] + s_red[tid][2] + s_red[tid][3];
+            fz.part[(size_t)tid * gridDim.x + blockIdx.x] = r;
+        }
+    }
 }
 
 // Pressure operator.  MODE 0: y = H p.  MODE 3: one fused CG step: every
@@ -704,22 +746,34 @@ int launch_fcg_apply(const tbdg_ctx* c, double alpha, const double* z, const dou
     return G;
 }
 
-void launch_apply_momentum(const tbdg_ctx* c, int st, const double* w, const double* u, double* y) {
+int launch_apply_momentum_fused(const tbdg_ctx* c, int st, const double* w, const double* u,
+                                double* y, const MomFuse& fz) {
     const double mcoef = c->mcoef(st), theta = c->theta[st];
     const Bnd bd = c->bnd(st);
+    if (fz.ndot < 0 || fz.ndot > MOM_FUSE_MAX_DOTS)
+        throw Error(TBDG_EINVAL, "fused dot count out of range");
+    int G = 0;
 #define L_(D, N)                                                                           \
     {                                                                                      \
         using FL = FaceLay<D, N>;                                                          \
+        G = (int)nblk(c->Nc, FL::CPB);                                                     \
+        if (fz.ndot > 0 && (int64_t)G * (fz.ndot + 1) > c->gm_part_len)                    \
+            throw Error(TBDG_EINVAL, "fused partial buffer too small");                    \
         TimedLaunch tl(c, 1);                                                              \
-        hipExtLaunchKernelGGL((k_momentum_face<D, N>), dim3(nblk(c->Nc, FL::CPB)),         \
-                              dim3(FL::THREADS), 0, c->stream, tl.start(), tl.stop(), 0,   \
-                              c->geom, c->lgeom, c->line_u, c->tab, c->cr_u,               \
-                              mcoef * c->geom.vol, theta * c->nu, theta, w, u, y,          \
-                              (int)c->Nc, bd);                                             \
+        hipExtLaunchKernelGGL((k_momentum_face<D, N>), dim3(G), dim3(FL::THREADS), 0,      \
+                              c->stream, tl.start(), tl.stop(), 0, c->geom, c->lgeom,      \
+                              c->line_u, c->tab, c->cr_u, mcoef * c->geom.vol,             \
+                              theta * c->nu, theta, w, u, y, (int)c->Nc, bd, fz);          \
     }
     TBDG_LINE_DISPATCH(c, L_);
 #undef L_
     TBDG_HIP(hipGetLastError());
+    return G;
+}
+
+void launch_apply_momentum(const tbdg_ctx* c, int st, const double* w, const double* u, double* y) {
+    launch_apply_momentum_fused(c, st, w, u, y,
+                                MomFuse{nullptr, nullptr, 0.0, nullptr, 0, 0, nullptr});
 }
 
 void launch_diag_momentum(const tbdg_ctx* c, int st, const double* w, double* d) {

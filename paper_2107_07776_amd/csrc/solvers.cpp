@@ -33,6 +33,10 @@ double norm2(tbdg_ctx* c, int64_t n, const double* x) {
     return std::sqrt(host_scalar(c, c->red_out + 63));
 }
 
+// shift of the Arnoldi operator in the momentum GMRES (the diagonal of the
+// Jacobi-scaled operator is one)
+constexpr double kArnoldiShift = 1.0;
+
 struct MomentumOp {
     tbdg_ctx* c;
     int s;
@@ -68,10 +72,13 @@ tbdg_status solve_momentum(tbdg_ctx* c, int s, const double* w, const double* b,
     std::vector<double> H((m + 1) * m), cs(m), sn(m), g(m + 1), y(m), h(m + 1);
     int total = 0;
     tbdg_status st = TBDG_ENOTCONV;
-    // initial residual r = b - A x into V_0
+    // initial residual r = b - A x into V_0; the Krylov vectors stay
+    // unnormalised, their inverse norms live in c->gsc on the device
+    double* gsc = c->gsc;
     A(x, c->gv);
     vec_axpby(c->stream, n, 1.0, b, -1.0, c->gv, V);
-    double beta = norm2(c, n, V);
+    gm_norm_inv(c, n, V, c->red_out + 63, gsc);
+    double beta = std::sqrt(host_scalar(c, c->red_out + 63));
     inf.res0 = beta / bnorm;
     while (true) {
         if (!std::isfinite(beta)) {
@@ -88,21 +95,31 @@ tbdg_status solve_momentum(tbdg_ctx* c, int s, const double* w, const double* b,
         }
         std::fill(g.begin(), g.end(), 0.0);
         g[0] = beta;
-        double pending = 1.0 / beta;   // V_j is stored unnormalised until its first use
         int j = 0;
         bool breakdown = false;
         for (; j < m && total < o.maxiter; ++j) {
             ++total;
             double* vj = V + (int64_t)j * ld;
             double* vn = V + (int64_t)(j + 1) * ld;
-            gm_scale_precond(c, n, pending, vj, c->invd_u, c->gz);
-            A(c->gz, vn);
+            // vn = (A D^{-1} - sigma) (gsc_j V_j): the Arnoldi process runs on
+            // the shifted operator, whose Krylov spaces are the same; with the
+            // Jacobi-scaled operator close to the identity the shift removes
+            // most of the cancellation, so one Gram-Schmidt pass is normally
+            // enough.  The first dots with V_0 .. V_j come out of the
+            // operator kernel when they fit.
+            const bool fused = j + 1 <= MOM_FUSE_MAX_DOTS;
+            const MomFuse fz{c->invd_u, gsc + j, kArnoldiShift, V, ld, fused ? j + 1 : 0,
+                             c->gm_part};
+            const int Gop = launch_apply_momentum_fused(c, s, w, vj, vn, fz);
             // classical Gram-Schmidt, repeated only when cancellation is large
             std::fill(h.begin(), h.end(), 0.0);
             double nn = 0.0;
             for (int pass = 0; pass < 2; ++pass) {
-                gm_dots(c, n, j + 1, V, ld, vn, hdev);
-                gm_update_norm(c, n, j + 1, V, ld, hdev, vn, nndev);
+                if (pass == 0 && fused)
+                    gm_finish_dots(c, Gop, j + 1, c->gm_part, gsc, hdev);
+                else
+                    gm_dots(c, n, j + 1, V, ld, vn, gsc, hdev);
+                gm_update_norm(c, n, j + 1, V, ld, hdev, gsc, vn, nndev, gsc + j + 1);
                 TBDG_HIP(hipMemcpyAsync(c->host_out, hdev, sizeof(double) * 63, hipMemcpyDeviceToHost,
                                         c->stream));
                 TBDG_HIP(hipStreamSynchronize(c->stream));
@@ -113,6 +130,7 @@ tbdg_status solve_momentum(tbdg_ctx* c, int s, const double* w, const double* b,
             }
             const double hn = std::sqrt(nn);
             for (int i = 0; i <= j; ++i) H[i * m + j] = h[i];
+            H[j * m + j] += kArnoldiShift;   // Hessenberg of A D^{-1} itself
             H[(j + 1) * m + j] = hn;
             for (int i = 0; i < j; ++i) {
                 const double t1 = cs[i] * H[i * m + j] + sn[i] * H[(i + 1) * m + j];
@@ -132,7 +150,6 @@ tbdg_status solve_momentum(tbdg_ctx* c, int s, const double* w, const double* b,
             H[(j + 1) * m + j] = 0.0;
             g[j + 1] = -sn[j] * g[j];
             g[j] = cs[j] * g[j];
-            pending = hn > 0.0 ? 1.0 / hn : 1.0;
             if (std::fabs(g[j + 1]) <= o.tol * bnorm || hn == 0.0) {
                 ++j;
                 break;
@@ -149,12 +166,13 @@ tbdg_status solve_momentum(tbdg_ctx* c, int s, const double* w, const double* b,
             TBDG_HIP(hipMemcpyAsync(c->red_out, c->host_out, sizeof(double) * k,
                                     hipMemcpyHostToDevice, c->stream));
             TBDG_HIP(hipMemsetAsync(c->gz, 0, sizeof(double) * n, c->stream));
-            vec_add_combo(c->stream, n, k, V, ld, c->red_out, c->gz);
+            vec_add_combo(c->stream, n, k, V, ld, c->red_out, gsc, c->gz);
             vec_add_div_diag_u(c->stream, n, c->dim, c->nbu, c->gz, c->diag_u, x);
         }
         A(x, c->gv);
         vec_axpby(c->stream, n, 1.0, b, -1.0, c->gv, V);
-        beta = norm2(c, n, V);
+        gm_norm_inv(c, n, V, c->red_out + 63, gsc);
+        beta = std::sqrt(host_scalar(c, c->red_out + 63));
         if (breakdown && beta > o.tol * bnorm) {
             st = TBDG_EBREAKDOWN;
             break;
