@@ -281,6 +281,10 @@ void launch_apply_momentum(const tbdg_ctx* c, int s, const double* w, const doub
 int launch_apply_momentum_fused(const tbdg_ctx* c, int s, const double* w, const double* u,
                                 double* y, const MomFuse& fz);
 void launch_diag_momentum(const tbdg_ctx* c, int s, const double* w, double* d);
+// line-structured momentum right-hand side (pv: pressure at the velocity nodes)
+void launch_rhs_lines(const tbdg_ctx* c, double mcoef, const double* u_prev, const double* u1,
+                      const double* w1, double cd1, double ca1, const double* u2, const double* w2,
+                      double cd2, double ca2, const double* pv, double* rhs);
 // rhs = m M u_prev + sum_pairs [ -cd L0 u_i + ca A0(w_i) u_i ] + Gw p
 void launch_rhs_momentum(const tbdg_ctx* c, double mcoef, const double* u_prev,
                          const double* u1, const double* w1, double cd1, double ca1,

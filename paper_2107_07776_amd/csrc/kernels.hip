@@ -101,149 +101,6 @@ __device__ inline double interp_p_at(const Tables& t, const double* pc, int nd) 
     return v;
 }
 
-// ============================================================================
-// Momentum right-hand side:
-//   rhs_c = m M u_prev,c + sum_pairs [ -cd L0 u_c + ca A0(w) u_c ] + (Gw p)_c
-// L0(u,v) = int grad u.grad v - sum_E int {{grad u}}.[[v]]
-// A0_w(u,v) = int u (w.grad v) - sum_E int {{u w}}.[[v]]
-// Gw p (v) = int p div v - sum_E int {{p}} [[v]]
-// The pressure enters through its interpolant at the velocity nodes (pv).
-// ============================================================================
-template <int DIM, int N>
-__global__ __launch_bounds__(256) void k_rhs_momentum(
-    Geom g, Periodic per, Tables t, double mcoef, const double* __restrict__ uprev,
-    const double* __restrict__ u1, const double* __restrict__ w1, double cd1, double ca1,
-    const double* __restrict__ u2, const double* __restrict__ w2, double cd2, double ca2,
-    const double* __restrict__ pv, double* __restrict__ rhs, int64_t Nc) {
-    using Lay = Layout<DIM, N>;
-    constexpr int NB = Lay::NB, NF = Lay::NF, CPB = Lay::CPB;
-    __shared__ double s_w[DIM][CPB * NB];
-    __shared__ double s_u[CPB * NB];
-    __shared__ double s_p[CPB * NB];
-    __shared__ double s_f[DIM][CPB * NB];
-    __shared__ double s_wf[CPB][2 * DIM][NF][2];
-    __shared__ double s_face[CPB][2 * DIM][NF][2];
-    const int tid = threadIdx.x;
-    const int lc = tid / NB, nd = tid % NB;
-    const int64_t cell = (int64_t)blockIdx.x * CPB + lc;
-    const bool active = cell < Nc;
-    const double* D = t.Du;
-    const double Wi = node_weight<DIM, N>(t.Wu, nd);
-    s_p[tid] = active ? pv[cell * NB + nd] : 0.0;
-    double acc[DIM];
-    for (int c = 0; c < DIM; ++c) acc[c] = active ? mcoef * g.vol * Wi * uprev[(cell * DIM + c) * NB + nd] : 0.0;
-    const int npairs = (u2 != nullptr) ? 2 : 1;
-    for (int pr = 0; pr < npairs; ++pr) {
-        const double* U = pr ? u2 : u1;
-        const double* Wf = pr ? w2 : w1;
-        const double cd = pr ? cd2 : cd1;
-        const double ca = pr ? ca2 : ca1;
-        __syncthreads();
-        for (int c = 0; c < DIM; ++c) s_w[c][tid] = active ? Wf[(cell * DIM + c) * NB + nd] : 0.0;
-        __syncthreads();
-        for (int it = nd; it < 2 * DIM * NF; it += NB) {
-            const int a = it / (2 * NF), s = (it / NF) % 2, tt = it % NF;
-            const double* Ls = s ? t.L1u : t.L0u;
-            const double* Ln = s ? t.L0u : t.L1u;
-            const double sg = s ? 1.0 : -1.0;
-            const int64_t nb = active ? neighbor<DIM>(g, per.p, cell, a, s) : -1;
-            double wo = 0.0, wn = 0.0;
-#pragma unroll
-            for (int m = 0; m < N; ++m) wo += Ls[m] * s_w[a][lc * NB + Lay::node(a, m, tt)];
-            if (nb >= 0) {
-#pragma unroll
-                for (int m = 0; m < N; ++m) wn += Ln[m] * Wf[(nb * DIM + a) * NB + Lay::node(a, m, tt)];
-            }
-            s_wf[lc][a * 2 + s][tt][0] = sg * wo;
-            s_wf[lc][a * 2 + s][tt][1] = sg * wn;
-        }
-        for (int c = 0; c < DIM; ++c) {
-            __syncthreads();
-            s_u[tid] = active ? U[(cell * DIM + c) * NB + nd] : 0.0;
-            __syncthreads();
-            const double uc = s_u[tid];
-            for (int a = 0; a < DIM; ++a) {
-                const int ia = Lay::coord(nd, a), tt = Lay::tang(nd, a);
-                double ga = 0.0;
-#pragma unroll
-                for (int m = 0; m < N; ++m) ga += D[ia * N + m] * s_u[lc * NB + Lay::node(a, m, tt)];
-                const double inv_h = 1.0 / g.h[a];
-                s_f[a][tid] = g.vol * Wi * inv_h * (-cd * ga * inv_h + ca * uc * s_w[a][tid]);
-            }
-            for (int it = nd; it < 2 * DIM * NF; it += NB) {
-                const int a = it / (2 * NF), s = (it / NF) % 2, tt = it % NF;
-                const double* Ls = s ? t.L1u : t.L0u;
-                const double* dLs = s ? t.dL1u : t.dL0u;
-                const double* Ln = s ? t.L0u : t.L1u;
-                const double* dLn = s ? t.dL0u : t.dL1u;
-                const double sg = s ? 1.0 : -1.0;
-                const int64_t nb = active ? neighbor<DIM>(g, per.p, cell, a, s) : -1;
-                double v0 = 0, d0 = 0, v1 = 0, d1 = 0;
-#pragma unroll
-                for (int m = 0; m < N; ++m) {
-                    const double uo = s_u[lc * NB + Lay::node(a, m, tt)];
-                    v0 += Ls[m] * uo;
-                    d0 += dLs[m] * uo;
-                }
-                const double inv_h = 1.0 / g.h[a];
-                const double wo = s_wf[lc][a * 2 + s][tt][0];
-                double val;
-                if (nb >= 0) {
-#pragma unroll
-                    for (int m = 0; m < N; ++m) {
-                        const double un = U[(nb * DIM + c) * NB + Lay::node(a, m, tt)];
-                        v1 += Ln[m] * un;
-                        d1 += dLn[m] * un;
-                    }
-                    const double wn = s_wf[lc][a * 2 + s][tt][1];
-                    val = cd * 0.5 * sg * (d0 + d1) * inv_h - ca * 0.5 * (v0 * wo + v1 * wn);
-                } else {
-                    val = cd * sg * d0 * inv_h - ca * v0 * wo;
-                }
-                s_face[lc][a * 2 + s][tt][0] = val * g.vol * inv_h * tang_weight<DIM, N>(t.Wu, tt);
-            }
-            __syncthreads();
-            for (int a = 0; a < DIM; ++a) {
-                const int ia = Lay::coord(nd, a), tt = Lay::tang(nd, a);
-                double sum = 0.0;
-#pragma unroll
-                for (int m = 0; m < N; ++m) sum += D[m * N + ia] * s_f[a][lc * NB + Lay::node(a, m, tt)];
-                acc[c] += sum + s_face[lc][a * 2][tt][0] * t.L0u[ia] + s_face[lc][a * 2 + 1][tt][0] * t.L1u[ia];
-            }
-        }
-    }
-    // pressure: volume int p d_c v and faces -{{p}} n_c v (only faces normal to c)
-    __syncthreads();
-    for (int c = 0; c < DIM; ++c) s_f[c][tid] = g.vol * Wi * s_p[tid] / g.h[c];
-    for (int it = nd; it < 2 * DIM * NF; it += NB) {
-        const int a = it / (2 * NF), s = (it / NF) % 2, tt = it % NF;
-        const double* Ls = s ? t.L1u : t.L0u;
-        const double* Ln = s ? t.L0u : t.L1u;
-        const double sg = s ? 1.0 : -1.0;
-        const int64_t nb = active ? neighbor<DIM>(g, per.p, cell, a, s) : -1;
-        double po = 0.0, pn = 0.0;
-#pragma unroll
-        for (int m = 0; m < N; ++m) po += Ls[m] * s_p[lc * NB + Lay::node(a, m, tt)];
-        double pavg = po;
-        if (nb >= 0) {
-#pragma unroll
-            for (int m = 0; m < N; ++m) pn += Ln[m] * pv[nb * NB + Lay::node(a, m, tt)];
-            pavg = 0.5 * (po + pn);
-        }
-        const double inv_h = 1.0 / g.h[a];
-        s_face[lc][a * 2 + s][tt][1] = -pavg * sg * g.vol * inv_h * tang_weight<DIM, N>(t.Wu, tt);
-    }
-    __syncthreads();
-    for (int c = 0; c < DIM; ++c) {
-        const int ic = Lay::coord(nd, c), tt = Lay::tang(nd, c);
-        double sum = 0.0;
-#pragma unroll
-        for (int m = 0; m < N; ++m) sum += D[m * N + ic] * s_f[c][lc * NB + Lay::node(c, m, tt)];
-        acc[c] += sum + s_face[lc][c * 2][tt][1] * t.L0u[ic] + s_face[lc][c * 2 + 1][tt][1] * t.L1u[ic];
-        if (active) rhs[(cell * DIM + c) * NB + nd] = acc[c];
-    }
-}
-
 // Dirichlet-data terms of the momentum functionals on the boundary faces
 // normal to direction a, per component c and face point (eq. rhs1 and its
 // stage-2 analogue with the stage's theta and data):
@@ -473,14 +330,11 @@ void launch_rhs_momentum(const tbdg_ctx* c, double mcoef, const double* u_prev,
         using Lay = Layout<D, N>;                                                         \
         hipLaunchKernelGGL((k_interp_p<D, N>), dim3(nblocks(c->Ns, 256)), dim3(256), 0,   \
                            c->stream, c->tab, p, pv, c->Nc);                              \
-        hipLaunchKernelGGL((k_rhs_momentum<D, N>), dim3(nblocks(c->Nc, Lay::CPB)),        \
-                           dim3(Lay::THREADS), 0, c->stream, c->geom, periodic_of(c),     \
-                           c->tab, mcoef, u_prev, u1, w1, cd1, ca1, u2, w2, cd2, ca2, pv, \
-                           rhs, c->Nc);                                                   \
     }
     TBDG_DISPATCH(c, L_);
 #undef L_
     TBDG_HIP(hipGetLastError());
+    launch_rhs_lines(c, mcoef, u_prev, u1, w1, cd1, ca1, u2, w2, cd2, ca2, pv, rhs);
 }
 
 void launch_dirichlet_rhs(const tbdg_ctx* c, int s, const double* w, double* rhs) {

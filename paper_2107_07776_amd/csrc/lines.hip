@@ -269,7 +269,7 @@ __global__ __launch_bounds__(256) void k_momentum_face(Geom g, LineGeom lg, Line
     // per-cell node arrays padded by one slot per x-row: lanes walking
     // x-lines then touch distinct LDS banks
     constexpr int NBP = NB + NB / N;
-    __shared__ double s_w[DIM][CPB * NBP];
+    __shared__ double s_wa[CPB * NBP];
     __shared__ double s_u[DIM][CPB * NBP];
     __shared__ double s_y[DIM][CPB * NBP];
     __shared__ double s_f[CPB * 2 * NF * REC];   // face records of one direction
@@ -284,10 +284,8 @@ __global__ __launch_bounds__(256) void k_momentum_face(Geom g, LineGeom lg, Line
     const int pi = lc * NBP + nd + nd / N;
     if (lc < CPB) {
 #pragma unroll
-        for (int c = 0; c < DIM; ++c) {
-            s_w[c][pi] = active ? w[((size_t)cell * DIM + c) * NB + nd] : 0.0;
+        for (int c = 0; c < DIM; ++c)
             s_u[c][pi] = active ? u[((size_t)cell * DIM + c) * NB + nd] : 0.0;
-        }
         if (fz.invd && active) {
             const double sc = us * fz.invd[(size_t)cell * NB + nd];
 #pragma unroll
@@ -317,6 +315,7 @@ __global__ __launch_bounds__(256) void k_momentum_face(Geom g, LineGeom lg, Line
     }
 #pragma unroll
     for (int a = 0; a < DIM; ++a) {
+        if (lc < CPB) s_wa[pi] = active ? w[((size_t)cell * DIM + a) * NB + nd] : 0.0;
         // phase 1 for direction a: the two faces of every own cell
         for (int it = tid; it < CPB * 2 * NF; it += 256) {
             const int lc1 = it / (2 * NF), s = (it / NF) & 1, tt = it % NF;
@@ -357,7 +356,7 @@ __global__ __launch_bounds__(256) void k_momentum_face(Geom g, LineGeom lg, Line
             for (int m = 0; m < N; ++m) {
                 const int nm = L::node(a, m, ln);
                 const int idx = base + nm + nm / N;
-                const double um = s_u[c][idx], wm = s_w[a][idx];
+                const double um = s_u[c][idx], wm = s_wa[idx];
                 uu[m] = um;
                 uw[m] = um * wm;
                 u0 += t.L0u[m] * um;
@@ -456,6 +455,180 @@ __global__ __launch_bounds__(256) void k_momentum_face(Geom g, LineGeom lg, Line
             const double r = s_red[tid][0] + s_red[tid][1] + s_red[tid][2] + s_red[tid][3];
             fz.part[(size_t)tid * gridDim.x + blockIdx.x] = r;
         }
+    }
+}
+
+// Momentum right-hand side in line form (the functionals of eq. rhs1 and its
+// stage-2 analogue):
+//   rhs_c = m |K| W_i u_prev,c + sum_pairs [ -cd L0(u) + ca A0_w(u) ]_c + (Gw p)_c
+// with, along direction a and per line (reference coordinate, h_a the cell
+// size, wt the tangential weights, l0/l1 the nodal basis at the line ends):
+//   L0: sdiff wt [ sum_j WD_ji (D u)_j - 1/2 (q1 + dR) l1_i + 1/2 (q0 + dL) l0_i ]
+//   A0: sadv wt [ sum_j WD_ji (u w_a)_j - 1/2 (u1 w1 + vR wR) l1_i
+//                 + 1/2 (u0 w0 + vL wL) l0_i ]
+//   Gw (only a = c): sadv wt [ sum_j WD_ji p_j - 1/2 (p1 + pR) l1_i + 1/2 (p0 + pL) l0_i ]
+// (u0, u1 the own end values, q0, q1 the own end derivatives, vL/vR, dL/dR,
+// wL/wR, pL/pR the neighbour's; on a boundary face the average is the own
+// trace).  The pressure enters through its interpolant pv at the velocity
+// nodes.  Same block structure as the operator kernel: the own cells in LDS,
+// one direction's neighbour records at a time, one work item per
+// (cell, component, line).
+template <int DIM, int N>
+__global__ __launch_bounds__(256) void k_rhs_lines(Geom g, LineGeom lg, Line1D lt, Tables t,
+                                                    double mcv, const double* __restrict__ uprev,
+                                                    const double* __restrict__ u1,
+                                                    const double* __restrict__ w1, double cd1,
+                                                    double ca1, const double* __restrict__ u2,
+                                                    const double* __restrict__ w2, double cd2,
+                                                    double ca2, const double* __restrict__ pv,
+                                                    double* __restrict__ rhs, int Nc) {
+    using L = Lay<DIM, N>;
+    using F = FaceLay<DIM, N>;
+    constexpr int NB = F::NB, NF = F::NF, CPB = F::CPB;
+    constexpr int REC = 2 * DIM + 2;
+    constexpr int NBP = NB + NB / N;
+    __shared__ double s_u[DIM][CPB * NBP];
+    __shared__ double s_y[DIM][CPB * NBP];
+    __shared__ double s_wa[CPB * NBP];
+    __shared__ double s_p[CPB * NBP];
+    __shared__ double s_f[CPB * 2 * NF * REC];
+    __shared__ int s_nbr[CPB * 2 * DIM];
+    __shared__ double s_W[N];
+    const int tid = threadIdx.x;
+    if (tid < N) s_W[tid] = t.Wu[tid];
+    const int blk = xcd_block(blockIdx.x, gridDim.x);
+    const int lc = tid / NB, nd = tid % NB;
+    const int cell = blk * CPB + lc;
+    const bool active = lc < CPB && cell < Nc;
+    const int pi = lc * NBP + nd + nd / N;
+    if (lc < CPB) s_p[pi] = active ? pv[(size_t)cell * NB + nd] : 0.0;
+    if (lc < CPB && nd == 0) {
+        const Nbrs<DIM> nb(g, lg, active ? cell : 0);
+#pragma unroll
+        for (int a = 0; a < DIM; ++a) {
+            s_nbr[lc * 2 * DIM + 2 * a] = active ? nb.left[a] : -1;
+            s_nbr[lc * 2 * DIM + 2 * a + 1] = active ? nb.right[a] : -1;
+        }
+    }
+    __syncthreads();
+    if (lc < CPB) {
+        const double Wi0 = L::wnode(s_W, nd);
+#pragma unroll
+        for (int c = 0; c < DIM; ++c)
+            s_y[c][pi] = active ? mcv * Wi0 * uprev[((size_t)cell * DIM + c) * NB + nd] : 0.0;
+    }
+    const int npairs = u2 ? 2 : 1;
+    for (int pr = 0; pr < npairs; ++pr) {
+        const double* U = pr ? u2 : u1;
+        const double* Wv = pr ? w2 : w1;
+        const double cd = pr ? cd2 : cd1, ca = pr ? ca2 : ca1;
+        const bool with_p = pr == 0;
+        if (lc < CPB) {
+#pragma unroll
+            for (int c = 0; c < DIM; ++c)
+                s_u[c][pi] = active ? U[((size_t)cell * DIM + c) * NB + nd] : 0.0;
+        }
+#pragma unroll
+        for (int a = 0; a < DIM; ++a) {
+            if (lc < CPB) s_wa[pi] = active ? Wv[((size_t)cell * DIM + a) * NB + nd] : 0.0;
+            for (int it = tid; it < CPB * 2 * NF; it += 256) {
+                const int lc1 = it / (2 * NF), sd = (it / NF) & 1, tt = it % NF;
+                double rec[REC];
+#pragma unroll
+                for (int q = 0; q < REC; ++q) rec[q] = 0.0;
+                const int nbr = s_nbr[lc1 * 2 * DIM + 2 * a + sd];
+                if (nbr >= 0) {
+#pragma unroll
+                    for (int m = 0; m < N; ++m) {
+                        const int idx = L::node(a, m, tt);
+                        const double lo = sd ? t.L0u[m] : t.L1u[m];
+                        const double dlo = sd ? t.dL0u[m] : t.dL1u[m];
+                        rec[2 * DIM] += lo * Wv[((size_t)nbr * DIM + a) * NB + idx];
+                        if (with_p) rec[2 * DIM + 1] += lo * pv[(size_t)nbr * NB + idx];
+#pragma unroll
+                        for (int c = 0; c < DIM; ++c) {
+                            const double uv = U[((size_t)nbr * DIM + c) * NB + idx];
+                            rec[2 * c] += lo * uv;
+                            rec[2 * c + 1] += dlo * uv;
+                        }
+                    }
+                }
+                double* dst = s_f + it * REC;
+#pragma unroll
+                for (int q = 0; q < REC; ++q) dst[q] = rec[q];
+            }
+            __syncthreads();
+            constexpr int ITEMS = CPB * DIM * NF;
+            for (int it = tid; it < ITEMS; it += 256) {
+                const int lc2 = it / (DIM * NF);
+                const int c = (it % (DIM * NF)) / NF, ln = it % NF;
+                if (blk * CPB + lc2 >= Nc) continue;
+                const int base = lc2 * NBP;
+                const bool pl = with_p && c == a;
+                double uu[N], uw[N], pp[N];
+                double u0 = 0.0, u1v = 0.0, w0 = 0.0, w1v = 0.0, q0 = 0.0, q1 = 0.0, p0 = 0.0, p1 = 0.0;
+#pragma unroll
+                for (int m = 0; m < N; ++m) {
+                    const int nm = L::node(a, m, ln);
+                    const int idx = base + nm + nm / N;
+                    const double um = s_u[c][idx], wm = s_wa[idx];
+                    uu[m] = um;
+                    uw[m] = um * wm;
+                    pp[m] = pl ? s_p[idx] : 0.0;
+                    u0 += t.L0u[m] * um;
+                    u1v += t.L1u[m] * um;
+                    q0 += t.dL0u[m] * um;
+                    q1 += t.dL1u[m] * um;
+                    w0 += t.L0u[m] * wm;
+                    w1v += t.L1u[m] * wm;
+                    p0 += t.L0u[m] * pp[m];
+                    p1 += t.L1u[m] * pp[m];
+                }
+                const double* recl = s_f + ((lc2 * 2) * NF + ln) * REC;
+                const double* recr = s_f + ((lc2 * 2 + 1) * NF + ln) * REC;
+                const bool hl = s_nbr[lc2 * 2 * DIM + 2 * a] >= 0;
+                const bool hr = s_nbr[lc2 * 2 * DIM + 2 * a + 1] >= 0;
+                // face averages (own trace on a boundary face)
+                const double gL = hl ? 0.5 * (q0 + recl[2 * c + 1]) : q0;
+                const double gR = hr ? 0.5 * (q1 + recr[2 * c + 1]) : q1;
+                const double fL = hl ? 0.5 * (u0 * w0 + recl[2 * c] * recl[2 * DIM]) : u0 * w0;
+                const double fR = hr ? 0.5 * (u1v * w1v + recr[2 * c] * recr[2 * DIM]) : u1v * w1v;
+                const double pL = hl ? 0.5 * (p0 + recl[2 * DIM + 1]) : p0;
+                const double pR = hr ? 0.5 * (p1 + recr[2 * DIM + 1]) : p1;
+                double gq[N];
+#pragma unroll
+                for (int j = 0; j < N; ++j) {
+                    double v = 0.0;
+#pragma unroll
+                    for (int m = 0; m < N; ++m) v += t.Du[j * N + m] * uu[m];
+                    gq[j] = v;
+                }
+                const double wt = L::wtan(s_W, ln);
+                const double kd = -cd * lg.sdiff[a] * wt, ka = ca * lg.sadv[a] * wt;
+                const double kp = pl ? lg.sadv[a] * wt : 0.0;
+                const double cl = kd * gL + ka * fL + kp * pL;
+                const double cr = kd * gR + ka * fR + kp * pR;
+#pragma unroll
+                for (int i = 0; i < N; ++i) {
+                    double vd = 0.0, va = 0.0, vp = 0.0;
+#pragma unroll
+                    for (int j = 0; j < N; ++j) {
+                        const double wd = lt.WD[j * N + i];
+                        vd += wd * gq[j];
+                        va += wd * uw[j];
+                        vp += wd * pp[j];
+                    }
+                    const double out = kd * vd + ka * va + kp * vp + t.L0u[i] * cl - t.L1u[i] * cr;
+                    const int ni = L::node(a, i, ln);
+                    s_y[c][base + ni + ni / N] += out;
+                }
+            }
+            __syncthreads();
+        }
+    }
+    if (active) {
+#pragma unroll
+        for (int c = 0; c < DIM; ++c) rhs[((size_t)cell * DIM + c) * NB + nd] = s_y[c][pi];
     }
 }
 
@@ -774,6 +947,22 @@ int launch_apply_momentum_fused(const tbdg_ctx* c, int st, const double* w, cons
 void launch_apply_momentum(const tbdg_ctx* c, int st, const double* w, const double* u, double* y) {
     launch_apply_momentum_fused(c, st, w, u, y,
                                 MomFuse{nullptr, nullptr, 0.0, nullptr, 0, 0, nullptr});
+}
+
+void launch_rhs_lines(const tbdg_ctx* c, double mcoef, const double* u_prev, const double* u1,
+                      const double* w1, double cd1, double ca1, const double* u2, const double* w2,
+                      double cd2, double ca2, const double* pv, double* rhs) {
+#define L_(D, N)                                                                           \
+    {                                                                                      \
+        using FL = FaceLay<D, N>;                                                          \
+        hipLaunchKernelGGL((k_rhs_lines<D, N>), dim3(nblk(c->Nc, FL::CPB)), dim3(FL::THREADS), \
+                           0, c->stream, c->geom, c->lgeom, c->line_u, c->tab,             \
+                           mcoef * c->geom.vol, u_prev, u1, w1, cd1, ca1, u2, w2, cd2, ca2, \
+                           pv, rhs, (int)c->Nc);                                           \
+    }
+    TBDG_LINE_DISPATCH(c, L_);
+#undef L_
+    TBDG_HIP(hipGetLastError());
 }
 
 void launch_diag_momentum(const tbdg_ctx* c, int st, const double* w, double* d) {
