@@ -289,6 +289,36 @@ __global__ __launch_bounds__(BS) void k_update_norm(int64_t n, int k, const doub
     if (threadIdx.x == 0) partial[blockIdx.x] = nn;
 }
 
+// GMRES restart without an operator apply: x += D^{-1} sum_{j<k} y_j gsc_j V_j
+// and V_0 = sum_{j<=k} cr_j gsc_j V_j (the residual of the updated x in the
+// Krylov basis), with the partial sums of |V_0|^2.  Each thread reads V_0[i]
+// before it overwrites it.
+__global__ __launch_bounds__(BS) void k_gm_restart(int64_t n, int dim, int64_t nb, int k, double* V,
+                                                   int64_t ldv, const double* y, const double* cr,
+                                                   const double* gsc, const double* invd, double* x,
+                                                   double* partial) {
+    __shared__ double s_y[64], s_c[64];
+    for (int j = threadIdx.x; j <= k; j += BS) {
+        s_y[j] = j < k ? y[j] * gsc[j] : 0.0;
+        s_c[j] = cr[j] * gsc[j];
+    }
+    __syncthreads();
+    double nn = 0.0;
+    for (int64_t i = (int64_t)blockIdx.x * BS + threadIdx.x; i < n; i += (int64_t)gridDim.x * BS) {
+        double sx = 0.0, sr = 0.0;
+        for (int j = 0; j <= k; ++j) {
+            const double v = V[(int64_t)j * ldv + i];
+            sx += s_y[j] * v;
+            sr += s_c[j] * v;
+        }
+        x[i] += sx * invd[diag_index(i, dim, nb)];
+        V[i] = sr;
+        nn += sr * sr;
+    }
+    nn = block_sum(nn);
+    if (threadIdx.x == 0) partial[blockIdx.x] = nn;
+}
+
 // out[j] = gsc[j] * sum_b partial[j * G + b] for j < k; out[k] = the plain
 // sum of slot k (w . w)
 __global__ __launch_bounds__(BS) void k_finish_gs(const double* partial, int G, int k,
@@ -426,6 +456,17 @@ void gm_update_norm(tbdg_ctx* c, int64_t n, int k, const double* V, int64_t ldv,
                        part);
     hipLaunchKernelGGL(k_finish_inv_norm, dim3(1), dim3(BS), 0, c->stream, part, G, dev_nn,
                        gsc_next);
+    TBDG_HIP(hipGetLastError());
+}
+
+void gm_restart(tbdg_ctx* c, int64_t n, int k, double* V, int64_t ldv, const double* y,
+                const double* cr, const double* gsc, const double* invd, double* x, double* dev_nn,
+                double* gsc0) {
+    const int G = reduce_grid(n, 4096);
+    double* part = c->red_part + 62 * 4096;
+    hipLaunchKernelGGL(k_gm_restart, dim3(G), dim3(BS), 0, c->stream, n, c->dim, c->nbu, k, V, ldv,
+                       y, cr, gsc, invd, x, part);
+    hipLaunchKernelGGL(k_finish_inv_norm, dim3(1), dim3(BS), 0, c->stream, part, G, dev_nn, gsc0);
     TBDG_HIP(hipGetLastError());
 }
 

@@ -367,6 +367,11 @@ void gm_finish_dots(tbdg_ctx* c, int G, int k, const double* part, const double*
 void gm_update_norm(tbdg_ctx* c, int64_t n, int k, const double* V, int64_t ldv, const double* h,
                     const double* gsc, double* w, double* dev_nn, double* gsc_next);
 void gm_norm_inv(tbdg_ctx* c, int64_t n, const double* v, double* dev_nn, double* inv);
+// restart without an operator apply: x += D^{-1} sum_{j<k} y_j gsc_j V_j,
+// V_0 = sum_{j<=k} cr_j gsc_j V_j; dev_nn = |V_0|^2, gsc0 = 1 / |V_0|
+void gm_restart(tbdg_ctx* c, int64_t n, int k, double* V, int64_t ldv, const double* y,
+                const double* cr, const double* gsc, const double* invd, double* x, double* dev_nn,
+                double* gsc0);
 // x += gz / diag (velocity layout)
 void vec_add_div_diag_u(hipStream_t s, int64_t n, int dim, int64_t nb, const double* gz,
                         const double* d, double* x);

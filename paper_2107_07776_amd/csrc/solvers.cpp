@@ -69,7 +69,7 @@ tbdg_status solve_momentum(tbdg_ctx* c, int s, const double* w, const double* b,
     const int64_t ld = n;
     double* hdev = c->red_out;        // h (j+1 entries) then w.w
     double* nndev = c->red_out + 62;  // |w'|^2
-    std::vector<double> H((m + 1) * m), cs(m), sn(m), g(m + 1), y(m), h(m + 1);
+    std::vector<double> H((m + 1) * m), H0((m + 1) * m), cs(m), sn(m), g(m + 1), y(m), h(m + 1);
     int total = 0;
     tbdg_status st = TBDG_ENOTCONV;
     // initial residual r = b - A x into V_0; the Krylov vectors stay
@@ -80,21 +80,32 @@ tbdg_status solve_momentum(tbdg_ctx* c, int s, const double* w, const double* b,
     gm_norm_inv(c, n, V, c->red_out + 63, gsc);
     double beta = std::sqrt(host_scalar(c, c->red_out + 63));
     inf.res0 = beta / bnorm;
+    // V_0 = b - A x recomputed (true) or formed from the Krylov basis at a
+    // restart; convergence and the final residual always use a true one
+    bool true_res = true;
+    auto true_residual = [&]() {
+        A(x, c->gv);
+        vec_axpby(c->stream, n, 1.0, b, -1.0, c->gv, V);
+        gm_norm_inv(c, n, V, c->red_out + 63, gsc);
+        beta = std::sqrt(host_scalar(c, c->red_out + 63));
+        true_res = true;
+    };
     while (true) {
         if (!std::isfinite(beta)) {
             st = TBDG_ENAN;
             break;
         }
-        if (beta <= o.tol * bnorm) {
-            st = TBDG_OK;
-            break;
-        }
-        if (total >= o.maxiter) {
-            st = TBDG_ENOTCONV;
+        if (beta <= o.tol * bnorm || total >= o.maxiter) {
+            if (!true_res) {
+                true_residual();
+                continue;
+            }
+            st = beta <= o.tol * bnorm ? TBDG_OK : TBDG_ENOTCONV;
             break;
         }
         std::fill(g.begin(), g.end(), 0.0);
         g[0] = beta;
+        const double g0 = beta;
         int j = 0;
         bool breakdown = false;
         for (; j < m && total < o.maxiter; ++j) {
@@ -132,6 +143,7 @@ tbdg_status solve_momentum(tbdg_ctx* c, int s, const double* w, const double* b,
             for (int i = 0; i <= j; ++i) H[i * m + j] = h[i];
             H[j * m + j] += kArnoldiShift;   // Hessenberg of A D^{-1} itself
             H[(j + 1) * m + j] = hn;
+            for (int i = 0; i <= j + 1; ++i) H0[i * m + j] = H[i * m + j];
             for (int i = 0; i < j; ++i) {
                 const double t1 = cs[i] * H[i * m + j] + sn[i] * H[(i + 1) * m + j];
                 const double t2 = -sn[i] * H[i * m + j] + cs[i] * H[(i + 1) * m + j];
@@ -161,6 +173,22 @@ tbdg_status solve_momentum(tbdg_ctx* c, int s, const double* w, const double* b,
             for (int q = i + 1; q < k; ++q) s2 -= H[i * m + q] * y[q];
             y[i] = s2 / H[i * m + i];
         }
+        if (k > 0 && !breakdown) {
+            // residual of the updated x in the basis: r = V_{k+1} (beta e_1 - Hbar y)
+            for (int i = 0; i <= k; ++i) {
+                double ci = i == 0 ? g0 : 0.0;
+                for (int q = (i > 0 ? i - 1 : 0); q < k; ++q) ci -= H0[i * m + q] * y[q];
+                c->host_out[k + i] = ci;
+            }
+            std::memcpy(c->host_out, y.data(), sizeof(double) * k);
+            TBDG_HIP(hipMemcpyAsync(c->red_out, c->host_out, sizeof(double) * (2 * k + 1),
+                                    hipMemcpyHostToDevice, c->stream));
+            gm_restart(c, n, k, V, ld, c->red_out, c->red_out + k, gsc, c->invd_u, x,
+                       c->red_out + 63, gsc);
+            beta = std::sqrt(host_scalar(c, c->red_out + 63));
+            true_res = false;
+            continue;
+        }
         if (k > 0) {
             std::memcpy(c->host_out, y.data(), sizeof(double) * k);
             TBDG_HIP(hipMemcpyAsync(c->red_out, c->host_out, sizeof(double) * k,
@@ -169,10 +197,7 @@ tbdg_status solve_momentum(tbdg_ctx* c, int s, const double* w, const double* b,
             vec_add_combo(c->stream, n, k, V, ld, c->red_out, gsc, c->gz);
             vec_add_div_diag_u(c->stream, n, c->dim, c->nbu, c->gz, c->diag_u, x);
         }
-        A(x, c->gv);
-        vec_axpby(c->stream, n, 1.0, b, -1.0, c->gv, V);
-        gm_norm_inv(c, n, V, c->red_out + 63, gsc);
-        beta = std::sqrt(host_scalar(c, c->red_out + 63));
+        true_residual();
         if (breakdown && beta > o.tol * bnorm) {
             st = TBDG_EBREAKDOWN;
             break;
