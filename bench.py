@@ -213,14 +213,15 @@ def main():
     ap.add_argument("--no-profile", action="store_true")
     ap.add_argument("--precond", default="mg_fp32", choices=["jacobi", "mg_fp32", "mg_bf16"],
                     help="pressure preconditioner of the timed solver")
-    ap.add_argument("--mg-degree", type=int, default=0)
+    ap.add_argument("--mg-degree", type=int, default=5,
+                    help="Chebyshev degree of the multigrid smoother (0: library default)")
     ap.add_argument("--no-compare", action="store_true",
                     help="skip the plain FP64 (Jacobi) reference run")
     ap.add_argument("--guess", default="previous", choices=["given", "previous", "learned"],
                     help="initial guess of the timed solver's pressure solves")
     ap.add_argument("--no-learned", action="store_true",
                     help="skip training and timing the learned-guess variant")
-    ap.add_argument("--restart", type=int, default=5, help="GMRES restart length of the timed solver")
+    ap.add_argument("--restart", type=int, default=4, help="GMRES restart length of the timed solver")
     ap.add_argument("--mom-guess", default="previous", choices=["given", "previous"],
                     help="momentum initial guess of the timed solver")
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
@@ -277,6 +278,7 @@ def main():
                       "momentum_initial_guess": {"given": "previous stage value",
                                                  "previous": "linear extrapolation to the stage time"}[args.mom_guess],
                       "momentum_solves_per_stage": W["nonlinear"],
+                      "mg_chebyshev_degree": args.mg_degree if args.precond != "jacobi" else None,
                       "tolerance": W["tol"], "cells": list(W["n"]), "degree": W["k"],
                       "velocity_dofs": ctx.N_u, "pressure_dofs": ctx.N_p,
                       "mean_iterations_per_step": main_run["iters"]}}

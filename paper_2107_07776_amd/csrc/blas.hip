@@ -322,27 +322,45 @@ __global__ __launch_bounds__(BS) void k_gm_restart(int64_t n, int dim, int64_t n
 // out[j] = gsc[j] * sum_b partial[j * G + b] for j < k; out[k] = the plain
 // sum of slot k (w . w)
 __global__ __launch_bounds__(BS) void k_finish_gs(const double* partial, int G, int k,
-                                                  const double* gsc, double* out) {
+                                                  const double* gsc, double* out, double* hout) {
     const int j = blockIdx.x;
     double acc = 0.0;
     for (int b = threadIdx.x; b < G; b += BS) acc += partial[(int64_t)j * G + b];
     acc = block_sum(acc);
-    if (threadIdx.x == 0) out[j] = j < k ? gsc[j] * acc : acc;
+    if (threadIdx.x == 0) {
+        const double v = j < k ? gsc[j] * acc : acc;
+        out[j] = v;
+        if (hout) {
+            hout[j] = v;
+            __threadfence_system();
+        }
+    }
 }
 
 // nn = sum of the partials; inv = 1 / sqrt(nn) (1 when nn is not positive)
 __global__ __launch_bounds__(BS) void k_finish_inv_norm(const double* partial, int G, double* nn,
-                                                        double* inv) {
+                                                        double* inv, double* hnn) {
     double acc = 0.0;
     for (int b = threadIdx.x; b < G; b += BS) acc += partial[b];
     acc = block_sum(acc);
     if (threadIdx.x == 0) {
         if (nn) nn[0] = acc;
         inv[0] = acc > 0.0 ? 1.0 / sqrt(acc) : 1.0;
+        if (hnn) {
+            hnn[0] = acc;
+            __threadfence_system();
+        }
     }
 }
 
 }  // namespace
+
+// address in host_out (as seen by the device) of a scalar slot of red_out
+double* host_mirror(const tbdg_ctx* c, const double* dev) {
+    if (!c->host_dev || dev < c->red_out || dev >= c->red_out + 128)
+        throw Error(TBDG_EINVAL, "scalar slot outside the mirrored range");
+    return c->host_dev + (dev - c->red_out);
+}
 
 int reduce_grid(int64_t n, int cap) {
     int64_t g = (n + BS - 1) / BS;
@@ -438,13 +456,14 @@ void gm_dots(tbdg_ctx* c, int64_t n, int k, const double* V, int64_t ldv, const 
     hipLaunchKernelGGL(k_mdot8, dim3(G, groups), dim3(BS), 0, c->stream, n, k, V, ldv, w,
                        c->red_part);
     hipLaunchKernelGGL(k_finish_gs, dim3(k + 1), dim3(BS), 0, c->stream, c->red_part, G, k, gsc,
-                       dev_out);
+                       dev_out, host_mirror(c, dev_out));
     TBDG_HIP(hipGetLastError());
 }
 
 void gm_finish_dots(tbdg_ctx* c, int G, int k, const double* part, const double* gsc,
                     double* dev_out) {
-    hipLaunchKernelGGL(k_finish_gs, dim3(k + 1), dim3(BS), 0, c->stream, part, G, k, gsc, dev_out);
+    hipLaunchKernelGGL(k_finish_gs, dim3(k + 1), dim3(BS), 0, c->stream, part, G, k, gsc, dev_out,
+                       host_mirror(c, dev_out));
     TBDG_HIP(hipGetLastError());
 }
 
@@ -455,7 +474,7 @@ void gm_update_norm(tbdg_ctx* c, int64_t n, int k, const double* V, int64_t ldv,
     hipLaunchKernelGGL(k_update_norm, dim3(G), dim3(BS), 0, c->stream, n, k, V, ldv, h, gsc, w,
                        part);
     hipLaunchKernelGGL(k_finish_inv_norm, dim3(1), dim3(BS), 0, c->stream, part, G, dev_nn,
-                       gsc_next);
+                       gsc_next, host_mirror(c, dev_nn));
     TBDG_HIP(hipGetLastError());
 }
 
@@ -466,7 +485,8 @@ void gm_restart(tbdg_ctx* c, int64_t n, int k, double* V, int64_t ldv, const dou
     double* part = c->red_part + 62 * 4096;
     hipLaunchKernelGGL(k_gm_restart, dim3(G), dim3(BS), 0, c->stream, n, c->dim, c->nbu, k, V, ldv,
                        y, cr, gsc, invd, x, part);
-    hipLaunchKernelGGL(k_finish_inv_norm, dim3(1), dim3(BS), 0, c->stream, part, G, dev_nn, gsc0);
+    hipLaunchKernelGGL(k_finish_inv_norm, dim3(1), dim3(BS), 0, c->stream, part, G, dev_nn, gsc0,
+                       host_mirror(c, dev_nn));
     TBDG_HIP(hipGetLastError());
 }
 
@@ -475,7 +495,7 @@ void gm_norm_inv(tbdg_ctx* c, int64_t n, const double* v, double* dev_nn, double
     hipLaunchKernelGGL(k_dot_many, dim3(G, 1), dim3(BS), 0, c->stream, n, v, (int64_t)0, v,
                        c->red_part);
     hipLaunchKernelGGL(k_finish_inv_norm, dim3(1), dim3(BS), 0, c->stream, c->red_part, G, dev_nn,
-                       inv);
+                       inv, host_mirror(c, dev_nn));
     TBDG_HIP(hipGetLastError());
 }
 

@@ -218,8 +218,11 @@ tbdg_status tbdg_create(const tbdg_mesh_desc* mesh, const tbdg_disc_desc* disc, 
         c->invd_p[1] = dalloc(c->Np);
         c->invd_p[2] = dalloc(c->Np);
         void* h = nullptr;
-        TBDG_HIP(hipHostMalloc(&h, sizeof(double) * 512, hipHostMallocDefault));
+        TBDG_HIP(hipHostMalloc(&h, sizeof(double) * 512, hipHostMallocCoherent | hipHostMallocMapped));
         c->host_out = static_cast<double*>(h);
+        void* hd = nullptr;
+        TBDG_HIP(hipHostGetDevicePointer(&hd, h, 0));
+        c->host_dev = static_cast<double*>(hd);
         c->s_w = dalloc(c->Nu);
         c->s_rhs = dalloc(c->Nu);
         c->s_ustar = dalloc(c->Nu);

@@ -237,7 +237,9 @@ struct tbdg_ctx {
     int64_t red_op_len = 0;
     double* invd_u = nullptr;       // 1 / momentum diagonal (Ns)
     double* invd_p[3] = {nullptr, nullptr, nullptr};
-    double* host_out = nullptr;     // pinned host mirror
+    double* host_out = nullptr;     // pinned host mirror (coherent)
+    double* host_dev = nullptr;     // device address of host_out: finishing kernels write
+                                    // scalars there directly
     // step scratch
     double* s_w = nullptr;
     double* s_rhs = nullptr;
@@ -360,6 +362,8 @@ int launch_cg_apply(const tbdg_ctx* c, double alpha, const double* r, const doub
 // operator kernel.  gm_update_norm: w -= sum_i dev h_i gsc_i V_i, dev_nn =
 // |w|^2, gsc_next = 1 / |w| (1 if zero).  gm_norm_inv: dev_nn = |v|^2 and
 // inv = 1 / |v|.
+// Every finishing step also writes its scalars to host_out (through host_dev)
+// at the same offsets as in red_out, so the host only synchronises.
 void gm_dots(tbdg_ctx* c, int64_t n, int k, const double* V, int64_t ldv, const double* w,
              const double* gsc, double* dev_out);
 void gm_finish_dots(tbdg_ctx* c, int G, int k, const double* part, const double* gsc,

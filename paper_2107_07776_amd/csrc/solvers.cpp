@@ -22,6 +22,12 @@ namespace trbdg {
 
 namespace {
 
+// scalar slot of red_out that a finishing kernel also wrote to host_out
+double mirrored(tbdg_ctx* c, const double* dev) {
+    TBDG_HIP(hipStreamSynchronize(c->stream));
+    return c->host_out[dev - c->red_out];
+}
+
 double host_scalar(tbdg_ctx* c, const double* dev, int k = 1) {
     TBDG_HIP(hipMemcpyAsync(c->host_out, dev, sizeof(double) * k, hipMemcpyDeviceToHost, c->stream));
     TBDG_HIP(hipStreamSynchronize(c->stream));
@@ -78,7 +84,7 @@ tbdg_status solve_momentum(tbdg_ctx* c, int s, const double* w, const double* b,
     A(x, c->gv);
     vec_axpby(c->stream, n, 1.0, b, -1.0, c->gv, V);
     gm_norm_inv(c, n, V, c->red_out + 63, gsc);
-    double beta = std::sqrt(host_scalar(c, c->red_out + 63));
+    double beta = std::sqrt(mirrored(c, c->red_out + 63));
     inf.res0 = beta / bnorm;
     // V_0 = b - A x recomputed (true) or formed from the Krylov basis at a
     // restart; convergence and the final residual always use a true one
@@ -87,7 +93,7 @@ tbdg_status solve_momentum(tbdg_ctx* c, int s, const double* w, const double* b,
         A(x, c->gv);
         vec_axpby(c->stream, n, 1.0, b, -1.0, c->gv, V);
         gm_norm_inv(c, n, V, c->red_out + 63, gsc);
-        beta = std::sqrt(host_scalar(c, c->red_out + 63));
+        beta = std::sqrt(mirrored(c, c->red_out + 63));
         true_res = true;
     };
     while (true) {
@@ -131,9 +137,7 @@ tbdg_status solve_momentum(tbdg_ctx* c, int s, const double* w, const double* b,
                 else
                     gm_dots(c, n, j + 1, V, ld, vn, gsc, hdev);
                 gm_update_norm(c, n, j + 1, V, ld, hdev, gsc, vn, nndev, gsc + j + 1);
-                TBDG_HIP(hipMemcpyAsync(c->host_out, hdev, sizeof(double) * 63, hipMemcpyDeviceToHost,
-                                        c->stream));
-                TBDG_HIP(hipStreamSynchronize(c->stream));
+                TBDG_HIP(hipStreamSynchronize(c->stream));   // h, w.w and |w'|^2 are in host_out
                 for (int i = 0; i <= j; ++i) h[i] += c->host_out[i];
                 const double ww = c->host_out[j + 1];
                 nn = c->host_out[62];
@@ -185,7 +189,7 @@ tbdg_status solve_momentum(tbdg_ctx* c, int s, const double* w, const double* b,
                                     hipMemcpyHostToDevice, c->stream));
             gm_restart(c, n, k, V, ld, c->red_out, c->red_out + k, gsc, c->invd_u, x,
                        c->red_out + 63, gsc);
-            beta = std::sqrt(host_scalar(c, c->red_out + 63));
+            beta = std::sqrt(mirrored(c, c->red_out + 63));
             true_res = false;
             continue;
         }
