@@ -68,6 +68,41 @@ def initial_fields(W, coords_u, coords_p):
     return synthetic.nodal_velocity(u, 2, nbu), p, synthetic.nodal_velocity(uh, 2, nbu)
 
 
+TRAFFIC_FILES = {("momentum_apply", "tgv32"): "momentum_face_tgv32_q3_traffic.txt"}
+
+
+def measured_traffic(kernel, workload):
+    """HBM bytes per launch of `kernel` from the committed byte-counter
+    summary of this workload (rocprofv3 FETCH_SIZE and WRITE_SIZE, each
+    scaled by the reading of a plain device copy of known size), or None.
+    The summary names the source revision of the kernels it measured; when
+    the kernel sources have changed since, the figure is not used."""
+    name = TRAFFIC_FILES.get((kernel, workload))
+    if not name:
+        return None
+    path = os.path.join(ROOT, "profiles", name)
+    if not os.path.exists(path):
+        return None
+    vals = {}
+    for line in open(path):
+        if "=" in line and not line.startswith("#"):
+            k, v = line.split("=", 1)
+            vals[k.strip()] = v.strip()
+    src = vals.get("kernel_source_sha256")
+    if src is None or src != kernel_source_digest():
+        return None
+    return {"bytes_per_launch": float(vals["traffic_bytes_per_launch"]), "source": f"profiles/{name}"}
+
+
+def kernel_source_digest():
+    """SHA-256 over the HIP sources of the operator kernels."""
+    import hashlib
+    h = hashlib.sha256()
+    for f in ("lines.hip", "lines.hpp", "internal.hpp"):
+        h.update(open(os.path.join(ROOT, "paper_2107_07776_amd", "csrc", f), "rb").read())
+    return h.hexdigest()
+
+
 def cpu_baseline(W, seconds_budget=20.0):
     """The oracle's TR-BDF2 step on a bounded sample of the same workload: the
     same domain, degree, nu and dt on a 4^3 (3D) mesh, scaled to the full
@@ -145,8 +180,9 @@ def run_solver(ctx, W, precond, steps, warmup, profile, mg_degree=0, guess="give
     torch.cuda.synchronize()
     if profile:
         ctx.profile(True)
-        ctx.profile_read(0)
-        ctx.profile_read(1)
+        for which in (0, 1):
+            ctx.profile_read(which)
+            ctx.profile_bytes(which)
     iters, used = [], []
     torch.cuda.synchronize()
     t0 = time.perf_counter()
@@ -166,7 +202,7 @@ def run_solver(ctx, W, precond, steps, warmup, profile, mg_degree=0, guess="give
                iters=[float(np.mean([it[j] for it in iters])) for j in range(4)], U=U, P=P,
                learned_rate=sum(1 for g in used if g == 2) / max(len(used), 1))
     if profile:
-        res["prof"] = (ctx.profile_read(0), ctx.profile_read(1))
+        res["prof"] = tuple(ctx.profile_read(w) + (ctx.profile_bytes(w),) for w in (0, 1))
         ctx.profile(False)
     return res
 
@@ -314,12 +350,10 @@ def main():
                               "p_mean_free_rel_l2_diff_vs_plain": dp0,
                               "after_steps": args.steps + args.warmup}
     if "prof" in main_run:
-        (ms_p, n_p), (ms_u, n_u) = main_run["prof"]
-        bytes_p = 16.0 * ctx.N_p          # read p, write y
-        bytes_u = 24.0 * ctx.N_u          # read u and w, write y
+        (ms_p, n_p, b_p), (ms_u, n_u, b_u) = main_run["prof"]
         kern = {
-            "pressure_apply": dict(ms=ms_p, n=n_p, bytes=bytes_p, dofs=ctx.N_p),
-            "momentum_apply": dict(ms=ms_u, n=n_u, bytes=bytes_u, dofs=ctx.N_u),
+            "pressure_apply": dict(ms=ms_p, n=n_p, bytes=b_p / max(n_p, 1), dofs=ctx.N_p),
+            "momentum_apply": dict(ms=ms_u, n=n_u, bytes=b_u / max(n_u, 1), dofs=ctx.N_u),
         }
         for name, kd in kern.items():
             avg_s = kd["ms"] * 1e-3 / max(kd["n"], 1)
@@ -328,8 +362,11 @@ def main():
             kd["gbs"] = kd["bytes"] / avg_s / 1e9 if avg_s > 0 else 0.0
         dom = max(kern, key=lambda k: kern[k]["ms"])
         kd = kern[dom]
+        traffic = measured_traffic(dom, args.workload)
         out["roofline"] = {"bound": "hbm", "kernel": dom, "achieved": kd["gbs"], "peak": HBM_PEAK_GBS,
-                           "unit": "GB/s", "frac": kd["gbs"] / HBM_PEAK_GBS, "traffic": None,
+                           "unit": "GB/s", "frac": kd["gbs"] / HBM_PEAK_GBS,
+                           "traffic": traffic["bytes_per_launch"] if traffic else None,
+                           "traffic_source": traffic["source"] if traffic else None,
                            "algorithmic_bytes_per_launch": kd["bytes"], "avg_launch_us": kd["avg_us"],
                            "launches": kd["n"],
                            "share_of_step_time": kd["ms"] * 1e-3 / main_run["elapsed"]}

@@ -391,6 +391,12 @@ TBDG_API tbdg_status tbdg_nonlinear_solves(tbdg_ctx* ctx, int* solves);
 TBDG_API tbdg_status tbdg_profile_enable(tbdg_ctx* ctx, int enable);
 TBDG_API tbdg_status tbdg_profile_read(tbdg_ctx* ctx, int which, double* total_ms,
                                        int64_t* launches);
+/* Algorithmic bytes (the compulsory FP64 reads and writes: pressure apply
+ * 16 B, fused CG step 40 B, flexible CG step 32 B per pressure DoF; momentum
+ * apply 24 B per velocity DoF, in GMRES plus 8 B per scalar node for the
+ * inverse diagonal and 8 B per velocity DoF per fused dot) of the launches
+ * timed for `which` since the previous call (host output), then reset.     */
+TBDG_API tbdg_status tbdg_profile_bytes(tbdg_ctx* ctx, int which, double* bytes);
 
 #ifdef __cplusplus
 }

@@ -685,4 +685,15 @@ tbdg_status tbdg_profile_read(tbdg_ctx* c, int which, double* total_ms, int64_t*
     });
 }
 
+tbdg_status tbdg_profile_bytes(tbdg_ctx* c, int which, double* bytes) {
+    if (!c) return TBDG_EINVAL;
+    return guarded(c, [&]() {
+        require(which == 0 || which == 1, "which must be 0 (pressure) or 1 (momentum)");
+        require(bytes != nullptr, "null output");
+        *bytes = c->timer.bytes[which];
+        c->timer.bytes[which] = 0.0;
+        return TBDG_OK;
+    });
+}
+
 }  // extern "C"

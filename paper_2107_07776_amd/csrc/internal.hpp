@@ -75,6 +75,7 @@ struct KTimer {
     std::vector<hipEvent_t> pool;
     double total_ms[2] = {0.0, 0.0};
     int64_t count[2] = {0, 0};
+    double bytes[2] = {0.0, 0.0};   // algorithmic bytes of the timed launches
 };
 
 // Dirichlet velocity data on the boundary faces of the box (the faces normal
@@ -304,7 +305,7 @@ void launch_node_coords(const tbdg_ctx* c, int field, double* xyz);
 // the interval is the kernel's execution); null events otherwise.
 class TimedLaunch {
   public:
-    TimedLaunch(const tbdg_ctx* c, int which);
+    TimedLaunch(const tbdg_ctx* c, int which, double bytes);
     ~TimedLaunch();
     hipEvent_t start() const { return e1_; }
     hipEvent_t stop() const { return e2_; }

@@ -811,7 +811,7 @@ void launch_apply_pressure(const tbdg_ctx* c, double alpha, const double* p, dou
 #define L_(D, N)                                                                           \
     {                                                                                      \
         using FL = FaceLay<D, N - 1>;                                                      \
-        TimedLaunch tl(c, 0);                                                              \
+        TimedLaunch tl(c, 0, 16.0 * (double)c->Np);                                        \
         hipExtLaunchKernelGGL((k_pressure_face<D, N - 1, 0>), dim3(nblk(c->Nc, FL::CPB)),  \
                               dim3(FL::THREADS), 0, c->stream, tl.start(), tl.stop(), 0,   \
                               c->geom, c->lgeom, c->line_p, c->tab, c->cr_p,               \
@@ -844,7 +844,7 @@ int launch_cg_apply(const tbdg_ctx* c, double alpha, const double* r, const doub
         using FL = FaceLay<D, N - 1>;                                                      \
         G = (int)nblk(c->Nc, FL::CPB);                                                     \
         if (G > c->red_op_len) throw Error(TBDG_EINVAL, "operator partial buffer too small"); \
-        TimedLaunch tl(c, 0);                                                              \
+        TimedLaunch tl(c, 0, 40.0 * (double)c->Np);                                        \
         hipExtLaunchKernelGGL((k_pressure_face<D, N - 1, 3>), dim3(G), dim3(FL::THREADS),  \
                               0, c->stream, tl.start(), tl.stop(), 0, c->geom, c->lgeom,   \
                               c->line_p, c->tab, c->cr_p, alpha * c->geom.vol, p_old, q,  \
@@ -906,7 +906,7 @@ int launch_fcg_apply(const tbdg_ctx* c, double alpha, const double* z, const dou
         using FL = FaceLay<D, N - 1>;                                                      \
         G = (int)nblk(c->Nc, FL::CPB);                                                     \
         if (G > c->red_op_len) throw Error(TBDG_EINVAL, "operator partial buffer too small"); \
-        TimedLaunch tl(c, 0);                                                              \
+        TimedLaunch tl(c, 0, 32.0 * (double)c->Np);                                        \
         hipExtLaunchKernelGGL((k_pressure_face<D, N - 1, 4>), dim3(G), dim3(FL::THREADS),  \
                               0, c->stream, tl.start(), tl.stop(), 0, c->geom, c->lgeom,   \
                               c->line_p, c->tab, c->cr_p, alpha * c->geom.vol, p_old, q,  \
@@ -926,13 +926,17 @@ int launch_apply_momentum_fused(const tbdg_ctx* c, int st, const double* w, cons
     if (fz.ndot < 0 || fz.ndot > MOM_FUSE_MAX_DOTS)
         throw Error(TBDG_EINVAL, "fused dot count out of range");
     int G = 0;
+    // algorithmic bytes: read u and w, write y; fused: the inverse diagonal
+    // and the basis vectors of the dots
+    double bytes = 24.0 * (double)c->Nu;
+    if (fz.invd) bytes += 8.0 * (double)c->Ns + 8.0 * fz.ndot * (double)c->Nu;
 #define L_(D, N)                                                                           \
     {                                                                                      \
         using FL = FaceLay<D, N>;                                                          \
         G = (int)nblk(c->Nc, FL::CPB);                                                     \
         if (fz.ndot > 0 && (int64_t)G * (fz.ndot + 1) > c->gm_part_len)                    \
             throw Error(TBDG_EINVAL, "fused partial buffer too small");                    \
-        TimedLaunch tl(c, 1);                                                              \
+        TimedLaunch tl(c, 1, bytes);                                                       \
         hipExtLaunchKernelGGL((k_momentum_face<D, N>), dim3(G), dim3(FL::THREADS), 0,      \
                               c->stream, tl.start(), tl.stop(), 0, c->geom, c->lgeom,      \
                               c->line_u, c->tab, c->cr_u, mcoef * c->geom.vol,             \

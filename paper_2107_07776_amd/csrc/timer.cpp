@@ -18,10 +18,11 @@ hipEvent_t take(const tbdg_ctx* c) {
 }
 }  // namespace
 
-TimedLaunch::TimedLaunch(const tbdg_ctx* c, int which) : c_(c), which_(which) {
+TimedLaunch::TimedLaunch(const tbdg_ctx* c, int which, double bytes) : c_(c), which_(which) {
     if (!c_->timer.on) return;
     e1_ = take(c_);
     e2_ = take(c_);
+    c_->timer.bytes[which_] += bytes;
 }
 
 TimedLaunch::~TimedLaunch() {

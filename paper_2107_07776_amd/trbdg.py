@@ -30,7 +30,7 @@ EXPORTED = [
     "tbdg_net_mse", "tbdg_net_adam_step", "tbdg_set_guess_net", "tbdg_guess_reset",
     "tbdg_guess_record", "tbdg_guess_recorded", "tbdg_guess_features", "tbdg_guess_inject",
     "tbdg_guess_last", "tbdg_face_qpoints", "tbdg_set_dirichlet", "tbdg_set_nonlinear",
-    "tbdg_nonlinear_solves",
+    "tbdg_nonlinear_solves", "tbdg_profile_bytes",
 ]
 
 GUESS = {"given": 0, "previous": 1, "learned": 2}
@@ -140,6 +140,7 @@ def load_library(path=LIB_PATH):
         "tbdg_set_dirichlet": ([vp, i, vp], i),
         "tbdg_set_nonlinear": ([vp, i, d], i),
         "tbdg_nonlinear_solves": ([vp, P(i)], i),
+        "tbdg_profile_bytes": ([vp, i, P(d)], i),
         "tbdg_guess_features": ([vp, i, vp, vp, vp, d, vp, d, vp, P(d)], i),
         "tbdg_guess_inject": ([vp, i, vp, vp, vp, d, vp], i),
     }
@@ -439,6 +440,12 @@ class Context:
         ms, n = ctypes.c_double(), ctypes.c_int64()
         self._check(self.lib.tbdg_profile_read(self.h, int(which), ctypes.byref(ms), ctypes.byref(n)))
         return ms.value, n.value
+
+    def profile_bytes(self, which):
+        """Algorithmic bytes of the timed launches since the last call."""
+        b = ctypes.c_double()
+        self._check(self.lib.tbdg_profile_bytes(self.h, int(which), ctypes.byref(b)))
+        return b.value
 
 
 class Net:
