@@ -257,7 +257,7 @@ __global__ __launch_bounds__(256) void k_momentum_face(Geom g, LineGeom lg, Line
                                                         const double* __restrict__ w,
                                                         const double* __restrict__ u,
                                                         double* __restrict__ y, int Nc, Bnd bd,
-                                                        MomFuse fz) {
+                                                        MomFuse fz, int zc) {
     using L = Lay<DIM, N>;
     using F = FaceLay<DIM, N>;
     constexpr int NB = F::NB, NF = F::NF, CPB = F::CPB;
@@ -274,18 +274,22 @@ __global__ __launch_bounds__(256) void k_momentum_face(Geom g, LineGeom lg, Line
     __shared__ double s_y[DIM][CPB * NBP];
     __shared__ double s_f[CPB * 2 * NF * REC];   // face records of one direction
     __shared__ int s_nbr[CPB * 2 * DIM];
+    __shared__ int s_cell[CPB];
     __shared__ double s_W[N];
     const int tid = threadIdx.x;
     if (tid < N) s_W[tid] = t.Wu[tid];
     const int blk = xcd_block(blockIdx.x, gridDim.x);
     const int lc = tid / NB, nd = tid % NB;
-    const int cell = blk * CPB + lc;
-    const bool active = lc < CPB && cell < Nc;
+    const int cell = lc < CPB ? tile_cell(blk, lc, g, CPB, zc, Nc) : -1;
+    const bool active = cell >= 0;
     const int pi = lc * NBP + nd + nd / N;
+    double wreg[DIM];
     if (lc < CPB) {
 #pragma unroll
-        for (int c = 0; c < DIM; ++c)
+        for (int c = 0; c < DIM; ++c) {
             s_u[c][pi] = active ? u[((size_t)cell * DIM + c) * NB + nd] : 0.0;
+            wreg[c] = active ? w[((size_t)cell * DIM + c) * NB + nd] : 0.0;
+        }
         if (fz.invd && active) {
             const double sc = us * fz.invd[(size_t)cell * NB + nd];
 #pragma unroll
@@ -296,6 +300,7 @@ __global__ __launch_bounds__(256) void k_momentum_face(Geom g, LineGeom lg, Line
         }
     }
     if (lc < CPB && nd == 0) {
+        s_cell[lc] = cell;
         // neighbour table of the cell, written with constant indices
         const Nbrs<DIM> nb(g, lg, active ? cell : 0);
 #pragma unroll
@@ -315,7 +320,7 @@ __global__ __launch_bounds__(256) void k_momentum_face(Geom g, LineGeom lg, Line
     }
 #pragma unroll
     for (int a = 0; a < DIM; ++a) {
-        if (lc < CPB) s_wa[pi] = active ? w[((size_t)cell * DIM + a) * NB + nd] : 0.0;
+        if (lc < CPB) s_wa[pi] = wreg[a];
         // phase 1 for direction a: the two faces of every own cell
         for (int it = tid; it < CPB * 2 * NF; it += 256) {
             const int lc1 = it / (2 * NF), s = (it / NF) & 1, tt = it % NF;
@@ -348,7 +353,8 @@ __global__ __launch_bounds__(256) void k_momentum_face(Geom g, LineGeom lg, Line
         for (int it = tid; it < ITEMS; it += 256) {
             const int lc2 = it / (DIM * NF);
             const int c = (it % (DIM * NF)) / NF, ln = it % NF;
-            if (blk * CPB + lc2 >= Nc) continue;
+            const int cell2 = s_cell[lc2];
+            if (cell2 < 0) continue;
             const int base = lc2 * NBP;
             double uu[N], uw[N];
             double u0 = 0.0, u1 = 0.0, w0 = 0.0, w1 = 0.0, q0 = 0.0, q1 = 0.0;
@@ -383,7 +389,7 @@ __global__ __launch_bounds__(256) void k_momentum_face(Geom g, LineGeom lg, Line
                 for (int m = 0; m < N; ++m) q0 += t.dL0u[m] * uu[m];
                 X0 = 0.5 * q0 + Cr * u0;
                 Y0 = -0.5 * u0;
-                const double uDa = bd.uD[bnd_point(bd, g, blk * CPB + lc2, a, 0, ln, NF) * DIM + a];
+                const double uDa = bd.uD[bnd_point(bd, g, cell2, a, 0, ln, NF) * DIM + a];
                 fl = fmax(fabs(w0), fabs(2.0 * uDa - w0)) * u0;
             }
             if (hr) {
@@ -397,7 +403,7 @@ __global__ __launch_bounds__(256) void k_momentum_face(Geom g, LineGeom lg, Line
                 for (int m = 0; m < N; ++m) q1 += t.dL1u[m] * uu[m];
                 X1 = -0.5 * q1 + Cr * u1;
                 Y1 = -0.5 * u1;
-                const double uDa = bd.uD[bnd_point(bd, g, blk * CPB + lc2, a, 1, ln, NF) * DIM + a];
+                const double uDa = bd.uD[bnd_point(bd, g, cell2, a, 1, ln, NF) * DIM + a];
                 fr = fmax(fabs(w1), fabs(2.0 * uDa - w1)) * u1;
             }
             const double wt = L::wtan(s_W, ln);
@@ -940,7 +946,8 @@ int launch_apply_momentum_fused(const tbdg_ctx* c, int st, const double* w, cons
         hipExtLaunchKernelGGL((k_momentum_face<D, N>), dim3(G), dim3(FL::THREADS), 0,      \
                               c->stream, tl.start(), tl.stop(), 0, c->geom, c->lgeom,      \
                               c->line_u, c->tab, c->cr_u, mcoef * c->geom.vol,             \
-                              theta * c->nu, theta, w, u, y, (int)c->Nc, bd, fz);          \
+                              theta * c->nu, theta, w, u, y, (int)c->Nc, bd, fz,           \
+                              tile_zchunk(c->dim, c->geom.nc, FL::CPB));                   \
     }
     TBDG_LINE_DISPATCH(c, L_);
 #undef L_

@@ -83,5 +83,35 @@ __device__ inline int xcd_block(int b, int G) {
     return x < r ? x * (q + 1) + i : r * (q + 1) + (x - r) * q + i;
 }
 
+// Cell of local slot lc in tile `blk` (tiles of cpb x-consecutive cells):
+// with zc == 0 tiles are numbered x-fastest; otherwise z-fastest within
+// chunks of zc z-planes (then x, then y, then chunk), so that the tiles
+// holding a cell's z-neighbours run next to it and the neighbour values it
+// gathers are still in L2 when their own tile reads them.  Needs
+// nc[0] % cpb == 0 and nc[2] % zc == 0.  Returns -1 past the last cell.
+__device__ inline int tile_cell(int blk, int lc, const Geom& g, int cpb, int zc, int Nc) {
+    if (zc == 0) {
+        const int c = blk * cpb + lc;
+        return c < Nc ? c : -1;
+    }
+    const int ntx = g.nc[0] / cpb;
+    int t = blk;
+    const int zz = t % zc;
+    t /= zc;
+    const int tx = t % ntx;
+    t /= ntx;
+    const int ty = t % g.nc[1];
+    const int tz = (t / g.nc[1]) * zc + zz;
+    if (tz >= g.nc[2]) return -1;
+    return (tx * cpb + lc) + g.nc[0] * (ty + g.nc[1] * tz);
+}
+
+// z-chunk depth for tile_cell on this mesh (0: plain x-fastest order)
+inline int tile_zchunk(int dim, const int* nc, int cpb) {
+    if (dim != 3 || nc[0] % cpb != 0) return 0;
+    for (int z : {4, 2}) if (nc[2] % z == 0) return z;
+    return 0;
+}
+
 }  // namespace lines
 }  // namespace trbdg
