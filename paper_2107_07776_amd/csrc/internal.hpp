@@ -284,6 +284,9 @@ void launch_apply_momentum(const tbdg_ctx* c, int s, const double* w, const doub
 int launch_apply_momentum_fused(const tbdg_ctx* c, int s, const double* w, const double* u,
                                 double* y, const MomFuse& fz);
 void launch_diag_momentum(const tbdg_ctx* c, int s, const double* w, double* d);
+// sum-factorised Helmholtz right-hand side
+void launch_rhs_p_lines(const tbdg_ctx* c, double alpha, double fcoef, const double* u_ss,
+                        const double* p_prev, double* rhs);
 // line-structured momentum right-hand side (pv: pressure at the velocity nodes)
 void launch_rhs_lines(const tbdg_ctx* c, double mcoef, const double* u_prev, const double* u1,
                       const double* w1, double cd1, double ca1, const double* u2, const double* w2,

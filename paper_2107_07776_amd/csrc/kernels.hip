@@ -196,85 +196,6 @@ __global__ __launch_bounds__(256) void k_add_grad_p(Geom g, Tables t, const doub
     }
 }
 
-// rhs = alpha M^p p_prev + f * [ int u.grad q - sum_E int {{u}}.[[q]] ]
-template <int DIM, int N>
-__global__ __launch_bounds__(256) void k_rhs_pressure(Geom g, Periodic per, Tables t,
-                                                       double alpha, double fcoef,
-                                                       const double* __restrict__ u,
-                                                       const double* __restrict__ pprev,
-                                                       double* __restrict__ rhs, int64_t Nc) {
-    constexpr int NP = N - 1;
-    using Lay = Layout<DIM, N>;
-    using LayP = Layout<DIM, NP>;
-    constexpr int NB = Lay::NB, NF = Lay::NF, CPB = Lay::CPB;
-    constexpr int NBP = ipow(NP, DIM);
-    __shared__ double s_f[DIM][CPB * NB];
-    __shared__ double s_face[CPB][2 * DIM][NF];
-    const int tid = threadIdx.x;
-    const int lc = tid / NB, nd = tid % NB;
-    const int64_t cell = (int64_t)blockIdx.x * CPB + lc;
-    const bool active = cell < Nc;
-    const double Wi = node_weight<DIM, N>(t.Wu, nd);
-    for (int c = 0; c < DIM; ++c)
-        s_f[c][tid] = active ? g.vol * Wi * u[(cell * DIM + c) * NB + nd] / g.h[c] : 0.0;
-    for (int it = nd; it < 2 * DIM * NF; it += NB) {
-        const int a = it / (2 * NF), s = (it / NF) % 2, tt = it % NF;
-        const double* Ls = s ? t.L1u : t.L0u;
-        const double* Ln = s ? t.L0u : t.L1u;
-        const double sg = s ? 1.0 : -1.0;
-        double uo = 0.0, un = 0.0, val = 0.0;
-        if (active) {
-            const int64_t nb = neighbor<DIM>(g, per.p, cell, a, s);
-#pragma unroll
-            for (int m = 0; m < N; ++m) uo += Ls[m] * u[(cell * DIM + a) * NB + Lay::node(a, m, tt)];
-            double uavg = uo;
-            if (nb >= 0) {
-#pragma unroll
-                for (int m = 0; m < N; ++m) un += Ln[m] * u[(nb * DIM + a) * NB + Lay::node(a, m, tt)];
-                uavg = 0.5 * (uo + un);
-            }
-            val = -uavg * sg * g.vol / g.h[a] * tang_weight<DIM, N>(t.Wu, tt);
-        }
-        s_face[lc][a * 2 + s][tt] = val;
-    }
-    __syncthreads();
-    if (nd < NBP && active) {
-        double acc = 0.0;
-        // volume: sum over velocity quadrature points
-        for (int q = 0; q < NB; ++q) {
-            for (int c = 0; c < DIM; ++c) {
-                double b = 1.0;
-                for (int e = 0; e < DIM; ++e) {
-                    const int qe = Lay::coord(q, e), ie = LayP::coord(nd, e);
-                    b *= (e == c) ? t.Dpu[qe * NMAX + ie] : t.Ip[qe * NMAX + ie];
-                }
-                acc += b * s_f[c][lc * NB + q];
-            }
-        }
-        // faces: psi_i at the velocity face points
-        for (int a = 0; a < DIM; ++a) {
-            const int ia = LayP::coord(nd, a);
-            for (int s = 0; s < 2; ++s) {
-                const double Lp = s ? t.L1p[ia] : t.L0p[ia];
-                double sum = 0.0;
-                for (int tt = 0; tt < NF; ++tt) {
-                    // tangential coordinates of the face point and of the pressure node
-                    const int q = Lay::node(a, 0, tt);
-                    double b = 1.0;
-                    for (int e = 0; e < DIM; ++e) {
-                        if (e == a) continue;
-                        b *= t.Ip[Lay::coord(q, e) * NMAX + LayP::coord(nd, e)];
-                    }
-                    sum += b * s_face[lc][a * 2 + s][tt];
-                }
-                acc += Lp * sum;
-            }
-        }
-        const double Wp = node_weight<DIM, NP>(t.Wp, nd);
-        rhs[cell * NBP + nd] = alpha * g.vol * Wp * pprev[cell * NBP + nd] + fcoef * acc;
-    }
-}
-
 template <int DIM, int N>
 __global__ void k_node_coords(Geom g, Tables t, int field, double* xyz, int64_t Nc) {
     const int n = field == 0 ? N : N - 1;
@@ -367,16 +288,7 @@ void launch_add_grad_p(const tbdg_ctx* c, const double* x, double a, const doubl
 
 void launch_rhs_pressure(const tbdg_ctx* c, double alpha, double fcoef, const double* u_ss,
                          const double* p_prev, double* rhs) {
-#define L_(D, N)                                                                          \
-    {                                                                                     \
-        using Lay = Layout<D, N>;                                                         \
-        hipLaunchKernelGGL((k_rhs_pressure<D, N>), dim3(nblocks(c->Nc, Lay::CPB)),        \
-                           dim3(Lay::THREADS), 0, c->stream, c->geom, periodic_of(c),     \
-                           c->tab, alpha, fcoef, u_ss, p_prev, rhs, c->Nc);               \
-    }
-    TBDG_DISPATCH(c, L_);
-#undef L_
-    TBDG_HIP(hipGetLastError());
+    launch_rhs_p_lines(c, alpha, fcoef, u_ss, p_prev, rhs);
 }
 
 void launch_node_coords(const tbdg_ctx* c, int field, double* xyz) {

@@ -638,6 +638,147 @@ __global__ __launch_bounds__(256) void k_rhs_lines(Geom g, LineGeom lg, Line1D l
     }
 }
 
+// Helmholtz right-hand side (eq. helmholtz_1 and its stage-2 analogue) in
+// sum-factorised form:
+//   rhs_i = alpha |K| W^p_i p_prev,i
+//         + f [ sum_c (|K|/h_c) sum_q W_q u_c(q) (d_c psi_i)(q)
+//               - sum_faces (|K|/h_a) sum_t W_t sg {{u_a}}(t) psi_i(t) ]
+// on the velocity quadrature (sg = -1 on the left face of a direction, +1 on
+// the right; on a boundary face the average is the own trace).  The volume
+// sum runs as one-dimensional contractions from the N^d velocity points to
+// the (N-1)^d pressure nodes, one direction at a time.
+template <int DIM, int N>
+__global__ __launch_bounds__(256) void k_rhs_p_lines(Geom g, LineGeom lg, Tables t, double alpha,
+                                                      double fcoef, const double* __restrict__ u,
+                                                      const double* __restrict__ pprev,
+                                                      double* __restrict__ rhs, int Nc) {
+    constexpr int NP = N - 1;
+    using L = Lay<DIM, N>;
+    using F = FaceLay<DIM, N>;
+    constexpr int NB = F::NB, NF = F::NF, CPB = F::CPB;
+    constexpr int NBq = ipow(NP, DIM);
+    constexpr int S1 = NP * ipow(N, DIM - 1);
+    constexpr int S2 = DIM == 3 ? NP * NP * N : 1;
+    constexpr int NFACE = 2 * DIM * NF;
+    __shared__ double s_v[DIM][CPB * NB];
+    __shared__ double s_1[DIM][CPB * S1];
+    __shared__ double s_2[DIM][CPB * S2];
+    __shared__ double s_face[CPB * NFACE];
+    __shared__ int s_nbr[CPB * 2 * DIM];
+    const int tid = threadIdx.x;
+    const int blk = xcd_block(blockIdx.x, gridDim.x);
+    const int lc = tid / NB, nd = tid % NB;
+    const int cell = blk * CPB + lc;
+    const bool active = lc < CPB && cell < Nc;
+    if (lc < CPB) {
+        double wq = 1.0;
+#pragma unroll
+        for (int a = 0; a < DIM; ++a) wq *= t.Wu[L::coord(nd, a)];
+#pragma unroll
+        for (int c = 0; c < DIM; ++c)
+            s_v[c][lc * NB + nd] =
+                active ? wq * (g.vol / g.h[c]) * u[((size_t)cell * DIM + c) * NB + nd] : 0.0;
+        if (nd == 0) {
+            const Nbrs<DIM> nb(g, lg, active ? cell : 0);
+#pragma unroll
+            for (int a = 0; a < DIM; ++a) {
+                s_nbr[lc * 2 * DIM + 2 * a] = active ? nb.left[a] : -1;
+                s_nbr[lc * 2 * DIM + 2 * a + 1] = active ? nb.right[a] : -1;
+            }
+        }
+    }
+    __syncthreads();
+    // face values -sg (|K|/h_a) W_t {{u_a}} at every face point of the own cells
+    for (int it = tid; it < CPB * NFACE; it += 256) {
+        const int lc1 = it / NFACE, face = (it / NF) % (2 * DIM), tt = it % NF;
+        const int a = face >> 1, sd = face & 1;
+        const int cell1 = blk * CPB + lc1;
+        double val = 0.0;
+        if (cell1 < Nc) {
+            double uo = 0.0;
+#pragma unroll
+            for (int m = 0; m < N; ++m)
+                uo += (sd ? t.L1u[m] : t.L0u[m]) * u[((size_t)cell1 * DIM + a) * NB + L::node(a, m, tt)];
+            double uavg = uo;
+            const int nbr = s_nbr[lc1 * 2 * DIM + face];
+            if (nbr >= 0) {
+                double un = 0.0;
+#pragma unroll
+                for (int m = 0; m < N; ++m)
+                    un += (sd ? t.L0u[m] : t.L1u[m]) * u[((size_t)nbr * DIM + a) * NB + L::node(a, m, tt)];
+                uavg = 0.5 * (uo + un);
+            }
+            val = -uavg * (sd ? 1.0 : -1.0) * (g.vol / g.h[a]) * L::wtan(t.Wu, tt);
+        }
+        s_face[it] = val;
+    }
+    // volume, first contraction (direction 0): [q0, q1, (q2)] -> [i0, q1, (q2)]
+    for (int it = tid; it < CPB * DIM * S1; it += 256) {
+        const int lc1 = it / (DIM * S1), c = (it / S1) % DIM, r = it % S1;
+        const int i0 = r % NP, rest = r / NP;   // rest = q1 + N q2
+        const double* B = c == 0 ? t.Dpu : t.Ip;
+        double acc = 0.0;
+#pragma unroll
+        for (int q0 = 0; q0 < N; ++q0) acc += B[q0 * NMAX + i0] * s_v[c][lc1 * NB + q0 + N * rest];
+        s_1[c][lc1 * S1 + r] = acc;
+    }
+    __syncthreads();
+    if (DIM == 3) {
+        // second contraction (direction 1): [i0, q1, q2] -> [i0, i1, q2]
+        for (int it = tid; it < CPB * DIM * S2; it += 256) {
+            const int lc1 = it / (DIM * S2), c = (it / S2) % DIM, r = it % S2;
+            const int i0 = r % NP, i1 = (r / NP) % NP, q2 = r / (NP * NP);
+            const double* B = c == 1 ? t.Dpu : t.Ip;
+            double acc = 0.0;
+#pragma unroll
+            for (int q1 = 0; q1 < N; ++q1)
+                acc += B[q1 * NMAX + i1] * s_1[c][lc1 * S1 + i0 + NP * (q1 + N * q2)];
+            s_2[c][lc1 * S2 + r] = acc;
+        }
+        __syncthreads();
+    }
+    // last contraction, sum over components and the faces: one thread per
+    // pressure node
+    for (int it = tid; it < CPB * NBq; it += 256) {
+        const int lc1 = it / NBq, i = it % NBq;
+        const int cell1 = blk * CPB + lc1;
+        if (cell1 >= Nc) continue;
+        int ic[3] = {i % NP, (i / NP) % NP, DIM == 3 ? i / (NP * NP) : 0};
+        double acc = 0.0;
+#pragma unroll
+        for (int c = 0; c < DIM; ++c) {
+            const double* B = c == DIM - 1 ? t.Dpu : t.Ip;
+#pragma unroll
+            for (int q = 0; q < N; ++q) {
+                const double v = DIM == 3 ? s_2[c][lc1 * S2 + ic[0] + NP * (ic[1] + NP * q)]
+                                          : s_1[c][lc1 * S1 + ic[0] + NP * q];
+                acc += B[q * NMAX + ic[DIM - 1]] * v;
+            }
+        }
+#pragma unroll
+        for (int a = 0; a < DIM; ++a) {
+#pragma unroll
+            for (int sd = 0; sd < 2; ++sd) {
+                double sum = 0.0;
+                for (int tt = 0; tt < NF; ++tt) {
+                    const int q = L::node(a, 0, tt);
+                    double b = 1.0;
+#pragma unroll
+                    for (int e = 0; e < DIM; ++e)
+                        if (e != a) b *= t.Ip[L::coord(q, e) * NMAX + ic[e]];
+                    sum += b * s_face[lc1 * NFACE + (2 * a + sd) * NF + tt];
+                }
+                acc += (sd ? t.L1p[ic[a]] : t.L0p[ic[a]]) * sum;
+            }
+        }
+        double wp = 1.0;
+#pragma unroll
+        for (int e = 0; e < DIM; ++e) wp *= t.Wp[ic[e]];
+        const size_t gi = (size_t)cell1 * NBq + i;
+        rhs[gi] = alpha * g.vol * wp * pprev[gi] + fcoef * acc;
+    }
+}
+
 // Pressure operator.  MODE 0: y = H p.  MODE 3: one fused CG step: every
 // block first adds the Gu partial sums (r.z, r.r) left by the previous update
 // kernel (same order in every block, so all blocks agree bit for bit) and
@@ -970,6 +1111,20 @@ void launch_rhs_lines(const tbdg_ctx* c, double mcoef, const double* u_prev, con
                            0, c->stream, c->geom, c->lgeom, c->line_u, c->tab,             \
                            mcoef * c->geom.vol, u_prev, u1, w1, cd1, ca1, u2, w2, cd2, ca2, \
                            pv, rhs, (int)c->Nc);                                           \
+    }
+    TBDG_LINE_DISPATCH(c, L_);
+#undef L_
+    TBDG_HIP(hipGetLastError());
+}
+
+void launch_rhs_p_lines(const tbdg_ctx* c, double alpha, double fcoef, const double* u_ss,
+                        const double* p_prev, double* rhs) {
+#define L_(D, N)                                                                           \
+    {                                                                                      \
+        using FL = FaceLay<D, N>;                                                          \
+        hipLaunchKernelGGL((k_rhs_p_lines<D, N>), dim3(nblk(c->Nc, FL::CPB)), dim3(FL::THREADS), \
+                           0, c->stream, c->geom, c->lgeom, c->tab, alpha, fcoef, u_ss, p_prev, \
+                           rhs, (int)c->Nc);                                               \
     }
     TBDG_LINE_DISPATCH(c, L_);
 #undef L_
