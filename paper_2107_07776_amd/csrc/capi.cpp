@@ -197,7 +197,7 @@ tbdg_status tbdg_create(const tbdg_mesh_desc* mesh, const tbdg_disc_desc* disc, 
         c->gv = dalloc(c->Nu);
         c->gz = dalloc(c->Nu);
         c->gsc = dalloc(GMRES_MAX + 2);
-        c->gm_part_len = (c->Nc + 1) * (trbdg::MOM_FUSE_MAX_DOTS + 1);
+        c->gm_part_len = (c->Nc + 4) * (trbdg::MOM_FUSE_MAX_DOTS + 1);   // per-wave partials too
         c->gm_part = dalloc(c->gm_part_len);
         c->cr = dalloc(c->Np);
         c->cp = dalloc(c->Np);
