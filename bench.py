@@ -145,7 +145,7 @@ def cpu_baseline(W, seconds_budget=20.0):
 
 
 def run_solver(ctx, W, precond, steps, warmup, profile, mg_degree=0, guess="given", restart=30,
-               mom_guess="given"):
+               mom_guess="given", mom_precond="jacobi"):
     """Fresh initial state, `warmup` untimed steps, `steps` timed steps with the
     given pressure preconditioner and initial guess.  Returns timing,
     iterations, final fields and (with `profile`) the event-timed operator
@@ -173,7 +173,8 @@ def run_solver(ctx, W, precond, steps, warmup, profile, mg_degree=0, guess="give
     n = 0
     for i in range(warmup):
         info, _ = ctx.step(U, H, P, t, n, mom_tol=tol, prs_tol=tol, prs_maxiter=20000, precond=precond,
-                           guess=guess, restart=restart, mom_guess=mom_guess)
+                           guess=guess, restart=restart, mom_guess=mom_guess,
+                           mom_precond=mom_precond)
         t += W["dt"]
         n += 1
         log(f"[bench] {precond}/{guess} warmup step {i + 1}/{warmup}: iterations {[x['iters'] for x in info]}")
@@ -188,7 +189,8 @@ def run_solver(ctx, W, precond, steps, warmup, profile, mg_degree=0, guess="give
     t0 = time.perf_counter()
     for i in range(steps):
         info, _ = ctx.step(U, H, P, t, n, mom_tol=tol, prs_tol=tol, prs_maxiter=20000, precond=precond,
-                           guess=guess, restart=restart, mom_guess=mom_guess)
+                           guess=guess, restart=restart, mom_guess=mom_guess,
+                           mom_precond=mom_precond)
         t += W["dt"]
         n += 1
         iters.append([x["iters"] for x in info])
@@ -258,6 +260,8 @@ def main():
     ap.add_argument("--no-learned", action="store_true",
                     help="skip training and timing the learned-guess variant")
     ap.add_argument("--restart", type=int, default=4, help="GMRES restart length of the timed solver")
+    ap.add_argument("--mom-precond", default="line", choices=["jacobi", "line"],
+                    help="momentum preconditioner of the timed solver")
     ap.add_argument("--mom-guess", default="previous", choices=["given", "previous"],
                     help="momentum initial guess of the timed solver")
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
@@ -300,7 +304,7 @@ def main():
         net, learned_info = train_guess(ctx, W)
         ctx.set_guess_net(net)
     main_run = run_solver(ctx, W, args.precond, args.steps, args.warmup, not args.no_profile,
-                          args.mg_degree, args.guess, args.restart, args.mom_guess)
+                          args.mg_degree, args.guess, args.restart, args.mom_guess, args.mom_precond)
     solver = {"jacobi": "Jacobi-preconditioned FP64 CG",
               "mg_fp32": "FP32 h/p-multigrid V-cycle (Chebyshev smoother) under FP64 flexible CG",
               "mg_bf16": "h/p-multigrid V-cycle with BF16 storage on the finest level under FP64 "
@@ -310,7 +314,8 @@ def main():
            "higher_is_better": True, "scaling": "strong", "vs_baseline": None, "dtype": "f64",
            "data": "synthetic (closed-form Taylor-Green initial field; seeded random-phase fields train the guess network)",
            "config": {"workload": W["label"], "pressure_solver": solver,
-                      "momentum_solver": f"Jacobi-preconditioned FP64 GMRES({args.restart})",
+                      "momentum_solver": ("line-block" if args.mom_precond == "line" else "Jacobi")
+                                         + f"-preconditioned FP64 GMRES({args.restart})",
                       "momentum_initial_guess": {"given": "previous stage value",
                                                  "previous": "linear extrapolation to the stage time"}[args.mom_guess],
                       "momentum_solves_per_stage": W["nonlinear"],
@@ -326,7 +331,7 @@ def main():
         out["preconditioner_dtype"] = "f32" if args.precond == "mg_fp32" else "bf16 storage, f32 arithmetic"
     if learned_info is not None and args.guess != "learned":
         lr_run = run_solver(ctx, W, args.precond, args.steps, args.warmup, False, args.mg_degree, "learned",
-                            args.restart, args.mom_guess)
+                            args.restart, args.mom_guess, args.mom_precond)
         learned_info.update({"steps_per_s": lr_run["sps"], "ms_per_step": lr_run["ms"],
                              "mean_iterations_per_step": lr_run["iters"],
                              "learned_used_rate": lr_run["learned_rate"],

@@ -172,7 +172,8 @@ TBDG_API tbdg_status tbdg_rhs_pressure(tbdg_ctx* ctx, int stage, const double* u
 /* Krylov options.  tol: relative true residual ||b - A x||_2 <= tol ||b||_2.
  * maxiter: total iterations (GMRES: over all restarts).  restart: GMRES
  * basis size m (<= 60).  precond: TBDG_PRECOND_*; the multigrid values apply
- * to tbdg_solve_pressure only.  guess: 0 = use the content of x_inout.     */
+ * to the pressure solves only, TBDG_PRECOND_LINE to the momentum solves
+ * only.  guess: 0 = use the content of x_inout.                            */
 enum {
     TBDG_GUESS_GIVEN = 0,       /* the content of x_inout (in tbdg_step: the previous pressure) */
     TBDG_GUESS_PREVIOUS = 1,    /* tbdg_step only: previous pressure + same stage's last increment */
@@ -181,7 +182,9 @@ enum {
 enum {
     TBDG_PRECOND_JACOBI = 0,
     TBDG_PRECOND_MG_FP32 = 1,   /* h/p-multigrid V-cycle in FP32 under FP64 flexible CG */
-    TBDG_PRECOND_MG_BF16 = 2    /* the same with BF16 storage on the finest level        */
+    TBDG_PRECOND_MG_BF16 = 2,   /* the same with BF16 storage on the finest level        */
+    TBDG_PRECOND_LINE = 3       /* momentum solves only: line-block preconditioner, see
+                                   tbdg_precond_momentum                                 */
 };
 typedef struct {
     double tol;
@@ -364,6 +367,20 @@ typedef struct {
  * first failing status is returned.                                        */
 TBDG_API tbdg_status tbdg_step(tbdg_ctx* ctx, tbdg_state* state, const tbdg_solver_opts* mom,
                       const tbdg_solver_opts* prs, tbdg_solve_info info[4]);
+
+/* The line-block preconditioner of the momentum solves (not in the paper,
+ * which uses Jacobi; for TBDG_PRECOND_LINE): z = P^{-1} v with
+ * P^{-1} = B_z^{-1} D B_y^{-1} D B_x^{-1} (2D: B_y^{-1} D B_x^{-1}) applied to
+ * each velocity component, D the Jacobi diagonal of the stage operator
+ * V_s(w) and B_a its exact restriction to each grid line of direction a
+ * inside a cell (D on the diagonal, the couplings of direction a off it:
+ * stiffness, advection volume term and the own-trace parts of the SIP and
+ * Lax-Friedrichs face terms of eqs. bilin_diff and trilinear).  Builds the
+ * inverse blocks for w, then applies them.  w, v, z: N_u (device); v and z
+ * must not alias.  The GMRES of TBDG_PRECOND_LINE uses the same operator
+ * (right preconditioning).                                                  */
+TBDG_API tbdg_status tbdg_precond_momentum(tbdg_ctx* ctx, int stage, const double* w,
+                                           const double* v, double* z);
 
 /* Fully nonlinear momentum predictors (Sec. 2: the advecting velocity of
  * each stage may be the stage unknown itself, found by fixed-point

@@ -296,7 +296,7 @@ __global__ __launch_bounds__(BS) void k_update_norm(int64_t n, int k, const doub
 __global__ __launch_bounds__(BS) void k_gm_restart(int64_t n, int dim, int64_t nb, int k, double* V,
                                                    int64_t ldv, const double* y, const double* cr,
                                                    const double* gsc, const double* invd, double* x,
-                                                   double* partial) {
+                                                   double* partial, double* xcomb) {
     __shared__ double s_y[64], s_c[64];
     for (int j = threadIdx.x; j <= k; j += BS) {
         s_y[j] = j < k ? y[j] * gsc[j] : 0.0;
@@ -311,7 +311,8 @@ __global__ __launch_bounds__(BS) void k_gm_restart(int64_t n, int dim, int64_t n
             sx += s_y[j] * v;
             sr += s_c[j] * v;
         }
-        x[i] += sx * invd[diag_index(i, dim, nb)];
+        if (xcomb) xcomb[i] = sx;
+        else x[i] += sx * invd[diag_index(i, dim, nb)];
         V[i] = sr;
         nn += sr * sr;
     }
@@ -480,11 +481,11 @@ void gm_update_norm(tbdg_ctx* c, int64_t n, int k, const double* V, int64_t ldv,
 
 void gm_restart(tbdg_ctx* c, int64_t n, int k, double* V, int64_t ldv, const double* y,
                 const double* cr, const double* gsc, const double* invd, double* x, double* dev_nn,
-                double* gsc0) {
+                double* gsc0, double* xcomb) {
     const int G = reduce_grid(n, 4096);
     double* part = c->red_part + 62 * 4096;
     hipLaunchKernelGGL(k_gm_restart, dim3(G), dim3(BS), 0, c->stream, n, c->dim, c->nbu, k, V, ldv,
-                       y, cr, gsc, invd, x, part);
+                       y, cr, gsc, invd, x, part, xcomb);
     hipLaunchKernelGGL(k_finish_inv_norm, dim3(1), dim3(BS), 0, c->stream, part, G, dev_nn, gsc0,
                        host_mirror(c, dev_nn));
     TBDG_HIP(hipGetLastError());

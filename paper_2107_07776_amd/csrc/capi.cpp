@@ -67,6 +67,7 @@ void free_all(tbdg_ctx* c) {
     dfree(c->diag_u);
     dfree(c->V);
     dfree(c->gsc);
+    dfree(c->mom_blk);
     dfree(c->gm_part);
     dfree(c->gv);
     dfree(c->gz);
@@ -106,7 +107,7 @@ tbdg_solver_opts defaults(const tbdg_solver_opts* o) {
     require(r.tol > 0.0 && std::isfinite(r.tol), "solver tol must be positive");
     require(r.maxiter > 0, "solver maxiter must be positive");
     require(r.restart >= 0 && r.restart <= GMRES_MAX, "GMRES restart must be in [0, 60]");
-    require(r.precond >= TBDG_PRECOND_JACOBI && r.precond <= TBDG_PRECOND_MG_BF16,
+    require(r.precond >= TBDG_PRECOND_JACOBI && r.precond <= TBDG_PRECOND_LINE,
             "unknown preconditioner");
     require(r.guess >= TBDG_GUESS_GIVEN && r.guess <= TBDG_GUESS_LEARNED, "unknown initial guess");
     return r;
@@ -466,11 +467,26 @@ tbdg_status tbdg_solve_momentum(tbdg_ctx* c, int stage, const double* w, const d
         check_stage(stage);
         require(w && rhs && u_inout, "null pointer");
         const tbdg_solver_opts o = defaults(opts);
-        if (o.precond != TBDG_PRECOND_JACOBI)
-            throw Error(TBDG_EUNSUPPORTED, "the momentum solve has only the Jacobi preconditioner");
+        if (o.precond != TBDG_PRECOND_JACOBI && o.precond != TBDG_PRECOND_LINE)
+            throw Error(TBDG_EUNSUPPORTED, "the momentum solve takes the Jacobi or the line preconditioner");
         const tbdg_status s = trbdg::solve_momentum(c, stage, w, rhs, u_inout, o, info);
         if (s != TBDG_OK) c->last_error = "momentum GMRES did not converge";
         return s;
+    });
+}
+
+tbdg_status tbdg_precond_momentum(tbdg_ctx* c, int stage, const double* w, const double* v,
+                                  double* z) {
+    if (!c) return TBDG_EINVAL;
+    return guarded(c, [&]() {
+        check_stage(stage);
+        require(w && v && z, "null pointer");
+        require(v != z, "v and z must not alias");
+        trbdg::launch_diag_momentum(c, stage, w, c->diag_u);
+        trbdg::ensure_mom_blk(c);
+        trbdg::launch_mom_lineblk(c, stage, w, c->diag_u, c->mom_blk);
+        trbdg::launch_mom_lineprec(c, c->mom_blk, c->diag_u, v, nullptr, z);
+        return TBDG_OK;
     });
 }
 
@@ -483,6 +499,8 @@ tbdg_status tbdg_solve_pressure(tbdg_ctx* c, int stage, const double* rhs, doubl
         const tbdg_solver_opts o = defaults(opts);
         if (o.guess != TBDG_GUESS_GIVEN)
             throw Error(TBDG_EINVAL, "initial-guess modes apply to the solves inside tbdg_step");
+        if (o.precond == TBDG_PRECOND_LINE)
+            throw Error(TBDG_EUNSUPPORTED, "the line preconditioner applies to the momentum solve");
         const tbdg_status s = trbdg::solve_pressure(c, stage, rhs, p_inout, o, info);
         if (s != TBDG_OK) c->last_error = "pressure CG did not converge";
         return s;
@@ -496,8 +514,10 @@ tbdg_status tbdg_step(tbdg_ctx* c, tbdg_state* state, const tbdg_solver_opts* mo
         require(state && state->u && state->u_hist && state->p, "null state");
         const tbdg_solver_opts mo = defaults(mom);
         const tbdg_solver_opts po = defaults(prs);
-        if (mo.precond != TBDG_PRECOND_JACOBI)
-            throw Error(TBDG_EUNSUPPORTED, "the momentum solve has only the Jacobi preconditioner");
+        if (mo.precond != TBDG_PRECOND_JACOBI && mo.precond != TBDG_PRECOND_LINE)
+            throw Error(TBDG_EUNSUPPORTED, "the momentum solve takes the Jacobi or the line preconditioner");
+        if (po.precond == TBDG_PRECOND_LINE)
+            throw Error(TBDG_EUNSUPPORTED, "the line preconditioner applies to the momentum solve");
         require(mo.guess != TBDG_GUESS_LEARNED, "the momentum solve has no learned guess");
         const tbdg_status s = trbdg::step(c, state, mo, po, info);
         if (s != TBDG_OK && c->last_error.empty()) c->last_error = "a stage solve failed";

@@ -103,6 +103,7 @@ struct MomFuse {
     int64_t ldv;
     int ndot;
     double* part;
+    const double* shv;   // without invd: the shift is - shift gsc[0] shv (the Krylov vector)
 };
 constexpr int MOM_FUSE_MAX_DOTS = 8;
 
@@ -222,6 +223,7 @@ struct tbdg_ctx {
     double* gv = nullptr;       // Nu scratch
     double* gz = nullptr;       // Nu scratch
     double* gsc = nullptr;      // inverse norms of the Krylov vectors (gm_m + 1)
+    double* mom_blk = nullptr;  // inverse line blocks of the momentum preconditioner (lazy)
     double* gm_part = nullptr;  // partials of the fused operator dots
     int64_t gm_part_len = 0;
     // CG
@@ -284,6 +286,13 @@ void launch_apply_momentum(const tbdg_ctx* c, int s, const double* w, const doub
 int launch_apply_momentum_fused(const tbdg_ctx* c, int s, const double* w, const double* u,
                                 double* y, const MomFuse& fz);
 void launch_diag_momentum(const tbdg_ctx* c, int s, const double* w, double* d);
+// line-block preconditioner of the momentum operator: inverse blocks of the
+// stage operator (w: advector, d: Jacobi diagonal) and z = P^{-1} (scale v)
+void launch_mom_lineblk(const tbdg_ctx* c, int st, const double* w, const double* d,
+                        double* blk);
+void ensure_mom_blk(tbdg_ctx* c);   // allocates c->mom_blk on first use
+void launch_mom_lineprec(const tbdg_ctx* c, const double* blk, const double* d, const double* v,
+                         const double* scale, double* z);
 // sum-factorised Helmholtz right-hand side
 void launch_rhs_p_lines(const tbdg_ctx* c, double alpha, double fcoef, const double* u_ss,
                         const double* p_prev, double* rhs);
@@ -375,11 +384,12 @@ void gm_finish_dots(tbdg_ctx* c, int G, int k, const double* part, const double*
 void gm_update_norm(tbdg_ctx* c, int64_t n, int k, const double* V, int64_t ldv, const double* h,
                     const double* gsc, double* w, double* dev_nn, double* gsc_next);
 void gm_norm_inv(tbdg_ctx* c, int64_t n, const double* v, double* dev_nn, double* inv);
-// restart without an operator apply: x += D^{-1} sum_{j<k} y_j gsc_j V_j,
+// restart without an operator apply (with xcomb: xcomb = sum_{j<k} y_j gsc_j V_j
+// instead of the update of x): x += D^{-1} sum_{j<k} y_j gsc_j V_j,
 // V_0 = sum_{j<=k} cr_j gsc_j V_j; dev_nn = |V_0|^2, gsc0 = 1 / |V_0|
 void gm_restart(tbdg_ctx* c, int64_t n, int k, double* V, int64_t ldv, const double* y,
                 const double* cr, const double* gsc, const double* invd, double* x, double* dev_nn,
-                double* gsc0);
+                double* gsc0, double* xcomb = nullptr);
 // x += gz / diag (velocity layout)
 void vec_add_div_diag_u(hipStream_t s, int64_t n, int dim, int64_t nb, const double* gz,
                         const double* d, double* x);

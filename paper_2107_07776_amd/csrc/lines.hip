@@ -430,7 +430,11 @@ __global__ __launch_bounds__(256) void k_momentum_face(Geom g, LineGeom lg, Line
         __syncthreads();
     }
     double yv[DIM];
-    const double ysh = fz.invd ? fz.shift * us : 0.0;
+    const double ysh = fz.invd ? fz.shift * us : (fz.shv ? fz.shift * fz.gsc[0] : 0.0);
+    if (fz.shv && active) {
+#pragma unroll
+        for (int c = 0; c < DIM; ++c) uraw[c] = fz.shv[((size_t)cell * DIM + c) * NB + nd];
+    }
 #pragma unroll
     for (int c = 0; c < DIM; ++c) yv[c] = active ? s_y[c][pi] - ysh * uraw[c] : 0.0;
     if (active) {
@@ -461,6 +465,199 @@ __global__ __launch_bounds__(256) void k_momentum_face(Geom g, LineGeom lg, Line
             const double r = s_red[tid][0] + s_red[tid][1] + s_red[tid][2] + s_red[tid][3];
             fz.part[(size_t)tid * gridDim.x + blockIdx.x] = r;
         }
+    }
+}
+
+// Line-block preconditioner of the momentum operator (not in the paper, which
+// uses Jacobi): P^{-1} = B_z^{-1} D B_y^{-1} D B_x^{-1} (2D: B_y^{-1} D B_x^{-1}),
+// B_a = the exact restriction of the scalar stage operator to each grid line
+// of direction a inside a cell: the full Jacobi diagonal D on its diagonal
+// and the couplings of direction a's line operator (stiffness, advection
+// volume term, the own-trace parts of the SIP and Lax-Friedrichs face terms,
+// Dirichlet self terms) off it.  The same for every velocity component.
+//
+// Set-up: one thread per (cell, direction, line) assembles B_a and stores
+// its inverse (Gauss-Jordan with partial pivoting) at
+// blk[((a Nc + cell) NF + line) N^2 + i N + j].
+template <int DIM, int N>
+__global__ __launch_bounds__(256) void k_mom_lineblk(Geom g, LineGeom lg, Line1D lt, Tables t,
+                                                      double Cr, double tnu, double th,
+                                                      const double* __restrict__ w,
+                                                      const double* __restrict__ d,
+                                                      double* __restrict__ blk, int Nc, Bnd bd) {
+    using L = Lay<DIM, N>;
+    constexpr int NB = L::NB;
+    constexpr int NF = ipow(N, DIM - 1);
+    const int64_t it = (int64_t)blockIdx.x * 256 + threadIdx.x;
+    if (it >= (int64_t)Nc * DIM * NF) return;
+    const int ln = (int)(it % NF);
+    const int a = (int)((it / NF) % DIM);
+    const int cell = (int)(it / ((int64_t)DIM * NF));
+    const Nbrs<DIM> nb(g, lg, cell);
+    int left = nb.left[0], right = nb.right[0];
+#pragma unroll
+    for (int e = 1; e < DIM; ++e)
+        if (a == e) {
+            left = nb.left[e];
+            right = nb.right[e];
+        }
+    double wl[N], dd[N];
+    double w0 = 0.0, w1 = 0.0, wL = 0.0, wR = 0.0;
+#pragma unroll
+    for (int m = 0; m < N; ++m) {
+        const int nm = L::node(a, m, ln);
+        wl[m] = w[((size_t)cell * DIM + a) * NB + nm];
+        dd[m] = d[(size_t)cell * NB + nm];
+        w0 += t.L0u[m] * wl[m];
+        w1 += t.L1u[m] * wl[m];
+        if (left >= 0) wL += t.L1u[m] * w[((size_t)left * DIM + a) * NB + nm];
+        if (right >= 0) wR += t.L0u[m] * w[((size_t)right * DIM + a) * NB + nm];
+    }
+    const double wt = L::wtan(t.Wu, ln);
+    const double sd = tnu * lg.sdiff[a] * wt, sv = th * lg.sadv[a] * wt;
+    // own-trace derivatives of the face terms: cl = sd X0 + sv fl and dl = sd Y0
+    // on the left face (coefficients of L0_j and dL0_j), the same on the right
+    double cl_v, cl_d, dl_v, cr_v, cr_d, dr_v;
+    if (left >= 0) {
+        const double lam = fmax(fabs(w0), fabs(wL));
+        cl_v = sv * 0.5 * (lam - w0);
+        cl_d = 0.0;
+        dl_v = 0.0;
+    } else {
+        const double uDa = bd.uD[bnd_point(bd, g, cell, a, 0, ln, NF) * DIM + a];
+        const double lam = fmax(fabs(w0), fabs(2.0 * uDa - w0));
+        cl_v = sd * Cr + sv * lam;
+        cl_d = sd * 0.5;
+        dl_v = -sd * 0.5;
+    }
+    if (right >= 0) {
+        const double lam = fmax(fabs(w1), fabs(wR));
+        cr_v = sv * 0.5 * (lam + w1);
+        cr_d = 0.0;
+        dr_v = 0.0;
+    } else {
+        const double uDa = bd.uD[bnd_point(bd, g, cell, a, 1, ln, NF) * DIM + a];
+        const double lam = fmax(fabs(w1), fabs(2.0 * uDa - w1));
+        cr_v = sd * Cr + sv * lam;
+        cr_d = -sd * 0.5;
+        dr_v = -sd * 0.5;
+    }
+    double B[N][2 * N];
+#pragma unroll
+    for (int i = 0; i < N; ++i) {
+#pragma unroll
+        for (int j = 0; j < N; ++j) {
+            // left face: L0_i (cl_v L0_j + cl_d dL0_j) - dL0_i dl_v L0_j;
+            // right face: L1_i (cr_v L1_j + cr_d dL1_j) + dL1_i dr_v L1_j
+            const double v = sd * lt.A[i * N + j] - sv * lt.WD[j * N + i] * wl[j] +
+                             t.L0u[i] * (cl_v * t.L0u[j] + cl_d * t.dL0u[j]) -
+                             t.dL0u[i] * dl_v * t.L0u[j] +
+                             t.L1u[i] * (cr_v * t.L1u[j] + cr_d * t.dL1u[j]) +
+                             t.dL1u[i] * dr_v * t.L1u[j];
+            B[i][j] = i == j ? dd[i] : v;
+            B[i][N + j] = i == j ? 1.0 : 0.0;
+        }
+    }
+    // Gauss-Jordan with partial pivoting (rows swapped by value)
+#pragma unroll
+    for (int k = 0; k < N; ++k) {
+        int piv = k;
+        double best = fabs(B[k][k]);
+#pragma unroll
+        for (int r = k + 1; r < N; ++r)
+            if (fabs(B[r][k]) > best) {
+                best = fabs(B[r][k]);
+                piv = r;
+            }
+#pragma unroll
+        for (int r = k + 1; r < N; ++r) {
+            if (r != piv) continue;
+#pragma unroll
+            for (int q = 0; q < 2 * N; ++q) {
+                const double tmp = B[k][q];
+                B[k][q] = B[r][q];
+                B[r][q] = tmp;
+            }
+        }
+        const double inv = 1.0 / B[k][k];
+#pragma unroll
+        for (int q = 0; q < 2 * N; ++q) B[k][q] *= inv;
+#pragma unroll
+        for (int r = 0; r < N; ++r) {
+            if (r == k) continue;
+            const double f = B[r][k];
+#pragma unroll
+            for (int q = 0; q < 2 * N; ++q) B[r][q] -= f * B[k][q];
+        }
+    }
+    double* out = blk + ((size_t)((int64_t)a * Nc + cell) * NF + ln) * (N * N);
+#pragma unroll
+    for (int i = 0; i < N; ++i)
+#pragma unroll
+        for (int j = 0; j < N; ++j) out[i * N + j] = B[i][N + j];
+}
+
+// Apply: z = P^{-1} (s v), s = *scale (1 when scale is null), per velocity
+// component; the own cells staged in LDS, one pass per direction, one work
+// item per (cell, component, line), scaled by D between the passes.
+template <int DIM, int N>
+__global__ __launch_bounds__(256) void k_mom_lineprec(const double* __restrict__ blk,
+                                                       const double* __restrict__ d,
+                                                       const double* __restrict__ v,
+                                                       const double* __restrict__ scale,
+                                                       double* __restrict__ z, int Nc) {
+    using L = Lay<DIM, N>;
+    using F = FaceLay<DIM, N>;
+    constexpr int NB = F::NB, NF = F::NF, CPB = F::CPB;
+    constexpr int NBP = NB + NB / N;
+    __shared__ double s_v[DIM][CPB * NBP];
+    const int tid = threadIdx.x;
+    const int lc = tid / NB, nd = tid % NB;
+    const int cell = blockIdx.x * CPB + lc;
+    const bool active = lc < CPB && cell < Nc;
+    const int pi = lc * NBP + nd + nd / N;
+    const double sc = scale ? scale[0] : 1.0;
+    double dn = 0.0;
+    if (lc < CPB) {
+        dn = active ? d[(size_t)cell * NB + nd] : 0.0;
+#pragma unroll
+        for (int c = 0; c < DIM; ++c)
+            s_v[c][pi] = active ? sc * v[((size_t)cell * DIM + c) * NB + nd] : 0.0;
+    }
+#pragma unroll
+    for (int a = 0; a < DIM; ++a) {
+        __syncthreads();
+        constexpr int ITEMS = CPB * DIM * NF;
+        for (int it = tid; it < ITEMS; it += 256) {
+            const int lc2 = it / (DIM * NF);
+            const int c = (it % (DIM * NF)) / NF, ln = it % NF;
+            const int cell2 = blockIdx.x * CPB + lc2;
+            if (cell2 >= Nc) continue;
+            const double* Bi = blk + ((size_t)((int64_t)a * Nc + cell2) * NF + ln) * (N * N);
+            double x[N];
+#pragma unroll
+            for (int m = 0; m < N; ++m) {
+                const int nm = L::node(a, m, ln);
+                x[m] = s_v[c][lc2 * NBP + nm + nm / N];
+            }
+#pragma unroll
+            for (int i = 0; i < N; ++i) {
+                double acc = 0.0;
+#pragma unroll
+                for (int j = 0; j < N; ++j) acc += Bi[i * N + j] * x[j];
+                const int nm = L::node(a, i, ln);
+                s_v[c][lc2 * NBP + nm + nm / N] = acc;
+            }
+        }
+        __syncthreads();
+        if (a + 1 < DIM && lc < CPB) {
+#pragma unroll
+            for (int c = 0; c < DIM; ++c) s_v[c][pi] *= dn;
+        }
+    }
+    if (active) {
+#pragma unroll
+        for (int c = 0; c < DIM; ++c) z[((size_t)cell * DIM + c) * NB + nd] = s_v[c][pi];
     }
 }
 
@@ -1076,7 +1273,9 @@ int launch_apply_momentum_fused(const tbdg_ctx* c, int st, const double* w, cons
     // algorithmic bytes: read u and w, write y; fused: the inverse diagonal
     // and the basis vectors of the dots
     double bytes = 24.0 * (double)c->Nu;
-    if (fz.invd) bytes += 8.0 * (double)c->Ns + 8.0 * fz.ndot * (double)c->Nu;
+    if (fz.invd) bytes += 8.0 * (double)c->Ns;
+    if (fz.shv) bytes += 8.0 * (double)c->Nu;
+    bytes += 8.0 * fz.ndot * (double)c->Nu;
 #define L_(D, N)                                                                           \
     {                                                                                      \
         using FL = FaceLay<D, N>;                                                          \
@@ -1098,7 +1297,7 @@ int launch_apply_momentum_fused(const tbdg_ctx* c, int st, const double* w, cons
 
 void launch_apply_momentum(const tbdg_ctx* c, int st, const double* w, const double* u, double* y) {
     launch_apply_momentum_fused(c, st, w, u, y,
-                                MomFuse{nullptr, nullptr, 0.0, nullptr, 0, 0, nullptr});
+                                MomFuse{nullptr, nullptr, 0.0, nullptr, 0, 0, nullptr, nullptr});
 }
 
 void launch_rhs_lines(const tbdg_ctx* c, double mcoef, const double* u_prev, const double* u1,
@@ -1125,6 +1324,35 @@ void launch_rhs_p_lines(const tbdg_ctx* c, double alpha, double fcoef, const dou
         hipLaunchKernelGGL((k_rhs_p_lines<D, N>), dim3(nblk(c->Nc, FL::CPB)), dim3(FL::THREADS), \
                            0, c->stream, c->geom, c->lgeom, c->tab, alpha, fcoef, u_ss, p_prev, \
                            rhs, (int)c->Nc);                                               \
+    }
+    TBDG_LINE_DISPATCH(c, L_);
+#undef L_
+    TBDG_HIP(hipGetLastError());
+}
+
+void launch_mom_lineblk(const tbdg_ctx* c, int st, const double* w, const double* d,
+                        double* blk) {
+    const double theta = c->theta[st];
+    const Bnd bd = c->bnd(st);
+#define L_(D, N)                                                                           \
+    {                                                                                      \
+        const int64_t items = c->Nc * D * ipow(N, D - 1);                                  \
+        hipLaunchKernelGGL((k_mom_lineblk<D, N>), dim3((unsigned)((items + 255) / 256)),    \
+                           dim3(256), 0, c->stream, c->geom, c->lgeom, c->line_u, c->tab,   \
+                           c->cr_u, theta * c->nu, theta, w, d, blk, (int)c->Nc, bd);       \
+    }
+    TBDG_LINE_DISPATCH(c, L_);
+#undef L_
+    TBDG_HIP(hipGetLastError());
+}
+
+void launch_mom_lineprec(const tbdg_ctx* c, const double* blk, const double* d, const double* v,
+                         const double* scale, double* z) {
+#define L_(D, N)                                                                           \
+    {                                                                                      \
+        using FL = FaceLay<D, N>;                                                          \
+        hipLaunchKernelGGL((k_mom_lineprec<D, N>), dim3(nblk(c->Nc, FL::CPB)),              \
+                           dim3(FL::THREADS), 0, c->stream, blk, d, v, scale, z, (int)c->Nc); \
     }
     TBDG_LINE_DISPATCH(c, L_);
 #undef L_

@@ -43,6 +43,19 @@ double norm2(tbdg_ctx* c, int64_t n, const double* x) {
 // Jacobi-scaled operator is one)
 constexpr double kArnoldiShift = 1.0;
 
+}  // namespace
+
+// storage of the line-block preconditioner (allocated on first use)
+void ensure_mom_blk(tbdg_ctx* c) {
+    if (c->mom_blk) return;
+    const int64_t nf = c->Nc * c->dim * (c->nbu / c->n) * c->n * c->n;
+    void* p = nullptr;
+    TBDG_HIP(hipMalloc(&p, sizeof(double) * nf));
+    c->mom_blk = static_cast<double*>(p);
+}
+
+namespace {
+
 struct MomentumOp {
     tbdg_ctx* c;
     int s;
@@ -58,8 +71,13 @@ tbdg_status solve_momentum(tbdg_ctx* c, int s, const double* w, const double* b,
     const int64_t n = c->Nu;
     const int m = std::min(o.restart > 0 ? o.restart : 30, c->gm_m);
     MomentumOp A{c, s, w};
+    const bool line = o.precond == TBDG_PRECOND_LINE;
     launch_diag_momentum(c, s, w, c->diag_u);
     vec_recip(c->stream, c->Ns, c->diag_u, c->invd_u);
+    if (line) {
+        ensure_mom_blk(c);
+        launch_mom_lineblk(c, s, w, c->diag_u, c->mom_blk);
+    }
     const double bnorm = norm2(c, n, b);
     tbdg_solve_info inf{0, 0.0, 0.0, 0};
     if (bnorm == 0.0) {
@@ -118,16 +136,25 @@ tbdg_status solve_momentum(tbdg_ctx* c, int s, const double* w, const double* b,
             ++total;
             double* vj = V + (int64_t)j * ld;
             double* vn = V + (int64_t)(j + 1) * ld;
-            // vn = (A D^{-1} - sigma) (gsc_j V_j): the Arnoldi process runs on
+            // vn = (A P^{-1} - sigma) (gsc_j V_j), P the Jacobi diagonal (applied
+            // inside the operator kernel) or the line-block preconditioner
+            // (applied by its own kernel into gz): the Arnoldi process runs on
             // the shifted operator, whose Krylov spaces are the same; with the
-            // Jacobi-scaled operator close to the identity the shift removes
+            // preconditioned operator close to the identity the shift removes
             // most of the cancellation, so one Gram-Schmidt pass is normally
             // enough.  The first dots with V_0 .. V_j come out of the
             // operator kernel when they fit.
             const bool fused = j + 1 <= MOM_FUSE_MAX_DOTS;
-            const MomFuse fz{c->invd_u, gsc + j, kArnoldiShift, V, ld, fused ? j + 1 : 0,
-                             c->gm_part};
-            const int Gop = launch_apply_momentum_fused(c, s, w, vj, vn, fz);
+            MomFuse fz{c->invd_u, gsc + j, kArnoldiShift, V, ld, fused ? j + 1 : 0,
+                       c->gm_part, nullptr};
+            const double* opnd = vj;
+            if (line) {
+                launch_mom_lineprec(c, c->mom_blk, c->diag_u, vj, gsc + j, c->gz);
+                opnd = c->gz;
+                fz.invd = nullptr;
+                fz.shv = vj;
+            }
+            const int Gop = launch_apply_momentum_fused(c, s, w, opnd, vn, fz);
             // classical Gram-Schmidt, repeated only when cancellation is large
             std::fill(h.begin(), h.end(), 0.0);
             double nn = 0.0;
@@ -187,8 +214,12 @@ tbdg_status solve_momentum(tbdg_ctx* c, int s, const double* w, const double* b,
             std::memcpy(c->host_out, y.data(), sizeof(double) * k);
             TBDG_HIP(hipMemcpyAsync(c->red_out, c->host_out, sizeof(double) * (2 * k + 1),
                                     hipMemcpyHostToDevice, c->stream));
-            gm_restart(c, n, k, V, ld, c->red_out, c->red_out + k, gsc, c->invd_u, x,
-                       c->red_out + 63, gsc);
+            gm_restart(c, n, k, V, ld, c->red_out, c->red_out + k, gsc, line ? nullptr : c->invd_u,
+                       x, c->red_out + 63, gsc, line ? c->gz : nullptr);
+            if (line) {
+                launch_mom_lineprec(c, c->mom_blk, c->diag_u, c->gz, nullptr, c->gv);
+                vec_axpby(c->stream, n, 1.0, x, 1.0, c->gv, x);
+            }
             beta = std::sqrt(mirrored(c, c->red_out + 63));
             true_res = false;
             continue;
@@ -199,7 +230,12 @@ tbdg_status solve_momentum(tbdg_ctx* c, int s, const double* w, const double* b,
                                     hipMemcpyHostToDevice, c->stream));
             TBDG_HIP(hipMemsetAsync(c->gz, 0, sizeof(double) * n, c->stream));
             vec_add_combo(c->stream, n, k, V, ld, c->red_out, gsc, c->gz);
-            vec_add_div_diag_u(c->stream, n, c->dim, c->nbu, c->gz, c->diag_u, x);
+            if (line) {
+                launch_mom_lineprec(c, c->mom_blk, c->diag_u, c->gz, nullptr, c->gv);
+                vec_axpby(c->stream, n, 1.0, x, 1.0, c->gv, x);
+            } else {
+                vec_add_div_diag_u(c->stream, n, c->dim, c->nbu, c->gz, c->diag_u, x);
+            }
         }
         true_residual();
         if (breakdown && beta > o.tol * bnorm) {

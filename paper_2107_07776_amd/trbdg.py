@@ -30,12 +30,12 @@ EXPORTED = [
     "tbdg_net_mse", "tbdg_net_adam_step", "tbdg_set_guess_net", "tbdg_guess_reset",
     "tbdg_guess_record", "tbdg_guess_recorded", "tbdg_guess_features", "tbdg_guess_inject",
     "tbdg_guess_last", "tbdg_face_qpoints", "tbdg_set_dirichlet", "tbdg_set_nonlinear",
-    "tbdg_nonlinear_solves", "tbdg_profile_bytes",
+    "tbdg_nonlinear_solves", "tbdg_profile_bytes", "tbdg_precond_momentum",
 ]
 
 GUESS = {"given": 0, "previous": 1, "learned": 2}
 
-PRECOND = {"jacobi": 0, "mg_fp32": 1, "mg_bf16": 2}
+PRECOND = {"jacobi": 0, "mg_fp32": 1, "mg_bf16": 2, "line": 3}
 
 
 class TrbdgError(RuntimeError):
@@ -141,6 +141,7 @@ def load_library(path=LIB_PATH):
         "tbdg_set_nonlinear": ([vp, i, d], i),
         "tbdg_nonlinear_solves": ([vp, P(i)], i),
         "tbdg_profile_bytes": ([vp, i, P(d)], i),
+        "tbdg_precond_momentum": ([vp, i, vp, vp, vp], i),
         "tbdg_guess_features": ([vp, i, vp, vp, vp, d, vp, d, vp, P(d)], i),
         "tbdg_guess_inject": ([vp, i, vp, vp, vp, d, vp], i),
     }
@@ -266,6 +267,13 @@ class Context:
                                                  _ptr(self._vec(u, self.N_u, "u")), _ptr(out)))
         return out
 
+    def precond_momentum(self, stage, w, v, out=None):
+        """z = P^{-1} v with the line-block preconditioner of V_s(w)."""
+        out = self.empty_u() if out is None else self._vec(out, self.N_u, "out")
+        self._check(self.lib.tbdg_precond_momentum(self.h, stage, _ptr(self._vec(w, self.N_u, "w")),
+                                                   _ptr(self._vec(v, self.N_u, "v")), _ptr(out)))
+        return out
+
     def apply_pressure(self, stage, p, out=None):
         out = self.empty_p() if out is None else self._vec(out, self.N_p, "out")
         self._check(self.lib.tbdg_apply_pressure(self.h, stage, _ptr(self._vec(p, self.N_p, "p")), _ptr(out)))
@@ -306,8 +314,10 @@ class Context:
                                                _ptr(self._vec(p_prev, self.N_p, "p_prev")), _ptr(out)))
         return out
 
-    def solve_momentum(self, stage, w, rhs, u_inout, tol=1e-8, maxiter=1000, restart=30, check=True):
-        o = solver_opts(tol, maxiter, restart)
+    def solve_momentum(self, stage, w, rhs, u_inout, tol=1e-8, maxiter=1000, restart=30, check=True,
+                       precond="jacobi"):
+        """GMRES(restart) with the Jacobi or the line-block ("line") preconditioner."""
+        o = solver_opts(tol, maxiter, restart, precond)
         info = SolveInfo()
         st = self.lib.tbdg_solve_momentum(self.h, stage, _ptr(self._vec(w, self.N_u, "w")),
                                           _ptr(self._vec(rhs, self.N_u, "rhs")),
@@ -330,14 +340,15 @@ class Context:
 
     def step(self, u, u_hist, p, t=0.0, n=0, mom_tol=1e-8, prs_tol=1e-8, mom_maxiter=1000,
              prs_maxiter=5000, restart=30, precond="jacobi", guess="given", mom_guess="given",
-             check=True):
+             check=True, mom_precond="jacobi"):
         """One TR-BDF2 step in place on (u, u_hist, p); returns per-solve info.
         ``precond`` selects the pressure preconditioner, ``guess`` the initial
         guess of the pressure solves ("given": previous pressure, "previous":
-        rescaled newest increment, "learned": the attached network)."""
+        rescaled newest increment, "learned": the attached network),
+        ``mom_precond`` the momentum preconditioner ("jacobi" or "line")."""
         S = State(_ptr(self._vec(u, self.N_u, "u")), _ptr(self._vec(u_hist, self.N_u, "u_hist")),
                   _ptr(self._vec(p, self.N_p, "p")), float(t), int(n))
-        mo = solver_opts(mom_tol, mom_maxiter, restart, guess=mom_guess)
+        mo = solver_opts(mom_tol, mom_maxiter, restart, mom_precond, guess=mom_guess)
         po = solver_opts(prs_tol, prs_maxiter, 0, precond, guess)
         infos = (SolveInfo * 4)()
         st = self.lib.tbdg_step(self.h, ctypes.byref(S), ctypes.byref(mo), ctypes.byref(po), infos)
