@@ -376,7 +376,8 @@ TBDG_API tbdg_status tbdg_step(tbdg_ctx* ctx, tbdg_state* state, const tbdg_solv
  * inside a cell (D on the diagonal, the couplings of direction a off it:
  * stiffness, advection volume term and the own-trace parts of the SIP and
  * Lax-Friedrichs face terms of eqs. bilin_diff and trilinear).  Builds the
- * inverse blocks for w, then applies them.  w, v, z: N_u (device); v and z
+ * inverse blocks for w (computed in FP64, stored in FP32), then applies
+ * them in FP64.  w, v, z: N_u (device); v and z
  * must not alias.  The GMRES of TBDG_PRECOND_LINE uses the same operator
  * (right preconditioning).                                                  */
 TBDG_API tbdg_status tbdg_precond_momentum(tbdg_ctx* ctx, int stage, const double* w,

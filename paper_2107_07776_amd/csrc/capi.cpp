@@ -67,7 +67,8 @@ void free_all(tbdg_ctx* c) {
     dfree(c->diag_u);
     dfree(c->V);
     dfree(c->gsc);
-    dfree(c->mom_blk);
+    if (c->mom_blk) (void)hipFree(c->mom_blk);
+    c->mom_blk = nullptr;
     dfree(c->gm_part);
     dfree(c->gv);
     dfree(c->gz);

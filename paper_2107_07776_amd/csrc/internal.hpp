@@ -223,7 +223,7 @@ struct tbdg_ctx {
     double* gv = nullptr;       // Nu scratch
     double* gz = nullptr;       // Nu scratch
     double* gsc = nullptr;      // inverse norms of the Krylov vectors (gm_m + 1)
-    double* mom_blk = nullptr;  // inverse line blocks of the momentum preconditioner (lazy)
+    float* mom_blk = nullptr;   // inverse line blocks of the momentum preconditioner (FP32, lazy)
     double* gm_part = nullptr;  // partials of the fused operator dots
     int64_t gm_part_len = 0;
     // CG
@@ -289,9 +289,9 @@ void launch_diag_momentum(const tbdg_ctx* c, int s, const double* w, double* d);
 // line-block preconditioner of the momentum operator: inverse blocks of the
 // stage operator (w: advector, d: Jacobi diagonal) and z = P^{-1} (scale v)
 void launch_mom_lineblk(const tbdg_ctx* c, int st, const double* w, const double* d,
-                        double* blk);
+                        float* blk);
 void ensure_mom_blk(tbdg_ctx* c);   // allocates c->mom_blk on first use
-void launch_mom_lineprec(const tbdg_ctx* c, const double* blk, const double* d, const double* v,
+void launch_mom_lineprec(const tbdg_ctx* c, const float* blk, const double* d, const double* v,
                          const double* scale, double* z);
 // sum-factorised Helmholtz right-hand side
 void launch_rhs_p_lines(const tbdg_ctx* c, double alpha, double fcoef, const double* u_ss,

@@ -476,15 +476,16 @@ __global__ __launch_bounds__(256) void k_momentum_face(Geom g, LineGeom lg, Line
 // volume term, the own-trace parts of the SIP and Lax-Friedrichs face terms,
 // Dirichlet self terms) off it.  The same for every velocity component.
 //
-// Set-up: one thread per (cell, direction, line) assembles B_a and stores
-// its inverse (Gauss-Jordan with partial pivoting) at
-// blk[((a Nc + cell) NF + line) N^2 + i N + j].
+// Set-up: one thread per (cell, direction, line) assembles B_a in FP64 and
+// stores its inverse (Gauss-Jordan with partial pivoting) rounded to FP32 at
+// blk[((a Nc + cell) NF + line) N^2 + i N + j]; the apply computes in FP64
+// with these fixed coefficients, so P^{-1} stays one linear operator.
 template <int DIM, int N>
 __global__ __launch_bounds__(256) void k_mom_lineblk(Geom g, LineGeom lg, Line1D lt, Tables t,
                                                       double Cr, double tnu, double th,
                                                       const double* __restrict__ w,
                                                       const double* __restrict__ d,
-                                                      double* __restrict__ blk, int Nc, Bnd bd) {
+                                                      float* __restrict__ blk, int Nc, Bnd bd) {
     using L = Lay<DIM, N>;
     constexpr int NB = L::NB;
     constexpr int NF = ipow(N, DIM - 1);
@@ -590,18 +591,19 @@ __global__ __launch_bounds__(256) void k_mom_lineblk(Geom g, LineGeom lg, Line1D
             for (int q = 0; q < 2 * N; ++q) B[r][q] -= f * B[k][q];
         }
     }
-    double* out = blk + ((size_t)((int64_t)a * Nc + cell) * NF + ln) * (N * N);
+    float* out = blk + ((size_t)((int64_t)a * Nc + cell) * NF + ln) * (N * N);
 #pragma unroll
     for (int i = 0; i < N; ++i)
 #pragma unroll
-        for (int j = 0; j < N; ++j) out[i * N + j] = B[i][N + j];
+        for (int j = 0; j < N; ++j) out[i * N + j] = (float)B[i][N + j];
 }
 
 // Apply: z = P^{-1} (s v), s = *scale (1 when scale is null), per velocity
 // component; the own cells staged in LDS, one pass per direction, one work
-// item per (cell, component, line), scaled by D between the passes.
+// item per (cell, line, component) with the component fastest (the threads
+// of one line read the same block), scaled by D between the passes.
 template <int DIM, int N>
-__global__ __launch_bounds__(256) void k_mom_lineprec(const double* __restrict__ blk,
+__global__ __launch_bounds__(256) void k_mom_lineprec(const float* __restrict__ blk,
                                                        const double* __restrict__ d,
                                                        const double* __restrict__ v,
                                                        const double* __restrict__ scale,
@@ -630,10 +632,10 @@ __global__ __launch_bounds__(256) void k_mom_lineprec(const double* __restrict__
         constexpr int ITEMS = CPB * DIM * NF;
         for (int it = tid; it < ITEMS; it += 256) {
             const int lc2 = it / (DIM * NF);
-            const int c = (it % (DIM * NF)) / NF, ln = it % NF;
+            const int ln = (it % (DIM * NF)) / DIM, c = it % DIM;
             const int cell2 = blockIdx.x * CPB + lc2;
             if (cell2 >= Nc) continue;
-            const double* Bi = blk + ((size_t)((int64_t)a * Nc + cell2) * NF + ln) * (N * N);
+            const float* Bi = blk + ((size_t)((int64_t)a * Nc + cell2) * NF + ln) * (N * N);
             double x[N];
 #pragma unroll
             for (int m = 0; m < N; ++m) {
@@ -644,7 +646,7 @@ __global__ __launch_bounds__(256) void k_mom_lineprec(const double* __restrict__
             for (int i = 0; i < N; ++i) {
                 double acc = 0.0;
 #pragma unroll
-                for (int j = 0; j < N; ++j) acc += Bi[i * N + j] * x[j];
+                for (int j = 0; j < N; ++j) acc += (double)Bi[i * N + j] * x[j];
                 const int nm = L::node(a, i, ln);
                 s_v[c][lc2 * NBP + nm + nm / N] = acc;
             }
@@ -1331,7 +1333,7 @@ void launch_rhs_p_lines(const tbdg_ctx* c, double alpha, double fcoef, const dou
 }
 
 void launch_mom_lineblk(const tbdg_ctx* c, int st, const double* w, const double* d,
-                        double* blk) {
+                        float* blk) {
     const double theta = c->theta[st];
     const Bnd bd = c->bnd(st);
 #define L_(D, N)                                                                           \
@@ -1346,7 +1348,7 @@ void launch_mom_lineblk(const tbdg_ctx* c, int st, const double* w, const double
     TBDG_HIP(hipGetLastError());
 }
 
-void launch_mom_lineprec(const tbdg_ctx* c, const double* blk, const double* d, const double* v,
+void launch_mom_lineprec(const tbdg_ctx* c, const float* blk, const double* d, const double* v,
                          const double* scale, double* z) {
 #define L_(D, N)                                                                           \
     {                                                                                      \

@@ -50,8 +50,8 @@ void ensure_mom_blk(tbdg_ctx* c) {
     if (c->mom_blk) return;
     const int64_t nf = c->Nc * c->dim * (c->nbu / c->n) * c->n * c->n;
     void* p = nullptr;
-    TBDG_HIP(hipMalloc(&p, sizeof(double) * nf));
-    c->mom_blk = static_cast<double*>(p);
+    TBDG_HIP(hipMalloc(&p, sizeof(float) * nf));
+    c->mom_blk = static_cast<float*>(p);
 }
 
 namespace {

@@ -4,7 +4,8 @@ z = B_z^{-1} D B_y^{-1} D B_x^{-1} v per velocity component, with D the
 diagonal of the oracle's assembled scalar stage operator V_s(w) and B_a its
 exact submatrix on the nodes of each grid line of direction a inside a cell
 (the definition, built here from the oracle's CSR matrix), against
-tbdg_precond_momentum at the FP64 operator bar; GMRES with it against the
+tbdg_precond_momentum to 1e-6 relative (the library stores the inverse
+blocks in FP32, 6e-8 relative each, applied in FP64); GMRES with it against the
 Jacobi GMRES (same tolerance, fewer iterations); steps with either agree.
 """
 import math
@@ -93,7 +94,7 @@ def test_precond_matches_line_blocks(case, stage):
         ref[:, c, :] = reference(A, dim, n, disc.Nc, V[:, c, :].reshape(-1)).reshape(disc.Nc, nb)
     ref = ref.reshape(-1)
     err = np.abs(z.cpu().numpy() - ref).max() / np.abs(ref).max()
-    assert err < 1e-12, err
+    assert err < 1e-6, err
     ctx.close()
 
 
