@@ -99,6 +99,8 @@ void free_all(tbdg_ctx* c) {
     trbdg::guess_free(c);
     dfree(c->bnd_uD[0]);
     dfree(c->bnd_uD[1]);
+    dfree(c->map_vtx);
+    dfree(c->map_gr);
 }
 
 tbdg_solver_opts defaults(const tbdg_solver_opts* o) {
@@ -145,7 +147,12 @@ tbdg_status tbdg_create(const tbdg_mesh_desc* mesh, const tbdg_disc_desc* disc, 
                 c->periodic_flags[a] = 1;
             }
         }
-        if (mesh->mapping != 0) throw Error(TBDG_EUNSUPPORTED, "only the affine box (mapping 0) is built");
+        require(mesh->mapping == 0 || mesh->mapping == 1, "mapping must be 0 (affine) or 1 (sine Q1)");
+        if (mesh->mapping == 1) {
+            if (c->dim != 2) throw Error(TBDG_EUNSUPPORTED, "Q1-mapped cells are built in 2D only");
+            require(std::isfinite(mesh->map_amp), "map_amp must be finite");
+            c->mapped = 1;
+        }
         require(disc->k_u >= 2, "velocity degree k_u must be >= 2");
         const int kmax = c->dim == 2 ? 5 : 3;
         if (disc->k_u > kmax) throw Error(TBDG_EUNSUPPORTED, "velocity degree too high for this dim");
@@ -256,6 +263,30 @@ tbdg_status tbdg_create(const tbdg_mesh_desc* mesh, const tbdg_disc_desc* disc, 
                                         c->stream));
             }
         }
+        if (c->mapped) {
+            std::vector<double> vtx, gr;
+            trbdg::build_mapped_geometry(c, mesh->map_amp, vtx, gr);
+            // the bilinear Jacobian determinant is linear in each reference
+            // coordinate: positive at the corners means positive everywhere
+            for (int64_t q = 0; q < c->Nc; ++q) {
+                const double* X = &vtx[(size_t)q * 8];
+                for (int v = 0; v < 4; ++v) {
+                    const double x0 = v & 1, x1 = v >> 1;
+                    const double j00 = (1 - x1) * (X[2] - X[0]) + x1 * (X[6] - X[4]);
+                    const double j10 = (1 - x1) * (X[3] - X[1]) + x1 * (X[7] - X[5]);
+                    const double j01 = (1 - x0) * (X[4] - X[0]) + x0 * (X[6] - X[2]);
+                    const double j11 = (1 - x0) * (X[5] - X[1]) + x0 * (X[7] - X[3]);
+                    require(j00 * j11 - j01 * j10 > 0.0, "map_amp inverts a cell");
+                }
+            }
+            c->map_vtx = dalloc((int64_t)vtx.size());
+            c->map_gr = dalloc((int64_t)gr.size());
+            TBDG_HIP(hipMemcpyAsync(c->map_vtx, vtx.data(), sizeof(double) * vtx.size(),
+                                    hipMemcpyHostToDevice, c->stream));
+            TBDG_HIP(hipMemcpyAsync(c->map_gr, gr.data(), sizeof(double) * gr.size(),
+                                    hipMemcpyHostToDevice, c->stream));
+            TBDG_HIP(hipStreamSynchronize(c->stream));
+        }
         trbdg::launch_diag_pressure(c, c->alpha(1), c->diag_p[1]);
         trbdg::launch_diag_pressure(c, c->alpha(2), c->diag_p[2]);
         trbdg::vec_recip(c->stream, c->Np, c->diag_p[1], c->invd_p[1]);
@@ -331,6 +362,11 @@ tbdg_status tbdg_face_qpoints(const tbdg_ctx* c, int64_t* n, double* xyz) {
         int64_t nf = 1;
         for (int a = 0; a < d - 1; ++a) nf *= N;
         std::vector<double> pts((size_t)c->bnd_npts * d);
+        std::vector<double> mvtx;
+        if (c->mapped) {
+            mvtx.resize((size_t)c->Nc * 8);
+            TBDG_HIP(hipMemcpy(mvtx.data(), c->map_vtx, sizeof(double) * mvtx.size(), hipMemcpyDeviceToHost));
+        }
         for (int a = 0; a < d; ++a) {
             if (c->bnd_off[a][0] < 0) continue;
             int oth[2] = {0, 0}, no = 0;
@@ -355,6 +391,20 @@ tbdg_status tbdg_face_qpoints(const tbdg_ctx* c, int64_t* n, double* xyz) {
                             pts[pt * d + b] = c->geom.lo[b] + (ci[b] + c->tab.xu[ib]) * c->geom.h[b];
                         }
                         pts[pt * d + a] = c->geom.lo[a] + (sd ? c->geom.nc[a] : 0) * c->geom.h[a];
+                        if (c->mapped) {
+                            // the bilinear image of the reference face point
+                            const int b = 1 - a;
+                            const int cell = (int)(a == 0 ? (sd ? c->geom.nc[0] - 1 : 0) + c->geom.nc[0] * tc
+                                                          : tc + c->geom.nc[0] * (sd ? c->geom.nc[1] - 1 : 0));
+                            double xi[2];
+                            xi[a] = sd;
+                            xi[b] = c->tab.xu[tt];
+                            const double* X = &mvtx[(size_t)cell * 8];
+                            const double w0 = (1 - xi[0]) * (1 - xi[1]), w1 = xi[0] * (1 - xi[1]),
+                                         w2 = (1 - xi[0]) * xi[1], w3 = xi[0] * xi[1];
+                            for (int e = 0; e < 2; ++e)
+                                pts[pt * d + e] = w0 * X[e] + w1 * X[2 + e] + w2 * X[4 + e] + w3 * X[6 + e];
+                        }
                     }
                 }
         }

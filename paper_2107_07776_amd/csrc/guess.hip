@@ -181,6 +181,8 @@ inline unsigned nb256(int64_t n) { return (unsigned)((n + 255) / 256); }
 int launch_guess_cells(const tbdg_ctx* c, const double* inc1, const double* inc2, const double* b,
                        const double* p, double c0, double c1, double cdiv, double alpha,
                        double* cells, double* partial) {
+    if (c->mapped)
+        throw Error(TBDG_EUNSUPPORTED, "the learned guess is built for affine cells only");
     const unsigned G = nb256(c->Nc);
 #define L_(D, NP)                                                                          \
     hipLaunchKernelGGL((k_guess_cells<D, NP>), dim3(G), dim3(256), 0, c->stream, (int)c->Nc,  \
@@ -201,6 +203,8 @@ void launch_guess_feat(const tbdg_ctx* c, const double* cells, const double* par
 
 void launch_guess_inject(const tbdg_ctx* c, const double* p, const double* inc2, const float* y,
                          double bdt, const double* sc, double* out) {
+    if (c->mapped)
+        throw Error(TBDG_EUNSUPPORTED, "the learned guess is built for affine cells only");
     const int64_t g = nb256(c->Np);
     const unsigned G = (unsigned)(g < 2048 ? g : 2048);
 #define L_(D, NP)                                                                          \
@@ -213,6 +217,8 @@ void launch_guess_inject(const tbdg_ctx* c, const double* p, const double* inc2,
 
 void launch_guess_target(const tbdg_ctx* c, const double* pn, const double* p, const double* inc2,
                          double inv_bdt, const double* sc, float* out) {
+    if (c->mapped)
+        throw Error(TBDG_EUNSUPPORTED, "the learned guess is built for affine cells only");
 #define L_(D, NP)                                                                          \
     hipLaunchKernelGGL((k_guess_target<D, NP>), dim3(nb256(c->Nc)), dim3(256), 0, c->stream,   \
                        (int)c->Nc, c->tab, pn, p, inc2, inv_bdt, sc, out);

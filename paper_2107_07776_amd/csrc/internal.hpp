@@ -107,6 +107,19 @@ struct MomFuse {
 };
 constexpr int MOM_FUSE_MAX_DOTS = 8;
 
+// Q1-mapped 2D mesh (device view): vertex coordinates per cell, vertex
+// v = vx + 2 vy at vtx[(cell * 4 + v) * 2 + {0, 1}]; gr[cell * 4 + 2a + s] =
+// |Gamma| / |K| of face (a, s); periodic flags and boundary-point offsets as
+// on the affine box; uD the Dirichlet data of the stage.
+struct MapMesh {
+    const double* vtx;
+    const double* gr;
+    int nc[2];
+    int per[2];
+    int64_t off[2][2];
+    const double* uD;
+};
+
 // Point index of the face point `tt` of boundary face (a, side) of `cell`.
 __host__ __device__ inline int64_t bnd_point(const Bnd& b, const Geom& g, int64_t cell, int a,
                                              int side, int tt, int nf) {
@@ -268,6 +281,11 @@ struct tbdg_ctx {
     int nl_max = 1;
     double nl_tol = 0.0;
     int nl_solves[2] = {0, 0};
+    // Q1-mapped cells (mapping 1, 2D): vertices [Nc][4][2] and face-to-cell
+    // measure ratios [Nc][4] on the device
+    int mapped = 0;
+    double* map_vtx = nullptr;
+    double* map_gr = nullptr;
     trbdg::MGData* mg = nullptr;    // multigrid hierarchy (built on first use)
     trbdg::GuessState* gs = nullptr;   // initial-guess history and network
 
@@ -328,6 +346,29 @@ class TimedLaunch {
 };
 void timer_collect(const tbdg_ctx* c);
 void timer_release(const tbdg_ctx* c);
+
+// ---- Q1-mapped cells (mapped.hip) ------------------------------------------------
+// pressure operator, mode 0 (apply), 3 (fused CG step) or 4 (fused flexible
+// CG step) with the arguments of the affine fused kernels; *G_out = blocks
+void map_apply_pressure(const tbdg_ctx* c, double alpha, const double* p, double* y, int mode,
+                        double* partial, const double* r, const double* invd, double* sc,
+                        double* p_out, const double* up, int Gu, int first, int slot,
+                        int slot_prev, int* G_out);
+void map_diag_pressure(const tbdg_ctx* c, double alpha, double* d);
+int map_apply_momentum(const tbdg_ctx* c, int st, const double* w, const double* u, double* y,
+                       const MomFuse& fz);
+void map_diag_momentum(const tbdg_ctx* c, int st, const double* w, double* d);
+void map_rhs_momentum(const tbdg_ctx* c, double mcoef, const double* u_prev, const double* u1,
+                      const double* w1, double cd1, double ca1, const double* u2, const double* w2,
+                      double cd2, double ca2, const double* p, double* rhs);
+void map_dirichlet_rhs(const tbdg_ctx* c, int s, const double* w, double* rhs);
+void map_rhs_pressure(const tbdg_ctx* c, double alpha, double fcoef, const double* u_ss,
+                      const double* p_prev, double* rhs);
+void map_add_grad_p(const tbdg_ctx* c, const double* x, double a, const double* p, double* y);
+void map_node_coords(const tbdg_ctx* c, int field, double* xyz);
+// host set-up of the mapped geometry (setup.cpp): vertices and measure ratios
+void build_mapped_geometry(const tbdg_ctx* c, double amp, std::vector<double>& vtx,
+                           std::vector<double>& gr);
 
 // ---- vector kernels implemented in blas.hip -------------------------------------
 void vec_axpby(hipStream_t s, int64_t n, double a, const double* x, double b, const double* y, double* out);

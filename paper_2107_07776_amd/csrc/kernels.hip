@@ -245,6 +245,10 @@ void launch_rhs_momentum(const tbdg_ctx* c, double mcoef, const double* u_prev,
                          const double* u1, const double* w1, double cd1, double ca1,
                          const double* u2, const double* w2, double cd2, double ca2,
                          const double* p, double* rhs) {
+    if (c->mapped) {
+        map_rhs_momentum(c, mcoef, u_prev, u1, w1, cd1, ca1, u2, w2, cd2, ca2, p, rhs);
+        return;
+    }
     double* pv = c->s_pv;
 #define L_(D, N)                                                                          \
     {                                                                                     \
@@ -259,6 +263,10 @@ void launch_rhs_momentum(const tbdg_ctx* c, double mcoef, const double* u_prev,
 }
 
 void launch_dirichlet_rhs(const tbdg_ctx* c, int s, const double* w, double* rhs) {
+    if (c->mapped) {
+        map_dirichlet_rhs(c, s, w, rhs);
+        return;
+    }
     const Bnd bd = c->bnd(s);
     for (int a = 0; a < c->dim; ++a) {
         if (bd.off[a][0] < 0) continue;
@@ -278,6 +286,10 @@ void launch_dirichlet_rhs(const tbdg_ctx* c, int s, const double* w, double* rhs
 }
 
 void launch_add_grad_p(const tbdg_ctx* c, const double* x, double a, const double* p, double* y) {
+    if (c->mapped) {
+        map_add_grad_p(c, x, a, p, y);
+        return;
+    }
 #define L_(D, N)                                                                          \
     hipLaunchKernelGGL((k_add_grad_p<D, N>), dim3(nblocks(c->Ns, 256)), dim3(256), 0,     \
                        c->stream, c->geom, c->tab, x, a, p, y, c->Nc);
@@ -288,10 +300,18 @@ void launch_add_grad_p(const tbdg_ctx* c, const double* x, double a, const doubl
 
 void launch_rhs_pressure(const tbdg_ctx* c, double alpha, double fcoef, const double* u_ss,
                          const double* p_prev, double* rhs) {
+    if (c->mapped) {
+        map_rhs_pressure(c, alpha, fcoef, u_ss, p_prev, rhs);
+        return;
+    }
     launch_rhs_p_lines(c, alpha, fcoef, u_ss, p_prev, rhs);
 }
 
 void launch_node_coords(const tbdg_ctx* c, int field, double* xyz) {
+    if (c->mapped) {
+        map_node_coords(c, field, xyz);
+        return;
+    }
     const int64_t n = field == 0 ? c->Ns : c->Np;
 #define L_(D, N)                                                                          \
     hipLaunchKernelGGL((k_node_coords<D, N>), dim3(nblocks(n, 256)), dim3(256), 0,        \

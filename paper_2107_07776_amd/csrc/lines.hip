@@ -1154,6 +1154,11 @@ inline unsigned nblk(int64_t work, int per) { return (unsigned)((work + per - 1)
     } while (0)
 
 void launch_apply_pressure(const tbdg_ctx* c, double alpha, const double* p, double* y) {
+    if (c->mapped) {
+        map_apply_pressure(c, alpha, p, y, 0, nullptr, nullptr, nullptr, nullptr, nullptr, nullptr,
+                           0, 0, 0, 0, nullptr);
+        return;
+    }
 #define L_(D, N)                                                                           \
     {                                                                                      \
         using FL = FaceLay<D, N - 1>;                                                      \
@@ -1172,6 +1177,10 @@ void launch_apply_pressure(const tbdg_ctx* c, double alpha, const double* p, dou
 }
 
 void launch_diag_pressure(const tbdg_ctx* c, double alpha, double* d) {
+    if (c->mapped) {
+        map_diag_pressure(c, alpha, d);
+        return;
+    }
 #define L_(D, N)                                                                           \
     hipLaunchKernelGGL((k_pressure_line<D, N - 1, 1>), dim3(nblk(c->Np, 256)), dim3(256),   \
                        0, c->stream, c->geom, c->lgeom, c->line_p, c->tab,                 \
@@ -1185,6 +1194,11 @@ int launch_cg_apply(const tbdg_ctx* c, double alpha, const double* r, const doub
                     const double* p_old, double* p_new, double* q, double* sc, const double* up,
                     int Gu, int first, int slot, int slot_prev) {
     int G = 0;
+    if (c->mapped) {
+        map_apply_pressure(c, alpha, p_old, q, 3, c->red_op, r, invd, sc, p_new, up, Gu, first,
+                           slot, slot_prev, &G);
+        return G;
+    }
 #define L_(D, N)                                                                           \
     {                                                                                      \
         using FL = FaceLay<D, N - 1>;                                                      \
@@ -1247,6 +1261,11 @@ void launch_diag_pressure_level(hipStream_t s, int dim, int np, const Geom& g, c
 int launch_fcg_apply(const tbdg_ctx* c, double alpha, const double* z, const double* p_old,
                      double* p_new, double* q, double* sc) {
     int G = 0;
+    if (c->mapped) {
+        map_apply_pressure(c, alpha, p_old, q, 4, c->red_op, z, nullptr, sc, p_new, nullptr, 0, 0,
+                           0, 0, &G);
+        return G;
+    }
 #define L_(D, N)                                                                           \
     {                                                                                      \
         using FL = FaceLay<D, N - 1>;                                                      \
@@ -1271,6 +1290,7 @@ int launch_apply_momentum_fused(const tbdg_ctx* c, int st, const double* w, cons
     const Bnd bd = c->bnd(st);
     if (fz.ndot < 0 || fz.ndot > MOM_FUSE_MAX_DOTS)
         throw Error(TBDG_EINVAL, "fused dot count out of range");
+    if (c->mapped) return map_apply_momentum(c, st, w, u, y, fz);
     int G = 0;
     // algorithmic bytes: read u and w, write y; fused: the inverse diagonal
     // and the basis vectors of the dots
@@ -1334,6 +1354,8 @@ void launch_rhs_p_lines(const tbdg_ctx* c, double alpha, double fcoef, const dou
 
 void launch_mom_lineblk(const tbdg_ctx* c, int st, const double* w, const double* d,
                         float* blk) {
+    if (c->mapped)
+        throw Error(TBDG_EUNSUPPORTED, "the line preconditioner is built for affine cells only");
     const double theta = c->theta[st];
     const Bnd bd = c->bnd(st);
 #define L_(D, N)                                                                           \
@@ -1350,6 +1372,8 @@ void launch_mom_lineblk(const tbdg_ctx* c, int st, const double* w, const double
 
 void launch_mom_lineprec(const tbdg_ctx* c, const float* blk, const double* d, const double* v,
                          const double* scale, double* z) {
+    if (c->mapped)
+        throw Error(TBDG_EUNSUPPORTED, "the line preconditioner is built for affine cells only");
 #define L_(D, N)                                                                           \
     {                                                                                      \
         using FL = FaceLay<D, N>;                                                          \
@@ -1362,6 +1386,10 @@ void launch_mom_lineprec(const tbdg_ctx* c, const float* blk, const double* d, c
 }
 
 void launch_diag_momentum(const tbdg_ctx* c, int st, const double* w, double* d) {
+    if (c->mapped) {
+        map_diag_momentum(c, st, w, d);
+        return;
+    }
     const double mcoef = c->mcoef(st), theta = c->theta[st];
     const Bnd bd = c->bnd(st);
 #define L_(D, N)                                                                           \

@@ -158,3 +158,43 @@ double tbdg_ctx::alpha(int s) const {
     if (std::isinf(c)) return 0.0;
     return 1.0 / (c * c * beta[s] * beta[s] * dt * dt);
 }
+
+namespace trbdg {
+
+// Vertices of the Q1-mapped 2D mesh: the Cartesian grid point (x, y) moves
+// by amp sin(2 pi x) sin(2 pi y) in both coordinates (the distortion of the
+// Kovasznay workload; it vanishes on box edges at multiples of 1/2).  Every
+// cell keeps its own four vertices (cells at a periodic wrap keep their
+// unwrapped shape).  gr holds |Gamma| / |K| per face (a, s): the edge length
+// over the cell area, both exact for the bilinear map.
+void build_mapped_geometry(const tbdg_ctx* c, double amp, std::vector<double>& vtx,
+                           std::vector<double>& gr) {
+    const int n0 = c->geom.nc[0], n1 = c->geom.nc[1];
+    const double pi2 = 2.0 * std::acos(-1.0);
+    auto vert = [&](int i, int j, double* out) {
+        const double x = c->geom.lo[0] + i * c->geom.h[0];
+        const double y = c->geom.lo[1] + j * c->geom.h[1];
+        const double d = amp * std::sin(pi2 * x) * std::sin(pi2 * y);
+        out[0] = x + d;
+        out[1] = y + d;
+    };
+    vtx.assign((size_t)c->Nc * 8, 0.0);
+    gr.assign((size_t)c->Nc * 4, 0.0);
+    for (int j = 0; j < n1; ++j)
+        for (int i = 0; i < n0; ++i) {
+            const size_t cell = (size_t)i + (size_t)n0 * j;
+            double* X = &vtx[cell * 8];
+            for (int v = 0; v < 4; ++v) vert(i + (v & 1), j + (v >> 1), X + 2 * v);
+            // area of the quadrilateral 0-1-3-2: half the cross product of the diagonals
+            const double d1x = X[6] - X[0], d1y = X[7] - X[1];
+            const double d2x = X[4] - X[2], d2y = X[5] - X[3];
+            const double area = 0.5 * std::fabs(d1x * d2y - d1y * d2x);
+            auto len = [&](int p, int q) { return std::hypot(X[2 * q] - X[2 * p], X[2 * q + 1] - X[2 * p + 1]); };
+            gr[cell * 4 + 0] = len(0, 2) / area;   // xi0 = 0
+            gr[cell * 4 + 1] = len(1, 3) / area;   // xi0 = 1
+            gr[cell * 4 + 2] = len(0, 1) / area;   // xi1 = 0
+            gr[cell * 4 + 3] = len(2, 3) / area;   // xi1 = 1
+        }
+}
+
+}  // namespace trbdg

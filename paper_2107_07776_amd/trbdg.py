@@ -165,7 +165,8 @@ class Context:
     """One mesh + discretisation on the current HIP device and stream."""
 
     def __init__(self, dim, n_cells, lo, hi, k, nu, dt, c=1.0e3, periodic=None,
-                 gamma=0.0, pen_u=1.0, pen_p=1.0, stream=None, device="cuda"):
+                 gamma=0.0, pen_u=1.0, pen_p=1.0, stream=None, device="cuda", mapping=0,
+                 map_amp=0.0):
         self.lib = load_library()
         self.device = torch.device(device)
         if self.device.type != "cuda" or not torch.cuda.is_available():
@@ -178,8 +179,8 @@ class Context:
             m.lo[a] = float(lo[a]) if a < dim else 0.0
             m.hi[a] = float(hi[a]) if a < dim else 1.0
             m.periodic[a] = int(bool(periodic[a])) if a < dim else 1
-        m.mapping = 0
-        m.map_amp = 0.0
+        m.mapping = int(mapping)
+        m.map_amp = float(map_amp)
         dd = DiscDesc(int(k), float(nu), float(c), float(dt), float(gamma), float(pen_u), float(pen_p))
         self.stream = stream if stream is not None else torch.cuda.current_stream(self.device)
         h = ctypes.c_void_p()

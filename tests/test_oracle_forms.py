@@ -213,3 +213,77 @@ def test_projection_gives_nodal_gradient(dim, k):
     xu = d.node_coords("u")
     ref = pgrad(xu).reshape(d.Nc, d.nbu, dim).transpose(0, 2, 1).reshape(-1)
     assert np.abs(Gp - ref).max() < 1e-10 * max(1.0, np.abs(ref).max())
+
+
+# ---------------------------------------------------------------------------
+# Q1-mapped (distorted) cells: the same structural properties must survive
+# the geometry map, and affine-invariant fields must be reproduced exactly.
+# ---------------------------------------------------------------------------
+def _sine_map(amp):
+    def f(X):
+        d = amp * np.sin(2 * math.pi * X[:, 0]) * np.sin(2 * math.pi * X[:, 1])
+        return X + np.stack([d, d], axis=1)
+    return f
+
+
+def _mapped(n, k, periodic, amp=0.06, lo=(0.0, 0.0), hi=(1.0, 1.0)):
+    mesh = BoxMesh(2, (n, n), lo, hi, (periodic,) * 2, vertex_map=_sine_map(amp))
+    return Discretization(mesh, k, nu=1.0)
+
+
+@pytest.mark.parametrize("k", [2, 3, 4])
+def test_mapped_sip_symmetric_null_space(k):
+    d = _mapped(3, k, True)
+    for A in (d.sip_p().toarray(), d.sip_u().toarray()):
+        scale = np.abs(A).max()
+        assert np.abs(A - A.T).max() <= 1e-13 * scale
+        assert np.abs(A.sum(axis=1)).max() <= 1e-12 * scale
+        ev = np.linalg.eigvalsh(A)
+        assert ev[0] > -1e-12 * scale and ev[1] > 1e-6 * scale
+
+
+@pytest.mark.parametrize("k", [2, 4])
+def test_mapped_masses_measure_the_box(k):
+    """The displacement vanishes on the box edges: the masses integrate 1 to
+    the box area exactly."""
+    d = _mapped(4, k, False, lo=(-0.5, -0.5), hi=(1.0, 1.5))
+    assert abs(d.mass_u().sum() - 3.0) < 1e-13
+    assert abs(d.mass_p().sum() - 3.0) < 1e-13
+
+
+@pytest.mark.parametrize("k", [2, 3])
+def test_mapped_projection_gives_gradient_of_linear_fields(k):
+    """A physically linear pressure is bilinear in the reference coordinates
+    of a Q1 cell, so it lies in the discrete space and M^{-1} P returns its
+    constant gradient at every velocity node (a transposed inverse Jacobian
+    would not)."""
+    d = _mapped(3, k, False, amp=0.08)
+    a = np.array([0.7, -1.3])
+    p = d.node_coords("p") @ a + 0.25
+    Gp = (d.projection() @ p) / d.mass_u_vector().diagonal()
+    ref = np.tile(np.repeat(a, d.nbu), d.Nc)
+    assert np.abs(Gp - ref).max() < 1e-11
+
+
+@pytest.mark.parametrize("k", [2, 3])
+def test_mapped_weak_gradient_is_minus_divergence_transpose(k):
+    d = _mapped(3, k, True)
+    Gw = d.weak_gradient().toarray()
+    D = d.divergence().toarray()
+    assert np.abs(Gw + D.T).max() <= 1e-13 * np.abs(D).max()
+    assert np.abs(D.sum(axis=0)).max() <= 1e-13 * np.abs(D).max()
+
+
+def test_mapped_lf_conservation_and_constants():
+    """Constant advection of a constant field is exactly zero on a periodic
+    mapped mesh (the Gauss rule integrates w . adj(J)^T grad v exactly), and
+    the form conserves momentum (1^T C = 0) for any advector."""
+    d = _mapped(3, 3, True)
+    w = np.tile(np.repeat([0.8, -0.3], d.nbu), d.Nc)
+    C = d.lf_advection(w).toarray()
+    assert np.abs(C.sum(axis=1)).max() < 1e-12 * np.abs(C).max()
+    assert np.abs(C.sum(axis=0)).max() < 1e-12 * np.abs(C).max()
+    S = 0.5 * (C + C.T)
+    assert np.linalg.eigvalsh(S)[0] > -1e-12 * np.abs(C).max()
+    Cr = d.lf_advection(random_vector(d.N_u, 5)).toarray()
+    assert np.abs(Cr.sum(axis=0)).max() < 1e-12 * np.abs(Cr).max()
