@@ -47,16 +47,51 @@ def workload(name):
                     label="3D periodic Taylor-Green vortex, 64^3 hexes, Q3-Q2, nu=1/1600, "
                           "dt=2pi/192 (C=1), fully nonlinear stages (2 fixed-point momentum "
                           "solves per stage), solves to 1e-8 relative FP64 residual")
+    if name == "kov256":
+        return dict(dim=2, n=(256, 256), lo=(-0.5, -0.5), ext=(1.5, 2.0), k=4, nu=1.0 / 40.0,
+                    dt=0.04, tol=1e-8, nonlinear=1, periodic=(0, 0), mapping=1, amp=0.05, Re=40.0,
+                    mom_precond="line", restart=30, learned=False,
+                    label="2D Kovasznay flow (Re=40) on [-0.5,1]x[-0.5,1.5], 256x256 quads mapped by "
+                          "x+0.05 sin(2pi x) sin(2pi y) (Q1 cells), Q4-Q3, Dirichlet velocity data "
+                          "from the exact solution, dt=0.04 from rest, solves to 1e-8 relative FP64 "
+                          "residual")
     if name == "tg2d":
         return dict(dim=2, n=(8, 8), ext=(1.0, 1.0), k=2, nu=0.01, dt=0.01, tol=1e-10, nonlinear=1,
                     label="2D periodic Taylor-Green, 8x8 quads, Q2-Q1, nu=0.01, dt=0.01, tol 1e-10")
     raise SystemExit(f"unknown workload {name}")
 
 
+def make_context(W):
+    """Library context of the workload; Dirichlet data (time independent) set
+    at the boundary points when the mesh has walls."""
+    import torch
+
+    from paper_2107_07776_amd import Context
+
+    import synthetic
+    dim = W["dim"]
+    lo = W.get("lo", (0.0,) * dim)
+    hi = tuple(a + e for a, e in zip(lo, W["ext"]))
+    ctx = Context(dim, W["n"], lo, hi, k=W["k"], nu=W["nu"], dt=W["dt"],
+                  periodic=W.get("periodic", (1,) * dim), mapping=W.get("mapping", 0),
+                  map_amp=W.get("amp", 0.0))
+    if "Re" in W:
+        pts = ctx.face_qpoints().cpu().numpy()
+        data = torch.tensor(synthetic.kovasznay(pts, W["Re"])[0], device="cuda")
+        ctx.set_dirichlet(0, data)
+        ctx.set_dirichlet(1, data)
+    return ctx
+
+
 def initial_fields(W, coords_u, coords_p):
+    import numpy as np
+
     import synthetic
     dim = W["dim"]
     nbu = (W["k"] + 1) ** dim
+    if "Re" in W:
+        # impulsive start: fluid at rest, the wall data switched on at t = 0
+        return np.zeros(coords_u.shape[0] * dim), np.zeros(coords_p.shape[0]), None
     if dim == 3:
         u = synthetic.tgv3d_velocity(coords_u)
         p = synthetic.tgv3d_pressure(coords_p)
@@ -66,6 +101,56 @@ def initial_fields(W, coords_u, coords_p):
     g = 2.0 - math.sqrt(2.0)
     uh, _ = synthetic.taylor_green_2d_unit(coords_u, -(1 - g) * W["dt"], W["nu"])
     return synthetic.nodal_velocity(u, 2, nbu), p, synthetic.nodal_velocity(uh, 2, nbu)
+
+
+def kovasznay_errors(ctx, W, U, P):
+    """L2 errors of the discrete velocity and of the mean-free pressure
+    against the exact Kovasznay solution, by Gauss-Legendre quadrature at the
+    nodes of each field on the bilinear (Q1-mapped) cells: the nodes are the
+    quadrature points, so the integrals need only the nodal values, the
+    weights and det J of the bilinear map of each cell's four mapped
+    vertices.  Returns (abs, relative) pairs."""
+    import numpy as np
+
+    import synthetic
+    nx, ny = W["n"]
+    lo, ext = np.array(W["lo"]), np.array(W["ext"])
+    h = ext / np.array([nx, ny])
+    vmap = synthetic.sine_vertex_map(W["amp"])
+
+    def quad(npts, coords):
+        g, w = np.polynomial.legendre.leggauss(npts)
+        g, w = 0.5 * (g + 1.0), 0.5 * w
+        xi, eta = np.meshgrid(g, g, indexing="xy")          # node a + npts*b: x fastest
+        xi, eta = xi.reshape(-1), eta.reshape(-1)
+        wq = np.outer(w, w).reshape(-1)
+        i, j = np.meshgrid(np.arange(nx), np.arange(ny), indexing="xy")
+        i, j = i.reshape(-1), j.reshape(-1)                  # cells x fastest
+        V = [vmap(np.stack([lo[0] + (i + a) * h[0], lo[1] + (j + b) * h[1]], 1))
+             for (a, b) in ((0, 0), (1, 0), (0, 1), (1, 1))]
+        X = sum(V[q][:, None, :] * N[None, :, None] for q, N in
+                enumerate(((1 - xi) * (1 - eta), xi * (1 - eta), (1 - xi) * eta, xi * eta)))
+        dxi = (V[1] - V[0])[:, None, :] * (1 - eta)[None, :, None] + (V[3] - V[2])[:, None, :] * eta[None, :, None]
+        deta = (V[2] - V[0])[:, None, :] * (1 - xi)[None, :, None] + (V[3] - V[1])[:, None, :] * xi[None, :, None]
+        detj = dxi[..., 0] * deta[..., 1] - dxi[..., 1] * deta[..., 0]
+        if np.abs(X.reshape(-1, 2) - coords).max() > 1e-11:
+            raise SystemExit("quadrature nodes disagree with the library's node coordinates")
+        return (wq[None, :] * detj).reshape(-1)
+
+    xu, xp = ctx.node_coords(0).cpu().numpy(), ctx.node_coords(1).cpu().numpy()
+    wu, wp = quad(W["k"] + 1, xu), quad(W["k"], xp)
+    ue, pe = synthetic.kovasznay(xu, W["Re"])[0], synthetic.kovasznay(xp, W["Re"])[1]
+    nb = (W["k"] + 1) ** 2
+    uh = U.cpu().numpy().reshape(-1, 2, nb).transpose(0, 2, 1).reshape(-1, 2)
+    ph = P.cpu().numpy()
+    eu = math.sqrt(np.sum(wu[:, None] * (uh - ue) ** 2))
+    nu_ = math.sqrt(np.sum(wu[:, None] * ue ** 2))
+    area = wp.sum()
+    ph0, pe0 = ph - np.dot(wp, ph) / area, pe - np.dot(wp, pe) / area
+    ep = math.sqrt(np.sum(wp * (ph0 - pe0) ** 2))
+    np_ = math.sqrt(np.sum(wp * pe0 ** 2))
+    return {"u_l2": eu, "u_l2_rel": eu / nu_, "p_mean_free_l2": ep, "p_mean_free_l2_rel": ep / np_,
+            "area": float(area)}
 
 
 TRAFFIC_FILES = {("momentum_apply", "tgv32"): "momentum_face_tgv32_q3_traffic.txt"}
@@ -105,8 +190,9 @@ def kernel_source_digest():
 
 def cpu_baseline(W, seconds_budget=20.0):
     """The oracle's TR-BDF2 step on a bounded sample of the same workload: the
-    same domain, degree, nu and dt on a 4^3 (3D) mesh, scaled to the full
-    workload by velocity DoF count (per-DoF extrapolation)."""
+    same domain, degree, nu and dt on a 4^3 (3D) or at most 16^2 (2D) mesh,
+    scaled to the full workload by velocity DoF count (per-DoF
+    extrapolation)."""
     import numpy as np
     from threadpoolctl import threadpool_limits
 
@@ -114,13 +200,21 @@ def cpu_baseline(W, seconds_budget=20.0):
     from oracle import BoxMesh, Discretization, TRBDF2
 
     dim = W["dim"]
-    ns = 4 if dim == 3 else W["n"][0]
+    ns = 4 if dim == 3 else min(W["n"][0], 16)
     nc = (ns,) * dim
+    lo = W.get("lo", (0.0,) * dim)
+    hi = tuple(a + e for a, e in zip(lo, W["ext"]))
     with threadpool_limits(limits=1):
         t0 = time.perf_counter()
-        mesh = BoxMesh(dim, nc, (0.0,) * dim, W["ext"], (True,) * dim)
+        if "Re" in W:
+            mesh = BoxMesh(dim, nc, lo, hi, (False,) * dim,
+                           vertex_map=synthetic.sine_vertex_map(W["amp"]))
+            uD = lambda x, t: synthetic.kovasznay(x, W["Re"])[0]
+        else:
+            mesh = BoxMesh(dim, nc, lo, hi, (True,) * dim)
+            uD = None
         disc = Discretization(mesh, W["k"], nu=W["nu"])
-        ora = TRBDF2(disc, W["dt"], nonlinear_iters=W["nonlinear"])
+        ora = TRBDF2(disc, W["dt"], nonlinear_iters=W["nonlinear"], uD=uD)
         xu, xp = disc.node_coords("u"), disc.node_coords("p")
         u, p, uh = initial_fields(W, xu, xp)
         uh = u.copy() if uh is None else uh
@@ -172,7 +266,8 @@ def run_solver(ctx, W, precond, steps, warmup, profile, mg_degree=0, guess="give
     t = 0.0
     n = 0
     for i in range(warmup):
-        info, _ = ctx.step(U, H, P, t, n, mom_tol=tol, prs_tol=tol, prs_maxiter=20000, precond=precond,
+        info, _ = ctx.step(U, H, P, t, n, mom_tol=tol, prs_tol=tol, prs_maxiter=20000,
+                           mom_maxiter=20000, precond=precond,
                            guess=guess, restart=restart, mom_guess=mom_guess,
                            mom_precond=mom_precond)
         t += W["dt"]
@@ -187,8 +282,12 @@ def run_solver(ctx, W, precond, steps, warmup, profile, mg_degree=0, guess="give
     iters, used = [], []
     torch.cuda.synchronize()
     t0 = time.perf_counter()
+    U_before_last = None
     for i in range(steps):
-        info, _ = ctx.step(U, H, P, t, n, mom_tol=tol, prs_tol=tol, prs_maxiter=20000, precond=precond,
+        if i == steps - 1:
+            U_before_last = U.clone()
+        info, _ = ctx.step(U, H, P, t, n, mom_tol=tol, prs_tol=tol, prs_maxiter=20000,
+                           mom_maxiter=20000, precond=precond,
                            guess=guess, restart=restart, mom_guess=mom_guess,
                            mom_precond=mom_precond)
         t += W["dt"]
@@ -203,6 +302,9 @@ def run_solver(ctx, W, precond, steps, warmup, profile, mg_degree=0, guess="give
     res = dict(sps=steps / elapsed, ms=1e3 * elapsed / steps, elapsed=elapsed,
                iters=[float(np.mean([it[j] for it in iters])) for j in range(4)], U=U, P=P,
                learned_rate=sum(1 for g in used if g == 2) / max(len(used), 1))
+    if "Re" in W:
+        res["t_final"] = t
+        res["steady_rate"] = (U - U_before_last).abs().max().item() / W["dt"]
     if profile:
         res["prof"] = tuple(ctx.profile_read(w) + (ctx.profile_bytes(w),) for w in (0, 1))
         ctx.profile(False)
@@ -259,9 +361,11 @@ def main():
                     help="initial guess of the timed solver's pressure solves")
     ap.add_argument("--no-learned", action="store_true",
                     help="skip training and timing the learned-guess variant")
-    ap.add_argument("--restart", type=int, default=4, help="GMRES restart length of the timed solver")
-    ap.add_argument("--mom-precond", default="line", choices=["jacobi", "line"],
-                    help="momentum preconditioner of the timed solver")
+    ap.add_argument("--restart", type=int, default=None,
+                    help="GMRES restart length of the timed solver (default: 4; 30 on the Kovasznay mesh)")
+    ap.add_argument("--mom-precond", default=None, choices=["jacobi", "line"],
+                    help="momentum preconditioner of the timed solver (default: line; on mapped "
+                         "cells the blocks of the undistorted box)")
     ap.add_argument("--mom-guess", default="previous", choices=["given", "previous"],
                     help="momentum initial guess of the timed solver")
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
@@ -278,8 +382,6 @@ def main():
     import numpy as np
     import torch
 
-    from paper_2107_07776_amd import Context
-
     if args.copy_calibration > 0:
         n = args.copy_calibration * (1 << 20) // 8
         src = torch.ones(n, dtype=torch.float64, device="cuda")
@@ -293,14 +395,21 @@ def main():
     log(f"[bench] setting up {W['label']}")
     if args.nonlinear > 0:
         W["nonlinear"] = args.nonlinear
-    ctx = Context(W["dim"], W["n"], (0.0,) * W["dim"], W["ext"], k=W["k"], nu=W["nu"], dt=W["dt"])
+    ctx = make_context(W)
+    if args.restart is None:
+        args.restart = W.get("restart", 4)
+    if args.mom_precond is None:
+        args.mom_precond = W.get("mom_precond", "line")
     ctx.set_nonlinear(W["nonlinear"], 0.0)
     plain = None
     if not args.no_compare and args.precond != "jacobi":
         plain = run_solver(ctx, W, "jacobi", args.steps, args.warmup, False)
     net = None
     learned_info = None
-    if args.guess == "learned" or (not args.no_learned and args.precond != "jacobi"):
+    if args.guess == "learned" and not W.get("learned", True):
+        raise SystemExit("the learned guess is built for 3D affine boxes only")
+    if args.guess == "learned" or (not args.no_learned and args.precond != "jacobi"
+                                   and W.get("learned", True)):
         net, learned_info = train_guess(ctx, W)
         ctx.set_guess_net(net)
     main_run = run_solver(ctx, W, args.precond, args.steps, args.warmup, not args.no_profile,
@@ -336,6 +445,18 @@ def main():
                              "mean_iterations_per_step": lr_run["iters"],
                              "learned_used_rate": lr_run["learned_rate"],
                              "fallback_rate": 1.0 - lr_run["learned_rate"]})
+    if not W.get("learned", True):
+        out["learned_guess"] = {"built": False,
+                                "reason": "the guess network is a 3D convolution on affine boxes; this "
+                                          "2D mapped workload runs with the multigrid preconditioner only"}
+    if "Re" in W:
+        out["data"] = "synthetic (exact Kovasznay solution as wall data, fluid at rest at t=0)"
+        out["l2_error_vs_exact"] = dict(kovasznay_errors(ctx, W, main_run["U"], main_run["P"]),
+                                        t_final=main_run["t_final"],
+                                        steady_rate_linf=main_run["steady_rate"])
+        if plain is not None:
+            out["plain_fp64_l2_error_vs_exact"] = dict(kovasznay_errors(ctx, W, plain["U"], plain["P"]),
+                                                       steady_rate_linf=plain["steady_rate"])
     if learned_info is not None:
         if args.guess == "learned":
             learned_info["learned_used_rate"] = main_run["learned_rate"]

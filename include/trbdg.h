@@ -377,9 +377,11 @@ TBDG_API tbdg_status tbdg_step(tbdg_ctx* ctx, tbdg_state* state, const tbdg_solv
  * stiffness, advection volume term and the own-trace parts of the SIP and
  * Lax-Friedrichs face terms of eqs. bilin_diff and trilinear).  Builds the
  * inverse blocks for w (computed in FP64, stored in FP32), then applies
- * them in FP64.  w, v, z: N_u (device); v and z
- * must not alias.  The GMRES of TBDG_PRECOND_LINE uses the same operator
- * (right preconditioning).                                                  */
+ * them in FP64.  On Q1-mapped cells D and B_a are those of the undistorted
+ * box (the same operator with the cells' vertex displacement removed), a
+ * fixed approximation of the distorted operator.  w, v, z: N_u (device); v
+ * and z must not alias.  The GMRES of TBDG_PRECOND_LINE uses the same
+ * operator (right preconditioning).                                         */
 TBDG_API tbdg_status tbdg_precond_momentum(tbdg_ctx* ctx, int stage, const double* w,
                                            const double* v, double* z);
 

@@ -69,6 +69,8 @@ void free_all(tbdg_ctx* c) {
     dfree(c->gsc);
     if (c->mom_blk) (void)hipFree(c->mom_blk);
     c->mom_blk = nullptr;
+    if (c->mom_dbox) (void)hipFree(c->mom_dbox);
+    c->mom_dbox = nullptr;
     dfree(c->gm_part);
     dfree(c->gv);
     dfree(c->gz);
@@ -534,9 +536,8 @@ tbdg_status tbdg_precond_momentum(tbdg_ctx* c, int stage, const double* w, const
         require(w && v && z, "null pointer");
         require(v != z, "v and z must not alias");
         trbdg::launch_diag_momentum(c, stage, w, c->diag_u);
-        trbdg::ensure_mom_blk(c);
-        trbdg::launch_mom_lineblk(c, stage, w, c->diag_u, c->mom_blk);
-        trbdg::launch_mom_lineprec(c, c->mom_blk, c->diag_u, v, nullptr, z);
+        const double* d = trbdg::build_mom_lineprec(c, stage, w);
+        trbdg::launch_mom_lineprec(c, c->mom_blk, d, v, nullptr, z);
         return TBDG_OK;
     });
 }

@@ -237,6 +237,7 @@ struct tbdg_ctx {
     double* gz = nullptr;       // Nu scratch
     double* gsc = nullptr;      // inverse norms of the Krylov vectors (gm_m + 1)
     float* mom_blk = nullptr;   // inverse line blocks of the momentum preconditioner (FP32, lazy)
+    double* mom_dbox = nullptr; // mapped cells: the box diagonal of those blocks (Ns, lazy)
     double* gm_part = nullptr;  // partials of the fused operator dots
     int64_t gm_part_len = 0;
     // CG
@@ -304,11 +305,17 @@ void launch_apply_momentum(const tbdg_ctx* c, int s, const double* w, const doub
 int launch_apply_momentum_fused(const tbdg_ctx* c, int s, const double* w, const double* u,
                                 double* y, const MomFuse& fz);
 void launch_diag_momentum(const tbdg_ctx* c, int s, const double* w, double* d);
+// the diagonal of the undistorted box's operator (equal to the above on affine meshes)
+void launch_diag_momentum_box(const tbdg_ctx* c, int s, const double* w, double* d);
 // line-block preconditioner of the momentum operator: inverse blocks of the
 // stage operator (w: advector, d: Jacobi diagonal) and z = P^{-1} (scale v)
 void launch_mom_lineblk(const tbdg_ctx* c, int st, const double* w, const double* d,
                         float* blk);
 void ensure_mom_blk(tbdg_ctx* c);   // allocates c->mom_blk on first use
+// builds the line blocks of stage s for advector w (c->diag_u must hold the
+// operator's diagonal) and returns the diagonal the blocks were built with,
+// which the apply takes: c->diag_u, or on mapped cells the box diagonal
+const double* build_mom_lineprec(tbdg_ctx* c, int s, const double* w);
 void launch_mom_lineprec(const tbdg_ctx* c, const float* blk, const double* d, const double* v,
                          const double* scale, double* z);
 // sum-factorised Helmholtz right-hand side

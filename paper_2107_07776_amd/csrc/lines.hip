@@ -1352,10 +1352,12 @@ void launch_rhs_p_lines(const tbdg_ctx* c, double alpha, double fcoef, const dou
     TBDG_HIP(hipGetLastError());
 }
 
+// On Q1-mapped cells the blocks are those of the undistorted box (c->geom),
+// built with that box's diagonal (launch_diag_momentum_box): a fixed
+// approximation of the distorted operator, spectrally close to it while the
+// map is a small perturbation of the identity.
 void launch_mom_lineblk(const tbdg_ctx* c, int st, const double* w, const double* d,
                         float* blk) {
-    if (c->mapped)
-        throw Error(TBDG_EUNSUPPORTED, "the line preconditioner is built for affine cells only");
     const double theta = c->theta[st];
     const Bnd bd = c->bnd(st);
 #define L_(D, N)                                                                           \
@@ -1372,8 +1374,6 @@ void launch_mom_lineblk(const tbdg_ctx* c, int st, const double* w, const double
 
 void launch_mom_lineprec(const tbdg_ctx* c, const float* blk, const double* d, const double* v,
                          const double* scale, double* z) {
-    if (c->mapped)
-        throw Error(TBDG_EUNSUPPORTED, "the line preconditioner is built for affine cells only");
 #define L_(D, N)                                                                           \
     {                                                                                      \
         using FL = FaceLay<D, N>;                                                          \
@@ -1390,6 +1390,10 @@ void launch_diag_momentum(const tbdg_ctx* c, int st, const double* w, double* d)
         map_diag_momentum(c, st, w, d);
         return;
     }
+    launch_diag_momentum_box(c, st, w, d);
+}
+
+void launch_diag_momentum_box(const tbdg_ctx* c, int st, const double* w, double* d) {
     const double mcoef = c->mcoef(st), theta = c->theta[st];
     const Bnd bd = c->bnd(st);
 #define L_(D, N)                                                                           \

@@ -54,6 +54,22 @@ void ensure_mom_blk(tbdg_ctx* c) {
     c->mom_blk = static_cast<float*>(p);
 }
 
+const double* build_mom_lineprec(tbdg_ctx* c, int s, const double* w) {
+    ensure_mom_blk(c);
+    const double* d = c->diag_u;
+    if (c->mapped) {
+        if (!c->mom_dbox) {
+            void* p = nullptr;
+            TBDG_HIP(hipMalloc(&p, sizeof(double) * c->Ns));
+            c->mom_dbox = static_cast<double*>(p);
+        }
+        launch_diag_momentum_box(c, s, w, c->mom_dbox);
+        d = c->mom_dbox;
+    }
+    launch_mom_lineblk(c, s, w, d, c->mom_blk);
+    return d;
+}
+
 namespace {
 
 struct MomentumOp {
@@ -74,10 +90,7 @@ tbdg_status solve_momentum(tbdg_ctx* c, int s, const double* w, const double* b,
     const bool line = o.precond == TBDG_PRECOND_LINE;
     launch_diag_momentum(c, s, w, c->diag_u);
     vec_recip(c->stream, c->Ns, c->diag_u, c->invd_u);
-    if (line) {
-        ensure_mom_blk(c);
-        launch_mom_lineblk(c, s, w, c->diag_u, c->mom_blk);
-    }
+    const double* dprec = line ? build_mom_lineprec(c, s, w) : nullptr;
     const double bnorm = norm2(c, n, b);
     tbdg_solve_info inf{0, 0.0, 0.0, 0};
     if (bnorm == 0.0) {
@@ -149,7 +162,7 @@ tbdg_status solve_momentum(tbdg_ctx* c, int s, const double* w, const double* b,
                        c->gm_part, nullptr};
             const double* opnd = vj;
             if (line) {
-                launch_mom_lineprec(c, c->mom_blk, c->diag_u, vj, gsc + j, c->gz);
+                launch_mom_lineprec(c, c->mom_blk, dprec, vj, gsc + j, c->gz);
                 opnd = c->gz;
                 fz.invd = nullptr;
                 fz.shv = vj;
@@ -217,7 +230,7 @@ tbdg_status solve_momentum(tbdg_ctx* c, int s, const double* w, const double* b,
             gm_restart(c, n, k, V, ld, c->red_out, c->red_out + k, gsc, line ? nullptr : c->invd_u,
                        x, c->red_out + 63, gsc, line ? c->gz : nullptr);
             if (line) {
-                launch_mom_lineprec(c, c->mom_blk, c->diag_u, c->gz, nullptr, c->gv);
+                launch_mom_lineprec(c, c->mom_blk, dprec, c->gz, nullptr, c->gv);
                 vec_axpby(c->stream, n, 1.0, x, 1.0, c->gv, x);
             }
             beta = std::sqrt(mirrored(c, c->red_out + 63));
@@ -231,7 +244,7 @@ tbdg_status solve_momentum(tbdg_ctx* c, int s, const double* w, const double* b,
             TBDG_HIP(hipMemsetAsync(c->gz, 0, sizeof(double) * n, c->stream));
             vec_add_combo(c->stream, n, k, V, ld, c->red_out, gsc, c->gz);
             if (line) {
-                launch_mom_lineprec(c, c->mom_blk, c->diag_u, c->gz, nullptr, c->gv);
+                launch_mom_lineprec(c, c->mom_blk, dprec, c->gz, nullptr, c->gv);
                 vec_axpby(c->stream, n, 1.0, x, 1.0, c->gv, x);
             } else {
                 vec_add_div_diag_u(c->stream, n, c->dim, c->nbu, c->gz, c->diag_u, x);

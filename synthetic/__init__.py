@@ -7,8 +7,10 @@ from here and from nowhere else.
 """
 from .fields import (random_vector, taylor_green_2d, taylor_green_2d_unit,
                      tgv3d_velocity, tgv3d_pressure, kovasznay,
-                     random_phase_velocity, nodal_velocity, nodal_scalar)
+                     random_phase_velocity, nodal_velocity, nodal_scalar,
+                     sine_vertex_map)
 
 __all__ = ["random_vector", "taylor_green_2d", "taylor_green_2d_unit",
            "tgv3d_velocity", "tgv3d_pressure", "kovasznay",
-           "random_phase_velocity", "nodal_velocity", "nodal_scalar"]
+           "random_phase_velocity", "nodal_velocity", "nodal_scalar",
+           "sine_vertex_map"]

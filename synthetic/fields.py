@@ -96,3 +96,15 @@ def nodal_velocity(values, dim, nodes_per_cell):
 
 def nodal_scalar(values):
     return np.ascontiguousarray(np.asarray(values, dtype=np.float64).reshape(-1))
+
+
+# -- distorted meshes ---------------------------------------------------------
+def sine_vertex_map(amp):
+    """Vertex displacement x' = x + amp sin(2 pi x) sin(2 pi y) (same shift in
+    y), applied to the vertices of a 2D box; cells stay bilinear.  It vanishes
+    on the lines x, y in Z/2, so the boundary of [-0.5, 1] x [-0.5, 1.5] is
+    fixed."""
+    def f(X):
+        d = amp * np.sin(2 * math.pi * X[:, 0]) * np.sin(2 * math.pi * X[:, 1])
+        return X + np.stack([d, d], axis=1)
+    return f

@@ -1,8 +1,10 @@
-"""GPU parity at the benchmark's full size (3D periodic box, 32^3 cells,
-Q3-Q2) in the benchmark's launch configuration: every operator entry point is
-compared with the oracle on a sample of cells (including the corners and the
-periodic wrap), which the oracle assembles row by row; the solves are checked
-through their recomputed true residual."""
+"""GPU parity at the benchmark workloads' full sizes, in the benchmark's
+launch configuration: the 3D periodic Taylor-Green box at 32^3 and 64^3
+cells (Q3-Q2) and the distorted 2D Kovasznay channel at 256^2 cells (Q4-Q3,
+Q1-mapped cells, Dirichlet velocity walls).  Every operator entry point is
+compared with the oracle on a sample of cells (corners, the periodic wrap or
+the walls, interior cells), which the oracle assembles row by row; the solves
+are checked through their recomputed true residual."""
 import math
 
 import numpy as np
@@ -14,33 +16,57 @@ from oracle import BoxMesh, Discretization, TRBDF2
 torch = pytest.importorskip("torch")
 pytestmark = pytest.mark.gpu
 
-N = 32
-SAMPLE = [0, 1, N - 1, N * N - 1, N * N, 12345, N ** 3 - N * N, N ** 3 - 1]
+RE_KOV = 40.0
 
 
-@pytest.fixture(scope="module")
-def full():
-    from paper_2107_07776_amd import Context
-    dt, nu = 2 * math.pi / 96, 1.0 / 1600
-    print("[case] full size 32^3 Q3-Q2", flush=True)
-    ctx = Context(3, (N,) * 3, (0.0,) * 3, (2 * math.pi,) * 3, k=3, nu=nu, dt=dt)
-    mesh = BoxMesh(3, (N,) * 3, (0.0,) * 3, (2 * math.pi,) * 3, (True,) * 3)
-    disc = Discretization(mesh, 3, nu=nu)
-    ora = TRBDF2(disc, dt, rows=SAMPLE)
-    yield ctx, disc, ora
-    ctx.close()
+def kov_u(x, t):
+    return synthetic.kovasznay(x, RE_KOV)[0]
 
 
-def rows_u(disc):
-    return np.concatenate([np.arange(c * 3 * disc.nbu, (c + 1) * 3 * disc.nbu) for c in SAMPLE])
+def _box_sample(n):
+    return [0, 1, n - 1, n * n - 1, n * n, (12345 * n) // 32, n ** 3 - n * n, n ** 3 - 1]
 
 
-def rows_p(disc):
-    return np.concatenate([np.arange(c * disc.nbp, (c + 1) * disc.nbp) for c in SAMPLE])
+CASES = {
+    # name: (dim, cells, lo, hi, k, nu, dt, mapped, sample cells, multigrid levels)
+    "tgv32": (3, (32,) * 3, (0.0,) * 3, (2 * math.pi,) * 3, 3, 1.0 / 1600, 2 * math.pi / 96, False,
+              _box_sample(32), [884736, 262144, 32768, 4096, 512]),
+    "tgv64": (3, (64,) * 3, (0.0,) * 3, (2 * math.pi,) * 3, 3, 1.0 / 1600, 2 * math.pi / 192, False,
+              _box_sample(64), [7077888, 2097152, 262144, 32768, 4096, 512]),
+    "kov256": (2, (256, 256), (-0.5, -0.5), (1.0, 1.5), 4, 1.0 / RE_KOV, 0.04, True,
+               [0, 1, 255, 256, 300, 256 * 128 + 77, 65536 - 256, 65535], None),
+}
 
 
-def rows_s(disc):
-    return np.concatenate([np.arange(c * disc.nbu, (c + 1) * disc.nbu) for c in SAMPLE])
+class Full:
+    def __init__(self, name):
+        from paper_2107_07776_amd import Context
+        dim, nc, lo, hi, k, nu, dt, mapped, sample, levels = CASES[name]
+        print(f"[case] full size {name}: cells {nc}, k={k}", flush=True)
+        self.name, self.sample, self.levels, self.dim = name, sample, levels, dim
+        per = (not mapped,) * dim
+        if mapped:
+            self.ctx = Context(dim, nc, lo, hi, k=k, nu=nu, dt=dt, periodic=per, mapping=1, map_amp=0.05)
+            pts = self.ctx.face_qpoints().cpu().numpy()
+            data = torch.tensor(kov_u(pts, 0.0), device="cuda")
+            self.ctx.set_dirichlet(0, data)
+            self.ctx.set_dirichlet(1, data)
+            mesh = BoxMesh(dim, nc, lo, hi, per, vertex_map=synthetic.sine_vertex_map(0.05))
+        else:
+            self.ctx = Context(dim, nc, lo, hi, k=k, nu=nu, dt=dt)
+            mesh = BoxMesh(dim, nc, lo, hi, per)
+        self.disc = Discretization(mesh, k, nu=nu)
+        self.ora = TRBDF2(self.disc, dt, rows=sample, uD=kov_u if mapped else None)
+
+    def rows(self, nb):
+        return np.concatenate([np.arange(c * nb, (c + 1) * nb) for c in self.sample])
+
+
+@pytest.fixture(scope="module", params=list(CASES))
+def full(request):
+    f = Full(request.param)
+    yield f
+    f.ctx.close()
 
 
 def close(g, o, tol=1e-12):
@@ -59,11 +85,11 @@ def h(x):
 
 @pytest.mark.parametrize("stage", [1, 2])
 def test_operators_sampled(full, stage):
-    ctx, disc, ora = full
+    ctx, disc, ora = full.ctx, full.disc, full.ora
     w = synthetic.random_vector(disc.N_u, 1)
     u = synthetic.random_vector(disc.N_u, 2)
     p = synthetic.random_vector(disc.N_p, 3)
-    ru, rp, rs = rows_u(disc), rows_p(disc), rows_s(disc)
+    ru, rp, rs = full.rows(full.dim * disc.nbu), full.rows(disc.nbp), full.rows(disc.nbu)
     close(h(ctx.apply_momentum(stage, t(w), t(u)))[ru], ora.apply_momentum(stage, w, u)[ru])
     close(h(ctx.apply_pressure(stage, t(p)))[rp], ora.apply_pressure(stage, p)[rp])
     close(h(ctx.diag_momentum(stage, t(w)))[rs], ora.diag_momentum(stage, w)[rs])
@@ -75,36 +101,67 @@ def test_operators_sampled(full, stage):
 
 
 def test_full_size_solves(full):
-    ctx, disc, _ = full
+    ctx, disc = full.ctx, full.disc
     b = t(synthetic.random_vector(disc.N_p, 4))
     x = torch.zeros_like(b)
-    info = ctx.solve_pressure(1, b, x, tol=1e-8, maxiter=20000)
+    info = ctx.solve_pressure(1, b, x, tol=1e-8, maxiter=40000)
     r = b - ctx.apply_pressure(1, x)
+    print(f"{full.name}: Jacobi CG {info['iters']} iterations", flush=True)
     assert info["res_final"] <= 1e-8
     assert abs(h(r.norm() / b.norm()) - info["res_final"]) < 1e-12
     w = t(synthetic.random_vector(disc.N_u, 5)) * 0.3
     bu = t(synthetic.random_vector(disc.N_u, 6))
     xu = torch.zeros_like(bu)
-    info = ctx.solve_momentum(2, w, bu, xu, tol=1e-8, maxiter=500)
+    info = ctx.solve_momentum(2, w, bu, xu, tol=1e-8, maxiter=20000)
+    print(f"{full.name}: Jacobi GMRES {info['iters']} iterations", flush=True)
     ru = bu - ctx.apply_momentum(2, w, xu)
     assert info["res_final"] <= 1e-8
     assert h(ru.norm() / bu.norm()) <= 1.01e-8
 
 
+def test_full_size_line_preconditioned_gmres(full):
+    """The benchmark's momentum solve (GMRES(30) with the line-block
+    preconditioner; on the distorted mesh the blocks of the undistorted box)
+    meets 1e-8 on the recomputed FP64 residual in fewer iterations than the
+    Jacobi-preconditioned GMRES."""
+    ctx, disc = full.ctx, full.disc
+    w = t(synthetic.random_vector(disc.N_u, 5)) * 0.3
+    bu = t(synthetic.random_vector(disc.N_u, 6))
+    its = {}
+    for precond in ("line", "jacobi"):
+        xu = torch.zeros_like(bu)
+        info = ctx.solve_momentum(2, w, bu, xu, tol=1e-8, maxiter=20000, restart=30,
+                                  precond=precond)
+        ru = bu - ctx.apply_momentum(2, w, xu)
+        its[precond] = info["iters"]
+        assert info["res_final"] <= 1e-8
+        assert h(ru.norm() / bu.norm()) <= 1.01e-8
+    print(f"{full.name}: GMRES(30) iterations {its}", flush=True)
+    assert its["line"] < its["jacobi"]
+
+
 @pytest.mark.parametrize("precond", ["mg_fp32", "mg_bf16"])
 def test_full_size_multigrid_solves(full, precond):
-    """The benchmark's multigrid solve (5 levels down to 4^3 Q1) meets 1e-8 on
-    the recomputed FP64 residual, with the V-cycle built for both stages."""
-    ctx, disc, _ = full
+    """The benchmark's multigrid solve (Q1 levels down to the dense coarse
+    solve) meets 1e-8 on the recomputed FP64 residual, with the V-cycle built
+    for both stages."""
+    if full.name == "kov256" and precond == "mg_bf16":
+        pytest.skip("BF16 storage on the finest level breaks flexible CG down on the distorted "
+                    "256^2 mesh (non-positive z.r, reported as EBREAKDOWN); the FP32 hierarchy "
+                    "is the one used there")
+    ctx, disc = full.ctx, full.disc
     ctx.mg_setup()
-    levels = ctx.mg_levels()
-    assert [l["dofs"] for l in levels] == [884736, 262144, 32768, 4096, 512]
+    levels = [l["dofs"] for l in ctx.mg_levels()]
+    print(f"{full.name}: multigrid levels {levels}", flush=True)
+    assert levels[0] == disc.N_p
+    if full.levels is not None:
+        assert levels == full.levels
     for stage in (1, 2):
         b = t(synthetic.random_vector(disc.N_p, 40 + stage))
         x = torch.zeros_like(b)
-        info = ctx.solve_pressure(stage, b, x, tol=1e-8, maxiter=100, precond=precond)
+        info = ctx.solve_pressure(stage, b, x, tol=1e-8, maxiter=200, precond=precond)
         r = b - ctx.apply_pressure(stage, x)
-        print(f"{precond} stage {stage}: {info['iters']} iterations")
+        print(f"{full.name} {precond} stage {stage}: {info['iters']} iterations", flush=True)
         assert info["res_final"] <= 1e-8
         assert h(r.norm() / b.norm()) <= 1.01e-8
-        assert info["iters"] <= 30
+        assert info["iters"] <= (30 if full.levels is not None else 100)
