@@ -182,7 +182,11 @@ enum {
 enum {
     TBDG_PRECOND_JACOBI = 0,
     TBDG_PRECOND_MG_FP32 = 1,   /* h/p-multigrid V-cycle in FP32 under FP64 flexible CG */
-    TBDG_PRECOND_MG_BF16 = 2,   /* the same with BF16 storage on the finest level        */
+    TBDG_PRECOND_MG_BF16 = 2,   /* the same with BF16 storage on the finest level; if
+                                   that cycle breaks flexible CG down (z.r <= 0) or the
+                                   residual norm fails to halve over 10 steps, the
+                                   solve restarts from its true residual with the FP32
+                                   cycle (tbdg_solve_info.precond_fallbacks)            */
     TBDG_PRECOND_LINE = 3       /* momentum solves only: line-block preconditioner, see
                                    tbdg_precond_momentum                                 */
 };
@@ -199,6 +203,8 @@ typedef struct {
     double res0;        /* ||b - A x0||_2 / ||b||_2                          */
     double res_final;   /* ||b - A x||_2 / ||b||_2, recomputed at the end    */
     int guess_used;     /* TBDG_GUESS_* actually used (tbdg_step)              */
+    int precond_fallbacks; /* TBDG_PRECOND_MG_BF16: restarts with the FP32 cycle
+                              after a breakdown or stall of the BF16 one (0/1)  */
 } tbdg_solve_info;
 
 /* Momentum predictor solve (right-preconditioned restarted GMRES with CGS2

@@ -462,6 +462,10 @@ void mg_apply(tbdg_ctx* c, int s, int precision, const double* r, double* z) {
     TBDG_HIP(hipMemcpyAsync(z, c->mg->z, sizeof(double) * c->Np, hipMemcpyDeviceToDevice, c->stream));
 }
 
+// steps of the BF16-preconditioned flexible CG over which the residual norm
+// must at least halve (r.r fall by 4), else the solve switches to FP32
+constexpr int kStallWindow = 10;
+
 // Flexible CG (Polak-Ribiere beta) preconditioned by one V-cycle; FP64
 // residual, dot products, recurrences.  One host synchronisation per
 // iteration (the residual norm).
@@ -469,7 +473,7 @@ tbdg_status solve_pressure_mg(tbdg_ctx* c, int s, const double* b, double* x,
                               const tbdg_solver_opts& o, tbdg_solve_info* info) {
     if (!c->mg) mg_setup(c, nullptr);
     MGData& M = *c->mg;
-    const int prec = o.precond == TBDG_PRECOND_MG_BF16 ? 2 : 1;
+    int prec = o.precond == TBDG_PRECOND_MG_BF16 ? 2 : 1;
     const int64_t n = c->Np;
     const double alpha = c->alpha(s);
     double* r = c->cr;
@@ -477,7 +481,7 @@ tbdg_status solve_pressure_mg(tbdg_ctx* c, int s, const double* b, double* x,
     double* pa = c->cp;
     double* pb = c->cp2;
     double* sc = c->red_out + 64;
-    tbdg_solve_info inf{0, 0.0, 0.0, 0};
+    tbdg_solve_info inf{0, 0.0, 0.0, 0, 0};
     dot2(c, n, b, b, c->red_out + 63);
     TBDG_HIP(hipMemcpyAsync(c->host_out, c->red_out + 63, sizeof(double), hipMemcpyDeviceToHost, c->stream));
     TBDG_HIP(hipStreamSynchronize(c->stream));
@@ -523,8 +527,9 @@ tbdg_status solve_pressure_mg(tbdg_ctx* c, int s, const double* b, double* x,
         if (total >= o.maxiter) break;
         run_vcycle(c, s, prec, r, nullptr);
         launch_mg_beta(c->stream, M.zpart, G0, sc, 1, 8, 9);
-        bool conv = false, broke = false, nan = false;
+        bool conv = false, broke = false, nan = false, stalled = false;
         int k = 0;
+        std::vector<double> hist{rr};   // r.r after each step of this cycle
         while (total < o.maxiter) {
             ++k;
             ++total;
@@ -545,9 +550,27 @@ tbdg_status solve_pressure_mg(tbdg_ctx* c, int s, const double* b, double* x,
                 conv = true;
                 break;
             }
+            hist.push_back(rr);
+            // BF16 storage bounds how far the cycle can reduce the residual;
+            // a residual not halved over kStallWindow steps is a stall
+            if (prec == 2 && (int)hist.size() > kStallWindow &&
+                rr > 0.25 * hist[hist.size() - 1 - kStallWindow]) {
+                stalled = true;
+                break;
+            }
             if (total >= o.maxiter) break;
             run_vcycle(c, s, prec, r, q);
             launch_mg_beta(c->stream, M.zpart, G0, sc, 0, 8 + (k & 1), slot);
+        }
+        if ((broke || stalled) && prec == 2) {
+            // BF16 rounding of the finest level made the cycle non-positive
+            // for this residual, or stalled it: restart from the true
+            // residual of the current iterate (finite: a failed step only
+            // scaled p) with the FP32 cycle for the rest of the solve
+            prec = 1;
+            ++inf.precond_fallbacks;
+            TBDG_HIP(hipMemsetAsync(sc, 0, sizeof(double) * 16, c->stream));
+            continue;
         }
         if (broke) {
             st = TBDG_EBREAKDOWN;

@@ -70,11 +70,12 @@ class MGDesc(ctypes.Structure):
 
 class SolveInfo(ctypes.Structure):
     _fields_ = [("iters", ctypes.c_int), ("res0", ctypes.c_double),
-                ("res_final", ctypes.c_double), ("guess_used", ctypes.c_int)]
+                ("res_final", ctypes.c_double), ("guess_used", ctypes.c_int),
+                ("precond_fallbacks", ctypes.c_int)]
 
     def as_dict(self):
         return dict(iters=self.iters, res0=self.res0, res_final=self.res_final,
-                    guess_used=self.guess_used)
+                    guess_used=self.guess_used, precond_fallbacks=self.precond_fallbacks)
 
 
 class State(ctypes.Structure):

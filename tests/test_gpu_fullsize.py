@@ -144,11 +144,9 @@ def test_full_size_line_preconditioned_gmres(full):
 def test_full_size_multigrid_solves(full, precond):
     """The benchmark's multigrid solve (Q1 levels down to the dense coarse
     solve) meets 1e-8 on the recomputed FP64 residual, with the V-cycle built
-    for both stages."""
-    if full.name == "kov256" and precond == "mg_bf16":
-        pytest.skip("BF16 storage on the finest level breaks flexible CG down on the distorted "
-                    "256^2 mesh (non-positive z.r, reported as EBREAKDOWN); the FP32 hierarchy "
-                    "is the one used there")
+    for both stages.  On the distorted 256^2 mesh the BF16 cycle can break
+    flexible CG down (z.r <= 0); the solve then restarts with the FP32 cycle
+    and reports it in precond_fallbacks."""
     ctx, disc = full.ctx, full.disc
     ctx.mg_setup()
     levels = [l["dofs"] for l in ctx.mg_levels()]
@@ -161,7 +159,9 @@ def test_full_size_multigrid_solves(full, precond):
         x = torch.zeros_like(b)
         info = ctx.solve_pressure(stage, b, x, tol=1e-8, maxiter=200, precond=precond)
         r = b - ctx.apply_pressure(stage, x)
-        print(f"{full.name} {precond} stage {stage}: {info['iters']} iterations", flush=True)
+        print(f"{full.name} {precond} stage {stage}: {info['iters']} iterations, "
+              f"{info['precond_fallbacks']} FP32 fallbacks", flush=True)
+        assert info["precond_fallbacks"] == 0 or (precond == "mg_bf16" and info["precond_fallbacks"] == 1)
         assert info["res_final"] <= 1e-8
         assert h(r.norm() / b.norm()) <= 1.01e-8
         assert info["iters"] <= (30 if full.levels is not None else 100)
