@@ -325,7 +325,11 @@ __global__ __launch_bounds__(256) void k_map_mom(MapMesh mm, Tables t, double fa
     __shared__ double s_w[2][256];
     __shared__ double s_F[2][2][256];
     __shared__ double s_A[12][256];   // uK[2] dK[2] uN[2] dN[2] wK[2] wN[2]
-    __shared__ double s_B[6][256];    // V[2] Ga[2] Gb[2]
+    // face fluxes V[2] Ga[2] Gb[2], written between the two barriers: V and
+    // Ga over wK, wN (each thread reads only its own entries of those, and
+    // before it writes), Gb over s_u (last read before the first barrier).
+    // Keeps the block under 53 KB of LDS: three blocks per CU.
+    double* const s_B[6] = {s_A[8], s_A[9], s_A[10], s_A[11], s_u[0], s_u[1]};
     const int tid = threadIdx.x;
     const int lc = tid / NB, nd = tid % NB;
     const int cell0 = blockIdx.x * CPB;
