@@ -56,3 +56,30 @@ def test_null_arguments_are_rejected_without_a_gpu(lib_path):
     assert lib.tbdg_apply_pressure(None, 1, None, None) == -1
     assert lib.tbdg_step(None, None, None, None, None) == -1
     assert lib.tbdg_last_error(None) == b"null context"
+
+
+def test_binding_structs_match_header(tmp_path):
+    """Every struct the Python binding mirrors has the size and field offsets
+    that a C compiler gives the header's declaration."""
+    from paper_2107_07776_amd import trbdg as b
+    mirrors = {"tbdg_mesh_desc": b.MeshDesc, "tbdg_disc_desc": b.DiscDesc,
+               "tbdg_solver_opts": b.SolverOpts, "tbdg_mg_desc": b.MGDesc,
+               "tbdg_solve_info": b.SolveInfo, "tbdg_state": b.State}
+    lines = ['#include <stdio.h>', '#include <stddef.h>', f'#include "{HEADER}"', 'int main(void) {']
+    for cname, py in mirrors.items():
+        lines.append(f'  printf("{cname} size %zu\\n", sizeof({cname}));')
+        for fname, _ in py._fields_:
+            lines.append(f'  printf("{cname} {fname} %zu\\n", offsetof({cname}, {fname}));')
+    lines.append('  return 0;\n}')
+    src = tmp_path / "layout.c"
+    src.write_text("\n".join(lines) + "\n")
+    exe = tmp_path / "layout"
+    subprocess.run(["gcc", "-std=c99", "-o", str(exe), str(src)], check=True)
+    got = {}
+    for ln in subprocess.run([str(exe)], check=True, capture_output=True, text=True).stdout.splitlines():
+        cname, key, val = ln.split()
+        got[(cname, key)] = int(val)
+    for cname, py in mirrors.items():
+        assert got[(cname, "size")] == ctypes.sizeof(py), cname
+        for fname, _ in py._fields_:
+            assert got[(cname, fname)] == getattr(py, fname).offset, (cname, fname)
