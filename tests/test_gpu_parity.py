@@ -205,3 +205,35 @@ def test_taylor_green_steps_match_oracle():
     eu, ru = disc.l2_error(Ug, lambda x: synthetic.taylor_green_2d_unit(x, t, nu)[0])
     print(f"config-1 L2 velocity error vs exact after 10 steps: {eu / ru:.3e}")
     ctx.close()
+
+
+@pytest.mark.parametrize("per", [(1, 1), (0, 1)])
+def test_zero_rhs_and_exact_guess(per):
+    """Degenerate right-hand sides of every solver: b = 0 returns x = 0 with
+    no iteration whatever x held; an initial guess that already solves the
+    system (b = A x0) returns at once with x0 unchanged."""
+    from paper_2107_07776_amd import Context
+    ctx = Context(2, (8, 8), (0.0, 0.0), (1.0, 1.0), k=3, nu=0.01, dt=0.01, periodic=per)
+    try:
+        dev = torch.device("cuda:0")
+        w = torch.tensor(0.5 * synthetic.random_vector(ctx.N_u, 300), device=dev)
+        for precond in ("jacobi", "line"):
+            x = torch.tensor(synthetic.random_vector(ctx.N_u, 301), device=dev)
+            info = ctx.solve_momentum(1, w, torch.zeros_like(x), x, tol=1e-10, precond=precond)
+            assert info["iters"] == 0 and torch.count_nonzero(x).item() == 0
+            x0 = torch.tensor(synthetic.random_vector(ctx.N_u, 302), device=dev)
+            b = ctx.apply_momentum(1, w, x0)
+            x = x0.clone()
+            info = ctx.solve_momentum(1, w, b, x, tol=1e-10, precond=precond)
+            assert info["iters"] == 0 and torch.equal(x, x0)
+        for precond in ("jacobi", "mg_fp32", "mg_bf16"):
+            x = torch.tensor(synthetic.random_vector(ctx.N_p, 303), device=dev)
+            info = ctx.solve_pressure(2, torch.zeros_like(x), x, tol=1e-10, precond=precond)
+            assert info["iters"] == 0 and torch.count_nonzero(x).item() == 0
+            x0 = torch.tensor(synthetic.random_vector(ctx.N_p, 304), device=dev)
+            b = ctx.apply_pressure(2, x0)
+            x = x0.clone()
+            info = ctx.solve_pressure(2, b, x, tol=1e-10, precond=precond)
+            assert info["iters"] == 0 and torch.equal(x, x0)
+    finally:
+        ctx.close()
