@@ -407,13 +407,15 @@ TBDG_API tbdg_status tbdg_set_nonlinear(tbdg_ctx* ctx, int max_solves, double to
  * tbdg_step (also of a failed one, up to the failing solve).               */
 TBDG_API tbdg_status tbdg_nonlinear_solves(tbdg_ctx* ctx, int* solves);
 
-/* Measurement hook.  While enabled, every launch of the pressure operator
- * kernel (which = 0: tbdg_apply_pressure and the CG iterations) and of the
- * momentum operator kernel (which = 1: tbdg_apply_momentum and the GMRES
- * iterations) is bracketed by a pair of HIP events on the context's stream.
+/* Measurement hook.  While enabled, every third launch of the pressure
+ * operator kernel (which = 0: tbdg_apply_pressure and the CG iterations) and
+ * of the momentum operator kernel (which = 1: tbdg_apply_momentum and the
+ * GMRES iterations), counted per calling thread, is bracketed by a pair of
+ * HIP events on the context's stream (a timed dispatch has a cost of its
+ * own; the stride keeps the mix of plain and fused launches).
  * tbdg_profile_read synchronises on the recorded events, returns the summed
- * kernel time in milliseconds and the number of launches for `which` since
- * the previous read, and resets those counters.                           */
+ * kernel time in milliseconds and the number of timed launches for `which`
+ * since the previous read, and resets those counters.                      */
 TBDG_API tbdg_status tbdg_profile_enable(tbdg_ctx* ctx, int enable);
 TBDG_API tbdg_status tbdg_profile_read(tbdg_ctx* ctx, int which, double* total_ms,
                                        int64_t* launches);
