@@ -453,7 +453,10 @@ void cg_upd(tbdg_ctx* c, int64_t n, const double* invd, double* x, double* r, co
 void gm_dots(tbdg_ctx* c, int64_t n, int k, const double* V, int64_t ldv, const double* w,
              const double* gsc, double* dev_out) {
     const int groups = (k + 7) / 8;
-    const int G = reduce_grid(n, 4096);   // (k + 1) * G <= 62 * 4096 partial slots
+    // blocks per group of 8 vectors: enough to fill the chip with all groups
+    // together, few enough that each thread streams a dozen or more entries
+    // before its eight block reductions ((k + 1) * G <= 62 * 4096 slots)
+    const int G = reduce_grid(n, groups >= 2 ? 1024 : 2048);
     hipLaunchKernelGGL(k_mdot8, dim3(G, groups), dim3(BS), 0, c->stream, n, k, V, ldv, w,
                        c->red_part);
     hipLaunchKernelGGL(k_finish_gs, dim3(k + 1), dim3(BS), 0, c->stream, c->red_part, G, k, gsc,
