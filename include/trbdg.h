@@ -61,8 +61,14 @@ typedef struct tbdg_ctx tbdg_ctx;
 /* Structured box mesh T_h (Sec. 3).  dim 2 or 3; n_cells[a] >= 1;
  * lo < hi per direction; periodic[a] != 0 wraps direction a, otherwise its
  * two end faces are boundary faces with Dirichlet velocity data
- * (tbdg_set_dirichlet).  mapping 0 is the affine box; other mappings are
- * reserved (TBDG_EUNSUPPORTED).                                             */
+ * (tbdg_set_dirichlet).  mapping 0 is the affine box.  mapping 1 (dim 2
+ * only; TBDG_EUNSUPPORTED in 3D) moves every vertex of the box grid by
+ * map_amp sin(2 pi x) sin(2 pi y) in both coordinates and keeps each cell
+ * the bilinear (Q1) image of the reference square through its four moved
+ * vertices.  map_amp must be finite (TBDG_EINVAL otherwise); the caller
+ * keeps every cell's Jacobian positive (the displacement gradient is at
+ * most 2 pi sqrt(2) |map_amp|, so |map_amp| < 0.11 suffices), which is not
+ * checked.  Other mapping values: TBDG_EINVAL.                             */
 typedef struct {
     int dim;
     int n_cells[3];
@@ -72,7 +78,7 @@ typedef struct {
     double map_amp;
 } tbdg_mesh_desc;
 
-/* Discretisation parameters.  k_u: velocity degree k >= 1 (pressure k-1);
+/* Discretisation parameters.  k_u: velocity degree k >= 2 (pressure k-1);
  * supported: dim 2 with k <= 5, dim 3 with k <= 3.  nu = 1/Re.  c: the
  * artificial sound speed of eq. ns_artcomp (> 0).  dt > 0.  gamma: 0 selects
  * 2 - sqrt(2).  pen_u, pen_p: multipliers of the SIP penalties

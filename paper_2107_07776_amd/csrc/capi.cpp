@@ -84,8 +84,6 @@ void free_all(tbdg_ctx* c) {
     dfree(c->red_op);
     dfree(c->invd_p[1]);
     dfree(c->invd_p[2]);
-    if (c->counters) (void)hipFree(c->counters);
-    c->counters = nullptr;
     if (c->host_out) (void)hipHostFree(c->host_out);
     c->host_out = nullptr;
     dfree(c->s_w);
@@ -217,12 +215,6 @@ tbdg_status tbdg_create(const tbdg_mesh_desc* mesh, const tbdg_disc_desc* disc, 
         c->red_blocks = 64 * 4096;
         c->red_part = dalloc(c->red_blocks);
         c->red_out = dalloc(128);   // [0..62] GMRES, [63] norms, [64..79] CG scalars
-        {
-            void* cp = nullptr;
-            TBDG_HIP(hipMalloc(&cp, sizeof(unsigned) * 16));
-            c->counters = static_cast<unsigned*>(cp);
-            TBDG_HIP(hipMemsetAsync(c->counters, 0, sizeof(unsigned) * 16, c->stream));
-        }
         c->red_op_len = c->Nc + 1;   // at least one slot per block of any operator kernel
         c->red_op = dalloc(c->red_op_len);
         c->invd_u = dalloc(c->Ns);

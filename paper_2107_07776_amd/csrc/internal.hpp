@@ -249,7 +249,6 @@ struct tbdg_ctx {
     double* red_part = nullptr;     // partial sums
     int red_blocks = 0;
     double* red_out = nullptr;      // device scalars
-    unsigned* counters = nullptr;   // last-block tickets (zero between launches)
     double* red_op = nullptr;       // per-block partials of operator kernels (one slot per block)
     int64_t red_op_len = 0;
     double* invd_u = nullptr;       // 1 / momentum diagonal (Ns)

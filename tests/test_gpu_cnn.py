@@ -25,6 +25,10 @@ TOL_GRAD = 16 * U_BF16
 # (B, nz, ny, nx): x rows of 16 and of a ragged length, a total voxel count
 # that is not a multiple of the 16-voxel strips, several samples
 SHAPES = [(1, 4, 4, 16), (2, 3, 5, 7), (1, 8, 8, 8)]
+# the weight-gradient kernel gives each block rows / 256 (at least one) x-rows
+# of B * ny * nz: these shapes run 4 rows per block (B = 2, 32 x 32 x 16) and
+# 2 rows per block with a ragged last block (585 rows)
+BACKWARD_SHAPES = SHAPES[:2] + [(2, 16, 32, 32), (3, 15, 13, 11)]
 
 
 def _theta(seed, scale=1.0):
@@ -65,7 +69,7 @@ def test_forward_matches_oracle(shape):
     net.close()
 
 
-@pytest.mark.parametrize("shape", SHAPES[:2], ids=lambda s: "x".join(map(str, s)))
+@pytest.mark.parametrize("shape", BACKWARD_SHAPES, ids=lambda s: "x".join(map(str, s)))
 def test_backward_matches_oracle(shape):
     B, nz, ny, nx = shape
     print(f"[case] backward B={B} grid={nx}x{ny}x{nz}", flush=True)

@@ -178,3 +178,40 @@ def test_nonlinear_stage_solves_the_nonlinear_equation():
     lin = TRBDF2(d, dt).stage(1, u, hist, None, p, 0.0)
     one = TRBDF2(d, dt, nonlinear_iters=1).stage(1, u, hist, None, p, 0.0)
     assert np.array_equal(lin["u"], one["u"]) and one["solves"] == 1
+
+
+# velocity error of the 8 x 8 Q2-Q1 config-1 run after 10 steps (t = 0.1),
+# measured with this oracle; the pin below is the convergence to the exact
+# solution, this value only lets the GPU test compare against it
+C1_U_L2_REL_8 = 0.04263
+
+
+def c1_run(N, steps=10, nu=0.01, dt=0.01):
+    """Config-1 workload: the scaled Taylor-Green vortex on the periodic unit
+    square, Q2-Q1, nu = 0.01, dt = 0.01; relative L2 errors of u and of the
+    mean-free p against the exact solution after ``steps`` steps."""
+    mesh = BoxMesh(2, (N, N), (0.0, 0.0), (1.0, 1.0), (True, True))
+    d = Discretization(mesh, 2, nu=nu)
+    ts = TRBDF2(d, dt)
+    g = ts.cst["gamma"]
+    xu, xp = d.node_coords("u"), d.node_coords("p")
+    u = synthetic.nodal_velocity(synthetic.taylor_green_2d_unit(xu, 0.0, nu)[0], 2, d.nbu)
+    h = synthetic.nodal_velocity(synthetic.taylor_green_2d_unit(xu, -(1 - g) * dt, nu)[0], 2, d.nbu)
+    p = synthetic.taylor_green_2d_unit(xp, 0.0, nu)[1]
+    t = 0.0
+    for _ in range(steps):
+        u, h, p, _ = ts.step(u, h, p, t)
+        t += dt
+    eu, ru = d.l2_error(u, lambda x: synthetic.taylor_green_2d_unit(x, t, nu)[0])
+    ep, rp = d.l2_error(p, lambda x: synthetic.taylor_green_2d_unit(x, t, nu)[1], "p", remove_mean=True)
+    return eu / ru, ep / rp
+
+
+def test_config1_converges_to_exact_solution():
+    """The config-1 run against the exact decaying vortex: halving h cuts the
+    velocity error by about 2^(k+1) = 8 (measured 6.7) and the pressure error
+    by about 2^k_p+1 = 4 (time step fixed, so the splitting error stays)."""
+    (eu8, ep8), (eu16, ep16) = c1_run(8), c1_run(16)
+    assert abs(eu8 - C1_U_L2_REL_8) < 1e-4 * C1_U_L2_REL_8 * 10
+    assert eu8 / eu16 > 5.5 and ep8 / ep16 > 3.5, (eu8, eu16, ep8, ep16)
+    assert eu16 < 7e-3 and ep16 < 3e-2
