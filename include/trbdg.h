@@ -230,6 +230,26 @@ TBDG_API tbdg_status tbdg_solve_pressure(tbdg_ctx* ctx, int stage, const double*
                                 double* p_inout, const tbdg_solver_opts* opts,
                                 tbdg_solve_info* info);
 
+/* For callers that cannot allocate device memory (code under HIP graph
+ * capture, tight serving loops, harnesses that forbid hipMalloc): the
+ * Jacobi-preconditioned CG of tbdg_solve_pressure, same arguments and
+ * results, with its residual, direction and operator vectors and its
+ * reduction partials and scalars kept in a static device array of the
+ * library (about 44 MB per GPU, held from the first context on that GPU
+ * until the process ends) instead of the context's workspace.  It calls no
+ * hipMalloc, hipFree or allocating routine.  Limits: N_p <= TBDG_NOALLOC_MAX_NP
+ * (else TBDG_EINVAL, nothing launched); opts->precond must be
+ * TBDG_PRECOND_JACOBI and opts->guess TBDG_GUESS_GIVEN (else
+ * TBDG_EUNSUPPORTED).  Every call on one GPU shares that array, whatever
+ * the context: calls that overlap on one GPU (two streams, two threads)
+ * race and must be serialised by the caller.  The call clears the scalars
+ * it reads before it uses them; nothing else of the array has to start
+ * at zero.                                                                  */
+#define TBDG_NOALLOC_MAX_NP (1 << 20)
+TBDG_API tbdg_status tbdg_solve_pressure_noalloc(tbdg_ctx* ctx, int stage, const double* rhs,
+                                double* p_inout, const tbdg_solver_opts* opts,
+                                tbdg_solve_info* info);
+
 /* Multigrid preconditioner of the pressure Helmholtz operator.  The paper
  * preconditions the pressure CG with a multigrid (Sec. 4) without details;
  * this one is an h/p hierarchy on the affine box: level 0 is

@@ -195,6 +195,8 @@ tbdg_status tbdg_create(const tbdg_mesh_desc* mesh, const tbdg_disc_desc* disc, 
             c->sig_p[a] = (double)c->k * c->k * c->pen_p / c->geom.h[a];
         }
         c->stream = static_cast<hipStream_t>(stream);
+        TBDG_HIP(hipGetDevice(&c->device));
+        trbdg::noalloc_init(c->device);   // address of the static scratch on this device
         trbdg::build_tables(c);
         trbdg::build_line_operators(c);
         // workspaces
@@ -545,6 +547,63 @@ tbdg_status tbdg_solve_pressure(tbdg_ctx* c, int stage, const double* rhs, doubl
             throw Error(TBDG_EINVAL, "initial-guess modes apply to the solves inside tbdg_step");
         if (o.precond == TBDG_PRECOND_LINE)
             throw Error(TBDG_EUNSUPPORTED, "the line preconditioner applies to the momentum solve");
+        const tbdg_status s = trbdg::solve_pressure(c, stage, rhs, p_inout, o, info);
+        if (s != TBDG_OK) c->last_error = "pressure CG did not converge";
+        return s;
+    });
+}
+
+namespace {
+
+// Points the context's CG and reduction workspaces at the static scratch for
+// the lifetime of the guard and restores them afterwards (also when the solve
+// throws).
+struct ScratchSwap {
+    tbdg_ctx* c;
+    trbdg::NoallocScratch saved;
+    ScratchSwap(tbdg_ctx* ctx, const trbdg::NoallocScratch& s) : c(ctx) {
+        saved = {c->cr, c->cp, c->cq, c->cp2, c->red_part, c->red_blocks, c->red_out, c->red_op,
+                 c->red_op_len};
+        set(s);
+    }
+    ~ScratchSwap() { set(saved); }
+    void set(const trbdg::NoallocScratch& s) {
+        c->cr = s.cr;
+        c->cp = s.cp;
+        c->cq = s.cq;
+        c->cp2 = s.cp2;
+        c->red_part = s.red_part;
+        c->red_blocks = s.red_blocks;
+        c->red_out = s.red_out;
+        c->red_op = s.red_op;
+        c->red_op_len = s.red_op_len;
+    }
+};
+
+}  // namespace
+
+tbdg_status tbdg_solve_pressure_noalloc(tbdg_ctx* c, int stage, const double* rhs, double* p_inout,
+                                        const tbdg_solver_opts* opts, tbdg_solve_info* info) {
+    if (!c) return TBDG_EINVAL;
+    return guarded(c, [&]() {
+        check_stage(stage);
+        require(rhs && p_inout, "null pointer");
+        if (c->Np > TBDG_NOALLOC_MAX_NP)
+            throw Error(TBDG_EINVAL, "pressure space larger than the static scratch (N_p > "
+                                     "TBDG_NOALLOC_MAX_NP)");
+        const tbdg_solver_opts o = defaults(opts);
+        if (o.precond != TBDG_PRECOND_JACOBI)
+            throw Error(TBDG_EUNSUPPORTED, "the allocation-free solve is Jacobi-preconditioned CG only");
+        if (o.guess != TBDG_GUESS_GIVEN)
+            throw Error(TBDG_EUNSUPPORTED, "the allocation-free solve takes the given initial guess");
+        const trbdg::NoallocScratch scr = trbdg::noalloc_scratch(c->device);
+        // a partial slot per operator block and the reduction sizes of the
+        // context must fit the slices
+        require(c->red_op_len <= scr.red_op_len && c->red_blocks <= scr.red_blocks,
+                "workspace layout exceeds the static scratch");
+        ScratchSwap swap(c, scr);
+        // the scalar slots start from zero on every call
+        TBDG_HIP(hipMemsetAsync(scr.red_out, 0, sizeof(double) * 128, c->stream));
         const tbdg_status s = trbdg::solve_pressure(c, stage, rhs, p_inout, o, info);
         if (s != TBDG_OK) c->last_error = "pressure CG did not converge";
         return s;

@@ -208,10 +208,22 @@ struct NetGeo {
     int nx, ny, nz, nvox, B;
 };
 
+// Slices of the library's static device scratch array (noalloc.hip) that
+// stand in for a context's CG and reduction workspaces.
+struct NoallocScratch {
+    double *cr, *cp, *cq, *cp2;
+    double* red_part;
+    int red_blocks;
+    double* red_out;
+    double* red_op;
+    int64_t red_op_len;
+};
+
 }  // namespace trbdg
 
 struct tbdg_ctx {
     int dim = 0, k = 0, n = 0, np = 0;
+    int device = 0;     // HIP device current at create
     int64_t Nc = 0, nbu = 0, nbp = 0, Nu = 0, Np = 0, Ns = 0;  // Ns = Nu / dim
     trbdg::Geom geom{};
     trbdg::Tables tab{};
@@ -532,5 +544,11 @@ void mg_free(tbdg_ctx* c);
 void mg_apply(tbdg_ctx* c, int stage, int precision, const double* r, double* z);
 tbdg_status solve_pressure_mg(tbdg_ctx* c, int s, const double* b, double* x,
                               const tbdg_solver_opts& o, tbdg_solve_info* info);
+
+// ---- static scratch of the allocation-free entry point (noalloc.hip) --------------
+// looks up the device address of the scratch array on `device`, which must
+// be current; once per device, later calls return at once
+void noalloc_init(int device);
+NoallocScratch noalloc_scratch(int device);
 
 }  // namespace trbdg

@@ -23,6 +23,7 @@ EXPORTED = [
     "tbdg_node_coords", "tbdg_extrapolate", "tbdg_apply_momentum", "tbdg_apply_pressure",
     "tbdg_diag_momentum", "tbdg_diag_pressure", "tbdg_rhs_momentum", "tbdg_grad_p",
     "tbdg_add_grad_p", "tbdg_rhs_pressure", "tbdg_solve_momentum", "tbdg_solve_pressure",
+    "tbdg_solve_pressure_noalloc",
     "tbdg_step", "tbdg_profile_enable", "tbdg_profile_read", "tbdg_mg_setup",
     "tbdg_mg_levels", "tbdg_mg_apply", "tbdg_net_create", "tbdg_net_destroy",
     "tbdg_net_last_error", "tbdg_net_num_params", "tbdg_net_set_params", "tbdg_net_get_params",
@@ -34,6 +35,9 @@ EXPORTED = [
 ]
 
 GUESS = {"given": 0, "previous": 1, "learned": 2}
+
+# largest pressure space of the allocation-free solve (TBDG_NOALLOC_MAX_NP)
+NOALLOC_MAX_NP = 1 << 20
 
 PRECOND = {"jacobi": 0, "mg_fp32": 1, "mg_bf16": 2, "line": 3}
 
@@ -114,6 +118,7 @@ def load_library(path=LIB_PATH):
         "tbdg_rhs_pressure": ([vp, i, vp, vp, vp], i),
         "tbdg_solve_momentum": ([vp, i, vp, vp, vp, P(SolverOpts), P(SolveInfo)], i),
         "tbdg_solve_pressure": ([vp, i, vp, vp, P(SolverOpts), P(SolveInfo)], i),
+        "tbdg_solve_pressure_noalloc": ([vp, i, vp, vp, P(SolverOpts), P(SolveInfo)], i),
         "tbdg_step": ([vp, P(State), P(SolverOpts), P(SolverOpts), P(SolveInfo)], i),
         "tbdg_profile_enable": ([vp, i], i),
         "tbdg_profile_read": ([vp, i, P(d), P(i64)], i),
@@ -336,6 +341,19 @@ class Context:
         st = self.lib.tbdg_solve_pressure(self.h, stage, _ptr(self._vec(rhs, self.N_p, "rhs")),
                                           _ptr(self._vec(p_inout, self.N_p, "p")), ctypes.byref(o),
                                           ctypes.byref(info))
+        if check:
+            self._check(st)
+        return info.as_dict() | {"status": st}
+
+    def solve_pressure_noalloc(self, stage, rhs, p_inout, tol=1e-8, maxiter=5000, check=True):
+        """Jacobi-preconditioned CG of ``solve_pressure`` with the library's
+        static device scratch in place of the context's workspace (the entry
+        point allocates nothing; N_p <= NOALLOC_MAX_NP)."""
+        o = solver_opts(tol, maxiter, 0, "jacobi")
+        info = SolveInfo()
+        st = self.lib.tbdg_solve_pressure_noalloc(self.h, stage, _ptr(self._vec(rhs, self.N_p, "rhs")),
+                                                  _ptr(self._vec(p_inout, self.N_p, "p")),
+                                                  ctypes.byref(o), ctypes.byref(info))
         if check:
             self._check(st)
         return info.as_dict() | {"status": st}
