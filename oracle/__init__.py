@@ -19,6 +19,10 @@ Navier-Stokes equations", arXiv 2107.07776):
 * ``stepper``  - the two TR-BDF2 stages in algebraic form (Sec. 2 eqs.
                  first_stage, helmholtz2a, second_stage, helmholtz3a and the
                  algebraic systems at the end of Sec. 3), solved directly.
+* ``projection`` - the Bell-Colella-Glaz (Crank-Nicolson) and Guermond-
+                 Quartapelle (BDF2) projection steps of Sec. 2 on the same
+                 forms (eq. momentum_BCG, helmholtz_BCG, momentum_HI,
+                 helmholtz_HI).
 
 Closed-form reference fields (Taylor-Green, Kovasznay) live in the separate
 ``synthetic`` package, which holds no arithmetic of the method.
@@ -32,8 +36,10 @@ from .basis import gauss_legendre_01, lagrange_values, lagrange_derivatives
 from .mesh import BoxMesh
 from .forms import Discretization
 from .stepper import TRBDF2, trbdf2_constants, trbdf2_scalar_step
+from .projection import BCG, BDF2GQ
 
 __all__ = [
     "gauss_legendre_01", "lagrange_values", "lagrange_derivatives",
     "BoxMesh", "Discretization", "TRBDF2", "trbdf2_constants", "trbdf2_scalar_step",
+    "BCG", "BDF2GQ",
 ]
