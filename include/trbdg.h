@@ -183,7 +183,8 @@ TBDG_API tbdg_status tbdg_rhs_pressure(tbdg_ctx* ctx, int stage, const double* u
 enum {
     TBDG_GUESS_GIVEN = 0,       /* the content of x_inout (in tbdg_step: the previous pressure) */
     TBDG_GUESS_PREVIOUS = 1,    /* tbdg_step only: previous pressure + same stage's last increment */
-    TBDG_GUESS_LEARNED = 2      /* tbdg_step only: the guess network, TBDG_GUESS_PREVIOUS as fallback */
+    TBDG_GUESS_LEARNED = 2,     /* tbdg_step only: the guess network, TBDG_GUESS_PREVIOUS as fallback */
+    TBDG_GUESS_EXTRAP2 = 3      /* tbdg_step only: previous pressure + 2 inc_2 - inc_4 (pressure only) */
 };
 enum {
     TBDG_PRECOND_JACOBI = 0,
@@ -294,8 +295,8 @@ TBDG_API tbdg_status tbdg_mg_apply(tbdg_ctx* ctx, int stage, int precision, cons
                                    double* z);
 
 /* Learned initial guess of the pressure solves: a small 3D convolutional
- * network on the cell grid (not part of the paper).  Layers 3 -> 32 -> 32 ->
- * 32 -> 1, 3x3x3 kernels, circular padding, ReLU between layers; bf16
+ * network on the cell grid (not part of the paper).  Layers 6 -> 32 -> 32 ->
+ * 32 -> 2, 3x3x3 kernels, circular padding, ReLU between layers; bf16
  * weights and activations with FP32 accumulation (matrix cores), FP32
  * master parameters and Adam.  Parameters are one flat FP32 vector
  * [W0, b0, W1, b1, W2, b2, W3, b3], each W laid out [out][in][dz][dy][dx];
@@ -305,9 +306,10 @@ TBDG_API tbdg_status tbdg_mg_apply(tbdg_ctx* ctx, int stage, int precision, cons
  * All arrays are device pointers; work is enqueued on the network's stream. */
 typedef struct tbdg_net tbdg_net;
 
-/* channels must be 32.  Weights He-uniform U(-a, a), a = sqrt(6 / (27 in)),
- * drawn from SplitMix64 outputs from state `seed` (top 53 bits scaled to
- * [0, 1)); biases zero; Adam moments zero.                                  */
+/* channels must be 32.  Weights of the three hidden layers He-uniform
+ * U(-a, a), a = sqrt(6 / (27 in)), drawn from SplitMix64 outputs from state
+ * `seed` (top 53 bits scaled to [0, 1)), layer after layer; the output
+ * layer's weights, every bias and the Adam moments zero.                   */
 TBDG_API tbdg_status tbdg_net_create(int channels, uint64_t seed, void* hip_stream, tbdg_net** out);
 TBDG_API void tbdg_net_destroy(tbdg_net* net);
 TBDG_API const char* tbdg_net_last_error(const tbdg_net* net);
@@ -317,8 +319,8 @@ TBDG_API tbdg_status tbdg_net_set_params(tbdg_net* net, const float* theta);
 TBDG_API tbdg_status tbdg_net_get_params(tbdg_net* net, float* theta);
 TBDG_API tbdg_status tbdg_net_get_grads(tbdg_net* net, float* grads);
 TBDG_API tbdg_status tbdg_net_zero_grad(tbdg_net* net);
-/* y = net(x): x FP32 [B][3][nz][ny][nx] (rounded to bf16), y FP32
- * [B][nz][ny][nx].  nx <= 93.  Keeps the activations for tbdg_net_backward.  */
+/* y = net(x): x FP32 [B][6][nz][ny][nx] (rounded to bf16), y FP32
+ * [B][2][nz][ny][nx].  nx <= 93.  Keeps the activations for tbdg_net_backward. */
 TBDG_API tbdg_status tbdg_net_forward(tbdg_net* net, const float* x, float* y, int B, int nx, int ny,
                                       int nz);
 /* Adds d(sum dy * y)/d(theta) of the last forward to the gradients; dy has
@@ -327,54 +329,73 @@ TBDG_API tbdg_status tbdg_net_backward(tbdg_net* net, const float* dy);
 /* dy = 2 (yhat - target) / n; *loss (host, may be NULL) = mean squared error. */
 TBDG_API tbdg_status tbdg_net_mse(tbdg_net* net, const float* yhat, const float* target, int64_t n,
                                   float* dy, double* loss);
+/* The guess's training loss: yhat FP32 [B][2][n] (the blend (y0, y1) of each
+ * of n cells), gram FP32 [B][6][n] (g11, g12, g22, r1, r2, ee per cell, as
+ * recorded by tbdg_guess_record); per cell
+ *   l = ee - 2 (y0 r1 + y1 r2) + y0^2 g11 + 2 y0 y1 g12 + y1^2 g22,
+ * *loss (host, may be NULL) = mean of l over the B n cells, dy [B][2][n] its
+ * gradient with respect to yhat.                                            */
+TBDG_API tbdg_status tbdg_net_quad_loss(tbdg_net* net, const float* yhat, const float* gram, int64_t n,
+                                        int B, float* dy, double* loss);
 /* One Adam step (Kingma and Ba, with bias correction) on the master
  * parameters from the accumulated gradients.                                */
 TBDG_API tbdg_status tbdg_net_adam_step(tbdg_net* net, float lr, float beta1, float beta2, float eps);
 
 /* Initial guesses of the Helmholtz solves in tbdg_step (not part of the
- * paper).  The context keeps the two newest pressure increments p_new - p_prev
- * of its solves (inc_1 the newest, from the other stage; inc_2 from the same
- * stage one step earlier) and their stage weights beta.  For the stage-s
- * solve with right-hand side b and previous pressure p:
- *   TBDG_GUESS_PREVIOUS: p + inc_2;
- *   TBDG_GUESS_LEARNED:  per cell K the network input is
- *     (f0 / s_inc, f1 / s_inc, div / s_div),  f0 = mean_K(inc_1) / (beta_1 dt),
- *     f1 = mean_K(inc_2) / (beta_2 dt), div = -(beta_s dt / |K|) sum_{i in K}
- *     (b_i - alpha_s (M^p p)_i) (cell average of div u** in flux form), mean_K
- *     the Gauss-rule cell average, s_inc and s_div the RMS over cells of f0
- *     and div (1 where zero); the network output y (cell averages of the
- *     correction to TBDG_GUESS_PREVIOUS) gives the guess
- *     p + inc_2 + beta_s dt s_inc I(y), I the multilinear interpolation of
- *     the cell values from the cell centres (periodic) to the nodes; the
- *     candidate with the smaller FP64 residual ||b - H x|| (learned or
- *     TBDG_GUESS_PREVIOUS) is used.
- * With fewer than two stored increments the previous pressure is used.  A
- * failed step clears the history.                                           */
+ * paper).  The context keeps the four newest pressure increments
+ * p_new - p_prev of its solves; for the stage-s solve with right-hand side b
+ * and previous pressure p, d1 and d2 are the same stage's increments of the
+ * last two steps and d0 the newest increment (the other stage's, weight
+ * beta0).  With <a, c>_K = sum_{i in K} W_i a_i c_i (W_i the product of the
+ * Gauss weights of node i on the unit cell):
+ *   TBDG_GUESS_PREVIOUS: p + d1 (the fallback);
+ *   TBDG_GUESS_EXTRAP2:  p + 2 d1 - d2;
+ *   TBDG_GUESS_LEARNED:  per cell K the network input is (m1 / s_inc,
+ *     m2 / s_inc, m0 / s_inc, div / s_div, cos_K, lr_K) with
+ *     m1 = <d1, 1>_K / (beta_s dt), m2 = <d2, 1>_K / (beta_s dt),
+ *     m0 = <d0, 1>_K / (beta0 dt), div = -(beta_s dt / |K|) sum_{i in K}
+ *     (b_i - alpha_s (M^p p)_i) (cell average of div u** in flux form),
+ *     s_inc and s_div the RMS over cells of m1 and div (1 where zero),
+ *     cos_K = <d1, d2>_K / sqrt(<d1, d1>_K <d2, d2>_K) and
+ *     lr_K = log(<d1, d1>_K / <d2, d2>_K) / 2 clamped to [-4, 4] (both 0
+ *     where a norm vanishes); the network output (y0_K, y1_K) gives the
+ *     guess p + (2 + y0_K) d1 - (1 - y1_K) d2 at the nodes of K (a
+ *     correction of TBDG_GUESS_EXTRAP2); the candidate with the smaller FP64
+ *     residual ||b - H x|| (learned or TBDG_GUESS_PREVIOUS) is used.
+ * Without the history a mode needs, TBDG_GUESS_PREVIOUS (or, without any,
+ * the previous pressure) is used.  A failed step clears the history.       */
 
 /* Attach (net != NULL) or detach the guess network; it must use the
  * context's stream.  The network is borrowed, not owned.  Clears the history. */
 TBDG_API tbdg_status tbdg_set_guess_net(tbdg_ctx* ctx, tbdg_net* net);
 /* Forget the stored increments (start of a new trajectory).                 */
 TBDG_API tbdg_status tbdg_guess_reset(tbdg_ctx* ctx);
-/* Record training samples: after each Helmholtz solve of tbdg_step that has
- * two stored increments, sample k of buf (device, FP32, [capacity][4][N_c])
- * receives the network input [3][N_c] and the target
- * mean_K(p_new - p - inc_2) / (beta_s dt) / s_inc.  buf NULL stops
- * recording; the history is cleared.                                        */
+/* Record training samples: after each TR-BDF2 Helmholtz solve of tbdg_step
+ * whose stage has two earlier increments, sample k of buf (device, FP32,
+ * [capacity][12][N_c]) receives the network input [6][N_c] and the Gram
+ * target [6][N_c] of tbdg_guess_target for the solve's p_new, p, d1, d2.
+ * buf NULL stops recording; the history is cleared.                        */
 TBDG_API tbdg_status tbdg_guess_record(tbdg_ctx* ctx, float* buf, int capacity);
 TBDG_API tbdg_status tbdg_guess_recorded(tbdg_ctx* ctx, int* count);
 /* ||b - H x|| of the learned and the fallback candidate of the last
  * TBDG_GUESS_LEARNED decision (host outputs; 0 before the first).          */
 TBDG_API tbdg_status tbdg_guess_last(tbdg_ctx* ctx, double* r_learned, double* r_fallback);
-/* The network input for given vectors (device, N_p each): x FP32 [3][N_c];
+/* The network input for given vectors (device, N_p each): x FP32 [6][N_c];
  * scales (host, may be NULL) = (s_inc, s_div).                              */
 TBDG_API tbdg_status tbdg_guess_features(tbdg_ctx* ctx, int stage, const double* b,
-                                         const double* p_prev, const double* inc1, double beta1,
-                                         const double* inc2, double beta2, float* x, double* scales);
-/* out = p_prev + inc2 + beta_s dt s_inc I(y) (y: FP32 [N_c], the rest N_p).  */
-TBDG_API tbdg_status tbdg_guess_inject(tbdg_ctx* ctx, int stage, const double* p_prev,
-                                       const double* inc2, const float* y, double s_inc,
-                                       double* out);
+                                         const double* p_prev, const double* d0, double beta0,
+                                         const double* d1, const double* d2, float* x, double* scales);
+/* out = p_prev + (2 + y0_K) d1 - (1 - y1_K) d2 (y: FP32 [2][N_c], the rest
+ * N_p).                                                                      */
+TBDG_API tbdg_status tbdg_guess_inject(tbdg_ctx* ctx, const double* p_prev, const double* d1,
+                                       const double* d2, const float* y, double* out);
+/* Gram target of a solve (device, N_p each; out FP32 [6][N_c]): per cell
+ * (<d1,d1>, <d1,d2>, <d2,d2>, <e,d1>, <e,d2>, <e,e>)_K / S with
+ * e = p_new - (p_prev + 2 d1 - d2) and S the mean over cells of <d1,d1>_K
+ * (1 where zero), so that the squared error <x - p_new, x - p_new>_K of the
+ * blended guess x is S times the per-cell loss of tbdg_net_quad_loss.      */
+TBDG_API tbdg_status tbdg_guess_target(tbdg_ctx* ctx, const double* p_new, const double* p_prev,
+                                       const double* d1, const double* d2, float* out);
 
 /* TR-BDF2 state: u = u^n, u_hist = u^{n-1+gamma} (history level of the
  * stage-1 extrapolation), p = p^n; t and n are host values.                 */
@@ -432,6 +453,41 @@ TBDG_API tbdg_status tbdg_set_nonlinear(tbdg_ctx* ctx, int max_solves, double to
 /* solves[0..1] (host): momentum solves of stages 1 and 2 in the last
  * tbdg_step (also of a failed one, up to the failing solve).               */
 TBDG_API tbdg_status tbdg_nonlinear_solves(tbdg_ctx* ctx, int* solves);
+
+/* Time scheme of tbdg_step.  Besides TR-BDF2 the paper compares two
+ * single-stage projection methods on the same DG forms (Sec. 2, eqs.
+ * momentum_BCG, helmholtz_BCG, momentum_HI, helmholtz_HI):
+ *   TBDG_SCHEME_BCG (Bell-Colella-Glaz, Crank-Nicolson): momentum
+ *     [M/dt + (nu A + C(w))/2] u* = M u^n/dt + (explicit diffusion and
+ *     advection of u^n advected by w)/2 + (weak gradient of p^n) + boundary
+ *     data, w the midpoint velocity: the first solve is advected by
+ *     (3 u^n - u^{n-1})/2, each later one (tbdg_set_nonlinear: up to
+ *     max_solves, early stop on ||w_j - w_{j-1}||_2 <= tol ||w_j||_2) by
+ *     (u*_{j-1} + u^n)/2; projection and Helmholtz solve with beta = 1;
+ *   TBDG_SCHEME_BDF2 (Guermond-Quartapelle): [3M/(2dt) + nu A + C(w)] u* =
+ *     M (4 u^n - u^{n-1})/(2 dt) + (weak gradient of p^n) + boundary data,
+ *     one solve, w the momentum predictor of the context's previous step
+ *     (u^n when state->n = 0); projection and Helmholtz solve with
+ *     beta = 2/3 (alpha = 1/(c^2 beta^2 dt^2), divergence term 1/(beta dt),
+ *     correction u^{n+1} = u** - beta dt M^{-1} P p^{n+1}).
+ * With a single-stage scheme, tbdg_state.u_hist holds u^{n-1} (the exact
+ * solution at t = -dt, or u^0, at the first step), the momentum and
+ * pressure solves of tbdg_step go to info[0] and info[1] (info[2..3] are
+ * zero), the stage-1 entry points (apply, diagonals, right-hand sides,
+ * solves with stage = 1) use the scheme's (beta, theta), the Dirichlet data
+ * of slot 1 (t^{n+1}) are used, mom->guess TBDG_GUESS_PREVIOUS starts from
+ * 2 u^n - u^{n-1}, prs->guess TBDG_GUESS_PREVIOUS / TBDG_GUESS_EXTRAP2
+ * extrapolate the pressure increments of the last one / two steps, and
+ * TBDG_GUESS_LEARNED is TBDG_EUNSUPPORTED.  Setting a scheme recomputes the
+ * stage-1 pressure diagonal, rebuilds an existing multigrid hierarchy with
+ * its parameters, and clears the initial-guess history and the lagged
+ * predictor.  Errors: TBDG_EINVAL for an unknown scheme.                   */
+enum {
+    TBDG_SCHEME_TRBDF2 = 0,
+    TBDG_SCHEME_BCG = 1,
+    TBDG_SCHEME_BDF2 = 2
+};
+TBDG_API tbdg_status tbdg_set_scheme(tbdg_ctx* ctx, int scheme);
 
 /* Measurement hook.  While enabled, every third launch of the pressure
  * operator kernel (which = 0: tbdg_apply_pressure and the CG iterations) and

@@ -1,17 +1,20 @@
 """Small 3D convolutional network of the learned pressure initial guess
 (oracle; TEST INFRASTRUCTURE ONLY).
 
-The network is not part of the paper; it predicts the next pressure increment
-of the projection step from cell averages of the solver's own history.  This
-module is its plain FP64 definition, written with numpy:
+The network is not part of the paper; it predicts, per cell, how to blend
+the solver's last two pressure increments into the next one, from cell
+statistics of its own history.  This module is its plain FP64 definition,
+written with numpy:
 
-* layers 3 -> C -> C -> C -> 1, 3x3x3 kernels, circular (periodic) padding,
-  ReLU after every layer but the last;
+* layers N_IN -> C -> C -> C -> N_OUT (6 -> 32 -> 32 -> 32 -> 2 in the
+  library), 3x3x3 kernels, circular (periodic) padding, ReLU after every
+  layer but the last;
 * convolution as cross-correlation, the layout of the weights being
   [out][in][dz][dy][dx] and of the activations [batch][channel][z][y][x]:
       y[o, z, y, x] = b[o] + sum_{i, dz, dy, dx} W[o, i, dz+1, dy+1, dx+1]
                               * X[i, (z+dz) mod nz, (y+dy) mod ny, (x+dx) mod nx];
-* mean-squared-error loss L = mean((yhat - y)^2);
+* mean-squared-error loss L = mean((yhat - y)^2) (the guess's own loss,
+  a quadratic form per cell, is ``oracle.guess.quad_loss``);
 * Adam (Kingma and Ba 2015) with bias correction;
 * round-to-nearest-even to bfloat16 (the upper 16 bits of an IEEE binary32).
 """
@@ -19,21 +22,23 @@ import numpy as np
 
 OFFSETS = [(dz, dy, dx) for dz in (-1, 0, 1) for dy in (-1, 0, 1) for dx in (-1, 0, 1)]
 
+N_IN, N_OUT = 6, 2
 
-def layer_shapes(channels=32, n_in=3):
+
+def layer_shapes(channels=32, n_in=N_IN, n_out=N_OUT):
     """(out, in) of the four layers."""
-    return [(channels, n_in), (channels, channels), (channels, channels), (1, channels)]
+    return [(channels, n_in), (channels, channels), (channels, channels), (n_out, channels)]
 
 
-def n_params(channels=32, n_in=3):
-    return sum(o * i * 27 + o for o, i in layer_shapes(channels, n_in))
+def n_params(channels=32, n_in=N_IN, n_out=N_OUT):
+    return sum(o * i * 27 + o for o, i in layer_shapes(channels, n_in, n_out))
 
 
-def unpack(theta, channels=32, n_in=3):
+def unpack(theta, channels=32, n_in=N_IN, n_out=N_OUT):
     """Split the flat parameter vector into [(W, b)] per layer, W in
     [out][in][3][3][3] order followed by b[out], layer after layer."""
     out, k = [], 0
-    for o, i in layer_shapes(channels, n_in):
+    for o, i in layer_shapes(channels, n_in, n_out):
         W = theta[k:k + o * i * 27].reshape(o, i, 3, 3, 3)
         k += o * i * 27
         b = theta[k:k + o]
@@ -76,7 +81,7 @@ def conv3d_grad(X, W, dY):
 
 
 def forward(params, X, act_round=None):
-    """Returns the output [B][1][nz][ny][nx] and the inputs of every layer.
+    """Returns the output [B][n_out][nz][ny][nx] and the inputs of every layer.
     ``act_round`` (e.g. bf16_round) is applied to every hidden activation,
     modelling storage of the activations in a narrower format."""
     acts = [X]

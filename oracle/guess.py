@@ -2,34 +2,56 @@
 (oracle; TEST INFRASTRUCTURE ONLY).
 
 Not part of the paper.  For the Helmholtz solve of stage s (beta_s, right-hand
-side b = alpha_s M^p p_prev + F_p(u**)) with the two newest pressure
-increments inc1 (the newest, from the other stage, weight beta1) and inc2
-(the same stage one step earlier, weight beta2):
+side b = alpha_s M^p p_prev + F_p(u**)) the solver keeps the pressure
+increments p_new - p_prev of its earlier solves: d1 and d2 of the same stage
+one and two steps back, d0 the newest one (of the other stage, weight
+beta0).  With <a, b>_K = sum_{i in K} W_i a_i b_i (W_i the product of the
+Gauss weights of node i on the unit reference cell, so <a, 1>_K is the cell
+average mean_K(a)):
 
-* per cell K, f0 = mean_K(inc1) / (beta1 dt), f1 = mean_K(inc2) / (beta2 dt),
-  where mean_K is the Gauss-rule cell average (sum of weight * nodal value);
-* div_K = -(beta_s dt / |K|) sum_{i in K} (b_i - alpha_s (M^p p_prev)_i),
-  i.e. -(beta_s dt / |K|) sum_{i in K} F_p(u**)_i, which is the cell average of
-  div u** in flux form (the test functions of K sum to one);
-* scales s_inc = RMS over cells of f0, s_div = RMS of div (1 where zero);
-* network input, cell-lexicographic: [f0 / s_inc, f1 / s_inc, div / s_div];
-* fallback: p_prev + inc2 (the pressures of the two stages carry different
-  offsets, so the other stage's increment predicts poorly);
-* the network predicts the cell averages of the correction to the fallback,
-  training target mean_K(p_new - p_prev - inc2) / (beta_s dt) / s_inc;
-* learned guess: fallback + beta_s dt s_inc I(y), I the multilinear
-  interpolation of the cell values from the cell centres (periodic) to the
-  nodes, so the correction is continuous.
+* network input per cell K (6 channels, cell-lexicographic):
+    m1 / s_inc, m2 / s_inc, m0 / s_inc, div / s_div, cos_K, lr_K
+  with m1 = mean_K(d1) / (beta_s dt), m2 = mean_K(d2) / (beta_s dt),
+  m0 = mean_K(d0) / (beta0 dt), div_K = -(beta_s dt / |K|) sum_{i in K}
+  (b_i - alpha_s (M^p p_prev)_i) (the cell average of div u** in flux
+  form), s_inc and s_div the RMS over cells of m1 and div (1 where zero),
+  cos_K = <d1, d2>_K / sqrt(<d1, d1>_K <d2, d2>_K) and
+  lr_K = log(<d1, d1>_K / <d2, d2>_K) / 2 clamped to [-4, 4] (both 0 where
+  a norm vanishes): the local shape and growth of the last two increments;
+* network output per cell: (y0_K, y1_K), the correction of the blend of the
+  two increments, guess = p_prev + (2 + y0_K) d1 - (1 - y1_K) d2 at the
+  nodes of K (y = 0: the increment extrapolated linearly from its last two
+  values; y = (-1, 1): the fallback p_prev + d1); the library starts the
+  network's last layer at zero, i.e. from the extrapolation;
+* training target: per cell the Gram data of the error
+  e = p_new - (p_prev + 2 d1 - d2) of the extrapolation,
+    (g11, g12, g22, r1, r2, ee) = (<d1,d1>, <d1,d2>, <d2,d2>, <e,d1>, <e,d2>,
+    <e,e>)_K / S,  S = the mean over cells of <d1,d1>_K (1 where zero),
+  so that the squared error of the blended guess in cell K is
+    l_K(y) = ee - 2 (y0 r1 + y1 r2) + y0^2 g11 + 2 y0 y1 g12 + y1^2 g22
+  (times S); the loss is the mean of l_K over cells and samples.
 """
 import numpy as np
+
+LR_CLAMP = 4.0
+
+
+def node_weights(disc):
+    """W_i of the pressure nodes of one cell ([node] lexicographic, x fastest)."""
+    w = np.ones(1)
+    for _ in range(disc.dim):
+        w = np.kron(disc.wp, w)
+    return w
 
 
 def cell_average(disc, p):
     """Gauss-rule cell averages of a pressure vector ([cell][node] layout)."""
-    w = np.ones(1)
-    for _ in range(disc.dim):
-        w = np.kron(disc.wp, w)
-    return p.reshape(disc.Nc, disc.nbp) @ w
+    return p.reshape(disc.Nc, disc.nbp) @ node_weights(disc)
+
+
+def cell_inner(disc, a, b):
+    """<a, b>_K per cell: the Gauss-rule cell average of the product."""
+    return (a.reshape(disc.Nc, disc.nbp) * b.reshape(disc.Nc, disc.nbp)) @ node_weights(disc)
 
 
 def _rms_or_one(v):
@@ -37,55 +59,67 @@ def _rms_or_one(v):
     return r if r > 0.0 else 1.0
 
 
-def features(ts, s, b, p_prev, inc1, beta1, inc2, beta2):
-    """(x [3][cells], s_inc, s_div) for stage s of the stepper ``ts``."""
+def shape_features(disc, d1, d2):
+    """(cos_K, lr_K) of the last two same-stage increments."""
+    g11, g22, g12 = cell_inner(disc, d1, d1), cell_inner(disc, d2, d2), cell_inner(disc, d1, d2)
+    ok = (g11 > 0.0) & (g22 > 0.0)
+    cos = np.zeros(disc.Nc)
+    lr = np.zeros(disc.Nc)
+    cos[ok] = g12[ok] / np.sqrt(g11[ok] * g22[ok])
+    lr[ok] = np.clip(0.5 * np.log(g11[ok] / g22[ok]), -LR_CLAMP, LR_CLAMP)
+    return cos, lr
+
+
+def features(ts, s, b, p_prev, d0, beta0, d1, d2):
+    """(x [6][cells], s_inc, s_div) for stage s of the stepper ``ts``."""
     disc = ts.disc
     dt = ts.dt
-    f0 = cell_average(disc, inc1) / (beta1 * dt)
-    f1 = cell_average(disc, inc2) / (beta2 * dt)
+    bs = ts.beta[s]
+    m1 = cell_average(disc, d1) / (bs * dt)
+    m2 = cell_average(disc, d2) / (bs * dt)
+    m0 = cell_average(disc, d0) / (beta0 * dt)
     Fp = b - ts.alpha(s) * (ts.Mp @ p_prev)
     vol = np.array([disc.cell_measure(c) for c in range(disc.Nc)])
-    div = -(ts.beta[s] * dt / vol) * Fp.reshape(disc.Nc, disc.nbp).sum(axis=1)
-    s_inc, s_div = _rms_or_one(f0), _rms_or_one(div)
-    return np.stack([f0 / s_inc, f1 / s_inc, div / s_div]), s_inc, s_div
+    div = -(bs * dt / vol) * Fp.reshape(disc.Nc, disc.nbp).sum(axis=1)
+    s_inc, s_div = _rms_or_one(m1), _rms_or_one(div)
+    cos, lr = shape_features(disc, d1, d2)
+    return np.stack([m1 / s_inc, m2 / s_inc, m0 / s_inc, div / s_div, cos, lr]), s_inc, s_div
 
 
-def target(ts, s, p_new, p_prev, inc2, s_inc):
-    return cell_average(ts.disc, p_new - p_prev - inc2) / (ts.beta[s] * ts.dt) / s_inc
+def gram_target(disc, p_new, p_prev, d1, d2):
+    """[6][cells]: (g11, g12, g22, r1, r2, ee) / S (module docstring)."""
+    e = p_new - extrapolate2(p_prev, d1, d2)
+    g11 = cell_inner(disc, d1, d1)
+    S = float(np.mean(g11))
+    S = S if S > 0.0 else 1.0
+    return np.stack([g11, cell_inner(disc, d1, d2), cell_inner(disc, d2, d2), cell_inner(disc, e, d1),
+                     cell_inner(disc, e, d2), cell_inner(disc, e, e)]) / S
 
 
-def interpolate_centres(disc, y):
-    """Multilinear interpolation of cell values (located at the cell centres,
-    periodic) to the pressure nodes, [cell][node] layout."""
-    mesh = disc.mesh
-    y = np.asarray(y, dtype=np.float64)
-    out = np.zeros(disc.N_p)
-    z = disc.zp
-    for c in range(disc.Nc):
-        ijk = mesh.cell_ijk(c)
-        for node in range(disc.nbp):
-            loc = [(node // disc.n_p ** a) % disc.n_p for a in range(disc.dim)]
-            lo, w = [], []
-            for a in range(disc.dim):
-                X = ijk[a] + z[loc[a]] - 0.5          # position in cell-centre units
-                i0 = int(np.floor(X))
-                lo.append(i0)
-                w.append(X - i0)
-            val = 0.0
-            for corner in range(2 ** disc.dim):
-                wt, idx = 1.0, []
-                for a in range(disc.dim):
-                    bit = (corner >> a) & 1
-                    wt *= w[a] if bit else 1.0 - w[a]
-                    idx.append((lo[a] + bit) % mesh.n_cells[a])
-                val += wt * y[mesh.cell_index(idx)]
-            out[c * disc.nbp + node] = val
-    return out
+def inject(disc, p_prev, d1, d2, y):
+    """p_prev + (2 + y0_K) d1 - (1 - y1_K) d2 with y = [2][cells]."""
+    a = np.repeat(np.asarray(y[0], dtype=np.float64), disc.nbp)
+    c = np.repeat(np.asarray(y[1], dtype=np.float64), disc.nbp)
+    return extrapolate2(p_prev, d1, d2) + a * d1 + c * d2
 
 
-def inject(ts, s, p_prev, inc2, y, s_inc):
-    return fallback(p_prev, inc2) + ts.beta[s] * ts.dt * s_inc * interpolate_centres(ts.disc, y)
+def fallback(p_prev, d1):
+    return p_prev + d1
 
 
-def fallback(p_prev, inc2):
-    return p_prev + inc2
+def extrapolate2(p_prev, d1, d2):
+    """The same-stage increment extrapolated linearly from its last two values."""
+    return p_prev + 2.0 * d1 - d2
+
+
+def quad_loss(y, G):
+    """Mean over cells (and leading batch axes) of l_K(y) and its gradient.
+    y: [..., 2, N], G: [..., 6, N]."""
+    y0, y1 = y[..., 0, :], y[..., 1, :]
+    g11, g12, g22, r1, r2, ee = (G[..., i, :] for i in range(6))
+    lk = ee - 2.0 * (y0 * r1 + y1 * r2) + y0 * y0 * g11 + 2.0 * y0 * y1 * g12 + y1 * y1 * g22
+    count = lk.size
+    dy = np.empty_like(y, dtype=np.float64)
+    dy[..., 0, :] = 2.0 * (y0 * g11 + y1 * g12 - r1) / count
+    dy[..., 1, :] = 2.0 * (y0 * g12 + y1 * g22 - r2) / count
+    return float(np.mean(lk)), dy

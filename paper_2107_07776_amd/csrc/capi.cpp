@@ -20,6 +20,8 @@ void rhs_momentum(tbdg_ctx* c, int s, const double* u_n, const double* u_g, cons
 void rhs_pressure(tbdg_ctx* c, int s, const double* u_ss, const double* p_prev, double* rhs);
 tbdg_status step(tbdg_ctx* c, tbdg_state* S, const tbdg_solver_opts& mo,
                  const tbdg_solver_opts& po, tbdg_solve_info info[4]);
+tbdg_status step_single(tbdg_ctx* c, tbdg_state* S, const tbdg_solver_opts& mo,
+                        const tbdg_solver_opts& po, tbdg_solve_info info[4]);
 }  // namespace trbdg
 
 using trbdg::Error;
@@ -95,6 +97,7 @@ void free_all(tbdg_ctx* c) {
     dfree(c->s_pg);
     dfree(c->s_p1);
     dfree(c->s_pv);
+    dfree(c->s_wlag);
     trbdg::mg_free(c);
     trbdg::guess_free(c);
     dfree(c->bnd_uD[0]);
@@ -112,7 +115,7 @@ tbdg_solver_opts defaults(const tbdg_solver_opts* o) {
     require(r.restart >= 0 && r.restart <= GMRES_MAX, "GMRES restart must be in [0, 60]");
     require(r.precond >= TBDG_PRECOND_JACOBI && r.precond <= TBDG_PRECOND_LINE,
             "unknown preconditioner");
-    require(r.guess >= TBDG_GUESS_GIVEN && r.guess <= TBDG_GUESS_LEARNED, "unknown initial guess");
+    require(r.guess >= TBDG_GUESS_GIVEN && r.guess <= TBDG_GUESS_EXTRAP2, "unknown initial guess");
     return r;
 }
 
@@ -621,8 +624,12 @@ tbdg_status tbdg_step(tbdg_ctx* c, tbdg_state* state, const tbdg_solver_opts* mo
             throw Error(TBDG_EUNSUPPORTED, "the momentum solve takes the Jacobi or the line preconditioner");
         if (po.precond == TBDG_PRECOND_LINE)
             throw Error(TBDG_EUNSUPPORTED, "the line preconditioner applies to the momentum solve");
-        require(mo.guess != TBDG_GUESS_LEARNED, "the momentum solve has no learned guess");
-        const tbdg_status s = trbdg::step(c, state, mo, po, info);
+        require(mo.guess != TBDG_GUESS_LEARNED && mo.guess != TBDG_GUESS_EXTRAP2,
+                "the momentum solve takes the given or the extrapolated guess");
+        if (c->scheme != TBDG_SCHEME_TRBDF2 && po.guess == TBDG_GUESS_LEARNED)
+            throw Error(TBDG_EUNSUPPORTED, "the learned guess is built for the two TR-BDF2 stages");
+        const tbdg_status s = c->scheme == TBDG_SCHEME_TRBDF2 ? trbdg::step(c, state, mo, po, info)
+                                                               : trbdg::step_single(c, state, mo, po, info);
         if (s != TBDG_OK && c->last_error.empty()) c->last_error = "a stage solve failed";
         return s;
     });
@@ -645,6 +652,36 @@ tbdg_status tbdg_nonlinear_solves(tbdg_ctx* c, int* solves) {
         require(solves != nullptr, "null output");
         solves[0] = c->nl_solves[0];
         solves[1] = c->nl_solves[1];
+        return TBDG_OK;
+    });
+}
+
+tbdg_status tbdg_set_scheme(tbdg_ctx* c, int scheme) {
+    if (!c) return TBDG_EINVAL;
+    return guarded(c, [&]() {
+        require(scheme == TBDG_SCHEME_TRBDF2 || scheme == TBDG_SCHEME_BCG || scheme == TBDG_SCHEME_BDF2,
+                "unknown time scheme");
+        // (beta, theta) of stage slot 1: the TR-BDF2 trapezoidal stage, the
+        // Crank-Nicolson step, or the BDF2 step written as
+        // (1/(beta dt)) (u* - (4 u^n - u^{n-1})/3) + ... with beta = 2/3
+        const double g = c->gamma;
+        const double beta1 = scheme == TBDG_SCHEME_TRBDF2 ? g : scheme == TBDG_SCHEME_BCG ? 1.0 : 2.0 / 3.0;
+        const double theta1 = scheme == TBDG_SCHEME_BDF2 ? 1.0 : 0.5;
+        if (scheme == TBDG_SCHEME_BDF2 && !c->s_wlag) c->s_wlag = dalloc(c->Nu);
+        c->scheme = scheme;
+        c->beta[1] = beta1;
+        c->theta[1] = theta1;
+        c->wlag_valid = false;
+        trbdg::guess_reset(c);
+        trbdg::launch_diag_pressure(c, c->alpha(1), c->diag_p[1]);
+        trbdg::vec_recip(c->stream, c->Np, c->diag_p[1], c->invd_p[1]);
+        if (c->mg) {
+            // the level operators and eigenvalue estimates depend on alpha_1
+            const trbdg::MGData& M = *c->mg;
+            tbdg_mg_desc d{M.degree, M.lanczos_steps, M.range, M.safety, M.coarse_cells, M.max_coarse};
+            trbdg::mg_setup(c, &d);
+        }
+        TBDG_HIP(hipStreamSynchronize(c->stream));
         return TBDG_OK;
     });
 }
@@ -749,15 +786,15 @@ tbdg_status tbdg_guess_last(tbdg_ctx* c, double* r_learned, double* r_fallback) 
 }
 
 tbdg_status tbdg_guess_features(tbdg_ctx* c, int stage, const double* b, const double* p_prev,
-                                const double* inc1, double beta1, const double* inc2, double beta2,
+                                const double* d0, double beta0, const double* d1, const double* d2,
                                 float* x, double* scales) {
     if (!c) return TBDG_EINVAL;
     return guarded(c, [&]() {
         check_stage(stage);
-        require(b && p_prev && inc1 && inc2 && x, "null pointer");
-        require(beta1 > 0.0 && beta2 > 0.0, "stage weights must be positive");
-        trbdg::guess_features(c, stage, b, p_prev, inc1, beta1, inc2, beta2);
-        TBDG_HIP(hipMemcpyAsync(x, c->gs->feat, sizeof(float) * 3 * c->Nc, hipMemcpyDeviceToDevice,
+        require(b && p_prev && d0 && d1 && d2 && x, "null pointer");
+        require(beta0 > 0.0 && std::isfinite(beta0), "stage weight must be positive");
+        trbdg::guess_features(c, stage, b, p_prev, d0, beta0, d1, d2);
+        TBDG_HIP(hipMemcpyAsync(x, c->gs->feat, sizeof(float) * 6 * c->Nc, hipMemcpyDeviceToDevice,
                                 c->stream));
         if (scales) {
             TBDG_HIP(hipMemcpyAsync(c->host_out, c->gs->sc, 2 * sizeof(double), hipMemcpyDeviceToHost,
@@ -770,17 +807,23 @@ tbdg_status tbdg_guess_features(tbdg_ctx* c, int stage, const double* b, const d
     });
 }
 
-tbdg_status tbdg_guess_inject(tbdg_ctx* c, int stage, const double* p_prev, const double* inc2,
-                              const float* y, double s_inc, double* out) {
+tbdg_status tbdg_guess_inject(tbdg_ctx* c, const double* p_prev, const double* d1, const double* d2,
+                              const float* y, double* out) {
     if (!c) return TBDG_EINVAL;
     return guarded(c, [&]() {
-        check_stage(stage);
-        require(p_prev && inc2 && y && out, "null pointer");
-        require(s_inc > 0.0 && std::isfinite(s_inc), "scale must be positive");
-        trbdg::guess_ensure(c);
-        c->host_out[0] = s_inc;
-        TBDG_HIP(hipMemcpyAsync(c->gs->sc, c->host_out, sizeof(double), hipMemcpyHostToDevice, c->stream));
-        trbdg::guess_inject(c, stage, p_prev, inc2, y, out);
+        require(p_prev && d1 && d2 && y && out, "null pointer");
+        trbdg::guess_inject(c, p_prev, d1, d2, y, out);
+        TBDG_HIP(hipStreamSynchronize(c->stream));
+        return TBDG_OK;
+    });
+}
+
+tbdg_status tbdg_guess_target(tbdg_ctx* c, const double* p_new, const double* p_prev, const double* d1,
+                              const double* d2, float* out) {
+    if (!c) return TBDG_EINVAL;
+    return guarded(c, [&]() {
+        require(p_new && p_prev && d1 && d2 && out, "null pointer");
+        trbdg::guess_target(c, p_new, p_prev, d1, d2, out);
         TBDG_HIP(hipStreamSynchronize(c->stream));
         return TBDG_OK;
     });

@@ -1,8 +1,10 @@
 // Initial guesses of the Helmholtz solves inside tbdg_step: the previous
 // pressure, the previous pressure plus the same stage's increment of the
-// previous step, or the learned guess of the network with that as fallback
-// (the guess with the smaller FP64 residual is used).  Also records (input, target) samples of
-// the network from the solver's own solves.
+// previous step (the fallback), that increment extrapolated from its last two
+// values, or the learned blend of the last two increments with the fallback
+// as the alternative (the guess with the smaller FP64 residual is used).
+// Also records (input, target) samples of the network from the solver's own
+// solves.
 #include <cmath>
 #include <utility>
 
@@ -40,14 +42,13 @@ void fill_state(tbdg_ctx* c, GuessState* g) {
         g->allocs.push_back(p);
         return static_cast<float*>(p);
     };
-    g->inc[0] = dal(c->Np);
-    g->inc[1] = dal(c->Np);
-    g->cells = dal(3 * c->Nc);
+    for (int i = 0; i < 4; ++i) g->inc[i] = dal(c->Np);
+    g->cells = dal(7 * c->Nc);
     g->partial = dal(2 * ((c->Nc + 255) / 256));
     g->sc = dal(8);
     g->trial = dal(c->Np);
-    g->feat = fal(3 * c->Nc);
-    g->y = fal(c->Nc);
+    g->feat = fal(6 * c->Nc);
+    g->y = fal(2 * c->Nc);
 }
 
 // ||b - H x||^2 into the device slot
@@ -72,23 +73,34 @@ void guess_reset(tbdg_ctx* c) {
     if (c->gs) c->gs->n = 0;
 }
 
-void guess_features(tbdg_ctx* c, int s, const double* b, const double* p, const double* inc1,
-                    double beta1, const double* inc2, double beta2) {
+void guess_features(tbdg_ctx* c, int s, const double* b, const double* p, const double* d0,
+                    double beta0, const double* d1, const double* d2) {
     ensure_state(c);
     GuessState& g = *c->gs;
-    const int G = launch_guess_cells(c, inc1, inc2, b, p, 1.0 / (beta1 * c->dt), 1.0 / (beta2 * c->dt),
-                                     -c->beta[s] * c->dt, c->alpha(s), g.cells, g.partial);
+    const double bdt = c->beta[s] * c->dt;
+    const int G = launch_guess_cells(c, d1, d2, d0, b, p, 1.0 / bdt, 1.0 / (beta0 * c->dt), -bdt,
+                                     c->alpha(s), g.cells, g.partial);
     launch_guess_feat(c, g.cells, g.partial, G, g.feat, g.sc);
 }
 
-void guess_inject(tbdg_ctx* c, int s, const double* p, const double* inc2, const float* y, double* out) {
+void guess_inject(tbdg_ctx* c, const double* p, const double* d1, const double* d2, const float* y,
+                  double* out) {
+    launch_guess_inject(c, p, d1, d2, y, out);
+}
+
+void guess_target(tbdg_ctx* c, const double* pn, const double* p, const double* d1, const double* d2,
+                  float* out) {
     ensure_state(c);
-    launch_guess_inject(c, p, inc2, y, c->beta[s] * c->dt, c->gs->sc, out);
+    launch_guess_target(c, pn, p, d1, d2, c->gs->cells, c->gs->partial, out);
 }
 
 int guess_prepare(tbdg_ctx* c, int s, int mode, const double* b, const double* p_prev, double* x) {
     const int64_t bp = (int64_t)sizeof(double) * c->Np;
-    const bool recording = c->gs && c->gs->rec && c->gs->rec_count < c->gs->rec_cap;
+    const bool two_stage = c->scheme == TBDG_SCHEME_TRBDF2;
+    const bool recording = two_stage && c->gs && c->gs->rec && c->gs->rec_count < c->gs->rec_cap;
+    // the same stage's increments one and two steps back: every other entry
+    // of the history with two stages per step, consecutive entries with one
+    const int lag1 = two_stage ? 1 : 0, lag2 = two_stage ? 3 : 1;
     if (mode == 0 && !recording) {
         TBDG_HIP(hipMemcpyAsync(x, p_prev, bp, hipMemcpyDeviceToDevice, c->stream));
         return 0;
@@ -96,22 +108,31 @@ int guess_prepare(tbdg_ctx* c, int s, int mode, const double* b, const double* p
     ensure_state(c);
     GuessState& g = *c->gs;
     g.feat_valid = false;
-    const bool learned = mode == 2 && g.net != nullptr && g.n >= 2;
-    if (g.n >= 2 && (learned || recording)) {
-        guess_features(c, s, b, p_prev, g.inc[0], g.beta[0], g.inc[1], g.beta[1]);
+    // the network needs the same stage's increments of the last two steps
+    const bool history = two_stage && g.n > lag2;
+    const bool learned = mode == TBDG_GUESS_LEARNED && g.net != nullptr && history;
+    if (history && (learned || recording)) {
+        guess_features(c, s, b, p_prev, g.inc[0], g.beta[0], g.inc[lag1], g.inc[lag2]);
         g.feat_valid = true;
     }
-    if (mode == 0 || g.n < 2) {
+    if (mode == 0 || g.n <= lag1) {
         TBDG_HIP(hipMemcpyAsync(x, p_prev, bp, hipMemcpyDeviceToDevice, c->stream));
         return 0;
     }
+    if (mode == TBDG_GUESS_EXTRAP2 && g.n > lag2) {
+        // the same stage's increment extrapolated linearly from its last two
+        // values: p + 2 inc[lag1] - inc[lag2]
+        vec_axpby(c->stream, c->Np, 2.0, g.inc[lag1], -1.0, g.inc[lag2], x);
+        vec_axpby(c->stream, c->Np, 1.0, p_prev, 1.0, x, x);
+        return TBDG_GUESS_EXTRAP2;
+    }
     // fallback: the increment of the same stage one step earlier (the two
-    // stages' pressures carry different offsets, so the other stage's
-    // increment is a poor predictor)
-    vec_axpby(c->stream, c->Np, 1.0, p_prev, 1.0, g.inc[1], x);
+    // TR-BDF2 stages' pressures carry different offsets, so the other
+    // stage's increment is a poor predictor)
+    vec_axpby(c->stream, c->Np, 1.0, p_prev, 1.0, g.inc[lag1], x);
     if (!learned) return 1;
     net_infer(g.net, g.feat, g.y, c->geom.nc[0], c->geom.nc[1], c->geom.nc[2]);
-    guess_inject(c, s, p_prev, g.inc[1], g.y, g.trial);
+    guess_inject(c, p_prev, g.inc[lag1], g.inc[lag2], g.y, g.trial);
     residual_sq(c, s, b, g.trial, c->red_out + 60);
     residual_sq(c, s, b, x, c->red_out + 61);
     TBDG_HIP(hipMemcpyAsync(c->host_out, c->red_out + 60, 2 * sizeof(double), hipMemcpyDeviceToHost,
@@ -131,17 +152,23 @@ void guess_after_solve(tbdg_ctx* c, int s, const double* p_new, const double* p_
     if (!c->gs) return;
     GuessState& g = *c->gs;
     if (g.feat_valid && g.rec && g.rec_count < g.rec_cap) {
-        float* dst = g.rec + (int64_t)g.rec_count * 4 * c->Nc;
-        TBDG_HIP(hipMemcpyAsync(dst, g.feat, sizeof(float) * 3 * c->Nc, hipMemcpyDeviceToDevice, c->stream));
-        launch_guess_target(c, p_new, p_prev, g.inc[1], 1.0 / (c->beta[s] * c->dt), g.sc, dst + 3 * c->Nc);
+        // sample = network input [6][Nc], then the Gram target [6][Nc]; the
+        // same stage's increments are inc[1] and inc[3] until the shift below
+        float* dst = g.rec + (int64_t)g.rec_count * 12 * c->Nc;
+        TBDG_HIP(hipMemcpyAsync(dst, g.feat, sizeof(float) * 6 * c->Nc, hipMemcpyDeviceToDevice, c->stream));
+        guess_target(c, p_new, p_prev, g.inc[1], g.inc[3], dst + 6 * c->Nc);
         ++g.rec_count;
     }
     g.feat_valid = false;
-    std::swap(g.inc[0], g.inc[1]);
-    g.beta[1] = g.beta[0];
+    double* oldest = g.inc[3];
+    for (int i = 3; i > 0; --i) {
+        g.inc[i] = g.inc[i - 1];
+        g.beta[i] = g.beta[i - 1];
+    }
+    g.inc[0] = oldest;
     vec_axpby(c->stream, c->Np, 1.0, p_new, -1.0, p_prev, g.inc[0]);
     g.beta[0] = c->beta[s];
-    g.n = g.n < 2 ? g.n + 1 : 2;
+    g.n = g.n < 4 ? g.n + 1 : 4;
 }
 
 }  // namespace trbdg

@@ -1,15 +1,22 @@
 // Cell-grid inputs and outputs of the learned pressure initial guess.
 //
 // Per Helmholtz solve of stage s (beta_s, right-hand side b, previous
-// pressure p, the two newest increments inc1 (beta1) and inc2 (beta2)):
-//   f0_K  = mean_K(inc1) / (beta1 dt),  f1_K = mean_K(inc2) / (beta2 dt),
+// pressure p) with the same stage's increments d1, d2 of the last two steps
+// and the newest increment d0 (weight beta0), <a, c>_K = sum_{i in K} W_i a_i c_i
+// (W_i: product of the Gauss weights of node i on the unit cell):
+//   m1_K = <d1, 1>_K / (beta_s dt),  m2_K = <d2, 1>_K / (beta_s dt),
+//   m0_K = <d0, 1>_K / (beta0 dt),
 //   div_K = -(beta_s dt / |K|) sum_{i in K} (b_i - alpha |K| W_i p_i),
-// mean_K = sum_i W_i v_i (W_i: product of the Gauss weights of node i);
-// network input (f0 / s_inc, f1 / s_inc, div / s_div) with s_inc, s_div the
-// RMS over cells of f0 and div (1 where zero).  The network output y (cell
-// averages of the correction to the fallback p + inc2) gives the guess
-// p + inc2 + beta_s dt s_inc I(y), I the multilinear interpolation from the
-// cell centres to the nodes.
+//   cos_K = <d1, d2>_K / sqrt(<d1, d1>_K <d2, d2>_K),
+//   lr_K = clamp(log(<d1, d1>_K / <d2, d2>_K) / 2, -4, 4)   (0 without history);
+// network input (m1 / s_inc, m2 / s_inc, m0 / s_inc, div / s_div, cos, lr)
+// with s_inc, s_div the RMS over cells of m1 and div (1 where zero).  The
+// network output (y0_K, y1_K) corrects the blend of the increments: the
+// guess is p + (2 + y0_K) d1 - (1 - y1_K) d2 at the nodes of K (y = 0: the
+// increment extrapolated from its last two values).  Training target per
+// cell: the Gram data (<d1,d1>, <d1,d2>, <d2,d2>, <e,d1>, <e,d2>, <e,e>)_K / S
+// of the extrapolation's error e = p_new - (p + 2 d1 - d2), S the mean over
+// cells of <d1,d1>_K.
 #include <hip/hip_runtime.h>
 
 #include "internal.hpp"
@@ -31,34 +38,45 @@ __device__ inline double node_weight(const double* W, int i) {
     return w;
 }
 
-// one thread per cell: f0, f1, div into cells[3][Nc]; per-block partial sums
-// of f0^2 and div^2
+// one thread per cell: m1, m2, m0, div, <d1,d1>, <d1,d2>, <d2,d2> into
+// cells[7][Nc]; per-block partial sums of m1^2 and div^2
 template <int DIM, int NP>
-__global__ __launch_bounds__(256) void k_guess_cells(int Nc, Tables t, const double* __restrict__ inc1,
-                                                      const double* __restrict__ inc2,
+__global__ __launch_bounds__(256) void k_guess_cells(int Nc, Tables t, const double* __restrict__ d1,
+                                                      const double* __restrict__ d2,
+                                                      const double* __restrict__ d0,
                                                       const double* __restrict__ b,
-                                                      const double* __restrict__ p, double c0, double c1,
+                                                      const double* __restrict__ p, double c1, double c0,
                                                       double cdiv, double inv_vol, double alpha,
                                                       double* __restrict__ cells, double* partial) {
     constexpr int NB = ipw(NP, DIM);
     const int c = blockIdx.x * 256 + threadIdx.x;
-    double f0 = 0.0, f1 = 0.0, dv = 0.0;
+    double m1 = 0.0, m2 = 0.0, m0 = 0.0, dv = 0.0, g11 = 0.0, g12 = 0.0, g22 = 0.0;
     if (c < Nc) {
         for (int i = 0; i < NB; ++i) {
             const double w = node_weight<DIM, NP>(t.Wp, i);
             const size_t gi = (size_t)c * NB + i;
-            f0 += w * inc1[gi];
-            f1 += w * inc2[gi];
+            const double a1 = d1[gi], a2 = d2[gi];
+            m1 += w * a1;
+            m2 += w * a2;
+            m0 += w * d0[gi];
+            g11 += w * a1 * a1;
+            g12 += w * a1 * a2;
+            g22 += w * a2 * a2;
             dv += b[gi] * inv_vol - alpha * w * p[gi];
         }
-        f0 *= c0;
-        f1 *= c1;
+        m1 *= c1;
+        m2 *= c1;
+        m0 *= c0;
         dv *= cdiv;
-        cells[c] = f0;
-        cells[Nc + c] = f1;
-        cells[2 * Nc + c] = dv;
+        cells[c] = m1;
+        cells[Nc + c] = m2;
+        cells[2 * Nc + c] = m0;
+        cells[3 * Nc + c] = dv;
+        cells[4 * Nc + c] = g11;
+        cells[5 * Nc + c] = g12;
+        cells[6 * Nc + c] = g22;
     }
-    const double s0 = red::block_sum(f0 * f0);
+    const double s0 = red::block_sum(m1 * m1);
     const double s2 = red::block_sum(dv * dv);
     if (threadIdx.x == 0) {
         partial[blockIdx.x] = s0;
@@ -67,7 +85,7 @@ __global__ __launch_bounds__(256) void k_guess_cells(int Nc, Tables t, const dou
 }
 
 // scales from the partials (every block sums them in the same order) and the
-// FP32 network input [3][Nc]; block 0 stores (s_inc, s_div) in sc
+// FP32 network input [6][Nc]; block 0 stores (s_inc, s_div) in sc
 __global__ __launch_bounds__(256) void k_guess_feat(int Nc, const double* __restrict__ cells,
                                                      const double* __restrict__ partial, int G,
                                                      float* __restrict__ feat, double* sc) {
@@ -92,75 +110,89 @@ __global__ __launch_bounds__(256) void k_guess_feat(int Nc, const double* __rest
     const double ri = 1.0 / s_scale[0], rd = 1.0 / s_scale[1];
     const int c = blockIdx.x * 256 + threadIdx.x;
     if (c < Nc) {
+        const double g11 = cells[4 * Nc + c], g12 = cells[5 * Nc + c], g22 = cells[6 * Nc + c];
+        double cs = 0.0, lr = 0.0;
+        if (g11 > 0.0 && g22 > 0.0) {
+            cs = g12 / sqrt(g11 * g22);
+            lr = fmin(fmax(0.5 * log(g11 / g22), -4.0), 4.0);
+        }
         feat[c] = (float)(cells[c] * ri);
         feat[Nc + c] = (float)(cells[Nc + c] * ri);
-        feat[2 * Nc + c] = (float)(cells[2 * Nc + c] * rd);
+        feat[2 * Nc + c] = (float)(cells[2 * Nc + c] * ri);
+        feat[3 * Nc + c] = (float)(cells[3 * Nc + c] * rd);
+        feat[4 * Nc + c] = (float)cs;
+        feat[5 * Nc + c] = (float)lr;
     }
 }
 
-// out_i = p_i + inc2_i + beta_s dt s_inc I(y)_i, I the multilinear
-// interpolation of the cell values from the cell centres (periodic)
-template <int DIM, int NP>
-__global__ __launch_bounds__(256) void k_guess_inject(int Nc, Geom g, Tables t,
-                                                       const double* __restrict__ p,
-                                                       const double* __restrict__ inc2,
-                                                       const float* __restrict__ y, double bdt,
-                                                       const double* __restrict__ sc,
+// out_i = p_i + (2 + y0_K) d1_i - (1 - y1_K) d2_i, y = [2][Nc]
+template <int NB>
+__global__ __launch_bounds__(256) void k_guess_inject(int Nc, const double* __restrict__ p,
+                                                       const double* __restrict__ d1,
+                                                       const double* __restrict__ d2,
+                                                       const float* __restrict__ y,
                                                        double* __restrict__ out) {
-    constexpr int NB = ipw(NP, DIM);
     const int64_t n = (int64_t)Nc * NB;
-    const double f = bdt * sc[0];
     for (int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x; i < n; i += (int64_t)gridDim.x * 256) {
         const int c = (int)(i / NB);
-        int node = (int)(i % NB), rest = c;
-        int lo[3] = {0, 0, 0};
-        double w[3] = {0.0, 0.0, 0.0};
-#pragma unroll
-        for (int a = 0; a < DIM; ++a) {
-            const int ca = rest % g.nc[a];
-            rest /= g.nc[a];
-            const double X = ca + t.xp[node % NP] - 0.5;     // position in cell-centre units
-            node /= NP;
-            const int i0 = (int)floor(X);
-            lo[a] = i0;
-            w[a] = X - i0;
-        }
-        double v = 0.0;
-#pragma unroll
-        for (int corner = 0; corner < (1 << DIM); ++corner) {
-            double wt = 1.0;
-            int idx = 0, stride = 1;
-#pragma unroll
-            for (int a = 0; a < DIM; ++a) {
-                const int bit = (corner >> a) & 1;
-                wt *= bit ? w[a] : 1.0 - w[a];
-                int ia = lo[a] + bit;
-                ia = ia < 0 ? ia + g.nc[a] : (ia >= g.nc[a] ? ia - g.nc[a] : ia);
-                idx += ia * stride;
-                stride *= g.nc[a];
-            }
-            v += wt * (double)y[idx];
-        }
-        out[i] = p[i] + inc2[i] + f * v;
+        out[i] = p[i] + (2.0 + (double)y[c]) * d1[i] - (1.0 - (double)y[Nc + c]) * d2[i];
     }
 }
 
-// out_K = mean_K(p_new - p - inc2) / (beta_s dt) / s_inc
+// Gram data per cell into rows[6][Nc] (unscaled) and per-block partial sums
+// of <d1,d1>_K
 template <int DIM, int NP>
-__global__ __launch_bounds__(256) void k_guess_target(int Nc, Tables t, const double* __restrict__ pn,
-                                                       const double* __restrict__ p,
-                                                       const double* __restrict__ inc2, double inv_bdt,
-                                                       const double* __restrict__ sc,
-                                                       float* __restrict__ out) {
+__global__ __launch_bounds__(256) void k_guess_gram(int Nc, Tables t, const double* __restrict__ pn,
+                                                     const double* __restrict__ p,
+                                                     const double* __restrict__ d1,
+                                                     const double* __restrict__ d2,
+                                                     double* __restrict__ rows, double* partial) {
     constexpr int NB = ipw(NP, DIM);
     const int c = blockIdx.x * 256 + threadIdx.x;
-    if (c >= Nc) return;
-    double s = 0.0;
-    for (int i = 0; i < NB; ++i) {
-        const size_t gi = (size_t)c * NB + i;
-        s += node_weight<DIM, NP>(t.Wp, i) * (pn[gi] - p[gi] - inc2[gi]);
+    double g11 = 0.0, g12 = 0.0, g22 = 0.0, r1 = 0.0, r2 = 0.0, ee = 0.0;
+    if (c < Nc) {
+        for (int i = 0; i < NB; ++i) {
+            const double w = node_weight<DIM, NP>(t.Wp, i);
+            const size_t gi = (size_t)c * NB + i;
+            const double a1 = d1[gi], a2 = d2[gi];
+            const double e = pn[gi] - (p[gi] + 2.0 * a1 - a2);
+            g11 += w * a1 * a1;
+            g12 += w * a1 * a2;
+            g22 += w * a2 * a2;
+            r1 += w * e * a1;
+            r2 += w * e * a2;
+            ee += w * e * e;
+        }
+        rows[c] = g11;
+        rows[Nc + c] = g12;
+        rows[2 * Nc + c] = g22;
+        rows[3 * Nc + c] = r1;
+        rows[4 * Nc + c] = r2;
+        rows[5 * Nc + c] = ee;
     }
-    out[c] = (float)(s * inv_bdt / sc[0]);
+    const double s = red::block_sum(g11);
+    if (threadIdx.x == 0) partial[blockIdx.x] = s;
+}
+
+// out[6][Nc] = rows / S, S = mean over cells of <d1,d1>_K (1 where zero);
+// every block sums the partials in the same order
+__global__ __launch_bounds__(256) void k_guess_gram_scale(int Nc, const double* __restrict__ rows,
+                                                           const double* __restrict__ partial, int G,
+                                                           float* __restrict__ out) {
+    __shared__ double s_inv;
+    double a = 0.0;
+    for (int k = threadIdx.x; k < G; k += 256) a += partial[k];
+    a = red::block_sum(a);
+    if (threadIdx.x == 0) {
+        const double S = a / Nc;
+        s_inv = S > 0.0 ? 1.0 / S : 1.0;
+    }
+    __syncthreads();
+    const int c = blockIdx.x * 256 + threadIdx.x;
+    if (c < Nc) {
+#pragma unroll
+        for (int r = 0; r < 6; ++r) out[(size_t)r * Nc + c] = (float)(rows[(size_t)r * Nc + c] * s_inv);
+    }
 }
 
 inline unsigned nb256(int64_t n) { return (unsigned)((n + 255) / 256); }
@@ -178,15 +210,15 @@ inline unsigned nb256(int64_t n) { return (unsigned)((n + 255) / 256); }
         else throw Error(TBDG_EUNSUPPORTED, "unsupported (dim, pressure nodes)");          \
     } while (0)
 
-int launch_guess_cells(const tbdg_ctx* c, const double* inc1, const double* inc2, const double* b,
-                       const double* p, double c0, double c1, double cdiv, double alpha,
-                       double* cells, double* partial) {
+int launch_guess_cells(const tbdg_ctx* c, const double* d1, const double* d2, const double* d0,
+                       const double* b, const double* p, double c1, double c0, double cdiv,
+                       double alpha, double* cells, double* partial) {
     if (c->mapped)
         throw Error(TBDG_EUNSUPPORTED, "the learned guess is built for affine cells only");
     const unsigned G = nb256(c->Nc);
 #define L_(D, NP)                                                                          \
     hipLaunchKernelGGL((k_guess_cells<D, NP>), dim3(G), dim3(256), 0, c->stream, (int)c->Nc,  \
-                       c->tab, inc1, inc2, b, p, c0, c1, cdiv, 1.0 / c->geom.vol, alpha,   \
+                       c->tab, d1, d2, d0, b, p, c1, c0, cdiv, 1.0 / c->geom.vol, alpha,   \
                        cells, partial);
     TBDG_GUESS_DISPATCH(c->dim, c->np, L_);
 #undef L_
@@ -201,29 +233,32 @@ void launch_guess_feat(const tbdg_ctx* c, const double* cells, const double* par
     TBDG_HIP(hipGetLastError());
 }
 
-void launch_guess_inject(const tbdg_ctx* c, const double* p, const double* inc2, const float* y,
-                         double bdt, const double* sc, double* out) {
+void launch_guess_inject(const tbdg_ctx* c, const double* p, const double* d1, const double* d2,
+                         const float* y, double* out) {
     if (c->mapped)
         throw Error(TBDG_EUNSUPPORTED, "the learned guess is built for affine cells only");
     const int64_t g = nb256(c->Np);
     const unsigned G = (unsigned)(g < 2048 ? g : 2048);
 #define L_(D, NP)                                                                          \
-    hipLaunchKernelGGL((k_guess_inject<D, NP>), dim3(G), dim3(256), 0, c->stream, (int)c->Nc,  \
-                       c->geom, c->tab, p, inc2, y, bdt, sc, out);
+    hipLaunchKernelGGL((k_guess_inject<ipw(NP, D)>), dim3(G), dim3(256), 0, c->stream,        \
+                       (int)c->Nc, p, d1, d2, y, out);
     TBDG_GUESS_DISPATCH(c->dim, c->np, L_);
 #undef L_
     TBDG_HIP(hipGetLastError());
 }
 
-void launch_guess_target(const tbdg_ctx* c, const double* pn, const double* p, const double* inc2,
-                         double inv_bdt, const double* sc, float* out) {
+void launch_guess_target(const tbdg_ctx* c, const double* pn, const double* p, const double* d1,
+                         const double* d2, double* rows, double* partial, float* out) {
     if (c->mapped)
         throw Error(TBDG_EUNSUPPORTED, "the learned guess is built for affine cells only");
+    const unsigned G = nb256(c->Nc);
 #define L_(D, NP)                                                                          \
-    hipLaunchKernelGGL((k_guess_target<D, NP>), dim3(nb256(c->Nc)), dim3(256), 0, c->stream,   \
-                       (int)c->Nc, c->tab, pn, p, inc2, inv_bdt, sc, out);
+    hipLaunchKernelGGL((k_guess_gram<D, NP>), dim3(G), dim3(256), 0, c->stream, (int)c->Nc,   \
+                       c->tab, pn, p, d1, d2, rows, partial);
     TBDG_GUESS_DISPATCH(c->dim, c->np, L_);
 #undef L_
+    hipLaunchKernelGGL(k_guess_gram_scale, dim3(G), dim3(256), 0, c->stream, (int)c->Nc, rows,
+                       partial, (int)G, out);
     TBDG_HIP(hipGetLastError());
 }
 

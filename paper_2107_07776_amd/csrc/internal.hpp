@@ -187,18 +187,20 @@ struct MGData {
 // Learned / extrapolated initial guesses of the Helmholtz solves in a step.
 struct GuessState {
     tbdg_net* net = nullptr;
-    double* inc[2] = {nullptr, nullptr};   // newest pressure increments (inc[0] newest)
-    double beta[2] = {0.0, 0.0};           // stage weights of those solves
+    // newest pressure increments, inc[0] the newest: inc[0], inc[2] of the
+    // stage solved last, inc[1], inc[3] of the other stage (one step apart)
+    double* inc[4] = {nullptr, nullptr, nullptr, nullptr};
+    double beta[4] = {0.0, 0.0, 0.0, 0.0}; // stage weights of those solves
     int n = 0;                              // valid increments
-    double* cells = nullptr;               // f0, f1, div per cell [3][Nc]
+    double* cells = nullptr;               // cell statistics [7][Nc] (also the Gram rows)
     double* partial = nullptr;
     double* sc = nullptr;                   // s_inc, s_div
     double* trial = nullptr;               // learned guess (N_p)
-    float* feat = nullptr;                  // network input [3][Nc]
-    float* y = nullptr;                     // network output [Nc]
+    float* feat = nullptr;                  // network input [6][Nc]
+    float* y = nullptr;                     // network output [2][Nc]
     bool feat_valid = false;
     double last_r[2] = {0.0, 0.0};          // residual norms of the last learned / fallback guesses
-    float* rec = nullptr;                   // recorded samples [cap][4][Nc] (caller's memory)
+    float* rec = nullptr;                   // recorded samples [cap][12][Nc] (caller's memory)
     int rec_cap = 0, rec_count = 0;
     std::vector<void*> allocs;
 };
@@ -224,6 +226,11 @@ struct NoallocScratch {
 struct tbdg_ctx {
     int dim = 0, k = 0, n = 0, np = 0;
     int device = 0;     // HIP device current at create
+    // time scheme of tbdg_step (TBDG_SCHEME_*); the single-stage schemes keep
+    // their (beta, theta) in stage slot 1
+    int scheme = TBDG_SCHEME_TRBDF2;
+    double* s_wlag = nullptr;   // BDF2: momentum predictor of the last step (lazy)
+    bool wlag_valid = false;
     int64_t Nc = 0, nbu = 0, nbp = 0, Nu = 0, Np = 0, Ns = 0;  // Ns = Nu / dim
     trbdg::Geom geom{};
     trbdg::Tables tab{};
@@ -279,11 +286,13 @@ struct tbdg_ctx {
     double* s_p1 = nullptr;
     double* s_pv = nullptr;     // pressure interpolated to velocity nodes (Ns)
     // Dirichlet data: slot 0 at the stage-1 time t^{n+gamma}, slot 1 at t^{n+1}
+    // (the single-stage schemes read slot 1)
     double* bnd_uD[2] = {nullptr, nullptr};
     int64_t bnd_npts = 0;
     int64_t bnd_off[3][2] = {{-1, -1}, {-1, -1}, {-1, -1}};
+    int bnd_slot(int s) const { return (s == 2 || scheme != TBDG_SCHEME_TRBDF2) ? 1 : 0; }
     trbdg::Bnd bnd(int s) const {
-        trbdg::Bnd b{bnd_uD[s == 2 ? 1 : 0], {}};
+        trbdg::Bnd b{bnd_uD[bnd_slot(s)], {}};
         for (int a = 0; a < 3; ++a)
             for (int k = 0; k < 2; ++k) b.off[a][k] = bnd_off[a][k];
         return b;
@@ -497,8 +506,10 @@ void build_line_matrix(int n, const double* W, const double* D, const double* L0
 void level_tables(int np, double pen_p, Tables& t, Line1D& line, double& cr);
 
 // ---- guess-network kernels (net.hip) -----------------------------------------------
+// mode 1 (last layer) writes nout FP32 outputs per voxel, [b][nout][voxel]
 void net_conv(hipStream_t st, const NetGeo& g, int cin, int cout, int mode, const uint16_t* X,
-              const uint16_t* Wp, const float* bias, uint16_t* Yb, float* Yf, const uint16_t* mask);
+              const uint16_t* Wp, const float* bias, uint16_t* Yb, float* Yf, const uint16_t* mask,
+              int nout = 1);
 int net_wgrad(hipStream_t st, const NetGeo& g, int cin, int cout, int dys, const uint16_t* X,
               const uint16_t* dY, float* partial, int rows_per_block);
 void net_wgrad_reduce(hipStream_t st, const float* partial, int G, int cout, int cin, int cin_real,
@@ -510,25 +521,32 @@ void net_pack_bwd(hipStream_t st, const float* theta, int64_t w_off, int cout_re
 void net_copy_bias(hipStream_t st, const float* theta, int64_t b_off, int n, float* b);
 void net_to_channel_last(hipStream_t st, const float* x, int B, int C, int nvox, int CP, uint16_t* out);
 int net_mse(hipStream_t st, const float* yhat, const float* y, int64_t n, float* dy, double* partial);
+int net_quad_loss(hipStream_t st, const float* yhat, const float* gram, int64_t n, int B, float* dy,
+                  double* partial);
 void net_adam(hipStream_t st, int64_t n, float* theta, const float* g, float* m, float* v, float lr,
               float b1, float b2, float eps, float c1, float c2);
 
 // ---- learned initial guess (guess.hip, guess.cpp, net.cpp) --------------------------
-int launch_guess_cells(const tbdg_ctx* c, const double* inc1, const double* inc2, const double* b,
-                       const double* p, double c0, double c1, double cdiv, double alpha,
-                       double* cells, double* partial);
+int launch_guess_cells(const tbdg_ctx* c, const double* d1, const double* d2, const double* d0,
+                       const double* b, const double* p, double c1, double c0, double cdiv,
+                       double alpha, double* cells, double* partial);
 void launch_guess_feat(const tbdg_ctx* c, const double* cells, const double* partial, int G,
                        float* feat, double* sc);
-void launch_guess_inject(const tbdg_ctx* c, const double* p, const double* inc2, const float* y,
-                         double bdt, const double* sc, double* out);
-void launch_guess_target(const tbdg_ctx* c, const double* pn, const double* p, const double* inc2,
-                         double inv_bdt, const double* sc, float* out);
+void launch_guess_inject(const tbdg_ctx* c, const double* p, const double* d1, const double* d2,
+                         const float* y, double* out);
+// Gram target [6][Nc] of the blend (rows: 6 Nc doubles of scratch, partial: Nc/256 + 1)
+void launch_guess_target(const tbdg_ctx* c, const double* pn, const double* p, const double* d1,
+                         const double* d2, double* rows, double* partial, float* out);
 void guess_ensure(tbdg_ctx* c);
 void guess_free(tbdg_ctx* c);
 void guess_reset(tbdg_ctx* c);
-void guess_features(tbdg_ctx* c, int s, const double* b, const double* p, const double* inc1,
-                    double beta1, const double* inc2, double beta2);
-void guess_inject(tbdg_ctx* c, int s, const double* p, const double* inc2, const float* y, double* out);
+// network input [6][Nc] (into the guess state) of the stage-s solve
+void guess_features(tbdg_ctx* c, int s, const double* b, const double* p, const double* d0,
+                    double beta0, const double* d1, const double* d2);
+void guess_inject(tbdg_ctx* c, const double* p, const double* d1, const double* d2, const float* y,
+                  double* out);
+void guess_target(tbdg_ctx* c, const double* pn, const double* p, const double* d1, const double* d2,
+                  float* out);
 // writes the initial guess of the stage-s solve to x; returns 0 (previous
 // pressure), 1 (rescaled increment) or 2 (learned)
 int guess_prepare(tbdg_ctx* c, int s, int mode, const double* b, const double* p_prev, double* x);

@@ -1032,7 +1032,7 @@ MapMesh map_mesh(const tbdg_ctx* c, int s) {
     m.per[1] = c->periodic_flags[1];
     for (int a = 0; a < 2; ++a)
         for (int k = 0; k < 2; ++k) m.off[a][k] = c->bnd_off[a][k];
-    m.uD = c->bnd_uD[s == 2 ? 1 : 0];
+    m.uD = c->bnd_uD[c->bnd_slot(s)];
     return m;
 }
 

@@ -1,7 +1,7 @@
 // Learned pressure-guess network: parameters, activations and the C ABI
 // (create, forward, backward, MSE, Adam, parameter access).
 //
-// Four 3x3x3 circular convolutions 3 -> 32 -> 32 -> 32 -> 1 with ReLU between
+// Four 3x3x3 circular convolutions 6 -> 32 -> 32 -> 32 -> 2 with ReLU between
 // them; bf16 weights and activations, FP32 accumulation, FP32 master
 // parameters in the flat order [W0, b0, W1, b1, W2, b2, W3, b3] with each W
 // as [out][in][dz][dy][dx].
@@ -15,6 +15,10 @@
 
 using trbdg::Error;
 using trbdg::NetGeo;
+
+namespace {
+constexpr int NET_IN = 6, NET_OUT = 2;   // network input channels, outputs per voxel
+}
 
 struct tbdg_net {
     struct Layer {
@@ -150,7 +154,7 @@ tbdg_status tbdg_net_create(int channels, uint64_t seed, void* hip_stream, tbdg_
         if (channels != 32) throw Error(TBDG_EUNSUPPORTED, "the network is built with 32 channels");
         n->C = channels;
         n->stream = static_cast<hipStream_t>(hip_stream);
-        const int cin_real[4] = {3, 32, 32, 32}, cout_real[4] = {32, 32, 32, 1};
+        const int cin_real[4] = {NET_IN, 32, 32, 32}, cout_real[4] = {32, 32, 32, NET_OUT};
         const int cin[4] = {8, 32, 32, 32}, cout[4] = {32, 32, 32, 16};
         int64_t off = 0;
         for (int l = 0; l < 4; ++l) {
@@ -181,11 +185,12 @@ tbdg_status tbdg_net_create(int channels, uint64_t seed, void* hip_stream, tbdg_
         void* h = nullptr;
         TBDG_HIP(hipHostMalloc(&h, sizeof(double) * 1024, hipHostMallocDefault));
         n->host = static_cast<double*>(h);
-        // He-uniform weights U(-a, a), a = sqrt(6 / fan_in), from SplitMix64;
-        // zero biases
+        // He-uniform weights U(-a, a), a = sqrt(6 / fan_in), from SplitMix64,
+        // for the hidden layers; the output layer and every bias start at
+        // zero (the network starts from a zero correction)
         std::vector<float> th(n->np, 0.0f);
         uint64_t s = seed;
-        for (int l = 0; l < 4; ++l) {
+        for (int l = 0; l < 3; ++l) {
             const auto& Y = n->L[l];
             const double a = std::sqrt(6.0 / (27.0 * Y.cin_real));
             for (int64_t i = 0; i < (int64_t)Y.cout_real * Y.cin_real * 27; ++i) {
@@ -280,11 +285,12 @@ tbdg_status tbdg_net_forward(tbdg_net* n, const float* x, float* y, int B, int n
         ensure_capacity(n, nvox * B);
         if (!n->packed) pack_all(n);
         const NetGeo& g = n->geo;
-        trbdg::net_to_channel_last(n->stream, x, B, 3, (int)nvox, 8, n->act[0]);
+        trbdg::net_to_channel_last(n->stream, x, B, NET_IN, (int)nvox, 8, n->act[0]);
         trbdg::net_conv(n->stream, g, 8, 32, 0, n->act[0], n->L[0].Wp, n->L[0].bias, n->act[1], nullptr, nullptr);
         trbdg::net_conv(n->stream, g, 32, 32, 0, n->act[1], n->L[1].Wp, n->L[1].bias, n->act[2], nullptr, nullptr);
         trbdg::net_conv(n->stream, g, 32, 32, 0, n->act[2], n->L[2].Wp, n->L[2].bias, n->act[3], nullptr, nullptr);
-        trbdg::net_conv(n->stream, g, 32, 16, 1, n->act[3], n->L[3].Wp, n->L[3].bias, nullptr, y, nullptr);
+        trbdg::net_conv(n->stream, g, 32, 16, 1, n->act[3], n->L[3].Wp, n->L[3].bias, nullptr, y, nullptr,
+                        NET_OUT);
         n->have_forward = true;
         return TBDG_OK;
     });
@@ -297,7 +303,7 @@ tbdg_status tbdg_net_backward(tbdg_net* n, const float* dy) {
         if (!n->have_forward) throw Error(TBDG_EINVAL, "backward needs a preceding forward");
         if (!n->packed) pack_all(n);
         const NetGeo& g = n->geo;
-        trbdg::net_to_channel_last(n->stream, dy, g.B, 1, g.nvox, 8, n->d4);
+        trbdg::net_to_channel_last(n->stream, dy, g.B, NET_OUT, g.nvox, 8, n->d4);
         wgrad(n, 3, n->act[3], n->d4, 8);
         trbdg::net_conv(n->stream, g, 8, 32, 2, n->d4, n->L[3].Wt, nullptr, n->dbuf[0], nullptr, n->act[3]);
         wgrad(n, 2, n->act[2], n->dbuf[0], 32);
@@ -321,6 +327,23 @@ tbdg_status tbdg_net_mse(tbdg_net* n, const float* yhat, const float* target, in
             double s = 0.0;
             for (int i = 0; i < G; ++i) s += n->host[i];
             *loss = s / (double)count;
+        }
+        return TBDG_OK;
+    });
+}
+
+tbdg_status tbdg_net_quad_loss(tbdg_net* n, const float* yhat, const float* gram, int64_t count, int B,
+                               float* dy, double* loss) {
+    if (!n) return TBDG_EINVAL;
+    return guarded(n, [&]() {
+        require(yhat && gram && dy && count > 0 && B >= 1, "null pointer or empty");
+        const int G = trbdg::net_quad_loss(n->stream, yhat, gram, count, B, dy, n->lpart);
+        if (loss) {
+            TBDG_HIP(hipMemcpyAsync(n->host, n->lpart, sizeof(double) * G, hipMemcpyDeviceToHost, n->stream));
+            TBDG_HIP(hipStreamSynchronize(n->stream));
+            double s = 0.0;
+            for (int i = 0; i < G; ++i) s += n->host[i];
+            *loss = s / ((double)count * B);
         }
         return TBDG_OK;
     });

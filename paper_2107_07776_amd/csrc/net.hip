@@ -54,7 +54,8 @@ struct VoxNbr {
 };
 
 // MODE 0: hidden layer, Y = bf16(relu(acc + bias)), [v][COUT]
-// MODE 1: last layer (output channel 0 of a 16-row tile), y = acc + bias, FP32 [v]
+// MODE 1: last layer (output channels 0 .. nout-1 <= 3 of a 16-row tile),
+//         y = acc + bias, FP32 [b][nout][voxel of the sample]
 // MODE 2: input gradient, Y = bf16(acc * (mask > 0)), mask [v][COUT] bf16
 template <int CIN, int COUT, int MODE>
 __global__ __launch_bounds__(256) void k_conv_mfma(NetGeo g, const uint16_t* __restrict__ X,
@@ -62,7 +63,7 @@ __global__ __launch_bounds__(256) void k_conv_mfma(NetGeo g, const uint16_t* __r
                                                     const float* __restrict__ bias,
                                                     uint16_t* __restrict__ Yb,
                                                     float* __restrict__ Yf,
-                                                    const uint16_t* __restrict__ mask) {
+                                                    const uint16_t* __restrict__ mask, int nout) {
     constexpr int CG = CIN / 8;
     constexpr int S = round4(27 * CG);
     constexpr int CT = COUT / 16;
@@ -98,7 +99,13 @@ __global__ __launch_bounds__(256) void k_conv_mfma(NetGeo g, const uint16_t* __r
         }
         if (v >= total) continue;
         if (MODE == 1) {
-            if (grp == 0) Yf[v] = acc[0][0] + bias[0];
+            // lanes of group 0 hold rows 0..3 of the tile: the output channels
+            if (grp == 0) {
+                const int b = v / g.nvox, r = v - b * g.nvox;
+#pragma unroll
+                for (int o = 0; o < 4; ++o)
+                    if (o < nout) Yf[((size_t)b * nout + o) * g.nvox + r] = acc[0][o] + bias[o];
+            }
             continue;
         }
 #pragma unroll
@@ -257,6 +264,30 @@ __global__ __launch_bounds__(256) void k_to_channel_last(const float* x, int B, 
     }
 }
 
+// Quadratic loss of the guess's blend per cell (y0, y1 at yhat[b][0..1][c],
+// Gram data at gram[b][0..5][c]): l = ee - 2 (y0 r1 + y1 r2) + y0^2 g11
+// + 2 y0 y1 g12 + y1^2 g22, dy = dl/dy / (B n); per-block partial sums of l
+__global__ __launch_bounds__(256) void k_quad_loss(const float* yhat, const float* gram, int64_t n, int B,
+                                                   float* dy, double* partial) {
+    const int64_t total = n * B;
+    const double inv = 1.0 / (double)total;
+    double acc = 0.0;
+    for (int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x; i < total; i += (int64_t)gridDim.x * 256) {
+        const int64_t b = i / n, c = i - b * n;
+        const float* yb = yhat + b * 2 * n;
+        const float* gb = gram + b * 6 * n;
+        const double y0 = yb[c], y1 = yb[n + c];
+        const double g11 = gb[c], g12 = gb[n + c], g22 = gb[2 * n + c];
+        const double r1 = gb[3 * n + c], r2 = gb[4 * n + c], ee = gb[5 * n + c];
+        acc += ee - 2.0 * (y0 * r1 + y1 * r2) + y0 * y0 * g11 + 2.0 * y0 * y1 * g12 + y1 * y1 * g22;
+        float* db = dy + b * 2 * n;
+        db[c] = (float)(2.0 * (y0 * g11 + y1 * g12 - r1) * inv);
+        db[n + c] = (float)(2.0 * (y0 * g12 + y1 * g22 - r2) * inv);
+    }
+    acc = red::block_sum(acc);
+    if (threadIdx.x == 0) partial[blockIdx.x] = acc;
+}
+
 // MSE: dy = 2 (yhat - y) / n, per-block partial sums of (yhat - y)^2
 __global__ __launch_bounds__(256) void k_mse(const float* yhat, const float* y, int64_t n, float* dy,
                                              double* partial) {
@@ -293,10 +324,12 @@ inline unsigned gs(int64_t n) {
 
 // ---- launchers ----------------------------------------------------------------------
 void net_conv(hipStream_t st, const NetGeo& g, int cin, int cout, int mode, const uint16_t* X,
-              const uint16_t* Wp, const float* bias, uint16_t* Yb, float* Yf, const uint16_t* mask) {
+              const uint16_t* Wp, const float* bias, uint16_t* Yb, float* Yf, const uint16_t* mask,
+              int nout) {
+    if (mode == 1 && (nout < 1 || nout > 4)) throw Error(TBDG_EINVAL, "last layer writes 1..4 outputs");
     // 4 waves x 4 strips x 16 voxels per block
     const unsigned G = (unsigned)((g.nvox * (int64_t)g.B + 255) / 256);
-#define K_(CI, CO, M) hipLaunchKernelGGL((k_conv_mfma<CI, CO, M>), dim3(G), dim3(256), 0, st, g, X, Wp, bias, Yb, Yf, mask)
+#define K_(CI, CO, M) hipLaunchKernelGGL((k_conv_mfma<CI, CO, M>), dim3(G), dim3(256), 0, st, g, X, Wp, bias, Yb, Yf, mask, nout)
     if (cin == 8 && cout == 32 && mode == 0) K_(8, 32, 0);
     else if (cin == 32 && cout == 32 && mode == 0) K_(32, 32, 0);
     else if (cin == 32 && cout == 16 && mode == 1) K_(32, 16, 1);
@@ -316,6 +349,7 @@ int net_wgrad(hipStream_t st, const NetGeo& g, int cin, int cout, int dys, const
     if (cin == 8 && cout == 32 && dys == 32) K_(8, 32, 32);
     else if (cin == 32 && cout == 32 && dys == 32) K_(32, 32, 32);
     else if (cin == 32 && cout == 1 && dys == 8) K_(32, 1, 8);
+    else if (cin == 32 && cout == 2 && dys == 8) K_(32, 2, 8);
     else throw Error(TBDG_EUNSUPPORTED, "unsupported weight-gradient shape");
 #undef K_
     TBDG_HIP(hipGetLastError());
@@ -353,6 +387,14 @@ void net_to_channel_last(hipStream_t st, const float* x, int B, int C, int nvox,
     hipLaunchKernelGGL(k_to_channel_last, dim3(gs((int64_t)B * nvox * CP)), dim3(256), 0, st, x, B, C,
                        nvox, CP, out);
     TBDG_HIP(hipGetLastError());
+}
+
+int net_quad_loss(hipStream_t st, const float* yhat, const float* gram, int64_t n, int B, float* dy,
+                  double* partial) {
+    const unsigned G = gs(n * B) < 1024 ? gs(n * B) : 1024;
+    hipLaunchKernelGGL(k_quad_loss, dim3(G), dim3(256), 0, st, yhat, gram, n, B, dy, partial);
+    TBDG_HIP(hipGetLastError());
+    return (int)G;
 }
 
 int net_mse(hipStream_t st, const float* yhat, const float* y, int64_t n, float* dy, double* partial) {

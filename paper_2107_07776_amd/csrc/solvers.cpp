@@ -524,4 +524,91 @@ tbdg_status step(tbdg_ctx* c, tbdg_state* S, const tbdg_solver_opts& mo,
     return TBDG_OK;
 }
 
+// One step of the single-stage projection schemes of Sec. 2 (eqs.
+// momentum_BCG / helmholtz_BCG and momentum_HI / helmholtz_HI) with their
+// (beta, theta) in stage slot 1; S->u_hist holds u^{n-1}.
+tbdg_status step_single(tbdg_ctx* c, tbdg_state* S, const tbdg_solver_opts& mo,
+                        const tbdg_solver_opts& po, tbdg_solve_info info[4]) {
+    const int64_t Nu = c->Nu, Np = c->Np;
+    hipStream_t st = c->stream;
+    const size_t bu = sizeof(double) * Nu, bp = sizeof(double) * Np;
+    const bool bcg = c->scheme == TBDG_SCHEME_BCG;
+    const bool bnd = c->bnd_npts > 0;
+    tbdg_solve_info loc[4] = {};
+    c->nl_solves[0] = c->nl_solves[1] = 0;
+    // first advecting field: the extrapolation to t^{n+1/2} (Crank-Nicolson)
+    // or the previous step's predictor (BDF2; u^n at the first step); the
+    // BDF2 base state (4 u^n - u^{n-1})/3 in s_ug
+    if (bcg) {
+        vec_axpby(st, Nu, 1.5, S->u, -0.5, S->u_hist, c->s_w);
+    } else {
+        const bool lag = S->n > 0 && c->wlag_valid;
+        TBDG_HIP(hipMemcpyAsync(c->s_w, lag ? c->s_wlag : S->u, bu, hipMemcpyDeviceToDevice, st));
+        vec_axpby(st, Nu, 4.0 / 3.0, S->u, -1.0 / 3.0, S->u_hist, c->s_ug);
+    }
+    if (mo.guess == TBDG_GUESS_PREVIOUS)
+        vec_axpby(st, Nu, 2.0, S->u, -1.0, S->u_hist, c->s_ustar);   // extrapolation to t^{n+1}
+    else
+        TBDG_HIP(hipMemcpyAsync(c->s_ustar, S->u, bu, hipMemcpyDeviceToDevice, st));
+    const int max_solves = bcg ? c->nl_max : 1;
+    tbdg_solve_info one{};
+    tbdg_status rc = TBDG_OK;
+    for (int solves = 1;; ++solves) {
+        if (bcg)
+            rhs_momentum_base(c, 1, S->u, nullptr, c->s_w, S->p, c->s_rhs);
+        else
+            launch_rhs_momentum(c, c->mcoef(1), c->s_ug, c->s_ug, c->s_w, 0.0, 0.0, nullptr, nullptr,
+                                0.0, 0.0, S->p, c->s_rhs);
+        if (bnd) launch_dirichlet_rhs(c, 1, c->s_w, c->s_rhs);
+        rc = solve_momentum(c, 1, c->s_w, c->s_rhs, c->s_ustar, mo, &one);
+        if (solves == 1) loc[0].res0 = one.res0;
+        loc[0].iters += one.iters;
+        loc[0].res_final = one.res_final;
+        c->nl_solves[0] = solves;
+        if (rc != TBDG_OK || solves >= max_solves) break;
+        // next midpoint velocity (u* + u^n)/2; stop once it has settled
+        vec_axpby(st, Nu, 0.5, c->s_ustar, 0.5, S->u, c->s_u1);
+        if (c->nl_tol > 0.0) {
+            vec_axpby(st, Nu, 1.0, c->s_u1, -1.0, c->s_w, c->s_rhs);
+            const double dn = norm2(c, Nu, c->s_rhs);
+            if (dn <= c->nl_tol * norm2(c, Nu, c->s_u1)) break;
+        }
+        TBDG_HIP(hipMemcpyAsync(c->s_w, c->s_u1, bu, hipMemcpyDeviceToDevice, st));
+    }
+    if (info) info[0] = loc[0];
+    if (rc != TBDG_OK) {
+        guess_reset(c);
+        return rc;
+    }
+    // projection (u** in s_u1, the predictor stays in s_ustar), Helmholtz
+    // solve, correction into s_ug
+    const double b1 = c->beta[1] * c->dt;
+    launch_add_grad_p(c, c->s_ustar, b1, S->p, c->s_u1);
+    rhs_pressure(c, 1, c->s_u1, S->p, c->s_pb);
+    const int used = guess_prepare(c, 1, po.guess, c->s_pb, S->p, c->s_p1);
+    rc = solve_pressure(c, 1, c->s_pb, c->s_p1, po, &loc[1]);
+    loc[1].guess_used = used;
+    if (info) {
+        info[1] = loc[1];
+        info[2] = info[3] = tbdg_solve_info{};
+    }
+    if (rc != TBDG_OK) {
+        guess_reset(c);
+        return rc;
+    }
+    guess_after_solve(c, 1, c->s_p1, S->p);
+    launch_add_grad_p(c, c->s_u1, -b1, c->s_p1, c->s_ug);
+    // ---- commit ----
+    if (!bcg) {
+        TBDG_HIP(hipMemcpyAsync(c->s_wlag, c->s_ustar, bu, hipMemcpyDeviceToDevice, st));
+        c->wlag_valid = true;
+    }
+    TBDG_HIP(hipMemcpyAsync(S->u_hist, S->u, bu, hipMemcpyDeviceToDevice, st));
+    TBDG_HIP(hipMemcpyAsync(S->u, c->s_ug, bu, hipMemcpyDeviceToDevice, st));
+    TBDG_HIP(hipMemcpyAsync(S->p, c->s_p1, bp, hipMemcpyDeviceToDevice, st));
+    S->t += c->dt;
+    S->n += 1;
+    return TBDG_OK;
+}
+
 }  // namespace trbdg

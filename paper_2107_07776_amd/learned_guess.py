@@ -14,13 +14,15 @@ import torch
 
 
 def generate(ctx, initial_state, seeds, steps, discard, precond="mg_fp32", tol=1e-8, maxiter=20000,
-             log=None):
-    """Samples [S][4][N_c] (float32, device) from ``steps`` recorded steps per
+             log=None, **step_kw):
+    """Samples [S][12][N_c] (float32, device: network input [6][N_c], Gram
+    target [6][N_c]) from ``steps`` recorded steps per
     seed after ``discard`` unrecorded ones.  ``initial_state(seed)`` returns
-    device tensors (u, u_hist, p).  A trajectory whose step fails (a solve
-    that does not converge) ends there; its samples so far are kept."""
+    device tensors (u, u_hist, p); ``step_kw`` go to ``ctx.step`` (momentum
+    solver settings).  A trajectory whose step fails (a solve that does not
+    converge) ends there; its samples so far are kept."""
     cap = 2 * steps * len(seeds)
-    buf = torch.zeros((cap, 4, ctx.N_c), dtype=torch.float32, device=ctx.device)
+    buf = torch.zeros((cap, 12, ctx.N_c), dtype=torch.float32, device=ctx.device)
     total = 0
     for seed in seeds:
         u, uh, p = initial_state(seed)
@@ -31,11 +33,12 @@ def generate(ctx, initial_state, seeds, steps, discard, precond="mg_fp32", tol=1
             if n == discard:
                 # recording clears the history: one more step refills it
                 ctx.guess_record(buf[total:])
-            _, st = ctx.step(u, uh, p, t, n, mom_tol=tol, prs_tol=tol, prs_maxiter=maxiter,
-                             precond=precond, guess="previous", check=False)
+            info, st = ctx.step(u, uh, p, t, n, mom_tol=tol, prs_tol=tol, prs_maxiter=maxiter,
+                                precond=precond, guess="previous", check=False, **step_kw)
             if st != 0:
                 if log:
-                    log(f"seed {seed}: step {n} failed with status {st}; trajectory ends")
+                    log(f"seed {seed}: step {n} failed with status {st} (iterations "
+                        f"{[i['iters'] for i in info]}); trajectory ends")
                 break
             t += ctx.dt
         total += ctx.guess_recorded()
@@ -44,12 +47,13 @@ def generate(ctx, initial_state, seeds, steps, discard, precond="mg_fp32", tol=1
 
 
 def train(net, samples, grid, epochs, batch=8, lr=1e-3, seed=0, log=None):
-    """Adam on the mean-squared error of the recorded targets; returns the
-    mean loss of every epoch.  ``grid`` = (nx, ny, nz) of the cell grid."""
+    """Adam on the per-cell quadratic loss of the recorded Gram targets (the
+    squared nodal error of the blended increment); returns the mean loss of
+    every epoch.  ``grid`` = (nx, ny, nz) of the cell grid."""
     nx, ny, nz = grid
     S = samples.shape[0]
-    x_all = samples[:, :3].reshape(S, 3, nz, ny, nx)
-    y_all = samples[:, 3].reshape(S, nz, ny, nx)
+    x_all = samples[:, :6].reshape(S, 6, nz, ny, nx)
+    y_all = samples[:, 6:].reshape(S, 6, nz, ny, nx)
     gen = torch.Generator(device="cpu")
     gen.manual_seed(seed)
     losses = []
@@ -61,7 +65,7 @@ def train(net, samples, grid, epochs, batch=8, lr=1e-3, seed=0, log=None):
             x = x_all.index_select(0, idx).contiguous()
             y = y_all.index_select(0, idx).contiguous()
             yhat = net.forward(x)
-            loss, dy = net.mse(yhat, y)
+            loss, dy = net.quad_loss(yhat, y)
             net.zero_grad()
             net.backward(dy)
             net.adam_step(lr)
@@ -74,34 +78,49 @@ def train(net, samples, grid, epochs, batch=8, lr=1e-3, seed=0, log=None):
 
 
 def evaluate(ctx, initial_state, seeds, steps, discard, modes=("given", "previous", "learned"),
-             precond="mg_fp32", tol=1e-8, maxiter=20000):
+             precond="mg_fp32", tol=1e-8, maxiter=20000, log=None, **step_kw):
     """Mean pressure-solve iterations, fallback rate and steps/s per guess
     mode over held-out trajectories (identical trajectories for every mode
-    up to the solver tolerance)."""
-    out = {}
+    up to the solver tolerance); ``step_kw`` go to ``ctx.step``.  A step
+    that fails (a solve that does not converge) ends that trajectory for
+    every mode: the statistics cover the steps all modes completed."""
+    per = {m: {} for m in modes}      # mode -> seed -> list of (iters, used, secs) per step
+    limit = {seed: discard + steps for seed in seeds}
     for mode in modes:
-        iters, used, secs, nsteps = [], [], 0.0, 0
         for seed in seeds:
             u, uh, p = initial_state(seed)
             ctx.guess_reset()
             t = 0.0
-            for n in range(discard + steps):
+            rec = []
+            for n in range(limit[seed]):
                 torch.cuda.synchronize()
                 t0 = time.perf_counter()
-                info, _ = ctx.step(u, uh, p, t, n, mom_tol=tol, prs_tol=tol, prs_maxiter=maxiter,
-                                   precond=precond, guess=mode)
+                info, st = ctx.step(u, uh, p, t, n, mom_tol=tol, prs_tol=tol, prs_maxiter=maxiter,
+                                    precond=precond, guess=mode, check=False, **step_kw)
                 torch.cuda.synchronize()
                 t += ctx.dt
-                if n >= discard:
-                    secs += time.perf_counter() - t0
-                    nsteps += 1
-                    for j in (1, 3):
-                        iters.append(info[j]["iters"])
-                        used.append(info[j]["guess_used"])
-        res = {"mean_pressure_iterations": sum(iters) / len(iters), "steps_per_s": nsteps / secs,
-               "solves": len(iters)}
+                if st != 0:
+                    if log:
+                        log(f"{mode}, seed {seed}: step {n} failed with status {st} "
+                            f"(iterations {[i['iters'] for i in info]}); trajectory ends")
+                    limit[seed] = n
+                    break
+                rec.append(([info[j]["iters"] for j in (1, 3)], [info[j]["guess_used"] for j in (1, 3)],
+                            time.perf_counter() - t0))
+            per[mode][seed] = rec
+    out = {}
+    for mode in modes:
+        iters, used, secs, nsteps = [], [], 0.0, 0
+        for seed in seeds:
+            for its, us, dt_s in per[mode][seed][discard:limit[seed]]:
+                iters += its
+                used += us
+                secs += dt_s
+                nsteps += 1
+        res = {"mean_pressure_iterations": sum(iters) / max(len(iters), 1),
+               "steps_per_s": nsteps / secs if secs > 0 else 0.0, "solves": len(iters), "steps": nsteps}
         if mode == "learned":
-            res["learned_used_rate"] = sum(1 for g in used if g == 2) / len(used)
+            res["learned_used_rate"] = sum(1 for g in used if g == 2) / max(len(used), 1)
             res["fallback_rate"] = 1.0 - res["learned_used_rate"]
         out[mode] = res
     return out

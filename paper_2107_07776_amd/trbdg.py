@@ -28,18 +28,26 @@ EXPORTED = [
     "tbdg_mg_levels", "tbdg_mg_apply", "tbdg_net_create", "tbdg_net_destroy",
     "tbdg_net_last_error", "tbdg_net_num_params", "tbdg_net_set_params", "tbdg_net_get_params",
     "tbdg_net_get_grads", "tbdg_net_zero_grad", "tbdg_net_forward", "tbdg_net_backward",
-    "tbdg_net_mse", "tbdg_net_adam_step", "tbdg_set_guess_net", "tbdg_guess_reset",
-    "tbdg_guess_record", "tbdg_guess_recorded", "tbdg_guess_features", "tbdg_guess_inject",
+    "tbdg_net_mse", "tbdg_net_quad_loss", "tbdg_net_adam_step", "tbdg_set_guess_net",
+    "tbdg_guess_reset", "tbdg_guess_record", "tbdg_guess_recorded", "tbdg_guess_features",
+    "tbdg_guess_inject", "tbdg_guess_target",
     "tbdg_guess_last", "tbdg_face_qpoints", "tbdg_set_dirichlet", "tbdg_set_nonlinear",
+    "tbdg_set_scheme",
     "tbdg_nonlinear_solves", "tbdg_profile_bytes", "tbdg_precond_momentum",
 ]
 
-GUESS = {"given": 0, "previous": 1, "learned": 2}
+GUESS = {"given": 0, "previous": 1, "learned": 2, "extrap2": 3}
+
+# channels of the guess network's input and output per cell
+GUESS_IN, GUESS_OUT = 6, 2
 
 # largest pressure space of the allocation-free solve (TBDG_NOALLOC_MAX_NP)
 NOALLOC_MAX_NP = 1 << 20
 
 PRECOND = {"jacobi": 0, "mg_fp32": 1, "mg_bf16": 2, "line": 3}
+
+# time schemes of step(): TR-BDF2, Bell-Colella-Glaz (Crank-Nicolson), BDF2
+SCHEME = {"trbdf2": 0, "bcg": 1, "bdf2": 2}
 
 
 class TrbdgError(RuntimeError):
@@ -136,6 +144,7 @@ def load_library(path=LIB_PATH):
         "tbdg_net_forward": ([vp, vp, vp, i, i, i, i], i),
         "tbdg_net_backward": ([vp, vp], i),
         "tbdg_net_mse": ([vp, vp, vp, i64, vp, P(d)], i),
+        "tbdg_net_quad_loss": ([vp, vp, vp, i64, i, vp, P(d)], i),
         "tbdg_net_adam_step": ([vp, ctypes.c_float, ctypes.c_float, ctypes.c_float, ctypes.c_float], i),
         "tbdg_set_guess_net": ([vp, vp], i),
         "tbdg_guess_reset": ([vp], i),
@@ -145,11 +154,13 @@ def load_library(path=LIB_PATH):
         "tbdg_face_qpoints": ([vp, P(i64), vp], i),
         "tbdg_set_dirichlet": ([vp, i, vp], i),
         "tbdg_set_nonlinear": ([vp, i, d], i),
+        "tbdg_set_scheme": ([vp, i], i),
         "tbdg_nonlinear_solves": ([vp, P(i)], i),
         "tbdg_profile_bytes": ([vp, i, P(d)], i),
         "tbdg_precond_momentum": ([vp, i, vp, vp, vp], i),
-        "tbdg_guess_features": ([vp, i, vp, vp, vp, d, vp, d, vp, P(d)], i),
-        "tbdg_guess_inject": ([vp, i, vp, vp, vp, d, vp], i),
+        "tbdg_guess_features": ([vp, i, vp, vp, vp, d, vp, vp, vp, P(d)], i),
+        "tbdg_guess_inject": ([vp, vp, vp, vp, vp, vp], i),
+        "tbdg_guess_target": ([vp, vp, vp, vp, vp, vp], i),
     }
     for name, (args, res) in sig.items():
         fn = getattr(lib, name)
@@ -386,6 +397,12 @@ class Context:
         (1 = the linearised scheme with the extrapolated advector)."""
         self._check(self.lib.tbdg_set_nonlinear(self.h, int(max_solves), float(tol)))
 
+    def set_scheme(self, scheme):
+        """Time scheme of step(): "trbdf2", "bcg" or "bdf2" (for the
+        single-stage schemes u_hist is u^{n-1} and the solves fill info[0]
+        and info[1])."""
+        self._check(self.lib.tbdg_set_scheme(self.h, SCHEME[scheme]))
+
     def mg_setup(self, degree=0, lanczos_steps=0, range_=0.0, safety=0.0, coarse_cells=0,
                  max_coarse_dofs=0):
         """Build the pressure multigrid hierarchy (0 = library default)."""
@@ -420,14 +437,15 @@ class Context:
 
     def guess_record(self, buf):
         """Record (input, target) samples of the pressure solves into buf
-        (float32 CUDA tensor [capacity][4][N_c]); None stops recording."""
+        (float32 CUDA tensor [capacity][12][N_c]: network input [6][N_c],
+        Gram target [6][N_c]); None stops recording."""
         if buf is None:
             self._rec = None
             self._check(self.lib.tbdg_guess_record(self.h, None, 0))
             return
         if buf.dtype != torch.float32 or buf.device.type != "cuda" or not buf.is_contiguous() \
-                or buf.dim() != 3 or buf.shape[1:] != (4, self.N_c):
-            raise ValueError("buf must be a contiguous float32 CUDA tensor [capacity][4][N_c]")
+                or buf.dim() != 3 or buf.shape[1:] != (GUESS_IN + 6, self.N_c):
+            raise ValueError("buf must be a contiguous float32 CUDA tensor [capacity][12][N_c]")
         self._rec = buf
         self._check(self.lib.tbdg_guess_record(self.h, _ptr(buf), buf.shape[0]))
 
@@ -442,23 +460,33 @@ class Context:
         self._check(self.lib.tbdg_guess_last(self.h, ctypes.byref(a), ctypes.byref(b)))
         return a.value, b.value
 
-    def guess_features(self, stage, b, p_prev, inc1, beta1, inc2, beta2):
-        """(x [3][N_c] float32, (s_inc, s_div)) of the guess network."""
-        x = torch.empty((3, self.N_c), dtype=torch.float32, device=self.device)
+    def guess_features(self, stage, b, p_prev, d0, beta0, d1, d2):
+        """(x [6][N_c] float32, (s_inc, s_div)) of the guess network."""
+        x = torch.empty((GUESS_IN, self.N_c), dtype=torch.float32, device=self.device)
         sc = (ctypes.c_double * 2)()
         self._check(self.lib.tbdg_guess_features(
             self.h, stage, _ptr(self._vec(b, self.N_p, "b")), _ptr(self._vec(p_prev, self.N_p, "p_prev")),
-            _ptr(self._vec(inc1, self.N_p, "inc1")), float(beta1), _ptr(self._vec(inc2, self.N_p, "inc2")),
-            float(beta2), _ptr(x), sc))
+            _ptr(self._vec(d0, self.N_p, "d0")), float(beta0), _ptr(self._vec(d1, self.N_p, "d1")),
+            _ptr(self._vec(d2, self.N_p, "d2")), _ptr(x), sc))
         return x, (sc[0], sc[1])
 
-    def guess_inject(self, stage, p_prev, inc2, y, s_inc):
+    def guess_inject(self, p_prev, d1, d2, y):
+        """p_prev + (2 + y0_K) d1 - (1 - y1_K) d2 for y float32 [2][N_c]."""
         out = self.empty_p()
-        if y.dtype != torch.float32 or y.numel() != self.N_c or not y.is_contiguous():
-            raise ValueError("y must be a contiguous float32 tensor of N_c entries")
-        self._check(self.lib.tbdg_guess_inject(self.h, stage, _ptr(self._vec(p_prev, self.N_p, "p_prev")),
-                                               _ptr(self._vec(inc2, self.N_p, "inc2")), _ptr(y),
-                                               float(s_inc), _ptr(out)))
+        if y.dtype != torch.float32 or y.numel() != GUESS_OUT * self.N_c or not y.is_contiguous():
+            raise ValueError("y must be a contiguous float32 tensor of 2 N_c entries")
+        self._check(self.lib.tbdg_guess_inject(self.h, _ptr(self._vec(p_prev, self.N_p, "p_prev")),
+                                               _ptr(self._vec(d1, self.N_p, "d1")),
+                                               _ptr(self._vec(d2, self.N_p, "d2")), _ptr(y), _ptr(out)))
+        return out
+
+    def guess_target(self, p_new, p_prev, d1, d2):
+        """Gram target [6][N_c] float32 of a solve (training data of the network)."""
+        out = torch.empty((6, self.N_c), dtype=torch.float32, device=self.device)
+        self._check(self.lib.tbdg_guess_target(self.h, _ptr(self._vec(p_new, self.N_p, "p_new")),
+                                               _ptr(self._vec(p_prev, self.N_p, "p_prev")),
+                                               _ptr(self._vec(d1, self.N_p, "d1")),
+                                               _ptr(self._vec(d2, self.N_p, "d2")), _ptr(out)))
         return out
 
     def profile(self, enable):
@@ -526,14 +554,14 @@ class Net:
         self._check(self.lib.tbdg_net_zero_grad(self.h))
 
     def forward(self, x):
-        """x: float32 [B][3][nz][ny][nx] -> y: float32 [B][nz][ny][nx]."""
-        if x.dim() != 5 or x.shape[1] != 3:
-            raise ValueError("x must have shape [B][3][nz][ny][nx]")
+        """x: float32 [B][6][nz][ny][nx] -> y: float32 [B][2][nz][ny][nx]."""
+        if x.dim() != 5 or x.shape[1] != GUESS_IN:
+            raise ValueError(f"x must have shape [B][{GUESS_IN}][nz][ny][nx]")
         B, _, nz, ny, nx = x.shape
         self._f32(x, x.numel(), "x")
-        y = torch.empty((B, nz, ny, nx), dtype=torch.float32, device=self.device)
+        y = torch.empty((B, GUESS_OUT, nz, ny, nx), dtype=torch.float32, device=self.device)
         self._check(self.lib.tbdg_net_forward(self.h, _ptr(x), _ptr(y), B, nx, ny, nz))
-        self.shape = (B, nz, ny, nx)
+        self.shape = (B, GUESS_OUT, nz, ny, nx)
         return y
 
     def backward(self, dy):
@@ -548,6 +576,18 @@ class Net:
         self._check(self.lib.tbdg_net_mse(self.h, _ptr(self._f32(yhat, yhat.numel(), "yhat")),
                                           _ptr(self._f32(target, yhat.numel(), "target")),
                                           yhat.numel(), _ptr(dy), ctypes.byref(loss)))
+        return loss.value, dy
+
+    def quad_loss(self, yhat, gram):
+        """(loss, dL/dyhat) of the guess's per-cell quadratic loss; yhat
+        [B][2][...], gram [B][6][...] (float32)."""
+        B = yhat.shape[0]
+        n = yhat.numel() // (GUESS_OUT * B)
+        dy = torch.empty_like(yhat)
+        loss = ctypes.c_double()
+        self._check(self.lib.tbdg_net_quad_loss(self.h, _ptr(self._f32(yhat, yhat.numel(), "yhat")),
+                                                _ptr(self._f32(gram, 6 * B * n, "gram")), n, B, _ptr(dy),
+                                                ctypes.byref(loss)))
         return loss.value, dy
 
     def adam_step(self, lr, beta1=0.9, beta2=0.999, eps=1e-8):

@@ -56,14 +56,14 @@ def test_forward_matches_oracle(shape):
     B, nz, ny, nx = shape
     print(f"[case] forward B={B} grid={nx}x{ny}x{nz}", flush=True)
     theta = _theta(10)
-    x = np.random.default_rng(11).standard_normal((B, 3, nz, ny, nx)).astype(np.float32)
+    x = np.random.default_rng(11).standard_normal((B, cnn.N_IN, nz, ny, nx)).astype(np.float32)
     net = _net(theta)
     y = net.forward(torch.tensor(x, device="cuda")).cpu().numpy()
     p = cnn.unpack(cnn.bf16_round(theta))
     xo = cnn.bf16_round(x)
     yr, _ = cnn.forward(p, xo, act_round=cnn.bf16_round)
     y64, _ = cnn.forward(p, xo)
-    e1, e2 = _rel(y, yr[:, 0]), _rel(y, y64[:, 0])
+    e1, e2 = _rel(y, yr), _rel(y, y64)
     print(f"forward: vs rounded-activation oracle {e1:.2e}, vs FP64 oracle {e2:.2e}")
     assert e1 <= TOL_FWD_ROUNDED and e2 <= TOL_FWD
     net.close()
@@ -75,8 +75,8 @@ def test_backward_matches_oracle(shape):
     print(f"[case] backward B={B} grid={nx}x{ny}x{nz}", flush=True)
     theta = _theta(20)
     rng = np.random.default_rng(21)
-    x = rng.standard_normal((B, 3, nz, ny, nx)).astype(np.float32)
-    target = rng.standard_normal((B, nz, ny, nx)).astype(np.float32)
+    x = rng.standard_normal((B, cnn.N_IN, nz, ny, nx)).astype(np.float32)
+    target = rng.standard_normal((B, cnn.N_OUT, nz, ny, nx)).astype(np.float32)
     net = _net(theta)
     yt = net.forward(torch.tensor(x, device="cuda"))
     loss, dy = net.mse(yt, torch.tensor(target, device="cuda"))
@@ -85,7 +85,7 @@ def test_backward_matches_oracle(shape):
     g = net.grads().cpu().numpy()
     p = cnn.unpack(cnn.bf16_round(theta))
     yo, acts = cnn.forward(p, cnn.bf16_round(x), act_round=cnn.bf16_round)
-    lo, dyo = cnn.mse(yo, target[:, None])
+    lo, dyo = cnn.mse(yo, target)
     assert abs(loss - lo) <= 1e-2 * lo
     go = cnn.backward(p, acts, dyo)
     for l, ((gw, gb), (Wg, bg)) in enumerate(zip(go, cnn.unpack(g.astype(np.float64)))):
@@ -99,9 +99,10 @@ def test_adam_step_and_training_reduce_loss():
     B, nz, ny, nx = 2, 8, 8, 8
     theta = _theta(30)
     rng = np.random.default_rng(31)
-    x = rng.standard_normal((B, 3, nz, ny, nx)).astype(np.float32)
+    x = rng.standard_normal((B, cnn.N_IN, nz, ny, nx)).astype(np.float32)
     # a target the network can represent: a smooth function of the inputs
-    target = (0.5 * x[:, 0] - 0.25 * np.roll(x[:, 1], 1, axis=-1)).astype(np.float32)
+    target = np.stack([0.5 * x[:, 0] - 0.25 * np.roll(x[:, 1], 1, axis=-1),
+                       0.3 * x[:, 4] + 0.2 * x[:, 2]], 1).astype(np.float32)
     net = _net(theta)
     xt, tt = torch.tensor(x, device="cuda"), torch.tensor(target, device="cuda")
     lr = 1e-3
@@ -114,7 +115,7 @@ def test_adam_step_and_training_reduce_loss():
     step = (net.params().cpu().numpy() - theta) / lr
     p = cnn.unpack(cnn.bf16_round(theta))
     yo, acts = cnn.forward(p, cnn.bf16_round(x), act_round=cnn.bf16_round)
-    _, dyo = cnn.mse(yo, target[:, None])
+    _, dyo = cnn.mse(yo, target)
     go = cnn.pack(cnn.backward(p, acts, dyo))
     expect = (cnn.adam_step(theta.astype(np.float64), go, np.zeros_like(go), np.zeros_like(go), 1, lr)
               - theta) / lr
@@ -137,7 +138,7 @@ def test_throughput_report():
     """Forward and forward+backward times at 32^3 and 48^3 (report only)."""
     for n in (32, 48):
         net = _net(_theta(40))
-        x = torch.randn((1, 3, n, n, n), device="cuda", dtype=torch.float32)
+        x = torch.randn((1, cnn.N_IN, n, n, n), device="cuda", dtype=torch.float32)
         y = net.forward(x)
         _, dy = net.mse(y, torch.zeros_like(y))
         net.backward(dy)
@@ -154,7 +155,26 @@ def test_throughput_report():
             net.backward(dy)
         torch.cuda.synchronize()
         tb = (time.perf_counter() - t0) / reps
-        flops = 2 * n ** 3 * 27 * (3 * 32 + 2 * 32 * 32 + 32)
+        flops = 2 * n ** 3 * 27 * (cnn.N_IN * 32 + 2 * 32 * 32 + 32 * cnn.N_OUT)
         print(f"{n}^3: forward {tf * 1e3:.3f} ms ({flops / tf / 1e12:.1f} TFLOP/s), "
               f"forward+backward {tb * 1e3:.3f} ms")
         net.close()
+
+
+def test_quad_loss_matches_oracle():
+    """The guess's training loss and its gradient against oracle.guess.quad_loss
+    (FP32 data, FP64 accumulation of the loss: 1e-6 relative)."""
+    from oracle import guess as oguess
+    from paper_2107_07776_amd import Net
+    rng = np.random.default_rng(50)
+    B, n = 3, 1000
+    A = rng.standard_normal((3, B, n, 5))                  # d1, d2, e at 5 nodes per cell
+    G = np.stack([(A[0] ** 2).sum(-1), (A[0] * A[1]).sum(-1), (A[1] ** 2).sum(-1),
+                  (A[2] * A[0]).sum(-1), (A[2] * A[1]).sum(-1), (A[2] ** 2).sum(-1)], 1).astype(np.float32)
+    y = rng.standard_normal((B, 2, n)).astype(np.float32)
+    net = Net(32, seed=1)
+    loss, dy = net.quad_loss(torch.tensor(y, device="cuda"), torch.tensor(G, device="cuda"))
+    lo, dyo = oguess.quad_loss(y.astype(np.float64), G.astype(np.float64))
+    assert abs(loss - lo) <= 1e-6 * abs(lo)
+    assert _rel(dy.cpu().numpy(), dyo) <= 1e-6
+    net.close()

@@ -14,9 +14,9 @@ import numpy as np
 from oracle import cnn
 
 
-def _params(rng, channels, n_in=3, scale=0.3):
-    theta = rng.standard_normal(cnn.n_params(channels, n_in)) * scale
-    return theta, cnn.unpack(theta, channels, n_in)
+def _params(rng, channels, n_in=3, n_out=1, scale=0.3):
+    theta = rng.standard_normal(cnn.n_params(channels, n_in, n_out)) * scale
+    return theta, cnn.unpack(theta, channels, n_in, n_out)
 
 
 def test_conv_equals_brute_force_loops():
@@ -61,7 +61,7 @@ def test_backward_equals_finite_differences():
     target = rng.standard_normal((2, 1, 3, 3, 4))
 
     def loss(th):
-        out, _ = cnn.forward(cnn.unpack(th, ch), X)
+        out, _ = cnn.forward(cnn.unpack(th, ch, 3, 1), X)
         return cnn.mse(out, target)[0]
 
     out, acts = cnn.forward(params, X)
@@ -102,5 +102,32 @@ def test_bf16_rounding():
     assert np.isnan(cnn.bf16_round(np.array([np.nan], dtype=np.float32))[0])
 
 
+def test_backward_with_the_guess_loss_equals_finite_differences():
+    """The library's shapes (6 inputs, 2 outputs) under the guess's
+    quadratic loss (oracle.guess.quad_loss, Gram data of a random
+    positive semi-definite form per cell)."""
+    from oracle import guess
+    rng = np.random.default_rng(5)
+    ch = 2
+    theta, params = _params(rng, ch, cnn.N_IN, cnn.N_OUT)
+    X = rng.standard_normal((2, cnn.N_IN, 2, 3, 3))
+    A = rng.standard_normal((2, 3, 2, 18))          # per cell: d1, d2, e at 3 "nodes"
+    G = np.stack([(A[:, :, 0] ** 2).sum(1), (A[:, :, 0] * A[:, :, 1]).sum(1), (A[:, :, 1] ** 2).sum(1),
+                  (A[:, :, 0] * A[:, :, 1]).sum(1) * 0.3, (A[:, :, 1] ** 2).sum(1) * -0.2,
+                  (A[:, :, 0] ** 2).sum(1) + 1.0], 1)
+
+    def loss(th):
+        out, _ = cnn.forward(cnn.unpack(th, ch), X)
+        return guess.quad_loss(out.reshape(2, 2, -1), G)[0]
+
+    out, acts = cnn.forward(params, X)
+    _, dy = guess.quad_loss(out.reshape(2, 2, -1), G)
+    g = cnn.pack(cnn.backward(params, acts, dy.reshape(out.shape)))
+    h = 1e-6
+    fd = np.array([(loss(theta + h * e) - loss(theta - h * e)) / (2 * h) for e in np.eye(theta.size)])
+    assert np.abs(g - fd).max() <= 1e-6 * np.abs(fd).max(), np.abs(g - fd).max()
+
+
 def test_parameter_count():
-    assert cnn.n_params(32, 3) == 58849
+    assert cnn.n_params(32, 3, 1) == 58849
+    assert cnn.n_params() == 32 * 6 * 27 + 32 + 2 * (32 * 32 * 27 + 32) + 2 * 32 * 27 + 2

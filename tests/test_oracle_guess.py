@@ -1,15 +1,22 @@
-"""Pins of the oracle's learned-guess inputs and outputs against closed forms.
+"""Pins of the oracle's learned-guess inputs and outputs against closed forms
+and library routines.
 
-* Gauss-rule cell averages are exact cell means for pressures the space holds;
+* Gauss-rule cell averages and cell inner products are the exact cell means
+  of pressures (and products of pressures) the space holds;
 * the divergence feature of an interpolated polynomial velocity equals the
   exact cell mean of its divergence (interior cells of a periodic mesh);
-* the multilinear interpolation of cell-centre values reproduces linear data,
-  and the target of an injected correction returns it;
-* the same-stage increment of the previous step is exact for pressures that
-  are linear in time up to a constant offset per stage.
+* the shape features of hand-built increments take their closed-form values;
+* for pressures quadratic in time with a constant offset per stage, the
+  network's zero output (linear extrapolation of the increment) has zero
+  loss in every cell and reproduces the new pressure, and the blend that
+  gives the fallback has the fallback's squared error as its loss;
+* the per-cell minimiser of the quadratic loss is the weighted least-squares
+  fit of the extrapolation's error on the two increments (numpy lstsq);
+* the fallback is exact for pressures linear in time with stage offsets.
 """
 import numpy as np
 
+import synthetic
 from oracle import BoxMesh, Discretization, TRBDF2
 from oracle import guess
 
@@ -26,29 +33,34 @@ def _cell_bounds(disc, c):
     return i * h, (i + 1) * h, j * h, (j + 1) * h
 
 
-def test_cell_average_is_exact_mean():
+def test_cell_average_and_inner_product_are_exact_means():
     disc, _ = _setup()
     xp = disc.node_coords("p")
     p = xp[:, 0] ** 2 * xp[:, 1]
+    q = xp[:, 1] ** 2 + xp[:, 0]
     avg = guess.cell_average(disc, p)
+    inner = guess.cell_inner(disc, p, q)
     for c in range(disc.Nc):
         x0, x1, y0, y1 = _cell_bounds(disc, c)
-        exact = (x1 ** 3 - x0 ** 3) / (3 * (x1 - x0)) * 0.5 * (y0 + y1)
-        assert abs(avg[c] - exact) < 1e-14
+        hx, hy = x1 - x0, y1 - y0
+        assert abs(avg[c] - (x1 ** 3 - x0 ** 3) / (3 * hx) * 0.5 * (y0 + y1)) < 1e-14
+        # mean of x^2 y (y^2 + x) = mean(x^2) mean(y^3) + mean(x^3) mean(y)
+        mx = lambda e: (x1 ** (e + 1) - x0 ** (e + 1)) / ((e + 1) * hx)
+        my = lambda e: (y1 ** (e + 1) - y0 ** (e + 1)) / ((e + 1) * hy)
+        assert abs(inner[c] - (mx(2) * my(3) + mx(3) * my(1))) < 1e-14
 
 
 def test_divergence_feature_is_cell_mean_of_divergence():
     disc, ts = _setup()
     xu = disc.node_coords("u")
     u = np.stack([xu[:, 0] ** 2, xu[:, 0] * xu[:, 1]], 1)
-    import synthetic
     us = synthetic.nodal_velocity(u, 2, disc.nbu)
     p_prev = np.random.default_rng(0).standard_normal(disc.N_p)
     for s in (1, 2):
         b = ts.rhs_pressure(s, us, p_prev)
         z = np.zeros(disc.N_p)
-        x, s_inc, s_div = guess.features(ts, s, b, p_prev, z + 1.0, 0.5, z + 2.0, 0.25)
-        div = x[2] * s_div
+        x, s_inc, s_div = guess.features(ts, s, b, p_prev, z + 3.0, 0.7, z + 1.0, z + 2.0)
+        div = x[3] * s_div
         n = disc.mesh.n_cells[0]
         for c in range(disc.Nc):
             i, j = disc.mesh.cell_ijk(c)
@@ -56,44 +68,90 @@ def test_divergence_feature_is_cell_mean_of_divergence():
                 x0, x1, _, _ = _cell_bounds(disc, c)
                 assert abs(div[c] - 1.5 * (x0 + x1)) < 1e-11, (c, div[c])
         # the increment channels are the rescaled cell averages
-        assert np.allclose(x[0] * s_inc, 1.0 / (0.5 * ts.dt)) and np.allclose(x[1] * s_inc, 2.0 / (0.25 * ts.dt))
+        bdt = ts.beta[s] * ts.dt
+        assert np.allclose(x[0] * s_inc, 1.0 / bdt) and np.allclose(x[1] * s_inc, 2.0 / bdt)
+        assert np.allclose(x[2] * s_inc, 3.0 / (0.7 * ts.dt))
+        # d2 = 2 d1 in every cell: aligned, half the size
+        assert np.allclose(x[4], 1.0) and np.allclose(x[5], np.log(0.5))
 
 
-def test_interpolation_and_target_reproduce_linear_cell_data():
-    """Cell values linear in the cell index are reproduced exactly by the
-    multilinear interpolation away from the periodic seam, and the target of
-    the injected correction returns them (the cell mean of a linear function
-    is its centre value); a constant is reproduced everywhere."""
-    disc, ts = _setup(n=6)
-    rng = np.random.default_rng(1)
-    p_prev, inc2 = rng.standard_normal(disc.N_p), rng.standard_normal(disc.N_p)
-    n = disc.mesh.n_cells[0]
-    ij = np.array([disc.mesh.cell_ijk(c) for c in range(disc.Nc)])
-    y = 0.3 + 0.7 * ij[:, 0] - 0.2 * ij[:, 1]
-    inner = (ij[:, 0] > 0) & (ij[:, 0] < n - 1) & (ij[:, 1] > 0) & (ij[:, 1] < n - 1)
-    for s in (1, 2):
-        pg = guess.inject(ts, s, p_prev, inc2, y, 3.5)
-        tgt = guess.target(ts, s, pg, p_prev, inc2, 3.5)
-        assert np.allclose(tgt[inner], y[inner], atol=1e-12)
-        const = guess.inject(ts, s, p_prev, inc2, np.full(disc.Nc, 2.0), 3.5)
-        assert np.allclose(const - p_prev - inc2, ts.beta[s] * ts.dt * 3.5 * 2.0, atol=1e-13)
+def test_shape_features_closed_forms():
+    disc, _ = _setup(n=2, k=2)
+    nb = disc.nbp
+    rng = np.random.default_rng(4)
+    d1 = rng.standard_normal(disc.N_p)
+    d2 = np.empty_like(d1)
+    d2[:nb] = -3.0 * d1[:nb]                    # opposite direction, three times larger
+    # orthogonal in the weighted inner product: subtract the projection
+    v = rng.standard_normal(nb)
+    a = d1[nb:2 * nb]
+    w = guess.node_weights(disc)
+    d2[nb:2 * nb] = v - (np.sum(w * v * a) / np.sum(w * a * a)) * a
+    d2[2 * nb:3 * nb] = 1e-9 * d1[2 * nb:3 * nb]   # growth beyond the clamp
+    d2[3 * nb:] = 0.0                            # no history in this cell
+    cos, lr = guess.shape_features(disc, d1, d2)
+    assert abs(cos[0] + 1.0) < 1e-14 and abs(lr[0] - np.log(1.0 / 3.0)) < 1e-14
+    assert abs(cos[1]) < 1e-13
+    assert lr[2] == guess.LR_CLAMP and abs(cos[2] - 1.0) < 1e-14
+    assert cos[3] == 0.0 and lr[3] == 0.0
+
+
+def _history(disc, ts, rng, quadratic):
+    """Pressures P(t) + o_s at stage times, P quadratic (or linear) in time:
+    returns p_prev, d1, d2 and p_new of a stage-1 solve of step n."""
+    p0, q1, q2, o1, o2 = (rng.standard_normal(disc.N_p) for _ in range(5))
+    g, dt = ts.cst["gamma"], ts.dt
+    P = lambda t: p0 + t * q1 + (t * t * q2 if quadratic else 0.0)
+    tn = 0.4
+    p_prev = P(tn) + o2
+    d1 = (P(tn - (1 - g) * dt) + o1) - (P(tn - dt) + o2)
+    d2 = (P(tn - (2 - g) * dt) + o1) - (P(tn - 2 * dt) + o2)
+    p_new = P(tn + g * dt) + o1
+    return p_prev, d1, d2, p_new
+
+
+def test_extrapolation_blend_is_exact_for_quadratic_in_time_pressure():
+    disc, ts = _setup()
+    rng = np.random.default_rng(2)
+    p_prev, d1, d2, p_new = _history(disc, ts, rng, quadratic=True)
+    G = guess.gram_target(disc, p_new, p_prev, d1, d2)
+    y = np.zeros((2, disc.Nc))
+    loss0, _ = guess.quad_loss(y, G)
+    assert loss0 < 1e-24 * np.abs(G[0]).max()
+    assert np.allclose(guess.inject(disc, p_prev, d1, d2, y), p_new, atol=1e-12)
+    assert np.allclose(guess.inject(disc, p_prev, d1, d2, y), guess.extrapolate2(p_prev, d1, d2))
+    # y = (-1, 1) is the fallback, whose loss is its own squared error; the
+    # expanded form cancels terms of the size of g11 (order one)
+    yf = np.stack([-np.ones(disc.Nc), np.ones(disc.Nc)])
+    assert np.allclose(guess.inject(disc, p_prev, d1, d2, yf), guess.fallback(p_prev, d1))
+    e = p_new - guess.fallback(p_prev, d1)
+    S = np.mean(guess.cell_inner(disc, d1, d1))
+    lossf, _ = guess.quad_loss(yf, G)
+    assert abs(lossf - np.mean(guess.cell_inner(disc, e, e)) / S) < 1e-12 * np.abs(G[0]).max()
+
+
+def test_loss_minimiser_is_the_weighted_least_squares_fit():
+    disc, ts = _setup(n=3)
+    rng = np.random.default_rng(6)
+    p_prev, d1, d2 = (rng.standard_normal(disc.N_p) for _ in range(3))
+    p_new = p_prev + d1 + rng.standard_normal(disc.N_p)
+    G = guess.gram_target(disc, p_new, p_prev, d1, d2)
+    sw = np.sqrt(guess.node_weights(disc))
+    e = p_new - guess.extrapolate2(p_prev, d1, d2)
+    y_ls = np.empty((2, disc.Nc))
+    for c in range(disc.Nc):
+        sl = slice(c * disc.nbp, (c + 1) * disc.nbp)
+        A = np.stack([d1[sl] * sw, d2[sl] * sw], 1)
+        y_ls[:, c] = np.linalg.lstsq(A, e[sl] * sw, rcond=None)[0]
+    _, grad = guess.quad_loss(y_ls, G)
+    assert np.abs(grad).max() < 1e-12
+    loss_ls, _ = guess.quad_loss(y_ls, G)
+    for t in range(5):
+        loss_y, _ = guess.quad_loss(y_ls + 0.1 * rng.standard_normal(y_ls.shape), G)
+        assert loss_y > loss_ls
 
 
 def test_fallback_exact_for_linear_in_time_pressure_with_stage_offsets():
-    """p = P(t) + o_s with P linear in time and a constant offset per stage:
-    the same-stage increment of the previous step predicts exactly."""
     disc, ts = _setup()
-    rng = np.random.default_rng(2)
-    p0, q, o1, o2 = (rng.standard_normal(disc.N_p) for _ in range(4))
-    g, dt = ts.cst["gamma"], ts.dt
-
-    def p(t, o):
-        return p0 + t * q + o
-
-    tn = 0.3
-    # stage 1 of step n: p_prev = p^n (a stage-2 value), inc2 = p^{n-1+g} - p^{n-1}
-    inc2 = p(tn - (1 - g) * dt, o1) - p(tn - dt, o2)
-    assert np.allclose(guess.fallback(p(tn, o2), inc2), p(tn + g * dt, o1), atol=1e-13)
-    # stage 2: p_prev = p^{n+g}, inc2 = p^n - p^{n-1+g}
-    inc2 = p(tn, o2) - p(tn - (1 - g) * dt, o1)
-    assert np.allclose(guess.fallback(p(tn + g * dt, o1), inc2), p(tn + dt, o2), atol=1e-13)
+    p_prev, d1, _, p_new = _history(disc, ts, np.random.default_rng(3), quadratic=False)
+    assert np.allclose(guess.fallback(p_prev, d1), p_new, atol=1e-13)
