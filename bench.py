@@ -1,16 +1,24 @@
 """Benchmark: TR-BDF2 steps/s of the DG projection scheme on one MI355X.
 
-Default workload (one step = both TR-BDF2 stages with all four implicit
-solves): 3D periodic Taylor-Green vortex on [0, 2 pi]^3, 32^3 hexahedra,
-velocity degree 3 / pressure degree 2 (6 291 456 + 884 736 DoFs), nu = 1/1600,
-dt = 2 pi / 96 (Courant number 1), fully nonlinear momentum predictors (two
-fixed-point solves per stage: at this Courant number the linearised
-predictor with the extrapolated advecting velocity is unstable), every solve
-to a 1e-8 relative FP64 residual.  The timed solver uses the FP32 h/p-multigrid preconditioner for
-the pressure (flexible FP64 CG); the same steps with the plain FP64 solver
-(Jacobi CG) are timed beside it from the same initial state and the two
-final fields are compared ("equal error").  Synthetic data: the closed-form
-initial vortex.  Inputs are resident in HBM before timing starts.
+Default workload (one step = both TR-BDF2 stages with all their implicit
+solves): 3D periodic Taylor-Green vortex on [0, 2 pi]^3, 64^3 hexahedra,
+velocity degree 3 / pressure degree 2 (50 331 648 + 7 077 888 DoFs),
+nu = 1/1600, dt = 2 pi / 192 (Courant number 1), fully nonlinear momentum
+predictors (two fixed-point solves per stage: at this Courant number the
+linearised predictor with the extrapolated advecting velocity is unstable),
+every solve to a 1e-8 relative FP64 residual.  The timed solver is the
+mixed-precision one: FP32 h/p-multigrid preconditioner under FP64 flexible
+CG for the pressure, started from the learned guess (3D CNN trained on the
+solver's own increments, previous-increment fallback judged by the FP64
+residual), line-block-preconditioned GMRES for the momentum.  Timed beside
+it from the same initial state: the plain FP64 solver (Jacobi CG, Jacobi
+GMRES); the two final fields are compared ("equal error").  Also reported:
+the same solver with the BF16-storage smoother, the held-out evaluation of
+the pressure initial guesses, the event-timed operator kernels (in a
+separate run, so the timed steps carry no measurement hooks) and the CPU
+oracle on a bounded sample.  Synthetic data: the closed-form initial vortex;
+seeded random-phase fields for the guess network.  Inputs are resident in
+HBM before timing starts.
 
 Prints one JSON line.  `--gpus N` with N > 1 is refused: this build runs on
 one GPU.
@@ -236,9 +244,23 @@ def cpu_baseline(W, seconds_budget=20.0):
     full_dofs = dim * int(np.prod(W["n"])) * (W["k"] + 1) ** dim
     scale = disc.N_u / full_dofs
     return {"value": sample_sps * scale, "unit": "steps/s", "cores": 1, "kind": "oracle",
-            "sample": f"{steps} oracle steps (assembled CSR + sparse LU) on {'x'.join(map(str, nc))} cells of "
-                      f"the same workload ({disc.N_u} velocity DoFs) at {sample_sps:.3g} steps/s, "
-                      f"scaled by DoF ratio {scale:.3g}; setup {setup:.1f}s excluded"}
+            "cpu_model": cpu_model(), "host_cpu_count": os.cpu_count(),
+            "sample": f"{steps} oracle steps (assembled CSR + sparse LU, one thread) on "
+                      f"{'x'.join(map(str, nc))} cells of the same workload ({disc.N_u} velocity DoFs) "
+                      f"at {sample_sps:.3g} steps/s, scaled to the full workload by the velocity-DoF "
+                      f"ratio {scale:.3g} (linear per-DoF extrapolation: an upper bound of the "
+                      f"oracle's speed, since its sparse-LU cost grows faster than linearly in the "
+                      f"DoFs); setup {setup:.1f}s excluded"}
+
+
+def cpu_model():
+    try:
+        for line in open("/proc/cpuinfo"):
+            if line.startswith("model name"):
+                return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
 
 
 def run_solver(ctx, W, precond, steps, warmup, profile, mg_degree=0, guess="given", restart=30,
@@ -283,6 +305,7 @@ def run_solver(ctx, W, precond, steps, warmup, profile, mg_degree=0, guess="give
             ctx.profile_read(which)
             ctx.profile_bytes(which)
     iters, used = [], []
+    fallbacks = 0
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     U_before_last = None
@@ -297,6 +320,7 @@ def run_solver(ctx, W, precond, steps, warmup, profile, mg_degree=0, guess="give
         n += 1
         iters.append([x["iters"] for x in info])
         used += [info[1]["guess_used"], info[3]["guess_used"]]
+        fallbacks += info[1].get("precond_fallbacks", 0) + info[3].get("precond_fallbacks", 0)
         log(f"[bench] {precond}/{guess} step {i + 1}/{steps}: iterations {iters[-1]}")
     torch.cuda.synchronize()
     elapsed = time.perf_counter() - t0
@@ -304,7 +328,7 @@ def run_solver(ctx, W, precond, steps, warmup, profile, mg_degree=0, guess="give
         raise SystemExit("non-finite velocity")
     res = dict(sps=steps / elapsed, ms=1e3 * elapsed / steps, elapsed=elapsed,
                iters=[float(np.mean([it[j] for it in iters])) for j in range(4)], U=U, P=P,
-               learned_rate=sum(1 for g in used if g == 2) / max(len(used), 1))
+               learned_rate=sum(1 for g in used if g == 2) / max(len(used), 1), fallbacks=fallbacks)
     if "Re" in W:
         res["t_final"] = t
         res["steady_rate"] = (U - U_before_last).abs().max().item() / W["dt"]
@@ -342,26 +366,32 @@ def march_to_steady(ctx, W, run, tol=1e-4, max_steps=500):
                 tolerance=tol, reached=rate <= tol, wall_s=time.perf_counter() - t0)
 
 
-def random_phase_state(ctx, W, seed, amplitude=1.0):
+def random_phase_state(ctx, W, seed, peak=1.0):
     """Divergence-free random-phase field of the learned guess's training
-    data (8 Fourier modes, |kappa| <= 4, amplitudes N(0,1)/|kappa|^2, times
-    `amplitude`), zero pressure."""
+    data (8 Fourier modes, |kappa| <= 4, amplitudes N(0,1)/|kappa|^2),
+    rescaled to the largest nodal speed `peak` (that of the vortex, so the
+    Courant number matches the timed workload's), zero pressure."""
+    import numpy as np
     import torch
 
     import synthetic
     xu = ctx.node_coords(0).cpu().numpy()
     nbu = (W["k"] + 1) ** W["dim"]
-    u = amplitude * synthetic.random_phase_velocity(xu, seed)
+    u = synthetic.random_phase_velocity(xu, seed)
+    u *= peak / np.sqrt((u * u).sum(axis=1)).max()
     u = torch.tensor(synthetic.nodal_velocity(u, W["dim"], nbu), device="cuda")
     return u, u.clone(), torch.zeros(ctx.N_p, dtype=torch.float64, device="cuda")
 
 
-def train_guess(ctx, W, seeds=(0, 1, 2, 3), steps=20, discard=3, epochs=20):
-    """Generate samples with the solver, train the guess network on the GPU."""
+def train_guess(ctx, W, step_kw, seeds=tuple(range(10)), steps=30, discard=5, epochs=12):
+    """Generate samples with the solver (random-phase trajectories of the
+    training seeds, `discard` unrecorded steps then `steps` recorded ones),
+    train the guess network on the GPU by its own kernels."""
     from paper_2107_07776_amd import Net, learned_guess
     t0 = time.perf_counter()
     samples = learned_guess.generate(ctx, lambda s: random_phase_state(ctx, W, s), list(seeds), steps,
-                                     discard, precond="mg_fp32", tol=W["tol"])
+                                     discard, precond="mg_fp32", tol=W["tol"],
+                                     log=lambda m: log(f"[bench] {m}"), **step_kw)
     t1 = time.perf_counter()
     net = Net(32, seed=1)
     nx, ny, nz = (list(W["n"]) + [1, 1])[:3]
@@ -371,27 +401,48 @@ def train_guess(ctx, W, seeds=(0, 1, 2, 3), steps=20, discard=3, epochs=20):
         f"{t2 - t1:.1f}s, loss {losses[0]:.3e} -> {losses[-1]:.3e}")
     return net, {"samples": int(samples.shape[0]), "generation_s": t1 - t0, "training_s": t2 - t1,
                  "epochs": epochs, "loss_first_epoch": losses[0], "loss_last_epoch": losses[-1],
-                 "train_seeds": list(seeds)}
+                 "train_seeds": list(seeds), "train_steps_per_seed": steps, "discarded_steps": discard}
+
+
+def evaluate_guesses(ctx, W, step_kw, modes, seeds=(100, 101), steps=50, discard=5):
+    """Held-out random-phase trajectories: mean pressure iterations, steps/s
+    and (learned) the rate at which the FP64 judge took the network's guess."""
+    from paper_2107_07776_amd import learned_guess
+    t0 = time.perf_counter()
+    res = learned_guess.evaluate(ctx, lambda s: random_phase_state(ctx, W, s), list(seeds), steps,
+                                 discard, modes=modes, precond="mg_fp32", tol=W["tol"],
+                                 log=lambda m: log(f"[bench] {m}"), **step_kw)
+    log(f"[bench] held-out evaluation in {time.perf_counter() - t0:.1f}s: "
+        + ", ".join(f"{m} {r['mean_pressure_iterations']:.2f} its" for m, r in res.items()))
+    return {"seeds": list(seeds), "steps_per_seed": steps, "discarded_steps": discard, "modes": res}
 
 
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=50)
+    ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=3)
-    ap.add_argument("--workload", default="tgv32")
+    ap.add_argument("--workload", default="tgv64", choices=["tgv64", "tgv32", "kov256", "tg2d"])
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--no-profile", action="store_true")
+    ap.add_argument("--no-profile", action="store_true",
+                    help="skip the separate event-timed run of the operator kernels")
+    ap.add_argument("--profile-steps", type=int, default=4)
     ap.add_argument("--precond", default="mg_fp32", choices=["jacobi", "mg_fp32", "mg_bf16"],
                     help="pressure preconditioner of the timed solver")
     ap.add_argument("--mg-degree", type=int, default=5,
                     help="Chebyshev degree of the multigrid smoother (0: library default)")
     ap.add_argument("--no-compare", action="store_true",
                     help="skip the plain FP64 (Jacobi) reference run")
-    ap.add_argument("--guess", default="previous", choices=["given", "previous", "learned"],
-                    help="initial guess of the timed solver's pressure solves")
+    ap.add_argument("--no-bf16", action="store_true", help="skip the BF16-smoother run")
+    ap.add_argument("--guess", default=None, choices=["given", "previous", "learned", "extrap2"],
+                    help="initial guess of the timed solver's pressure solves (default: learned "
+                         "where the network is built, else previous)")
     ap.add_argument("--no-learned", action="store_true",
-                    help="skip training and timing the learned-guess variant")
+                    help="skip training and evaluating the learned guess")
+    ap.add_argument("--no-eval", action="store_true", help="skip the held-out guess evaluation")
+    ap.add_argument("--train-seeds", type=int, default=10)
+    ap.add_argument("--train-steps", type=int, default=30)
+    ap.add_argument("--epochs", type=int, default=12)
     ap.add_argument("--restart", type=int, default=None,
                     help="GMRES restart length of the timed solver (default: 4; 30 on the Kovasznay mesh)")
     ap.add_argument("--mom-precond", default=None, choices=["jacobi", "line"],
@@ -412,7 +463,6 @@ def main():
               file=sys.stderr)
         sys.exit(2)
 
-    import numpy as np
     import torch
 
     if args.copy_calibration > 0:
@@ -434,28 +484,47 @@ def main():
     if args.mom_precond is None:
         args.mom_precond = W.get("mom_precond", "line")
     ctx.set_nonlinear(W["nonlinear"], 0.0)
+    learned_ok = W.get("learned", True) and args.precond != "jacobi"
+    if args.guess is None:
+        args.guess = "learned" if learned_ok and not args.no_learned else "previous"
+    if args.guess == "learned" and not learned_ok:
+        raise SystemExit("the learned guess is built for 3D affine boxes with the multigrid solver")
+    step_kw = dict(restart=args.restart, mom_guess=args.mom_guess, mom_precond=args.mom_precond,
+                   mom_maxiter=20000)
     plain = None
     if not args.no_compare and args.precond != "jacobi":
         plain = run_solver(ctx, W, "jacobi", args.steps, args.warmup, False)
     net = None
     learned_info = None
-    if args.guess == "learned" and not W.get("learned", True):
-        raise SystemExit("the learned guess is built for 3D affine boxes only")
-    if args.guess == "learned" or (not args.no_learned and args.precond != "jacobi"
-                                   and W.get("learned", True)):
-        net, learned_info = train_guess(ctx, W)
+    if learned_ok and (args.guess == "learned" or not args.no_learned):
+        net, learned_info = train_guess(ctx, W, step_kw, seeds=tuple(range(args.train_seeds)),
+                                        steps=args.train_steps, epochs=args.epochs)
         ctx.set_guess_net(net)
-    main_run = run_solver(ctx, W, args.precond, args.steps, args.warmup, not args.no_profile,
-                          args.mg_degree, args.guess, args.restart, args.mom_guess, args.mom_precond)
+    # the timed run carries no measurement hooks
+    main_run = run_solver(ctx, W, args.precond, args.steps, args.warmup, False, args.mg_degree,
+                          args.guess, args.restart, args.mom_guess, args.mom_precond)
+    prof_run = None
+    if not args.no_profile:
+        prof_run = run_solver(ctx, W, args.precond, args.profile_steps, 1, True, args.mg_degree,
+                              args.guess, args.restart, args.mom_guess, args.mom_precond)
     solver = {"jacobi": "Jacobi-preconditioned FP64 CG",
               "mg_fp32": "FP32 h/p-multigrid V-cycle (Chebyshev smoother) under FP64 flexible CG",
               "mg_bf16": "h/p-multigrid V-cycle with BF16 storage on the finest level under FP64 "
                          "flexible CG"}[args.precond]
+    guess_desc = {
+        "given": "previous pressure",
+        "previous": "previous pressure + the same stage's increment of the previous step",
+        "learned": "learned (3D CNN, bf16 MFMA) guess, previous pressure + the same stage's last "
+                   "increment as fallback, the smaller FP64 residual decides",
+        "extrap2": "previous pressure + the same stage's increment extrapolated linearly from its "
+                   "last two values"}
     out = {"metric": METRIC, "value": main_run["sps"], "unit": "steps/s", "n_gpus": 1,
            "steps": args.steps, "warmup": args.warmup, "ms_per_step": main_run["ms"],
            "higher_is_better": True, "scaling": "strong", "vs_baseline": None, "dtype": "f64",
-           "data": "synthetic (closed-form Taylor-Green initial field; seeded random-phase fields train the guess network)",
+           "data": "synthetic (closed-form Taylor-Green initial field; seeded random-phase fields train "
+                   "and evaluate the guess network)",
            "config": {"workload": W["label"], "pressure_solver": solver,
+                      "pressure_initial_guess": guess_desc[args.guess],
                       "momentum_solver": ("line-block" if args.mom_precond == "line" else "Jacobi")
                                          + f"-preconditioned FP64 GMRES({args.restart})",
                       "momentum_initial_guess": {"given": "previous stage value",
@@ -465,19 +534,21 @@ def main():
                       "tolerance": W["tol"], "cells": list(W["n"]), "degree": W["k"],
                       "velocity_dofs": ctx.N_u, "pressure_dofs": ctx.N_p,
                       "mean_iterations_per_step": main_run["iters"]}}
-    out["config"]["pressure_initial_guess"] = {
-        "given": "previous pressure",
-        "previous": "previous pressure + the same stage's increment of the previous step",
-        "learned": "learned (3D CNN, bf16) correction of the same-stage increment, FP64 residual judge"}[args.guess]
+    if args.guess == "learned":
+        out["config"]["learned_guess_used_rate"] = main_run["learned_rate"]
     if args.precond != "jacobi":
         out["preconditioner_dtype"] = "f32" if args.precond == "mg_fp32" else "bf16 storage, f32 arithmetic"
-    if learned_info is not None and args.guess != "learned":
-        lr_run = run_solver(ctx, W, args.precond, args.steps, args.warmup, False, args.mg_degree, "learned",
-                            args.restart, args.mom_guess, args.mom_precond)
-        learned_info.update({"steps_per_s": lr_run["sps"], "ms_per_step": lr_run["ms"],
-                             "mean_iterations_per_step": lr_run["iters"],
-                             "learned_used_rate": lr_run["learned_rate"],
-                             "fallback_rate": 1.0 - lr_run["learned_rate"]})
+    if args.precond == "mg_fp32" and not args.no_bf16:
+        bf = run_solver(ctx, W, "mg_bf16", args.steps, args.warmup, False, args.mg_degree, args.guess,
+                        args.restart, args.mom_guess, args.mom_precond)
+        out["bf16_smoother"] = {"steps_per_s": bf["sps"], "ms_per_step": bf["ms"],
+                                "mean_iterations_per_step": bf["iters"],
+                                "precond_fallbacks": bf["fallbacks"],
+                                "u_rel_l2_diff_vs_fp32": (bf["U"] - main_run["U"]).norm().item()
+                                                         / main_run["U"].norm().item()}
+    if learned_info is not None and not args.no_eval:
+        modes = ("given", "previous", "extrap2", "learned")
+        learned_info["held_out"] = evaluate_guesses(ctx, W, step_kw, modes)
     if not W.get("learned", True):
         out["learned_guess"] = {"built": False,
                                 "reason": "the guess network is a 3D convolution on affine boxes; this "
@@ -493,8 +564,6 @@ def main():
         if not args.no_steady:
             out["steady_state"] = march_to_steady(ctx, W, main_run)
     if learned_info is not None:
-        if args.guess == "learned":
-            learned_info["learned_used_rate"] = main_run["learned_rate"]
         out["learned_guess"] = learned_info
     if plain is not None:
         du = (main_run["U"] - plain["U"]).norm().item() / plain["U"].norm().item()
@@ -510,17 +579,20 @@ def main():
         out["equal_error"] = {"u_rel_l2_diff_vs_plain": du, "p_rel_l2_diff_vs_plain": dp,
                               "p_mean_free_rel_l2_diff_vs_plain": dp0,
                               "after_steps": args.steps + args.warmup}
-    if "prof" in main_run:
-        (ms_p, n_p, b_p), (ms_u, n_u, b_u) = main_run["prof"]
+    if prof_run is not None:
+        (ms_p, n_p, b_p), (ms_u, n_u, b_u) = prof_run["prof"]
         kern = {
-            "pressure_apply": dict(ms=ms_p, n=n_p, bytes=b_p / max(n_p, 1), dofs=ctx.N_p),
-            "momentum_apply": dict(ms=ms_u, n=n_u, bytes=b_u / max(n_u, 1), dofs=ctx.N_u),
+            "pressure_apply": dict(ms=ms_p, n=n_p, bytes=b_p / max(n_p, 1), dofs=ctx.N_p, unit_bytes=16),
+            "momentum_apply": dict(ms=ms_u, n=n_u, bytes=b_u / max(n_u, 1), dofs=ctx.N_u, unit_bytes=24),
         }
         for name, kd in kern.items():
             avg_s = kd["ms"] * 1e-3 / max(kd["n"], 1)
             kd["avg_us"] = avg_s * 1e6
             kd["gdofs"] = kd["dofs"] / avg_s / 1e9 if avg_s > 0 else 0.0
             kd["gbs"] = kd["bytes"] / avg_s / 1e9 if avg_s > 0 else 0.0
+            # the operator's own compulsory bytes (read the operand(s), write
+            # the result) without the fused Krylov work of the launch
+            kd["apply_gbs"] = kd["unit_bytes"] * kd["dofs"] / avg_s / 1e9 if avg_s > 0 else 0.0
         dom = max(kern, key=lambda k: kern[k]["ms"])
         kd = kern[dom]
         traffic = measured_traffic(dom, args.workload)
@@ -529,10 +601,13 @@ def main():
                            "traffic": traffic["bytes_per_launch"] if traffic else None,
                            "traffic_source": traffic["source"] if traffic else None,
                            "algorithmic_bytes_per_launch": kd["bytes"], "avg_launch_us": kd["avg_us"],
+                           "apply_only_achieved": kd["apply_gbs"],
+                           "apply_only_frac": kd["apply_gbs"] / HBM_PEAK_GBS,
                            "launches_timed": kd["n"], "launch_sample_stride": LAUNCH_SAMPLE_STRIDE,
+                           "sampled_run_steps": args.profile_steps,
                            # the timed launches are every third one: their time
                            # scaled by the stride estimates the kernel's total
-                           "share_of_step_time": LAUNCH_SAMPLE_STRIDE * kd["ms"] * 1e-3 / main_run["elapsed"]}
+                           "share_of_step_time": LAUNCH_SAMPLE_STRIDE * kd["ms"] * 1e-3 / prof_run["elapsed"]}
         out["operator_gdofs"] = {k: round(v["gdofs"], 3) for k, v in kern.items()}
         out["operator_avg_us"] = {k: round(v["avg_us"], 3) for k, v in kern.items()}
     if not args.no_cpu_baseline:

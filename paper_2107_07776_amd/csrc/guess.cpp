@@ -44,7 +44,7 @@ void fill_state(tbdg_ctx* c, GuessState* g) {
     };
     for (int i = 0; i < 4; ++i) g->inc[i] = dal(c->Np);
     g->cells = dal(7 * c->Nc);
-    g->partial = dal(2 * ((c->Nc + 255) / 256));
+    g->partial = dal(2 * c->Nc + 2);   // two partials per block of at least one cell
     g->sc = dal(8);
     g->trial = dal(c->Np);
     g->feat = fal(6 * c->Nc);

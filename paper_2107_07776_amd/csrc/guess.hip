@@ -38,8 +38,16 @@ __device__ inline double node_weight(const double* W, int i) {
     return w;
 }
 
-// one thread per cell: m1, m2, m0, div, <d1,d1>, <d1,d2>, <d2,d2> into
-// cells[7][Nc]; per-block partial sums of m1^2 and div^2
+// Cells of a block: one thread per node loads it (coalesced) and forms its
+// weighted terms, one thread per cell sums them in node order.
+template <int DIM, int NP>
+struct CellBlock {
+    static constexpr int NB = ipw(NP, DIM);
+    static constexpr int CPB = 256 / NB;
+};
+
+// m1, m2, m0, div, <d1,d1>, <d1,d2>, <d2,d2> into cells[7][Nc]; per-block
+// partial sums of m1^2 and div^2
 template <int DIM, int NP>
 __global__ __launch_bounds__(256) void k_guess_cells(int Nc, Tables t, const double* __restrict__ d1,
                                                       const double* __restrict__ d2,
@@ -48,33 +56,49 @@ __global__ __launch_bounds__(256) void k_guess_cells(int Nc, Tables t, const dou
                                                       const double* __restrict__ p, double c1, double c0,
                                                       double cdiv, double inv_vol, double alpha,
                                                       double* __restrict__ cells, double* partial) {
-    constexpr int NB = ipw(NP, DIM);
-    const int c = blockIdx.x * 256 + threadIdx.x;
-    double m1 = 0.0, m2 = 0.0, m0 = 0.0, dv = 0.0, g11 = 0.0, g12 = 0.0, g22 = 0.0;
-    if (c < Nc) {
-        for (int i = 0; i < NB; ++i) {
-            const double w = node_weight<DIM, NP>(t.Wp, i);
-            const size_t gi = (size_t)c * NB + i;
+    using CB = CellBlock<DIM, NP>;
+    constexpr int NB = CB::NB, CPB = CB::CPB;
+    __shared__ double s_v[7][CPB * NB];
+    const int tid = threadIdx.x;
+    const int lc = tid / NB, nd = tid % NB;
+    const int c = blockIdx.x * CPB + lc;
+    if (lc < CPB) {
+        double v[7] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
+        if (c < Nc) {
+            const double w = node_weight<DIM, NP>(t.Wp, nd);
+            const size_t gi = (size_t)c * NB + nd;
             const double a1 = d1[gi], a2 = d2[gi];
-            m1 += w * a1;
-            m2 += w * a2;
-            m0 += w * d0[gi];
-            g11 += w * a1 * a1;
-            g12 += w * a1 * a2;
-            g22 += w * a2 * a2;
-            dv += b[gi] * inv_vol - alpha * w * p[gi];
+            v[0] = w * a1;
+            v[1] = w * a2;
+            v[2] = w * d0[gi];
+            v[3] = b[gi] * inv_vol - alpha * w * p[gi];
+            v[4] = w * a1 * a1;
+            v[5] = w * a1 * a2;
+            v[6] = w * a2 * a2;
         }
-        m1 *= c1;
-        m2 *= c1;
-        m0 *= c0;
-        dv *= cdiv;
-        cells[c] = m1;
-        cells[Nc + c] = m2;
-        cells[2 * Nc + c] = m0;
-        cells[3 * Nc + c] = dv;
-        cells[4 * Nc + c] = g11;
-        cells[5 * Nc + c] = g12;
-        cells[6 * Nc + c] = g22;
+#pragma unroll
+        for (int q = 0; q < 7; ++q) s_v[q][tid] = v[q];
+    }
+    __syncthreads();
+    double m1 = 0.0, dv = 0.0;
+    const int cc = blockIdx.x * CPB + tid;
+    if (tid < CPB && cc < Nc) {
+        double sum[7];
+#pragma unroll
+        for (int q = 0; q < 7; ++q) {
+            double a = 0.0;
+            for (int i = 0; i < NB; ++i) a += s_v[q][tid * NB + i];
+            sum[q] = a;
+        }
+        m1 = sum[0] * c1;
+        dv = sum[3] * cdiv;
+        cells[cc] = m1;
+        cells[Nc + cc] = sum[1] * c1;
+        cells[2 * Nc + cc] = sum[2] * c0;
+        cells[3 * Nc + cc] = dv;
+        cells[4 * Nc + cc] = sum[4];
+        cells[5 * Nc + cc] = sum[5];
+        cells[6 * Nc + cc] = sum[6];
     }
     const double s0 = red::block_sum(m1 * m1);
     const double s2 = red::block_sum(dv * dv);
@@ -147,28 +171,40 @@ __global__ __launch_bounds__(256) void k_guess_gram(int Nc, Tables t, const doub
                                                      const double* __restrict__ d1,
                                                      const double* __restrict__ d2,
                                                      double* __restrict__ rows, double* partial) {
-    constexpr int NB = ipw(NP, DIM);
-    const int c = blockIdx.x * 256 + threadIdx.x;
-    double g11 = 0.0, g12 = 0.0, g22 = 0.0, r1 = 0.0, r2 = 0.0, ee = 0.0;
-    if (c < Nc) {
-        for (int i = 0; i < NB; ++i) {
-            const double w = node_weight<DIM, NP>(t.Wp, i);
-            const size_t gi = (size_t)c * NB + i;
+    using CB = CellBlock<DIM, NP>;
+    constexpr int NB = CB::NB, CPB = CB::CPB;
+    __shared__ double s_v[6][CPB * NB];
+    const int tid = threadIdx.x;
+    const int lc = tid / NB, nd = tid % NB;
+    const int c = blockIdx.x * CPB + lc;
+    if (lc < CPB) {
+        double v[6] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
+        if (c < Nc) {
+            const double w = node_weight<DIM, NP>(t.Wp, nd);
+            const size_t gi = (size_t)c * NB + nd;
             const double a1 = d1[gi], a2 = d2[gi];
             const double e = pn[gi] - (p[gi] + 2.0 * a1 - a2);
-            g11 += w * a1 * a1;
-            g12 += w * a1 * a2;
-            g22 += w * a2 * a2;
-            r1 += w * e * a1;
-            r2 += w * e * a2;
-            ee += w * e * e;
+            v[0] = w * a1 * a1;
+            v[1] = w * a1 * a2;
+            v[2] = w * a2 * a2;
+            v[3] = w * e * a1;
+            v[4] = w * e * a2;
+            v[5] = w * e * e;
         }
-        rows[c] = g11;
-        rows[Nc + c] = g12;
-        rows[2 * Nc + c] = g22;
-        rows[3 * Nc + c] = r1;
-        rows[4 * Nc + c] = r2;
-        rows[5 * Nc + c] = ee;
+#pragma unroll
+        for (int q = 0; q < 6; ++q) s_v[q][tid] = v[q];
+    }
+    __syncthreads();
+    double g11 = 0.0;
+    const int cc = blockIdx.x * CPB + tid;
+    if (tid < CPB && cc < Nc) {
+#pragma unroll
+        for (int q = 0; q < 6; ++q) {
+            double a = 0.0;
+            for (int i = 0; i < NB; ++i) a += s_v[q][tid * NB + i];
+            rows[(size_t)q * Nc + cc] = a;
+            if (q == 0) g11 = a;
+        }
     }
     const double s = red::block_sum(g11);
     if (threadIdx.x == 0) partial[blockIdx.x] = s;
@@ -215,8 +251,9 @@ int launch_guess_cells(const tbdg_ctx* c, const double* d1, const double* d2, co
                        double alpha, double* cells, double* partial) {
     if (c->mapped)
         throw Error(TBDG_EUNSUPPORTED, "the learned guess is built for affine cells only");
-    const unsigned G = nb256(c->Nc);
+    unsigned G = 0;
 #define L_(D, NP)                                                                          \
+    G = (unsigned)((c->Nc + CellBlock<D, NP>::CPB - 1) / CellBlock<D, NP>::CPB);           \
     hipLaunchKernelGGL((k_guess_cells<D, NP>), dim3(G), dim3(256), 0, c->stream, (int)c->Nc,  \
                        c->tab, d1, d2, d0, b, p, c1, c0, cdiv, 1.0 / c->geom.vol, alpha,   \
                        cells, partial);
@@ -251,14 +288,15 @@ void launch_guess_target(const tbdg_ctx* c, const double* pn, const double* p, c
                          const double* d2, double* rows, double* partial, float* out) {
     if (c->mapped)
         throw Error(TBDG_EUNSUPPORTED, "the learned guess is built for affine cells only");
-    const unsigned G = nb256(c->Nc);
+    unsigned G = 0;
 #define L_(D, NP)                                                                          \
+    G = (unsigned)((c->Nc + CellBlock<D, NP>::CPB - 1) / CellBlock<D, NP>::CPB);           \
     hipLaunchKernelGGL((k_guess_gram<D, NP>), dim3(G), dim3(256), 0, c->stream, (int)c->Nc,   \
                        c->tab, pn, p, d1, d2, rows, partial);
     TBDG_GUESS_DISPATCH(c->dim, c->np, L_);
 #undef L_
-    hipLaunchKernelGGL(k_guess_gram_scale, dim3(G), dim3(256), 0, c->stream, (int)c->Nc, rows,
-                       partial, (int)G, out);
+    hipLaunchKernelGGL(k_guess_gram_scale, dim3(nb256(c->Nc)), dim3(256), 0, c->stream, (int)c->Nc,
+                       rows, partial, (int)G, out);
     TBDG_HIP(hipGetLastError());
 }
 

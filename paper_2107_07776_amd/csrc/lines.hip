@@ -600,8 +600,10 @@ __global__ __launch_bounds__(256) void k_mom_lineblk(Geom g, LineGeom lg, Line1D
 
 // Apply: z = P^{-1} (s v), s = *scale (1 when scale is null), per velocity
 // component; the own cells staged in LDS, one pass per direction, one work
-// item per (cell, line, component) with the component fastest (the threads
-// of one line read the same block), scaled by D between the passes.
+// item per (cell, component, line) with the line fastest (consecutive lanes
+// read consecutive blocks, and their LDS accesses fall on distinct banks:
+// with the component fastest, the three components of a node share a bank),
+// scaled by D between the passes.
 template <int DIM, int N>
 __global__ __launch_bounds__(256) void k_mom_lineprec(const float* __restrict__ blk,
                                                        const double* __restrict__ d,
@@ -632,7 +634,7 @@ __global__ __launch_bounds__(256) void k_mom_lineprec(const float* __restrict__ 
         constexpr int ITEMS = CPB * DIM * NF;
         for (int it = tid; it < ITEMS; it += 256) {
             const int lc2 = it / (DIM * NF);
-            const int ln = (it % (DIM * NF)) / DIM, c = it % DIM;
+            const int c = (it % (DIM * NF)) / NF, ln = it % NF;
             const int cell2 = blockIdx.x * CPB + lc2;
             if (cell2 >= Nc) continue;
             const float* Bi = blk + ((size_t)((int64_t)a * Nc + cell2) * NF + ln) * (N * N);
