@@ -53,7 +53,7 @@ typedef enum {
     TBDG_ENOTCONV = -4,      /* Krylov solver reached maxiter above tolerance   */
     TBDG_EBREAKDOWN = -5,    /* Krylov breakdown (zero or negative curvature)   */
     TBDG_ENAN = -6,          /* a non-finite residual was detected              */
-    TBDG_EUNSUPPORTED = -7   /* valid request outside what this build supports  */
+    TBDG_EUNSUPPORTED = -7   /* valid request outside what the library supports  */
 } tbdg_status;
 
 typedef struct tbdg_ctx tbdg_ctx;
@@ -177,9 +177,10 @@ TBDG_API tbdg_status tbdg_rhs_pressure(tbdg_ctx* ctx, int stage, const double* u
 
 /* Krylov options.  tol: relative true residual ||b - A x||_2 <= tol ||b||_2.
  * maxiter: total iterations (GMRES: over all restarts).  restart: GMRES
- * basis size m (<= 60).  precond: TBDG_PRECOND_*; the multigrid values apply
- * to the pressure solves only, TBDG_PRECOND_LINE to the momentum solves
- * only.  guess: 0 = use the content of x_inout.                            */
+ * basis size m (<= 60).  precond: TBDG_PRECOND_*; TBDG_PRECOND_LINE applies
+ * to the momentum solves only, TBDG_PRECOND_MG_BF16 to the pressure solves
+ * only, TBDG_PRECOND_MG_FP32 to both (momentum: see
+ * tbdg_mg_apply_momentum).  guess: 0 = use the content of x_inout.        */
 enum {
     TBDG_GUESS_GIVEN = 0,       /* the content of x_inout (in tbdg_step: the previous pressure) */
     TBDG_GUESS_PREVIOUS = 1,    /* tbdg_step only: previous pressure + same stage's last increment */
@@ -188,7 +189,9 @@ enum {
 };
 enum {
     TBDG_PRECOND_JACOBI = 0,
-    TBDG_PRECOND_MG_FP32 = 1,   /* h/p-multigrid V-cycle in FP32 under FP64 flexible CG */
+    TBDG_PRECOND_MG_FP32 = 1,   /* h/p-multigrid V-cycle in FP32 under FP64 flexible CG;
+                                   momentum: one velocity-component V-cycle per component
+                                   under FP64 GMRES (right preconditioning)             */
     TBDG_PRECOND_MG_BF16 = 2,   /* the same with BF16 storage on the finest level; if
                                    that cycle breaks flexible CG down (z.r <= 0) or the
                                    residual norm fails to halve over 10 steps, the
@@ -293,6 +296,36 @@ TBDG_API tbdg_status tbdg_mg_levels(tbdg_ctx* ctx, int cap, int* n_levels, int64
  * 2: BF16 storage on level 0).  r, z: device, N_p, FP64; may not alias.     */
 TBDG_API tbdg_status tbdg_mg_apply(tbdg_ctx* ctx, int stage, int precision, const double* r,
                                    double* z);
+
+/* Multigrid preconditioner of the momentum solves (not in the paper, which
+ * uses Jacobi; for TBDG_PRECOND_MG_FP32 in the momentum options).  The
+ * stage-s momentum operator of Sec. 3 on one velocity component is
+ * m_s M + theta_s (nu A + C(w)), with A the SIP form of eq. bilin_diff
+ * (Dirichlet walls: boundary terms with the doubled penalty).  Its
+ * symmetric part without advection is theta_s nu H with H = alpha_s M + A,
+ * alpha_s = m_s / (theta_s nu): a Helmholtz operator of the same kind as the
+ * pressure's, built into a second hierarchy by the rules of tbdg_mg_setup
+ * (same parameters; level 0 the velocity space Q_k with the velocity
+ * penalty, Dirichlet instead of natural conditions at walls; on Q1-mapped
+ * cells the levels of the undistorted box).  z = P^{-1} v applies one FP32
+ * V-cycle of H to each component of v / (theta_s nu).  The hierarchy is
+ * built on first use (TBDG_EINVAL if nu = 0) and dropped by tbdg_mg_setup
+ * and tbdg_set_scheme.  v, z: device, N_u, velocity layout, FP64; may not
+ * alias.                                                                    */
+TBDG_API tbdg_status tbdg_mg_apply_momentum(tbdg_ctx* ctx, int stage, const double* v, double* z);
+
+/* The momentum hierarchy's description, as tbdg_mg_levels (builds it if
+ * needed).                                                                  */
+TBDG_API tbdg_status tbdg_mg_levels_momentum(tbdg_ctx* ctx, int cap, int* n_levels, int64_t* desc,
+                                             double* lambda);
+
+/* enable = 1 (the default): every V-cycle of the pressure flexible CG, of
+ * the momentum GMRES and of tbdg_mg_apply_momentum runs as one replay of a
+ * HIP graph captured from its kernel launches on first use (per hierarchy,
+ * stage, precision and output buffer); 0: the same kernels launched one by
+ * one.  The results are the same bit for bit.  Captures are dropped with
+ * their hierarchy; tbdg_mg_apply always launches kernel by kernel.         */
+TBDG_API tbdg_status tbdg_set_mg_graphs(tbdg_ctx* ctx, int enable);
 
 /* Learned initial guess of the pressure solves: a small 3D convolutional
  * network on the cell grid (not part of the paper).  Layers 6 -> 32 -> 32 ->

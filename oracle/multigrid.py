@@ -1,5 +1,6 @@
-"""h/p-multigrid preconditioner for the pressure Helmholtz operator
-(oracle; TEST INFRASTRUCTURE ONLY).
+"""h/p-multigrid preconditioners for the pressure Helmholtz operator and for
+one velocity component of the momentum operator (oracle; TEST
+INFRASTRUCTURE ONLY).
 
 The paper solves the pressure systems of Sec. 3 with a multigrid-preconditioned
 CG (Sec. 4) and gives no details of the multigrid; this module fixes one
@@ -11,6 +12,14 @@ concrete method and computes it in plain FP64 with assembled matrices:
   number of cells and the level has more than ``coarse_cells`` cells.  Every
   level operator is rediscretised: H_l = alpha M^p_l + K_l with the SIP
   penalty of its own degree q and cell size, sigma = (q+1)^2 / h.
+* Velocity field (``field="u"``; not in the paper, which preconditions the
+  momentum solves with Jacobi).  The stage-s momentum operator on one
+  component is m_s M + theta_s (nu A + C(w)) with A the SIP form of eq.
+  bilin_diff (Dirichlet walls).  Its symmetric part without advection is
+  theta_s nu (alpha M + A) with alpha = m_s / (theta_s nu), and the same
+  construction applies to H = alpha M + A: level 0 the velocity space Q_k,
+  the velocity penalty (q+1)^2 pen_u / h on every level and the Dirichlet
+  boundary terms of A (doubled penalty) instead of the natural condition.
 * Transfers.  Prolongation is the embedding of the coarse space in the fine
   one, i.e. the coarse polynomial evaluated at the fine nodes: for p-transfer
   the Q_1 basis at the Q_q nodes of the same cell, for h-transfer the parent
@@ -148,13 +157,19 @@ def _kron_cell(tabs):
 
 
 class Level:
-    """One level: mesh, degree q, assembled H_l = alpha M^p + K and its diagonal."""
+    """One level: mesh, degree q, assembled H_l = alpha M + K and its diagonal
+    (field "p": the pressure space's M^p and K; "u": one velocity component's
+    mass and SIP form with Dirichlet walls)."""
 
-    def __init__(self, mesh, q, alpha, pen_p):
+    def __init__(self, mesh, q, alpha, pen, field="p"):
         self.mesh = mesh
         self.q = int(q)
-        self.disc = Discretization(mesh, q + 1, nu=1.0, pen_p=pen_p)
-        self.H = (alpha * self.disc.mass_p() + self.disc.sip_p()).tocsr()
+        if field == "p":
+            self.disc = Discretization(mesh, q + 1, nu=1.0, pen_p=pen)
+            self.H = (alpha * self.disc.mass_p() + self.disc.sip_p()).tocsr()
+        else:
+            self.disc = Discretization(mesh, q, nu=1.0, pen_u=pen)
+            self.H = (alpha * self.disc.mass_u() + self.disc.sip_u()).tocsr()
         self.d = self.H.diagonal().copy()
         self.N = self.H.shape[0]
         self.nb = (q + 1) ** mesh.dim
@@ -191,14 +206,15 @@ def _prolongation(fine, coarse):
 
 
 class Multigrid:
-    """h/p-multigrid V-cycle for H = alpha M^p + K on an affine box (periodic
-    directions wrap, the others carry the natural Neumann condition).
+    """h/p-multigrid V-cycle for H = alpha M + K on an affine box (periodic
+    directions wrap; the others carry the natural Neumann condition for the
+    pressure, homogeneous Dirichlet for a velocity component).
 
     ``disc`` gives the mesh and the velocity degree k (pressure degree k-1);
-    ``alpha`` the mass coefficient of the stage."""
+    ``alpha`` the mass coefficient of the stage; ``field`` "p" or "u"."""
 
     def __init__(self, disc, alpha, degree=3, lanczos_steps=15, range_=15.0, safety=1.1,
-                 coarse_cells=None, seed=0):
+                 coarse_cells=None, seed=0, field="p"):
         mesh = disc.mesh
         if not mesh.affine:
             raise ValueError("the multigrid hierarchy is defined on affine boxes")
@@ -206,14 +222,17 @@ class Multigrid:
             coarse_cells = 64 if mesh.dim == 3 else 16
         self.degree = int(degree)
         self.alpha = float(alpha)
-        levels = [Level(mesh, disc.k - 1, alpha, disc.pen_p)]
-        if disc.k - 1 > 1:
-            levels.append(Level(mesh, 1, alpha, disc.pen_p))
+        if field not in ("p", "u"):
+            raise ValueError("field must be 'p' or 'u'")
+        q0, pen = (disc.k - 1, disc.pen_p) if field == "p" else (disc.k, disc.pen_u)
+        levels = [Level(mesh, q0, alpha, pen, field)]
+        if q0 > 1:
+            levels.append(Level(mesh, 1, alpha, pen, field))
         while True:
             m = levels[-1].mesh
             if m.N <= coarse_cells or any(v % 2 for v in m.n_cells):
                 break
-            levels.append(Level(_coarse_mesh(m), 1, alpha, disc.pen_p))
+            levels.append(Level(_coarse_mesh(m), 1, alpha, pen, field))
         self.levels = levels
         self.P = [_prolongation(levels[i], levels[i + 1]) for i in range(len(levels) - 1)]
         self.lam = []

@@ -99,11 +99,30 @@ void free_all(tbdg_ctx* c) {
     dfree(c->s_pv);
     dfree(c->s_wlag);
     trbdg::mg_free(c);
+    if (c->cap_stream) (void)hipStreamDestroy(c->cap_stream);
+    c->cap_stream = nullptr;
     trbdg::guess_free(c);
     dfree(c->bnd_uD[0]);
     dfree(c->bnd_uD[1]);
     dfree(c->map_vtx);
     dfree(c->map_gr);
+}
+
+void levels_of(const trbdg::MGData& M, int cap, int* n_levels, int64_t* desc, double* lambda) {
+    const int nl = (int)M.lv.size();
+    *n_levels = nl;
+    for (int l = 0; l < nl && l < cap; ++l) {
+        const trbdg::MGLevel& L = M.lv[l];
+        if (desc) {
+            desc[5 * l] = L.np;
+            for (int a = 0; a < 3; ++a) desc[5 * l + 1 + a] = L.geom.nc[a];
+            desc[5 * l + 4] = L.N;
+        }
+        if (lambda) {
+            lambda[l] = L.lam[1];
+            lambda[cap + l] = L.lam[2];
+        }
+    }
 }
 
 tbdg_solver_opts defaults(const tbdg_solver_opts* o) {
@@ -517,8 +536,8 @@ tbdg_status tbdg_solve_momentum(tbdg_ctx* c, int stage, const double* w, const d
         check_stage(stage);
         require(w && rhs && u_inout, "null pointer");
         const tbdg_solver_opts o = defaults(opts);
-        if (o.precond != TBDG_PRECOND_JACOBI && o.precond != TBDG_PRECOND_LINE)
-            throw Error(TBDG_EUNSUPPORTED, "the momentum solve takes the Jacobi or the line preconditioner");
+        if (o.precond == TBDG_PRECOND_MG_BF16)
+            throw Error(TBDG_EUNSUPPORTED, "the momentum solve takes the Jacobi, line or FP32 multigrid preconditioner");
         const tbdg_status s = trbdg::solve_momentum(c, stage, w, rhs, u_inout, o, info);
         if (s != TBDG_OK) c->last_error = "momentum GMRES did not converge";
         return s;
@@ -535,6 +554,37 @@ tbdg_status tbdg_precond_momentum(tbdg_ctx* c, int stage, const double* w, const
         trbdg::launch_diag_momentum(c, stage, w, c->diag_u);
         const double* d = trbdg::build_mom_lineprec(c, stage, w);
         trbdg::launch_mom_lineprec(c, c->mom_blk, d, v, nullptr, z);
+        return TBDG_OK;
+    });
+}
+
+tbdg_status tbdg_mg_apply_momentum(tbdg_ctx* c, int stage, const double* v, double* z) {
+    if (!c) return TBDG_EINVAL;
+    return guarded(c, [&]() {
+        check_stage(stage);
+        require(v && z, "null pointer");
+        require(v != z, "v and z must not alias");
+        trbdg::mg_apply_velocity(c, stage, v, nullptr, z);
+        return TBDG_OK;
+    });
+}
+
+tbdg_status tbdg_set_mg_graphs(tbdg_ctx* c, int enable) {
+    if (!c) return TBDG_EINVAL;
+    return guarded(c, [&]() {
+        require(enable == 0 || enable == 1, "enable must be 0 or 1");
+        c->mg_graphs = enable != 0;
+        return TBDG_OK;
+    });
+}
+
+tbdg_status tbdg_mg_levels_momentum(tbdg_ctx* c, int cap, int* n_levels, int64_t* desc,
+                                    double* lambda) {
+    if (!c) return TBDG_EINVAL;
+    return guarded(c, [&]() {
+        require(n_levels != nullptr && cap >= 0, "null n_levels or negative cap");
+        trbdg::mgu_ensure(c);
+        levels_of(*c->mgu, cap, n_levels, desc, lambda);
         return TBDG_OK;
     });
 }
@@ -620,8 +670,8 @@ tbdg_status tbdg_step(tbdg_ctx* c, tbdg_state* state, const tbdg_solver_opts* mo
         require(state && state->u && state->u_hist && state->p, "null state");
         const tbdg_solver_opts mo = defaults(mom);
         const tbdg_solver_opts po = defaults(prs);
-        if (mo.precond != TBDG_PRECOND_JACOBI && mo.precond != TBDG_PRECOND_LINE)
-            throw Error(TBDG_EUNSUPPORTED, "the momentum solve takes the Jacobi or the line preconditioner");
+        if (mo.precond == TBDG_PRECOND_MG_BF16)
+            throw Error(TBDG_EUNSUPPORTED, "the momentum solve takes the Jacobi, line or FP32 multigrid preconditioner");
         if (po.precond == TBDG_PRECOND_LINE)
             throw Error(TBDG_EUNSUPPORTED, "the line preconditioner applies to the momentum solve");
         require(mo.guess != TBDG_GUESS_LEARNED && mo.guess != TBDG_GUESS_EXTRAP2,
@@ -675,12 +725,9 @@ tbdg_status tbdg_set_scheme(tbdg_ctx* c, int scheme) {
         trbdg::guess_reset(c);
         trbdg::launch_diag_pressure(c, c->alpha(1), c->diag_p[1]);
         trbdg::vec_recip(c->stream, c->Np, c->diag_p[1], c->invd_p[1]);
-        if (c->mg) {
-            // the level operators and eigenvalue estimates depend on alpha_1
-            const trbdg::MGData& M = *c->mg;
-            tbdg_mg_desc d{M.degree, M.lanczos_steps, M.range, M.safety, M.coarse_cells, M.max_coarse};
-            trbdg::mg_setup(c, &d);
-        }
+        // the level operators and eigenvalue estimates depend on (beta_1, theta_1)
+        trbdg::mgu_free(c);
+        if (c->mg) trbdg::mg_setup(c, &c->mg_desc);
         TBDG_HIP(hipStreamSynchronize(c->stream));
         return TBDG_OK;
     });
@@ -699,20 +746,7 @@ tbdg_status tbdg_mg_levels(tbdg_ctx* c, int cap, int* n_levels, int64_t* desc, d
     return guarded(c, [&]() {
         require(n_levels != nullptr && cap >= 0, "null n_levels or negative cap");
         if (!c->mg) throw Error(TBDG_EINVAL, "multigrid hierarchy not built (tbdg_mg_setup)");
-        const int nl = (int)c->mg->lv.size();
-        *n_levels = nl;
-        for (int l = 0; l < nl && l < cap; ++l) {
-            const trbdg::MGLevel& L = c->mg->lv[l];
-            if (desc) {
-                desc[5 * l] = L.np;
-                for (int a = 0; a < 3; ++a) desc[5 * l + 1 + a] = L.geom.nc[a];
-                desc[5 * l + 4] = L.N;
-            }
-            if (lambda) {
-                lambda[l] = L.lam[1];
-                lambda[cap + l] = L.lam[2];
-            }
-        }
+        levels_of(*c->mg, cap, n_levels, desc, lambda);
         return TBDG_OK;
     });
 }

@@ -49,10 +49,16 @@ struct Line1D {
 
 // Per-direction scale factors of the line operators on the affine box:
 // sdiff[a] = |K| / h_a^2 (SIP), sadv[a] = |K| / h_a (advection).
+// wall: the SIP form of a scalar field at a non-periodic end (no neighbour)
+// takes the traces of the own cell's mirror image, even for the natural
+// condition (-1: the pressure's homogeneous Neumann, no face terms) or odd
+// for a homogeneous Dirichlet condition (+1: the velocity's boundary terms
+// with the doubled penalty); read by the pressure-type line kernels only.
 struct LineGeom {
     int periodic[3];
     double sdiff[3], sadv[3];
     double inv_nc[3];   // 1 / cells per direction (fast index division)
+    double wall;
 };
 
 struct Error : std::runtime_error {
@@ -130,7 +136,7 @@ __host__ __device__ inline int64_t bnd_point(const Bnd& b, const Geom& g, int64_
     return b.off[a][side] + tc * nf + tt;
 }
 
-// ---- multigrid hierarchy of the pressure operator ------------------------------
+// ---- multigrid hierarchies (pressure; one velocity component) --------------------
 constexpr int MG_MAXDEG = 16;     // largest Chebyshev degree
 // smoother step kinds of the fused level kernel
 enum { MG_PRE1 = 0, MG_STEP = 1, MG_LAST = 2, MG_RES = 3, MG_ZFIN = 4 };
@@ -139,11 +145,13 @@ constexpr int MG_MAXLEVELS = 16;
 // FP32 1D tables of one level (row i = test function, column j = trial):
 // A = SIP element matrix with both end-face self terms, L0/L1/dL0/dL1 = basis
 // values/derivatives at the cell ends, W = Gauss weights; Cr = reference
-// penalty; cm[s] = alpha_s |K| per stage; sdiff[a] = |K| / h_a^2.
+// penalty; cm[s] = alpha_s |K| per stage; sdiff[a] = |K| / h_a^2; wall =
+// LineGeom::wall.
 struct LevelTabF {
     float A[NMAX * NMAX];
     float L0[NMAX], L1[NMAX], dL0[NMAX], dL1[NMAX], W[NMAX];
     float Cr;
+    float wall;
     float cm[3];
     float sdiff[3];
 };
@@ -173,15 +181,37 @@ struct MGLevel {
     double c1[3][MG_MAXDEG] = {}, c2[3][MG_MAXDEG] = {};
 };
 
+// The operator of every level is H_l = alpha_s M_l + K_l (K the SIP form of
+// the level's degree with penalty factor pen, walls as in LineGeom::wall).
+// Pressure: level 0 is the pressure space, alpha_s of the Helmholtz
+// equation, natural walls.  Velocity (field 1): level 0 is the space of one
+// velocity component, alpha_s = m_s / (theta_s nu) and Dirichlet walls, so
+// that theta_s nu H_0 is the symmetric part (mass and diffusion) of the
+// stage-s momentum operator on each component.
+// A V-cycle captured from the library's launches and replayed as one HIP
+// graph; valid for the hierarchy it was captured from and the key below.
+struct VGraph {
+    int s = 0, prec = 0;
+    const void *z = nullptr, *r64 = nullptr, *q64 = nullptr;
+    hipGraphExec_t exec = nullptr;
+};
+
 struct MGData {
+    int field = 0;              // 0 pressure, 1 velocity component
+    int np0 = 0;                // nodes per direction of level 0
+    int64_t n0 = 0;             // level-0 DoFs
+    double pen = 1.0, wall = -1.0;
+    double alpha[3] = {0.0, 0.0, 0.0};
     int degree = 4, lanczos_steps = 15, coarse_cells = 0, max_coarse = 2048;
     double range = 15.0, safety = 1.1;
     std::vector<MGLevel> lv;
     double* ainv[3] = {nullptr, nullptr, nullptr};   // coarse inverses per stage (device, row-major)
-    double* z = nullptr;        // FP64 preconditioned residual (N_p)
+    double* z = nullptr;        // FP64 preconditioned residual (pressure: n0; velocity:
+                                // every component, velocity layout)
     double* zpart = nullptr;    // partial sums z.r, z.q of the finest smoother step
     double* rpart = nullptr;    // partial sums r.r of the FP64 update
     std::vector<void*> allocs;
+    std::vector<VGraph> graphs;
 };
 
 // Learned / extrapolated initial guesses of the Helmholtz solves in a step.
@@ -308,6 +338,10 @@ struct tbdg_ctx {
     double* map_vtx = nullptr;
     double* map_gr = nullptr;
     trbdg::MGData* mg = nullptr;    // multigrid hierarchy (built on first use)
+    trbdg::MGData* mgu = nullptr;   // velocity-component hierarchy (momentum solves, lazy)
+    bool mg_graphs = true;          // replay the solvers' V-cycles as captured HIP graphs
+    hipStream_t cap_stream = nullptr;  // private stream the captures are recorded on (lazy)
+    tbdg_mg_desc mg_desc{};         // parameters of the last tbdg_mg_setup (zeros: defaults)
     trbdg::GuessState* gs = nullptr;   // initial-guess history and network
 
     double alpha(int s) const;
@@ -476,10 +510,12 @@ int launch_fcg_apply(const tbdg_ctx* c, double alpha, const double* z, const dou
                      double* p_new, double* q, double* sc);
 
 // ---- multigrid kernels (mg.hip) ---------------------------------------------------
+// MG_ZFIN: z, r64, q64 hold zs values per cell (the level's NB consecutive
+// ones are used); r64 and q64 may be null (no partial sums), partial too.
 template <typename S>
 int launch_level_step(hipStream_t st, int dim, const MGLevel& L, int stage, int mode, float c1,
                       float c2, const S* dop, S* x, S* r, const S* b, S* dout, double* z,
-                      const double* r64, const double* q64, double* partial);
+                      const double* r64, const double* q64, double* partial, int zs = 0);
 int level_blocks(int dim, const MGLevel& L);
 template <typename S>
 void launch_restrict(hipStream_t st, int dim, const MGLevel& F, const MGLevel& C, int stage,
@@ -494,6 +530,11 @@ int launch_mg_prep(hipStream_t st, int64_t n, int update, const double* pa, int 
                    const float* invd, float c2, double* partial);
 void launch_mg_beta(hipStream_t st, const double* partial, int G, double* sc, int first, int slot,
                     int slot_prev);
+// b0 = s v_comp (s = scale, times *sc_dev when given), d0 = c2 D^{-1} b0: the
+// level-0 data of one velocity component ([cell][component][node] layout)
+void launch_vel_prep(hipStream_t st, int64_t Nc, int nb, int dim, int comp, const double* v,
+                     const double* sc_dev, double scale, float* b0, float* d0, const float* invd,
+                     float c2);
 void vec_mul(hipStream_t st, int64_t n, const double* a, const double* b, double* out);
 void vec_unit(hipStream_t st, int64_t n, int64_t j, double* out);
 void vec_inv_sqrt(hipStream_t st, int64_t n, const double* d, double* out, float* invf);
@@ -560,6 +601,12 @@ void mg_setup(tbdg_ctx* c, const tbdg_mg_desc* desc);
 void mg_free(tbdg_ctx* c);
 // z = B r, one V-cycle (precision 1: FP32, 2: BF16 storage on the finest level)
 void mg_apply(tbdg_ctx* c, int stage, int precision, const double* r, double* z);
+// velocity hierarchy, built on first use with the parameters of the last
+// tbdg_mg_setup; z = P^{-1} (s v) with P = theta_s nu H_0 on every component
+// (one FP32 V-cycle each), s = *sc_dev when given, else 1
+void mgu_ensure(tbdg_ctx* c);
+void mgu_free(tbdg_ctx* c);
+void mg_apply_velocity(tbdg_ctx* c, int stage, const double* v, const double* sc_dev, double* z);
 tbdg_status solve_pressure_mg(tbdg_ctx* c, int s, const double* b, double* x,
                               const tbdg_solver_opts& o, tbdg_solve_info* info);
 

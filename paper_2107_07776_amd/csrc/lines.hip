@@ -72,8 +72,8 @@ __global__ __launch_bounds__(256) void k_pressure_line(Geom g, LineGeom lg, Line
         if (!active) {
         } else if (DIAG) {
             s = A[ia * NP + ia];
-            if (lf < 0) s -= F0[ia * NP + ia];
-            if (rt < 0) s -= F1[ia * NP + ia];
+            if (lf < 0) s += lg.wall * F0[ia * NP + ia];
+            if (rt < 0) s += lg.wall * F1[ia * NP + ia];
             if (lf == cell) s += Lm[ia * NP + ia];
             if (rt == cell) s += Rm[ia * NP + ia];
         } else {
@@ -81,8 +81,8 @@ __global__ __launch_bounds__(256) void k_pressure_line(Geom g, LineGeom lg, Line
             for (int j = 0; j < NP; ++j) {
                 const int idx = L::node(a, j, tt);
                 double c = A[ia * NP + j];
-                if (lf < 0) c -= F0[ia * NP + j];
-                if (rt < 0) c -= F1[ia * NP + j];
+                if (lf < 0) c += lg.wall * F0[ia * NP + j];
+                if (rt < 0) c += lg.wall * F1[ia * NP + j];
                 s += c * p[cell * NB + idx];
                 if (lf >= 0) s += Lm[ia * NP + j] * p[lf * NB + idx];
                 if (rt >= 0) s += Rm[ia * NP + j] * p[rt * NB + idx];
@@ -1098,11 +1098,12 @@ __global__ __launch_bounds__(256) void k_pressure_face(Geom g, LineGeom lg, Line
             X0 = 0.5 * s_f[rl + 1] - Cr * s_f[rl];
             Y0 = 0.5 * s_f[rl];
         } else {
+            // no neighbour: traces of the own cell's mirror image (LineGeom::wall)
             double q0 = 0.0;
 #pragma unroll
             for (int m = 0; m < NP; ++m) q0 += t.dL0p[m] * pp[m];
-            X0 = -0.5 * q0 - Cr * p0;
-            Y0 = 0.5 * p0;
+            X0 = lg.wall * (0.5 * q0 + Cr * p0);
+            Y0 = -lg.wall * 0.5 * p0;
         }
         if (hr) {
             const int rr = 2 * (lc2 * NFACE + (2 * a + 1) * NF + ln);
@@ -1112,8 +1113,8 @@ __global__ __launch_bounds__(256) void k_pressure_face(Geom g, LineGeom lg, Line
             double q1 = 0.0;
 #pragma unroll
             for (int m = 0; m < NP; ++m) q1 += t.dL1p[m] * pp[m];
-            X1 = 0.5 * q1 - Cr * p1;
-            Y1 = 0.5 * p1;
+            X1 = lg.wall * (Cr * p1 - 0.5 * q1);
+            Y1 = -lg.wall * 0.5 * p1;
         }
         const double sd = lg.sdiff[a] * L::wtan(s_W, ln);
 #pragma unroll
@@ -1227,8 +1228,10 @@ int launch_cg_apply(const tbdg_ctx* c, double alpha, const double* r, const doub
         else if ((dim) == 2 && (np) == 3) { FN(2, 3); }                                   \
         else if ((dim) == 2 && (np) == 4) { FN(2, 4); }                                   \
         else if ((dim) == 2 && (np) == 5) { FN(2, 5); }                                   \
+        else if ((dim) == 2 && (np) == 6) { FN(2, 6); }                                   \
         else if ((dim) == 3 && (np) == 2) { FN(3, 2); }                                   \
         else if ((dim) == 3 && (np) == 3) { FN(3, 3); }                                   \
+        else if ((dim) == 3 && (np) == 4) { FN(3, 4); }                                   \
         else throw Error(TBDG_EUNSUPPORTED, "unsupported (dim, pressure nodes)");          \
     } while (0)
 

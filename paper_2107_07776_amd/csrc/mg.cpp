@@ -1,8 +1,9 @@
-// Multigrid preconditioner of the pressure Helmholtz operator: hierarchy
-// set-up (level geometry and tables, Jacobi diagonals, Lanczos eigenvalue
-// estimates, dense coarse inverse), the V-cycle and the FP64 flexible CG
-// that uses it.  The hierarchy, smoother and cycle are defined in the header
-// next to tbdg_mg_setup.
+// Multigrid preconditioners: hierarchy set-up (level geometry and tables,
+// Jacobi diagonals, Lanczos eigenvalue estimates, dense coarse inverse), the
+// V-cycle, the FP64 flexible CG of the pressure Helmholtz solves that uses
+// it, and the velocity-component V-cycles that precondition the momentum
+// GMRES.  The hierarchy, smoother and cycle are defined in the header next
+// to tbdg_mg_setup.
 #include <algorithm>
 #include <cmath>
 #include <cstring>
@@ -144,7 +145,7 @@ void spd_inverse(std::vector<double>& A, int n) {
         }
 }
 
-MGLevel make_level(const tbdg_ctx* c, const int nc[3], int np) {
+MGLevel make_level(const tbdg_ctx* c, const MGData& M, const int nc[3], int np) {
     MGLevel L;
     L.np = np;
     L.Nc = 1;
@@ -167,7 +168,8 @@ MGLevel make_level(const tbdg_ctx* c, const int nc[3], int np) {
         L.lgeom.sadv[a] = L.geom.vol / L.geom.h[a];
         L.lgeom.sdiff[a] = L.geom.vol / (L.geom.h[a] * L.geom.h[a]);
     }
-    level_tables(np, c->pen_p, L.tab, L.line, L.cr);
+    L.lgeom.wall = M.wall;
+    level_tables(np, M.pen, L.tab, L.line, L.cr);
     LevelTabF& f = L.tf;
     std::memset(&f, 0, sizeof(f));
     for (int i = 0; i < np * np; ++i) f.A[i] = (float)L.line.A[i];
@@ -179,7 +181,8 @@ MGLevel make_level(const tbdg_ctx* c, const int nc[3], int np) {
         f.W[i] = (float)L.tab.Wp[i];
     }
     f.Cr = (float)L.cr;
-    for (int s = 1; s <= 2; ++s) f.cm[s] = (float)(c->alpha(s) * L.geom.vol);
+    f.wall = (float)M.wall;
+    for (int s = 1; s <= 2; ++s) f.cm[s] = (float)(M.alpha[s] * L.geom.vol);
     for (int a = 0; a < 3; ++a) f.sdiff[a] = (float)L.lgeom.sdiff[a];
     return L;
 }
@@ -200,6 +203,12 @@ void set_transfer(MGLevel& F, int kind) {
                 for (int j = 0; j < 2; ++j)
                     F.tt.T[b][i][j] = (float)lagrange_value(zc, 2, j, 0.5 * (b + zc[i]));
     }
+}
+
+void destroy_graphs(MGData& M) {
+    for (VGraph& g : M.graphs)
+        if (g.exec) (void)hipGraphExecDestroy(g.exec);
+    M.graphs.clear();
 }
 
 template <typename S>
@@ -223,8 +232,8 @@ LevelVecs<uint16_t> vecs0<uint16_t>(MGLevel& L) {
 // the buffer holding the final direction, whose addition to x is left to the
 // consumer (prolongation or the finest level's z).
 template <typename S>
-void presmooth(tbdg_ctx* c, MGLevel& L, int s, LevelVecs<S> v) {
-    const int m = c->mg->degree;
+void presmooth(tbdg_ctx* c, const MGData& M, MGLevel& L, int s, LevelVecs<S> v) {
+    const int m = M.degree;
     S* d[2] = {v.d0, v.d1};
     // k = 1: x = d0, r = b - H d0, d1
     launch_level_step<S>(c->stream, c->dim, L, s, MG_PRE1, (float)L.c1[s][1], (float)L.c2[s][1],
@@ -237,28 +246,38 @@ void presmooth(tbdg_ctx* c, MGLevel& L, int s, LevelVecs<S> v) {
                          v.b, nullptr, nullptr, nullptr, nullptr, nullptr);
 }
 
+// Output of the finest level's last step: z (zs values per cell) and, when
+// r64 / q64 are given, per-block partial sums z.r64, z.q64 in partial.
+struct ZOut {
+    double* z;
+    int zs;
+    const double* r64;
+    const double* q64;
+    double* partial;
+};
+
 template <typename S>
-S* postsmooth(tbdg_ctx* c, MGLevel& L, int s, LevelVecs<S> v, double* z, const double* r64,
-              const double* q64, double* partial) {
-    const int m = c->mg->degree;
+S* postsmooth(tbdg_ctx* c, const MGData& M, MGLevel& L, int s, LevelVecs<S> v, const ZOut* zo) {
+    const int m = M.degree;
     S* d[2] = {v.d0, v.d1};
     launch_level_step<S>(c->stream, c->dim, L, s, MG_RES, 0.0f, (float)(1.0 / L.theta[s]), nullptr,
                          v.x, v.r, v.b, d[0], nullptr, nullptr, nullptr, nullptr);
     for (int k = 1; k < m; ++k) {
-        const bool fin = z != nullptr && k == m - 1;
+        const bool fin = zo != nullptr && k == m - 1;
         launch_level_step<S>(c->stream, c->dim, L, s, fin ? MG_ZFIN : MG_STEP, (float)L.c1[s][k],
-                             (float)L.c2[s][k], d[(k - 1) & 1], v.x, v.r, v.b, d[k & 1], z, r64,
-                             q64, partial);
+                             (float)L.c2[s][k], d[(k - 1) & 1], v.x, v.r, v.b, d[k & 1],
+                             fin ? zo->z : nullptr, fin ? zo->r64 : nullptr,
+                             fin ? zo->q64 : nullptr, fin ? zo->partial : nullptr,
+                             fin ? zo->zs : 0);
     }
     return d[(m - 1) & 1];
 }
 
 // One V-cycle below the finest level's right-hand side and first direction
-// (already in place).  The finest level's final step writes z = x + d and the
-// partial sums z.r64, z.q64 to mg->zpart.
+// (already in place).  The finest level's final step writes z = x + d (and
+// the partial sums) as `zo` says.
 template <typename S>
-void vcycle(tbdg_ctx* c, int s, const double* r64, const double* q64) {
-    MGData& M = *c->mg;
+void vcycle(tbdg_ctx* c, MGData& M, int s, const ZOut& zo) {
     const int nl = (int)M.lv.size();
     // descent
     for (int l = 0; l < nl - 1; ++l) {
@@ -267,12 +286,12 @@ void vcycle(tbdg_ctx* c, int s, const double* r64, const double* q64) {
         const bool coarsest = l + 1 == nl - 1;
         if (l == 0) {
             LevelVecs<S> v = vecs0<S>(L);
-            presmooth<S>(c, L, s, v);
+            presmooth<S>(c, M, L, s, v);
             launch_restrict<S>(c->stream, c->dim, L, C, s, coarsest ? 0.0f : (float)(1.0 / C.theta[s]),
                                v.r, !coarsest);
         } else {
             LevelVecs<float> v = vecs0<float>(L);
-            presmooth<float>(c, L, s, v);
+            presmooth<float>(c, M, L, s, v);
             launch_restrict<float>(c->stream, c->dim, L, C, s,
                                    coarsest ? 0.0f : (float)(1.0 / C.theta[s]), v.r, !coarsest);
         }
@@ -287,18 +306,70 @@ void vcycle(tbdg_ctx* c, int s, const double* r64, const double* q64) {
         if (l == 0) {
             LevelVecs<S> v = vecs0<S>(L);
             launch_prolong<S>(c->stream, c->dim, L, C, v.x, pending);
-            postsmooth<S>(c, L, s, v, M.z, r64, q64, M.zpart);
+            postsmooth<S>(c, M, L, s, v, &zo);
         } else {
             LevelVecs<float> v = vecs0<float>(L);
             launch_prolong<float>(c->stream, c->dim, L, C, v.x, pending);
-            pending = postsmooth<float>(c, L, s, v, nullptr, nullptr, nullptr, nullptr);
+            pending = postsmooth<float>(c, M, L, s, v, nullptr);
         }
     }
 }
 
-void run_vcycle(tbdg_ctx* c, int s, int precision, const double* r64, const double* q64) {
-    if (precision == 2) vcycle<uint16_t>(c, s, r64, q64);
-    else vcycle<float>(c, s, r64, q64);
+void vcycle_eager(tbdg_ctx* c, MGData& M, int s, int precision, const ZOut& zo) {
+    if (precision == 2) vcycle<uint16_t>(c, M, s, zo);
+    else vcycle<float>(c, M, s, zo);
+}
+
+constexpr size_t kMaxGraphs = 16;   // captures kept per hierarchy
+
+// The V-cycle of (stage, precision, outputs) as one graph launch on the
+// library's stream.  Its launches (several per level, most of them short on
+// the coarse levels) are recorded once on a private stream and replayed:
+// the host issues one call instead of one per kernel.  The cycle has no
+// memset, copy or host synchronisation, only kernels on the hierarchy's
+// own buffers and the outputs of the key.
+void vcycle_graph(tbdg_ctx* c, MGData& M, int s, int precision, const ZOut& zo) {
+    VGraph* hit = nullptr;
+    for (VGraph& g : M.graphs)
+        if (g.s == s && g.prec == precision && g.z == zo.z && g.r64 == zo.r64 && g.q64 == zo.q64)
+            hit = &g;
+    if (!hit) {
+        if (M.graphs.size() >= kMaxGraphs) destroy_graphs(M);
+        if (!c->cap_stream) TBDG_HIP(hipStreamCreateWithFlags(&c->cap_stream, hipStreamNonBlocking));
+        hipStream_t saved = c->stream;
+        c->stream = c->cap_stream;
+        hipGraph_t graph = nullptr;
+        TBDG_HIP(hipStreamBeginCapture(c->cap_stream, hipStreamCaptureModeThreadLocal));
+        try {
+            vcycle_eager(c, M, s, precision, zo);
+        } catch (...) {
+            (void)hipStreamEndCapture(c->cap_stream, &graph);
+            if (graph) (void)hipGraphDestroy(graph);
+            c->stream = saved;
+            throw;
+        }
+        c->stream = saved;
+        TBDG_HIP(hipStreamEndCapture(c->cap_stream, &graph));
+        hipGraphExec_t exec = nullptr;
+        const hipError_t e = hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0);
+        (void)hipGraphDestroy(graph);
+        TBDG_HIP(e);
+        M.graphs.push_back(VGraph{s, precision, zo.z, zo.r64, zo.q64, exec});
+        hit = &M.graphs.back();
+    }
+    TBDG_HIP(hipGraphLaunch(hit->exec, c->stream));
+}
+
+void run_cycle(tbdg_ctx* c, MGData& M, int s, int precision, const ZOut& zo, bool graph) {
+    if (graph && c->mg_graphs) vcycle_graph(c, M, s, precision, zo);
+    else vcycle_eager(c, M, s, precision, zo);
+}
+
+// pressure: z to mg->z, partial sums z.r64, z.q64 to mg->zpart
+void run_vcycle(tbdg_ctx* c, int s, int precision, const double* r64, const double* q64,
+                bool graph) {
+    MGData& M = *c->mg;
+    run_cycle(c, M, s, precision, ZOut{M.z, 0, r64, q64, M.zpart}, graph);
 }
 
 int prep(tbdg_ctx* c, int s, int precision, int update, const double* pa, int Ga, double* sc,
@@ -315,10 +386,20 @@ int prep(tbdg_ctx* c, int s, int precision, int update, const double* pa, int Ga
 }  // namespace
 
 void mg_free(tbdg_ctx* c) {
+    mgu_free(c);
     if (!c->mg) return;
+    destroy_graphs(*c->mg);
     for (void* p : c->mg->allocs) (void)hipFree(p);
     delete c->mg;
     c->mg = nullptr;
+}
+
+void mgu_free(tbdg_ctx* c) {
+    if (!c->mgu) return;
+    destroy_graphs(*c->mgu);
+    for (void* p : c->mgu->allocs) (void)hipFree(p);
+    delete c->mgu;
+    c->mgu = nullptr;
 }
 
 namespace {
@@ -339,10 +420,10 @@ void mg_build(tbdg_ctx* c, MGData& M, const tbdg_mg_desc* desc) {
         throw Error(TBDG_EINVAL, "invalid multigrid parameters");
     // ---- hierarchy ----
     int nc[3] = {c->geom.nc[0], c->geom.nc[1], c->geom.nc[2]};
-    M.lv.push_back(make_level(c, nc, c->np));
-    if (c->np > 2) {
+    M.lv.push_back(make_level(c, M, nc, M.np0));
+    if (M.np0 > 2) {
         set_transfer(M.lv.back(), 1);
-        M.lv.push_back(make_level(c, nc, 2));
+        M.lv.push_back(make_level(c, M, nc, 2));
     }
     while ((int)M.lv.size() < MG_MAXLEVELS) {
         const MGLevel& L = M.lv.back();
@@ -351,7 +432,7 @@ void mg_build(tbdg_ctx* c, MGData& M, const tbdg_mg_desc* desc) {
         if (L.Nc <= M.coarse_cells || !even) break;
         set_transfer(M.lv.back(), 2);
         for (int a = 0; a < c->dim; ++a) nc[a] /= 2;
-        M.lv.push_back(make_level(c, nc, 2));
+        M.lv.push_back(make_level(c, M, nc, 2));
     }
     const int nl = (int)M.lv.size();
     if (nl < 2) throw Error(TBDG_EUNSUPPORTED, "multigrid needs at least two levels on this mesh");
@@ -377,9 +458,14 @@ void mg_build(tbdg_ctx* c, MGData& M, const tbdg_mg_desc* desc) {
             L.hd[1] = mg_alloc<uint16_t>(&M, L.N);
         }
     }
-    M.z = mg_alloc<double>(&M, c->Np);
-    M.zpart = mg_alloc<double>(&M, 2 * (int64_t)level_blocks(c->dim, M.lv[0]));
-    M.rpart = mg_alloc<double>(&M, 1024);
+    if (M.field == 0) {
+        // the flexible CG's glue
+        M.z = mg_alloc<double>(&M, M.n0);
+        M.zpart = mg_alloc<double>(&M, 2 * (int64_t)level_blocks(c->dim, M.lv[0]));
+        M.rpart = mg_alloc<double>(&M, 1024);
+    } else {
+        M.z = mg_alloc<double>(&M, M.n0 * c->dim);
+    }
     // ---- diagonals, eigenvalue estimates, Chebyshev coefficients ----
     int64_t nmax = 0;
     for (const MGLevel& L : M.lv) nmax = std::max(nmax, L.N);
@@ -390,7 +476,7 @@ void mg_build(tbdg_ctx* c, MGData& M, const tbdg_mg_desc* desc) {
     double* w3 = mg_alloc<double>(&M, nmax);
     double* w4 = mg_alloc<double>(&M, nmax);
     for (int s = 1; s <= 2; ++s) {
-        const double alpha = c->alpha(s);
+        const double alpha = M.alpha[s];
         for (int l = 0; l < nl - 1; ++l) {
             MGLevel& L = M.lv[l];
             launch_diag_pressure_level(c->stream, c->dim, L.np, L.geom, L.lgeom, L.line, L.tab,
@@ -436,14 +522,26 @@ void mg_build(tbdg_ctx* c, MGData& M, const tbdg_mg_desc* desc) {
     }
 }
 
-}  // namespace
-
-// The context sees the hierarchy only once it is complete: a failed set-up
-// (too few levels, a coarse matrix that is not SPD, an allocation) leaves no
-// partial state behind that a later solve could use.
-void mg_setup(tbdg_ctx* c, const tbdg_mg_desc* desc) {
-    mg_free(c);
+// Builds a hierarchy of the given field; the caller sees it only once it is
+// complete: a failed set-up (too few levels, a coarse matrix that is not
+// SPD, an allocation) leaves no partial state behind that a later solve
+// could use.
+MGData* mg_new(tbdg_ctx* c, int field, const tbdg_mg_desc* desc) {
     MGData* M = new MGData();
+    M->field = field;
+    if (field == 0) {
+        M->np0 = c->np;
+        M->n0 = c->Np;
+        M->pen = c->pen_p;
+        M->wall = -1.0;
+        for (int s = 1; s <= 2; ++s) M->alpha[s] = c->alpha(s);
+    } else {
+        M->np0 = c->n;
+        M->n0 = c->Ns;
+        M->pen = c->pen_u;
+        M->wall = 1.0;
+        for (int s = 1; s <= 2; ++s) M->alpha[s] = c->mcoef(s) / (c->theta[s] * c->nu);
+    }
     try {
         mg_build(c, *M, desc);
     } catch (...) {
@@ -451,14 +549,50 @@ void mg_setup(tbdg_ctx* c, const tbdg_mg_desc* desc) {
         delete M;
         throw;
     }
-    c->mg = M;
+    return M;
+}
+
+}  // namespace
+
+// The velocity hierarchy is dropped with it and rebuilt on its next use with
+// the same parameters.
+void mg_setup(tbdg_ctx* c, const tbdg_mg_desc* desc) {
+    mg_free(c);
+    if (desc) c->mg_desc = *desc;
+    else c->mg_desc = tbdg_mg_desc{};
+    c->mg = mg_new(c, 0, &c->mg_desc);
+}
+
+void mgu_ensure(tbdg_ctx* c) {
+    if (c->mgu) return;
+    if (!(c->nu > 0.0))
+        throw Error(TBDG_EINVAL, "the momentum multigrid needs a positive viscosity");
+    c->mgu = mg_new(c, 1, &c->mg_desc);
+}
+
+// The stage-s momentum operator's symmetric part on each component is
+// theta_s nu H_0 of the velocity hierarchy: z_comp = H_0^{-1} (s v_comp) /
+// (theta_s nu), one FP32 V-cycle per component into the hierarchy's own
+// velocity-layout buffer (a fixed graph output), then one copy to z.
+void mg_apply_velocity(tbdg_ctx* c, int s, const double* v, const double* sc_dev, double* z) {
+    mgu_ensure(c);
+    MGData& M = *c->mgu;
+    MGLevel& L = M.lv[0];
+    const int nb = (int)(L.N / L.Nc);
+    const float c2 = (float)(1.0 / L.theta[s]);
+    const double scale = 1.0 / (c->theta[s] * c->nu);
+    for (int d = 0; d < c->dim; ++d) {
+        launch_vel_prep(c->stream, L.Nc, nb, c->dim, d, v, sc_dev, scale, L.b, L.d[0], L.invd[s], c2);
+        run_cycle(c, M, s, 1, ZOut{M.z + (int64_t)d * nb, c->dim * nb, nullptr, nullptr, nullptr}, true);
+    }
+    TBDG_HIP(hipMemcpyAsync(z, M.z, sizeof(double) * M.n0 * c->dim, hipMemcpyDeviceToDevice, c->stream));
 }
 
 void mg_apply(tbdg_ctx* c, int s, int precision, const double* r, double* z) {
-    if (!c->mg) mg_setup(c, nullptr);
+    if (!c->mg) mg_setup(c, &c->mg_desc);
     double* sc = c->red_out + 64;
     prep(c, s, precision, 0, nullptr, 0, sc, 0, nullptr, const_cast<double*>(r), nullptr, nullptr);
-    run_vcycle(c, s, precision, r, nullptr);
+    run_vcycle(c, s, precision, r, nullptr, false);
     TBDG_HIP(hipMemcpyAsync(z, c->mg->z, sizeof(double) * c->Np, hipMemcpyDeviceToDevice, c->stream));
 }
 
@@ -471,7 +605,7 @@ constexpr int kStallWindow = 10;
 // iteration (the residual norm).
 tbdg_status solve_pressure_mg(tbdg_ctx* c, int s, const double* b, double* x,
                               const tbdg_solver_opts& o, tbdg_solve_info* info) {
-    if (!c->mg) mg_setup(c, nullptr);
+    if (!c->mg) mg_setup(c, &c->mg_desc);
     MGData& M = *c->mg;
     int prec = o.precond == TBDG_PRECOND_MG_BF16 ? 2 : 1;
     const int64_t n = c->Np;
@@ -525,7 +659,7 @@ tbdg_status solve_pressure_mg(tbdg_ctx* c, int s, const double* b, double* x,
             break;
         }
         if (total >= o.maxiter) break;
-        run_vcycle(c, s, prec, r, nullptr);
+        run_vcycle(c, s, prec, r, nullptr, true);
         launch_mg_beta(c->stream, M.zpart, G0, sc, 1, 8, 9);
         bool conv = false, broke = false, nan = false, stalled = false;
         int k = 0;
@@ -559,7 +693,7 @@ tbdg_status solve_pressure_mg(tbdg_ctx* c, int s, const double* b, double* x,
                 break;
             }
             if (total >= o.maxiter) break;
-            run_vcycle(c, s, prec, r, q);
+            run_vcycle(c, s, prec, r, q, true);
             launch_mg_beta(c->stream, M.zpart, G0, sc, 0, 8 + (k & 1), slot);
         }
         if ((broke || stalled) && prec == 2) {

@@ -1,7 +1,8 @@
-// Multigrid kernels for the pressure Helmholtz operator H = alpha M^p + K:
-// the FP32 (or BF16-storage / FP32-arithmetic) level operator fused with one
-// step of the Chebyshev smoother, the nested-space transfers, the FP64 coarse
-// solve and the FP64 flexible-CG glue.
+// Multigrid kernels for Helmholtz operators H = alpha M + K (the pressure's,
+// and one velocity component's with Dirichlet walls): the FP32 (or
+// BF16-storage / FP32-arithmetic) level operator fused with one step of the
+// Chebyshev smoother, the nested-space transfers, the FP64 coarse solve and
+// the FP64 glue of flexible CG and of the velocity preconditioner.
 //
 // Smoother (Chebyshev acceleration of the Jacobi-preconditioned system on
 // [lo, hi], theta = (hi + lo)/2): d_0 = D^{-1} r_0 / theta, then per step
@@ -57,7 +58,9 @@ struct Sto<uint16_t> {
 //   MG_LAST  x += d;     r -= H d
 //   MG_RES   r = b - H x;              d' = c2 D^{-1} r
 //   MG_ZFIN  as MG_STEP, but writes only z = x + d' in FP64 and per-block
-//           partial sums z.r64 and z.q64 (the last step of the finest level)
+//           partial sums z.r64 and z.q64 (the last step of the finest level;
+//           z, r64, q64 hold zs values per cell, r64 / q64 / partial may be
+//           null)
 // The operator is the same line-structured SIP form as the FP64 kernel:
 // neighbour traces (value, normal derivative) gathered in LDS, one work item
 // per (cell, direction, grid line), then mass term and directions summed.
@@ -71,7 +74,7 @@ __global__ __launch_bounds__(256) void k_level(Geom g, LineGeom lg, LevelTabF t,
                                                 double* __restrict__ z,
                                                 const double* __restrict__ r64,
                                                 const double* __restrict__ q64,
-                                                double* __restrict__ partial) {
+                                                double* __restrict__ partial, int zs) {
     using L = Lay<DIM, NP>;
     using F = FaceLay<DIM, NP>;
     using T = Sto<S>;
@@ -138,11 +141,12 @@ __global__ __launch_bounds__(256) void k_level(Geom g, LineGeom lg, LevelTabF t,
             X0 = 0.5f * s_f[rl + 1] - t.Cr * s_f[rl];
             Y0 = 0.5f * s_f[rl];
         } else {
+            // no neighbour: traces of the own cell's mirror image (LineGeom::wall)
             float q0 = 0.0f;
 #pragma unroll
             for (int m = 0; m < NP; ++m) q0 += t.dL0[m] * pp[m];
-            X0 = -0.5f * q0 - t.Cr * p0;
-            Y0 = 0.5f * p0;
+            X0 = t.wall * (0.5f * q0 + t.Cr * p0);
+            Y0 = -t.wall * 0.5f * p0;
         }
         if (hr) {
             const int rr = 2 * (lc2 * NFACE + (2 * a + 1) * NF + ln);
@@ -152,8 +156,8 @@ __global__ __launch_bounds__(256) void k_level(Geom g, LineGeom lg, LevelTabF t,
             float q1 = 0.0f;
 #pragma unroll
             for (int m = 0; m < NP; ++m) q1 += t.dL1[m] * pp[m];
-            X1 = 0.5f * q1 - t.Cr * p1;
-            Y1 = 0.5f * p1;
+            X1 = t.wall * (t.Cr * p1 - 0.5f * q1);
+            Y1 = -t.wall * 0.5f * p1;
         }
         float wt = 1.0f;
         if (DIM == 2) wt = t.W[ln];
@@ -197,12 +201,13 @@ __global__ __launch_bounds__(256) void k_level(Geom g, LineGeom lg, LevelTabF t,
             const float rn = T::ld(r, gi) - y;
             const float dn = c1 * pown + c2 * id * rn;
             const double zi = (double)xn + (double)dn;
-            z[gi] = zi;
-            zr = zi * r64[gi];
-            if (q64) zq = zi * q64[gi];
+            const size_t zi_idx = (size_t)cell * zs + nd;
+            z[zi_idx] = zi;
+            if (r64) zr = zi * r64[zi_idx];
+            if (q64) zq = zi * q64[zi_idx];
         }
     }
-    if (MODE == MG_ZFIN) {
+    if (MODE == MG_ZFIN && partial) {
         zr = red::block_sum(zr);
         zq = red::block_sum(zq);
         if (tid == 0) {
@@ -373,6 +378,24 @@ __global__ __launch_bounds__(256) void k_mg_beta(const double* partial, int G, d
     }
 }
 
+// b0 = s v_comp, d0 = c2 D^{-1} b0 (s = scale, times *sc_dev when given);
+// v in the velocity layout [cell][component][node], b0 and d0 one scalar
+// field [cell][node].
+__global__ __launch_bounds__(256) void k_vel_prep(int64_t n, int nb, int dim, int comp,
+                                                   const double* __restrict__ v,
+                                                   const double* __restrict__ sc_dev, double scale,
+                                                   float* __restrict__ b0, float* __restrict__ d0,
+                                                   const float* __restrict__ invd, float c2) {
+    const double s = sc_dev ? scale * sc_dev[0] : scale;
+    for (int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x; i < n; i += (int64_t)gridDim.x * 256) {
+        const int64_t cell = i / nb;
+        const int nd = (int)(i - cell * nb);
+        const float bs = (float)(s * v[(cell * dim + comp) * nb + nd]);
+        b0[i] = bs;
+        d0[i] = c2 * invd[i] * bs;
+    }
+}
+
 __global__ __launch_bounds__(256) void k_mul3(int64_t n, const double* a, const double* b,
                                                double* out) {
     for (int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x; i < n; i += (int64_t)gridDim.x * 256)
@@ -407,22 +430,25 @@ inline unsigned gs_grid(int64_t n) {
         else if ((dim) == 2 && (np) == 3) { FN(2, 3); }                                   \
         else if ((dim) == 2 && (np) == 4) { FN(2, 4); }                                   \
         else if ((dim) == 2 && (np) == 5) { FN(2, 5); }                                   \
+        else if ((dim) == 2 && (np) == 6) { FN(2, 6); }                                   \
         else if ((dim) == 3 && (np) == 2) { FN(3, 2); }                                   \
         else if ((dim) == 3 && (np) == 3) { FN(3, 3); }                                   \
+        else if ((dim) == 3 && (np) == 4) { FN(3, 4); }                                   \
         else throw Error(TBDG_EUNSUPPORTED, "unsupported multigrid level");               \
     } while (0)
 
 template <typename S>
 int launch_level_step(hipStream_t st, int dim, const MGLevel& L, int stage, int mode, float c1,
                       float c2, const S* dop, S* x, S* r, const S* b, S* dout, double* z,
-                      const double* r64, const double* q64, double* partial) {
+                      const double* r64, const double* q64, double* partial, int zs) {
     int G = 0;
+    if (zs <= 0) zs = (int)(L.N / L.Nc);
     const float cm = L.tf.cm[stage];
     const float* invd = L.invd[stage];
 #define K_(D, NP, MODE)                                                                    \
     hipLaunchKernelGGL((k_level<D, NP, S, MODE>), dim3(G), dim3(256), 0, st, L.geom,       \
                        L.lgeom, L.tf, cm, c1, c2, dop, x, r, b, invd, dout, (int)L.Nc, z,  \
-                       r64, q64, partial)
+                       r64, q64, partial, zs)
 #define L_(D, NP)                                                                          \
     {                                                                                      \
         G = (int)nblk(L.Nc, FaceLay<D, NP>::CPB);                                          \
@@ -442,11 +468,11 @@ int launch_level_step(hipStream_t st, int dim, const MGLevel& L, int stage, int 
 }
 template int launch_level_step<float>(hipStream_t, int, const MGLevel&, int, int, float, float,
                                       const float*, float*, float*, const float*, float*,
-                                      double*, const double*, const double*, double*);
+                                      double*, const double*, const double*, double*, int);
 template int launch_level_step<uint16_t>(hipStream_t, int, const MGLevel&, int, int, float,
                                          float, const uint16_t*, uint16_t*, uint16_t*,
                                          const uint16_t*, uint16_t*, double*, const double*,
-                                         const double*, double*);
+                                         const double*, double*, int);
 
 int level_blocks(int dim, const MGLevel& L) {
     int G = 0;
@@ -531,6 +557,15 @@ void launch_mg_beta(hipStream_t st, const double* partial, int G, double* sc, in
                     int slot_prev) {
     hipLaunchKernelGGL(k_mg_beta, dim3(1), dim3(256), 0, st, partial, G, sc, first, slot,
                        slot_prev);
+    TBDG_HIP(hipGetLastError());
+}
+
+void launch_vel_prep(hipStream_t st, int64_t Nc, int nb, int dim, int comp, const double* v,
+                     const double* sc_dev, double scale, float* b0, float* d0, const float* invd,
+                     float c2) {
+    const int64_t n = Nc * nb;
+    hipLaunchKernelGGL(k_vel_prep, dim3(gs_grid(n)), dim3(256), 0, st, n, nb, dim, comp, v, sc_dev,
+                       scale, b0, d0, invd, c2);
     TBDG_HIP(hipGetLastError());
 }
 

@@ -150,6 +150,7 @@ void build_line_operators(tbdg_ctx* c) {
         c->lgeom.sadv[a] = c->geom.vol / c->geom.h[a];
         c->lgeom.sdiff[a] = c->geom.vol / (c->geom.h[a] * c->geom.h[a]);
     }
+    c->lgeom.wall = -1.0;   // pressure forms: natural condition at walls
 }
 
 }  // namespace trbdg

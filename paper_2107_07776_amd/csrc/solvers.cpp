@@ -1,7 +1,8 @@
 // Krylov solvers and the TR-BDF2 step (host orchestration of device kernels).
 //
 // GMRES (momentum predictor): restarted, right-preconditioned with the exact
-// Jacobi diagonal; classical Gram-Schmidt through one multi-vector dot kernel
+// Jacobi diagonal, the line blocks, or FP32 multigrid V-cycles of the
+// operator's symmetric part on each component; classical Gram-Schmidt through one multi-vector dot kernel
 // and one update kernel that also returns the new norm, repeated once when
 // the norm drops below 1/sqrt(2) of its value before orthogonalisation
 // (the "twice is enough" criterion); Givens rotations on the host.
@@ -88,9 +89,18 @@ tbdg_status solve_momentum(tbdg_ctx* c, int s, const double* w, const double* b,
     const int m = std::min(o.restart > 0 ? o.restart : 30, c->gm_m);
     MomentumOp A{c, s, w};
     const bool line = o.precond == TBDG_PRECOND_LINE;
+    const bool mgp = o.precond == TBDG_PRECOND_MG_FP32;
+    // line blocks and multigrid are applied by their own kernels into gz;
+    // the Jacobi scaling inside the operator kernel
+    const bool pc = line || mgp;
     launch_diag_momentum(c, s, w, c->diag_u);
     vec_recip(c->stream, c->Ns, c->diag_u, c->invd_u);
     const double* dprec = line ? build_mom_lineprec(c, s, w) : nullptr;
+    if (mgp) mgu_ensure(c);
+    auto apply_pc = [&](const double* in, const double* sc_dev, double* out) {
+        if (line) launch_mom_lineprec(c, c->mom_blk, dprec, in, sc_dev, out);
+        else mg_apply_velocity(c, s, in, sc_dev, out);
+    };
     const double bnorm = norm2(c, n, b);
     tbdg_solve_info inf{0, 0.0, 0.0, 0};
     if (bnorm == 0.0) {
@@ -150,8 +160,8 @@ tbdg_status solve_momentum(tbdg_ctx* c, int s, const double* w, const double* b,
             double* vj = V + (int64_t)j * ld;
             double* vn = V + (int64_t)(j + 1) * ld;
             // vn = (A P^{-1} - sigma) (gsc_j V_j), P the Jacobi diagonal (applied
-            // inside the operator kernel) or the line-block preconditioner
-            // (applied by its own kernel into gz): the Arnoldi process runs on
+            // inside the operator kernel) or the line-block or multigrid
+            // preconditioner (applied into gz): the Arnoldi process runs on
             // the shifted operator, whose Krylov spaces are the same; with the
             // preconditioned operator close to the identity the shift removes
             // most of the cancellation, so one Gram-Schmidt pass is normally
@@ -161,8 +171,8 @@ tbdg_status solve_momentum(tbdg_ctx* c, int s, const double* w, const double* b,
             MomFuse fz{c->invd_u, gsc + j, kArnoldiShift, V, ld, fused ? j + 1 : 0,
                        c->gm_part, nullptr};
             const double* opnd = vj;
-            if (line) {
-                launch_mom_lineprec(c, c->mom_blk, dprec, vj, gsc + j, c->gz);
+            if (pc) {
+                apply_pc(vj, gsc + j, c->gz);
                 opnd = c->gz;
                 fz.invd = nullptr;
                 fz.shv = vj;
@@ -227,10 +237,10 @@ tbdg_status solve_momentum(tbdg_ctx* c, int s, const double* w, const double* b,
             std::memcpy(c->host_out, y.data(), sizeof(double) * k);
             TBDG_HIP(hipMemcpyAsync(c->red_out, c->host_out, sizeof(double) * (2 * k + 1),
                                     hipMemcpyHostToDevice, c->stream));
-            gm_restart(c, n, k, V, ld, c->red_out, c->red_out + k, gsc, line ? nullptr : c->invd_u,
-                       x, c->red_out + 63, gsc, line ? c->gz : nullptr);
-            if (line) {
-                launch_mom_lineprec(c, c->mom_blk, dprec, c->gz, nullptr, c->gv);
+            gm_restart(c, n, k, V, ld, c->red_out, c->red_out + k, gsc, pc ? nullptr : c->invd_u,
+                       x, c->red_out + 63, gsc, pc ? c->gz : nullptr);
+            if (pc) {
+                apply_pc(c->gz, nullptr, c->gv);
                 vec_axpby(c->stream, n, 1.0, x, 1.0, c->gv, x);
             }
             beta = std::sqrt(mirrored(c, c->red_out + 63));
@@ -243,8 +253,8 @@ tbdg_status solve_momentum(tbdg_ctx* c, int s, const double* w, const double* b,
                                     hipMemcpyHostToDevice, c->stream));
             TBDG_HIP(hipMemsetAsync(c->gz, 0, sizeof(double) * n, c->stream));
             vec_add_combo(c->stream, n, k, V, ld, c->red_out, gsc, c->gz);
-            if (line) {
-                launch_mom_lineprec(c, c->mom_blk, dprec, c->gz, nullptr, c->gv);
+            if (pc) {
+                apply_pc(c->gz, nullptr, c->gv);
                 vec_axpby(c->stream, n, 1.0, x, 1.0, c->gv, x);
             } else {
                 vec_add_div_diag_u(c->stream, n, c->dim, c->nbu, c->gz, c->diag_u, x);

@@ -25,7 +25,9 @@ EXPORTED = [
     "tbdg_add_grad_p", "tbdg_rhs_pressure", "tbdg_solve_momentum", "tbdg_solve_pressure",
     "tbdg_solve_pressure_noalloc",
     "tbdg_step", "tbdg_profile_enable", "tbdg_profile_read", "tbdg_mg_setup",
-    "tbdg_mg_levels", "tbdg_mg_apply", "tbdg_net_create", "tbdg_net_destroy",
+    "tbdg_mg_levels", "tbdg_mg_apply", "tbdg_mg_apply_momentum", "tbdg_mg_levels_momentum",
+    "tbdg_set_mg_graphs",
+    "tbdg_net_create", "tbdg_net_destroy",
     "tbdg_net_last_error", "tbdg_net_num_params", "tbdg_net_set_params", "tbdg_net_get_params",
     "tbdg_net_get_grads", "tbdg_net_zero_grad", "tbdg_net_forward", "tbdg_net_backward",
     "tbdg_net_mse", "tbdg_net_quad_loss", "tbdg_net_adam_step", "tbdg_set_guess_net",
@@ -133,6 +135,9 @@ def load_library(path=LIB_PATH):
         "tbdg_mg_setup": ([vp, P(MGDesc)], i),
         "tbdg_mg_levels": ([vp, i, P(i), P(i64), P(d)], i),
         "tbdg_mg_apply": ([vp, i, i, vp, vp], i),
+        "tbdg_mg_apply_momentum": ([vp, i, vp, vp], i),
+        "tbdg_mg_levels_momentum": ([vp, i, P(i), P(i64), P(d)], i),
+        "tbdg_set_mg_graphs": ([vp, i], i),
         "tbdg_net_create": ([i, ctypes.c_uint64, vp, P(vp)], i),
         "tbdg_net_destroy": ([vp], None),
         "tbdg_net_last_error": ([vp], ctypes.c_char_p),
@@ -376,7 +381,8 @@ class Context:
         ``precond`` selects the pressure preconditioner, ``guess`` the initial
         guess of the pressure solves ("given": previous pressure, "previous":
         rescaled newest increment, "learned": the attached network),
-        ``mom_precond`` the momentum preconditioner ("jacobi" or "line")."""
+        ``mom_precond`` the momentum preconditioner ("jacobi", "line" or
+        "mg_fp32")."""
         S = State(_ptr(self._vec(u, self.N_u, "u")), _ptr(self._vec(u_hist, self.N_u, "u_hist")),
                   _ptr(self._vec(p, self.N_p, "p")), float(t), int(n))
         mo = solver_opts(mom_tol, mom_maxiter, restart, mom_precond, guess=mom_guess)
@@ -410,13 +416,15 @@ class Context:
                    int(max_coarse_dofs))
         self._check(self.lib.tbdg_mg_setup(self.h, ctypes.byref(d)))
 
-    def mg_levels(self, cap=16):
+    def mg_levels(self, cap=16, field="p"):
         """List of per-level dicts (nodes per direction, cells, DoFs, eigenvalue
-        estimates of stages 1 and 2)."""
+        estimates of stages 1 and 2) of the pressure ("p") or the momentum
+        ("u") hierarchy."""
         n = ctypes.c_int()
         desc = (ctypes.c_int64 * (5 * cap))()
         lam = (ctypes.c_double * (2 * cap))()
-        self._check(self.lib.tbdg_mg_levels(self.h, cap, ctypes.byref(n), desc, lam))
+        fn = self.lib.tbdg_mg_levels if field == "p" else self.lib.tbdg_mg_levels_momentum
+        self._check(fn(self.h, cap, ctypes.byref(n), desc, lam))
         return [dict(np=desc[5 * l], cells=tuple(desc[5 * l + 1:5 * l + 4]), dofs=desc[5 * l + 4],
                      lam=(lam[l], lam[cap + l])) for l in range(min(n.value, cap))]
 
@@ -426,6 +434,19 @@ class Context:
         self._check(self.lib.tbdg_mg_apply(self.h, stage, 1 if precision == "fp32" else 2,
                                            _ptr(self._vec(r, self.N_p, "r")), _ptr(z)))
         return z
+
+    def mg_apply_momentum(self, stage, v):
+        """z = P^{-1} v: one FP32 V-cycle of the momentum hierarchy per velocity
+        component of v / (theta_s nu)."""
+        z = self.empty_u()
+        self._check(self.lib.tbdg_mg_apply_momentum(self.h, stage, _ptr(self._vec(v, self.N_u, "v")),
+                                                    _ptr(z)))
+        return z
+
+    def set_mg_graphs(self, enable):
+        """V-cycles inside the solves as HIP-graph replays (True, the
+        default) or launched kernel by kernel (False); same results."""
+        self._check(self.lib.tbdg_set_mg_graphs(self.h, 1 if enable else 0))
 
     def set_guess_net(self, net):
         """Attach a Net (same stream) for guess="learned", or None to detach."""
