@@ -164,7 +164,8 @@ def kovasznay_errors(ctx, W, U, P):
 # the library's measurement hook times every third launch of an operator kernel
 LAUNCH_SAMPLE_STRIDE = 3
 
-TRAFFIC_FILES = {("momentum_apply", "tgv32"): "momentum_face_tgv32_q3_traffic.txt"}
+TRAFFIC_FILES = {("momentum_apply", "tgv32"): "momentum_face_tgv32_q3_traffic.txt",
+                 ("momentum_apply", "tgv64"): "momentum_face_tgv64_q3_traffic.txt"}
 
 
 def measured_traffic(kernel, workload):
