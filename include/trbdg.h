@@ -277,6 +277,11 @@ typedef struct {
     double safety;       /* 0 => 1.1                                            */
     int coarse_cells;    /* 0 => 64 (3D) / 16 (2D)                              */
     int max_coarse_dofs; /* largest coarsest level solved densely (0 => 2048)    */
+    int no_fuse;         /* 0: the longest run of Q1 levels below level 0 (down to
+                            the coarsest) whose FP32 vectors fit one workgroup's
+                            LDS runs as one single-workgroup launch per V-cycle
+                            (same smoother, transfers and coarse solve);
+                            1: every level launched on its own                 */
 } tbdg_mg_desc;
 
 /* (Re)builds the hierarchy for both stages (desc NULL: defaults).  Fails
@@ -318,6 +323,11 @@ TBDG_API tbdg_status tbdg_mg_apply_momentum(tbdg_ctx* ctx, int stage, const doub
  * needed).                                                                  */
 TBDG_API tbdg_status tbdg_mg_levels_momentum(tbdg_ctx* ctx, int cap, int* n_levels, int64_t* desc,
                                              double* lambda);
+
+/* The single-workgroup coarse cycle of a built hierarchy (field 0: pressure,
+ * 1: momentum): *first_level = the first level it runs (-1: none, every
+ * level launched on its own), *lds_bytes = its LDS.  Host outputs.         */
+TBDG_API tbdg_status tbdg_mg_fused(tbdg_ctx* ctx, int field, int* first_level, int64_t* lds_bytes);
 
 /* enable = 1 (the default): every V-cycle of the pressure flexible CG, of
  * the momentum GMRES and of tbdg_mg_apply_momentum runs as one replay of a

@@ -569,6 +569,19 @@ tbdg_status tbdg_mg_apply_momentum(tbdg_ctx* c, int stage, const double* v, doub
     });
 }
 
+tbdg_status tbdg_mg_fused(tbdg_ctx* c, int field, int* first_level, int64_t* lds_bytes) {
+    if (!c) return TBDG_EINVAL;
+    return guarded(c, [&]() {
+        require(first_level && lds_bytes, "null output");
+        require(field == 0 || field == 1, "field must be 0 (pressure) or 1 (momentum)");
+        const trbdg::MGData* M = field == 0 ? c->mg : c->mgu;
+        if (!M) throw Error(TBDG_EINVAL, "multigrid hierarchy not built");
+        *first_level = M->fuse_from;
+        *lds_bytes = M->fuse_from > 0 ? (int64_t)M->fuse_lds : 0;
+        return TBDG_OK;
+    });
+}
+
 tbdg_status tbdg_set_mg_graphs(tbdg_ctx* c, int enable) {
     if (!c) return TBDG_EINVAL;
     return guarded(c, [&]() {

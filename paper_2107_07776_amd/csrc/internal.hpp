@@ -188,6 +188,31 @@ struct MGLevel {
 // velocity component, alpha_s = m_s / (theta_s nu) and Dirichlet walls, so
 // that theta_s nu H_0 is the symmetric part (mass and diffusion) of the
 // stage-s momentum operator on each component.
+// The coarse end of a V-cycle run by one workgroup: the Q1 levels from some
+// level below level 0 down to the coarsest, every vector resident in LDS
+// (5 FP32 vectors per smoothing level, 2 on the coarsest), the same smoother,
+// transfers and dense FP64 coarse solve as the level-by-level launches.
+// Filled per stage by the host; passed by value.
+constexpr int FUSE_MAXLV = 8;
+constexpr int FUSE_THREADS = 1024;
+struct FusedLv {
+    int nc[3];
+    int Nc, N, off;             // cells, DoFs, float offset of x (r, b, d0, d1 follow)
+    float sdiff[3], cm, c2res;  // cm = alpha_s |K|; c2res = 1 / theta_s (residual step)
+    float c1[MG_MAXDEG], c2[MG_MAXDEG];
+    const float* invd;          // stage-s inverse diagonal (global)
+};
+struct FusedCycle {
+    int nlev, degree;
+    int periodic[3];
+    float A[4], L0[2], L1[2], dL0[2], dL1[2], W[2], Cr, wall;
+    TransferTab tt;             // h-transfer (the same for every pair of Q1 levels)
+    const double* ainv;         // coarsest level's inverse (row-major, FP64)
+    const float* b_top;         // right-hand side of the top fused level (global)
+    float* x_top;               // its output x + d (global)
+    FusedLv lv[FUSE_MAXLV];
+};
+
 // A V-cycle captured from the library's launches and replayed as one HIP
 // graph; valid for the hierarchy it was captured from and the key below.
 struct VGraph {
@@ -212,6 +237,9 @@ struct MGData {
     double* rpart = nullptr;    // partial sums r.r of the FP64 update
     std::vector<void*> allocs;
     std::vector<VGraph> graphs;
+    bool no_fuse = false;
+    int fuse_from = -1;         // first level of the single-workgroup coarse cycle (-1: none)
+    size_t fuse_lds = 0;        // its LDS bytes
 };
 
 // Learned / extrapolated initial guesses of the Helmholtz solves in a step.
@@ -530,6 +558,11 @@ int launch_mg_prep(hipStream_t st, int64_t n, int update, const double* pa, int 
                    const float* invd, float c2, double* partial);
 void launch_mg_beta(hipStream_t st, const double* partial, int G, double* sc, int first, int slot,
                     int slot_prev);
+// the coarse end of a V-cycle in one workgroup (levels fc.lv[0..nlev-1])
+void launch_fused_cycle(hipStream_t st, int dim, const FusedCycle& fc, size_t lds);
+// largest LDS a workgroup may take on the current device (after raising the
+// fused kernel's limit to it)
+size_t fused_lds_limit(int dim);
 // b0 = s v_comp (s = scale, times *sc_dev when given), d0 = c2 D^{-1} b0: the
 // level-0 data of one velocity component ([cell][component][node] layout)
 void launch_vel_prep(hipStream_t st, int64_t Nc, int nb, int dim, int comp, const double* v,

@@ -273,12 +273,63 @@ S* postsmooth(tbdg_ctx* c, const MGData& M, MGLevel& L, int s, LevelVecs<S> v, c
     return d[(m - 1) & 1];
 }
 
+// The stage-s description of the single-workgroup coarse cycle (levels
+// fuse_from .. coarsest).
+FusedCycle fused_desc(const MGData& M, int s) {
+    FusedCycle fc;
+    std::memset(&fc, 0, sizeof(fc));
+    const int nl = (int)M.lv.size();
+    const MGLevel& T = M.lv[M.fuse_from];
+    fc.nlev = nl - M.fuse_from;
+    fc.degree = M.degree;
+    for (int a = 0; a < 3; ++a) fc.periodic[a] = T.lgeom.periodic[a];
+    for (int i = 0; i < 4; ++i) fc.A[i] = T.tf.A[i];
+    for (int i = 0; i < 2; ++i) {
+        fc.L0[i] = T.tf.L0[i];
+        fc.L1[i] = T.tf.L1[i];
+        fc.dL0[i] = T.tf.dL0[i];
+        fc.dL1[i] = T.tf.dL1[i];
+        fc.W[i] = T.tf.W[i];
+    }
+    fc.Cr = T.tf.Cr;
+    fc.wall = T.tf.wall;
+    fc.tt = T.tt;
+    fc.ainv = M.ainv[s];
+    fc.b_top = T.b;
+    fc.x_top = T.x;
+    int off = 0;
+    for (int i = 0; i < fc.nlev; ++i) {
+        const MGLevel& L = M.lv[M.fuse_from + i];
+        FusedLv& F = fc.lv[i];
+        for (int a = 0; a < 3; ++a) {
+            F.nc[a] = L.geom.nc[a];
+            F.sdiff[a] = L.tf.sdiff[a];
+        }
+        F.Nc = (int)L.Nc;
+        F.N = (int)L.N;
+        F.off = off;
+        off += 5 * F.N;
+        F.cm = L.tf.cm[s];
+        F.c2res = i + 1 < fc.nlev ? (float)(1.0 / L.theta[s]) : 0.0f;
+        for (int k = 0; k < MG_MAXDEG; ++k) {
+            F.c1[k] = (float)L.c1[s][k];
+            F.c2[k] = (float)L.c2[s][k];
+        }
+        F.invd = L.invd[s];
+    }
+    return fc;
+}
+
 // One V-cycle below the finest level's right-hand side and first direction
 // (already in place).  The finest level's final step writes z = x + d (and
-// the partial sums) as `zo` says.
+// the partial sums) as `zo` says.  With a fused range the levels from
+// fuse_from down run in one single-workgroup launch, which leaves x + d in
+// the top fused level's x.
 template <typename S>
 void vcycle(tbdg_ctx* c, MGData& M, int s, const ZOut& zo) {
-    const int nl = (int)M.lv.size();
+    const int nl_all = (int)M.lv.size();
+    const bool fused = M.fuse_from > 0;
+    const int nl = fused ? M.fuse_from + 1 : nl_all;   // the top fused level acts as coarsest
     // descent
     for (int l = 0; l < nl - 1; ++l) {
         MGLevel& L = M.lv[l];
@@ -297,7 +348,8 @@ void vcycle(tbdg_ctx* c, MGData& M, int s, const ZOut& zo) {
         }
     }
     MGLevel& LC = M.lv[nl - 1];
-    launch_coarse(c->stream, M.ainv[s], LC.b, LC.x, (int)LC.N);
+    if (fused) launch_fused_cycle(c->stream, c->dim, fused_desc(M, s), M.fuse_lds);
+    else launch_coarse(c->stream, M.ainv[s], LC.b, LC.x, (int)LC.N);
     // ascent
     const float* pending = nullptr;   // final direction of the level below, not yet in its x
     for (int l = nl - 2; l >= 0; --l) {
@@ -414,6 +466,7 @@ void mg_build(tbdg_ctx* c, MGData& M, const tbdg_mg_desc* desc) {
         if (desc->safety > 0.0) M.safety = desc->safety;
         if (desc->coarse_cells) M.coarse_cells = desc->coarse_cells;
         if (desc->max_coarse_dofs) M.max_coarse = desc->max_coarse_dofs;
+        M.no_fuse = desc->no_fuse != 0;
     }
     if (M.degree < 2 || M.degree >= MG_MAXDEG) throw Error(TBDG_EINVAL, "multigrid degree must be in [2, 15]");
     if (M.lanczos_steps < 1 || M.range <= 1.0 || M.safety < 1.0 || M.coarse_cells < 1)
@@ -465,6 +518,27 @@ void mg_build(tbdg_ctx* c, MGData& M, const tbdg_mg_desc* desc) {
         M.rpart = mg_alloc<double>(&M, 1024);
     } else {
         M.z = mg_alloc<double>(&M, M.n0 * c->dim);
+    }
+    // ---- single-workgroup coarse cycle: the longest run of Q1 levels below
+    // level 0, joined by h-transfers down to the coarsest, whose vectors fit
+    // one workgroup's LDS (5 FP32 vectors per level) ----
+    M.fuse_from = -1;
+    if (!M.no_fuse) {
+        const size_t lim = fused_lds_limit(c->dim);
+        size_t bytes = 0;
+        int from = nl;
+        for (int l = nl - 1; l >= 1 && nl - l <= FUSE_MAXLV; --l) {
+            const MGLevel& L = M.lv[l];
+            if (L.np != 2 || (l < nl - 1 && L.transfer != 2)) break;
+            const size_t add = 5 * sizeof(float) * (size_t)L.N;
+            if (bytes + add > lim) break;
+            bytes += add;
+            from = l;
+        }
+        if (nl - from >= 2) {
+            M.fuse_from = from;
+            M.fuse_lds = bytes;
+        }
     }
     // ---- diagonals, eigenvalue estimates, Chebyshev coefficients ----
     int64_t nmax = 0;

@@ -309,6 +309,222 @@ __global__ __launch_bounds__(256) void k_coarse(const double* __restrict__ Ainv,
     if (row < n && lane == 0) x[row] = (float)acc;
 }
 
+// ---- the coarse end of a V-cycle in one workgroup --------------------------------
+// Every Q1 level from fc.lv[0] down to the coarsest lives in LDS; each
+// smoother step, transfer and the coarse solve is one pass of the block's
+// 1024 threads over the level's nodes, separated by block barriers.  The
+// per-node arithmetic is k_level's, k_restrict's / k_prolong's (h-transfer)
+// and k_coarse's.
+
+// neighbour of a cell with coordinates ci along direction a, side s (0 left,
+// 1 right), or -1 at a wall
+template <int DIM>
+__device__ inline int fz_nbr(const int* nc, const int* per, const int* ci, int cell, int a, int s) {
+    int stride = 1;
+    for (int e = 0; e < a; ++e) stride *= nc[e];
+    if (s == 0) return ci[a] > 0 ? cell - stride : (per[a] ? cell + (nc[a] - 1) * stride : -1);
+    return ci[a] < nc[a] - 1 ? cell + stride : (per[a] ? cell - (nc[a] - 1) * stride : -1);
+}
+
+// (H p) at node nd of a cell of a Q1 level in LDS
+template <int DIM>
+__device__ float fz_apply(const FusedCycle& fc, const FusedLv& L, const float* p, int cell, int nd) {
+    constexpr int NB = 1 << DIM;
+    int ci[3] = {0, 0, 0};
+    int rr = cell;
+    for (int a = 0; a < DIM; ++a) {
+        ci[a] = rr % L.nc[a];
+        rr /= L.nc[a];
+    }
+    float wn = 1.0f;
+    for (int a = 0; a < DIM; ++a) wn *= fc.W[(nd >> a) & 1];
+    float y = L.cm * wn * p[cell * NB + nd];
+    for (int a = 0; a < DIM; ++a) {
+        const int ia = (nd >> a) & 1;
+        const int n0 = nd & ~(1 << a), n1 = nd | (1 << a);   // the line's two nodes
+        const float pp0 = p[cell * NB + n0], pp1 = p[cell * NB + n1];
+        const float p0 = fc.L0[0] * pp0 + fc.L0[1] * pp1;
+        const float p1 = fc.L1[0] * pp0 + fc.L1[1] * pp1;
+        const int lf = fz_nbr<DIM>(L.nc, fc.periodic, ci, cell, a, 0);
+        const int rt = fz_nbr<DIM>(L.nc, fc.periodic, ci, cell, a, 1);
+        float X0, Y0, X1, Y1;
+        if (lf >= 0) {
+            const float v0 = p[lf * NB + n0], v1 = p[lf * NB + n1];
+            const float v = fc.L1[0] * v0 + fc.L1[1] * v1;
+            const float d = fc.dL1[0] * v0 + fc.dL1[1] * v1;
+            X0 = 0.5f * d - fc.Cr * v;
+            Y0 = 0.5f * v;
+        } else {
+            const float q0 = fc.dL0[0] * pp0 + fc.dL0[1] * pp1;
+            X0 = fc.wall * (0.5f * q0 + fc.Cr * p0);
+            Y0 = -fc.wall * 0.5f * p0;
+        }
+        if (rt >= 0) {
+            const float v0 = p[rt * NB + n0], v1 = p[rt * NB + n1];
+            const float v = fc.L0[0] * v0 + fc.L0[1] * v1;
+            const float d = fc.dL0[0] * v0 + fc.dL0[1] * v1;
+            X1 = -0.5f * d - fc.Cr * v;
+            Y1 = 0.5f * v;
+        } else {
+            const float q1 = fc.dL1[0] * pp0 + fc.dL1[1] * pp1;
+            X1 = fc.wall * (fc.Cr * p1 - 0.5f * q1);
+            Y1 = -fc.wall * 0.5f * p1;
+        }
+        float wt = 1.0f;
+        for (int e = 0; e < DIM; ++e)
+            if (e != a) wt *= fc.W[(nd >> e) & 1];
+        float sl = fc.A[ia * 2] * pp0 + fc.A[ia * 2 + 1] * pp1;
+        sl += fc.L0[ia] * X0 - fc.dL0[ia] * Y0 + fc.L1[ia] * X1 + fc.dL1[ia] * Y1;
+        y += L.sdiff[a] * wt * sl;
+    }
+    return y;
+}
+
+// one smoother step (modes of k_level) on a level in LDS; returns after the
+// block barrier
+template <int DIM, int MODE>
+__device__ void fz_step(const FusedCycle& fc, const FusedLv& L, float* lds, int din, float c1,
+                        float c2) {
+    constexpr int NB = 1 << DIM;
+    float* x = lds + L.off;
+    float* r = x + L.N;
+    const float* b = x + 2 * L.N;
+    float* d[2] = {x + 3 * L.N, x + 4 * L.N};
+    const float* op = MODE == MG_RES ? x : d[din];
+    float* dout = MODE == MG_RES ? d[0] : d[din ^ 1];
+    for (int i = threadIdx.x; i < L.N; i += FUSE_THREADS) {
+        const int cell = i / NB, nd = i % NB;
+        const float y = fz_apply<DIM>(fc, L, op, cell, nd);
+        const float pown = op[i];
+        const float id = MODE == MG_LAST ? 0.0f : L.invd[i];
+        if (MODE == MG_PRE1) {
+            x[i] = pown;
+            const float rn = b[i] - y;
+            r[i] = rn;
+            dout[i] = c1 * pown + c2 * id * rn;
+        } else if (MODE == MG_STEP) {
+            x[i] = x[i] + pown;
+            const float rn = r[i] - y;
+            r[i] = rn;
+            dout[i] = c1 * pown + c2 * id * rn;
+        } else if (MODE == MG_LAST) {
+            x[i] = x[i] + pown;
+            r[i] = r[i] - y;
+        } else {   // MG_RES
+            const float rn = b[i] - y;
+            r[i] = rn;
+            dout[i] = c2 * id * rn;
+        }
+    }
+    __syncthreads();
+}
+
+template <int DIM>
+__global__ __launch_bounds__(FUSE_THREADS) void k_fused_cycle(FusedCycle fc) {
+    extern __shared__ float lds[];
+    constexpr int NB = 1 << DIM;
+    const int tid = threadIdx.x;
+    const int m = fc.degree;
+    const int nl = fc.nlev;
+    // top level: right-hand side and first direction
+    {
+        const FusedLv& L = fc.lv[0];
+        float* b = lds + L.off + 2 * L.N;
+        float* d0 = lds + L.off + 3 * L.N;
+        for (int i = tid; i < L.N; i += FUSE_THREADS) {
+            const float bs = fc.b_top[i];
+            b[i] = bs;
+            d0[i] = L.c2res * L.invd[i] * bs;
+        }
+        __syncthreads();
+    }
+    // descent
+    for (int l = 0; l < nl - 1; ++l) {
+        const FusedLv& L = fc.lv[l];
+        fz_step<DIM, MG_PRE1>(fc, L, lds, 0, L.c1[1], L.c2[1]);
+        for (int k = 2; k < m; ++k)
+            fz_step<DIM, MG_STEP>(fc, L, lds, (k - 1) & 1, L.c1[k], L.c2[k]);
+        fz_step<DIM, MG_LAST>(fc, L, lds, (m - 1) & 1, 0.0f, 0.0f);
+        // b_c = P^T r (h-transfer), and the coarse level's first direction
+        const FusedLv& C = fc.lv[l + 1];
+        const bool coarsest = l + 1 == nl - 1;
+        const float* rf = lds + L.off + L.N;
+        float* bc = lds + C.off + 2 * C.N;
+        float* dc = lds + C.off + 3 * C.N;
+        for (int gid = tid; gid < C.N; gid += FUSE_THREADS) {
+            const int Cc = gid / NB, J = gid % NB;
+            const int jx = J & 1, jy = (J >> 1) & 1, jz = (J >> 2) & 1;
+            const int cx = Cc % C.nc[0], cy = (Cc / C.nc[0]) % C.nc[1], cz = Cc / (C.nc[0] * C.nc[1]);
+            const int fnx = 2 * C.nc[0], fny = 2 * C.nc[1];
+            float acc = 0.0f;
+            for (int ch = 0; ch < NB; ++ch) {
+                const int bx = ch & 1, by = (ch >> 1) & 1, bz = (ch >> 2) & 1;
+                const int f = (2 * cx + bx) + fnx * ((2 * cy + by) + (DIM == 3 ? fny * (2 * cz + bz) : 0));
+                for (int I = 0; I < NB; ++I) {
+                    const int ix = I & 1, iy = (I >> 1) & 1, iz = (I >> 2) & 1;
+                    float w = fc.tt.T[bx][ix][jx] * fc.tt.T[by][iy][jy];
+                    if (DIM == 3) w *= fc.tt.T[bz][iz][jz];
+                    acc += w * rf[f * NB + I];
+                }
+            }
+            bc[gid] = acc;
+            if (!coarsest) dc[gid] = C.c2res * C.invd[gid] * acc;
+        }
+        __syncthreads();
+    }
+    // coarsest: x = H^{-1} b with the FP64 inverse, one wave per row
+    {
+        const FusedLv& C = fc.lv[nl - 1];
+        const float* b = lds + C.off + 2 * C.N;
+        float* x = lds + C.off;
+        const int lane = tid & 63, wv = tid >> 6;
+        for (int row = wv; row < C.N; row += FUSE_THREADS / 64) {
+            double acc = 0.0;
+            for (int j = lane; j < C.N; j += 64) acc += fc.ainv[(size_t)row * C.N + j] * (double)b[j];
+            acc = red::wave_sum(acc);
+            if (lane == 0) x[row] = (float)acc;
+        }
+        __syncthreads();
+    }
+    // ascent
+    int pend = -1;   // direction buffer of the level below not yet added to its x
+    for (int l = nl - 2; l >= 0; --l) {
+        const FusedLv& L = fc.lv[l];
+        const FusedLv& C = fc.lv[l + 1];
+        const float* xc = lds + C.off;
+        const float* dcp = pend >= 0 ? lds + C.off + (3 + pend) * C.N : nullptr;
+        float* xf = lds + L.off;
+        for (int gid = tid; gid < L.N; gid += FUSE_THREADS) {
+            const int c = gid / NB, I = gid % NB;
+            const int fx = c % L.nc[0], fy = (c / L.nc[0]) % L.nc[1], fzz = c / (L.nc[0] * L.nc[1]);
+            const int bx = fx & 1, by = fy & 1, bz = fzz & 1;
+            const int Cc = (fx >> 1) + C.nc[0] * ((fy >> 1) + (DIM == 3 ? C.nc[1] * (fzz >> 1) : 0));
+            const int ix = I & 1, iy = (I >> 1) & 1, iz = (I >> 2) & 1;
+            float acc = 0.0f;
+            for (int J = 0; J < NB; ++J) {
+                const int jx = J & 1, jy = (J >> 1) & 1, jz = (J >> 2) & 1;
+                float w = fc.tt.T[bx][ix][jx] * fc.tt.T[by][iy][jy];
+                if (DIM == 3) w *= fc.tt.T[bz][iz][jz];
+                const int ci = Cc * NB + J;
+                acc += w * (xc[ci] + (dcp ? dcp[ci] : 0.0f));
+            }
+            xf[gid] = xf[gid] + acc;
+        }
+        __syncthreads();
+        fz_step<DIM, MG_RES>(fc, L, lds, 0, 0.0f, L.c2res);
+        for (int k = 1; k < m; ++k)
+            fz_step<DIM, MG_STEP>(fc, L, lds, (k - 1) & 1, L.c1[k], L.c2[k]);
+        pend = (m - 1) & 1;
+    }
+    // top level out: x + d
+    {
+        const FusedLv& L = fc.lv[0];
+        const float* x = lds + L.off;
+        const float* d = lds + L.off + (3 + pend) * L.N;
+        for (int i = tid; i < L.N; i += FUSE_THREADS) fc.x_top[i] = x[i] + d[i];
+    }
+}
+
 // FP64 side of flexible CG.  With `update`: alpha = sc[slot] / (sum of the Ga
 // partials of p.q) (block 0 records it in sc[4], a non-positive p.q raises
 // sc[6]); x += alpha p; r -= alpha q.  Always: b0 = r rounded to the level-0
@@ -558,6 +774,26 @@ void launch_mg_beta(hipStream_t st, const double* partial, int G, double* sc, in
     hipLaunchKernelGGL(k_mg_beta, dim3(1), dim3(256), 0, st, partial, G, sc, first, slot,
                        slot_prev);
     TBDG_HIP(hipGetLastError());
+}
+
+void launch_fused_cycle(hipStream_t st, int dim, const FusedCycle& fc, size_t lds) {
+    if (dim == 2)
+        hipLaunchKernelGGL(k_fused_cycle<2>, dim3(1), dim3(FUSE_THREADS), lds, st, fc);
+    else
+        hipLaunchKernelGGL(k_fused_cycle<3>, dim3(1), dim3(FUSE_THREADS), lds, st, fc);
+    TBDG_HIP(hipGetLastError());
+}
+
+size_t fused_lds_limit(int dim) {
+    int dev = 0, v = 0;
+    TBDG_HIP(hipGetDevice(&dev));
+    TBDG_HIP(hipDeviceGetAttribute(&v, hipDeviceAttributeMaxSharedMemoryPerBlock, dev));
+    const void* fn = dim == 2 ? (const void*)k_fused_cycle<2> : (const void*)k_fused_cycle<3>;
+    if (hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, v) != hipSuccess) {
+        (void)hipGetLastError();
+        v = 65536 < v ? 65536 : v;
+    }
+    return (size_t)v;
 }
 
 void launch_vel_prep(hipStream_t st, int64_t Nc, int nb, int dim, int comp, const double* v,

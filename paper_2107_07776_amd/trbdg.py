@@ -26,7 +26,7 @@ EXPORTED = [
     "tbdg_solve_pressure_noalloc",
     "tbdg_step", "tbdg_profile_enable", "tbdg_profile_read", "tbdg_mg_setup",
     "tbdg_mg_levels", "tbdg_mg_apply", "tbdg_mg_apply_momentum", "tbdg_mg_levels_momentum",
-    "tbdg_set_mg_graphs",
+    "tbdg_set_mg_graphs", "tbdg_mg_fused",
     "tbdg_net_create", "tbdg_net_destroy",
     "tbdg_net_last_error", "tbdg_net_num_params", "tbdg_net_set_params", "tbdg_net_get_params",
     "tbdg_net_get_grads", "tbdg_net_zero_grad", "tbdg_net_forward", "tbdg_net_backward",
@@ -79,7 +79,7 @@ class SolverOpts(ctypes.Structure):
 class MGDesc(ctypes.Structure):
     _fields_ = [("degree", ctypes.c_int), ("lanczos_steps", ctypes.c_int), ("range", ctypes.c_double),
                 ("safety", ctypes.c_double), ("coarse_cells", ctypes.c_int),
-                ("max_coarse_dofs", ctypes.c_int)]
+                ("max_coarse_dofs", ctypes.c_int), ("no_fuse", ctypes.c_int)]
 
 
 class SolveInfo(ctypes.Structure):
@@ -138,6 +138,7 @@ def load_library(path=LIB_PATH):
         "tbdg_mg_apply_momentum": ([vp, i, vp, vp], i),
         "tbdg_mg_levels_momentum": ([vp, i, P(i), P(i64), P(d)], i),
         "tbdg_set_mg_graphs": ([vp, i], i),
+        "tbdg_mg_fused": ([vp, i, P(i), P(i64)], i),
         "tbdg_net_create": ([i, ctypes.c_uint64, vp, P(vp)], i),
         "tbdg_net_destroy": ([vp], None),
         "tbdg_net_last_error": ([vp], ctypes.c_char_p),
@@ -410,10 +411,11 @@ class Context:
         self._check(self.lib.tbdg_set_scheme(self.h, SCHEME[scheme]))
 
     def mg_setup(self, degree=0, lanczos_steps=0, range_=0.0, safety=0.0, coarse_cells=0,
-                 max_coarse_dofs=0):
-        """Build the pressure multigrid hierarchy (0 = library default)."""
+                 max_coarse_dofs=0, fuse=True):
+        """Build the pressure multigrid hierarchy (0 = library default; fuse:
+        the coarse Q1 levels in one single-workgroup launch per V-cycle)."""
         d = MGDesc(int(degree), int(lanczos_steps), float(range_), float(safety), int(coarse_cells),
-                   int(max_coarse_dofs))
+                   int(max_coarse_dofs), 0 if fuse else 1)
         self._check(self.lib.tbdg_mg_setup(self.h, ctypes.byref(d)))
 
     def mg_levels(self, cap=16, field="p"):
@@ -442,6 +444,15 @@ class Context:
         self._check(self.lib.tbdg_mg_apply_momentum(self.h, stage, _ptr(self._vec(v, self.N_u, "v")),
                                                     _ptr(z)))
         return z
+
+    def mg_fused(self, field="p"):
+        """(first level of the single-workgroup coarse cycle or -1, its LDS
+        bytes) of the pressure ("p") or momentum ("u") hierarchy."""
+        first = ctypes.c_int()
+        lds = ctypes.c_int64()
+        self._check(self.lib.tbdg_mg_fused(self.h, 0 if field == "p" else 1, ctypes.byref(first),
+                                           ctypes.byref(lds)))
+        return first.value, lds.value
 
     def set_mg_graphs(self, enable):
         """V-cycles inside the solves as HIP-graph replays (True, the

@@ -53,6 +53,7 @@ class MGPair:
         print(f"[case] multigrid dim={dim} cells={nc} k={k} coarse_cells={coarse}", flush=True)
         self.gpu = Context(dim, nc, (0.0,) * dim, ext, k=k, nu=nu, dt=dt)
         self.gpu.mg_setup(degree=3, coarse_cells=coarse)
+        self.gpu._coarse_cells = coarse
         mesh = BoxMesh(dim, nc, (0.0,) * dim, ext, (True,) * dim)
         self.disc = Discretization(mesh, k, nu=nu)
         self.ora = TRBDF2(self.disc, dt)
@@ -114,6 +115,38 @@ def test_mg_cg_meets_oracle_residual(mp, precision):
         ij = mp.gpu.solve_pressure(stage, mp.t(b), xj, tol=tol, maxiter=20000)
         print(f"{precision} stage {stage}: {info['iters']} iterations (Jacobi CG {ij['iters']})")
         assert 2 * info["iters"] < ij["iters"]
+
+
+@pytest.mark.parametrize("stage", [1, 2])
+def test_fused_coarse_cycle_matches_level_by_level(mp, stage):
+    """The coarse Q1 levels run in one single-workgroup launch (default) or
+    level by level: the same V-cycle to FP32 rounding, both within the
+    oracle bound."""
+    from paper_2107_07776_amd import Context
+    g = mp.gpu
+    first, lds = g.mg_fused()
+    nl = len(g.mg_levels())
+    if nl < 3:     # a single level below level 0: nothing to fuse
+        assert (first, lds) == (-1, 0)
+        return
+    assert 1 <= first <= nl - 2 and lds > 0, (first, lds, nl)
+    d = mp.disc
+    ext = tuple(h - l for l, h in zip(d.mesh.lo, d.mesh.hi))
+    ref = Context(d.dim, tuple(d.mesh.n_cells), (0.0,) * d.dim, ext, k=d.k, nu=d.nu, dt=mp.ora.dt)
+    try:
+        ref.mg_setup(degree=3, coarse_cells=g._coarse_cells, fuse=False)
+        assert ref.mg_fused() == (-1, 0)
+        for seed in range(3):
+            r = synthetic.random_vector(d.N_p, 320 + 10 * stage + seed)
+            zf = mp.h(g.mg_apply(stage, mp.t(r)))
+            zl = mp.h(ref.mg_apply(stage, mp.t(r)))
+            zo = mp.mg[stage].vcycle(r)
+            scale = np.abs(zo).max()
+            print(f"fused vs level-by-level stage {stage}: {np.abs(zf - zl).max() / scale:.3e}")
+            assert np.abs(zf - zl).max() <= 50 * 2.0 ** -24 * scale
+            assert np.abs(zf - zo).max() <= TOL_VC32 * scale
+    finally:
+        ref.close()
 
 
 def test_single_level_mesh_is_rejected():
