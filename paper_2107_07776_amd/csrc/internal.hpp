@@ -190,14 +190,15 @@ struct MGLevel {
 // stage-s momentum operator on each component.
 // The coarse end of a V-cycle run by one workgroup: the Q1 levels from some
 // level below level 0 down to the coarsest, every vector resident in LDS
-// (5 FP32 vectors per smoothing level, 2 on the coarsest), the same smoother,
+// (x, r, b, two directions and the inverse diagonal: 6 FP32 vectors per
+// level), the same smoother,
 // transfers and dense FP64 coarse solve as the level-by-level launches.
 // Filled per stage by the host; passed by value.
 constexpr int FUSE_MAXLV = 8;
 constexpr int FUSE_THREADS = 1024;
 struct FusedLv {
     int nc[3];
-    int Nc, N, off;             // cells, DoFs, float offset of x (r, b, d0, d1 follow)
+    int Nc, N, off;             // cells, DoFs, float offset of x (r, b, d0, d1, invd follow)
     float sdiff[3], cm, c2res;  // cm = alpha_s |K|; c2res = 1 / theta_s (residual step)
     float c1[MG_MAXDEG], c2[MG_MAXDEG];
     const float* invd;          // stage-s inverse diagonal (global)

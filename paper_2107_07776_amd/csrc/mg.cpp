@@ -308,7 +308,7 @@ FusedCycle fused_desc(const MGData& M, int s) {
         F.Nc = (int)L.Nc;
         F.N = (int)L.N;
         F.off = off;
-        off += 5 * F.N;
+        off += 6 * F.N;
         F.cm = L.tf.cm[s];
         F.c2res = i + 1 < fc.nlev ? (float)(1.0 / L.theta[s]) : 0.0f;
         for (int k = 0; k < MG_MAXDEG; ++k) {
@@ -530,7 +530,7 @@ void mg_build(tbdg_ctx* c, MGData& M, const tbdg_mg_desc* desc) {
         for (int l = nl - 1; l >= 1 && nl - l <= FUSE_MAXLV; --l) {
             const MGLevel& L = M.lv[l];
             if (L.np != 2 || (l < nl - 1 && L.transfer != 2)) break;
-            const size_t add = 5 * sizeof(float) * (size_t)L.N;
+            const size_t add = 6 * sizeof(float) * (size_t)L.N;
             if (bytes + add > lim) break;
             bytes += add;
             from = l;

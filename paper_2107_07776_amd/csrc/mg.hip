@@ -326,62 +326,99 @@ __device__ inline int fz_nbr(const int* nc, const int* per, const int* ci, int c
     return ci[a] < nc[a] - 1 ? cell + stride : (per[a] ? cell - (nc[a] - 1) * stride : -1);
 }
 
-// (H p) at node nd of a cell of a Q1 level in LDS
+// threads of the single-workgroup cycle: 1024 in 2D; 512 in 3D, where a
+// cell's eight nodes need twice the registers
 template <int DIM>
-__device__ float fz_apply(const FusedCycle& fc, const FusedLv& L, const float* p, int cell, int nd) {
+constexpr int fz_threads() { return DIM == 2 ? FUSE_THREADS : FUSE_THREADS / 2; }
+
+// the NB = 2^DIM values of one cell of a Q1 level in LDS (16-byte loads)
+template <int DIM>
+__device__ inline void fz_load(const float* p, int cell, float* v) {
+    constexpr int NB = 1 << DIM;
+    const float4* q = reinterpret_cast<const float4*>(p + cell * NB);
+#pragma unroll
+    for (int k = 0; k < NB / 4; ++k) {
+        const float4 t = q[k];
+        v[4 * k] = t.x;
+        v[4 * k + 1] = t.y;
+        v[4 * k + 2] = t.z;
+        v[4 * k + 3] = t.w;
+    }
+}
+
+// y = (H p) at the NB nodes of one cell of a Q1 level in LDS: the per-node
+// arithmetic of k_level, each line's neighbour traces formed once per cell
+template <int DIM>
+__device__ void fz_apply(const FusedCycle& fc, const FusedLv& L, const float* p, int cell, float* y) {
     constexpr int NB = 1 << DIM;
     int ci[3] = {0, 0, 0};
     int rr = cell;
+#pragma unroll
     for (int a = 0; a < DIM; ++a) {
         ci[a] = rr % L.nc[a];
         rr /= L.nc[a];
     }
-    float wn = 1.0f;
-    for (int a = 0; a < DIM; ++a) wn *= fc.W[(nd >> a) & 1];
-    float y = L.cm * wn * p[cell * NB + nd];
+    float pv[NB];
+    fz_load<DIM>(p, cell, pv);
+#pragma unroll
+    for (int n = 0; n < NB; ++n) {
+        float wn = 1.0f;
+#pragma unroll
+        for (int a = 0; a < DIM; ++a) wn *= fc.W[(n >> a) & 1];
+        y[n] = L.cm * wn * pv[n];
+    }
+#pragma unroll
     for (int a = 0; a < DIM; ++a) {
-        const int ia = (nd >> a) & 1;
-        const int n0 = nd & ~(1 << a), n1 = nd | (1 << a);   // the line's two nodes
-        const float pp0 = p[cell * NB + n0], pp1 = p[cell * NB + n1];
-        const float p0 = fc.L0[0] * pp0 + fc.L0[1] * pp1;
-        const float p1 = fc.L1[0] * pp0 + fc.L1[1] * pp1;
         const int lf = fz_nbr<DIM>(L.nc, fc.periodic, ci, cell, a, 0);
         const int rt = fz_nbr<DIM>(L.nc, fc.periodic, ci, cell, a, 1);
-        float X0, Y0, X1, Y1;
-        if (lf >= 0) {
-            const float v0 = p[lf * NB + n0], v1 = p[lf * NB + n1];
-            const float v = fc.L1[0] * v0 + fc.L1[1] * v1;
-            const float d = fc.dL1[0] * v0 + fc.dL1[1] * v1;
-            X0 = 0.5f * d - fc.Cr * v;
-            Y0 = 0.5f * v;
-        } else {
-            const float q0 = fc.dL0[0] * pp0 + fc.dL0[1] * pp1;
-            X0 = fc.wall * (0.5f * q0 + fc.Cr * p0);
-            Y0 = -fc.wall * 0.5f * p0;
+        float pl[NB], pr[NB];
+        if (lf >= 0) fz_load<DIM>(p, lf, pl);
+        if (rt >= 0) fz_load<DIM>(p, rt, pr);
+#pragma unroll
+        for (int n0 = 0; n0 < NB; ++n0) {
+            if ((n0 >> a) & 1) continue;        // one line per node with coordinate a = 0
+            const int n1 = n0 | (1 << a);
+            const float pp0 = pv[n0], pp1 = pv[n1];
+            const float p0 = fc.L0[0] * pp0 + fc.L0[1] * pp1;
+            const float p1 = fc.L1[0] * pp0 + fc.L1[1] * pp1;
+            float X0, Y0, X1, Y1;
+            if (lf >= 0) {
+                const float v = fc.L1[0] * pl[n0] + fc.L1[1] * pl[n1];
+                const float d = fc.dL1[0] * pl[n0] + fc.dL1[1] * pl[n1];
+                X0 = 0.5f * d - fc.Cr * v;
+                Y0 = 0.5f * v;
+            } else {
+                const float q0 = fc.dL0[0] * pp0 + fc.dL0[1] * pp1;
+                X0 = fc.wall * (0.5f * q0 + fc.Cr * p0);
+                Y0 = -fc.wall * 0.5f * p0;
+            }
+            if (rt >= 0) {
+                const float v = fc.L0[0] * pr[n0] + fc.L0[1] * pr[n1];
+                const float d = fc.dL0[0] * pr[n0] + fc.dL0[1] * pr[n1];
+                X1 = -0.5f * d - fc.Cr * v;
+                Y1 = 0.5f * v;
+            } else {
+                const float q1 = fc.dL1[0] * pp0 + fc.dL1[1] * pp1;
+                X1 = fc.wall * (fc.Cr * p1 - 0.5f * q1);
+                Y1 = -fc.wall * 0.5f * p1;
+            }
+            float wt = 1.0f;
+#pragma unroll
+            for (int e = 0; e < DIM; ++e)
+                if (e != a) wt *= fc.W[(n0 >> e) & 1];
+            const float sd = L.sdiff[a] * wt;
+#pragma unroll
+            for (int ia = 0; ia < 2; ++ia) {
+                float sl = fc.A[ia * 2] * pp0 + fc.A[ia * 2 + 1] * pp1;
+                sl += fc.L0[ia] * X0 - fc.dL0[ia] * Y0 + fc.L1[ia] * X1 + fc.dL1[ia] * Y1;
+                y[ia ? n1 : n0] += sd * sl;
+            }
         }
-        if (rt >= 0) {
-            const float v0 = p[rt * NB + n0], v1 = p[rt * NB + n1];
-            const float v = fc.L0[0] * v0 + fc.L0[1] * v1;
-            const float d = fc.dL0[0] * v0 + fc.dL0[1] * v1;
-            X1 = -0.5f * d - fc.Cr * v;
-            Y1 = 0.5f * v;
-        } else {
-            const float q1 = fc.dL1[0] * pp0 + fc.dL1[1] * pp1;
-            X1 = fc.wall * (fc.Cr * p1 - 0.5f * q1);
-            Y1 = -fc.wall * 0.5f * p1;
-        }
-        float wt = 1.0f;
-        for (int e = 0; e < DIM; ++e)
-            if (e != a) wt *= fc.W[(nd >> e) & 1];
-        float sl = fc.A[ia * 2] * pp0 + fc.A[ia * 2 + 1] * pp1;
-        sl += fc.L0[ia] * X0 - fc.dL0[ia] * Y0 + fc.L1[ia] * X1 + fc.dL1[ia] * Y1;
-        y += L.sdiff[a] * wt * sl;
     }
-    return y;
 }
 
-// one smoother step (modes of k_level) on a level in LDS; returns after the
-// block barrier
+// one smoother step (modes of k_level) on a level in LDS, one thread per
+// cell; returns after the block barrier
 template <int DIM, int MODE>
 __device__ void fz_step(const FusedCycle& fc, const FusedLv& L, float* lds, int din, float c1,
                         float c2) {
@@ -390,48 +427,60 @@ __device__ void fz_step(const FusedCycle& fc, const FusedLv& L, float* lds, int 
     float* r = x + L.N;
     const float* b = x + 2 * L.N;
     float* d[2] = {x + 3 * L.N, x + 4 * L.N};
+    const float* invd = x + 5 * L.N;
     const float* op = MODE == MG_RES ? x : d[din];
     float* dout = MODE == MG_RES ? d[0] : d[din ^ 1];
-    for (int i = threadIdx.x; i < L.N; i += FUSE_THREADS) {
-        const int cell = i / NB, nd = i % NB;
-        const float y = fz_apply<DIM>(fc, L, op, cell, nd);
-        const float pown = op[i];
-        const float id = MODE == MG_LAST ? 0.0f : L.invd[i];
-        if (MODE == MG_PRE1) {
-            x[i] = pown;
-            const float rn = b[i] - y;
-            r[i] = rn;
-            dout[i] = c1 * pown + c2 * id * rn;
-        } else if (MODE == MG_STEP) {
-            x[i] = x[i] + pown;
-            const float rn = r[i] - y;
-            r[i] = rn;
-            dout[i] = c1 * pown + c2 * id * rn;
-        } else if (MODE == MG_LAST) {
-            x[i] = x[i] + pown;
-            r[i] = r[i] - y;
-        } else {   // MG_RES
-            const float rn = b[i] - y;
-            r[i] = rn;
-            dout[i] = c2 * id * rn;
+    for (int cell = threadIdx.x; cell < L.Nc; cell += fz_threads<DIM>()) {
+        float y[NB];
+        fz_apply<DIM>(fc, L, op, cell, y);
+#pragma unroll
+        for (int n = 0; n < NB; ++n) {
+            const int i = cell * NB + n;
+            const float pown = op[i];
+            const float id = MODE == MG_LAST ? 0.0f : invd[i];
+            if (MODE == MG_PRE1) {
+                x[i] = pown;
+                const float rn = b[i] - y[n];
+                r[i] = rn;
+                dout[i] = c1 * pown + c2 * id * rn;
+            } else if (MODE == MG_STEP) {
+                x[i] = x[i] + pown;
+                const float rn = r[i] - y[n];
+                r[i] = rn;
+                dout[i] = c1 * pown + c2 * id * rn;
+            } else if (MODE == MG_LAST) {
+                x[i] = x[i] + pown;
+                r[i] = r[i] - y[n];
+            } else {   // MG_RES
+                const float rn = b[i] - y[n];
+                r[i] = rn;
+                dout[i] = c2 * id * rn;
+            }
         }
     }
     __syncthreads();
 }
 
 template <int DIM>
-__global__ __launch_bounds__(FUSE_THREADS) void k_fused_cycle(FusedCycle fc) {
+__global__ __launch_bounds__(fz_threads<DIM>()) void k_fused_cycle(FusedCycle fc) {
+    constexpr int NT = fz_threads<DIM>();
     extern __shared__ float lds[];
     constexpr int NB = 1 << DIM;
     const int tid = threadIdx.x;
     const int m = fc.degree;
     const int nl = fc.nlev;
+    // the smoothing levels' inverse diagonals, read every step, into LDS
+    for (int l = 0; l < nl - 1; ++l) {
+        const FusedLv& L = fc.lv[l];
+        float* dst = lds + L.off + 5 * L.N;
+        for (int i = tid; i < L.N; i += NT) dst[i] = L.invd[i];
+    }
     // top level: right-hand side and first direction
     {
         const FusedLv& L = fc.lv[0];
         float* b = lds + L.off + 2 * L.N;
         float* d0 = lds + L.off + 3 * L.N;
-        for (int i = tid; i < L.N; i += FUSE_THREADS) {
+        for (int i = tid; i < L.N; i += NT) {
             const float bs = fc.b_top[i];
             b[i] = bs;
             d0[i] = L.c2res * L.invd[i] * bs;
@@ -451,7 +500,7 @@ __global__ __launch_bounds__(FUSE_THREADS) void k_fused_cycle(FusedCycle fc) {
         const float* rf = lds + L.off + L.N;
         float* bc = lds + C.off + 2 * C.N;
         float* dc = lds + C.off + 3 * C.N;
-        for (int gid = tid; gid < C.N; gid += FUSE_THREADS) {
+        for (int gid = tid; gid < C.N; gid += NT) {
             const int Cc = gid / NB, J = gid % NB;
             const int jx = J & 1, jy = (J >> 1) & 1, jz = (J >> 2) & 1;
             const int cx = Cc % C.nc[0], cy = (Cc / C.nc[0]) % C.nc[1], cz = Cc / (C.nc[0] * C.nc[1]);
@@ -468,7 +517,7 @@ __global__ __launch_bounds__(FUSE_THREADS) void k_fused_cycle(FusedCycle fc) {
                 }
             }
             bc[gid] = acc;
-            if (!coarsest) dc[gid] = C.c2res * C.invd[gid] * acc;
+            if (!coarsest) dc[gid] = C.c2res * lds[C.off + 5 * C.N + gid] * acc;
         }
         __syncthreads();
     }
@@ -478,7 +527,7 @@ __global__ __launch_bounds__(FUSE_THREADS) void k_fused_cycle(FusedCycle fc) {
         const float* b = lds + C.off + 2 * C.N;
         float* x = lds + C.off;
         const int lane = tid & 63, wv = tid >> 6;
-        for (int row = wv; row < C.N; row += FUSE_THREADS / 64) {
+        for (int row = wv; row < C.N; row += NT / 64) {
             double acc = 0.0;
             for (int j = lane; j < C.N; j += 64) acc += fc.ainv[(size_t)row * C.N + j] * (double)b[j];
             acc = red::wave_sum(acc);
@@ -494,7 +543,7 @@ __global__ __launch_bounds__(FUSE_THREADS) void k_fused_cycle(FusedCycle fc) {
         const float* xc = lds + C.off;
         const float* dcp = pend >= 0 ? lds + C.off + (3 + pend) * C.N : nullptr;
         float* xf = lds + L.off;
-        for (int gid = tid; gid < L.N; gid += FUSE_THREADS) {
+        for (int gid = tid; gid < L.N; gid += NT) {
             const int c = gid / NB, I = gid % NB;
             const int fx = c % L.nc[0], fy = (c / L.nc[0]) % L.nc[1], fzz = c / (L.nc[0] * L.nc[1]);
             const int bx = fx & 1, by = fy & 1, bz = fzz & 1;
@@ -521,7 +570,7 @@ __global__ __launch_bounds__(FUSE_THREADS) void k_fused_cycle(FusedCycle fc) {
         const FusedLv& L = fc.lv[0];
         const float* x = lds + L.off;
         const float* d = lds + L.off + (3 + pend) * L.N;
-        for (int i = tid; i < L.N; i += FUSE_THREADS) fc.x_top[i] = x[i] + d[i];
+        for (int i = tid; i < L.N; i += NT) fc.x_top[i] = x[i] + d[i];
     }
 }
 
@@ -778,9 +827,9 @@ void launch_mg_beta(hipStream_t st, const double* partial, int G, double* sc, in
 
 void launch_fused_cycle(hipStream_t st, int dim, const FusedCycle& fc, size_t lds) {
     if (dim == 2)
-        hipLaunchKernelGGL(k_fused_cycle<2>, dim3(1), dim3(FUSE_THREADS), lds, st, fc);
+        hipLaunchKernelGGL(k_fused_cycle<2>, dim3(1), dim3(fz_threads<2>()), lds, st, fc);
     else
-        hipLaunchKernelGGL(k_fused_cycle<3>, dim3(1), dim3(FUSE_THREADS), lds, st, fc);
+        hipLaunchKernelGGL(k_fused_cycle<3>, dim3(1), dim3(fz_threads<3>()), lds, st, fc);
     TBDG_HIP(hipGetLastError());
 }
 
