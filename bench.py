@@ -435,7 +435,7 @@ def main():
     ap.add_argument("--no-compare", action="store_true",
                     help="skip the plain FP64 (Jacobi) reference run")
     ap.add_argument("--no-bf16", action="store_true", help="skip the BF16-smoother run")
-    ap.add_argument("--guess", default=None, choices=["given", "previous", "learned", "extrap2"],
+    ap.add_argument("--guess", default=None, choices=["given", "previous", "learned", "extrap2", "extrap3"],
                     help="initial guess of the timed solver's pressure solves (default: learned "
                          "where the network is built, else previous)")
     ap.add_argument("--no-learned", action="store_true",
@@ -519,7 +519,9 @@ def main():
         "learned": "learned (3D CNN, bf16 MFMA) guess, previous pressure + the same stage's last "
                    "increment as fallback, the smaller FP64 residual decides",
         "extrap2": "previous pressure + the same stage's increment extrapolated linearly from its "
-                   "last two values"}
+                   "last two values",
+        "extrap3": "previous pressure + the same stage's increment extrapolated quadratically from "
+                   "its last three values"}
     out = {"metric": METRIC, "value": main_run["sps"], "unit": "steps/s", "n_gpus": 1,
            "steps": args.steps, "warmup": args.warmup, "ms_per_step": main_run["ms"],
            "higher_is_better": True, "scaling": "strong", "vs_baseline": None, "dtype": "f64",

@@ -185,7 +185,9 @@ enum {
     TBDG_GUESS_GIVEN = 0,       /* the content of x_inout (in tbdg_step: the previous pressure) */
     TBDG_GUESS_PREVIOUS = 1,    /* tbdg_step only: previous pressure + same stage's last increment */
     TBDG_GUESS_LEARNED = 2,     /* tbdg_step only: the guess network, TBDG_GUESS_PREVIOUS as fallback */
-    TBDG_GUESS_EXTRAP2 = 3      /* tbdg_step only: previous pressure + 2 inc_2 - inc_4 (pressure only) */
+    TBDG_GUESS_EXTRAP2 = 3,     /* tbdg_step only: previous pressure + 2 inc_2 - inc_4 (pressure only) */
+    TBDG_GUESS_EXTRAP3 = 4      /* tbdg_step only: previous pressure + 3 inc_2 - 3 inc_4 + inc_6
+                                   (pressure only)                                               */
 };
 enum {
     TBDG_PRECOND_JACOBI = 0,
@@ -385,14 +387,15 @@ TBDG_API tbdg_status tbdg_net_quad_loss(tbdg_net* net, const float* yhat, const 
 TBDG_API tbdg_status tbdg_net_adam_step(tbdg_net* net, float lr, float beta1, float beta2, float eps);
 
 /* Initial guesses of the Helmholtz solves in tbdg_step (not part of the
- * paper).  The context keeps the four newest pressure increments
+ * paper).  The context keeps the six newest pressure increments
  * p_new - p_prev of its solves; for the stage-s solve with right-hand side b
- * and previous pressure p, d1 and d2 are the same stage's increments of the
- * last two steps and d0 the newest increment (the other stage's, weight
- * beta0).  With <a, c>_K = sum_{i in K} W_i a_i c_i (W_i the product of the
+ * and previous pressure p, d1, d2 and d3 are the same stage's increments of
+ * the last three steps and d0 the newest increment (the other stage's,
+ * weight beta0).  With <a, c>_K = sum_{i in K} W_i a_i c_i (W_i the product of the
  * Gauss weights of node i on the unit cell):
  *   TBDG_GUESS_PREVIOUS: p + d1 (the fallback);
  *   TBDG_GUESS_EXTRAP2:  p + 2 d1 - d2;
+ *   TBDG_GUESS_EXTRAP3:  p + 3 d1 - 3 d2 + d3;
  *   TBDG_GUESS_LEARNED:  per cell K the network input is (m1 / s_inc,
  *     m2 / s_inc, m0 / s_inc, div / s_div, cos_K, lr_K) with
  *     m1 = <d1, 1>_K / (beta_s dt), m2 = <d2, 1>_K / (beta_s dt),

@@ -134,7 +134,7 @@ tbdg_solver_opts defaults(const tbdg_solver_opts* o) {
     require(r.restart >= 0 && r.restart <= GMRES_MAX, "GMRES restart must be in [0, 60]");
     require(r.precond >= TBDG_PRECOND_JACOBI && r.precond <= TBDG_PRECOND_LINE,
             "unknown preconditioner");
-    require(r.guess >= TBDG_GUESS_GIVEN && r.guess <= TBDG_GUESS_EXTRAP2, "unknown initial guess");
+    require(r.guess >= TBDG_GUESS_GIVEN && r.guess <= TBDG_GUESS_EXTRAP3, "unknown initial guess");
     return r;
 }
 
@@ -687,7 +687,8 @@ tbdg_status tbdg_step(tbdg_ctx* c, tbdg_state* state, const tbdg_solver_opts* mo
             throw Error(TBDG_EUNSUPPORTED, "the momentum solve takes the Jacobi, line or FP32 multigrid preconditioner");
         if (po.precond == TBDG_PRECOND_LINE)
             throw Error(TBDG_EUNSUPPORTED, "the line preconditioner applies to the momentum solve");
-        require(mo.guess != TBDG_GUESS_LEARNED && mo.guess != TBDG_GUESS_EXTRAP2,
+        require(mo.guess != TBDG_GUESS_LEARNED && mo.guess != TBDG_GUESS_EXTRAP2 &&
+                    mo.guess != TBDG_GUESS_EXTRAP3,
                 "the momentum solve takes the given or the extrapolated guess");
         if (c->scheme != TBDG_SCHEME_TRBDF2 && po.guess == TBDG_GUESS_LEARNED)
             throw Error(TBDG_EUNSUPPORTED, "the learned guess is built for the two TR-BDF2 stages");

@@ -42,7 +42,7 @@ void fill_state(tbdg_ctx* c, GuessState* g) {
         g->allocs.push_back(p);
         return static_cast<float*>(p);
     };
-    for (int i = 0; i < 4; ++i) g->inc[i] = dal(c->Np);
+    for (int i = 0; i < GuessState::kHist; ++i) g->inc[i] = dal(c->Np);
     g->cells = dal(7 * c->Nc);
     g->partial = dal(2 * c->Nc + 2);   // two partials per block of at least one cell
     g->sc = dal(8);
@@ -100,7 +100,7 @@ int guess_prepare(tbdg_ctx* c, int s, int mode, const double* b, const double* p
     const bool recording = two_stage && c->gs && c->gs->rec && c->gs->rec_count < c->gs->rec_cap;
     // the same stage's increments one and two steps back: every other entry
     // of the history with two stages per step, consecutive entries with one
-    const int lag1 = two_stage ? 1 : 0, lag2 = two_stage ? 3 : 1;
+    const int lag1 = two_stage ? 1 : 0, lag2 = two_stage ? 3 : 1, lag3 = two_stage ? 5 : 2;
     if (mode == 0 && !recording) {
         TBDG_HIP(hipMemcpyAsync(x, p_prev, bp, hipMemcpyDeviceToDevice, c->stream));
         return 0;
@@ -119,7 +119,15 @@ int guess_prepare(tbdg_ctx* c, int s, int mode, const double* b, const double* p
         TBDG_HIP(hipMemcpyAsync(x, p_prev, bp, hipMemcpyDeviceToDevice, c->stream));
         return 0;
     }
-    if (mode == TBDG_GUESS_EXTRAP2 && g.n > lag2) {
+    if (mode == TBDG_GUESS_EXTRAP3 && g.n > lag3) {
+        // quadratic extrapolation of the same stage's increment from its last
+        // three values: p + 3 inc[lag1] - 3 inc[lag2] + inc[lag3]
+        vec_axpby(c->stream, c->Np, 3.0, g.inc[lag1], -3.0, g.inc[lag2], x);
+        vec_axpby(c->stream, c->Np, 1.0, g.inc[lag3], 1.0, x, x);
+        vec_axpby(c->stream, c->Np, 1.0, p_prev, 1.0, x, x);
+        return TBDG_GUESS_EXTRAP3;
+    }
+    if ((mode == TBDG_GUESS_EXTRAP2 || mode == TBDG_GUESS_EXTRAP3) && g.n > lag2) {
         // the same stage's increment extrapolated linearly from its last two
         // values: p + 2 inc[lag1] - inc[lag2]
         vec_axpby(c->stream, c->Np, 2.0, g.inc[lag1], -1.0, g.inc[lag2], x);
@@ -160,15 +168,16 @@ void guess_after_solve(tbdg_ctx* c, int s, const double* p_new, const double* p_
         ++g.rec_count;
     }
     g.feat_valid = false;
-    double* oldest = g.inc[3];
-    for (int i = 3; i > 0; --i) {
+    constexpr int H = GuessState::kHist;
+    double* oldest = g.inc[H - 1];
+    for (int i = H - 1; i > 0; --i) {
         g.inc[i] = g.inc[i - 1];
         g.beta[i] = g.beta[i - 1];
     }
     g.inc[0] = oldest;
     vec_axpby(c->stream, c->Np, 1.0, p_new, -1.0, p_prev, g.inc[0]);
     g.beta[0] = c->beta[s];
-    g.n = g.n < 4 ? g.n + 1 : 4;
+    g.n = g.n < H ? g.n + 1 : H;
 }
 
 }  // namespace trbdg

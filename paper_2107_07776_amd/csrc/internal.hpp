@@ -246,10 +246,12 @@ struct MGData {
 // Learned / extrapolated initial guesses of the Helmholtz solves in a step.
 struct GuessState {
     tbdg_net* net = nullptr;
-    // newest pressure increments, inc[0] the newest: inc[0], inc[2] of the
-    // stage solved last, inc[1], inc[3] of the other stage (one step apart)
-    double* inc[4] = {nullptr, nullptr, nullptr, nullptr};
-    double beta[4] = {0.0, 0.0, 0.0, 0.0}; // stage weights of those solves
+    // newest pressure increments, inc[0] the newest: inc[0], inc[2], inc[4]
+    // of the stage solved last, inc[1], inc[3], inc[5] of the other stage
+    // (one step apart)
+    static constexpr int kHist = 6;
+    double* inc[kHist] = {nullptr, nullptr, nullptr, nullptr, nullptr, nullptr};
+    double beta[kHist] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0}; // stage weights of those solves
     int n = 0;                              // valid increments
     double* cells = nullptr;               // cell statistics [7][Nc] (also the Gram rows)
     double* partial = nullptr;
@@ -399,8 +401,9 @@ void ensure_mom_blk(tbdg_ctx* c);   // allocates c->mom_blk on first use
 // operator's diagonal) and returns the diagonal the blocks were built with,
 // which the apply takes: c->diag_u, or on mapped cells the box diagonal
 const double* build_mom_lineprec(tbdg_ctx* c, int s, const double* w);
+// z = P^{-1} (s v) (s = *scale when given); with accumulate z += P^{-1} (s v)
 void launch_mom_lineprec(const tbdg_ctx* c, const float* blk, const double* d, const double* v,
-                         const double* scale, double* z);
+                         const double* scale, double* z, bool accumulate = false);
 // sum-factorised Helmholtz right-hand side
 void launch_rhs_p_lines(const tbdg_ctx* c, double alpha, double fcoef, const double* u_ss,
                         const double* p_prev, double* rhs);
@@ -640,7 +643,8 @@ void mg_apply(tbdg_ctx* c, int stage, int precision, const double* r, double* z)
 // (one FP32 V-cycle each), s = *sc_dev when given, else 1
 void mgu_ensure(tbdg_ctx* c);
 void mgu_free(tbdg_ctx* c);
-void mg_apply_velocity(tbdg_ctx* c, int stage, const double* v, const double* sc_dev, double* z);
+void mg_apply_velocity(tbdg_ctx* c, int stage, const double* v, const double* sc_dev, double* z,
+                       bool accumulate = false);
 tbdg_status solve_pressure_mg(tbdg_ctx* c, int s, const double* b, double* x,
                               const tbdg_solver_opts& o, tbdg_solve_info* info);
 

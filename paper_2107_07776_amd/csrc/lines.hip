@@ -609,7 +609,7 @@ __global__ __launch_bounds__(256) void k_mom_lineprec(const float* __restrict__ 
                                                        const double* __restrict__ d,
                                                        const double* __restrict__ v,
                                                        const double* __restrict__ scale,
-                                                       double* __restrict__ z, int Nc) {
+                                                       double* __restrict__ z, int Nc, int acc) {
     using L = Lay<DIM, N>;
     using F = FaceLay<DIM, N>;
     constexpr int NB = F::NB, NF = F::NF, CPB = F::CPB;
@@ -661,7 +661,10 @@ __global__ __launch_bounds__(256) void k_mom_lineprec(const float* __restrict__ 
     }
     if (active) {
 #pragma unroll
-        for (int c = 0; c < DIM; ++c) z[((size_t)cell * DIM + c) * NB + nd] = s_v[c][pi];
+        for (int c = 0; c < DIM; ++c) {
+            const size_t gi = ((size_t)cell * DIM + c) * NB + nd;
+            z[gi] = acc ? z[gi] + s_v[c][pi] : s_v[c][pi];
+        }
     }
 }
 
@@ -1378,12 +1381,13 @@ void launch_mom_lineblk(const tbdg_ctx* c, int st, const double* w, const double
 }
 
 void launch_mom_lineprec(const tbdg_ctx* c, const float* blk, const double* d, const double* v,
-                         const double* scale, double* z) {
+                         const double* scale, double* z, bool accumulate) {
 #define L_(D, N)                                                                           \
     {                                                                                      \
         using FL = FaceLay<D, N>;                                                          \
         hipLaunchKernelGGL((k_mom_lineprec<D, N>), dim3(nblk(c->Nc, FL::CPB)),              \
-                           dim3(FL::THREADS), 0, c->stream, blk, d, v, scale, z, (int)c->Nc); \
+                           dim3(FL::THREADS), 0, c->stream, blk, d, v, scale, z, (int)c->Nc, \
+                           accumulate ? 1 : 0);                                            \
     }
     TBDG_LINE_DISPATCH(c, L_);
 #undef L_

@@ -648,7 +648,8 @@ void mgu_ensure(tbdg_ctx* c) {
 // theta_s nu H_0 of the velocity hierarchy: z_comp = H_0^{-1} (s v_comp) /
 // (theta_s nu), one FP32 V-cycle per component into the hierarchy's own
 // velocity-layout buffer (a fixed graph output), then one copy to z.
-void mg_apply_velocity(tbdg_ctx* c, int s, const double* v, const double* sc_dev, double* z) {
+void mg_apply_velocity(tbdg_ctx* c, int s, const double* v, const double* sc_dev, double* z,
+                       bool accumulate) {
     mgu_ensure(c);
     MGData& M = *c->mgu;
     MGLevel& L = M.lv[0];
@@ -659,7 +660,8 @@ void mg_apply_velocity(tbdg_ctx* c, int s, const double* v, const double* sc_dev
         launch_vel_prep(c->stream, L.Nc, nb, c->dim, d, v, sc_dev, scale, L.b, L.d[0], L.invd[s], c2);
         run_cycle(c, M, s, 1, ZOut{M.z + (int64_t)d * nb, c->dim * nb, nullptr, nullptr, nullptr}, true);
     }
-    TBDG_HIP(hipMemcpyAsync(z, M.z, sizeof(double) * M.n0 * c->dim, hipMemcpyDeviceToDevice, c->stream));
+    if (accumulate) vec_axpby(c->stream, M.n0 * c->dim, 1.0, z, 1.0, M.z, z);
+    else TBDG_HIP(hipMemcpyAsync(z, M.z, sizeof(double) * M.n0 * c->dim, hipMemcpyDeviceToDevice, c->stream));
 }
 
 void mg_apply(tbdg_ctx* c, int s, int precision, const double* r, double* z) {

@@ -97,9 +97,9 @@ tbdg_status solve_momentum(tbdg_ctx* c, int s, const double* w, const double* b,
     vec_recip(c->stream, c->Ns, c->diag_u, c->invd_u);
     const double* dprec = line ? build_mom_lineprec(c, s, w) : nullptr;
     if (mgp) mgu_ensure(c);
-    auto apply_pc = [&](const double* in, const double* sc_dev, double* out) {
-        if (line) launch_mom_lineprec(c, c->mom_blk, dprec, in, sc_dev, out);
-        else mg_apply_velocity(c, s, in, sc_dev, out);
+    auto apply_pc = [&](const double* in, const double* sc_dev, double* out, bool acc) {
+        if (line) launch_mom_lineprec(c, c->mom_blk, dprec, in, sc_dev, out, acc);
+        else mg_apply_velocity(c, s, in, sc_dev, out, acc);
     };
     const double bnorm = norm2(c, n, b);
     tbdg_solve_info inf{0, 0.0, 0.0, 0};
@@ -172,7 +172,7 @@ tbdg_status solve_momentum(tbdg_ctx* c, int s, const double* w, const double* b,
                        c->gm_part, nullptr};
             const double* opnd = vj;
             if (pc) {
-                apply_pc(vj, gsc + j, c->gz);
+                apply_pc(vj, gsc + j, c->gz, false);
                 opnd = c->gz;
                 fz.invd = nullptr;
                 fz.shv = vj;
@@ -240,8 +240,7 @@ tbdg_status solve_momentum(tbdg_ctx* c, int s, const double* w, const double* b,
             gm_restart(c, n, k, V, ld, c->red_out, c->red_out + k, gsc, pc ? nullptr : c->invd_u,
                        x, c->red_out + 63, gsc, pc ? c->gz : nullptr);
             if (pc) {
-                apply_pc(c->gz, nullptr, c->gv);
-                vec_axpby(c->stream, n, 1.0, x, 1.0, c->gv, x);
+                apply_pc(c->gz, nullptr, x, true);   // x += P^{-1} (V y)
             }
             beta = std::sqrt(mirrored(c, c->red_out + 63));
             true_res = false;
@@ -254,8 +253,7 @@ tbdg_status solve_momentum(tbdg_ctx* c, int s, const double* w, const double* b,
             TBDG_HIP(hipMemsetAsync(c->gz, 0, sizeof(double) * n, c->stream));
             vec_add_combo(c->stream, n, k, V, ld, c->red_out, gsc, c->gz);
             if (pc) {
-                apply_pc(c->gz, nullptr, c->gv);
-                vec_axpby(c->stream, n, 1.0, x, 1.0, c->gv, x);
+                apply_pc(c->gz, nullptr, x, true);   // x += P^{-1} (V y)
             } else {
                 vec_add_div_diag_u(c->stream, n, c->dim, c->nbu, c->gz, c->diag_u, x);
             }

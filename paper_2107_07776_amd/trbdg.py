@@ -38,7 +38,7 @@ EXPORTED = [
     "tbdg_nonlinear_solves", "tbdg_profile_bytes", "tbdg_precond_momentum",
 ]
 
-GUESS = {"given": 0, "previous": 1, "learned": 2, "extrap2": 3}
+GUESS = {"given": 0, "previous": 1, "learned": 2, "extrap2": 3, "extrap3": 4}
 
 # channels of the guess network's input and output per cell
 GUESS_IN, GUESS_OUT = 6, 2
