@@ -390,19 +390,33 @@ def train_guess(ctx, W, step_kw, seeds=tuple(range(10)), steps=30, discard=5, ep
     train the guess network on the GPU by its own kernels."""
     from paper_2107_07776_amd import Net, learned_guess
     t0 = time.perf_counter()
-    samples = learned_guess.generate(ctx, lambda s: random_phase_state(ctx, W, s), list(seeds), steps,
-                                     discard, precond="mg_fp32", tol=W["tol"],
-                                     log=lambda m: log(f"[bench] {m}"), **step_kw)
+    # the last fifth of the seeds' trajectories validate (the parameters with
+    # the lowest validation loss are kept, the untrained ones included)
+    n_val = max(1, len(seeds) // 5)
+    fit, val = list(seeds[:-n_val]), list(seeds[-n_val:])
+    gen = lambda ss: learned_guess.generate(ctx, lambda s: random_phase_state(ctx, W, s), ss, steps,
+                                            discard, precond="mg_fp32", tol=W["tol"],
+                                            log=lambda m: log(f"[bench] {m}"), **step_kw)
+    samples, vsamples = gen(fit), gen(val)
     t1 = time.perf_counter()
     net = Net(32, seed=1)
     nx, ny, nz = (list(W["n"]) + [1, 1])[:3]
-    losses = learned_guess.train(net, samples, (nx, ny, nz), epochs=epochs, batch=8, lr=1e-3)
+    rep = {}
+    # the extrapolated increment leaves a squared error ~1e-8 of the
+    # increment's: Adam's steps must stay below that scale from the start
+    losses = learned_guess.train(net, samples, (nx, ny, nz), epochs=epochs, batch=8, lr=3e-5,
+                                 val=vsamples, report=rep, log=lambda m: log(f"[bench] {m}"))
     t2 = time.perf_counter()
-    log(f"[bench] guess network: {samples.shape[0]} samples in {t1 - t0:.1f}s, {epochs} epochs in "
-        f"{t2 - t1:.1f}s, loss {losses[0]:.3e} -> {losses[-1]:.3e}")
-    return net, {"samples": int(samples.shape[0]), "generation_s": t1 - t0, "training_s": t2 - t1,
+    log(f"[bench] guess network: {samples.shape[0]} + {vsamples.shape[0]} samples in {t1 - t0:.1f}s, "
+        f"{epochs} epochs in {t2 - t1:.1f}s, loss {losses[0]:.3e} -> {losses[-1]:.3e}, validation "
+        f"{rep['validation_losses'][0]:.3e} (untrained) -> kept epoch {rep['epoch_kept']}")
+    return net, {"samples": int(samples.shape[0]), "validation_samples": int(vsamples.shape[0]),
+                 "generation_s": t1 - t0, "training_s": t2 - t1,
                  "epochs": epochs, "loss_first_epoch": losses[0], "loss_last_epoch": losses[-1],
-                 "train_seeds": list(seeds), "train_steps_per_seed": steps, "discarded_steps": discard}
+                 "validation_loss_untrained": rep["validation_losses"][0],
+                 "validation_losses": rep["validation_losses"][1:], "epoch_kept": rep["epoch_kept"],
+                 "train_seeds": fit, "validation_seeds": val, "train_steps_per_seed": steps,
+                 "discarded_steps": discard}
 
 
 def evaluate_guesses(ctx, W, step_kw, modes, seeds=(100, 101), steps=50, discard=5):
@@ -516,8 +530,9 @@ def main():
     guess_desc = {
         "given": "previous pressure",
         "previous": "previous pressure + the same stage's increment of the previous step",
-        "learned": "learned (3D CNN, bf16 MFMA) guess, previous pressure + the same stage's last "
-                   "increment as fallback, the smaller FP64 residual decides",
+        "learned": "learned (3D CNN, bf16 MFMA) correction of the quadratically extrapolated "
+                   "increment, previous pressure + the same stage's last increment as fallback, "
+                   "the smaller FP64 residual decides",
         "extrap2": "previous pressure + the same stage's increment extrapolated linearly from its "
                    "last two values",
         "extrap3": "previous pressure + the same stage's increment extrapolated quadratically from "
@@ -552,7 +567,7 @@ def main():
                                 "u_rel_l2_diff_vs_fp32": (bf["U"] - main_run["U"]).norm().item()
                                                          / main_run["U"].norm().item()}
     if learned_info is not None and not args.no_eval:
-        modes = ("given", "previous", "extrap2", "learned")
+        modes = ("given", "previous", "extrap2", "extrap3", "learned")
         learned_info["held_out"] = evaluate_guesses(ctx, W, step_kw, modes)
     if not W.get("learned", True):
         out["learned_guess"] = {"built": False,

@@ -405,8 +405,8 @@ TBDG_API tbdg_status tbdg_net_adam_step(tbdg_net* net, float lr, float beta1, fl
  *     cos_K = <d1, d2>_K / sqrt(<d1, d1>_K <d2, d2>_K) and
  *     lr_K = log(<d1, d1>_K / <d2, d2>_K) / 2 clamped to [-4, 4] (both 0
  *     where a norm vanishes); the network output (y0_K, y1_K) gives the
- *     guess p + (2 + y0_K) d1 - (1 - y1_K) d2 at the nodes of K (a
- *     correction of TBDG_GUESS_EXTRAP2); the candidate with the smaller FP64
+ *     guess p + (3 + y0_K) d1 - (3 - y1_K) d2 + d3 at the nodes of K (a
+ *     correction of TBDG_GUESS_EXTRAP3); the candidate with the smaller FP64
  *     residual ||b - H x|| (learned or TBDG_GUESS_PREVIOUS) is used.
  * Without the history a mode needs, TBDG_GUESS_PREVIOUS (or, without any,
  * the previous pressure) is used.  A failed step clears the history.       */
@@ -417,9 +417,9 @@ TBDG_API tbdg_status tbdg_set_guess_net(tbdg_ctx* ctx, tbdg_net* net);
 /* Forget the stored increments (start of a new trajectory).                 */
 TBDG_API tbdg_status tbdg_guess_reset(tbdg_ctx* ctx);
 /* Record training samples: after each TR-BDF2 Helmholtz solve of tbdg_step
- * whose stage has two earlier increments, sample k of buf (device, FP32,
+ * whose stage has three earlier increments, sample k of buf (device, FP32,
  * [capacity][12][N_c]) receives the network input [6][N_c] and the Gram
- * target [6][N_c] of tbdg_guess_target for the solve's p_new, p, d1, d2.
+ * target [6][N_c] of tbdg_guess_target for the solve's p_new, p, d1, d2, d3.
  * buf NULL stops recording; the history is cleared.                        */
 TBDG_API tbdg_status tbdg_guess_record(tbdg_ctx* ctx, float* buf, int capacity);
 TBDG_API tbdg_status tbdg_guess_recorded(tbdg_ctx* ctx, int* count);
@@ -431,17 +431,20 @@ TBDG_API tbdg_status tbdg_guess_last(tbdg_ctx* ctx, double* r_learned, double* r
 TBDG_API tbdg_status tbdg_guess_features(tbdg_ctx* ctx, int stage, const double* b,
                                          const double* p_prev, const double* d0, double beta0,
                                          const double* d1, const double* d2, float* x, double* scales);
-/* out = p_prev + (2 + y0_K) d1 - (1 - y1_K) d2 (y: FP32 [2][N_c], the rest
- * N_p).                                                                      */
+/* out = p_prev + (3 + y0_K) d1 - (3 - y1_K) d2 + d3 (y: FP32 [2][N_c], the
+ * rest N_p).                                                                 */
 TBDG_API tbdg_status tbdg_guess_inject(tbdg_ctx* ctx, const double* p_prev, const double* d1,
-                                       const double* d2, const float* y, double* out);
+                                       const double* d2, const double* d3, const float* y,
+                                       double* out);
 /* Gram target of a solve (device, N_p each; out FP32 [6][N_c]): per cell
  * (<d1,d1>, <d1,d2>, <d2,d2>, <e,d1>, <e,d2>, <e,e>)_K / S with
- * e = p_new - (p_prev + 2 d1 - d2) and S the mean over cells of <d1,d1>_K
- * (1 where zero), so that the squared error <x - p_new, x - p_new>_K of the
- * blended guess x is S times the per-cell loss of tbdg_net_quad_loss.      */
+ * e = p_new - (p_prev + 3 d1 - 3 d2 + d3) and S the mean over cells of
+ * <d1,d1>_K (1 where zero), so that the squared error <x - p_new, x - p_new>_K
+ * of the injected guess x is S times the per-cell loss of
+ * tbdg_net_quad_loss.                                                        */
 TBDG_API tbdg_status tbdg_guess_target(tbdg_ctx* ctx, const double* p_new, const double* p_prev,
-                                       const double* d1, const double* d2, float* out);
+                                       const double* d1, const double* d2, const double* d3,
+                                       float* out);
 
 /* TR-BDF2 state: u = u^n, u_hist = u^{n-1+gamma} (history level of the
  * stage-1 extrapolation), p = p^n; t and n are host values.                 */

@@ -3,9 +3,9 @@
 
 Not part of the paper.  For the Helmholtz solve of stage s (beta_s, right-hand
 side b = alpha_s M^p p_prev + F_p(u**)) the solver keeps the pressure
-increments p_new - p_prev of its earlier solves: d1 and d2 of the same stage
-one and two steps back, d0 the newest one (of the other stage, weight
-beta0).  With <a, b>_K = sum_{i in K} W_i a_i b_i (W_i the product of the
+increments p_new - p_prev of its earlier solves: d1, d2 and d3 of the same
+stage one, two and three steps back, d0 the newest one (of the other stage,
+weight beta0).  With <a, b>_K = sum_{i in K} W_i a_i b_i (W_i the product of the
 Gauss weights of node i on the unit reference cell, so <a, 1>_K is the cell
 average mean_K(a)):
 
@@ -18,13 +18,13 @@ average mean_K(a)):
   cos_K = <d1, d2>_K / sqrt(<d1, d1>_K <d2, d2>_K) and
   lr_K = log(<d1, d1>_K / <d2, d2>_K) / 2 clamped to [-4, 4] (both 0 where
   a norm vanishes): the local shape and growth of the last two increments;
-* network output per cell: (y0_K, y1_K), the correction of the blend of the
-  two increments, guess = p_prev + (2 + y0_K) d1 - (1 - y1_K) d2 at the
-  nodes of K (y = 0: the increment extrapolated linearly from its last two
-  values; y = (-1, 1): the fallback p_prev + d1); the library starts the
+* network output per cell: (y0_K, y1_K), a correction along the last two
+  increments of the increment extrapolated quadratically from its last
+  three values, guess = p_prev + (3 + y0_K) d1 - (3 - y1_K) d2 + d3 at the
+  nodes of K (y = 0: the quadratic extrapolation); the library starts the
   network's last layer at zero, i.e. from the extrapolation;
 * training target: per cell the Gram data of the error
-  e = p_new - (p_prev + 2 d1 - d2) of the extrapolation,
+  e = p_new - (p_prev + 3 d1 - 3 d2 + d3) of the extrapolation,
     (g11, g12, g22, r1, r2, ee) = (<d1,d1>, <d1,d2>, <d2,d2>, <e,d1>, <e,d2>,
     <e,e>)_K / S,  S = the mean over cells of <d1,d1>_K (1 where zero),
   so that the squared error of the blended guess in cell K is
@@ -86,9 +86,9 @@ def features(ts, s, b, p_prev, d0, beta0, d1, d2):
     return np.stack([m1 / s_inc, m2 / s_inc, m0 / s_inc, div / s_div, cos, lr]), s_inc, s_div
 
 
-def gram_target(disc, p_new, p_prev, d1, d2):
+def gram_target(disc, p_new, p_prev, d1, d2, d3):
     """[6][cells]: (g11, g12, g22, r1, r2, ee) / S (module docstring)."""
-    e = p_new - extrapolate2(p_prev, d1, d2)
+    e = p_new - extrapolate3(p_prev, d1, d2, d3)
     g11 = cell_inner(disc, d1, d1)
     S = float(np.mean(g11))
     S = S if S > 0.0 else 1.0
@@ -96,11 +96,11 @@ def gram_target(disc, p_new, p_prev, d1, d2):
                      cell_inner(disc, e, d2), cell_inner(disc, e, e)]) / S
 
 
-def inject(disc, p_prev, d1, d2, y):
-    """p_prev + (2 + y0_K) d1 - (1 - y1_K) d2 with y = [2][cells]."""
+def inject(disc, p_prev, d1, d2, d3, y):
+    """p_prev + (3 + y0_K) d1 - (3 - y1_K) d2 + d3 with y = [2][cells]."""
     a = np.repeat(np.asarray(y[0], dtype=np.float64), disc.nbp)
     c = np.repeat(np.asarray(y[1], dtype=np.float64), disc.nbp)
-    return extrapolate2(p_prev, d1, d2) + a * d1 + c * d2
+    return extrapolate3(p_prev, d1, d2, d3) + a * d1 + c * d2
 
 
 def fallback(p_prev, d1):
@@ -110,6 +110,12 @@ def fallback(p_prev, d1):
 def extrapolate2(p_prev, d1, d2):
     """The same-stage increment extrapolated linearly from its last two values."""
     return p_prev + 2.0 * d1 - d2
+
+
+def extrapolate3(p_prev, d1, d2, d3):
+    """The same-stage increment extrapolated quadratically from its last three
+    values (the parabola through them evaluated one step on)."""
+    return p_prev + 3.0 * d1 - 3.0 * d2 + d3
 
 
 def quad_loss(y, G):

@@ -856,22 +856,22 @@ tbdg_status tbdg_guess_features(tbdg_ctx* c, int stage, const double* b, const d
 }
 
 tbdg_status tbdg_guess_inject(tbdg_ctx* c, const double* p_prev, const double* d1, const double* d2,
-                              const float* y, double* out) {
+                              const double* d3, const float* y, double* out) {
     if (!c) return TBDG_EINVAL;
     return guarded(c, [&]() {
-        require(p_prev && d1 && d2 && y && out, "null pointer");
-        trbdg::guess_inject(c, p_prev, d1, d2, y, out);
+        require(p_prev && d1 && d2 && d3 && y && out, "null pointer");
+        trbdg::guess_inject(c, p_prev, d1, d2, d3, y, out);
         TBDG_HIP(hipStreamSynchronize(c->stream));
         return TBDG_OK;
     });
 }
 
 tbdg_status tbdg_guess_target(tbdg_ctx* c, const double* p_new, const double* p_prev, const double* d1,
-                              const double* d2, float* out) {
+                              const double* d2, const double* d3, float* out) {
     if (!c) return TBDG_EINVAL;
     return guarded(c, [&]() {
-        require(p_new && p_prev && d1 && d2 && out, "null pointer");
-        trbdg::guess_target(c, p_new, p_prev, d1, d2, out);
+        require(p_new && p_prev && d1 && d2 && d3 && out, "null pointer");
+        trbdg::guess_target(c, p_new, p_prev, d1, d2, d3, out);
         TBDG_HIP(hipStreamSynchronize(c->stream));
         return TBDG_OK;
     });

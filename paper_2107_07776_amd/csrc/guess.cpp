@@ -1,8 +1,9 @@
 // Initial guesses of the Helmholtz solves inside tbdg_step: the previous
 // pressure, the previous pressure plus the same stage's increment of the
-// previous step (the fallback), that increment extrapolated from its last two
-// values, or the learned blend of the last two increments with the fallback
-// as the alternative (the guess with the smaller FP64 residual is used).
+// previous step (the fallback), that increment extrapolated linearly from its
+// last two or quadratically from its last three values, or the learned
+// correction of the quadratic extrapolation with the fallback as the
+// alternative (the guess with the smaller FP64 residual is used).
 // Also records (input, target) samples of the network from the solver's own
 // solves.
 #include <cmath>
@@ -83,15 +84,15 @@ void guess_features(tbdg_ctx* c, int s, const double* b, const double* p, const 
     launch_guess_feat(c, g.cells, g.partial, G, g.feat, g.sc);
 }
 
-void guess_inject(tbdg_ctx* c, const double* p, const double* d1, const double* d2, const float* y,
-                  double* out) {
-    launch_guess_inject(c, p, d1, d2, y, out);
+void guess_inject(tbdg_ctx* c, const double* p, const double* d1, const double* d2, const double* d3,
+                  const float* y, double* out) {
+    launch_guess_inject(c, p, d1, d2, d3, y, out);
 }
 
 void guess_target(tbdg_ctx* c, const double* pn, const double* p, const double* d1, const double* d2,
-                  float* out) {
+                  const double* d3, float* out) {
     ensure_state(c);
-    launch_guess_target(c, pn, p, d1, d2, c->gs->cells, c->gs->partial, out);
+    launch_guess_target(c, pn, p, d1, d2, d3, c->gs->cells, c->gs->partial, out);
 }
 
 int guess_prepare(tbdg_ctx* c, int s, int mode, const double* b, const double* p_prev, double* x) {
@@ -108,8 +109,8 @@ int guess_prepare(tbdg_ctx* c, int s, int mode, const double* b, const double* p
     ensure_state(c);
     GuessState& g = *c->gs;
     g.feat_valid = false;
-    // the network needs the same stage's increments of the last two steps
-    const bool history = two_stage && g.n > lag2;
+    // the network needs the same stage's increments of the last three steps
+    const bool history = two_stage && g.n > lag3;
     const bool learned = mode == TBDG_GUESS_LEARNED && g.net != nullptr && history;
     if (history && (learned || recording)) {
         guess_features(c, s, b, p_prev, g.inc[0], g.beta[0], g.inc[lag1], g.inc[lag2]);
@@ -140,7 +141,7 @@ int guess_prepare(tbdg_ctx* c, int s, int mode, const double* b, const double* p
     vec_axpby(c->stream, c->Np, 1.0, p_prev, 1.0, g.inc[lag1], x);
     if (!learned) return 1;
     net_infer(g.net, g.feat, g.y, c->geom.nc[0], c->geom.nc[1], c->geom.nc[2]);
-    guess_inject(c, p_prev, g.inc[lag1], g.inc[lag2], g.y, g.trial);
+    guess_inject(c, p_prev, g.inc[lag1], g.inc[lag2], g.inc[lag3], g.y, g.trial);
     residual_sq(c, s, b, g.trial, c->red_out + 60);
     residual_sq(c, s, b, x, c->red_out + 61);
     TBDG_HIP(hipMemcpyAsync(c->host_out, c->red_out + 60, 2 * sizeof(double), hipMemcpyDeviceToHost,
@@ -161,10 +162,11 @@ void guess_after_solve(tbdg_ctx* c, int s, const double* p_new, const double* p_
     GuessState& g = *c->gs;
     if (g.feat_valid && g.rec && g.rec_count < g.rec_cap) {
         // sample = network input [6][Nc], then the Gram target [6][Nc]; the
-        // same stage's increments are inc[1] and inc[3] until the shift below
+        // same stage's increments are inc[1], inc[3] and inc[5] until the
+        // shift below
         float* dst = g.rec + (int64_t)g.rec_count * 12 * c->Nc;
         TBDG_HIP(hipMemcpyAsync(dst, g.feat, sizeof(float) * 6 * c->Nc, hipMemcpyDeviceToDevice, c->stream));
-        guess_target(c, p_new, p_prev, g.inc[1], g.inc[3], dst + 6 * c->Nc);
+        guess_target(c, p_new, p_prev, g.inc[1], g.inc[3], g.inc[5], dst + 6 * c->Nc);
         ++g.rec_count;
     }
     g.feat_valid = false;

@@ -154,12 +154,13 @@ template <int NB>
 __global__ __launch_bounds__(256) void k_guess_inject(int Nc, const double* __restrict__ p,
                                                        const double* __restrict__ d1,
                                                        const double* __restrict__ d2,
+                                                       const double* __restrict__ d3,
                                                        const float* __restrict__ y,
                                                        double* __restrict__ out) {
     const int64_t n = (int64_t)Nc * NB;
     for (int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x; i < n; i += (int64_t)gridDim.x * 256) {
         const int c = (int)(i / NB);
-        out[i] = p[i] + (2.0 + (double)y[c]) * d1[i] - (1.0 - (double)y[Nc + c]) * d2[i];
+        out[i] = p[i] + (3.0 + (double)y[c]) * d1[i] - (3.0 - (double)y[Nc + c]) * d2[i] + d3[i];
     }
 }
 
@@ -170,6 +171,7 @@ __global__ __launch_bounds__(256) void k_guess_gram(int Nc, Tables t, const doub
                                                      const double* __restrict__ p,
                                                      const double* __restrict__ d1,
                                                      const double* __restrict__ d2,
+                                                     const double* __restrict__ d3,
                                                      double* __restrict__ rows, double* partial) {
     using CB = CellBlock<DIM, NP>;
     constexpr int NB = CB::NB, CPB = CB::CPB;
@@ -183,7 +185,7 @@ __global__ __launch_bounds__(256) void k_guess_gram(int Nc, Tables t, const doub
             const double w = node_weight<DIM, NP>(t.Wp, nd);
             const size_t gi = (size_t)c * NB + nd;
             const double a1 = d1[gi], a2 = d2[gi];
-            const double e = pn[gi] - (p[gi] + 2.0 * a1 - a2);
+            const double e = pn[gi] - (p[gi] + 3.0 * a1 - 3.0 * a2 + d3[gi]);
             v[0] = w * a1 * a1;
             v[1] = w * a1 * a2;
             v[2] = w * a2 * a2;
@@ -271,28 +273,29 @@ void launch_guess_feat(const tbdg_ctx* c, const double* cells, const double* par
 }
 
 void launch_guess_inject(const tbdg_ctx* c, const double* p, const double* d1, const double* d2,
-                         const float* y, double* out) {
+                         const double* d3, const float* y, double* out) {
     if (c->mapped)
         throw Error(TBDG_EUNSUPPORTED, "the learned guess is built for affine cells only");
     const int64_t g = nb256(c->Np);
     const unsigned G = (unsigned)(g < 2048 ? g : 2048);
 #define L_(D, NP)                                                                          \
     hipLaunchKernelGGL((k_guess_inject<ipw(NP, D)>), dim3(G), dim3(256), 0, c->stream,        \
-                       (int)c->Nc, p, d1, d2, y, out);
+                       (int)c->Nc, p, d1, d2, d3, y, out);
     TBDG_GUESS_DISPATCH(c->dim, c->np, L_);
 #undef L_
     TBDG_HIP(hipGetLastError());
 }
 
 void launch_guess_target(const tbdg_ctx* c, const double* pn, const double* p, const double* d1,
-                         const double* d2, double* rows, double* partial, float* out) {
+                         const double* d2, const double* d3, double* rows, double* partial,
+                         float* out) {
     if (c->mapped)
         throw Error(TBDG_EUNSUPPORTED, "the learned guess is built for affine cells only");
     unsigned G = 0;
 #define L_(D, NP)                                                                          \
     G = (unsigned)((c->Nc + CellBlock<D, NP>::CPB - 1) / CellBlock<D, NP>::CPB);           \
     hipLaunchKernelGGL((k_guess_gram<D, NP>), dim3(G), dim3(256), 0, c->stream, (int)c->Nc,   \
-                       c->tab, pn, p, d1, d2, rows, partial);
+                       c->tab, pn, p, d1, d2, d3, rows, partial);
     TBDG_GUESS_DISPATCH(c->dim, c->np, L_);
 #undef L_
     hipLaunchKernelGGL(k_guess_gram_scale, dim3(nb256(c->Nc)), dim3(256), 0, c->stream, (int)c->Nc,

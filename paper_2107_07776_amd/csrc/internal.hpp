@@ -611,20 +611,21 @@ int launch_guess_cells(const tbdg_ctx* c, const double* d1, const double* d2, co
 void launch_guess_feat(const tbdg_ctx* c, const double* cells, const double* partial, int G,
                        float* feat, double* sc);
 void launch_guess_inject(const tbdg_ctx* c, const double* p, const double* d1, const double* d2,
-                         const float* y, double* out);
+                         const double* d3, const float* y, double* out);
 // Gram target [6][Nc] of the blend (rows: 6 Nc doubles of scratch, partial: Nc/256 + 1)
 void launch_guess_target(const tbdg_ctx* c, const double* pn, const double* p, const double* d1,
-                         const double* d2, double* rows, double* partial, float* out);
+                         const double* d2, const double* d3, double* rows, double* partial,
+                         float* out);
 void guess_ensure(tbdg_ctx* c);
 void guess_free(tbdg_ctx* c);
 void guess_reset(tbdg_ctx* c);
 // network input [6][Nc] (into the guess state) of the stage-s solve
 void guess_features(tbdg_ctx* c, int s, const double* b, const double* p, const double* d0,
                     double beta0, const double* d1, const double* d2);
-void guess_inject(tbdg_ctx* c, const double* p, const double* d1, const double* d2, const float* y,
-                  double* out);
+void guess_inject(tbdg_ctx* c, const double* p, const double* d1, const double* d2, const double* d3,
+                  const float* y, double* out);
 void guess_target(tbdg_ctx* c, const double* pn, const double* p, const double* d1, const double* d2,
-                  float* out);
+                  const double* d3, float* out);
 // writes the initial guess of the stage-s solve to x; returns 0 (previous
 // pressure), 1 (rescaled increment) or 2 (learned)
 int guess_prepare(tbdg_ctx* c, int s, int mode, const double* b, const double* p_prev, double* x);

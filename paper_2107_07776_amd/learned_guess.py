@@ -29,9 +29,10 @@ def generate(ctx, initial_state, seeds, steps, discard, precond="mg_fp32", tol=1
         ctx.guess_record(None)
         ctx.guess_reset()
         t = 0.0
-        for n in range(discard + steps + 1):
+        for n in range(discard + steps + 3):
             if n == discard:
-                # recording clears the history: one more step refills it
+                # recording clears the history; the network's input needs the
+                # same stage's last three increments: three steps refill it
                 ctx.guess_record(buf[total:])
             info, st = ctx.step(u, uh, p, t, n, mom_tol=tol, prs_tol=tol, prs_maxiter=maxiter,
                                 precond=precond, guess="previous", check=False, **step_kw)
@@ -46,17 +47,40 @@ def generate(ctx, initial_state, seeds, steps, discard, precond="mg_fp32", tol=1
     return buf[:total]
 
 
-def train(net, samples, grid, epochs, batch=8, lr=1e-3, seed=0, log=None):
+def mean_loss(net, samples, grid, batch=8):
+    """Mean per-cell quadratic loss of the network's output over samples."""
+    nx, ny, nz = grid
+    S = samples.shape[0]
+    x_all = samples[:, :6].reshape(S, 6, nz, ny, nx)
+    y_all = samples[:, 6:].reshape(S, 6, nz, ny, nx)
+    tot = 0.0
+    for i in range(0, S, batch):
+        x = x_all[i:i + batch].contiguous()
+        y = y_all[i:i + batch].contiguous()
+        loss, _ = net.quad_loss(net.forward(x), y)
+        tot += loss * x.shape[0]
+    return tot / max(S, 1)
+
+
+def train(net, samples, grid, epochs, batch=8, lr=1e-3, seed=0, log=None, val=None, report=None):
     """Adam on the per-cell quadratic loss of the recorded Gram targets (the
-    squared nodal error of the blended increment); returns the mean loss of
-    every epoch.  ``grid`` = (nx, ny, nz) of the cell grid."""
+    squared nodal error of the injected guess); returns the mean loss of
+    every epoch.  ``grid`` = (nx, ny, nz) of the cell grid.  With validation
+    samples ``val`` (other trajectories), the parameters with the lowest
+    validation loss are kept, the untrained ones (zero output: the
+    extrapolated increment itself) included; ``report`` (a dict) receives the
+    validation losses and the epoch kept."""
     nx, ny, nz = grid
     S = samples.shape[0]
     x_all = samples[:, :6].reshape(S, 6, nz, ny, nx)
     y_all = samples[:, 6:].reshape(S, 6, nz, ny, nx)
     gen = torch.Generator(device="cpu")
     gen.manual_seed(seed)
-    losses = []
+    losses, vlosses = [], []
+    best = None
+    if val is not None:
+        vlosses.append(mean_loss(net, val, grid, batch))
+        best = (vlosses[0], net.params().clone(), 0)
     for ep in range(epochs):
         perm = torch.randperm(S, generator=gen)
         tot, cnt = 0.0, 0
@@ -72,8 +96,18 @@ def train(net, samples, grid, epochs, batch=8, lr=1e-3, seed=0, log=None):
             tot += loss * len(idx)
             cnt += len(idx)
         losses.append(tot / cnt)
+        msg = f"epoch {ep + 1}/{epochs}: loss {losses[-1]:.4e}"
+        if val is not None:
+            vlosses.append(mean_loss(net, val, grid, batch))
+            msg += f", validation {vlosses[-1]:.4e}"
+            if vlosses[-1] < best[0]:
+                best = (vlosses[-1], net.params().clone(), ep + 1)
         if log:
-            log(f"epoch {ep + 1}/{epochs}: loss {losses[-1]:.4e}")
+            log(msg)
+    if best is not None:
+        net.set_params(best[1])
+    if report is not None:
+        report.update(validation_losses=vlosses, epoch_kept=best[2] if best else epochs)
     return losses
 
 

@@ -165,8 +165,8 @@ def load_library(path=LIB_PATH):
         "tbdg_profile_bytes": ([vp, i, P(d)], i),
         "tbdg_precond_momentum": ([vp, i, vp, vp, vp], i),
         "tbdg_guess_features": ([vp, i, vp, vp, vp, d, vp, vp, vp, P(d)], i),
-        "tbdg_guess_inject": ([vp, vp, vp, vp, vp, vp], i),
-        "tbdg_guess_target": ([vp, vp, vp, vp, vp, vp], i),
+        "tbdg_guess_inject": ([vp, vp, vp, vp, vp, vp, vp], i),
+        "tbdg_guess_target": ([vp, vp, vp, vp, vp, vp, vp], i),
     }
     for name, (args, res) in sig.items():
         fn = getattr(lib, name)
@@ -502,23 +502,25 @@ class Context:
             _ptr(self._vec(d2, self.N_p, "d2")), _ptr(x), sc))
         return x, (sc[0], sc[1])
 
-    def guess_inject(self, p_prev, d1, d2, y):
-        """p_prev + (2 + y0_K) d1 - (1 - y1_K) d2 for y float32 [2][N_c]."""
+    def guess_inject(self, p_prev, d1, d2, d3, y):
+        """p_prev + (3 + y0_K) d1 - (3 - y1_K) d2 + d3 for y float32 [2][N_c]."""
         out = self.empty_p()
         if y.dtype != torch.float32 or y.numel() != GUESS_OUT * self.N_c or not y.is_contiguous():
             raise ValueError("y must be a contiguous float32 tensor of 2 N_c entries")
         self._check(self.lib.tbdg_guess_inject(self.h, _ptr(self._vec(p_prev, self.N_p, "p_prev")),
                                                _ptr(self._vec(d1, self.N_p, "d1")),
-                                               _ptr(self._vec(d2, self.N_p, "d2")), _ptr(y), _ptr(out)))
+                                               _ptr(self._vec(d2, self.N_p, "d2")),
+                                               _ptr(self._vec(d3, self.N_p, "d3")), _ptr(y), _ptr(out)))
         return out
 
-    def guess_target(self, p_new, p_prev, d1, d2):
+    def guess_target(self, p_new, p_prev, d1, d2, d3):
         """Gram target [6][N_c] float32 of a solve (training data of the network)."""
         out = torch.empty((6, self.N_c), dtype=torch.float32, device=self.device)
         self._check(self.lib.tbdg_guess_target(self.h, _ptr(self._vec(p_new, self.N_p, "p_new")),
                                                _ptr(self._vec(p_prev, self.N_p, "p_prev")),
                                                _ptr(self._vec(d1, self.N_p, "d1")),
-                                               _ptr(self._vec(d2, self.N_p, "d2")), _ptr(out)))
+                                               _ptr(self._vec(d2, self.N_p, "d2")),
+                                               _ptr(self._vec(d3, self.N_p, "d3")), _ptr(out)))
         return out
 
     def profile(self, enable):

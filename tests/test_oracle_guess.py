@@ -6,10 +6,12 @@ and library routines.
 * the divergence feature of an interpolated polynomial velocity equals the
   exact cell mean of its divergence (interior cells of a periodic mesh);
 * the shape features of hand-built increments take their closed-form values;
-* for pressures quadratic in time with a constant offset per stage, the
-  network's zero output (linear extrapolation of the increment) has zero
-  loss in every cell and reproduces the new pressure, and the blend that
-  gives the fallback has the fallback's squared error as its loss;
+* for pressures cubic in time with a constant offset per stage, the
+  network's zero output (quadratic extrapolation of the increment) has zero
+  loss in every cell and reproduces the new pressure (the linear
+  extrapolation does not; both are exact for quadratic pressures);
+* the quadratic loss of any output equals the weighted squared error of the
+  guess it injects, computed directly;
 * the per-cell minimiser of the quadratic loss is the weighted least-squares
   fit of the extrapolation's error on the two increments (numpy lstsq);
 * the fallback is exact for pressures linear in time with stage offsets.
@@ -96,48 +98,60 @@ def test_shape_features_closed_forms():
     assert cos[3] == 0.0 and lr[3] == 0.0
 
 
-def _history(disc, ts, rng, quadratic):
-    """Pressures P(t) + o_s at stage times, P quadratic (or linear) in time:
-    returns p_prev, d1, d2 and p_new of a stage-1 solve of step n."""
-    p0, q1, q2, o1, o2 = (rng.standard_normal(disc.N_p) for _ in range(5))
+def _history(disc, ts, rng, degree):
+    """Pressures P(t) + o_s at stage times, P a polynomial of the given degree
+    in time: returns p_prev, d1, d2, d3 and p_new of a stage-1 solve of step n."""
+    q = [rng.standard_normal(disc.N_p) for _ in range(degree + 1)]
+    o1, o2 = rng.standard_normal(disc.N_p), rng.standard_normal(disc.N_p)
     g, dt = ts.cst["gamma"], ts.dt
-    P = lambda t: p0 + t * q1 + (t * t * q2 if quadratic else 0.0)
+    P = lambda t: sum(qi * t ** i for i, qi in enumerate(q))
     tn = 0.4
     p_prev = P(tn) + o2
-    d1 = (P(tn - (1 - g) * dt) + o1) - (P(tn - dt) + o2)
-    d2 = (P(tn - (2 - g) * dt) + o1) - (P(tn - 2 * dt) + o2)
+    d = [(P(tn - j * dt + g * dt) + o1) - (P(tn - j * dt) + o2) for j in (1, 2, 3)]
     p_new = P(tn + g * dt) + o1
-    return p_prev, d1, d2, p_new
+    return p_prev, d[0], d[1], d[2], p_new
 
 
-def test_extrapolation_blend_is_exact_for_quadratic_in_time_pressure():
+def test_extrapolation_blend_is_exact_for_cubic_in_time_pressure():
     disc, ts = _setup()
     rng = np.random.default_rng(2)
-    p_prev, d1, d2, p_new = _history(disc, ts, rng, quadratic=True)
-    G = guess.gram_target(disc, p_new, p_prev, d1, d2)
+    p_prev, d1, d2, d3, p_new = _history(disc, ts, rng, degree=3)
+    G = guess.gram_target(disc, p_new, p_prev, d1, d2, d3)
     y = np.zeros((2, disc.Nc))
     loss0, _ = guess.quad_loss(y, G)
     assert loss0 < 1e-24 * np.abs(G[0]).max()
-    assert np.allclose(guess.inject(disc, p_prev, d1, d2, y), p_new, atol=1e-12)
-    assert np.allclose(guess.inject(disc, p_prev, d1, d2, y), guess.extrapolate2(p_prev, d1, d2))
-    # y = (-1, 1) is the fallback, whose loss is its own squared error; the
-    # expanded form cancels terms of the size of g11 (order one)
-    yf = np.stack([-np.ones(disc.Nc), np.ones(disc.Nc)])
-    assert np.allclose(guess.inject(disc, p_prev, d1, d2, yf), guess.fallback(p_prev, d1))
-    e = p_new - guess.fallback(p_prev, d1)
+    assert np.allclose(guess.inject(disc, p_prev, d1, d2, d3, y), p_new, atol=1e-12)
+    assert np.allclose(guess.inject(disc, p_prev, d1, d2, d3, y), guess.extrapolate3(p_prev, d1, d2, d3))
+    # the linear extrapolation misses the cubic term; for quadratic pressures
+    # both are exact
+    assert np.abs(guess.extrapolate2(p_prev, d1, d2) - p_new).max() > 1e-6
+    p_prev, d1, d2, d3, p_new = _history(disc, ts, rng, degree=2)
+    assert np.allclose(guess.extrapolate2(p_prev, d1, d2), p_new, atol=1e-12)
+    assert np.allclose(guess.extrapolate3(p_prev, d1, d2, d3), p_new, atol=1e-12)
+
+
+def test_loss_equals_squared_error_of_injected_guess():
+    disc, ts = _setup(n=3)
+    rng = np.random.default_rng(8)
+    p_prev, d1, d2, d3, p_new = (rng.standard_normal(disc.N_p) for _ in range(5))
+    G = guess.gram_target(disc, p_new, p_prev, d1, d2, d3)
     S = np.mean(guess.cell_inner(disc, d1, d1))
-    lossf, _ = guess.quad_loss(yf, G)
-    assert abs(lossf - np.mean(guess.cell_inner(disc, e, e)) / S) < 1e-12 * np.abs(G[0]).max()
+    for t in range(4):
+        y = rng.standard_normal((2, disc.Nc))
+        e = p_new - guess.inject(disc, p_prev, d1, d2, d3, y)
+        direct = np.mean(guess.cell_inner(disc, e, e)) / S
+        loss, _ = guess.quad_loss(y, G)
+        assert abs(loss - direct) <= 1e-12 * max(direct, np.abs(G).max())
 
 
 def test_loss_minimiser_is_the_weighted_least_squares_fit():
     disc, ts = _setup(n=3)
     rng = np.random.default_rng(6)
-    p_prev, d1, d2 = (rng.standard_normal(disc.N_p) for _ in range(3))
+    p_prev, d1, d2, d3 = (rng.standard_normal(disc.N_p) for _ in range(4))
     p_new = p_prev + d1 + rng.standard_normal(disc.N_p)
-    G = guess.gram_target(disc, p_new, p_prev, d1, d2)
+    G = guess.gram_target(disc, p_new, p_prev, d1, d2, d3)
     sw = np.sqrt(guess.node_weights(disc))
-    e = p_new - guess.extrapolate2(p_prev, d1, d2)
+    e = p_new - guess.extrapolate3(p_prev, d1, d2, d3)
     y_ls = np.empty((2, disc.Nc))
     for c in range(disc.Nc):
         sl = slice(c * disc.nbp, (c + 1) * disc.nbp)
@@ -153,5 +167,5 @@ def test_loss_minimiser_is_the_weighted_least_squares_fit():
 
 def test_fallback_exact_for_linear_in_time_pressure_with_stage_offsets():
     disc, ts = _setup()
-    p_prev, d1, _, p_new = _history(disc, ts, np.random.default_rng(3), quadratic=False)
+    p_prev, d1, _, _, p_new = _history(disc, ts, np.random.default_rng(3), degree=1)
     assert np.allclose(guess.fallback(p_prev, d1), p_new, atol=1e-13)
