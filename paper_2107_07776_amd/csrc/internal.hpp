@@ -236,6 +236,9 @@ struct MGData {
                                 // every component, velocity layout)
     double* zpart = nullptr;    // partial sums z.r, z.q of the finest smoother step
     double* rpart = nullptr;    // partial sums r.r of the FP64 update
+    double* mones = nullptr;    // pressure: M^p 1 (the constant mode of the BF16 cycle)
+    double mtot = 0.0;          // 1 . M^p 1
+    double* dsum = nullptr;     // partials of the constant-mode sums
     std::vector<void*> allocs;
     std::vector<VGraph> graphs;
     bool no_fuse = false;
@@ -562,6 +565,15 @@ int launch_mg_prep(hipStream_t st, int64_t n, int update, const double* pa, int 
                    const float* invd, float c2, double* partial);
 void launch_mg_beta(hipStream_t st, const double* partial, int G, double* sc, int first, int slot,
                     int slot_prev);
+// z += gamma 1 with the exact constant mode (see mg.hip), and the z.r, z.q
+// partials of flexible CG recomputed into zpart; returns their count
+int launch_deflate(hipStream_t st, int64_t n, double alpha, double mtot, const double* m,
+                   const double* r, const double* q, double* z, double* sums, double* zpart,
+                   int max_blocks);
+// x += g 1, r -= g alpha m with g = (1.r) / (alpha 1.m): the residual's
+// constant mode solved exactly (start of a BF16 solve)
+void launch_deflate_start(hipStream_t st, int64_t n, double alpha, double mtot, const double* m,
+                          double* x, double* r, double* sums);
 // the coarse end of a V-cycle in one workgroup (levels fc.lv[0..nlev-1])
 void launch_fused_cycle(hipStream_t st, int dim, const FusedCycle& fc, size_t lds);
 // largest LDS a workgroup may take on the current device (after raising the
@@ -574,6 +586,7 @@ void launch_vel_prep(hipStream_t st, int64_t Nc, int nb, int dim, int comp, cons
                      float c2);
 void vec_mul(hipStream_t st, int64_t n, const double* a, const double* b, double* out);
 void vec_unit(hipStream_t st, int64_t n, int64_t j, double* out);
+void vec_fill(hipStream_t st, int64_t n, double v, double* out);
 void vec_inv_sqrt(hipStream_t st, int64_t n, const double* d, double* out, float* invf);
 
 // ---- set-up helpers (setup.cpp) ---------------------------------------------------

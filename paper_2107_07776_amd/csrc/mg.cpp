@@ -512,10 +512,17 @@ void mg_build(tbdg_ctx* c, MGData& M, const tbdg_mg_desc* desc) {
         }
     }
     if (M.field == 0) {
-        // the flexible CG's glue
+        // the flexible CG's glue, and the constant mode M^p 1 = H 1 / alpha
+        // (K 1 = 0) of the BF16 cycle's correction
         M.z = mg_alloc<double>(&M, M.n0);
         M.zpart = mg_alloc<double>(&M, 2 * (int64_t)level_blocks(c->dim, M.lv[0]));
         M.rpart = mg_alloc<double>(&M, 1024);
+        M.mones = mg_alloc<double>(&M, M.n0);
+        M.dsum = mg_alloc<double>(&M, 3 * 256);
+        double* ones = mg_alloc<double>(&M, M.n0);
+        vec_fill(c->stream, M.n0, 1.0, ones);
+        launch_apply_pressure(c, 1.0, ones, M.mones);
+        M.mtot = host_dot(c, M.n0, M.mones, ones);
     } else {
         M.z = mg_alloc<double>(&M, M.n0 * c->dim);
     }
@@ -719,9 +726,11 @@ tbdg_status solve_pressure_mg(tbdg_ctx* c, int s, const double* b, double* x,
     bool first_cycle = true;
     const int G0 = level_blocks(c->dim, M.lv[0]);
     while (true) {
-        // (re)start from the true residual
+        // (re)start from the true residual; with BF16 storage its constant
+        // mode is first solved exactly (see the cycle's correction in mg.hip)
         launch_apply_pressure(c, alpha, x, q);
         vec_axpby(c->stream, n, 1.0, b, -1.0, q, r);
+        if (prec == 2 && alpha > 0.0) launch_deflate_start(c->stream, n, alpha, M.mtot, M.mones, x, r, M.dsum);
         const int G = prep(c, s, prec, 0, nullptr, 0, sc, 0, x, r, nullptr, nullptr);
         double rr = read_rr(G);
         if (first_cycle) inf.res0 = std::sqrt(rr) / bnorm;
@@ -736,7 +745,10 @@ tbdg_status solve_pressure_mg(tbdg_ctx* c, int s, const double* b, double* x,
         }
         if (total >= o.maxiter) break;
         run_vcycle(c, s, prec, r, nullptr, true);
-        launch_mg_beta(c->stream, M.zpart, G0, sc, 1, 8, 9);
+        int Gz = G0;
+        if (prec == 2 && alpha > 0.0)
+            Gz = launch_deflate(c->stream, n, alpha, M.mtot, M.mones, r, nullptr, M.z, M.dsum, M.zpart, G0);
+        launch_mg_beta(c->stream, M.zpart, Gz, sc, 1, 8, 9);
         bool conv = false, broke = false, nan = false, stalled = false;
         int k = 0;
         std::vector<double> hist{rr};   // r.r after each step of this cycle
@@ -770,7 +782,10 @@ tbdg_status solve_pressure_mg(tbdg_ctx* c, int s, const double* b, double* x,
             }
             if (total >= o.maxiter) break;
             run_vcycle(c, s, prec, r, q, true);
-            launch_mg_beta(c->stream, M.zpart, G0, sc, 0, 8 + (k & 1), slot);
+            Gz = G0;
+            if (prec == 2 && alpha > 0.0)
+                Gz = launch_deflate(c->stream, n, alpha, M.mtot, M.mones, r, q, M.z, M.dsum, M.zpart, G0);
+            launch_mg_beta(c->stream, M.zpart, Gz, sc, 0, 8 + (k & 1), slot);
         }
         if ((broke || stalled) && prec == 2) {
             // BF16 rounding of the finest level made the cycle non-positive

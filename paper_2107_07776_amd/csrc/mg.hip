@@ -624,6 +624,93 @@ __global__ __launch_bounds__(256) void k_mg_prep(int64_t n, int update, const do
     }
 }
 
+// ---- the constant mode of the BF16 cycle -----------------------------------------
+// K 1 = 0, so H 1 = alpha M 1 exactly and H^{-1} r has the constant component
+// (1.r) / (alpha 1.M1) with m.z = (1.r) / alpha (m = M 1); the rest is
+// m-orthogonal.  Rounding the finest level's vectors to bf16 injects a
+// constant component of relative size 2^-9 that the cycle, an approximate
+// inverse, multiplies by ~1/alpha (alpha = 1/(c^2 beta^2 dt^2) is small):
+// z then carries a spurious constant.  The fix replaces z's m-weighted
+// constant by the exact one, z += gamma 1 with
+//   gamma = (1.r) / (alpha 1.m) - (m.z) / (1.m),
+// and recomputes the z.r and z.q partials of flexible CG.
+
+// partials of 1.r, 1.q (q may be null) and m.z
+__global__ __launch_bounds__(256) void k_defl_sums(int64_t n, const double* __restrict__ r,
+                                                    const double* __restrict__ q,
+                                                    const double* __restrict__ m,
+                                                    const double* __restrict__ z,
+                                                    double* __restrict__ partial) {
+    double sr = 0.0, sq = 0.0, mz = 0.0;
+    for (int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x; i < n; i += (int64_t)gridDim.x * 256) {
+        sr += r[i];
+        if (q) sq += q[i];
+        if (z) mz += m[i] * z[i];
+    }
+    sr = red::block_sum(sr);
+    sq = red::block_sum(sq);
+    mz = red::block_sum(mz);
+    if (threadIdx.x == 0) {
+        partial[blockIdx.x] = sr;
+        partial[gridDim.x + blockIdx.x] = sq;
+        partial[2 * gridDim.x + blockIdx.x] = mz;
+    }
+}
+
+// every block sums the G partials of k_defl_sums in the same order, forms
+// gamma, adds it to z and writes its partials of z.r and z.q (k_mg_beta's
+// layout: G2 blocks of this kernel)
+__global__ __launch_bounds__(256) void k_defl_apply(int64_t n, const double* __restrict__ sums, int G,
+                                                     double alpha, double mtot,
+                                                     const double* __restrict__ r,
+                                                     const double* __restrict__ q,
+                                                     double* __restrict__ z,
+                                                     double* __restrict__ partial) {
+    __shared__ double s_g;
+    double sr = 0.0, mz = 0.0;
+    for (int k = threadIdx.x; k < G; k += 256) {
+        sr += sums[k];
+        mz += sums[2 * G + k];
+    }
+    sr = red::block_sum(sr);
+    mz = red::block_sum(mz);
+    if (threadIdx.x == 0) s_g = sr / (alpha * mtot) - mz / mtot;
+    __syncthreads();
+    const double g = s_g;
+    double zr = 0.0, zq = 0.0;
+    for (int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x; i < n; i += (int64_t)gridDim.x * 256) {
+        const double zi = z[i] + g;
+        z[i] = zi;
+        zr += zi * r[i];
+        if (q) zq += zi * q[i];
+    }
+    zr = red::block_sum(zr);
+    zq = red::block_sum(zq);
+    if (threadIdx.x == 0) {
+        partial[blockIdx.x] = zr;
+        partial[gridDim.x + blockIdx.x] = zq;
+    }
+}
+
+// start of a BF16 solve: the exact constant mode of the residual moved into
+// x, x += g 1 and r -= g alpha m with g = (1.r) / (alpha 1.m) (H 1 = alpha m)
+__global__ __launch_bounds__(256) void k_defl_start(int64_t n, const double* __restrict__ sums, int G,
+                                                     double alpha, double mtot,
+                                                     const double* __restrict__ m,
+                                                     double* __restrict__ x, double* __restrict__ r) {
+    __shared__ double s_g;
+    double sr = 0.0;
+    for (int k = threadIdx.x; k < G; k += 256) sr += sums[k];
+    sr = red::block_sum(sr);
+    if (threadIdx.x == 0) s_g = sr / (alpha * mtot);
+    __syncthreads();
+    const double g = s_g;
+    for (int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x; i < n; i += (int64_t)gridDim.x * 256) {
+        x[i] += g;
+        r[i] -= g * alpha * m[i];
+    }
+}
+
 // beta of flexible CG from the z.r and z.q partials of the last smoother step:
 // beta = -alpha z.q / (z.r)_old (0 on the first step); sc[slot] = z.r.  A
 // non-positive or non-finite z.r (preconditioner not positive) raises sc[6].
@@ -670,6 +757,11 @@ __global__ __launch_bounds__(256) void k_mul3(int64_t n, const double* a, const 
 __global__ __launch_bounds__(256) void k_unit(int64_t n, int64_t j, double* out) {
     for (int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x; i < n; i += (int64_t)gridDim.x * 256)
         out[i] = i == j ? 1.0 : 0.0;
+}
+
+__global__ __launch_bounds__(256) void k_fill(int64_t n, double v, double* out) {
+    for (int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x; i < n; i += (int64_t)gridDim.x * 256)
+        out[i] = v;
 }
 
 __global__ __launch_bounds__(256) void k_inv_sqrt_to(int64_t n, const double* d, double* out,
@@ -818,6 +910,29 @@ template int launch_mg_prep<uint16_t>(hipStream_t, int64_t, int, const double*, 
                                       double*, double*, const double*, const double*, uint16_t*,
                                       uint16_t*, const float*, float, double*);
 
+int launch_deflate(hipStream_t st, int64_t n, double alpha, double mtot, const double* m,
+                   const double* r, const double* q, double* z, double* sums, double* zpart,
+                   int max_blocks) {
+    const unsigned G = gs_grid(n) < 256u ? gs_grid(n) : 256u;
+    hipLaunchKernelGGL(k_defl_sums, dim3(G), dim3(256), 0, st, n, r, q, m, z, sums);
+    unsigned G2 = gs_grid(n);
+    if ((int)G2 > max_blocks) G2 = (unsigned)max_blocks;
+    hipLaunchKernelGGL(k_defl_apply, dim3(G2), dim3(256), 0, st, n, sums, (int)G, alpha, mtot, r, q, z,
+                       zpart);
+    TBDG_HIP(hipGetLastError());
+    return (int)G2;
+}
+
+void launch_deflate_start(hipStream_t st, int64_t n, double alpha, double mtot, const double* m,
+                          double* x, double* r, double* sums) {
+    const unsigned G = gs_grid(n) < 256u ? gs_grid(n) : 256u;
+    hipLaunchKernelGGL(k_defl_sums, dim3(G), dim3(256), 0, st, n, r, (const double*)nullptr, m,
+                       (const double*)nullptr, sums);
+    hipLaunchKernelGGL(k_defl_start, dim3(gs_grid(n)), dim3(256), 0, st, n, sums, (int)G, alpha, mtot, m,
+                       x, r);
+    TBDG_HIP(hipGetLastError());
+}
+
 void launch_mg_beta(hipStream_t st, const double* partial, int G, double* sc, int first, int slot,
                     int slot_prev) {
     hipLaunchKernelGGL(k_mg_beta, dim3(1), dim3(256), 0, st, partial, G, sc, first, slot,
@@ -856,6 +971,11 @@ void launch_vel_prep(hipStream_t st, int64_t Nc, int nb, int dim, int comp, cons
 
 void vec_mul(hipStream_t st, int64_t n, const double* a, const double* b, double* out) {
     hipLaunchKernelGGL(k_mul3, dim3(gs_grid(n)), dim3(256), 0, st, n, a, b, out);
+    TBDG_HIP(hipGetLastError());
+}
+
+void vec_fill(hipStream_t st, int64_t n, double v, double* out) {
+    hipLaunchKernelGGL(k_fill, dim3(gs_grid(n)), dim3(256), 0, st, n, v, out);
     TBDG_HIP(hipGetLastError());
 }
 
