@@ -149,6 +149,31 @@ def test_fused_coarse_cycle_matches_level_by_level(mp, stage):
         ref.close()
 
 
+@pytest.mark.parametrize("dim,n,k,per", [(2, 32, 4, (0, 0)), (2, 32, 4, (1, 1)), (3, 12, 3, (1, 1, 1)),
+                                          (3, 8, 3, (0, 0, 0))])
+def test_bf16_solves_converge_without_fallback(dim, n, k, per):
+    """Random right-hand sides (with a mean) on square boxes: the BF16 cycle
+    with the exact constant mode converges without the FP32 restart, within
+    a few iterations of the FP32 cycle."""
+    from paper_2107_07776_amd import Context
+    L = 2 * math.pi
+    ctx = Context(dim, (n,) * dim, (0.0,) * dim, (L,) * dim, k=k, nu=0.025, dt=0.04, periodic=per)
+    try:
+        ctx.mg_setup(degree=5)
+        for s in (1, 2):
+            b = torch.tensor(synthetic.random_vector(ctx.N_p, 40 + s), device="cuda")
+            its = {}
+            for prec in ("mg_fp32", "mg_bf16"):
+                x = torch.zeros_like(b)
+                info = ctx.solve_pressure(s, b, x, tol=1e-8, maxiter=200, precond=prec)
+                assert info["res_final"] <= 1e-8 and info["precond_fallbacks"] == 0, (prec, info)
+                its[prec] = info["iters"]
+            print(f"d{dim} {n} k{k} periodic {per} stage {s}: {its}")
+            assert its["mg_bf16"] <= 2 * its["mg_fp32"], its
+    finally:
+        ctx.close()
+
+
 def test_single_level_mesh_is_rejected():
     from paper_2107_07776_amd import Context
     from paper_2107_07776_amd.trbdg import TrbdgError
