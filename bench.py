@@ -459,7 +459,7 @@ def main():
     ap.add_argument("--train-steps", type=int, default=30)
     ap.add_argument("--epochs", type=int, default=12)
     ap.add_argument("--restart", type=int, default=None,
-                    help="GMRES restart length of the timed solver (default: 4; 30 on the Kovasznay mesh)")
+                    help="GMRES restart length of the timed solver (default: 6; 30 on the Kovasznay mesh)")
     ap.add_argument("--mom-precond", default=None, choices=["jacobi", "line", "mg_fp32"],
                     help="momentum preconditioner of the timed solver (default: line blocks; FP32 "
                          "velocity multigrid on the Kovasznay mesh; on mapped cells both use the "
@@ -496,7 +496,7 @@ def main():
         W["nonlinear"] = args.nonlinear
     ctx = make_context(W)
     if args.restart is None:
-        args.restart = W.get("restart", 4)
+        args.restart = W.get("restart", 6)
     if args.mom_precond is None:
         args.mom_precond = W.get("mom_precond", "line")
     ctx.set_nonlinear(W["nonlinear"], 0.0)

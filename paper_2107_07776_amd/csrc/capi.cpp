@@ -10,8 +10,6 @@
 namespace trbdg {
 void build_tables(tbdg_ctx* c);
 void build_line_operators(tbdg_ctx* c);
-tbdg_status solve_momentum(tbdg_ctx* c, int s, const double* w, const double* b, double* x,
-                           const tbdg_solver_opts& o, tbdg_solve_info* info);
 tbdg_status solve_pressure(tbdg_ctx* c, int s, const double* b, double* x,
                            const tbdg_solver_opts& o, tbdg_solve_info* info);
 void extrapolate(tbdg_ctx* c, int s, const double* u_new, const double* u_old, double* w);
@@ -553,6 +551,7 @@ tbdg_status tbdg_precond_momentum(tbdg_ctx* c, int stage, const double* w, const
         require(v != z, "v and z must not alias");
         trbdg::launch_diag_momentum(c, stage, w, c->diag_u);
         const double* d = trbdg::build_mom_lineprec(c, stage, w);
+        c->lineprec_stage = 0;   // built for this w, not a stage's advector
         trbdg::launch_mom_lineprec(c, c->mom_blk, d, v, nullptr, z);
         return TBDG_OK;
     });

@@ -374,6 +374,8 @@ struct tbdg_ctx {
     trbdg::MGData* mg = nullptr;    // multigrid hierarchy (built on first use)
     trbdg::MGData* mgu = nullptr;   // velocity-component hierarchy (momentum solves, lazy)
     bool mg_graphs = true;          // replay the solvers' V-cycles as captured HIP graphs
+    int lineprec_stage = 0;         // stage the momentum line blocks were last built for
+    bool reuse_lineprec = true;     // later fixed-point solves of a stage keep them
     hipStream_t cap_stream = nullptr;  // private stream the captures are recorded on (lazy)
     tbdg_mg_desc mg_desc{};         // parameters of the last tbdg_mg_setup (zeros: defaults)
     trbdg::GuessState* gs = nullptr;   // initial-guess history and network
@@ -648,6 +650,10 @@ void net_infer(tbdg_net* net, const float* x, float* y, int nx, int ny, int nz);
 hipStream_t net_stream(const tbdg_net* net);
 
 // ---- multigrid host side (mg.cpp) ---------------------------------------------------
+// momentum GMRES (solvers.cpp); reuse_prec: a later fixed-point solve of the
+// stage whose line blocks were built by the previous one keeps them
+tbdg_status solve_momentum(tbdg_ctx* c, int s, const double* w, const double* b, double* x,
+                           const tbdg_solver_opts& o, tbdg_solve_info* info, bool reuse_prec = false);
 void mg_setup(tbdg_ctx* c, const tbdg_mg_desc* desc);
 void mg_free(tbdg_ctx* c);
 // z = B r, one V-cycle (precision 1: FP32, 2: BF16 storage on the finest level)

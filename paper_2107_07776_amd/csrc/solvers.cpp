@@ -84,18 +84,29 @@ struct MomentumOp {
 
 // ---------------------------------------------------------------------------
 tbdg_status solve_momentum(tbdg_ctx* c, int s, const double* w, const double* b, double* x,
-                           const tbdg_solver_opts& o, tbdg_solve_info* info) {
+                           const tbdg_solver_opts& o, tbdg_solve_info* info, bool reuse_prec) {
     const int64_t n = c->Nu;
     const int m = std::min(o.restart > 0 ? o.restart : 30, c->gm_m);
     MomentumOp A{c, s, w};
     const bool line = o.precond == TBDG_PRECOND_LINE;
     const bool mgp = o.precond == TBDG_PRECOND_MG_FP32;
     // line blocks and multigrid are applied by their own kernels into gz;
-    // the Jacobi scaling inside the operator kernel
+    // the Jacobi scaling inside the operator kernel (the only user of D^{-1})
     const bool pc = line || mgp;
-    launch_diag_momentum(c, s, w, c->diag_u);
-    vec_recip(c->stream, c->Ns, c->diag_u, c->invd_u);
-    const double* dprec = line ? build_mom_lineprec(c, s, w) : nullptr;
+    const double* dprec = nullptr;
+    if (line && reuse_prec && c->lineprec_stage == s) {
+        // a later fixed-point solve of the same stage: the blocks built for
+        // the previous advector stay a fixed preconditioner of this one
+        dprec = c->mapped ? c->mom_dbox : c->diag_u;
+    } else if (!mgp) {
+        launch_diag_momentum(c, s, w, c->diag_u);
+        if (line) {
+            dprec = build_mom_lineprec(c, s, w);
+            c->lineprec_stage = s;
+        } else {
+            vec_recip(c->stream, c->Ns, c->diag_u, c->invd_u);
+        }
+    }
     if (mgp) mgu_ensure(c);
     auto apply_pc = [&](const double* in, const double* sc_dev, double* out, bool acc) {
         if (line) launch_mom_lineprec(c, c->mom_blk, dprec, in, sc_dev, out, acc);
@@ -443,7 +454,7 @@ tbdg_status momentum_stage(tbdg_ctx* c, int s, const double* u_n, const double* 
             launch_dirichlet_rhs(c, s, c->s_w, c->s_u1);
             b = c->s_u1;
         }
-        rc = solve_momentum(c, s, c->s_w, b, c->s_ustar, mo, &one);
+        rc = solve_momentum(c, s, c->s_w, b, c->s_ustar, mo, &one, solves > 1 && c->reuse_lineprec);
         if (solves == 1) acc.res0 = one.res0;
         acc.iters += one.iters;
         acc.res_final = one.res_final;
