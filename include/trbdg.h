@@ -279,11 +279,15 @@ typedef struct {
     double safety;       /* 0 => 1.1                                            */
     int coarse_cells;    /* 0 => 64 (3D) / 16 (2D)                              */
     int max_coarse_dofs; /* largest coarsest level solved densely (0 => 2048)    */
-    int no_fuse;         /* 0: the longest run of Q1 levels below level 0 (down to
-                            the coarsest) whose FP32 vectors fit one workgroup's
-                            LDS runs as one single-workgroup launch per V-cycle
-                            (same smoother, transfers and coarse solve);
-                            1: every level launched on its own                 */
+    int no_fuse;         /* 0: in 2D the longest run of Q1 levels below level 0
+                            (down to the coarsest) whose FP32 vectors fit one
+                            workgroup's LDS runs as one single-workgroup launch
+                            per V-cycle (same smoother, transfers and coarse
+                            solve), in 3D every level is launched on its own
+                            (there the single workgroup is slower: 101 against
+                            ~65 us per cycle on the 64^3 vortex's 8^3 and 4^3
+                            levels); 1: every level on its own; 2: the single
+                            workgroup in 2D and 3D                              */
 } tbdg_mg_desc;
 
 /* (Re)builds the hierarchy for both stages (desc NULL: defaults).  Fails

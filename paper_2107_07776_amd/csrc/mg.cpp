@@ -458,6 +458,7 @@ namespace {
 
 // Builds the whole hierarchy into M (allocations recorded in M.allocs).
 void mg_build(tbdg_ctx* c, MGData& M, const tbdg_mg_desc* desc) {
+    M.no_fuse = c->dim == 3;   // the default; desc->no_fuse overrides
     M.coarse_cells = c->dim == 3 ? 64 : 16;
     if (desc) {
         if (desc->degree) M.degree = desc->degree;
@@ -466,7 +467,8 @@ void mg_build(tbdg_ctx* c, MGData& M, const tbdg_mg_desc* desc) {
         if (desc->safety > 0.0) M.safety = desc->safety;
         if (desc->coarse_cells) M.coarse_cells = desc->coarse_cells;
         if (desc->max_coarse_dofs) M.max_coarse = desc->max_coarse_dofs;
-        M.no_fuse = desc->no_fuse != 0;
+        if (desc->no_fuse < 0 || desc->no_fuse > 2) throw Error(TBDG_EINVAL, "no_fuse must be 0, 1 or 2");
+        M.no_fuse = desc->no_fuse == 1 || (desc->no_fuse == 0 && c->dim == 3);
     }
     if (M.degree < 2 || M.degree >= MG_MAXDEG) throw Error(TBDG_EINVAL, "multigrid degree must be in [2, 15]");
     if (M.lanczos_steps < 1 || M.range <= 1.0 || M.safety < 1.0 || M.coarse_cells < 1)

@@ -313,8 +313,8 @@ __global__ __launch_bounds__(256) void k_coarse(const double* __restrict__ Ainv,
 // Every Q1 level from fc.lv[0] down to the coarsest lives in LDS; each
 // smoother step, transfer and the coarse solve is one pass of the block's
 // 1024 threads over the level's nodes, separated by block barriers.  The
-// per-node arithmetic is k_level's, k_restrict's / k_prolong's (h-transfer)
-// and k_coarse's.
+// per-node arithmetic is k_level's and k_restrict's / k_prolong's
+// (h-transfer); the coarse solve multiplies by the same FP64 inverse.
 
 // neighbour of a cell with coordinates ci along direction a, side s (0 left,
 // 1 right), or -1 at a wall
@@ -521,17 +521,18 @@ __global__ __launch_bounds__(fz_threads<DIM>()) void k_fused_cycle(FusedCycle fc
         }
         __syncthreads();
     }
-    // coarsest: x = H^{-1} b with the FP64 inverse, one wave per row
+    // coarsest: x = H^{-1} b with the FP64 inverse, one thread per row; the
+    // inverse is symmetric (stored so), so thread `row` walks column `row`
+    // and a wave's loads of one j are contiguous and all independent
     {
         const FusedLv& C = fc.lv[nl - 1];
         const float* b = lds + C.off + 2 * C.N;
         float* x = lds + C.off;
-        const int lane = tid & 63, wv = tid >> 6;
-        for (int row = wv; row < C.N; row += NT / 64) {
+        for (int row = tid; row < C.N; row += NT) {
             double acc = 0.0;
-            for (int j = lane; j < C.N; j += 64) acc += fc.ainv[(size_t)row * C.N + j] * (double)b[j];
-            acc = red::wave_sum(acc);
-            if (lane == 0) x[row] = (float)acc;
+#pragma unroll 8
+            for (int j = 0; j < C.N; ++j) acc += fc.ainv[(size_t)j * C.N + row] * (double)b[j];
+            x[row] = (float)acc;
         }
         __syncthreads();
     }

@@ -411,11 +411,13 @@ class Context:
         self._check(self.lib.tbdg_set_scheme(self.h, SCHEME[scheme]))
 
     def mg_setup(self, degree=0, lanczos_steps=0, range_=0.0, safety=0.0, coarse_cells=0,
-                 max_coarse_dofs=0, fuse=True):
+                 max_coarse_dofs=0, fuse="auto"):
         """Build the pressure multigrid hierarchy (0 = library default; fuse:
-        the coarse Q1 levels in one single-workgroup launch per V-cycle)."""
+        the coarse Q1 levels in one single-workgroup launch per V-cycle,
+        "auto" in 2D only, True in 2D and 3D, False never)."""
+        nf = 0 if fuse == "auto" else (2 if fuse else 1)
         d = MGDesc(int(degree), int(lanczos_steps), float(range_), float(safety), int(coarse_cells),
-                   int(max_coarse_dofs), 0 if fuse else 1)
+                   int(max_coarse_dofs), nf)
         self._check(self.lib.tbdg_mg_setup(self.h, ctypes.byref(d)))
 
     def mg_levels(self, cap=16, field="p"):

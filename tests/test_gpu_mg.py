@@ -52,7 +52,7 @@ class MGPair:
         from paper_2107_07776_amd import Context
         print(f"[case] multigrid dim={dim} cells={nc} k={k} coarse_cells={coarse}", flush=True)
         self.gpu = Context(dim, nc, (0.0,) * dim, ext, k=k, nu=nu, dt=dt)
-        self.gpu.mg_setup(degree=3, coarse_cells=coarse)
+        self.gpu.mg_setup(degree=3, coarse_cells=coarse, fuse=True)
         self.gpu._coarse_cells = coarse
         mesh = BoxMesh(dim, nc, (0.0,) * dim, ext, (True,) * dim)
         self.disc = Discretization(mesh, k, nu=nu)
@@ -172,6 +172,22 @@ def test_bf16_solves_converge_without_fallback(dim, n, k, per):
             assert its["mg_bf16"] <= 2 * its["mg_fp32"], its
     finally:
         ctx.close()
+
+
+def test_fusion_default_by_dimension():
+    """By default the coarse levels share one workgroup in 2D, not in 3D."""
+    from paper_2107_07776_amd import Context
+    c2 = Context(2, (16, 16), (0.0, 0.0), (1.0, 1.0), k=3, nu=0.01, dt=0.01)
+    c3 = Context(3, (8, 8, 8), (0.0,) * 3, (1.0,) * 3, k=3, nu=0.01, dt=0.01)
+    try:
+        c2.mg_setup(degree=3)
+        c3.mg_setup(degree=3, coarse_cells=8)
+        assert c2.mg_fused()[0] >= 1 and c3.mg_fused() == (-1, 0)
+        c3.mg_setup(degree=3, coarse_cells=8, fuse=True)
+        assert c3.mg_fused()[0] >= 1
+    finally:
+        c2.close()
+        c3.close()
 
 
 def test_single_level_mesh_is_rejected():
