@@ -63,11 +63,24 @@ __global__ __launch_bounds__(BS) void k_dot_many(int64_t n, const double* V, int
     if (threadIdx.x == 0) partial[(int64_t)j * gridDim.x + blockIdx.x] = acc;
 }
 
+// this thread's share of sum_b p[b] (b = tid, tid + BS, ...): eight
+// independent sums keep eight loads in flight (an operator kernel leaves one
+// partial per block, 65 536 at 64^3 Q3), combined in a fixed order
+__device__ inline double thread_sum(const double* p, int G) {
+    double a[8] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
+    int b = threadIdx.x;
+    for (; b + 7 * BS < G; b += 8 * BS) {
+#pragma unroll
+        for (int q = 0; q < 8; ++q) a[q] += p[b + q * BS];
+    }
+    for (int q = 0; b < G; b += BS, ++q) a[q & 7] += p[b];
+    return ((a[0] + a[1]) + (a[2] + a[3])) + ((a[4] + a[5]) + (a[6] + a[7]));
+}
+
 // out[j] = sum_b partial[j * G + b]
 __global__ __launch_bounds__(BS) void k_finish(const double* partial, int G, double* out) {
     const int j = blockIdx.x;
-    double acc = 0.0;
-    for (int b = threadIdx.x; b < G; b += BS) acc += partial[(int64_t)j * G + b];
+    double acc = thread_sum(partial + (int64_t)j * G, G);
     acc = block_sum(acc);
     if (threadIdx.x == 0) out[j] = acc;
 }
@@ -325,8 +338,7 @@ __global__ __launch_bounds__(BS) void k_gm_restart(int64_t n, int dim, int64_t n
 __global__ __launch_bounds__(BS) void k_finish_gs(const double* partial, int G, int k,
                                                   const double* gsc, double* out, double* hout) {
     const int j = blockIdx.x;
-    double acc = 0.0;
-    for (int b = threadIdx.x; b < G; b += BS) acc += partial[(int64_t)j * G + b];
+    double acc = thread_sum(partial + (int64_t)j * G, G);
     acc = block_sum(acc);
     if (threadIdx.x == 0) {
         const double v = j < k ? gsc[j] * acc : acc;
