@@ -4,8 +4,9 @@
 // Jacobi diagonal, the line blocks, or FP32 multigrid V-cycles of the
 // operator's symmetric part on each component; classical Gram-Schmidt through one multi-vector dot kernel
 // and one update kernel that also returns the new norm, repeated once when
-// the norm drops below 1/sqrt(2) of its value before orthogonalisation
-// (the "twice is enough" criterion); Givens rotations on the host.
+// the norm drops below 1/sqrt(10) of its value before orthogonalisation (a
+// looser form of the "twice is enough" test, enough for short restarts);
+// Givens rotations on the host.
 // CG (Helmholtz): Jacobi-preconditioned, three kernels per iteration
 // (direction, operator fused with p.q and the step length, update fused with
 // r.z, r.r and the next beta); all scalars stay on the device and the host
@@ -202,7 +203,10 @@ tbdg_status solve_momentum(tbdg_ctx* c, int s, const double* w, const double* b,
                 for (int i = 0; i <= j; ++i) h[i] += c->host_out[i];
                 const double ww = c->host_out[j + 1];
                 nn = c->host_out[62];
-                if (!(nn < 0.5 * ww)) break;   // |w'| >= |w| / sqrt(2): twice is not needed
+                // one classical pass leaves an orthogonality error of about
+                // eps |w|^2 / |w'|^2; up to a cancellation of |w'|^2 = |w|^2 / 10
+                // that is ~10 eps, which a restart of a few vectors cannot feel
+                if (!(nn < 0.1 * ww)) break;
             }
             const double hn = std::sqrt(nn);
             for (int i = 0; i <= j; ++i) H[i * m + j] = h[i];
