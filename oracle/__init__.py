@@ -23,6 +23,9 @@ Navier-Stokes equations", arXiv 2107.07776):
                  Quartapelle (BDF2) projection steps of Sec. 2 on the same
                  forms (eq. momentum_BCG, helmholtz_BCG, momentum_HI,
                  helmholtz_HI).
+* ``adaptive`` - 2D quadtree meshes with hanging nodes, a_p and M^p on
+                 them, the refinement indicator, marking and field transfer
+                 of the adaptive runs of Sec. 4.
 
 Closed-form reference fields (Taylor-Green, Kovasznay) live in the separate
 ``synthetic`` package, which holds no arithmetic of the method.
