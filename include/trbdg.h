@@ -561,6 +561,82 @@ TBDG_API tbdg_status tbdg_profile_read(tbdg_ctx* ctx, int which, double* total_m
  * timed for `which` since the previous call (host output), then reset.     */
 TBDG_API tbdg_status tbdg_profile_bytes(tbdg_ctx* ctx, int which, double* bytes);
 
+/* ------------------------------------------------------------------------
+ * Adaptive 2D meshes with hanging nodes (Sec. 4, the adaptive runs: the
+ * indicator eta_K = diam(K)^2 ||omega||^2_K, refinement of the 10 % of
+ * cells with the largest indicator and coarsening of the 30 % with the
+ * smallest, bounded element sizes).
+ *
+ * A quadtree over every cell of an n_cells[0] x n_cells[1] box; the leaves
+ * (level l, integer position i, j: the cell [i, i+1] x [j, j+1] in units of
+ * the base cell size / 2^l) stay 2:1 balanced across faces, so a face meets
+ * at most two cells of half its size.  Cells are ordered by base cell (x
+ * fastest), then by the Morton index (x bit below y bit) of their lower-left
+ * corner at level max_level.  Fields use the layouts of the box mesh:
+ * velocity [cell][component][node], pressure [cell][node], nodes the
+ * (k+1)^2 resp. k^2 Gauss-Legendre points of the cell, x fastest.  Vectors
+ * are device pointers on the handle's device, used on its stream; the mesh
+ * itself (the forest) is host data of the handle.
+ * ------------------------------------------------------------------------ */
+typedef struct tbdg_amr tbdg_amr;
+typedef struct {
+    int n_cells[2];     /* base grid, >= 1; >= 2 in a periodic direction     */
+    double lo[2], hi[2];
+    int periodic[2];    /* non-periodic ends: pressure faces without terms
+                           (homogeneous Neumann)                               */
+    int k;              /* velocity degree 1..7 (pressure k - 1)             */
+    int max_level;      /* deepest level, 0..20, n_cells[a] << max_level < 2^29 */
+    double pen_p;       /* multiplier of the pressure SIP penalty (1 = paper) */
+} tbdg_amr_desc;
+
+/* The base grid (every cell at level 0) on the current device; hip_stream
+ * may be NULL (default stream).  Errors: TBDG_EINVAL for a bad descriptor. */
+TBDG_API tbdg_status tbdg_amr_create(const tbdg_amr_desc* desc, void* hip_stream, tbdg_amr** out);
+TBDG_API void tbdg_amr_destroy(tbdg_amr* amr);
+TBDG_API const char* tbdg_amr_last_error(const tbdg_amr* amr);
+TBDG_API tbdg_status tbdg_amr_set_stream(tbdg_amr* amr, void* hip_stream);
+/* Cell count and the velocity / pressure vector lengths of the current mesh. */
+TBDG_API tbdg_status tbdg_amr_sizes(const tbdg_amr* amr, int64_t* n_cells, int64_t* n_u,
+                                    int64_t* n_p);
+/* (level, i, j) of every cell, host array of 3 n_cells int32.              */
+TBDG_API tbdg_status tbdg_amr_leaves(const tbdg_amr* amr, int32_t* lij);
+
+/* y = (alpha M^p + K) p with a_p of Sec. 3 on the adapted mesh: on a face
+ * shared by a coarse and two fine cells every integral is the sum over the
+ * two fine faces with their Gauss rule, the coarse traces evaluated there;
+ * penalty C = average of the two cells' k^2 pen_p / h_a.  p, y distinct.  */
+TBDG_API tbdg_status tbdg_amr_apply_pressure(tbdg_amr* amr, double alpha, const double* p, double* y);
+/* d = diag(alpha M^p + K).                                                 */
+TBDG_API tbdg_status tbdg_amr_diag_pressure(tbdg_amr* amr, double alpha, double* d);
+/* Jacobi-preconditioned CG for (alpha M^p + K) x = b from the given x
+ * (alpha > 0), FP64 throughout, to ||b - A x|| <= tol ||b||.  Errors:
+ * TBDG_ENOTCONV, TBDG_EBREAKDOWN, TBDG_ENAN; x holds the last iterate.      */
+TBDG_API tbdg_status tbdg_amr_solve_pressure(tbdg_amr* amr, double alpha, const double* b, double* x,
+                                             double tol, int maxiter, tbdg_solve_info* info);
+/* eta[c] = (h_x^2 + h_y^2) int_K (d_x u_y - d_y u_x)^2 (the diagonal as
+ * diam(K); the velocity Gauss rule, exact for the squared vorticity).      */
+TBDG_API tbdg_status tbdg_amr_indicator(tbdg_amr* amr, const double* u, double* eta);
+/* Fixed-fraction marking from eta (device): the floor(refine_frac N) cells
+ * of largest eta (ties: lower index first) get +1 unless their children's
+ * larger edge would fall below h_min or the level is max_level; of the
+ * others, the floor(coarsen_frac N) of smallest eta get -1 unless the
+ * parent's larger edge would exceed h_max or the level is 0; the rest 0.
+ * flags: host array of N int8.  Errors: TBDG_ENAN for a NaN indicator.     */
+TBDG_API tbdg_status tbdg_amr_mark(tbdg_amr* amr, const double* eta, double refine_frac,
+                                   double coarsen_frac, double h_min, double h_max, int8_t* flags);
+/* Remeshing in three calls, so that the caller owns every vector:
+ * tbdg_amr_plan builds the adapted forest from host flags (> 0 refine, < 0
+ * coarsen; refinement spreads to coarser face neighbours until balanced; a
+ * family of four flagged, unrefined leaves is coarsened unless a face
+ * neighbour would end finer than the family's leaves) and returns its cell
+ * count; tbdg_amr_transfer moves a field (0: velocity, 1: pressure) from
+ * the current mesh to the planned one (kept cells copy, children
+ * interpolate their parent's polynomial, a parent is the L2 projection of
+ * its four children); tbdg_amr_commit makes the planned mesh current.      */
+TBDG_API tbdg_status tbdg_amr_plan(tbdg_amr* amr, const int8_t* flags, int64_t* new_cells);
+TBDG_API tbdg_status tbdg_amr_transfer(tbdg_amr* amr, int field, const double* src, double* dst);
+TBDG_API tbdg_status tbdg_amr_commit(tbdg_amr* amr);
+
 #ifdef __cplusplus
 }
 #endif

@@ -4,6 +4,6 @@ The computation lives in the HIP library ``libtrbdg.so`` (sources in
 ``csrc/``, C interface in ``include/trbdg.h``); ``trbdg`` is its thin ctypes
 binding.
 """
-from .trbdg import (Context, Net, TrbdgError, load_library, solver_opts, EXPORTED, LIB_PATH)
+from .trbdg import (Adaptive, Context, Net, TrbdgError, load_library, solver_opts, EXPORTED, LIB_PATH)
 
-__all__ = ["Context", "Net", "TrbdgError", "load_library", "solver_opts", "EXPORTED", "LIB_PATH"]
+__all__ = ["Adaptive", "Context", "Net", "TrbdgError", "load_library", "solver_opts", "EXPORTED", "LIB_PATH"]

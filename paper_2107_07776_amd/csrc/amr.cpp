@@ -1,0 +1,679 @@
+// Adaptive 2D quadrilateral meshes with hanging nodes (the adaptive runs of
+// Sec. 4): the forest of quadtrees on the host, its device view, the
+// refinement indicator, fixed-fraction marking, remeshing with field
+// transfer, and the pressure Helmholtz operator and its Jacobi CG solve on
+// the adapted mesh; the C ABI of all of it.
+//
+// The forest lives on the host: remeshing happens every few hundred or
+// thousand steps and is integer bookkeeping over the cell list, while every
+// per-DoF operation (operators, indicator, transfer, reductions) runs in the
+// kernels of amr.hip on the device view built here after each remesh.
+#include <algorithm>
+#include <cmath>
+#include <cstring>
+#include <new>
+#include <string>
+#include <unordered_map>
+#include <vector>
+
+#include "amr.hpp"
+#include "internal.hpp"
+
+using trbdg::Error;
+namespace A = trbdg::amr;
+
+namespace {
+
+struct Leaf {
+    int l, i, j;
+};
+
+inline uint64_t pack(int l, int i, int j) {
+    return ((uint64_t)l << 58) | ((uint64_t)(uint32_t)i << 29) | (uint64_t)(uint32_t)j;
+}
+
+inline uint64_t morton(uint64_t x, uint64_t y, int bits) {
+    uint64_t m = 0;
+    for (int b = 0; b < bits; ++b) {
+        m |= ((x >> b) & 1u) << (2 * b);
+        m |= ((y >> b) & 1u) << (2 * b + 1);
+    }
+    return m;
+}
+
+struct Nb {
+    int kind;      // A::FACE_*
+    int n0, n1;    // neighbour, or the two finer ones (tangential halves 0, 1)
+    int half;      // FACE_COARSER: the half of the neighbour's face
+};
+
+struct Forest {
+    int nc[2] = {0, 0};
+    double lo[2] = {0, 0}, H[2] = {0, 0};
+    int per[2] = {0, 0};
+    int maxl = 0;
+    std::vector<Leaf> leaves;
+    std::unordered_map<uint64_t, int> index;
+
+    std::pair<int64_t, uint64_t> key(const Leaf& c) const {
+        const int tx = c.i >> c.l, ty = c.j >> c.l;
+        const uint64_t li = (uint64_t)(c.i - (tx << c.l)) << (maxl - c.l);
+        const uint64_t lj = (uint64_t)(c.j - (ty << c.l)) << (maxl - c.l);
+        return {(int64_t)ty * nc[0] + tx, morton(li, lj, maxl)};
+    }
+
+    void finalize() {
+        std::sort(leaves.begin(), leaves.end(),
+                  [&](const Leaf& a, const Leaf& b) { return key(a) < key(b); });
+        index.clear();
+        index.reserve(leaves.size() * 2);
+        for (size_t n = 0; n < leaves.size(); ++n)
+            index[pack(leaves[n].l, leaves[n].i, leaves[n].j)] = (int)n;
+    }
+
+    int find(int l, int i, int j) const {
+        auto it = index.find(pack(l, i, j));
+        return it == index.end() ? -1 : it->second;
+    }
+
+    double size(int c, int a) const { return H[a] / (double)(1 << leaves[c].l); }
+
+    Nb neighbours(int c, int a, int s) const {
+        const Leaf& L = leaves[c];
+        int ij[2] = {L.i, L.j};
+        ij[a] += s ? 1 : -1;
+        const int n = nc[a] << L.l;
+        if (ij[a] < 0 || ij[a] >= n) {
+            if (!per[a]) return {A::FACE_BOUNDARY, -1, -1, 0};
+            ij[a] = (ij[a] % n + n) % n;
+        }
+        int o = find(L.l, ij[0], ij[1]);
+        if (o >= 0) return {A::FACE_SAME, o, -1, 0};
+        if (L.l > 0) {
+            o = find(L.l - 1, ij[0] >> 1, ij[1] >> 1);
+            if (o >= 0) return {A::FACE_COARSER, o, -1, ij[1 - a] & 1};
+        }
+        int kids[2];
+        for (int h = 0; h < 2; ++h) {
+            int ch[2] = {2 * ij[0], 2 * ij[1]};
+            ch[a] += s ? 0 : 1;
+            ch[1 - a] += h;
+            kids[h] = find(L.l + 1, ch[0], ch[1]);
+            if (kids[h] < 0) throw Error(TBDG_EINVAL, "adaptive mesh is not 2:1 balanced");
+        }
+        return {A::FACE_FINER, kids[0], kids[1], 0};
+    }
+
+    void face_leaves(int c, std::vector<int>& out) const {
+        out.clear();
+        for (int a = 0; a < 2; ++a)
+            for (int s = 0; s < 2; ++s) {
+                const Nb nb = neighbours(c, a, s);
+                if (nb.kind == A::FACE_SAME || nb.kind == A::FACE_COARSER) out.push_back(nb.n0);
+                else if (nb.kind == A::FACE_FINER) {
+                    out.push_back(nb.n0);
+                    out.push_back(nb.n1);
+                }
+            }
+    }
+
+    // The adapted forest: flags > 0 refine, < 0 coarsen; refinement spreads
+    // to coarser face neighbours until the refined mesh is balanced; a family
+    // of four flagged, unrefined leaves is coarsened unless a face neighbour
+    // would end finer than the family's leaves (families dropped until the
+    // set is consistent with the final levels).
+    Forest adapt(const int8_t* flags) const {
+        const int N = (int)leaves.size();
+        std::vector<char> ref(N, 0);
+        std::vector<int> work, nbs;
+        for (int c = 0; c < N; ++c)
+            if (flags[c] > 0 && leaves[c].l < maxl) {
+                ref[c] = 1;
+                work.push_back(c);
+            }
+        while (!work.empty()) {
+            const int c = work.back();
+            work.pop_back();
+            face_leaves(c, nbs);
+            for (int o : nbs)
+                if (leaves[o].l < leaves[c].l && !ref[o]) {
+                    ref[o] = 1;
+                    work.push_back(o);
+                }
+        }
+        std::unordered_map<uint64_t, std::vector<int>> fam;
+        for (int c = 0; c < N; ++c) {
+            const Leaf& L = leaves[c];
+            if (L.l > 0 && flags[c] < 0 && !ref[c])
+                fam[pack(L.l - 1, L.i >> 1, L.j >> 1)].push_back(c);
+        }
+        std::vector<uint64_t> live;
+        for (auto& kv : fam)
+            if (kv.second.size() == 4) live.push_back(kv.first);
+        std::vector<uint64_t> member(N, ~(uint64_t)0);
+        for (;;) {
+            std::fill(member.begin(), member.end(), ~(uint64_t)0);
+            for (uint64_t p : live)
+                for (int c : fam[p]) member[c] = p;
+            std::vector<uint64_t> keep;
+            for (uint64_t p : live) {
+                bool ok = true;
+                for (int c : fam[p]) {
+                    face_leaves(c, nbs);
+                    for (int o : nbs) {
+                        if (member[o] == p) continue;
+                        const int fin = leaves[o].l + (ref[o] ? 1 : 0) - (member[o] != ~(uint64_t)0 ? 1 : 0);
+                        if (fin > leaves[c].l) ok = false;
+                    }
+                }
+                if (ok) keep.push_back(p);
+            }
+            if (keep.size() == live.size()) break;
+            live.swap(keep);
+        }
+        std::fill(member.begin(), member.end(), ~(uint64_t)0);
+        for (uint64_t p : live)
+            for (int c : fam[p]) member[c] = p;
+        Forest F;
+        std::memcpy(F.nc, nc, sizeof nc);
+        std::memcpy(F.lo, lo, sizeof lo);
+        std::memcpy(F.H, H, sizeof H);
+        std::memcpy(F.per, per, sizeof per);
+        F.maxl = maxl;
+        for (int c = 0; c < N; ++c) {
+            const Leaf& L = leaves[c];
+            if (ref[c]) {
+                for (int dj = 0; dj < 2; ++dj)
+                    for (int di = 0; di < 2; ++di) F.leaves.push_back({L.l + 1, 2 * L.i + di, 2 * L.j + dj});
+            } else if (member[c] != ~(uint64_t)0) {
+                // the family's parent, once (from its first child in (di, dj) order)
+                if ((L.i & 1) == 0 && (L.j & 1) == 0) F.leaves.push_back({L.l - 1, L.i >> 1, L.j >> 1});
+            } else {
+                F.leaves.push_back(L);
+            }
+        }
+        F.finalize();
+        return F;
+    }
+};
+
+void tab1(int n, A::Tab1& t) {
+    std::memset(&t, 0, sizeof t);
+    t.n = n;
+    trbdg::gauss_legendre(n, t.z, t.W);
+    auto val = [&](int j, double x) { return trbdg::lagrange_value(t.z, n, j, x); };
+    auto der = [&](int j, double x) {
+        // l_j'(x) by the product rule over the factors of l_j
+        double s = 0.0;
+        for (int m = 0; m < n; ++m) {
+            if (m == j) continue;
+            double term = 1.0 / (t.z[j] - t.z[m]);
+            for (int q = 0; q < n; ++q)
+                if (q != j && q != m) term *= (x - t.z[q]) / (t.z[j] - t.z[q]);
+            s += term;
+        }
+        return s;
+    };
+    for (int m = 0; m < n; ++m)
+        for (int j = 0; j < n; ++j) t.D[m * n + j] = der(j, t.z[m]);
+    for (int i = 0; i < n; ++i)
+        for (int j = 0; j < n; ++j) {
+            double s = 0.0;
+            for (int m = 0; m < n; ++m) s += t.W[m] * t.D[m * n + i] * t.D[m * n + j];
+            t.S[i * n + j] = s;
+        }
+    for (int j = 0; j < n; ++j) {
+        t.L[0][j] = val(j, 0.0);
+        t.L[1][j] = val(j, 1.0);
+        t.dL[0][j] = der(j, 0.0);
+        t.dL[1][j] = der(j, 1.0);
+    }
+    for (int h = 0; h < 2; ++h)
+        for (int q = 0; q < n; ++q)
+            for (int m = 0; m < n; ++m) t.T[h][q * n + m] = val(m, 0.5 * (h + t.z[q]));
+}
+
+template <typename T>
+T* devalloc(int64_t count) {
+    void* p = nullptr;
+    const hipError_t e = hipMalloc(&p, sizeof(T) * (size_t)(count > 0 ? count : 1));
+    if (e != hipSuccess) throw Error(TBDG_ENOMEM, std::string("hipMalloc: ") + hipGetErrorString(e));
+    return static_cast<T*>(p);
+}
+
+template <typename T>
+void devfree(T*& p) {
+    if (p) (void)hipFree(p);
+    p = nullptr;
+}
+
+}  // namespace
+
+struct tbdg_amr {
+    int device = 0;
+    hipStream_t stream = nullptr;
+    int k = 2;
+    double pen_p = 1.0;
+    Forest F, next;
+    bool planned = false;
+    A::Tab1 tp, tu;
+    int *level = nullptr, *meta = nullptr, *nbr = nullptr;
+    int64_t geo_cap = 0;
+    int *xkind = nullptr, *xsrc = nullptr;
+    int64_t x_cap = 0;
+    double *cg = nullptr;   // r, z, p, q, d
+    int64_t cg_cap = 0;
+    double* part = nullptr;
+    double* scal = nullptr;      // device scalars: rz[2], pq, rr, bb
+    double* host = nullptr;      // pinned
+    std::string last_error;
+
+    int64_t Nc() const { return (int64_t)F.leaves.size(); }
+    int64_t Np() const { return Nc() * k * k; }
+    int64_t Nu() const { return Nc() * 2 * (k + 1) * (k + 1); }
+
+    A::Geo geo() const {
+        A::Geo g;
+        g.level = level;
+        g.meta = meta;
+        g.nbr = nbr;
+        g.Nc = (int)Nc();
+        g.H[0] = F.H[0];
+        g.H[1] = F.H[1];
+        g.csig = (double)k * k * pen_p;
+        return g;
+    }
+
+    // device connectivity of the current forest
+    void upload() {
+        const int64_t N = Nc();
+        std::vector<int> lv(N), mt(4 * N), nb(8 * N, -1);
+        for (int64_t c = 0; c < N; ++c) {
+            lv[c] = F.leaves[c].l;
+            for (int a = 0; a < 2; ++a)
+                for (int s = 0; s < 2; ++s) {
+                    const int f = 2 * a + s;
+                    const Nb o = F.neighbours((int)c, a, s);
+                    mt[4 * c + f] = o.kind | (o.half << 4);
+                    nb[8 * c + 2 * f] = o.n0;
+                    nb[8 * c + 2 * f + 1] = o.n1;
+                }
+        }
+        if (N > geo_cap) {
+            devfree(level);
+            devfree(meta);
+            devfree(nbr);
+            const int64_t cap = std::max<int64_t>(N, geo_cap * 3 / 2);
+            level = devalloc<int>(cap);
+            meta = devalloc<int>(4 * cap);
+            nbr = devalloc<int>(8 * cap);
+            geo_cap = cap;
+        }
+        if (N > 0) {
+            TBDG_HIP(hipMemcpyAsync(level, lv.data(), sizeof(int) * N, hipMemcpyHostToDevice, stream));
+            TBDG_HIP(hipMemcpyAsync(meta, mt.data(), sizeof(int) * 4 * N, hipMemcpyHostToDevice, stream));
+            TBDG_HIP(hipMemcpyAsync(nbr, nb.data(), sizeof(int) * 8 * N, hipMemcpyHostToDevice, stream));
+        }
+        // the host vectors die here: wait for the copies
+        TBDG_HIP(hipStreamSynchronize(stream));
+    }
+
+    void free_all() {
+        devfree(level);
+        devfree(meta);
+        devfree(nbr);
+        devfree(xkind);
+        devfree(xsrc);
+        devfree(cg);
+        devfree(part);
+        devfree(scal);
+        if (host) (void)hipHostFree(host);
+        host = nullptr;
+    }
+};
+
+namespace {
+
+constexpr int DOT_BLOCKS = 1024;
+
+template <class F>
+tbdg_status aguard(tbdg_amr* m, F&& f) {
+    try {
+        if (m) TBDG_HIP(hipSetDevice(m->device));
+        return f();
+    } catch (const Error& e) {
+        if (m) m->last_error = e.what();
+        return e.status;
+    } catch (const std::bad_alloc&) {
+        if (m) m->last_error = "host allocation failed";
+        return TBDG_ENOMEM;
+    } catch (const std::exception& e) {
+        if (m) m->last_error = e.what();
+        return TBDG_EINVAL;
+    }
+}
+
+void need(bool ok, const char* msg) {
+    if (!ok) throw Error(TBDG_EINVAL, msg);
+}
+
+double dot(tbdg_amr* m, int64_t n, const double* a, const double* b, int slot) {
+    A::launch_amr_dot(m->stream, n, a, b, m->part, DOT_BLOCKS, m->scal + slot);
+    TBDG_HIP(hipMemcpyAsync(m->host, m->scal + slot, sizeof(double), hipMemcpyDeviceToHost, m->stream));
+    TBDG_HIP(hipStreamSynchronize(m->stream));
+    return m->host[0];
+}
+
+}  // namespace
+
+extern "C" {
+
+tbdg_status tbdg_amr_create(const tbdg_amr_desc* d, void* hip_stream, tbdg_amr** out) {
+    if (!out) return TBDG_EINVAL;
+    *out = nullptr;
+    if (!d) return TBDG_EINVAL;
+    tbdg_amr* m = nullptr;
+    try {
+        m = new tbdg_amr();
+    } catch (const std::bad_alloc&) {
+        return TBDG_ENOMEM;
+    }
+    const tbdg_status st = aguard(nullptr, [&]() {
+        for (int a = 0; a < 2; ++a) {
+            need(d->n_cells[a] >= 1, "n_cells must be >= 1");
+            need(std::isfinite(d->lo[a]) && std::isfinite(d->hi[a]) && d->lo[a] < d->hi[a],
+                 "need finite lo < hi");
+            need(!d->periodic[a] || d->n_cells[a] >= 2, "a periodic direction needs >= 2 base cells");
+        }
+        need(d->k >= 1 && d->k <= 7, "velocity degree k must be 1..7");
+        need(d->max_level >= 0 && d->max_level <= 20, "max_level must be 0..20");
+        for (int a = 0; a < 2; ++a)
+            need(((int64_t)d->n_cells[a] << d->max_level) < ((int64_t)1 << 29),
+                 "n_cells << max_level must stay below 2^29");
+        need(std::isfinite(d->pen_p) && d->pen_p >= 0.0, "pen_p must be finite and >= 0");
+        TBDG_HIP(hipGetDevice(&m->device));
+        m->stream = static_cast<hipStream_t>(hip_stream);
+        m->k = d->k;
+        m->pen_p = d->pen_p;
+        Forest& F = m->F;
+        for (int a = 0; a < 2; ++a) {
+            F.nc[a] = d->n_cells[a];
+            F.lo[a] = d->lo[a];
+            F.H[a] = (d->hi[a] - d->lo[a]) / d->n_cells[a];
+            F.per[a] = d->periodic[a] != 0;
+        }
+        F.maxl = d->max_level;
+        for (int j = 0; j < F.nc[1]; ++j)
+            for (int i = 0; i < F.nc[0]; ++i) F.leaves.push_back({0, i, j});
+        F.finalize();
+        tab1(m->k, m->tp);
+        tab1(m->k + 1, m->tu);
+        m->part = devalloc<double>(DOT_BLOCKS);
+        m->scal = devalloc<double>(8);
+        TBDG_HIP(hipHostMalloc((void**)&m->host, 8 * sizeof(double), hipHostMallocDefault));
+        m->upload();
+        return TBDG_OK;
+    });
+    if (st != TBDG_OK) {
+        m->free_all();
+        delete m;
+        return st;
+    }
+    *out = m;
+    return TBDG_OK;
+}
+
+void tbdg_amr_destroy(tbdg_amr* m) {
+    if (!m) return;
+    (void)hipSetDevice(m->device);
+    if (m->stream) (void)hipStreamSynchronize(m->stream);
+    m->free_all();
+    delete m;
+}
+
+const char* tbdg_amr_last_error(const tbdg_amr* m) { return m ? m->last_error.c_str() : "null handle"; }
+
+tbdg_status tbdg_amr_set_stream(tbdg_amr* m, void* hip_stream) {
+    if (!m) return TBDG_EINVAL;
+    return aguard(m, [&]() {
+        m->stream = static_cast<hipStream_t>(hip_stream);
+        return TBDG_OK;
+    });
+}
+
+tbdg_status tbdg_amr_sizes(const tbdg_amr* m, int64_t* n_cells, int64_t* n_u, int64_t* n_p) {
+    if (!m) return TBDG_EINVAL;
+    if (n_cells) *n_cells = m->Nc();
+    if (n_u) *n_u = m->Nu();
+    if (n_p) *n_p = m->Np();
+    return TBDG_OK;
+}
+
+tbdg_status tbdg_amr_leaves(const tbdg_amr* m, int32_t* lij) {
+    if (!m || !lij) return TBDG_EINVAL;
+    for (int64_t c = 0; c < m->Nc(); ++c) {
+        lij[3 * c] = m->F.leaves[c].l;
+        lij[3 * c + 1] = m->F.leaves[c].i;
+        lij[3 * c + 2] = m->F.leaves[c].j;
+    }
+    return TBDG_OK;
+}
+
+tbdg_status tbdg_amr_apply_pressure(tbdg_amr* m, double alpha, const double* p, double* y) {
+    if (!m) return TBDG_EINVAL;
+    return aguard(m, [&]() {
+        need(std::isfinite(alpha), "alpha must be finite");
+        need(m->Nc() == 0 || (p && y), "null vector");
+        A::launch_amr_pressure(m->stream, m->geo(), m->tp, alpha, p, y, false);
+        return TBDG_OK;
+    });
+}
+
+tbdg_status tbdg_amr_diag_pressure(tbdg_amr* m, double alpha, double* d) {
+    if (!m) return TBDG_EINVAL;
+    return aguard(m, [&]() {
+        need(std::isfinite(alpha), "alpha must be finite");
+        need(m->Nc() == 0 || d, "null vector");
+        A::launch_amr_pressure(m->stream, m->geo(), m->tp, alpha, nullptr, d, true);
+        return TBDG_OK;
+    });
+}
+
+tbdg_status tbdg_amr_solve_pressure(tbdg_amr* m, double alpha, const double* b, double* x, double tol,
+                                    int maxiter, tbdg_solve_info* info) {
+    if (!m) return TBDG_EINVAL;
+    return aguard(m, [&]() {
+        need(std::isfinite(alpha) && alpha > 0.0, "alpha must be finite and > 0");
+        need(tol > 0.0 && maxiter >= 0, "need tol > 0 and maxiter >= 0");
+        need(b && x, "null vector");
+        const int64_t n = m->Np();
+        if (n > m->cg_cap) {
+            devfree(m->cg);
+            m->cg = devalloc<double>(5 * n);
+            m->cg_cap = n;
+        }
+        double *r = m->cg, *z = r + n, *p = z + n, *q = p + n, *d = q + n;
+        double* rz[2] = {m->scal, m->scal + 1};
+        double* pq = m->scal + 2;
+        const hipStream_t st = m->stream;
+        const A::Geo g = m->geo();
+        tbdg_solve_info inf{0, 0.0, 0.0, 0, 0};
+        A::launch_amr_pressure(st, g, m->tp, alpha, nullptr, d, true);
+        A::launch_amr_pressure(st, g, m->tp, alpha, x, q, false);
+        trbdg::vec_axpby(st, n, 1.0, b, -1.0, q, r);
+        const double bnorm = std::sqrt(dot(m, n, b, b, 4));
+        if (bnorm == 0.0) {
+            TBDG_HIP(hipMemsetAsync(x, 0, sizeof(double) * n, st));
+            if (info) *info = inf;
+            return TBDG_OK;
+        }
+        if (!std::isfinite(bnorm)) return TBDG_ENAN;
+        double res = std::sqrt(dot(m, n, r, r, 3)) / bnorm;
+        inf.res0 = res;
+        A::launch_amr_div(st, n, r, d, z);
+        TBDG_HIP(hipMemcpyAsync(p, z, sizeof(double) * n, hipMemcpyDeviceToDevice, st));
+        A::launch_amr_dot(st, n, r, z, m->part, DOT_BLOCKS, rz[0]);
+        tbdg_status status = TBDG_ENOTCONV;
+        int it = 0, cur = 0;
+        for (;;) {
+            if (!std::isfinite(res)) {
+                status = TBDG_ENAN;
+                break;
+            }
+            if (res <= tol) {
+                status = TBDG_OK;
+                break;
+            }
+            if (it >= maxiter) break;
+            ++it;
+            A::launch_amr_pressure(st, g, m->tp, alpha, p, q, false);
+            const double pqv = dot(m, n, p, q, 2);
+            if (!(pqv > 0.0)) {
+                status = std::isfinite(pqv) ? TBDG_EBREAKDOWN : TBDG_ENAN;
+                break;
+            }
+            A::launch_amr_cg_update(st, n, rz[cur], pq, p, q, d, x, r, z);
+            A::launch_amr_dot(st, n, r, z, m->part, DOT_BLOCKS, rz[1 - cur]);
+            res = std::sqrt(dot(m, n, r, r, 3)) / bnorm;
+            A::launch_amr_cg_dir(st, n, rz[1 - cur], rz[cur], z, p);
+            cur = 1 - cur;
+        }
+        inf.iters = it;
+        inf.res_final = res;
+        if (info) *info = inf;
+        if (status != TBDG_OK) m->last_error = "adaptive-mesh pressure CG did not converge";
+        return status;
+    });
+}
+
+tbdg_status tbdg_amr_indicator(tbdg_amr* m, const double* u, double* eta) {
+    if (!m) return TBDG_EINVAL;
+    return aguard(m, [&]() {
+        need(m->Nc() == 0 || (u && eta), "null vector");
+        A::launch_amr_indicator(m->stream, m->geo(), m->tu, u, eta);
+        return TBDG_OK;
+    });
+}
+
+tbdg_status tbdg_amr_mark(tbdg_amr* m, const double* eta, double refine_frac, double coarsen_frac,
+                          double h_min, double h_max, int8_t* flags) {
+    if (!m) return TBDG_EINVAL;
+    return aguard(m, [&]() {
+        need(refine_frac >= 0.0 && refine_frac <= 1.0 && coarsen_frac >= 0.0 && coarsen_frac <= 1.0,
+             "fractions must lie in [0, 1]");
+        need(h_min >= 0.0 && h_max > 0.0 && !std::isnan(h_min) && !std::isnan(h_max), "bad size limits");
+        const int64_t N = m->Nc();
+        need(N == 0 || (eta && flags), "null pointer");
+        std::vector<double> e(N);
+        if (N > 0) {
+            TBDG_HIP(hipMemcpyAsync(e.data(), eta, sizeof(double) * N, hipMemcpyDeviceToHost, m->stream));
+            TBDG_HIP(hipStreamSynchronize(m->stream));
+        }
+        for (double v : e)
+            if (std::isnan(v)) throw Error(TBDG_ENAN, "indicator holds NaN");
+        const int64_t nr = (int64_t)std::floor(refine_frac * N + 1e-12);
+        const int64_t ncs = (int64_t)std::floor(coarsen_frac * N + 1e-12);
+        std::vector<int64_t> ord(N);
+        for (int64_t c = 0; c < N; ++c) ord[c] = c;
+        std::sort(ord.begin(), ord.end(), [&](int64_t a, int64_t b) {
+            return e[a] > e[b] || (e[a] == e[b] && a < b);
+        });
+        std::vector<char> top(N, 0);
+        std::memset(flags, 0, (size_t)N);
+        const Forest& F = m->F;
+        for (int64_t r = 0; r < nr; ++r) {
+            const int64_t c = ord[r];
+            top[c] = 1;
+            const double hm = std::max(F.size((int)c, 0), F.size((int)c, 1));
+            if (0.5 * hm >= h_min * (1.0 - 1e-12) && F.leaves[c].l < F.maxl) flags[c] = 1;
+        }
+        std::sort(ord.begin(), ord.end(), [&](int64_t a, int64_t b) {
+            return e[a] < e[b] || (e[a] == e[b] && a < b);
+        });
+        int64_t taken = 0;
+        for (int64_t r = 0; r < N && taken < ncs; ++r) {
+            const int64_t c = ord[r];
+            if (top[c]) continue;
+            ++taken;
+            const double hm = std::max(F.size((int)c, 0), F.size((int)c, 1));
+            if (F.leaves[c].l > 0 && 2.0 * hm <= h_max * (1.0 + 1e-12)) flags[c] = -1;
+        }
+        return TBDG_OK;
+    });
+}
+
+tbdg_status tbdg_amr_plan(tbdg_amr* m, const int8_t* flags, int64_t* new_cells) {
+    if (!m) return TBDG_EINVAL;
+    return aguard(m, [&]() {
+        const int64_t N = m->Nc();
+        need(N == 0 || flags, "null flags");
+        m->next = m->F.adapt(flags);
+        const Forest& Fn = m->next;
+        const int64_t Nn = (int64_t)Fn.leaves.size();
+        std::vector<int> kind(Nn), src(4 * Nn, -1);
+        for (int64_t c = 0; c < Nn; ++c) {
+            const Leaf& L = Fn.leaves[c];
+            int o = m->F.find(L.l, L.i, L.j);
+            if (o >= 0) {
+                kind[c] = 0;
+                src[4 * c] = o;
+            } else if (L.l > 0 && (o = m->F.find(L.l - 1, L.i >> 1, L.j >> 1)) >= 0) {
+                kind[c] = 1 | (((L.i & 1) + 2 * (L.j & 1)) << 4);
+                src[4 * c] = o;
+            } else {
+                kind[c] = 2;
+                for (int ch = 0; ch < 4; ++ch) {
+                    src[4 * c + ch] = m->F.find(L.l + 1, 2 * L.i + (ch & 1), 2 * L.j + (ch >> 1));
+                    if (src[4 * c + ch] < 0) throw Error(TBDG_EINVAL, "inconsistent adaptation");
+                }
+            }
+        }
+        if (Nn > m->x_cap) {
+            devfree(m->xkind);
+            devfree(m->xsrc);
+            m->xkind = devalloc<int>(Nn);
+            m->xsrc = devalloc<int>(4 * Nn);
+            m->x_cap = Nn;
+        }
+        if (Nn > 0) {
+            TBDG_HIP(hipMemcpyAsync(m->xkind, kind.data(), sizeof(int) * Nn, hipMemcpyHostToDevice,
+                                    m->stream));
+            TBDG_HIP(hipMemcpyAsync(m->xsrc, src.data(), sizeof(int) * 4 * Nn, hipMemcpyHostToDevice,
+                                    m->stream));
+        }
+        TBDG_HIP(hipStreamSynchronize(m->stream));
+        m->planned = true;
+        if (new_cells) *new_cells = Nn;
+        return TBDG_OK;
+    });
+}
+
+tbdg_status tbdg_amr_transfer(tbdg_amr* m, int field, const double* src, double* dst) {
+    if (!m) return TBDG_EINVAL;
+    return aguard(m, [&]() {
+        need(m->planned, "no adaptation planned (tbdg_amr_plan)");
+        need(field == 0 || field == 1, "field must be 0 (velocity) or 1 (pressure)");
+        const int64_t Nn = (int64_t)m->next.leaves.size();
+        need((m->Nc() == 0 || src) && (Nn == 0 || dst), "null vector");
+        need(src != dst, "source and destination must differ");
+        A::XferMap xm{m->xkind, m->xsrc, (int)Nn};
+        A::launch_amr_transfer(m->stream, xm, field == 0 ? m->tu : m->tp, field == 0 ? 2 : 1, src, dst);
+        return TBDG_OK;
+    });
+}
+
+tbdg_status tbdg_amr_commit(tbdg_amr* m) {
+    if (!m) return TBDG_EINVAL;
+    return aguard(m, [&]() {
+        need(m->planned, "no adaptation planned (tbdg_amr_plan)");
+        // kernels still reading the old connectivity must finish first
+        TBDG_HIP(hipStreamSynchronize(m->stream));
+        m->F = std::move(m->next);
+        m->next = Forest();
+        m->planned = false;
+        m->upload();
+        return TBDG_OK;
+    });
+}
+
+}  // extern "C"

@@ -1,0 +1,431 @@
+// Kernels on adaptive 2D quadrilateral meshes with hanging nodes.
+//
+// Every cell is an axis-aligned rectangle of the size of its level, so the
+// pressure SIP form a_p (Sec. 3) splits along grid lines as on the uniform
+// box: one work item per (cell, direction, line) applies the 1D stiffness
+// and the terms of the line's two end faces.  What changes is the exterior
+// trace at a face node of the cell (value and normal derivative):
+//   same-level neighbour: its trace along the same line;
+//   coarser neighbour (this face is half h of its face): the neighbour's
+//     face trace, a polynomial along the face, evaluated at this cell's
+//     face nodes (tangential interpolation T_h);
+//   two finer neighbours: the face integral is the sum of the two fine faces
+//     with their own Gauss points; tested against this cell's tangential
+//     basis l_t, the exterior part becomes
+//       (1 / W_t) sum_h sum_q (w_q / 2) T_h[q][t] (fine trace at q),
+//     while the own-trace parts reduce exactly to the node values (the two
+//     half rules integrate the degree 2n-2 products exactly).
+// The penalty on a face is the average of the two cells' k^2 / h_a.
+// Pressure boundary faces carry no term (homogeneous Neumann).
+#include <hip/hip_runtime.h>
+
+#include "amr.hpp"
+#include "internal.hpp"
+#include "reduce.hpp"
+
+namespace trbdg {
+namespace amr {
+namespace {
+
+template <int NP>
+__device__ inline int nd2(int a, int m, int t) {
+    return a == 0 ? m + NP * t : t + NP * m;
+}
+
+// value and reference normal derivative of cell's trace at side `side` of
+// direction a, on the grid line through tangential node tt
+template <int NP>
+__device__ inline void trace(const double* __restrict__ p, const Tab1& t, int cell, int a, int side,
+                             int tt, double& v, double& d) {
+    constexpr int NB = NP * NP;
+    v = 0.0;
+    d = 0.0;
+#pragma unroll
+    for (int m = 0; m < NP; ++m) {
+        const double pv = p[(size_t)cell * NB + nd2<NP>(a, m, tt)];
+        v += t.L[side][m] * pv;
+        d += t.dL[side][m] * pv;
+    }
+}
+
+// y = (alpha M + K) p, or its diagonal (DIAG)
+template <int NP, bool DIAG>
+__global__ __launch_bounds__(256) void k_amr_pressure(Geo g, Tab1 t, double alpha,
+                                                      const double* __restrict__ p,
+                                                      double* __restrict__ y) {
+    constexpr int NB = NP * NP;
+    constexpr int CPB = 256 / NB;
+    __shared__ double s_p[CPB * NB];
+    __shared__ double s_e[CPB * 4 * NP * 2];
+    __shared__ double s_y[2][CPB * NB];
+    const int tid = threadIdx.x;
+    const int lc = tid / NB, nd = tid % NB;
+    const int cell0 = blockIdx.x * CPB;
+    const int cell = cell0 + lc;
+    const bool active = lc < CPB && cell < g.Nc;
+    if (lc < CPB) s_p[tid] = (active && !DIAG) ? p[(size_t)cell * NB + nd] : 0.0;
+    // exterior traces at every face node of the block's cells
+    for (int it = tid; it < CPB * 4 * NP; it += 256) {
+        const int c2 = it / (4 * NP), f = (it / NP) % 4, tt = it % NP;
+        const int cl = cell0 + c2;
+        double ve = 0.0, de = 0.0;
+        if (!DIAG && cl < g.Nc) {
+            const int meta = g.meta[cl * 4 + f];
+            const int kind = meta & 15, half = meta >> 4;
+            const int a = f >> 1, s = f & 1, so = 1 - s;
+            const int own = g.level[cl];
+            if (kind == FACE_SAME) {
+                const int nb = g.nbr[cl * 8 + f * 2];
+                trace<NP>(p, t, nb, a, so, tt, ve, de);
+                de *= (double)(1 << own) / g.H[a];
+            } else if (kind == FACE_COARSER) {
+                const int nb = g.nbr[cl * 8 + f * 2];
+#pragma unroll
+                for (int m = 0; m < NP; ++m) {
+                    double v, d;
+                    trace<NP>(p, t, nb, a, so, m, v, d);
+                    ve += t.T[half][tt * NP + m] * v;
+                    de += t.T[half][tt * NP + m] * d;
+                }
+                de *= (double)(1 << (own - 1)) / g.H[a];
+            } else if (kind == FACE_FINER) {
+                for (int h = 0; h < 2; ++h) {
+                    const int nb = g.nbr[cl * 8 + f * 2 + h];
+#pragma unroll
+                    for (int q = 0; q < NP; ++q) {
+                        double v, d;
+                        trace<NP>(p, t, nb, a, so, q, v, d);
+                        const double wq = 0.5 * t.W[q] * t.T[h][q * NP + tt];
+                        ve += wq * v;
+                        de += wq * d;
+                    }
+                }
+                ve /= t.W[tt];
+                de *= (double)(1 << (own + 1)) / (g.H[a] * t.W[tt]);
+            }
+        }
+        s_e[it * 2] = ve;
+        s_e[it * 2 + 1] = de;
+    }
+    __syncthreads();
+    // one item per (cell, direction, line)
+    for (int it = tid; it < CPB * 2 * NP; it += 256) {
+        const int c2 = it / (2 * NP), a = (it / NP) % 2, tt = it % NP;
+        const int cl = cell0 + c2;
+        if (cl >= g.Nc) continue;
+        const int own = g.level[cl];
+        const double sc = 1.0 / (double)(1 << own);
+        const double h = g.H[a] * sc, ht = g.H[1 - a] * sc;
+        const double Wt = t.W[tt] * ht;
+        double pp[NP];
+#pragma unroll
+        for (int m = 0; m < NP; ++m) pp[m] = s_p[c2 * NB + nd2<NP>(a, m, tt)];
+        double pv[2], pn[2], C[2], ve[2], de[2];
+        int kind[2];
+        const double sig = g.csig / h;
+#pragma unroll
+        for (int s = 0; s < 2; ++s) {
+            const double nu = s ? 1.0 : -1.0;
+            pv[s] = 0.0;
+            pn[s] = 0.0;
+#pragma unroll
+            for (int j = 0; j < NP; ++j) {
+                pv[s] += t.L[s][j] * pp[j];
+                pn[s] += t.dL[s][j] * pp[j];
+            }
+            pn[s] *= nu / h;
+            const int f = 2 * a + s;
+            kind[s] = g.meta[cl * 4 + f] & 15;
+            C[s] = kind[s] == FACE_SAME ? sig
+                 : kind[s] == FACE_COARSER ? 0.5 * (sig + 0.5 * sig)
+                 : kind[s] == FACE_FINER ? 0.5 * (sig + 2.0 * sig) : 0.0;
+            const int e = ((c2 * 4 + f) * NP + tt) * 2;
+            ve[s] = s_e[e];
+            de[s] = s_e[e + 1];
+        }
+#pragma unroll
+        for (int i = 0; i < NP; ++i) {
+            double r = 0.0;
+            if (DIAG) {
+                r = t.S[i * NP + i] * Wt / h;
+            } else {
+#pragma unroll
+                for (int j = 0; j < NP; ++j) r += t.S[i * NP + j] * pp[j];
+                r *= Wt / h;
+            }
+#pragma unroll
+            for (int s = 0; s < 2; ++s) {
+                if (kind[s] == FACE_BOUNDARY) continue;
+                const double nu = s ? 1.0 : -1.0;
+                const double Li = t.L[s][i], dLi = nu * t.dL[s][i] / h;
+                if (DIAG) {
+                    r += Wt * (-dLi * Li + C[s] * Li * Li);
+                } else {
+                    r += Wt * (-0.5 * (pn[s] + nu * de[s]) * Li - 0.5 * dLi * (pv[s] - ve[s])
+                               + C[s] * (pv[s] - ve[s]) * Li);
+                }
+            }
+            s_y[a][c2 * NB + nd2<NP>(a, i, tt)] = r;
+        }
+    }
+    __syncthreads();
+    if (active) {
+        const double sc = 1.0 / (double)(1 << g.level[cell]);
+        const double m = alpha * t.W[nd % NP] * t.W[nd / NP] * g.H[0] * g.H[1] * sc * sc;
+        const double own = DIAG ? 1.0 : s_p[tid];
+        y[(size_t)cell * NB + nd] = m * own + s_y[0][tid] + s_y[1][tid];
+    }
+}
+
+// eta_K = (h_x^2 + h_y^2) sum_nodes W |K| omega^2, omega = d_x u_y - d_y u_x
+template <int N>
+__global__ __launch_bounds__(256) void k_amr_indicator(Geo g, Tab1 t, const double* __restrict__ u,
+                                                       double* __restrict__ eta) {
+    constexpr int NB = N * N;
+    constexpr int CPB = 256 / NB;
+    __shared__ double s_u[2][CPB * NB];
+    __shared__ double s_w[CPB * NB];
+    const int tid = threadIdx.x;
+    const int lc = tid / NB, nd = tid % NB;
+    const int cell = blockIdx.x * CPB + lc;
+    const bool active = lc < CPB && cell < g.Nc;
+    if (lc < CPB) {
+#pragma unroll
+        for (int c = 0; c < 2; ++c) s_u[c][tid] = active ? u[((size_t)cell * 2 + c) * NB + nd] : 0.0;
+    }
+    __syncthreads();
+    if (lc < CPB) {
+        double om2 = 0.0;
+        if (active) {
+            const double sc = 1.0 / (double)(1 << g.level[cell]);
+            const double hx = g.H[0] * sc, hy = g.H[1] * sc;
+            const int ix = nd % N, iy = nd / N;
+            double dxuy = 0.0, dyux = 0.0;
+#pragma unroll
+            for (int j = 0; j < N; ++j) {
+                dxuy += t.D[ix * N + j] * s_u[1][lc * NB + j + N * iy];
+                dyux += t.D[iy * N + j] * s_u[0][lc * NB + ix + N * j];
+            }
+            const double om = dxuy / hx - dyux / hy;
+            om2 = t.W[ix] * t.W[iy] * hx * hy * om * om;
+        }
+        s_w[tid] = om2;
+    }
+    __syncthreads();
+    if (lc < CPB && nd == 0 && active) {
+        double sum = 0.0;
+        for (int q = 0; q < NB; ++q) sum += s_w[lc * NB + q];
+        const double sc = 1.0 / (double)(1 << g.level[cell]);
+        const double hx = g.H[0] * sc, hy = g.H[1] * sc;
+        eta[cell] = (hx * hx + hy * hy) * sum;
+    }
+}
+
+// one thread per (new cell, component, node)
+template <int N>
+__global__ __launch_bounds__(256) void k_amr_transfer(XferMap mp, Tab1 t, int ncomp,
+                                                      const double* __restrict__ src,
+                                                      double* __restrict__ dst) {
+    constexpr int NB = N * N;
+    const int64_t gid = (int64_t)blockIdx.x * 256 + threadIdx.x;
+    const int64_t total = (int64_t)mp.Nnew * ncomp * NB;
+    if (gid >= total) return;
+    const int cell = (int)(gid / (ncomp * NB));
+    const int rem = (int)(gid % (ncomp * NB));
+    const int comp = rem / NB, nd = rem % NB;
+    const int ix = nd % N, iy = nd / N;
+    const int kd = mp.kind[cell];
+    const int kind = kd & 15, pos = kd >> 4;
+    const int* s4 = mp.src + (size_t)cell * 4;
+    double v = 0.0;
+    if (kind == 0) {
+        v = src[((size_t)s4[0] * ncomp + comp) * NB + nd];
+    } else if (kind == 1) {
+        // the parent's polynomial at this child's node
+        const int bx = pos & 1, by = pos >> 1;
+        const double* ps = src + ((size_t)s4[0] * ncomp + comp) * NB;
+#pragma unroll
+        for (int my = 0; my < N; ++my) {
+            double row = 0.0;
+#pragma unroll
+            for (int mx = 0; mx < N; ++mx) row += t.T[bx][ix * N + mx] * ps[mx + N * my];
+            v += t.T[by][iy * N + my] * row;
+        }
+    } else {
+        // L2 projection of the four children onto the parent node (ix, iy)
+        for (int ch = 0; ch < 4; ++ch) {
+            const int dx = ch & 1, dy = ch >> 1;
+            const double* cs = src + ((size_t)s4[ch] * ncomp + comp) * NB;
+            double acc = 0.0;
+#pragma unroll
+            for (int qy = 0; qy < N; ++qy) {
+                double row = 0.0;
+#pragma unroll
+                for (int qx = 0; qx < N; ++qx) row += t.W[qx] * t.T[dx][qx * N + ix] * cs[qx + N * qy];
+                acc += t.W[qy] * t.T[dy][qy * N + iy] * row;
+            }
+            v += 0.25 * acc;
+        }
+        v /= t.W[ix] * t.W[iy];
+    }
+    dst[((size_t)cell * ncomp + comp) * NB + nd] = v;
+}
+
+__global__ __launch_bounds__(256) void k_amr_dot(int64_t n, const double* __restrict__ a,
+                                                 const double* __restrict__ b, double* part) {
+    double s = 0.0;
+    for (int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x; i < n; i += (int64_t)gridDim.x * 256)
+        s += a[i] * b[i];
+    s = red::block_sum(s);
+    if (threadIdx.x == 0) part[blockIdx.x] = s;
+}
+
+__global__ __launch_bounds__(256) void k_amr_dot_finish(const double* part, int G, double* out) {
+    double s = 0.0;
+    for (int i = threadIdx.x; i < G; i += 256) s += part[i];
+    s = red::block_sum(s);
+    if (threadIdx.x == 0) *out = s;
+}
+
+__global__ __launch_bounds__(256) void k_amr_cg_update(int64_t n, const double* rz,
+                                                       const double* pq,
+                                                       const double* __restrict__ p,
+                                                       const double* __restrict__ q,
+                                                       const double* __restrict__ d,
+                                                       double* __restrict__ x, double* __restrict__ r,
+                                                       double* __restrict__ z) {
+    const int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
+    if (i >= n) return;
+    const double al = *rz / *pq;
+    x[i] += al * p[i];
+    const double ri = r[i] - al * q[i];
+    r[i] = ri;
+    z[i] = ri / d[i];
+}
+
+__global__ __launch_bounds__(256) void k_amr_cg_dir(int64_t n, const double* rz_new,
+                                                    const double* rz_old,
+                                                    const double* __restrict__ z,
+                                                    double* __restrict__ p) {
+    const int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
+    if (i >= n) return;
+    p[i] = z[i] + (*rz_new / *rz_old) * p[i];
+}
+
+__global__ __launch_bounds__(256) void k_amr_div(int64_t n, const double* __restrict__ r,
+                                                 const double* __restrict__ d,
+                                                 double* __restrict__ z) {
+    const int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
+    if (i >= n) return;
+    z[i] = r[i] / d[i];
+}
+
+inline int blocks(int64_t n) { return (int)((n + 255) / 256); }
+
+}  // namespace
+
+void launch_amr_pressure(hipStream_t st, const Geo& g, const Tab1& t, double alpha, const double* p,
+                         double* y, bool diag) {
+    if (g.Nc == 0) return;
+#define TBDG_AMR_P(NPV)                                                                       \
+    case NPV: {                                                                               \
+        constexpr int CPB = 256 / (NPV * NPV);                                                \
+        const int G = (g.Nc + CPB - 1) / CPB;                                                 \
+        if (diag) hipLaunchKernelGGL((k_amr_pressure<NPV, true>), dim3(G), dim3(256), 0, st, g, t, \
+                                     alpha, p, y);                                           \
+        else hipLaunchKernelGGL((k_amr_pressure<NPV, false>), dim3(G), dim3(256), 0, st, g, t,  \
+                                alpha, p, y);                                                \
+        break;                                                                                \
+    }
+    switch (t.n) {
+        TBDG_AMR_P(1)
+        TBDG_AMR_P(2)
+        TBDG_AMR_P(3)
+        TBDG_AMR_P(4)
+        TBDG_AMR_P(5)
+        TBDG_AMR_P(6)
+        TBDG_AMR_P(7)
+        default: throw Error(TBDG_EUNSUPPORTED, "pressure nodes per direction must be 1..7");
+    }
+#undef TBDG_AMR_P
+    TBDG_HIP(hipGetLastError());
+}
+
+void launch_amr_indicator(hipStream_t st, const Geo& g, const Tab1& t, const double* u, double* eta) {
+    if (g.Nc == 0) return;
+#define TBDG_AMR_I(NV)                                                                        \
+    case NV: {                                                                                \
+        constexpr int CPB = 256 / (NV * NV);                                                  \
+        hipLaunchKernelGGL((k_amr_indicator<NV>), dim3((g.Nc + CPB - 1) / CPB), dim3(256), 0, st, \
+                           g, t, u, eta);                                                     \
+        break;                                                                                \
+    }
+    switch (t.n) {
+        TBDG_AMR_I(2)
+        TBDG_AMR_I(3)
+        TBDG_AMR_I(4)
+        TBDG_AMR_I(5)
+        TBDG_AMR_I(6)
+        TBDG_AMR_I(7)
+        TBDG_AMR_I(8)
+        default: throw Error(TBDG_EUNSUPPORTED, "velocity nodes per direction must be 2..8");
+    }
+#undef TBDG_AMR_I
+    TBDG_HIP(hipGetLastError());
+}
+
+void launch_amr_transfer(hipStream_t st, const XferMap& m, const Tab1& t, int ncomp, const double* src,
+                         double* dst) {
+    const int64_t total = (int64_t)m.Nnew * ncomp * t.n * t.n;
+    if (total == 0) return;
+#define TBDG_AMR_T(NV)                                                                        \
+    case NV:                                                                                  \
+        hipLaunchKernelGGL((k_amr_transfer<NV>), dim3(blocks(total)), dim3(256), 0, st, m, t,    \
+                           ncomp, src, dst);                                                  \
+        break;
+    switch (t.n) {
+        TBDG_AMR_T(1)
+        TBDG_AMR_T(2)
+        TBDG_AMR_T(3)
+        TBDG_AMR_T(4)
+        TBDG_AMR_T(5)
+        TBDG_AMR_T(6)
+        TBDG_AMR_T(7)
+        TBDG_AMR_T(8)
+        default: throw Error(TBDG_EUNSUPPORTED, "nodes per direction must be 1..8");
+    }
+#undef TBDG_AMR_T
+    TBDG_HIP(hipGetLastError());
+}
+
+void launch_amr_dot(hipStream_t st, int64_t n, const double* a, const double* b, double* part, int G,
+                    double* out) {
+    hipLaunchKernelGGL(k_amr_dot, dim3(G), dim3(256), 0, st, n, a, b, part);
+    hipLaunchKernelGGL(k_amr_dot_finish, dim3(1), dim3(256), 0, st, part, G, out);
+    TBDG_HIP(hipGetLastError());
+}
+
+void launch_amr_cg_update(hipStream_t st, int64_t n, const double* rz, const double* pq,
+                          const double* p, const double* q, const double* d, double* x, double* r,
+                          double* z) {
+    if (n == 0) return;
+    hipLaunchKernelGGL(k_amr_cg_update, dim3(blocks(n)), dim3(256), 0, st, n, rz, pq, p, q, d, x, r,
+                       z);
+    TBDG_HIP(hipGetLastError());
+}
+
+void launch_amr_cg_dir(hipStream_t st, int64_t n, const double* rz_new, const double* rz_old,
+                       const double* z, double* p) {
+    if (n == 0) return;
+    hipLaunchKernelGGL(k_amr_cg_dir, dim3(blocks(n)), dim3(256), 0, st, n, rz_new, rz_old, z, p);
+    TBDG_HIP(hipGetLastError());
+}
+
+void launch_amr_div(hipStream_t st, int64_t n, const double* r, const double* d, double* z) {
+    if (n == 0) return;
+    hipLaunchKernelGGL(k_amr_div, dim3(blocks(n)), dim3(256), 0, st, n, r, d, z);
+    TBDG_HIP(hipGetLastError());
+}
+
+}  // namespace amr
+}  // namespace trbdg

@@ -1,0 +1,66 @@
+// Adaptive 2D quadrilateral meshes with hanging nodes: the device-side view
+// shared by the host forest (amr.cpp) and the kernels (amr.hip).
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+
+namespace trbdg {
+namespace amr {
+
+constexpr int MAXN = 8;   // nodes per direction (velocity degree <= 7)
+
+// Face neighbour kinds of one cell face (meta & 15); a coarser neighbour
+// carries the half of its face this cell touches in meta >> 4.
+enum : int { FACE_BOUNDARY = 0, FACE_SAME = 1, FACE_COARSER = 2, FACE_FINER = 3 };
+
+// 1D tables of one nodal basis (n Gauss-Legendre nodes on [0,1]).
+struct Tab1 {
+    int n;
+    double z[MAXN], W[MAXN];
+    double D[MAXN * MAXN];        // D[m n + j] = l_j'(z_m)
+    double S[MAXN * MAXN];        // S[i n + j] = sum_m W_m D[m][i] D[m][j]
+    double L[2][MAXN];            // l_j(0), l_j(1)
+    double dL[2][MAXN];           // l_j'(0), l_j'(1)
+    double T[2][MAXN * MAXN];     // T[h][q n + m] = l_m((h + z_q) / 2)
+};
+
+// Cells in the order of the forest; face f = 2 a + s (direction a, side s).
+struct Geo {
+    const int* level;     // [Nc]
+    const int* meta;      // [Nc][4]
+    const int* nbr;       // [Nc][4][2]: the neighbour, or the two finer ones
+    int Nc;
+    double H[2];          // base cell size per direction
+    double csig;          // k^2 times the penalty multiplier
+};
+
+// Source of every new cell in a transfer: kind 0 copy of src[0], kind 1
+// child (position bx + 2 by) of src[0], kind 2 parent of src[0..3] (children
+// (0,0), (1,0), (0,1), (1,1)).
+struct XferMap {
+    const int* kind;      // [Nnew]: kind | (child position << 4)
+    const int* src;       // [Nnew][4]
+    int Nnew;
+};
+
+void launch_amr_pressure(hipStream_t st, const Geo& g, const Tab1& t, double alpha, const double* p,
+                         double* y, bool diag);
+void launch_amr_indicator(hipStream_t st, const Geo& g, const Tab1& t, const double* u, double* eta);
+void launch_amr_transfer(hipStream_t st, const XferMap& m, const Tab1& t, int ncomp, const double* src,
+                         double* dst);
+// partial sums of a.b over G blocks into part, then the sum into *out
+void launch_amr_dot(hipStream_t st, int64_t n, const double* a, const double* b, double* part, int G,
+                    double* out);
+// Jacobi PCG glue on device scalars: x += al p, r -= al q, z = r / d with
+// al = *rz / *pq; then p = z + (*rz_new / *rz_old) p
+void launch_amr_cg_update(hipStream_t st, int64_t n, const double* rz, const double* pq,
+                          const double* p, const double* q, const double* d, double* x, double* r,
+                          double* z);
+void launch_amr_cg_dir(hipStream_t st, int64_t n, const double* rz_new, const double* rz_old,
+                       const double* z, double* p);
+void launch_amr_div(hipStream_t st, int64_t n, const double* r, const double* d, double* z);
+
+}  // namespace amr
+}  // namespace trbdg

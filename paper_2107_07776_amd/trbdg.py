@@ -9,6 +9,7 @@ import ctypes
 import math
 import os
 
+import numpy as np
 import torch
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
@@ -36,6 +37,10 @@ EXPORTED = [
     "tbdg_guess_last", "tbdg_face_qpoints", "tbdg_set_dirichlet", "tbdg_set_nonlinear",
     "tbdg_set_scheme",
     "tbdg_nonlinear_solves", "tbdg_profile_bytes", "tbdg_precond_momentum",
+    "tbdg_amr_create", "tbdg_amr_destroy", "tbdg_amr_last_error", "tbdg_amr_set_stream",
+    "tbdg_amr_sizes", "tbdg_amr_leaves", "tbdg_amr_apply_pressure", "tbdg_amr_diag_pressure",
+    "tbdg_amr_solve_pressure", "tbdg_amr_indicator", "tbdg_amr_mark", "tbdg_amr_plan",
+    "tbdg_amr_transfer", "tbdg_amr_commit",
 ]
 
 GUESS = {"given": 0, "previous": 1, "learned": 2, "extrap2": 3, "extrap3": 4}
@@ -50,6 +55,12 @@ PRECOND = {"jacobi": 0, "mg_fp32": 1, "mg_bf16": 2, "line": 3}
 
 # time schemes of step(): TR-BDF2, Bell-Colella-Glaz (Crank-Nicolson), BDF2
 SCHEME = {"trbdf2": 0, "bcg": 1, "bdf2": 2}
+
+
+class AmrDesc(ctypes.Structure):
+    _fields_ = [("n_cells", ctypes.c_int * 2), ("lo", ctypes.c_double * 2),
+                ("hi", ctypes.c_double * 2), ("periodic", ctypes.c_int * 2), ("k", ctypes.c_int),
+                ("max_level", ctypes.c_int), ("pen_p", ctypes.c_double)]
 
 
 class TrbdgError(RuntimeError):
@@ -167,6 +178,20 @@ def load_library(path=LIB_PATH):
         "tbdg_guess_features": ([vp, i, vp, vp, vp, d, vp, vp, vp, P(d)], i),
         "tbdg_guess_inject": ([vp, vp, vp, vp, vp, vp, vp], i),
         "tbdg_guess_target": ([vp, vp, vp, vp, vp, vp, vp], i),
+        "tbdg_amr_create": ([P(AmrDesc), vp, P(vp)], i),
+        "tbdg_amr_destroy": ([vp], None),
+        "tbdg_amr_last_error": ([vp], ctypes.c_char_p),
+        "tbdg_amr_set_stream": ([vp, vp], i),
+        "tbdg_amr_sizes": ([vp, P(i64), P(i64), P(i64)], i),
+        "tbdg_amr_leaves": ([vp, vp], i),
+        "tbdg_amr_apply_pressure": ([vp, d, vp, vp], i),
+        "tbdg_amr_diag_pressure": ([vp, d, vp], i),
+        "tbdg_amr_solve_pressure": ([vp, d, vp, vp, d, i, P(SolveInfo)], i),
+        "tbdg_amr_indicator": ([vp, vp, vp], i),
+        "tbdg_amr_mark": ([vp, vp, d, d, d, d, vp], i),
+        "tbdg_amr_plan": ([vp, vp, P(i64)], i),
+        "tbdg_amr_transfer": ([vp, i, vp, vp], i),
+        "tbdg_amr_commit": ([vp], i),
     }
     for name, (args, res) in sig.items():
         fn = getattr(lib, name)
@@ -632,6 +657,121 @@ class Net:
     def close(self):
         if getattr(self, "h", None):
             self.lib.tbdg_net_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+class Adaptive:
+    """Adaptive 2D mesh with hanging nodes on the current HIP device and
+    stream: the pressure Helmholtz operator and its CG solve, the vorticity
+    indicator, marking and remeshing with field transfer."""
+
+    def __init__(self, n_cells, lo, hi, k, max_level, periodic=(0, 0), pen_p=1.0, stream=None,
+                 device="cuda"):
+        self.lib = load_library()
+        self.device = torch.device(device)
+        if self.device.type != "cuda" or not torch.cuda.is_available():
+            raise RuntimeError("trbdg needs a ROCm GPU device")
+        d = AmrDesc()
+        for a in range(2):
+            d.n_cells[a] = int(n_cells[a])
+            d.lo[a] = float(lo[a])
+            d.hi[a] = float(hi[a])
+            d.periodic[a] = int(bool(periodic[a]))
+        d.k, d.max_level, d.pen_p = int(k), int(max_level), float(pen_p)
+        self.stream = stream if stream is not None else torch.cuda.current_stream(self.device)
+        h = ctypes.c_void_p()
+        st = self.lib.tbdg_amr_create(ctypes.byref(d), ctypes.c_void_p(self.stream.cuda_stream),
+                                      ctypes.byref(h))
+        if st != 0:
+            raise TrbdgError(st, "tbdg_amr_create failed (invalid descriptor)")
+        self.h = h
+        self.k = int(k)
+        self._sizes()
+
+    def _check(self, st):
+        if st != 0:
+            msg = self.lib.tbdg_amr_last_error(self.h)
+            raise TrbdgError(st, msg.decode() if msg else "")
+
+    def _sizes(self):
+        nc, nu, np_ = ctypes.c_int64(), ctypes.c_int64(), ctypes.c_int64()
+        self._check(self.lib.tbdg_amr_sizes(self.h, ctypes.byref(nc), ctypes.byref(nu), ctypes.byref(np_)))
+        self.N_c, self.N_u, self.N_p = nc.value, nu.value, np_.value
+
+    def _vec(self, t, n, name):
+        if not isinstance(t, torch.Tensor) or t.device.type != "cuda" or t.dtype != torch.float64 \
+                or not t.is_contiguous() or t.numel() != n:
+            raise ValueError(f"{name} must be a contiguous float64 CUDA tensor of {n} entries")
+        return t
+
+    def leaves(self):
+        """(N_c, 3) int32 array of (level, i, j)."""
+        out = np.empty((self.N_c, 3), dtype=np.int32)
+        self._check(self.lib.tbdg_amr_leaves(self.h, out.ctypes.data_as(ctypes.c_void_p)))
+        return out
+
+    def apply_pressure(self, alpha, p, out=None):
+        y = out if out is not None else torch.empty(self.N_p, dtype=torch.float64, device=self.device)
+        self._check(self.lib.tbdg_amr_apply_pressure(self.h, float(alpha), _ptr(self._vec(p, self.N_p, "p")),
+                                                     _ptr(self._vec(y, self.N_p, "out"))))
+        return y
+
+    def diag_pressure(self, alpha):
+        y = torch.empty(self.N_p, dtype=torch.float64, device=self.device)
+        self._check(self.lib.tbdg_amr_diag_pressure(self.h, float(alpha), _ptr(y)))
+        return y
+
+    def solve_pressure(self, alpha, b, x, tol=1e-10, maxiter=5000, check=True):
+        info = SolveInfo()
+        st = self.lib.tbdg_amr_solve_pressure(self.h, float(alpha), _ptr(self._vec(b, self.N_p, "b")),
+                                              _ptr(self._vec(x, self.N_p, "x")), float(tol), int(maxiter),
+                                              ctypes.byref(info))
+        if check:
+            self._check(st)
+        return info.as_dict() | {"status": st}
+
+    def indicator(self, u):
+        eta = torch.empty(self.N_c, dtype=torch.float64, device=self.device)
+        self._check(self.lib.tbdg_amr_indicator(self.h, _ptr(self._vec(u, self.N_u, "u")), _ptr(eta)))
+        return eta
+
+    def mark(self, eta, refine_frac=0.1, coarsen_frac=0.3, h_min=0.0, h_max=float("inf")):
+        flags = np.zeros(self.N_c, dtype=np.int8)
+        self._check(self.lib.tbdg_amr_mark(self.h, _ptr(self._vec(eta, self.N_c, "eta")), float(refine_frac),
+                                           float(coarsen_frac), float(h_min), float(h_max),
+                                           flags.ctypes.data_as(ctypes.c_void_p)))
+        return flags
+
+    def adapt(self, flags, fields=()):
+        """Remesh with host flags; ``fields`` = [("u" | "p", tensor), ...] on
+        the current mesh; returns the transferred tensors on the new mesh."""
+        flags = np.ascontiguousarray(flags, dtype=np.int8)
+        if flags.size != self.N_c:
+            raise ValueError(f"flags has {flags.size} entries, expected {self.N_c}")
+        nn = ctypes.c_int64()
+        self._check(self.lib.tbdg_amr_plan(self.h, flags.ctypes.data_as(ctypes.c_void_p), ctypes.byref(nn)))
+        nbu, nbp = 2 * (self.k + 1) ** 2, self.k ** 2
+        out = []
+        for kind, t in fields:
+            f = 0 if kind == "u" else 1
+            nb = nbu if f == 0 else nbp
+            self._vec(t, self.N_c * nb, kind)
+            dst = torch.empty(nn.value * nb, dtype=torch.float64, device=self.device)
+            self._check(self.lib.tbdg_amr_transfer(self.h, f, _ptr(t), _ptr(dst)))
+            out.append(dst)
+        self._check(self.lib.tbdg_amr_commit(self.h))
+        self._sizes()
+        return out
+
+    def close(self):
+        if getattr(self, "h", None):
+            self.lib.tbdg_amr_destroy(self.h)
             self.h = None
 
     def __del__(self):

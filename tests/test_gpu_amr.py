@@ -1,0 +1,196 @@
+"""Adaptive 2D meshes with hanging nodes on the GPU (tbdg_amr_*) against the
+oracle (oracle/adaptive.py): the same flags give the same forest cell for
+cell; the pressure Helmholtz operator, its diagonal, the indicator and the
+field transfer agree to FP64 rounding; the marking agrees flag for flag on
+the same indicator; the Jacobi CG solve reaches its tolerance and the
+oracle's direct solution."""
+import numpy as np
+import pytest
+import scipy.sparse.linalg as spla
+
+import synthetic
+from oracle.adaptive import AdaptiveDisc, QuadForest, mark, transfer
+
+torch = pytest.importorskip("torch")
+pytestmark = pytest.mark.gpu
+
+
+def _t(a):
+    return torch.tensor(np.ascontiguousarray(a), dtype=torch.float64, device="cuda")
+
+
+def _pair(seed, n_cells, periodic, k, max_level=3, rounds=3, lo=(0.0, 0.0), hi=(1.5, 1.0)):
+    """A GPU mesh and an oracle forest driven by the same random flags."""
+    from paper_2107_07776_amd import Adaptive
+    print(f"[case] amr seed={seed} cells={n_cells} periodic={periodic} k={k}", flush=True)
+    g = Adaptive(n_cells, lo, hi, k, max_level, periodic=periodic)
+    f = QuadForest(n_cells, lo, hi, periodic, max_level)
+    rng = np.random.default_rng(seed)
+    for _ in range(rounds):
+        flags = rng.choice([-1, 0, 1], size=f.N, p=[0.35, 0.35, 0.3]).astype(np.int8)
+        g.adapt(flags)
+        f = f.adapt(flags)
+        assert [tuple(r) for r in g.leaves().tolist()] == f.leaves
+    return g, f
+
+
+CASES = [(0, (3, 2), (0, 0), 2), (1, (3, 2), (1, 0), 3), (2, (4, 3), (1, 1), 4), (3, (2, 5), (0, 1), 3)]
+
+
+@pytest.mark.parametrize("seed,nc,per,k", CASES)
+def test_pressure_operator_and_diagonal_match_oracle(seed, nc, per, k):
+    g, f = _pair(seed, nc, per, k)
+    try:
+        ad = AdaptiveDisc(f, k)
+        alpha = 7.5
+        A = ad.helmholtz_p(alpha)
+        p = synthetic.random_vector(ad.N_p, seed)
+        y = g.apply_pressure(alpha, _t(p)).cpu().numpy()
+        ref = A @ p
+        assert np.abs(y - ref).max() <= 1e-12 * np.abs(ref).max()
+        d = g.diag_pressure(alpha).cpu().numpy()
+        assert np.abs(d - A.diagonal()).max() <= 1e-12 * np.abs(A.diagonal()).max()
+    finally:
+        g.close()
+
+
+def test_penalty_multiplier_and_alpha_zero():
+    from paper_2107_07776_amd import Adaptive
+    f = QuadForest((3, 3), (0.0, 0.0), (1.0, 1.0), (0, 0), 2)
+    g = Adaptive((3, 3), (0.0, 0.0), (1.0, 1.0), 3, 2, pen_p=2.5)
+    try:
+        flags = np.zeros(f.N, dtype=np.int8)
+        flags[4] = 1
+        g.adapt(flags)
+        f = f.adapt(flags)
+        ad = AdaptiveDisc(f, 3, pen_p=2.5)
+        p = synthetic.random_vector(ad.N_p, 9)
+        y = g.apply_pressure(0.0, _t(p)).cpu().numpy()
+        ref = ad.sip_p() @ p
+        assert np.abs(y - ref).max() <= 1e-12 * np.abs(ref).max()
+    finally:
+        g.close()
+
+
+@pytest.mark.parametrize("seed,nc,per,k", CASES[:3])
+def test_cg_solve_reaches_tolerance_and_direct_solution(seed, nc, per, k):
+    g, f = _pair(seed, nc, per, k)
+    try:
+        ad = AdaptiveDisc(f, k)
+        alpha = 3.0
+        A = ad.helmholtz_p(alpha)
+        b = synthetic.random_vector(ad.N_p, 100 + seed)
+        x = torch.zeros(ad.N_p, dtype=torch.float64, device="cuda")
+        info = g.solve_pressure(alpha, _t(b), x, tol=1e-13, maxiter=20000)
+        xs = x.cpu().numpy()
+        assert np.linalg.norm(b - A @ xs) <= 1e-12 * np.linalg.norm(b)
+        xd = spla.spsolve(A.tocsc(), b)
+        assert np.abs(xs - xd).max() <= 1e-7 * np.abs(xd).max(), info
+        # a converged start returns at once
+        info2 = g.solve_pressure(alpha, _t(b), x, tol=1e-9)
+        assert info2["iters"] == 0
+    finally:
+        g.close()
+
+
+@pytest.mark.parametrize("seed,nc,per,k", CASES)
+def test_indicator_matches_oracle(seed, nc, per, k):
+    g, f = _pair(seed, nc, per, k)
+    try:
+        ad = AdaptiveDisc(f, k)
+        u = synthetic.random_vector(ad.N_u, 200 + seed)
+        eta = g.indicator(_t(u)).cpu().numpy()
+        ref = ad.indicator(u)
+        assert np.abs(eta - ref).max() <= 1e-12 * np.abs(ref).max()
+    finally:
+        g.close()
+
+
+@pytest.mark.parametrize("seed,nc,per,k", CASES[:2])
+def test_marking_matches_oracle_on_the_same_indicator(seed, nc, per, k):
+    g, f = _pair(seed, nc, per, k, max_level=4)
+    try:
+        rng = np.random.default_rng(seed)
+        eta = rng.random(f.N)
+        eta[::7] = eta[3]          # ties
+        for rf, cf, hmin, hmax in ((0.1, 0.3, 0.0, np.inf), (0.25, 0.5, 0.1, 0.6), (0.0, 1.0, 0.0, np.inf),
+                                   (1.0, 0.0, 0.0, np.inf)):
+            fl = g.mark(_t(eta), rf, cf, hmin, hmax)
+            ref = mark(eta, f, rf, cf, hmin, hmax)
+            assert np.array_equal(fl.astype(np.int64), ref), (rf, cf, hmin, hmax)
+    finally:
+        g.close()
+
+
+@pytest.mark.parametrize("seed,nc,per,k", CASES)
+def test_adapt_transfers_fields_like_oracle(seed, nc, per, k):
+    g, f = _pair(seed, nc, per, k, max_level=4, rounds=2)
+    try:
+        rng = np.random.default_rng(50 + seed)
+        for step in range(3):
+            u = synthetic.random_vector(2 * f.N * (k + 1) ** 2, 300 + step)
+            p = synthetic.random_vector(f.N * k * k, 400 + step)
+            flags = rng.choice([-1, 0, 1], size=f.N).astype(np.int8)
+            un, pn = g.adapt(flags, [("u", _t(u)), ("p", _t(p))])
+            f2 = f.adapt(flags)
+            assert [tuple(r) for r in g.leaves().tolist()] == f2.leaves
+            ru = transfer(f, f2, u, k + 1, 2)
+            rp = transfer(f, f2, p, k, 1)
+            assert np.abs(un.cpu().numpy() - ru).max() <= 1e-13 * np.abs(ru).max()
+            assert np.abs(pn.cpu().numpy() - rp).max() <= 1e-13 * np.abs(rp).max()
+            f = f2
+        # no flags: nothing changes
+        p = synthetic.random_vector(f.N * k * k, 7)
+        (pn,) = g.adapt(np.zeros(f.N, dtype=np.int8), [("p", _t(p))])
+        assert np.array_equal(pn.cpu().numpy(), p)
+    finally:
+        g.close()
+
+
+def test_indicator_driven_remeshing_of_a_vortex():
+    """eta of a Taylor-Green field drives three rounds of marking (10 % /
+    30 %) and remeshing with transfer; the GPU and the oracle stay equal."""
+    from paper_2107_07776_amd import Adaptive
+    k = 3
+    L = 2 * np.pi
+    g = Adaptive((4, 4), (0.0, 0.0), (L, L), k, 3, periodic=(1, 1))
+    f = QuadForest((4, 4), (0.0, 0.0), (L, L), (1, 1), 3)
+    try:
+        ad = AdaptiveDisc(f, k)
+        xu = ad.node_coords("u")
+        u = synthetic.nodal_velocity(synthetic.taylor_green_2d(xu, 0.0, 100.0)[0], 2, ad.nbu)
+        U = _t(u)
+        for _ in range(3):
+            eta = g.indicator(U)
+            ad = AdaptiveDisc(f, k)
+            ref = ad.indicator(u)
+            assert np.abs(eta.cpu().numpy() - ref).max() <= 1e-12 * ref.max()
+            flags = g.mark(eta, 0.1, 0.3, 0.0, np.inf)
+            (U,) = g.adapt(flags, [("u", U)])
+            f2 = f.adapt(flags)
+            u = transfer(f, f2, u, k + 1, 2)
+            f = f2
+            assert np.abs(U.cpu().numpy() - u).max() <= 1e-12 * np.abs(u).max()
+        assert f.N > 16
+    finally:
+        g.close()
+
+
+def test_errors():
+    from paper_2107_07776_amd import Adaptive
+    from paper_2107_07776_amd.trbdg import TrbdgError
+    with pytest.raises(TrbdgError):
+        Adaptive((1, 2), (0.0, 0.0), (1.0, 1.0), 2, 2, periodic=(1, 0))   # periodic needs >= 2
+    with pytest.raises(TrbdgError):
+        Adaptive((2, 2), (0.0, 0.0), (1.0, 1.0), 0, 2)
+    g = Adaptive((2, 2), (0.0, 0.0), (1.0, 1.0), 2, 2)
+    try:
+        x = torch.zeros(g.N_p, dtype=torch.float64, device="cuda")
+        with pytest.raises(TrbdgError):
+            g.solve_pressure(0.0, x.clone(), x)      # alpha must be > 0
+        assert g.lib.tbdg_amr_transfer(g.h, 1, None, None) == -1   # nothing planned
+        eta = torch.full((g.N_c,), float("nan"), dtype=torch.float64, device="cuda")
+        with pytest.raises(TrbdgError):
+            g.mark(eta)
+    finally:
+        g.close()
