@@ -432,12 +432,169 @@ def evaluate_guesses(ctx, W, step_kw, modes, seeds=(100, 101), steps=50, discard
     return {"seeds": list(seeds), "steps_per_seed": steps, "discarded_steps": discard, "modes": res}
 
 
+AMR_LABEL = ("2D adaptive quadtree mesh with hanging nodes on (0, 2pi)^2, periodic, 256^2 base "
+             "cells, Q3-Q2, at most two refinement levels (h_min = H/4, h_max = H); velocity of "
+             "twelve seeded Gaussian vortices; per cycle: vorticity indicator, marking of the 10 %% "
+             "largest / 30 %% smallest, remeshing with velocity and pressure transfer, then %d "
+             "applications of the pressure Helmholtz operator")
+
+
+def amr_vortices(x):
+    """Velocity of twelve seeded Gaussian vortices (stream function sum of
+    A exp(-r^2 / s^2)); x (n, 2) -> (n, 2)."""
+    import numpy as np
+    rng = np.random.default_rng(2107)
+    u = np.zeros_like(x)
+    for _ in range(12):
+        c = rng.uniform(0.8, 2 * math.pi - 0.8, 2)
+        A, s = rng.uniform(-1.0, 1.0), rng.uniform(0.15, 0.4)
+        dx, dy = x[:, 0] - c[0], x[:, 1] - c[1]
+        e = A * np.exp(-(dx * dx + dy * dy) / (s * s))
+        u[:, 0] += -2.0 * dy / (s * s) * e
+        u[:, 1] += 2.0 * dx / (s * s) * e
+    return u
+
+
+def amr_nodes(leaves, H, k):
+    """Velocity node coordinates of the cells (level, i, j), x fastest."""
+    import numpy as np
+    z = 0.5 * (np.polynomial.legendre.leggauss(k + 1)[0] + 1.0)
+    n = k + 1
+    h = H / (1 << leaves[:, 0].astype(np.int64))
+    ox, oy = leaves[:, 1] * h, leaves[:, 2] * h
+    px = ox[:, None] + h[:, None] * np.tile(z, n)[None, :]
+    py = oy[:, None] + h[:, None] * np.repeat(z, n)[None, :]
+    return np.stack([px.ravel(), py.ravel()], 1)
+
+
+def amr_cpu_baseline(k, seconds_budget=15.0):
+    """The oracle's assembled a_p + alpha M^p (hanging-node mesh of the same
+    kind: 8^2 base cells, two rounds of indicator-driven refinement) applied
+    as a sparse matrix-vector product on one thread; assembly excluded."""
+    import numpy as np
+    from threadpoolctl import threadpool_limits
+
+    from oracle.adaptive import AdaptiveDisc, QuadForest, mark
+    with threadpool_limits(limits=1):
+        L = 2 * math.pi
+        f = QuadForest((8, 8), (0.0, 0.0), (L, L), (1, 1), 2)
+        for _ in range(2):
+            ad = AdaptiveDisc(f, k)
+            xu = ad.node_coords("u")
+            uv = amr_vortices(xu)
+            u = np.zeros(ad.N_u)
+            for c in range(f.N):
+                sl = slice(c * ad.nbu, (c + 1) * ad.nbu)
+                u[2 * c * ad.nbu:(2 * c + 1) * ad.nbu] = uv[sl, 0]
+                u[(2 * c + 1) * ad.nbu:(2 * c + 2) * ad.nbu] = uv[sl, 1]
+            f = f.adapt(mark(ad.indicator(u), f, 0.1, 0.3, L / 32, L / 8))
+        ad = AdaptiveDisc(f, k)
+        A = ad.helmholtz_p(1.0)
+        p = np.random.default_rng(0).standard_normal(ad.N_p)
+        n = 0
+        t0 = time.perf_counter()
+        while time.perf_counter() - t0 < seconds_budget and n < 200000:
+            p = A @ p
+            p /= np.abs(p).max()
+            n += 1
+        el = time.perf_counter() - t0
+    return {"value": ad.N_p * n / el / 1e9, "unit": "GDoF/s", "cores": 1, "kind": "oracle",
+            "cpu_model": cpu_model(), "host_cpu_count": os.cpu_count(),
+            "sample": f"{n} products of the oracle's assembled CSR operator on an adapted mesh of "
+                      f"{f.N} cells ({ad.N_p} pressure DoFs), one thread; assembly excluded"}
+
+
+def run_amr(args, applies=50):
+    """Adaptive-mesh workload: cycles of indicator, marking, remeshing with
+    transfer and a fixed number of pressure-operator applications."""
+    import numpy as np
+    import torch
+
+    from paper_2107_07776_amd import Adaptive
+    k, base, maxl = 3, 256, 2
+    L = 2 * math.pi
+    H = L / base
+    g = Adaptive((base, base), (0.0, 0.0), (L, L), k, maxl, periodic=(1, 1))
+    nbu = 2 * (k + 1) ** 2
+
+    def velocity():
+        x = amr_nodes(g.leaves(), H, k)
+        uv = amr_vortices(x)
+        n = (k + 1) ** 2
+        u = np.empty(g.N_u)
+        u.reshape(-1, 2, n)[:, 0, :] = uv[:, 0].reshape(-1, n)
+        u.reshape(-1, 2, n)[:, 1, :] = uv[:, 1].reshape(-1, n)
+        return torch.tensor(u, device="cuda")
+
+    U = velocity()
+    P = torch.tensor(np.random.default_rng(1).standard_normal(g.N_p), device="cuda")
+    alpha = 1.0
+    Y = torch.empty_like(P)
+
+    def cycle():
+        nonlocal U, P, Y
+        eta = g.indicator(U)
+        flags = g.mark(eta, 0.1, 0.3, H / 4, H)
+        U, P = g.adapt(flags, [("u", U), ("p", P)])
+        Y = torch.empty_like(P)
+        for i in range(applies):
+            g.apply_pressure(alpha, P, Y)
+            P, Y = Y, P
+            if i % 10 == 9:
+                P.div_(P.abs().max())   # keep the repeated products in range
+
+    log("[bench] adaptive mesh: warm-up cycles")
+    for _ in range(args.warmup):
+        cycle()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        cycle()
+    torch.cuda.synchronize()
+    el = time.perf_counter() - t0
+    lv = g.leaves()[:, 0]
+    # the operator alone: a pair of HIP events around each launch on the
+    # library's (torch's current) stream, so that the host's call overhead
+    # between launches is not counted
+    reps = 40
+    ev = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True))
+          for _ in range(reps)]
+    for e0, e1 in ev:
+        e0.record()
+        g.apply_pressure(alpha, P, Y)
+        e1.record()
+    torch.cuda.synchronize()
+    avg_s = sum(e0.elapsed_time(e1) for e0, e1 in ev) * 1e-3 / reps
+    # compulsory bytes: read p, write y (16 B per DoF) + the cell's level,
+    # face kinds and neighbour ids (4 + 16 + 32 B per cell)
+    bytes_launch = 16.0 * g.N_p + 52.0 * g.N_c
+    gbs = bytes_launch / avg_s / 1e9
+    out = {"metric": "adaptive-mesh pressure Helmholtz operator GDoF/s (hanging nodes)",
+           "value": g.N_p / avg_s / 1e9, "unit": "GDoF/s", "n_gpus": 1, "steps": args.steps,
+           "warmup": args.warmup, "ms_per_step": el / args.steps * 1e3, "higher_is_better": True,
+           "scaling": "strong", "vs_baseline": None, "dtype": "f64",
+           "data": "synthetic (seeded Gaussian vortices; seeded random pressure)",
+           "config": {"workload": AMR_LABEL % applies, "cells": int(g.N_c),
+                      "cells_per_level": [int((lv == l).sum()) for l in range(maxl + 1)],
+                      "pressure_dofs": int(g.N_p), "velocity_dofs": int(g.N_u), "degree": k,
+                      "cycles_per_s": args.steps / el},
+           "roofline": {"bound": "hbm", "kernel": "k_amr_pressure", "achieved": gbs,
+                        "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": gbs / HBM_PEAK_GBS,
+                        "traffic": None, "algorithmic_bytes_per_launch": bytes_launch,
+                        "avg_launch_us": avg_s * 1e6, "launches_timed": reps}}
+    if not args.no_cpu_baseline:
+        log("[bench] timing the CPU oracle's operator on a bounded sample")
+        out["cpu_baseline"] = amr_cpu_baseline(k)
+    g.close()
+    print(json.dumps(out), flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=3)
-    ap.add_argument("--workload", default="tgv64", choices=["tgv64", "tgv32", "kov256", "tg2d"])
+    ap.add_argument("--workload", default="tgv64", choices=["tgv64", "tgv32", "kov256", "tg2d", "amr2d"])
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-profile", action="store_true",
                     help="skip the separate event-timed run of the operator kernels")
@@ -481,6 +638,9 @@ def main():
 
     import torch
 
+    if args.workload == "amr2d":
+        run_amr(args)
+        return
     if args.copy_calibration > 0:
         n = args.copy_calibration * (1 << 20) // 8
         src = torch.ones(n, dtype=torch.float64, device="cuda")
