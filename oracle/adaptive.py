@@ -17,8 +17,10 @@ This module holds, in 2D:
 * ``QuadForest`` - a quadtree over every cell of a base box grid, leaves
   2:1 balanced across faces, refined and coarsened by one level per call;
 * ``AdaptiveDisc`` - the pressure mass matrix and the SIP form a_p of Sec. 3
-  on such a mesh, with the face integrals of a face shared by one coarse and
-  two fine cells taken on each fine face; the indicator eta_K;
+  on such a mesh, and the velocity mass, SIP (eq. bilin_diff, Dirichlet
+  walls) and Lax-Friedrichs advection (eq. trilinear) forms, with the face
+  integrals of a face shared by one coarse and two fine cells taken on each
+  fine face; the indicator eta_K;
 * ``mark`` - the fixed-fraction marking with the size limits;
 * ``transfer`` - velocity and pressure fields from one mesh to the adapted
   one (refinement: exact interpolation of the parent polynomial; coarsening:
@@ -34,10 +36,15 @@ Readings (the paper names the strategy, not these details):
   the sum over the two fine faces, each with the Gauss rule of the fine
   cell, the coarse traces evaluated at those points (exact: the integrands
   are polynomials of degree 2 n_p - 2 on each fine face).
-* SIP penalty on a face: the average of the two cells' k^2 |Gamma_K|/|K|,
-  |Gamma_K| the cell's own full face (the conforming reading; on a
-  rectangle |Gamma_K|/|K| = 1/h_a).  Pressure faces on the boundary carry
-  no term (homogeneous Neumann), as on the conforming meshes.
+* SIP penalty on a face: the average of the two cells' k^2 |Gamma_K|/|K|
+  (pressure) or (k+1)^2 |Gamma_K|/|K| (velocity), |Gamma_K| the cell's own
+  full face (the conforming reading; on a rectangle |Gamma_K|/|K| = 1/h_a).
+  Pressure faces on the boundary carry no term (homogeneous Neumann), as on
+  the conforming meshes; velocity boundary faces the Dirichlet terms of the
+  conforming oracle.
+* The Lax-Friedrichs speed on a coarse-fine face is taken pointwise at the
+  fine faces' Gauss points from the two traces there, as on conforming
+  faces.
 * diam(K) in eta_K is the cell's diagonal; the size limits H_min, H_max are
   on the edge length, as the paper's H of its uniform meshes.
 * Marking: the floor(0.1 N) cells of largest eta (ties: lower cell index
@@ -250,10 +257,11 @@ class AdaptiveDisc:
     indicator (degree k, n = k+1 nodes) on a QuadForest; all cells are
     axis-aligned rectangles, so every map is affine and diagonal."""
 
-    def __init__(self, forest, k, pen_p=1.0):
+    def __init__(self, forest, k, pen_p=1.0, pen_u=1.0):
         self.f = forest
         self.k = int(k)
         self.pen_p = float(pen_p)
+        self.pen_u = float(pen_u)
         self.n = self.k + 1
         self.n_p = self.k
         self.zu, self.wu = gauss_legendre_01(self.n)
@@ -354,6 +362,157 @@ class AdaptiveDisc:
                             add(ct, cs, blk)
         return sp.coo_matrix((np.concatenate(vals), (np.concatenate(rows), np.concatenate(cols))),
                              shape=(self.N_p, self.N_p)).tocsr()
+
+    # ------------------------------------------------------------------
+    # velocity forms (one scalar component, degree k, n = k + 1 nodes)
+    # ------------------------------------------------------------------
+    def _assemble(self, blocks, nb, n):
+        rows, cols, vals = [], [], []
+        for rc, cc_, blk in blocks:
+            rr, cc = np.meshgrid(np.arange(nb) + rc * nb, np.arange(nb) + cc_ * nb, indexing="ij")
+            rows.append(rr.ravel()); cols.append(cc.ravel()); vals.append(blk.ravel())
+        return sp.coo_matrix((np.concatenate(vals), (np.concatenate(rows), np.concatenate(cols))),
+                             shape=(n, n)).tocsr()
+
+    def _cell_tab_u(self, c):
+        h = self.f.size(c)
+        xr, yr = np.tile(self.zu, self.n), np.repeat(self.zu, self.n)
+        V, G = self._tab(self.zu, xr, yr, h)
+        return V, G, np.kron(self.wu, self.wu) * h[0] * h[1]
+
+    def _interfaces(self):
+        """Every interior face once: (a, c, s, other, sub) with c the cell
+        whose face (a, s) carries the quadrature (the finer or, on a
+        same-level face, the side-0 cell) and sub the half of the other
+        cell's face (None when conforming)."""
+        for c in range(self.Nc):
+            for a in range(2):
+                for s in (0, 1):
+                    nbr = self.f.neighbours(c, a, s)
+                    if nbr[0] == "C" and s == 1:
+                        yield a, c, s, nbr[1], None
+                    elif nbr[0] == "c":
+                        yield a, c, s, nbr[1], nbr[2]
+
+    def _face_pair_u(self, a, c, s, other, sub):
+        h, ho = self.f.size(c), self.f.size(other)
+        pc = np.zeros((self.n, 2)); pc[:, a] = float(s); pc[:, 1 - a] = self.zu
+        po = np.zeros((self.n, 2)); po[:, a] = float(1 - s)
+        po[:, 1 - a] = self.zu if sub is None else 0.5 * (sub + self.zu)
+        Vc, Gc = self._tab(self.zu, pc[:, 0], pc[:, 1], h)
+        Vo, Go = self._tab(self.zu, po[:, 0], po[:, 1], ho)
+        nvec = np.zeros(2); nvec[a] = 1.0 if s == 1 else -1.0
+        return Vc, Gc, Vo, Go, nvec, self.wu * float(h[1 - a])
+
+    def _sigma_u(self, c, a):
+        return (self.k + 1) ** 2 * self.pen_u / float(self.f.size(c)[a])
+
+    def mass_u(self):
+        blocks = []
+        for c in range(self.Nc):
+            V, _, W = self._cell_tab_u(c)
+            blocks.append((c, c, V.T @ (W[:, None] * V)))
+        return self._assemble(blocks, self.nbu, self.Nc * self.nbu)
+
+    def sip_u(self):
+        """The bracket of eq. bilin_diff for one component: interior faces as
+        in a_p (penalty (k+1)^2 pen_u |Gamma_K|/|K| averaged), boundary faces
+        of a non-periodic direction -grad u.n v - u n.grad v + 2 C u v."""
+        blocks = []
+        for c in range(self.Nc):
+            V, G, W = self._cell_tab_u(c)
+            blocks.append((c, c, sum(G[:, :, d].T @ (W[:, None] * G[:, :, d]) for d in range(2))))
+        for a, c, s, other, sub in self._interfaces():
+            Vc, Gc, Vo, Go, nvec, dS = self._face_pair_u(a, c, s, other, sub)
+            C = 0.5 * (self._sigma_u(c, a) + self._sigma_u(other, a))
+            tabs = [(c, Vc, Gc, nvec), (other, Vo, Go, -nvec)]
+            for (ct, Vt, Gt, nt) in tabs:
+                for (cs, Vs, Gs, ns) in tabs:
+                    avg_trial = 0.5 * np.einsum("qjd,d->qj", Gs, nt)
+                    avg_test = 0.5 * np.einsum("qid,d->qi", Gt, ns)
+                    blk = (-(Vt * dS[:, None]).T @ avg_trial - (avg_test * dS[:, None]).T @ Vs
+                           + (Vt * (C * float(ns @ nt) * dS)[:, None]).T @ Vs)
+                    blocks.append((ct, cs, blk))
+        for c, a, s in self._boundary_faces():
+            h = self.f.size(c)
+            pc = np.zeros((self.n, 2)); pc[:, a] = float(s); pc[:, 1 - a] = self.zu
+            V, G = self._tab(self.zu, pc[:, 0], pc[:, 1], h)
+            nvec = np.zeros(2); nvec[a] = 1.0 if s == 1 else -1.0
+            dS = self.wu * float(h[1 - a])
+            gn = np.einsum("qjd,d->qj", G, nvec)
+            C = self._sigma_u(c, a)
+            blocks.append((c, c, -(V * dS[:, None]).T @ gn - (gn * dS[:, None]).T @ V
+                           + (V * (2.0 * C * dS)[:, None]).T @ V))
+        return self._assemble(blocks, self.nbu, self.Nc * self.nbu)
+
+    def _boundary_faces(self):
+        for c in range(self.Nc):
+            for a in range(2):
+                for s in (0, 1):
+                    if self.f.neighbours(c, a, s)[0] == "B":
+                        yield c, a, s
+
+    def boundary_points(self):
+        """Velocity face points of every boundary face: cells in order, faces
+        f = 2a + s in order, the n Gauss points along the face."""
+        pts = []
+        for c, a, s in self._boundary_faces():
+            o, h = self.f.origin(c), self.f.size(c)
+            x = np.zeros((self.n, 2))
+            x[:, a] = o[a] + s * h[a]
+            x[:, 1 - a] = o[1 - a] + h[1 - a] * self.zu
+            pts.append(x)
+        return np.concatenate(pts) if pts else np.zeros((0, 2))
+
+    def _w_cell(self, w, c):
+        return w[c * 2 * self.nbu:(c + 1) * 2 * self.nbu].reshape(2, self.nbu)
+
+    def lf_advection(self, w, uD=None):
+        """Linearised advection with the local Lax-Friedrichs flux (eq.
+        trilinear) for one component, as in the box-mesh oracle:
+        -int u (w.grad v) + sum_I int ({{u w}}.[[v]] + lambda/2 [[u]].[[v]])
+        + sum_B int lambda u v, lambda = max |w.n| of the two traces at each
+        face point (boundary: exterior state 2 u_D - w).  Faces between a
+        coarse and two fine cells: the fine faces' Gauss points.  uD: (n_b, 2)
+        at boundary_points()."""
+        blocks = []
+        for c in range(self.Nc):
+            V, G, W = self._cell_tab_u(c)
+            wq = V @ self._w_cell(w, c).T
+            wgv = np.einsum("qd,qid->qi", wq, G)
+            blocks.append((c, c, -(wgv * W[:, None]).T @ V))
+        for a, c, s, other, sub in self._interfaces():
+            Vc, _, Vo, _, nvec, dS = self._face_pair_u(a, c, s, other, sub)
+            wc = Vc @ self._w_cell(w, c).T
+            wo = Vo @ self._w_cell(w, other).T
+            lam = np.maximum(np.abs(wc @ nvec), np.abs(wo @ nvec))
+            tabs = [(c, Vc, nvec, wc), (other, Vo, -nvec, wo)]
+            for (ct, Vt, nt, _) in tabs:
+                for (cs, Vs, ns, ws) in tabs:
+                    coef = 0.5 * (ws @ nt) + 0.5 * lam * float(ns @ nt)
+                    blocks.append((ct, cs, (Vt * (coef * dS)[:, None]).T @ Vs))
+        b = 0
+        for c, a, s in self._boundary_faces():
+            h = self.f.size(c)
+            pc = np.zeros((self.n, 2)); pc[:, a] = float(s); pc[:, 1 - a] = self.zu
+            V, _ = self._tab(self.zu, pc[:, 0], pc[:, 1], h)
+            nvec = np.zeros(2); nvec[a] = 1.0 if s == 1 else -1.0
+            wq = V @ self._w_cell(w, c).T
+            wext = 2.0 * uD[b:b + self.n] - wq
+            b += self.n
+            lam = np.maximum(np.abs(wq @ nvec), np.abs(wext @ nvec))
+            blocks.append((c, c, (V * (lam * self.wu * float(h[1 - a]))[:, None]).T @ V))
+        return self._assemble(blocks, self.nbu, self.Nc * self.nbu)
+
+    def apply_momentum(self, mc, tnu, th, w, u, uD=None):
+        """y_c = (mc M + tnu A + th C(w)) u_c for both components of u
+        ([cell][component][node])."""
+        A = (mc * self.mass_u() + tnu * self.sip_u() + th * self.lf_advection(w, uD)).tocsr()
+        U = u.reshape(self.Nc, 2, self.nbu)
+        out = np.empty_like(U)
+        for comp in range(2):
+            out[:, comp, :] = (A @ U[:, comp, :].reshape(-1)).reshape(self.Nc, self.nbu)
+        return out.reshape(-1)
 
     def helmholtz_p(self, alpha):
         """alpha M^p + K: the stage pressure operator of Sec. 3."""

@@ -299,3 +299,113 @@ def test_transfer_exact_projection_and_roundtrip(n):
     Md = np.tile(np.kron(wq, wq) * hx * hy, Pi_r.shape[0] // (n * n))
     resid = Pi_c.T @ (Md * (Pi_r @ w - Pi_c @ wc))
     assert np.abs(resid).max() < 1e-13
+
+
+# ---------------------------------------------------------------------------
+# velocity forms
+# ---------------------------------------------------------------------------
+@pytest.mark.parametrize("k", [2, 3])
+@pytest.mark.parametrize("periodic", [(False, False), (True, False)])
+def test_velocity_forms_equal_embedded_conforming_forms(k, periodic):
+    """Without the penalty, the velocity mass and SIP forms (Dirichlet walls
+    included) equal the uniform fine mesh's through the exact embedding; with
+    a constant advecting field and constant wall data every advection
+    integral is exact, so the LF form embeds too."""
+    f = _random_forest(21 + k, periodic=periodic, max_level=2, rounds=2)
+    ad = AdaptiveDisc(f, k, pen_u=0.0)
+    Pi, box = _embedding(f, k + 1)
+    disc = Discretization(box, k, nu=1.0, pen_u=0.0)
+    assert abs(ad.mass_u() - Pi.T @ disc.mass_u() @ Pi).max() < 1e-13
+    Kf = disc.sip_u()
+    assert abs(ad.sip_u() - Pi.T @ Kf @ Pi).max() < 1e-11 * abs(Kf).max()
+    wc = np.array([0.7, -1.3])
+    uDc = np.array([0.4, 2.1])
+    wa = np.tile(np.repeat(wc, ad.nbu), f.N)
+    wf = np.tile(np.repeat(wc, disc.nbu), box.N)
+    uD = np.tile(uDc, (len(ad.boundary_points()), 1))
+    Cf = disc.lf_advection(wf, lambda c, a, s, x: np.tile(uDc, (len(x), 1)))
+    Ca = ad.lf_advection(wa, uD)
+    assert abs(Ca - Pi.T @ Cf @ Pi).max() < 1e-12 * abs(Cf).max()
+
+
+def test_velocity_penalty_closed_form_and_boundary_points():
+    k = 2
+    f = _random_forest(8, max_level=3, rounds=3)
+    J = (AdaptiveDisc(f, k, pen_u=1.0).sip_u() - AdaptiveDisc(f, k, pen_u=0.0).sip_u()).tocsr()
+    nbu = (k + 1) ** 2
+    sig = lambda c, a: (k + 1) ** 2 / float(f.size(c)[a])
+    for c0 in range(0, f.N, max(1, f.N // 6)):
+        e = np.zeros(f.N * nbu)
+        e[c0 * nbu:(c0 + 1) * nbu] = 1.0
+        want = 0.0
+        for a in range(2):
+            for s in (0, 1):
+                nb = f.neighbours(c0, a, s)
+                if nb[0] == "B":
+                    want += 2.0 * sig(c0, a) * f.size(c0)[1 - a]
+                elif nb[0] == "C":
+                    want += sig(c0, a) * f.size(c0)[1 - a]
+                elif nb[0] == "c":
+                    want += 0.5 * (sig(c0, a) + sig(nb[1], a)) * f.size(c0)[1 - a]
+                else:
+                    for o in nb[1]:
+                        want += 0.5 * (sig(c0, a) + sig(o, a)) * f.size(o)[1 - a]
+        assert abs(e @ (J @ e) - want) < 1e-12 * want
+    # the boundary points lie on the boundary, n per boundary face
+    ad = AdaptiveDisc(f, k)
+    x = ad.boundary_points()
+    nbf = sum(1 for c in range(f.N) for a in range(2) for s in (0, 1) if f.neighbours(c, a, s)[0] == "B")
+    assert x.shape == (nbf * (k + 1), 2)
+    on = np.isclose(x[:, 0], f.lo[0]) | np.isclose(x[:, 0], f.hi[0]) | \
+        np.isclose(x[:, 1], f.lo[1]) | np.isclose(x[:, 1], f.hi[1])
+    assert on.all()
+
+
+def test_advection_conserves_on_a_periodic_mesh():
+    """The constant test function sees no advection on a periodic mesh: its
+    gradient vanishes and so do its jumps, so 1^T C(w) u = 0 for every w and
+    u; the flux a coarse cell sends through a hanging face is exactly what
+    its two fine neighbours receive."""
+    k = 3
+    f = _random_forest(4, periodic=(True, True), max_level=3, rounds=2)
+    assert any(f.neighbours(c, a, s)[0] == "f" for c in range(f.N) for a in range(2) for s in (0, 1))
+    ad = AdaptiveDisc(f, k)
+    rng = np.random.default_rng(0)
+    w = rng.standard_normal(ad.N_u)
+    C = ad.lf_advection(w)
+    u = rng.standard_normal(C.shape[0])
+    assert abs(np.ones(C.shape[0]) @ (C @ u)) < 1e-12 * abs(C).max() * np.abs(u).sum()
+
+
+@pytest.mark.parametrize("periodic", [(True, True), (False, True)])
+def test_advection_cell_self_term_closed_form(periodic):
+    """A cellwise constant advecting field W_c and u = v = the indicator of
+    one cell: the volume term vanishes and every face (or fine half face) F
+    of the cell adds |F| (W_c.n + max(|W_c.n|, |W_nb.n|)) / 2; a wall face
+    adds |F| max(|W_c.n|, |(2 u_D - W_c).n|)."""
+    k = 2
+    f = _random_forest(6, periodic=periodic, max_level=3, rounds=3)
+    ad = AdaptiveDisc(f, k)
+    rng = np.random.default_rng(3)
+    Wc = rng.standard_normal((f.N, 2))
+    w = np.stack([np.repeat(Wc[:, 0:1], ad.nbu, 1), np.repeat(Wc[:, 1:2], ad.nbu, 1)], 1).reshape(-1)
+    uDc = np.array([0.3, -0.8])
+    C = ad.lf_advection(w, np.tile(uDc, (len(ad.boundary_points()), 1)))
+    nbu = ad.nbu
+    for c0 in range(f.N):
+        e = np.zeros(C.shape[0])
+        e[c0 * nbu:(c0 + 1) * nbu] = 1.0
+        want = 0.0
+        for a in range(2):
+            for s in (0, 1):
+                n = np.zeros(2); n[a] = 1.0 if s else -1.0
+                nb = f.neighbours(c0, a, s)
+                wn = Wc[c0] @ n
+                if nb[0] == "B":
+                    want += f.size(c0)[1 - a] * max(abs(wn), abs((2 * uDc - Wc[c0]) @ n))
+                elif nb[0] in ("C", "c"):
+                    want += f.size(c0)[1 - a] * 0.5 * (wn + max(abs(wn), abs(Wc[nb[1]] @ n)))
+                else:
+                    for o in nb[1]:
+                        want += f.size(o)[1 - a] * 0.5 * (wn + max(abs(wn), abs(Wc[o] @ n)))
+        assert abs(e @ (C @ e) - want) < 1e-12 * (1 + abs(want)), c0
