@@ -587,6 +587,7 @@ typedef struct {
     int k;              /* velocity degree 1..7 (pressure k - 1)             */
     int max_level;      /* deepest level, 0..20, n_cells[a] << max_level < 2^29 */
     double pen_p;       /* multiplier of the pressure SIP penalty (1 = paper) */
+    double pen_u;       /* multiplier of the velocity SIP penalty (1 = paper) */
 } tbdg_amr_desc;
 
 /* The base grid (every cell at level 0) on the current device; hip_stream
@@ -606,6 +607,23 @@ TBDG_API tbdg_status tbdg_amr_leaves(const tbdg_amr* amr, int32_t* lij);
  * two fine faces with their Gauss rule, the coarse traces evaluated there;
  * penalty C = average of the two cells' k^2 pen_p / h_a.  p, y distinct.  */
 TBDG_API tbdg_status tbdg_amr_apply_pressure(tbdg_amr* amr, double alpha, const double* p, double* y);
+/* Velocity Gauss points of the boundary faces of a non-periodic direction:
+ * cells in order, faces (direction a, side s) in the order 2a + s, the k+1
+ * points along each face; *n_points always, xy (device, [point][2]) when
+ * not NULL.  Wall data for tbdg_amr_apply_momentum use this order.          */
+TBDG_API tbdg_status tbdg_amr_face_qpoints(const tbdg_amr* amr, int64_t* n_points, double* xy);
+/* y_c = mc M u_c + tnu A u_c + th C(w) u_c for both velocity components:
+ * A the SIP bracket of eq. bilin_diff (penalty (k+1)^2 pen_u / h_a averaged
+ * over the two cells; on walls -grad u.n v - u n.grad v + 2 C u v), C(w)
+ * the Lax-Friedrichs form of eq. trilinear (lambda = max |w.n| of the two
+ * traces at each face point; on walls lambda u v with the exterior state
+ * 2 u_D - w).  Faces between a coarse and two fine cells are integrated on
+ * the fine faces' Gauss points.  uD: wall data at tbdg_amr_face_qpoints
+ * ([point][2], device), may be NULL on a fully periodic mesh.  y must not
+ * alias u or w.                                                            */
+TBDG_API tbdg_status tbdg_amr_apply_momentum(tbdg_amr* amr, double mc, double tnu, double th,
+                                             const double* w, const double* u, const double* uD,
+                                             double* y);
 /* d = diag(alpha M^p + K).                                                 */
 TBDG_API tbdg_status tbdg_amr_diag_pressure(tbdg_amr* amr, double alpha, double* d);
 /* Jacobi-preconditioned CG for (alpha M^p + K) x = b from the given x

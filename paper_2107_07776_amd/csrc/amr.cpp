@@ -1,8 +1,9 @@
 // Adaptive 2D quadrilateral meshes with hanging nodes (the adaptive runs of
 // Sec. 4): the forest of quadtrees on the host, its device view, the
 // refinement indicator, fixed-fraction marking, remeshing with field
-// transfer, and the pressure Helmholtz operator and its Jacobi CG solve on
-// the adapted mesh; the C ABI of all of it.
+// transfer, the pressure Helmholtz operator and its Jacobi CG solve, and the
+// momentum operator (mass, SIP diffusion, Lax-Friedrichs advection, walls)
+// on the adapted mesh; the C ABI of all of it.
 //
 // The forest lives on the host: remeshing happens every few hundred or
 // thousand steps and is integer bookkeeping over the cell list, while every
@@ -257,7 +258,9 @@ struct tbdg_amr {
     Forest F, next;
     bool planned = false;
     A::Tab1 tp, tu;
-    int *level = nullptr, *meta = nullptr, *nbr = nullptr;
+    int *level = nullptr, *meta = nullptr, *nbr = nullptr, *bface = nullptr;
+    int64_t n_bfaces = 0;
+    double pen_u = 1.0;
     int64_t geo_cap = 0;
     int *xkind = nullptr, *xsrc = nullptr;
     int64_t x_cap = 0;
@@ -277,17 +280,20 @@ struct tbdg_amr {
         g.level = level;
         g.meta = meta;
         g.nbr = nbr;
+        g.bface = bface;
         g.Nc = (int)Nc();
         g.H[0] = F.H[0];
         g.H[1] = F.H[1];
         g.csig = (double)k * k * pen_p;
+        g.csig_u = (double)(k + 1) * (k + 1) * pen_u;
         return g;
     }
 
     // device connectivity of the current forest
     void upload() {
         const int64_t N = Nc();
-        std::vector<int> lv(N), mt(4 * N), nb(8 * N, -1);
+        std::vector<int> lv(N), mt(4 * N), nb(8 * N, -1), bf(4 * N, -1);
+        n_bfaces = 0;
         for (int64_t c = 0; c < N; ++c) {
             lv[c] = F.leaves[c].l;
             for (int a = 0; a < 2; ++a)
@@ -297,22 +303,26 @@ struct tbdg_amr {
                     mt[4 * c + f] = o.kind | (o.half << 4);
                     nb[8 * c + 2 * f] = o.n0;
                     nb[8 * c + 2 * f + 1] = o.n1;
+                    if (o.kind == A::FACE_BOUNDARY) bf[4 * c + f] = (int)n_bfaces++;
                 }
         }
         if (N > geo_cap) {
             devfree(level);
             devfree(meta);
             devfree(nbr);
+            devfree(bface);
             const int64_t cap = std::max<int64_t>(N, geo_cap * 3 / 2);
             level = devalloc<int>(cap);
             meta = devalloc<int>(4 * cap);
             nbr = devalloc<int>(8 * cap);
+            bface = devalloc<int>(4 * cap);
             geo_cap = cap;
         }
         if (N > 0) {
             TBDG_HIP(hipMemcpyAsync(level, lv.data(), sizeof(int) * N, hipMemcpyHostToDevice, stream));
             TBDG_HIP(hipMemcpyAsync(meta, mt.data(), sizeof(int) * 4 * N, hipMemcpyHostToDevice, stream));
             TBDG_HIP(hipMemcpyAsync(nbr, nb.data(), sizeof(int) * 8 * N, hipMemcpyHostToDevice, stream));
+            TBDG_HIP(hipMemcpyAsync(bface, bf.data(), sizeof(int) * 4 * N, hipMemcpyHostToDevice, stream));
         }
         // the host vectors die here: wait for the copies
         TBDG_HIP(hipStreamSynchronize(stream));
@@ -322,6 +332,7 @@ struct tbdg_amr {
         devfree(level);
         devfree(meta);
         devfree(nbr);
+        devfree(bface);
         devfree(xkind);
         devfree(xsrc);
         devfree(cg);
@@ -391,10 +402,12 @@ tbdg_status tbdg_amr_create(const tbdg_amr_desc* d, void* hip_stream, tbdg_amr**
             need(((int64_t)d->n_cells[a] << d->max_level) < ((int64_t)1 << 29),
                  "n_cells << max_level must stay below 2^29");
         need(std::isfinite(d->pen_p) && d->pen_p >= 0.0, "pen_p must be finite and >= 0");
+        need(std::isfinite(d->pen_u) && d->pen_u >= 0.0, "pen_u must be finite and >= 0");
         TBDG_HIP(hipGetDevice(&m->device));
         m->stream = static_cast<hipStream_t>(hip_stream);
         m->k = d->k;
         m->pen_p = d->pen_p;
+        m->pen_u = d->pen_u;
         Forest& F = m->F;
         for (int a = 0; a < 2; ++a) {
             F.nc[a] = d->n_cells[a];
@@ -465,6 +478,49 @@ tbdg_status tbdg_amr_apply_pressure(tbdg_amr* m, double alpha, const double* p, 
         need(std::isfinite(alpha), "alpha must be finite");
         need(m->Nc() == 0 || (p && y), "null vector");
         A::launch_amr_pressure(m->stream, m->geo(), m->tp, alpha, p, y, false);
+        return TBDG_OK;
+    });
+}
+
+tbdg_status tbdg_amr_face_qpoints(const tbdg_amr* m, int64_t* n_points, double* xy) {
+    if (!m || !n_points) return TBDG_EINVAL;
+    return aguard(const_cast<tbdg_amr*>(m), [&]() {
+        const int n = m->k + 1;
+        *n_points = m->n_bfaces * n;
+        if (!xy || m->n_bfaces == 0) return TBDG_OK;
+        std::vector<double> pts(2 * (size_t)*n_points);
+        const Forest& F = m->F;
+        int64_t b = 0;
+        for (int64_t c = 0; c < m->Nc(); ++c) {
+            const Leaf& L = F.leaves[c];
+            const double h[2] = {F.size((int)c, 0), F.size((int)c, 1)};
+            const double o[2] = {F.lo[0] + L.i * h[0], F.lo[1] + L.j * h[1]};
+            for (int a = 0; a < 2; ++a)
+                for (int s = 0; s < 2; ++s) {
+                    if (F.neighbours((int)c, a, s).kind != A::FACE_BOUNDARY) continue;
+                    for (int q = 0; q < n; ++q) {
+                        pts[2 * (b * n + q) + a] = o[a] + s * h[a];
+                        pts[2 * (b * n + q) + 1 - a] = o[1 - a] + h[1 - a] * m->tu.z[q];
+                    }
+                    ++b;
+                }
+        }
+        TBDG_HIP(hipMemcpyAsync(xy, pts.data(), sizeof(double) * pts.size(), hipMemcpyHostToDevice,
+                                m->stream));
+        TBDG_HIP(hipStreamSynchronize(m->stream));
+        return TBDG_OK;
+    });
+}
+
+tbdg_status tbdg_amr_apply_momentum(tbdg_amr* m, double mc, double tnu, double th, const double* w,
+                                    const double* u, const double* uD, double* y) {
+    if (!m) return TBDG_EINVAL;
+    return aguard(m, [&]() {
+        need(std::isfinite(mc) && std::isfinite(tnu) && std::isfinite(th), "coefficients must be finite");
+        need(m->Nc() == 0 || (w && u && y), "null vector");
+        need(m->n_bfaces == 0 || uD, "the mesh has walls: wall data uD needed");
+        need(u != y && w != y, "y must not alias u or w");
+        A::launch_amr_momentum(m->stream, m->geo(), m->tu, mc, tnu, th, w, u, uD, y);
         return TBDG_OK;
     });
 }

@@ -177,6 +177,233 @@ __global__ __launch_bounds__(256) void k_amr_pressure(Geo g, Tab1 t, double alph
     }
 }
 
+// Momentum operator y_c = mc M u_c + tnu A u_c + th C(w) u_c on both
+// velocity components: A the SIP form of eq. bilin_diff (Dirichlet walls:
+// -grad u.n v - u n.grad v + 2 C u v), C(w) the Lax-Friedrichs form of
+// eq. trilinear.  The face phase forms, at each face node of every cell,
+// the exterior SIP traces as in the pressure kernel and the whole
+// advective flux seen by the cell's own test functions: at its own nodes
+// when the neighbour is as fine or coarser (the coarser traces
+// interpolated), and on a face with two finer neighbours at the fine
+// faces' Gauss points (own traces interpolated there, lambda from the two
+// traces at each point), tested against the cell's tangential basis.
+template <int N>
+__global__ __launch_bounds__(256) void k_amr_momentum(Geo g, Tab1 t, double mc, double tnu, double th,
+                                                      const double* __restrict__ w,
+                                                      const double* __restrict__ u,
+                                                      const double* __restrict__ uD,
+                                                      double* __restrict__ y) {
+    constexpr int NB = N * N;
+    constexpr int CPB = 256 / NB;
+    __shared__ double s_u[2][CPB * NB];
+    __shared__ double s_w[2][CPB * NB];
+    __shared__ double s_e[CPB * 4 * N * 6];
+    __shared__ double s_y[2][2][CPB * NB];
+    const int tid = threadIdx.x;
+    const int lc = tid / NB, nd = tid % NB;
+    const int cell0 = blockIdx.x * CPB;
+    const int cell = cell0 + lc;
+    const bool active = lc < CPB && cell < g.Nc;
+    if (lc < CPB) {
+#pragma unroll
+        for (int c = 0; c < 2; ++c) {
+            s_u[c][tid] = active ? u[((size_t)cell * 2 + c) * NB + nd] : 0.0;
+            s_w[c][tid] = active ? w[((size_t)cell * 2 + c) * NB + nd] : 0.0;
+        }
+    }
+    __syncthreads();
+    for (int it = tid; it < CPB * 4 * N; it += 256) {
+        const int c2 = it / (4 * N), f = (it / N) % 4, tt = it % N;
+        const int cl = cell0 + c2;
+        double e[6] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0};   // (ve, de, F) per component
+        if (cl < g.Nc) {
+            const int meta = g.meta[cl * 4 + f];
+            const int kind = meta & 15, half = meta >> 4;
+            const int a = f >> 1, s = f & 1, so = 1 - s;
+            const double nu = s ? 1.0 : -1.0;
+            const int own = g.level[cl];
+            const int base = c2 * NB;
+            // own face traces at own face node m: u_c and w_a
+            auto own_trace = [&](int m, double& u0, double& u1, double& wa) {
+                u0 = u1 = wa = 0.0;
+#pragma unroll
+                for (int j = 0; j < N; ++j) {
+                    const int q = base + nd2<N>(a, j, m);
+                    u0 += t.L[s][j] * s_u[0][q];
+                    u1 += t.L[s][j] * s_u[1][q];
+                    wa += t.L[s][j] * s_w[a][q];
+                }
+            };
+            // neighbour's traces on its grid line m at its side so: values
+            // and reference derivatives of u_c, value of w_a
+            auto nbr_trace = [&](int nb, int m, double* v, double* d, double& wa) {
+                v[0] = v[1] = d[0] = d[1] = wa = 0.0;
+#pragma unroll
+                for (int j = 0; j < N; ++j) {
+                    const int q = nd2<N>(a, j, m);
+                    const double u0 = u[((size_t)nb * 2 + 0) * NB + q];
+                    const double u1 = u[((size_t)nb * 2 + 1) * NB + q];
+                    v[0] += t.L[so][j] * u0;
+                    v[1] += t.L[so][j] * u1;
+                    d[0] += t.dL[so][j] * u0;
+                    d[1] += t.dL[so][j] * u1;
+                    wa += t.L[so][j] * w[((size_t)nb * 2 + a) * NB + q];
+                }
+            };
+            if (kind == FACE_BOUNDARY) {
+                double u0, u1, wa;
+                own_trace(tt, u0, u1, wa);
+                const double uda = uD[((size_t)g.bface[cl * 4 + f] * N + tt) * 2 + a];
+                const double lam = fmax(fabs(wa), fabs(2.0 * uda - wa));
+                e[2] = lam * u0;
+                e[5] = lam * u1;
+            } else if (kind == FACE_SAME || kind == FACE_COARSER) {
+                double v[2], d[2], we;
+                const int nb = g.nbr[cl * 8 + f * 2];
+                if (kind == FACE_SAME) {
+                    nbr_trace(nb, tt, v, d, we);
+                } else {
+                    v[0] = v[1] = d[0] = d[1] = we = 0.0;
+#pragma unroll
+                    for (int m = 0; m < N; ++m) {
+                        double vm[2], dm[2], wm;
+                        nbr_trace(nb, m, vm, dm, wm);
+                        const double T = t.T[half][tt * N + m];
+                        v[0] += T * vm[0];
+                        v[1] += T * vm[1];
+                        d[0] += T * dm[0];
+                        d[1] += T * dm[1];
+                        we += T * wm;
+                    }
+                }
+                const double hn = g.H[a] / (double)(1 << (kind == FACE_SAME ? own : own - 1));
+                double uo[2], wo;
+                own_trace(tt, uo[0], uo[1], wo);
+                const double lam = fmax(fabs(wo), fabs(we));
+#pragma unroll
+                for (int c = 0; c < 2; ++c) {
+                    e[3 * c] = v[c];
+                    e[3 * c + 1] = d[c] / hn;
+                    e[3 * c + 2] = 0.5 * nu * (uo[c] * wo + v[c] * we) + 0.5 * lam * (uo[c] - v[c]);
+                }
+            } else if (kind == FACE_FINER) {
+                const double hn = g.H[a] / (double)(1 << (own + 1));
+                double tr0[N], tr1[N], trw[N];
+#pragma unroll
+                for (int m = 0; m < N; ++m) own_trace(m, tr0[m], tr1[m], trw[m]);
+                for (int h = 0; h < 2; ++h) {
+                    const int nb = g.nbr[cl * 8 + f * 2 + h];
+#pragma unroll
+                    for (int q = 0; q < N; ++q) {
+                        double v[2], d[2], we;
+                        nbr_trace(nb, q, v, d, we);
+                        double uo0 = 0.0, uo1 = 0.0, wo = 0.0;
+#pragma unroll
+                        for (int m = 0; m < N; ++m) {
+                            const double T = t.T[h][q * N + m];
+                            uo0 += T * tr0[m];
+                            uo1 += T * tr1[m];
+                            wo += T * trw[m];
+                        }
+                        const double lam = fmax(fabs(wo), fabs(we));
+                        const double wq = 0.5 * t.W[q] * t.T[h][q * N + tt];
+                        const double F0 = 0.5 * nu * (uo0 * wo + v[0] * we) + 0.5 * lam * (uo0 - v[0]);
+                        const double F1 = 0.5 * nu * (uo1 * wo + v[1] * we) + 0.5 * lam * (uo1 - v[1]);
+                        e[0] += wq * v[0];
+                        e[1] += wq * d[0];
+                        e[2] += wq * F0;
+                        e[3] += wq * v[1];
+                        e[4] += wq * d[1];
+                        e[5] += wq * F1;
+                    }
+                }
+                const double iw = 1.0 / t.W[tt];
+#pragma unroll
+                for (int c = 0; c < 2; ++c) {
+                    e[3 * c] *= iw;
+                    e[3 * c + 1] *= iw / hn;
+                    e[3 * c + 2] *= iw;
+                }
+            }
+        }
+#pragma unroll
+        for (int q = 0; q < 6; ++q) s_e[it * 6 + q] = e[q];
+    }
+    __syncthreads();
+    // one item per (cell, direction, component, line)
+    for (int it = tid; it < CPB * 4 * N; it += 256) {
+        const int c2 = it / (4 * N), a = (it / (2 * N)) % 2, c = (it / N) % 2, tt = it % N;
+        const int cl = cell0 + c2;
+        if (cl >= g.Nc) continue;
+        const int own = g.level[cl];
+        const double sc = 1.0 / (double)(1 << own);
+        const double h = g.H[a] * sc, ht = g.H[1 - a] * sc;
+        const double Wt = t.W[tt] * ht;
+        double pp[N], wa[N];
+#pragma unroll
+        for (int m = 0; m < N; ++m) {
+            const int q = c2 * NB + nd2<N>(a, m, tt);
+            pp[m] = s_u[c][q];
+            wa[m] = s_w[a][q];
+        }
+        const double sig = g.csig_u / h;
+        double pv[2], pn[2], C[2], ve[2], de[2], F[2];
+        int kind[2];
+#pragma unroll
+        for (int s = 0; s < 2; ++s) {
+            const double nu = s ? 1.0 : -1.0;
+            pv[s] = 0.0;
+            pn[s] = 0.0;
+#pragma unroll
+            for (int j = 0; j < N; ++j) {
+                pv[s] += t.L[s][j] * pp[j];
+                pn[s] += t.dL[s][j] * pp[j];
+            }
+            pn[s] *= nu / h;
+            const int f = 2 * a + s;
+            kind[s] = g.meta[cl * 4 + f] & 15;
+            C[s] = kind[s] == FACE_SAME ? sig
+                 : kind[s] == FACE_COARSER ? 0.5 * (sig + 0.5 * sig)
+                 : kind[s] == FACE_FINER ? 0.5 * (sig + 2.0 * sig) : sig;
+            const int e = (((c2 * 4 + f) * N + tt) * 6) + 3 * c;
+            ve[s] = s_e[e];
+            de[s] = s_e[e + 1];
+            F[s] = s_e[e + 2];
+        }
+#pragma unroll
+        for (int i = 0; i < N; ++i) {
+            double rd = 0.0, ra = 0.0;
+#pragma unroll
+            for (int j = 0; j < N; ++j) {
+                rd += t.S[i * N + j] * pp[j];
+                ra -= t.W[j] * t.D[j * N + i] * pp[j] * wa[j];
+            }
+            rd *= Wt / h;
+            ra *= Wt;
+#pragma unroll
+            for (int s = 0; s < 2; ++s) {
+                const double nu = s ? 1.0 : -1.0;
+                const double Li = t.L[s][i], dLi = nu * t.dL[s][i] / h;
+                if (kind[s] == FACE_BOUNDARY)
+                    rd += Wt * (-pn[s] * Li - dLi * pv[s] + 2.0 * C[s] * pv[s] * Li);
+                else
+                    rd += Wt * (-0.5 * (pn[s] + nu * de[s]) * Li - 0.5 * dLi * (pv[s] - ve[s])
+                                + C[s] * (pv[s] - ve[s]) * Li);
+                ra += Wt * Li * F[s];
+            }
+            s_y[c][a][c2 * NB + nd2<N>(a, i, tt)] = tnu * rd + th * ra;
+        }
+    }
+    __syncthreads();
+    if (active) {
+        const double sc = 1.0 / (double)(1 << g.level[cell]);
+        const double m = mc * t.W[nd % N] * t.W[nd / N] * g.H[0] * g.H[1] * sc * sc;
+#pragma unroll
+        for (int c = 0; c < 2; ++c)
+            y[((size_t)cell * 2 + c) * NB + nd] = m * s_u[c][tid] + s_y[c][0][tid] + s_y[c][1][tid];
+    }
+}
+
 // eta_K = (h_x^2 + h_y^2) sum_nodes W |K| omega^2, omega = d_x u_y - d_y u_x
 template <int N>
 __global__ __launch_bounds__(256) void k_amr_indicator(Geo g, Tab1 t, const double* __restrict__ u,
@@ -348,6 +575,30 @@ void launch_amr_pressure(hipStream_t st, const Geo& g, const Tab1& t, double alp
         default: throw Error(TBDG_EUNSUPPORTED, "pressure nodes per direction must be 1..7");
     }
 #undef TBDG_AMR_P
+    TBDG_HIP(hipGetLastError());
+}
+
+void launch_amr_momentum(hipStream_t st, const Geo& g, const Tab1& t, double mc, double tnu, double th,
+                         const double* w, const double* u, const double* uD, double* y) {
+    if (g.Nc == 0) return;
+#define TBDG_AMR_M(NV)                                                                        \
+    case NV: {                                                                                \
+        constexpr int CPB = 256 / (NV * NV);                                                  \
+        hipLaunchKernelGGL((k_amr_momentum<NV>), dim3((g.Nc + CPB - 1) / CPB), dim3(256), 0, st, \
+                           g, t, mc, tnu, th, w, u, uD, y);                                   \
+        break;                                                                                \
+    }
+    switch (t.n) {
+        TBDG_AMR_M(2)
+        TBDG_AMR_M(3)
+        TBDG_AMR_M(4)
+        TBDG_AMR_M(5)
+        TBDG_AMR_M(6)
+        TBDG_AMR_M(7)
+        TBDG_AMR_M(8)
+        default: throw Error(TBDG_EUNSUPPORTED, "velocity nodes per direction must be 2..8");
+    }
+#undef TBDG_AMR_M
     TBDG_HIP(hipGetLastError());
 }
 

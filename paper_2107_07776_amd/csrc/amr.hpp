@@ -31,9 +31,11 @@ struct Geo {
     const int* level;     // [Nc]
     const int* meta;      // [Nc][4]
     const int* nbr;       // [Nc][4][2]: the neighbour, or the two finer ones
+    const int* bface;     // [Nc][4]: boundary face number (cell, face order), or -1
     int Nc;
     double H[2];          // base cell size per direction
-    double csig;          // k^2 times the penalty multiplier
+    double csig;          // pressure: k^2 times the penalty multiplier
+    double csig_u;        // velocity: (k+1)^2 times the penalty multiplier
 };
 
 // Source of every new cell in a transfer: kind 0 copy of src[0], kind 1
@@ -47,6 +49,10 @@ struct XferMap {
 
 void launch_amr_pressure(hipStream_t st, const Geo& g, const Tab1& t, double alpha, const double* p,
                          double* y, bool diag);
+// y_c = mc M u_c + tnu A u_c + th C(w) u_c, c = 0, 1; uD: wall data at the
+// velocity Gauss points of the boundary faces (face number bface, n points)
+void launch_amr_momentum(hipStream_t st, const Geo& g, const Tab1& t, double mc, double tnu, double th,
+                         const double* w, const double* u, const double* uD, double* y);
 void launch_amr_indicator(hipStream_t st, const Geo& g, const Tab1& t, const double* u, double* eta);
 void launch_amr_transfer(hipStream_t st, const XferMap& m, const Tab1& t, int ncomp, const double* src,
                          double* dst);

@@ -40,7 +40,7 @@ EXPORTED = [
     "tbdg_amr_create", "tbdg_amr_destroy", "tbdg_amr_last_error", "tbdg_amr_set_stream",
     "tbdg_amr_sizes", "tbdg_amr_leaves", "tbdg_amr_apply_pressure", "tbdg_amr_diag_pressure",
     "tbdg_amr_solve_pressure", "tbdg_amr_indicator", "tbdg_amr_mark", "tbdg_amr_plan",
-    "tbdg_amr_transfer", "tbdg_amr_commit",
+    "tbdg_amr_transfer", "tbdg_amr_commit", "tbdg_amr_face_qpoints", "tbdg_amr_apply_momentum",
 ]
 
 GUESS = {"given": 0, "previous": 1, "learned": 2, "extrap2": 3, "extrap3": 4}
@@ -60,7 +60,7 @@ SCHEME = {"trbdf2": 0, "bcg": 1, "bdf2": 2}
 class AmrDesc(ctypes.Structure):
     _fields_ = [("n_cells", ctypes.c_int * 2), ("lo", ctypes.c_double * 2),
                 ("hi", ctypes.c_double * 2), ("periodic", ctypes.c_int * 2), ("k", ctypes.c_int),
-                ("max_level", ctypes.c_int), ("pen_p", ctypes.c_double)]
+                ("max_level", ctypes.c_int), ("pen_p", ctypes.c_double), ("pen_u", ctypes.c_double)]
 
 
 class TrbdgError(RuntimeError):
@@ -192,6 +192,8 @@ def load_library(path=LIB_PATH):
         "tbdg_amr_plan": ([vp, vp, P(i64)], i),
         "tbdg_amr_transfer": ([vp, i, vp, vp], i),
         "tbdg_amr_commit": ([vp], i),
+        "tbdg_amr_face_qpoints": ([vp, P(i64), vp], i),
+        "tbdg_amr_apply_momentum": ([vp, d, d, d, vp, vp, vp, vp], i),
     }
     for name, (args, res) in sig.items():
         fn = getattr(lib, name)
@@ -671,8 +673,8 @@ class Adaptive:
     stream: the pressure Helmholtz operator and its CG solve, the vorticity
     indicator, marking and remeshing with field transfer."""
 
-    def __init__(self, n_cells, lo, hi, k, max_level, periodic=(0, 0), pen_p=1.0, stream=None,
-                 device="cuda"):
+    def __init__(self, n_cells, lo, hi, k, max_level, periodic=(0, 0), pen_p=1.0, pen_u=1.0,
+                 stream=None, device="cuda"):
         self.lib = load_library()
         self.device = torch.device(device)
         if self.device.type != "cuda" or not torch.cuda.is_available():
@@ -683,7 +685,7 @@ class Adaptive:
             d.lo[a] = float(lo[a])
             d.hi[a] = float(hi[a])
             d.periodic[a] = int(bool(periodic[a]))
-        d.k, d.max_level, d.pen_p = int(k), int(max_level), float(pen_p)
+        d.k, d.max_level, d.pen_p, d.pen_u = int(k), int(max_level), float(pen_p), float(pen_u)
         self.stream = stream if stream is not None else torch.cuda.current_stream(self.device)
         h = ctypes.c_void_p()
         st = self.lib.tbdg_amr_create(ctypes.byref(d), ctypes.c_void_p(self.stream.cuda_stream),
@@ -720,6 +722,24 @@ class Adaptive:
         y = out if out is not None else torch.empty(self.N_p, dtype=torch.float64, device=self.device)
         self._check(self.lib.tbdg_amr_apply_pressure(self.h, float(alpha), _ptr(self._vec(p, self.N_p, "p")),
                                                      _ptr(self._vec(y, self.N_p, "out"))))
+        return y
+
+    def face_qpoints(self):
+        """(n, 2) tensor of the wall faces' velocity Gauss points."""
+        n = ctypes.c_int64()
+        self._check(self.lib.tbdg_amr_face_qpoints(self.h, ctypes.byref(n), None))
+        out = torch.empty((n.value, 2), dtype=torch.float64, device=self.device)
+        if n.value:
+            self._check(self.lib.tbdg_amr_face_qpoints(self.h, ctypes.byref(n), _ptr(out)))
+        return out
+
+    def apply_momentum(self, mc, tnu, th, w, u, uD=None, out=None):
+        y = out if out is not None else torch.empty(self.N_u, dtype=torch.float64, device=self.device)
+        if uD is not None and (uD.dtype != torch.float64 or not uD.is_contiguous()):
+            raise ValueError("uD must be a contiguous float64 CUDA tensor")
+        self._check(self.lib.tbdg_amr_apply_momentum(
+            self.h, float(mc), float(tnu), float(th), _ptr(self._vec(w, self.N_u, "w")),
+            _ptr(self._vec(u, self.N_u, "u")), _ptr(uD), _ptr(self._vec(y, self.N_u, "out"))))
         return y
 
     def diag_pressure(self, alpha):

@@ -194,3 +194,43 @@ def test_errors():
             g.mark(eta)
     finally:
         g.close()
+
+
+MOM_CASES = [(4, (3, 2), (0, 0), 2), (5, (3, 2), (1, 0), 3), (6, (4, 3), (1, 1), 3), (7, (2, 5), (0, 1), 4)]
+
+
+@pytest.mark.parametrize("seed,nc,per,k", MOM_CASES)
+def test_momentum_operator_matches_oracle(seed, nc, per, k):
+    """mc M + tnu A + th C(w) on both components, random w and u, wall data
+    from a smooth field at the wall points (exported in the oracle's order)."""
+    g, f = _pair(seed, nc, per, k)
+    try:
+        ad = AdaptiveDisc(f, k)
+        xb = g.face_qpoints().cpu().numpy()
+        assert np.abs(xb - ad.boundary_points()).max() < 1e-14 if len(xb) else True
+        uD = np.stack([np.sin(xb[:, 0] + 2 * xb[:, 1]), np.cos(3 * xb[:, 0] - xb[:, 1])], 1) \
+            if len(xb) else np.zeros((0, 2))
+        w = synthetic.random_vector(ad.N_u, 500 + seed)
+        u = synthetic.random_vector(ad.N_u, 600 + seed)
+        for mc, tnu, th in ((3.0, 0.01, 0.5), (0.0, 1.0, 0.0), (0.0, 0.0, 1.0)):
+            y = g.apply_momentum(mc, tnu, th, _t(w), _t(u), _t(uD) if len(xb) else None)
+            ref = ad.apply_momentum(mc, tnu, th, w, u, uD)
+            err = np.abs(y.cpu().numpy() - ref).max() / np.abs(ref).max()
+            assert err <= 1e-12, (mc, tnu, th, err)
+    finally:
+        g.close()
+
+
+def test_momentum_walls_need_data():
+    from paper_2107_07776_amd import Adaptive
+    from paper_2107_07776_amd.trbdg import TrbdgError
+    g = Adaptive((2, 2), (0.0, 0.0), (1.0, 1.0), 2, 2, periodic=(1, 0))
+    try:
+        u = torch.zeros(g.N_u, dtype=torch.float64, device="cuda")
+        with pytest.raises(TrbdgError):
+            g.apply_momentum(1.0, 1.0, 1.0, u, u.clone())
+        uD = torch.zeros((g.face_qpoints().shape[0], 2), dtype=torch.float64, device="cuda")
+        with pytest.raises(TrbdgError):
+            g.apply_momentum(1.0, 1.0, 1.0, u.clone(), u, uD, out=u)   # y aliases u
+    finally:
+        g.close()
