@@ -624,6 +624,16 @@ TBDG_API tbdg_status tbdg_amr_face_qpoints(const tbdg_amr* amr, int64_t* n_point
 TBDG_API tbdg_status tbdg_amr_apply_momentum(tbdg_amr* amr, double mc, double tnu, double th,
                                              const double* w, const double* u, const double* uD,
                                              double* y);
+/* Restarted GMRES(restart) for (mc M + tnu A + th C(w)) x = b (both
+ * components in one Krylov space), right-preconditioned by the diagonal of
+ * mc M + tnu A, modified Gram-Schmidt, FP64 throughout, from the given x to
+ * a true residual ||b - A x|| <= tol ||b|| (checked at every restart).
+ * Errors: TBDG_ENOTCONV, TBDG_EBREAKDOWN, TBDG_ENAN; x holds the last
+ * iterate.                                                                  */
+TBDG_API tbdg_status tbdg_amr_solve_momentum(tbdg_amr* amr, double mc, double tnu, double th,
+                                             const double* w, const double* uD, const double* b,
+                                             double* x, double tol, int maxiter, int restart,
+                                             tbdg_solve_info* info);
 /* d = diag(alpha M^p + K).                                                 */
 TBDG_API tbdg_status tbdg_amr_diag_pressure(tbdg_amr* amr, double alpha, double* d);
 /* Jacobi-preconditioned CG for (alpha M^p + K) x = b from the given x

@@ -266,6 +266,8 @@ struct tbdg_amr {
     int64_t x_cap = 0;
     double *cg = nullptr;   // r, z, p, q, d
     int64_t cg_cap = 0;
+    double* gm = nullptr;   // momentum GMRES: basis, z, diagonal
+    int64_t gm_cap = 0;
     double* part = nullptr;
     double* scal = nullptr;      // device scalars: rz[2], pq, rr, bb
     double* host = nullptr;      // pinned
@@ -336,6 +338,7 @@ struct tbdg_amr {
         devfree(xkind);
         devfree(xsrc);
         devfree(cg);
+        devfree(gm);
         devfree(part);
         devfree(scal);
         if (host) (void)hipHostFree(host);
@@ -522,6 +525,131 @@ tbdg_status tbdg_amr_apply_momentum(tbdg_amr* m, double mc, double tnu, double t
         need(u != y && w != y, "y must not alias u or w");
         A::launch_amr_momentum(m->stream, m->geo(), m->tu, mc, tnu, th, w, u, uD, y);
         return TBDG_OK;
+    });
+}
+
+tbdg_status tbdg_amr_solve_momentum(tbdg_amr* m, double mc, double tnu, double th, const double* w,
+                                    const double* uD, const double* b, double* x, double tol,
+                                    int maxiter, int restart, tbdg_solve_info* info) {
+    if (!m) return TBDG_EINVAL;
+    return aguard(m, [&]() {
+        need(std::isfinite(mc) && std::isfinite(tnu) && std::isfinite(th), "coefficients must be finite");
+        need(tol > 0.0 && maxiter >= 0 && restart >= 1 && restart <= 200, "need tol > 0, restart 1..200");
+        need(w && b && x, "null vector");
+        need(m->n_bfaces == 0 || uD, "the mesh has walls: wall data uD needed");
+        need(x != w && b != w && x != b, "x, b and w must be distinct");
+        const int64_t n = m->Nu();
+        const int mr = restart;
+        // basis (mr + 1 vectors), z, the diagonal
+        const int64_t need_cap = (int64_t)(mr + 3) * n;
+        if (need_cap > m->gm_cap) {
+            devfree(m->gm);
+            m->gm = devalloc<double>(need_cap);
+            m->gm_cap = need_cap;
+        }
+        double* V = m->gm;
+        double* z = V + (int64_t)(mr + 1) * n;
+        double* dg = z + n;
+        const hipStream_t st = m->stream;
+        const A::Geo g = m->geo();
+        auto op = [&](const double* in, double* out) {
+            A::launch_amr_momentum(st, g, m->tu, mc, tnu, th, w, in, uD, out);
+        };
+        A::launch_amr_momentum_diag(st, g, m->tu, mc, tnu, dg);
+        tbdg_solve_info inf{0, 0.0, 0.0, 0, 0};
+        const double bnorm = std::sqrt(dot(m, n, b, b, 4));
+        if (bnorm == 0.0) {
+            TBDG_HIP(hipMemsetAsync(x, 0, sizeof(double) * n, st));
+            if (info) *info = inf;
+            return TBDG_OK;
+        }
+        if (!std::isfinite(bnorm)) return TBDG_ENAN;
+        std::vector<double> H((size_t)(mr + 1) * mr), cs(mr), sn(mr), gv(mr + 1), y(mr);
+        int total = 0;
+        tbdg_status status = TBDG_ENOTCONV;
+        double res = 0.0;
+        for (bool first = true;; first = false) {
+            // true residual r = b - A x into V_0
+            op(x, z);
+            trbdg::vec_axpby(st, n, 1.0, b, -1.0, z, V);
+            const double beta = std::sqrt(dot(m, n, V, V, 3));
+            res = beta / bnorm;
+            if (first) inf.res0 = res;
+            if (!std::isfinite(res)) {
+                status = TBDG_ENAN;
+                break;
+            }
+            if (res <= tol) {
+                status = TBDG_OK;
+                break;
+            }
+            if (total >= maxiter) break;
+            trbdg::vec_scale_copy(st, n, 1.0 / beta, V, V);
+            std::fill(gv.begin(), gv.end(), 0.0);
+            gv[0] = beta;
+            int j = 0;
+            bool breakdown = false;
+            for (; j < mr && total < maxiter; ++j) {
+                ++total;
+                double* vj = V + (int64_t)j * n;
+                double* vn = V + (int64_t)(j + 1) * n;
+                A::launch_amr_div(st, n, vj, dg, z);
+                op(z, vn);
+                // modified Gram-Schmidt
+                for (int i = 0; i <= j; ++i) {
+                    const double hij = dot(m, n, vn, V + (int64_t)i * n, 2);
+                    H[(size_t)i * mr + j] = hij;
+                    trbdg::vec_axpby(st, n, 1.0, vn, -hij, V + (int64_t)i * n, vn);
+                }
+                const double hn = std::sqrt(dot(m, n, vn, vn, 2));
+                H[(size_t)(j + 1) * mr + j] = hn;
+                for (int i = 0; i < j; ++i) {
+                    const double t1 = cs[i] * H[(size_t)i * mr + j] + sn[i] * H[(size_t)(i + 1) * mr + j];
+                    const double t2 = -sn[i] * H[(size_t)i * mr + j] + cs[i] * H[(size_t)(i + 1) * mr + j];
+                    H[(size_t)i * mr + j] = t1;
+                    H[(size_t)(i + 1) * mr + j] = t2;
+                }
+                const double a = H[(size_t)j * mr + j], bb = H[(size_t)(j + 1) * mr + j];
+                const double r = std::hypot(a, bb);
+                if (r == 0.0 || !std::isfinite(r)) {
+                    breakdown = true;
+                    break;
+                }
+                cs[j] = a / r;
+                sn[j] = bb / r;
+                H[(size_t)j * mr + j] = r;
+                H[(size_t)(j + 1) * mr + j] = 0.0;
+                gv[j + 1] = -sn[j] * gv[j];
+                gv[j] = cs[j] * gv[j];
+                if (hn == 0.0 || std::fabs(gv[j + 1]) <= tol * bnorm) {
+                    ++j;
+                    break;
+                }
+                trbdg::vec_scale_copy(st, n, 1.0 / hn, vn, vn);
+            }
+            const int k = j;
+            for (int i = k - 1; i >= 0; --i) {
+                double s2 = gv[i];
+                for (int q = i + 1; q < k; ++q) s2 -= H[(size_t)i * mr + q] * y[q];
+                y[i] = s2 / H[(size_t)i * mr + i];
+            }
+            // x += D^{-1} V y
+            if (k > 0) {
+                trbdg::vec_scale_copy(st, n, y[0], V, z);
+                for (int i = 1; i < k; ++i) trbdg::vec_axpby(st, n, 1.0, z, y[i], V + (int64_t)i * n, z);
+                A::launch_amr_div(st, n, z, dg, z);
+                trbdg::vec_axpby(st, n, 1.0, x, 1.0, z, x);
+            }
+            if (breakdown && k == 0) {
+                status = TBDG_EBREAKDOWN;
+                break;
+            }
+        }
+        inf.iters = total;
+        inf.res_final = res;
+        if (info) *info = inf;
+        if (status != TBDG_OK) m->last_error = "adaptive-mesh momentum GMRES did not converge";
+        return status;
     });
 }
 

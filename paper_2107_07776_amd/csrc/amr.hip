@@ -404,6 +404,43 @@ __global__ __launch_bounds__(256) void k_amr_momentum(Geo g, Tab1 t, double mc, 
     }
 }
 
+// Diagonal of mc M + tnu A (the momentum operator without its advection),
+// in the velocity layout [cell][component][node]: the Jacobi scaling of the
+// momentum GMRES on adapted meshes.
+template <int N>
+__global__ __launch_bounds__(256) void k_amr_momentum_diag(Geo g, Tab1 t, double mc, double tnu,
+                                                           double* __restrict__ d) {
+    constexpr int NB = N * N;
+    const int64_t gid = (int64_t)blockIdx.x * 256 + threadIdx.x;
+    if (gid >= (int64_t)g.Nc * NB) return;
+    const int cell = (int)(gid / NB), nd = (int)(gid % NB);
+    const int own = g.level[cell];
+    const double sc = 1.0 / (double)(1 << own);
+    double r = mc * t.W[nd % N] * t.W[nd / N] * g.H[0] * g.H[1] * sc * sc;
+#pragma unroll
+    for (int a = 0; a < 2; ++a) {
+        const int i = a == 0 ? nd % N : nd / N, tt = a == 0 ? nd / N : nd % N;
+        const double h = g.H[a] * sc, ht = g.H[1 - a] * sc;
+        const double Wt = t.W[tt] * ht;
+        const double sig = g.csig_u / h;
+        double ra = t.S[i * N + i] * Wt / h;
+        for (int s = 0; s < 2; ++s) {
+            const int kind = g.meta[cell * 4 + 2 * a + s] & 15;
+            const double nu = s ? 1.0 : -1.0;
+            const double Li = t.L[s][i], dLi = nu * t.dL[s][i] / h;
+            if (kind == FACE_BOUNDARY) {
+                ra += Wt * (-2.0 * dLi * Li + 2.0 * sig * Li * Li);
+            } else {
+                const double C = kind == FACE_SAME ? sig : kind == FACE_COARSER ? 0.75 * sig : 1.5 * sig;
+                ra += Wt * (-dLi * Li + C * Li * Li);
+            }
+        }
+        r += tnu * ra;
+    }
+    d[((size_t)cell * 2 + 0) * NB + nd] = r;
+    d[((size_t)cell * 2 + 1) * NB + nd] = r;
+}
+
 // eta_K = (h_x^2 + h_y^2) sum_nodes W |K| omega^2, omega = d_x u_y - d_y u_x
 template <int N>
 __global__ __launch_bounds__(256) void k_amr_indicator(Geo g, Tab1 t, const double* __restrict__ u,
@@ -539,9 +576,9 @@ __global__ __launch_bounds__(256) void k_amr_cg_dir(int64_t n, const double* rz_
     p[i] = z[i] + (*rz_new / *rz_old) * p[i];
 }
 
-__global__ __launch_bounds__(256) void k_amr_div(int64_t n, const double* __restrict__ r,
-                                                 const double* __restrict__ d,
-                                                 double* __restrict__ z) {
+// z = r / d elementwise; z may alias r
+__global__ __launch_bounds__(256) void k_amr_div(int64_t n, const double* r, const double* d,
+                                                 double* z) {
     const int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
     if (i >= n) return;
     z[i] = r[i] / d[i];
@@ -599,6 +636,29 @@ void launch_amr_momentum(hipStream_t st, const Geo& g, const Tab1& t, double mc,
         default: throw Error(TBDG_EUNSUPPORTED, "velocity nodes per direction must be 2..8");
     }
 #undef TBDG_AMR_M
+    TBDG_HIP(hipGetLastError());
+}
+
+void launch_amr_momentum_diag(hipStream_t st, const Geo& g, const Tab1& t, double mc, double tnu,
+                              double* d) {
+    const int64_t total = (int64_t)g.Nc * t.n * t.n;
+    if (total == 0) return;
+#define TBDG_AMR_MD(NV)                                                                       \
+    case NV:                                                                                  \
+        hipLaunchKernelGGL((k_amr_momentum_diag<NV>), dim3(blocks(total)), dim3(256), 0, st, g, t, \
+                           mc, tnu, d);                                                       \
+        break;
+    switch (t.n) {
+        TBDG_AMR_MD(2)
+        TBDG_AMR_MD(3)
+        TBDG_AMR_MD(4)
+        TBDG_AMR_MD(5)
+        TBDG_AMR_MD(6)
+        TBDG_AMR_MD(7)
+        TBDG_AMR_MD(8)
+        default: throw Error(TBDG_EUNSUPPORTED, "velocity nodes per direction must be 2..8");
+    }
+#undef TBDG_AMR_MD
     TBDG_HIP(hipGetLastError());
 }
 

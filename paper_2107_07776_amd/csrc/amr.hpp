@@ -53,6 +53,9 @@ void launch_amr_pressure(hipStream_t st, const Geo& g, const Tab1& t, double alp
 // velocity Gauss points of the boundary faces (face number bface, n points)
 void launch_amr_momentum(hipStream_t st, const Geo& g, const Tab1& t, double mc, double tnu, double th,
                          const double* w, const double* u, const double* uD, double* y);
+// diag(mc M + tnu A) in the velocity layout (both components)
+void launch_amr_momentum_diag(hipStream_t st, const Geo& g, const Tab1& t, double mc, double tnu,
+                              double* d);
 void launch_amr_indicator(hipStream_t st, const Geo& g, const Tab1& t, const double* u, double* eta);
 void launch_amr_transfer(hipStream_t st, const XferMap& m, const Tab1& t, int ncomp, const double* src,
                          double* dst);

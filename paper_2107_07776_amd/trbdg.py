@@ -41,6 +41,7 @@ EXPORTED = [
     "tbdg_amr_sizes", "tbdg_amr_leaves", "tbdg_amr_apply_pressure", "tbdg_amr_diag_pressure",
     "tbdg_amr_solve_pressure", "tbdg_amr_indicator", "tbdg_amr_mark", "tbdg_amr_plan",
     "tbdg_amr_transfer", "tbdg_amr_commit", "tbdg_amr_face_qpoints", "tbdg_amr_apply_momentum",
+    "tbdg_amr_solve_momentum",
 ]
 
 GUESS = {"given": 0, "previous": 1, "learned": 2, "extrap2": 3, "extrap3": 4}
@@ -194,6 +195,7 @@ def load_library(path=LIB_PATH):
         "tbdg_amr_commit": ([vp], i),
         "tbdg_amr_face_qpoints": ([vp, P(i64), vp], i),
         "tbdg_amr_apply_momentum": ([vp, d, d, d, vp, vp, vp, vp], i),
+        "tbdg_amr_solve_momentum": ([vp, d, d, d, vp, vp, vp, vp, d, i, i, P(SolveInfo)], i),
     }
     for name, (args, res) in sig.items():
         fn = getattr(lib, name)
@@ -741,6 +743,17 @@ class Adaptive:
             self.h, float(mc), float(tnu), float(th), _ptr(self._vec(w, self.N_u, "w")),
             _ptr(self._vec(u, self.N_u, "u")), _ptr(uD), _ptr(self._vec(y, self.N_u, "out"))))
         return y
+
+    def solve_momentum(self, mc, tnu, th, w, b, x, uD=None, tol=1e-10, maxiter=5000, restart=30,
+                       check=True):
+        info = SolveInfo()
+        st = self.lib.tbdg_amr_solve_momentum(
+            self.h, float(mc), float(tnu), float(th), _ptr(self._vec(w, self.N_u, "w")), _ptr(uD),
+            _ptr(self._vec(b, self.N_u, "b")), _ptr(self._vec(x, self.N_u, "x")), float(tol),
+            int(maxiter), int(restart), ctypes.byref(info))
+        if check:
+            self._check(st)
+        return info.as_dict() | {"status": st}
 
     def diag_pressure(self, alpha):
         y = torch.empty(self.N_p, dtype=torch.float64, device=self.device)

@@ -234,3 +234,34 @@ def test_momentum_walls_need_data():
             g.apply_momentum(1.0, 1.0, 1.0, u.clone(), u, uD, out=u)   # y aliases u
     finally:
         g.close()
+
+
+@pytest.mark.parametrize("seed,nc,per,k", MOM_CASES[:3])
+def test_momentum_gmres_reaches_tolerance_and_direct_solution(seed, nc, per, k):
+    """A TR-BDF2 stage-like operator (mass 1/(gamma dt), theta nu = 0.01 / 2,
+    advection 1/2) with a random advecting field: GMRES(20) to 1e-12, the
+    true residual against the oracle's assembled operator and its direct
+    solution per component."""
+    import scipy.sparse.linalg as spla
+    g, f = _pair(seed, nc, per, k)
+    try:
+        ad = AdaptiveDisc(f, k)
+        xb = g.face_qpoints().cpu().numpy()
+        uD = np.stack([np.sin(xb[:, 0]), np.cos(xb[:, 1])], 1) if len(xb) else np.zeros((0, 2))
+        w = synthetic.random_vector(ad.N_u, 700 + seed)
+        b = synthetic.random_vector(ad.N_u, 800 + seed)
+        mc, tnu, th = 1.0 / (0.5858 * 0.02), 0.005, 0.5
+        x = torch.zeros(ad.N_u, dtype=torch.float64, device="cuda")
+        info = g.solve_momentum(mc, tnu, th, _t(w), _t(b), x, _t(uD) if len(xb) else None, tol=1e-12,
+                                maxiter=4000, restart=20)
+        xs = x.cpu().numpy()
+        r = b - ad.apply_momentum(mc, tnu, th, w, xs, uD)
+        assert np.linalg.norm(r) <= 1.01e-12 * np.linalg.norm(b), info
+        A = (mc * ad.mass_u() + tnu * ad.sip_u() + th * ad.lf_advection(w, uD)).tocsc()
+        B = b.reshape(f.N, 2, ad.nbu)
+        for comp in range(2):
+            xd = spla.spsolve(A, B[:, comp, :].reshape(-1))
+            xc = xs.reshape(f.N, 2, ad.nbu)[:, comp, :].reshape(-1)
+            assert np.abs(xc - xd).max() <= 1e-9 * np.abs(xd).max()
+    finally:
+        g.close()
