@@ -257,11 +257,15 @@ class AdaptiveDisc:
     indicator (degree k, n = k+1 nodes) on a QuadForest; all cells are
     axis-aligned rectangles, so every map is affine and diagonal."""
 
-    def __init__(self, forest, k, pen_p=1.0, pen_u=1.0):
+    def __init__(self, forest, k, pen_p=1.0, pen_u=1.0, nu=1.0, c=1.0e3):
         self.f = forest
+        self.mesh = forest
+        self.dim = 2
         self.k = int(k)
         self.pen_p = float(pen_p)
         self.pen_u = float(pen_u)
+        self.nu = float(nu)
+        self.c = float(c)
         self.n = self.k + 1
         self.n_p = self.k
         self.zu, self.wu = gauss_legendre_01(self.n)
@@ -271,6 +275,7 @@ class AdaptiveDisc:
         self.Nc = forest.N
         self.N_p = self.Nc * self.nbp
         self.N_u = 2 * self.Nc * self.nbu
+        self.n_scalar = self.Nc * self.nbu
 
     # tabulation of the 2D Lagrange basis on ``nodes`` at reference points
     # (xr, yr) of a cell of size h: values and physical gradients
@@ -288,7 +293,7 @@ class AdaptiveDisc:
     def _sigma(self, c, a):
         return self.k ** 2 * self.pen_p / float(self.f.size(c)[a])
 
-    def mass_p(self):
+    def mass_p(self, cells=None):
         rows, cols, vals = [], [], []
         for c in range(self.Nc):
             h = self.f.size(c)
@@ -312,7 +317,7 @@ class AdaptiveDisc:
         pts[:, 1 - a] = t
         return pts
 
-    def sip_p(self):
+    def sip_p(self, cells=None):
         """a_p(psi_j, psi_i): cell terms, then every interior face once, a
         coarse-fine face as two fine faces."""
         nb = self.nbp
@@ -407,14 +412,14 @@ class AdaptiveDisc:
     def _sigma_u(self, c, a):
         return (self.k + 1) ** 2 * self.pen_u / float(self.f.size(c)[a])
 
-    def mass_u(self):
+    def mass_u(self, cells=None):
         blocks = []
         for c in range(self.Nc):
             V, _, W = self._cell_tab_u(c)
             blocks.append((c, c, V.T @ (W[:, None] * V)))
         return self._assemble(blocks, self.nbu, self.Nc * self.nbu)
 
-    def sip_u(self):
+    def sip_u(self, cells=None):
         """The bracket of eq. bilin_diff for one component: interior faces as
         in a_p (penalty (k+1)^2 pen_u |Gamma_K|/|K| averaged), boundary faces
         of a non-periodic direction -grad u.n v - u n.grad v + 2 C u v."""
@@ -467,7 +472,186 @@ class AdaptiveDisc:
     def _w_cell(self, w, c):
         return w[c * 2 * self.nbu:(c + 1) * 2 * self.nbu].reshape(2, self.nbu)
 
-    def lf_advection(self, w, uD=None):
+    def _uD_at(self, uD, b, c, a, s, x):
+        """Wall data at the points x of boundary face (c, a, s), the b-th:
+        uD an (n_b, 2) array at boundary_points() or uD(c, a, s, x)."""
+        if callable(uD):
+            return np.asarray(uD(c, a, s, x), dtype=np.float64).reshape(len(x), 2)
+        return uD[b * self.n:(b + 1) * self.n]
+
+    def _bnd_face(self, c, a, s):
+        h, o = self.f.size(c), self.f.origin(c)
+        pc = np.zeros((self.n, 2)); pc[:, a] = float(s); pc[:, 1 - a] = self.zu
+        Vu, Gu = self._tab(self.zu, pc[:, 0], pc[:, 1], h)
+        Vp, Gp = self._tab(self.zp, pc[:, 0], pc[:, 1], h)
+        nvec = np.zeros(2); nvec[a] = 1.0 if s == 1 else -1.0
+        x = o[None, :] + pc * h[None, :]
+        return Vu, Gu, Vp, Gp, nvec, self.wu * float(h[1 - a]), x
+
+    def _pair_mixed(self, a, c, s, other, sub):
+        """Velocity and pressure tabulations of both sides at the velocity
+        Gauss points of the face (a, s) of c (the finer side)."""
+        h, ho = self.f.size(c), self.f.size(other)
+        pc = np.zeros((self.n, 2)); pc[:, a] = float(s); pc[:, 1 - a] = self.zu
+        po = np.zeros((self.n, 2)); po[:, a] = float(1 - s)
+        po[:, 1 - a] = self.zu if sub is None else 0.5 * (sub + self.zu)
+        side_c = self._tab(self.zu, pc[:, 0], pc[:, 1], h) + self._tab(self.zp, pc[:, 0], pc[:, 1], h)
+        side_o = self._tab(self.zu, po[:, 0], po[:, 1], ho) + self._tab(self.zp, po[:, 0], po[:, 1], ho)
+        nvec = np.zeros(2); nvec[a] = 1.0 if s == 1 else -1.0
+        return side_c, side_o, nvec, self.wu * float(h[1 - a])
+
+    def _cell_mixed(self, c):
+        h = self.f.size(c)
+        xr, yr = np.tile(self.zu, self.n), np.repeat(self.zu, self.n)
+        Vu, Gu = self._tab(self.zu, xr, yr, h)
+        Vp, Gp = self._tab(self.zp, xr, yr, h)
+        return Vu, Gu, Vp, Gp, np.kron(self.wu, self.wu) * h[0] * h[1]
+
+    def faces(self, cells=None):
+        """('I', ...) once per interior face or fine half face, ('B', a, c, s)
+        per boundary face."""
+        for a, c, s, other, sub in self._interfaces():
+            yield ("I", a, c, other)
+        for c, a, s in self._boundary_faces():
+            yield ("B", a, c, s)
+
+    def mass_u_vector(self, cells=None):
+        M = self.mass_u()
+        out = sp.block_diag([M, M]).tocsr()
+        # reorder [component][cell][node] -> [cell][component][node]
+        perm = np.arange(self.N_u).reshape(2, self.Nc, self.nbu).transpose(1, 0, 2).reshape(-1)
+        return out[perm][:, perm].tocsr()
+
+    def explicit_diffusion(self, cells=None):
+        """L0(u, v) = int grad u.grad v - sum_E int {{grad u}}.[[v]], the
+        whole skeleton (boundary: the interior trace), one component."""
+        blocks = []
+        for c in range(self.Nc):
+            V, G, W = self._cell_tab_u(c)
+            blocks.append((c, c, sum(G[:, :, d].T @ (W[:, None] * G[:, :, d]) for d in range(2))))
+        for a, c, s, other, sub in self._interfaces():
+            Vc, Gc, Vo, Go, nvec, dS = self._face_pair_u(a, c, s, other, sub)
+            tabs = [(c, Vc, Gc, nvec), (other, Vo, Go, -nvec)]
+            for (ct, Vt, _, nt) in tabs:
+                for (cs, _, Gs, _) in tabs:
+                    g = 0.5 * np.einsum("qjd,d->qj", Gs, nt)
+                    blocks.append((ct, cs, -(Vt * dS[:, None]).T @ g))
+        for c, a, s in self._boundary_faces():
+            Vu, Gu, _, _, nvec, dS, _ = self._bnd_face(c, a, s)
+            g = np.einsum("qjd,d->qj", Gu, nvec)
+            blocks.append((c, c, -(Vu * dS[:, None]).T @ g))
+        return self._assemble(blocks, self.nbu, self.Nc * self.nbu)
+
+    def explicit_advection(self, w, cells=None):
+        """A0_w(u, v) = int u (w.grad v) - sum_E int {{u w}}.[[v]], no
+        upwinding, the whole skeleton, one component."""
+        blocks = []
+        for c in range(self.Nc):
+            V, G, W = self._cell_tab_u(c)
+            wq = V @ self._w_cell(w, c).T
+            wgv = np.einsum("qd,qid->qi", wq, G)
+            blocks.append((c, c, (wgv * W[:, None]).T @ V))
+        for a, c, s, other, sub in self._interfaces():
+            Vc, _, Vo, _, nvec, dS = self._face_pair_u(a, c, s, other, sub)
+            wc = Vc @ self._w_cell(w, c).T
+            wo = Vo @ self._w_cell(w, other).T
+            tabs = [(c, Vc, nvec, wc), (other, Vo, -nvec, wo)]
+            for (ct, Vt, nt, _) in tabs:
+                for (cs, Vs, _, ws) in tabs:
+                    blocks.append((ct, cs, -(Vt * (0.5 * (ws @ nt) * dS)[:, None]).T @ Vs))
+        for c, a, s in self._boundary_faces():
+            Vu, _, _, _, nvec, dS, _ = self._bnd_face(c, a, s)
+            wq = Vu @ self._w_cell(w, c).T
+            blocks.append((c, c, -(Vu * ((wq @ nvec) * dS)[:, None]).T @ Vu))
+        return self._assemble(blocks, self.nbu, self.Nc * self.nbu)
+
+    def _mixed(self, blocks, rows_u):
+        """Assemble (velocity rows, pressure cols) or the transpose from
+        (row cell, col cell, component, block) entries."""
+        r, cidx, v = [], [], []
+        for (ru, cu, comp, blk) in blocks:
+            if rows_u:
+                r0 = (ru * 2 + comp) * self.nbu
+                c0 = cu * self.nbp
+            else:
+                r0 = ru * self.nbp
+                c0 = (cu * 2 + comp) * self.nbu
+            rr, cc = np.meshgrid(np.arange(blk.shape[0]) + r0, np.arange(blk.shape[1]) + c0, indexing="ij")
+            r.append(rr.ravel()); cidx.append(cc.ravel()); v.append(blk.ravel())
+        shape = (self.N_u, self.N_p) if rows_u else (self.N_p, self.N_u)
+        return sp.coo_matrix((np.concatenate(v), (np.concatenate(r), np.concatenate(cidx))),
+                             shape=shape).tocsr()
+
+    def weak_gradient(self, cells=None):
+        """(Gw p)(v) = sum_K int p div v - sum_E int {{p}} [[v]] (eq. rhs1)."""
+        blocks = []
+        for c in range(self.Nc):
+            Vu, Gu, Vp, _, W = self._cell_mixed(c)
+            for a in range(2):
+                blocks.append((c, c, a, (Gu[:, :, a] * W[:, None]).T @ Vp))
+        for a_, c, s, other, sub in self._interfaces():
+            (Vuc, _, Vpc, _), (Vuo, _, Vpo, _), nvec, dS = self._pair_mixed(a_, c, s, other, sub)
+            tabs = [(c, Vuc, Vpc, nvec), (other, Vuo, Vpo, -nvec)]
+            for (ct, Vut, _, nt) in tabs:
+                for (cs, _, Vps, _) in tabs:
+                    for a in range(2):
+                        blocks.append((ct, cs, a, -(Vut * (0.5 * nt[a] * dS)[:, None]).T @ Vps))
+        for c, a_, s in self._boundary_faces():
+            Vu, _, Vp, _, nvec, dS, _ = self._bnd_face(c, a_, s)
+            for a in range(2):
+                blocks.append((c, c, a, -(Vu * (nvec[a] * dS)[:, None]).T @ Vp))
+        return self._mixed(blocks, True)
+
+    def divergence(self, cells=None):
+        """(D u)(q) = sum_K int u.grad q - sum_E int {{u}}.[[q]]."""
+        blocks = []
+        for c in range(self.Nc):
+            Vu, _, _, Gp, W = self._cell_mixed(c)
+            for a in range(2):
+                blocks.append((c, c, a, (Gp[:, :, a] * W[:, None]).T @ Vu))
+        for a_, c, s, other, sub in self._interfaces():
+            (Vuc, _, Vpc, _), (Vuo, _, Vpo, _), nvec, dS = self._pair_mixed(a_, c, s, other, sub)
+            tabs = [(c, Vuc, Vpc, nvec), (other, Vuo, Vpo, -nvec)]
+            for (ct, _, Vpt, nt) in tabs:
+                for (cs, Vus, _, _) in tabs:
+                    for a in range(2):
+                        blocks.append((ct, cs, a, -(Vpt * (0.5 * nt[a] * dS)[:, None]).T @ Vus))
+        for c, a_, s in self._boundary_faces():
+            Vu, _, Vp, _, nvec, dS, _ = self._bnd_face(c, a_, s)
+            for a in range(2):
+                blocks.append((c, c, a, -(Vp * (nvec[a] * dS)[:, None]).T @ Vu))
+        return self._mixed(blocks, False)
+
+    def projection(self, cells=None):
+        """P_ij = sum_K int grad psi_j . phi_i (velocity rows, pressure cols)."""
+        blocks = []
+        for c in range(self.Nc):
+            Vu, _, _, Gp, W = self._cell_mixed(c)
+            for a in range(2):
+                blocks.append((c, c, a, (Vu * W[:, None]).T @ Gp[:, :, a]))
+        return self._mixed(blocks, True)
+
+    def dirichlet_rhs(self, theta, w, uD):
+        """Wall-data part of F_u: per component -theta nu int u_D (n.grad v)
+        + theta nu int 2 C u_D v - theta int u_D (w.n) v + theta int lambda u_D v."""
+        out = np.zeros(self.N_u)
+        for b, (c, a, s) in enumerate(self._boundary_faces()):
+            Vu, Gu, _, _, nvec, dS, x = self._bnd_face(c, a, s)
+            ud = self._uD_at(uD, b, c, a, s, x)
+            wq = Vu @ self._w_cell(w, c).T
+            wn = wq @ nvec
+            lam = np.maximum(np.abs(wn), np.abs((2.0 * ud - wq) @ nvec))
+            gn = np.einsum("qid,d->qi", Gu, nvec)
+            C = self._sigma_u(c, a)
+            for comp in range(2):
+                g = ud[:, comp] * dS
+                contrib = (-theta * self.nu * (gn.T @ g) + theta * self.nu * 2.0 * C * (Vu.T @ g)
+                           - theta * (Vu.T @ (g * wn)) + theta * (Vu.T @ (g * lam)))
+                base = (c * 2 + comp) * self.nbu
+                out[base:base + self.nbu] += contrib
+        return out
+
+    def lf_advection(self, w, uD=None, cells=None):
         """Linearised advection with the local Lax-Friedrichs flux (eq.
         trilinear) for one component, as in the box-mesh oracle:
         -int u (w.grad v) + sum_I int ({{u w}}.[[v]] + lambda/2 [[u]].[[v]])
@@ -491,17 +675,12 @@ class AdaptiveDisc:
                 for (cs, Vs, ns, ws) in tabs:
                     coef = 0.5 * (ws @ nt) + 0.5 * lam * float(ns @ nt)
                     blocks.append((ct, cs, (Vt * (coef * dS)[:, None]).T @ Vs))
-        b = 0
-        for c, a, s in self._boundary_faces():
-            h = self.f.size(c)
-            pc = np.zeros((self.n, 2)); pc[:, a] = float(s); pc[:, 1 - a] = self.zu
-            V, _ = self._tab(self.zu, pc[:, 0], pc[:, 1], h)
-            nvec = np.zeros(2); nvec[a] = 1.0 if s == 1 else -1.0
+        for b, (c, a, s) in enumerate(self._boundary_faces()):
+            V, _, _, _, nvec, dS, x = self._bnd_face(c, a, s)
             wq = V @ self._w_cell(w, c).T
-            wext = 2.0 * uD[b:b + self.n] - wq
-            b += self.n
+            wext = 2.0 * self._uD_at(uD, b, c, a, s, x) - wq
             lam = np.maximum(np.abs(wq @ nvec), np.abs(wext @ nvec))
-            blocks.append((c, c, (V * (lam * self.wu * float(h[1 - a]))[:, None]).T @ V))
+            blocks.append((c, c, (V * (lam * dS)[:, None]).T @ V))
         return self._assemble(blocks, self.nbu, self.Nc * self.nbu)
 
     def apply_momentum(self, mc, tnu, th, w, u, uD=None):

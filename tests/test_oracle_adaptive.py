@@ -409,3 +409,84 @@ def test_advection_cell_self_term_closed_form(periodic):
                     for o in nb[1]:
                         want += f.size(o)[1 - a] * 0.5 * (wn + max(abs(wn), abs(Wc[o] @ n)))
         assert abs(e @ (C @ e) - want) < 1e-12 * (1 + abs(want)), c0
+
+
+# ---------------------------------------------------------------------------
+# the explicit and mixed forms, and the TR-BDF2 step on adapted meshes
+# ---------------------------------------------------------------------------
+def _vector_embedding(Pi, ncell_f, ncell_c, nb):
+    """Componentwise embedding of [cell][component][node] vectors."""
+    Pi = Pi.tocoo()
+    r, c, v = [], [], []
+    for comp in range(2):
+        fr, fn = np.divmod(Pi.row, nb)
+        cr, cn = np.divmod(Pi.col, nb)
+        r.append((fr * 2 + comp) * nb + fn)
+        c.append((cr * 2 + comp) * nb + cn)
+        v.append(Pi.data)
+    return sp.coo_matrix((np.concatenate(v), (np.concatenate(r), np.concatenate(c))),
+                         shape=(2 * ncell_f * nb, 2 * ncell_c * nb)).tocsr()
+
+
+@pytest.mark.parametrize("periodic", [(False, False), (True, False)])
+def test_explicit_and_mixed_forms_equal_embedded_conforming_forms(periodic):
+    k = 3
+    f = _random_forest(31, periodic=periodic, max_level=2, rounds=2)
+    ad = AdaptiveDisc(f, k, nu=0.1)
+    Pu, box = _embedding(f, k + 1)
+    Pp, _ = _embedding(f, k)
+    disc = Discretization(box, k, nu=0.1)
+    Puv = _vector_embedding(Pu, box.N, f.N, ad.nbu)
+    L0 = disc.explicit_diffusion()
+    assert abs(ad.explicit_diffusion() - Pu.T @ L0 @ Pu).max() < 1e-11 * abs(L0).max()
+    for name, A, L, R in (("weak_gradient", ad.weak_gradient(), Puv, Pp),
+                          ("divergence", ad.divergence(), Pp, Puv),
+                          ("projection", ad.projection(), Puv, Pp),
+                          ("mass_u_vector", ad.mass_u_vector(), Puv, Puv)):
+        ref = getattr(disc, name)()
+        assert abs(A - L.T @ ref @ R).max() < 1e-12 * abs(ref).max(), name
+    wc = np.array([-0.4, 0.9])
+    wa = np.tile(np.repeat(wc, ad.nbu), f.N)
+    wf = np.tile(np.repeat(wc, disc.nbu), box.N)
+    A0 = disc.explicit_advection(wf)
+    assert abs(ad.explicit_advection(wa) - Pu.T @ A0 @ Pu).max() < 1e-12 * abs(A0).max()
+
+
+@pytest.mark.parametrize("walls", [False, True])
+def test_trbdf2_step_on_a_one_level_forest_equals_the_box_oracle(walls):
+    """Every cell at level 1 and no hanging node: the oracle's TR-BDF2 step
+    (two fixed-point solves per stage) on the adaptive forms equals the box
+    oracle's step on the same cells (Morton vs lexicographic order)."""
+    import synthetic
+    from oracle import TRBDF2
+    k, nu, dt = 3, 0.05, 0.02
+    per = (not walls, not walls)
+    f = QuadForest((2, 2), (0.0, 0.0), (1.0, 1.0), per, 2)
+    f = f.adapt(np.ones(f.N))
+    ad = AdaptiveDisc(f, k, nu=nu)
+    box = BoxMesh(2, (4, 4), (0.0, 0.0), (1.0, 1.0), per)
+    disc = Discretization(box, k, nu=nu)
+    perm = np.array([i + 4 * j for (_, i, j) in f.leaves])   # adapted cell -> box cell
+    def to_box(v, nb, ncomp):
+        out = np.empty_like(v)
+        V = v.reshape(f.N, ncomp * nb)
+        out.reshape(box.N, ncomp * nb)[perm] = V
+        return out
+    xu = disc.node_coords("u")
+    if walls:
+        ex = lambda x, t: synthetic.kovasznay(x - 0.5, 40.0)[0]
+        u0 = synthetic.nodal_velocity(ex(xu, 0.0), 2, disc.nbu)
+        uD = ex
+    else:
+        u0 = synthetic.nodal_velocity(synthetic.taylor_green_2d_unit(xu, 0.0, nu)[0], 2, disc.nbu)
+        uD = None
+    p0 = np.sin(2 * np.pi * disc.node_coords("p")[:, 0])
+    # the same fields on the adapted cells
+    ua = u0.reshape(box.N, -1)[perm].reshape(-1)
+    pa = p0.reshape(box.N, -1)[perm].reshape(-1)
+    sb = TRBDF2(disc, dt, uD=uD, nonlinear_iters=2)
+    sa = TRBDF2(ad, dt, uD=uD, nonlinear_iters=2)
+    ub, hb, pb, _ = sb.step(u0, u0, p0, 0.0)
+    uad, ha, pad, _ = sa.step(ua, ua, pa, 0.0)
+    assert np.abs(to_box(uad, disc.nbu, 2) - ub).max() < 1e-11 * np.abs(ub).max()
+    assert np.abs(to_box(pad, disc.nbp, 1) - pb).max() < 1e-10 * np.abs(pb).max()
