@@ -634,6 +634,41 @@ TBDG_API tbdg_status tbdg_amr_solve_momentum(tbdg_amr* amr, double mc, double tn
                                              const double* w, const double* uD, const double* b,
                                              double* x, double tol, int maxiter, int restart,
                                              tbdg_solve_info* info);
+/* The flow of the stage forms below: viscosity nu = 1/Re, time step dt and
+ * artificial sound speed c (alpha_s = 1/(c beta_s dt)^2; INFINITY: none).  */
+TBDG_API tbdg_status tbdg_amr_set_flow(tbdg_amr* amr, double nu, double dt, double c);
+/* m_s M u_prev + F_u^(s) on the adapted mesh (eq. rhs1 and its stage-2
+ * analogue, the TR-BDF2 coefficients of tbdg_rhs_momentum): stage 1 u_prev
+ * = u_n and the explicit advection advected by w_explicit (NULL: w);
+ * stage 2 u_prev = u_g with a32 (u_g, u_g) + a31 (u_n, u_n); the weak
+ * gradient of p_prev; the wall-data terms with the implicit advector w and
+ * uD (at tbdg_amr_face_qpoints; NULL on a fully periodic mesh).  out must
+ * not alias an input.                                                      */
+TBDG_API tbdg_status tbdg_amr_rhs_momentum(tbdg_amr* amr, int stage, const double* u_n,
+                                           const double* u_g, const double* w,
+                                           const double* w_explicit, const double* p_prev,
+                                           const double* uD, double* out);
+/* alpha_s M^p p_prev + (1/(beta_s dt)) D u_ss, D the bracket of F_p.      */
+TBDG_API tbdg_status tbdg_amr_rhs_pressure(tbdg_amr* amr, int stage, const double* u_ss,
+                                           const double* p_prev, double* out);
+/* y = x + a M^{-1} P p (x, y may alias).                                    */
+TBDG_API tbdg_status tbdg_amr_add_grad_p(tbdg_amr* amr, const double* x, double a, const double* p,
+                                         double* y);
+typedef struct {
+    int nonlinear;      /* momentum solves per stage (>= 1): fixed point      */
+    double mom_tol, prs_tol;
+    int mom_maxiter, prs_maxiter, restart;   /* restart <= 0: 30            */
+} tbdg_amr_step_opts;
+/* One TR-BDF2 step on the adapted mesh (the stages of tbdg_step: the
+ * advecting velocity extrapolated from u and u_hist = u^{n-1+gamma}, the
+ * momentum GMRES of tbdg_amr_solve_momentum from the stage's previous
+ * value, the pressure CG of tbdg_amr_solve_pressure from the previous
+ * pressure, time-independent wall data uD).  On success u, u_hist, p hold
+ * u^{n+1}, u^{n+gamma}, p^{n+1}; on failure they are unchanged.  info: the
+ * four solves (stage-1 momentum, pressure, stage-2 momentum, pressure).    */
+TBDG_API tbdg_status tbdg_amr_step(tbdg_amr* amr, const tbdg_amr_step_opts* opts, double* u,
+                                   double* u_hist, double* p, const double* uD,
+                                   tbdg_solve_info info[4]);
 /* d = diag(alpha M^p + K).                                                 */
 TBDG_API tbdg_status tbdg_amr_diag_pressure(tbdg_amr* amr, double alpha, double* d);
 /* Jacobi-preconditioned CG for (alpha M^p + K) x = b from the given x

@@ -234,6 +234,35 @@ void tab1(int n, A::Tab1& t) {
             for (int m = 0; m < n; ++m) t.T[h][q * n + m] = val(m, 0.5 * (h + t.z[q]));
 }
 
+void mixtab(const A::Tab1& tu, const A::Tab1& tp, A::MixTab& x) {
+    std::memset(&x, 0, sizeof x);
+    x.n = tu.n;
+    x.np = tp.n;
+    const int n = tu.n, np = tp.n;
+    auto dval = [&](int m, double z) {
+        double sum = 0.0;
+        for (int r = 0; r < np; ++r) {
+            if (r == m) continue;
+            double term = 1.0 / (tp.z[m] - tp.z[r]);
+            for (int q = 0; q < np; ++q)
+                if (q != m && q != r) term *= (z - tp.z[q]) / (tp.z[m] - tp.z[q]);
+            sum += term;
+        }
+        return sum;
+    };
+    for (int q = 0; q < n; ++q)
+        for (int m = 0; m < np; ++m) {
+            x.I[q * np + m] = trbdg::lagrange_value(tp.z, np, m, tu.z[q]);
+            x.DI[q * np + m] = dval(m, tu.z[q]);
+            for (int h = 0; h < 2; ++h)
+                x.Ih[h][q * np + m] = trbdg::lagrange_value(tp.z, np, m, 0.5 * (h + tu.z[q]));
+        }
+    for (int m = 0; m < np; ++m) {
+        x.Lp[0][m] = trbdg::lagrange_value(tp.z, np, m, 0.0);
+        x.Lp[1][m] = trbdg::lagrange_value(tp.z, np, m, 1.0);
+    }
+}
+
 template <typename T>
 T* devalloc(int64_t count) {
     void* p = nullptr;
@@ -258,6 +287,11 @@ struct tbdg_amr {
     Forest F, next;
     bool planned = false;
     A::Tab1 tp, tu;
+    A::MixTab mx;
+    double nu = 0.0, dt = 0.0, c = 1.0e3;   // tbdg_amr_set_flow
+    bool flow = false;
+    double* sv = nullptr;   // step vectors: velocity x6, pressure x3
+    int64_t sv_cap = 0;
     int *level = nullptr, *meta = nullptr, *nbr = nullptr, *bface = nullptr;
     int64_t n_bfaces = 0;
     double pen_u = 1.0;
@@ -339,6 +373,7 @@ struct tbdg_amr {
         devfree(xsrc);
         devfree(cg);
         devfree(gm);
+        devfree(sv);
         devfree(part);
         devfree(scal);
         if (host) (void)hipHostFree(host);
@@ -376,6 +411,71 @@ double dot(tbdg_amr* m, int64_t n, const double* a, const double* b, int slot) {
     TBDG_HIP(hipMemcpyAsync(m->host, m->scal + slot, sizeof(double), hipMemcpyDeviceToHost, m->stream));
     TBDG_HIP(hipStreamSynchronize(m->stream));
     return m->host[0];
+}
+
+// TR-BDF2 constants (eq. trbdf2, second_stage) and the extrapolation
+// weights of the advecting velocity (stage 1 to its midpoint from the
+// previous step's stage value, stage 2 to t^{n+1}), as on the box mesh
+struct Trbdf2 {
+    double g, a31, a32, a33, e1[2], e2[2];
+    Trbdf2() {
+        g = 2.0 - std::sqrt(2.0);
+        a31 = (1.0 - g) / (2.0 * (2.0 - g));
+        a32 = a31;
+        a33 = 1.0 / (2.0 - g);
+        e1[0] = 1.0 + g / (2.0 * (1.0 - g));
+        e1[1] = -g / (2.0 * (1.0 - g));
+        e2[0] = 1.0 + (1.0 - g) / g;
+        e2[1] = -(1.0 - g) / g;
+    }
+    double beta(int s) const { return s == 1 ? g : 1.0 - g; }
+    double theta(int s) const { return s == 1 ? 0.5 : a33; }
+};
+
+void rhs_momentum_amr(tbdg_amr* m, int s, const double* u_n, const double* u_g, const double* w,
+                      const double* w_ex, const double* p, const double* uD, double* out) {
+    const Trbdf2 T;
+    const A::Geo g = m->geo();
+    const double ms = 1.0 / (T.beta(s) * m->dt);
+    A::ExplicitArgs e{};
+    e.visc = m->nu;
+    e.thd = T.theta(s);
+    e.wd = w;
+    e.uD = m->n_bfaces ? uD : nullptr;
+    e.p = p;
+    e.cg = 1.0;
+    e.acc = false;
+    if (s == 1) {
+        e.mcoef = ms;
+        e.uprev = u_n;
+        e.cl = -T.theta(1) * m->nu;
+        e.ca = T.theta(1);
+        e.ue = u_n;
+        e.we = w_ex ? w_ex : w;
+        A::launch_amr_explicit(m->stream, g, m->tu, m->mx, e, out);
+    } else {
+        e.mcoef = ms;
+        e.uprev = u_g;
+        e.cl = -m->nu * T.a32;
+        e.ca = T.a32;
+        e.ue = u_g;
+        e.we = u_g;
+        A::launch_amr_explicit(m->stream, g, m->tu, m->mx, e, out);
+        A::ExplicitArgs e2{};
+        e2.cl = -m->nu * T.a31;
+        e2.ca = T.a31;
+        e2.ue = u_n;
+        e2.we = u_n;
+        e2.acc = true;
+        A::launch_amr_explicit(m->stream, g, m->tu, m->mx, e2, out);
+    }
+}
+
+void rhs_pressure_amr(tbdg_amr* m, int s, const double* u_ss, const double* p, double* out) {
+    const Trbdf2 T;
+    const double b = T.beta(s) * m->dt;
+    const double alpha = std::isinf(m->c) ? 0.0 : 1.0 / (m->c * m->c * b * b);
+    A::launch_amr_rhs_p(m->stream, m->geo(), m->tu, m->mx, alpha, p, 1.0 / b, u_ss, out);
 }
 
 }  // namespace
@@ -424,6 +524,7 @@ tbdg_status tbdg_amr_create(const tbdg_amr_desc* d, void* hip_stream, tbdg_amr**
         F.finalize();
         tab1(m->k, m->tp);
         tab1(m->k + 1, m->tu);
+        mixtab(m->tu, m->tp, m->mx);
         m->part = devalloc<double>(DOT_BLOCKS);
         m->scal = devalloc<double>(8);
         TBDG_HIP(hipHostMalloc((void**)&m->host, 8 * sizeof(double), hipHostMallocDefault));
@@ -650,6 +751,133 @@ tbdg_status tbdg_amr_solve_momentum(tbdg_amr* m, double mc, double tnu, double t
         if (info) *info = inf;
         if (status != TBDG_OK) m->last_error = "adaptive-mesh momentum GMRES did not converge";
         return status;
+    });
+}
+
+tbdg_status tbdg_amr_set_flow(tbdg_amr* m, double nu, double dt, double c) {
+    if (!m) return TBDG_EINVAL;
+    return aguard(m, [&]() {
+        need(std::isfinite(nu) && nu > 0.0 && std::isfinite(dt) && dt > 0.0, "need nu > 0 and dt > 0");
+        need(c > 0.0, "need c > 0 (infinite: no artificial compressibility term)");
+        m->nu = nu;
+        m->dt = dt;
+        m->c = c;
+        m->flow = true;
+        return TBDG_OK;
+    });
+}
+
+tbdg_status tbdg_amr_rhs_momentum(tbdg_amr* m, int stage, const double* u_n, const double* u_g,
+                                  const double* w, const double* w_explicit, const double* p_prev,
+                                  const double* uD, double* out) {
+    if (!m) return TBDG_EINVAL;
+    return aguard(m, [&]() {
+        need(m->flow, "tbdg_amr_set_flow first");
+        need(stage == 1 || stage == 2, "stage must be 1 or 2");
+        need(m->Nc() == 0 || (u_n && w && p_prev && out && (stage == 1 || u_g)), "null vector");
+        need(m->n_bfaces == 0 || uD, "the mesh has walls: wall data uD needed");
+        need(out != u_n && out != u_g && out != w && out != w_explicit, "out must not alias an input");
+        rhs_momentum_amr(m, stage, u_n, u_g, w, w_explicit, p_prev, uD, out);
+        return TBDG_OK;
+    });
+}
+
+tbdg_status tbdg_amr_rhs_pressure(tbdg_amr* m, int stage, const double* u_ss, const double* p_prev,
+                                  double* out) {
+    if (!m) return TBDG_EINVAL;
+    return aguard(m, [&]() {
+        need(m->flow, "tbdg_amr_set_flow first");
+        need(stage == 1 || stage == 2, "stage must be 1 or 2");
+        need(m->Nc() == 0 || (u_ss && p_prev && out), "null vector");
+        need(out != p_prev, "out must not alias p_prev");
+        rhs_pressure_amr(m, stage, u_ss, p_prev, out);
+        return TBDG_OK;
+    });
+}
+
+tbdg_status tbdg_amr_add_grad_p(tbdg_amr* m, const double* x, double a, const double* p, double* y) {
+    if (!m) return TBDG_EINVAL;
+    return aguard(m, [&]() {
+        need(std::isfinite(a), "a must be finite");
+        need(m->Nc() == 0 || (x && p && y), "null vector");
+        A::launch_amr_grad(m->stream, m->geo(), m->tu, m->mx, x, a, p, y);
+        return TBDG_OK;
+    });
+}
+
+tbdg_status tbdg_amr_step(tbdg_amr* m, const tbdg_amr_step_opts* o, double* u, double* u_hist,
+                          double* p, const double* uD, tbdg_solve_info info[4]) {
+    if (!m || !o) return TBDG_EINVAL;
+    return aguard(m, [&]() {
+        need(m->flow, "tbdg_amr_set_flow first");
+        need(u && u_hist && p, "null vector");
+        need(m->n_bfaces == 0 || uD, "the mesh has walls: wall data uD needed");
+        need(o->nonlinear >= 1 && o->mom_tol > 0.0 && o->prs_tol > 0.0, "bad step options");
+        const int64_t nu_ = m->Nu(), np_ = m->Np();
+        const int64_t cap = 6 * nu_ + 3 * np_;
+        if (cap > m->sv_cap) {
+            devfree(m->sv);
+            m->sv = devalloc<double>(cap);
+            m->sv_cap = cap;
+        }
+        double* w = m->sv;
+        double* rhs = w + nu_;
+        double* us = rhs + nu_;
+        double* uss = us + nu_;
+        double* ug = uss + nu_;
+        double* un = ug + nu_;
+        double* b = un + nu_;
+        double* pg = b + np_;
+        double* pn = pg + np_;
+        const hipStream_t st = m->stream;
+        const Trbdf2 T;
+        const size_t bu = sizeof(double) * nu_, bp = sizeof(double) * np_;
+        tbdg_solve_info loc[4] = {};
+        auto stage = [&](int s, const double* u_n, const double* u_h, const double* u_gs,
+                         const double* p_prev, double* u_out, double* p_out) -> tbdg_status {
+            const double* base = s == 1 ? u_n : u_gs;
+            if (s == 1) trbdg::vec_axpby(st, nu_, T.e1[0], u_n, T.e1[1], u_h, w);
+            else trbdg::vec_axpby(st, nu_, T.e2[0], u_gs, T.e2[1], u_n, w);
+            const double ms = 1.0 / (T.beta(s) * m->dt), th = T.theta(s);
+            const double* w_ex = (o->nonlinear > 1 && s == 1) ? u_n : nullptr;
+            TBDG_HIP(hipMemcpyAsync(us, base, bu, hipMemcpyDeviceToDevice, st));
+            tbdg_solve_info acc{0, 0.0, 0.0, 0, 0}, one{};
+            for (int solves = 1;; ++solves) {
+                rhs_momentum_amr(m, s, u_n, u_gs, w, w_ex, p_prev, uD, rhs);
+                const tbdg_status rc = tbdg_amr_solve_momentum(m, ms, th * m->nu, th, w, uD, rhs, us,
+                                                               o->mom_tol, o->mom_maxiter,
+                                                               o->restart > 0 ? o->restart : 30, &one);
+                if (solves == 1) acc.res0 = one.res0;
+                acc.iters += one.iters;
+                acc.res_final = one.res_final;
+                if (rc != TBDG_OK) {
+                    loc[2 * (s - 1)] = acc;
+                    return rc;
+                }
+                if (solves >= o->nonlinear) break;
+                TBDG_HIP(hipMemcpyAsync(w, us, bu, hipMemcpyDeviceToDevice, st));
+            }
+            loc[2 * (s - 1)] = acc;
+            const double bdt = T.beta(s) * m->dt;
+            A::launch_amr_grad(st, m->geo(), m->tu, m->mx, us, bdt, p_prev, uss);
+            rhs_pressure_amr(m, s, uss, p_prev, b);
+            TBDG_HIP(hipMemcpyAsync(p_out, p_prev, bp, hipMemcpyDeviceToDevice, st));
+            const double alpha = std::isinf(m->c) ? 0.0 : 1.0 / (m->c * m->c * bdt * bdt);
+            const tbdg_status rc = tbdg_amr_solve_pressure(m, alpha, b, p_out, o->prs_tol, o->prs_maxiter,
+                                                           &loc[2 * (s - 1) + 1]);
+            if (rc != TBDG_OK) return rc;
+            A::launch_amr_grad(st, m->geo(), m->tu, m->mx, uss, -bdt, p_out, u_out);
+            return TBDG_OK;
+        };
+        tbdg_status rc = stage(1, u, u_hist, nullptr, p, ug, pg);
+        if (rc == TBDG_OK) rc = stage(2, u, nullptr, ug, pg, un, pn);
+        if (info)
+            for (int q = 0; q < 4; ++q) info[q] = loc[q];
+        if (rc != TBDG_OK) return rc;
+        TBDG_HIP(hipMemcpyAsync(u_hist, ug, bu, hipMemcpyDeviceToDevice, st));
+        TBDG_HIP(hipMemcpyAsync(u, un, bu, hipMemcpyDeviceToDevice, st));
+        TBDG_HIP(hipMemcpyAsync(p, pn, bp, hipMemcpyDeviceToDevice, st));
+        return TBDG_OK;
     });
 }
 

@@ -404,6 +404,408 @@ __global__ __launch_bounds__(256) void k_amr_momentum(Geo g, Tab1 t, double mc, 
     }
 }
 
+// Explicit momentum functional of a stage (eq. rhs1 and its stage-2
+// analogue) on both components, see launch_amr_explicit.  The face phase
+// forms per face node: the exterior normal derivatives (L0), the whole
+// central flux {{u w}}.n seen by the cell's test functions (A0; on coarse
+// sides at the fine faces' points), and the own and exterior pressure
+// traces at the velocity face points (Gw); on walls the interior traces and
+// the wall data.
+template <int N>
+__global__ __launch_bounds__(256) void k_amr_explicit(Geo g, Tab1 t, MixTab x, ExplicitArgs ea,
+                                                      double* __restrict__ y) {
+    constexpr int NB = N * N;
+    constexpr int NP = N - 1;
+    constexpr int NBP = NP * NP;
+    constexpr int CPB = 256 / NB;
+    __shared__ double s_u[2][CPB * NB];
+    __shared__ double s_w[2][CPB * NB];
+    __shared__ double s_pu[CPB * NB];     // pressure at the velocity nodes
+    __shared__ double s_e[CPB * 4 * N * 6];
+    __shared__ double s_y[2][2][CPB * NB];
+    const int tid = threadIdx.x;
+    const int lc = tid / NB, nd = tid % NB;
+    const int cell0 = blockIdx.x * CPB;
+    const int cell = cell0 + lc;
+    const bool active = lc < CPB && cell < g.Nc;
+    if (lc < CPB) {
+#pragma unroll
+        for (int c = 0; c < 2; ++c) {
+            s_u[c][tid] = active ? ea.ue[((size_t)cell * 2 + c) * NB + nd] : 0.0;
+            s_w[c][tid] = active ? ea.we[((size_t)cell * 2 + c) * NB + nd] : 0.0;
+        }
+        double pu = 0.0;
+        if (active && ea.p) {
+            const int ix = nd % N, iy = nd / N;
+            for (int my = 0; my < NP; ++my) {
+                double row = 0.0;
+                for (int mx = 0; mx < NP; ++mx) row += x.I[ix * NP + mx] * ea.p[(size_t)cell * NBP + mx + NP * my];
+                pu += x.I[iy * NP + my] * row;
+            }
+        }
+        s_pu[tid] = pu;
+    }
+    __syncthreads();
+    for (int it = tid; it < CPB * 4 * N; it += 256) {
+        const int c2 = it / (4 * N), f = (it / N) % 4, tt = it % N;
+        const int cl = cell0 + c2;
+        double e[6] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
+        if (cl < g.Nc) {
+            const int meta = g.meta[cl * 4 + f];
+            const int kind = meta & 15, half = meta >> 4;
+            const int a = f >> 1, s = f & 1, so = 1 - s;
+            const double nu = s ? 1.0 : -1.0;
+            const int own = g.level[cl];
+            const int base = c2 * NB;
+            auto own_trace = [&](int m, double& u0, double& u1, double& wa) {
+                u0 = u1 = wa = 0.0;
+#pragma unroll
+                for (int j = 0; j < N; ++j) {
+                    const int q = base + nd2<N>(a, j, m);
+                    u0 += t.L[s][j] * s_u[0][q];
+                    u1 += t.L[s][j] * s_u[1][q];
+                    wa += t.L[s][j] * s_w[a][q];
+                }
+            };
+            // pressure trace of `pc` at face side `side`, tangential weights tw
+            auto p_trace = [&](int pc, int side, const double* tw) {
+                double v = 0.0;
+                for (int mt = 0; mt < NP; ++mt) {
+                    double l = 0.0;
+                    for (int ma = 0; ma < NP; ++ma) {
+                        const int pn = a == 0 ? ma + NP * mt : mt + NP * ma;
+                        l += x.Lp[side][ma] * ea.p[(size_t)pc * NBP + pn];
+                    }
+                    v += tw[mt] * l;
+                }
+                return v;
+            };
+            auto nbr_trace = [&](int nb, int m, double* v, double* d, double& wa) {
+                v[0] = v[1] = d[0] = d[1] = wa = 0.0;
+#pragma unroll
+                for (int j = 0; j < N; ++j) {
+                    const int q = nd2<N>(a, j, m);
+                    const double u0 = ea.ue[((size_t)nb * 2 + 0) * NB + q];
+                    const double u1 = ea.ue[((size_t)nb * 2 + 1) * NB + q];
+                    v[0] += t.L[so][j] * u0;
+                    v[1] += t.L[so][j] * u1;
+                    d[0] += t.dL[so][j] * u0;
+                    d[1] += t.dL[so][j] * u1;
+                    wa += t.L[so][j] * ea.we[((size_t)nb * 2 + a) * NB + q];
+                }
+            };
+            const double pown = ea.p ? p_trace(cl, s, x.I + tt * NP) : 0.0;
+            if (kind == FACE_BOUNDARY) {
+                double u0, u1, wa;
+                own_trace(tt, u0, u1, wa);
+                e[2] = nu * u0 * wa;
+                e[3] = nu * u1 * wa;
+                e[5] = pown;
+                if (ea.uD) {
+                    const size_t pt = (size_t)g.bface[cl * 4 + f] * N + tt;
+                    const double ud0 = ea.uD[pt * 2], ud1 = ea.uD[pt * 2 + 1];
+                    double wd = 0.0;
+#pragma unroll
+                    for (int j = 0; j < N; ++j)
+                        wd += t.L[s][j] * ea.wd[((size_t)cl * 2 + a) * NB + nd2<N>(a, j, tt)];
+                    const double uda = a == 0 ? ud0 : ud1;
+                    const double lam = fmax(fabs(wd), fabs(2.0 * uda - wd));
+                    e[0] = ud0;
+                    e[1] = ud1;
+                    e[4] = ea.thd * (-nu * wd + lam);
+                }
+            } else if (kind == FACE_SAME || kind == FACE_COARSER) {
+                double v[2], d[2], we;
+                double pe = 0.0;
+                const int nb = g.nbr[cl * 8 + f * 2];
+                if (kind == FACE_SAME) {
+                    nbr_trace(nb, tt, v, d, we);
+                    if (ea.p) pe = p_trace(nb, so, x.I + tt * NP);
+                } else {
+                    v[0] = v[1] = d[0] = d[1] = we = 0.0;
+#pragma unroll
+                    for (int m = 0; m < N; ++m) {
+                        double vm[2], dm[2], wm;
+                        nbr_trace(nb, m, vm, dm, wm);
+                        const double T = t.T[half][tt * N + m];
+                        v[0] += T * vm[0];
+                        v[1] += T * vm[1];
+                        d[0] += T * dm[0];
+                        d[1] += T * dm[1];
+                        we += T * wm;
+                    }
+                    if (ea.p) pe = p_trace(nb, so, x.Ih[half] + tt * NP);
+                }
+                const double hn = g.H[a] / (double)(1 << (kind == FACE_SAME ? own : own - 1));
+                double uo[2], wo;
+                own_trace(tt, uo[0], uo[1], wo);
+#pragma unroll
+                for (int c = 0; c < 2; ++c) {
+                    e[c] = d[c] / hn;
+                    e[2 + c] = 0.5 * nu * (uo[c] * wo + v[c] * we);
+                }
+                e[4] = pe;
+                e[5] = pown;
+            } else if (kind == FACE_FINER) {
+                const double hn = g.H[a] / (double)(1 << (own + 1));
+                double tr0[N], tr1[N], trw[N];
+#pragma unroll
+                for (int m = 0; m < N; ++m) own_trace(m, tr0[m], tr1[m], trw[m]);
+                for (int h = 0; h < 2; ++h) {
+                    const int nb = g.nbr[cl * 8 + f * 2 + h];
+#pragma unroll
+                    for (int q = 0; q < N; ++q) {
+                        double v[2], d[2], we;
+                        nbr_trace(nb, q, v, d, we);
+                        double uo0 = 0.0, uo1 = 0.0, wo = 0.0;
+#pragma unroll
+                        for (int m = 0; m < N; ++m) {
+                            const double T = t.T[h][q * N + m];
+                            uo0 += T * tr0[m];
+                            uo1 += T * tr1[m];
+                            wo += T * trw[m];
+                        }
+                        const double wq = 0.5 * t.W[q] * t.T[h][q * N + tt];
+                        e[0] += wq * d[0];
+                        e[1] += wq * d[1];
+                        e[2] += wq * 0.5 * nu * (uo0 * wo + v[0] * we);
+                        e[3] += wq * 0.5 * nu * (uo1 * wo + v[1] * we);
+                        if (ea.p) e[4] += wq * p_trace(nb, so, x.I + q * NP);
+                    }
+                }
+                const double iw = 1.0 / t.W[tt];
+                e[0] *= iw / hn;
+                e[1] *= iw / hn;
+                e[2] *= iw;
+                e[3] *= iw;
+                e[4] *= iw;
+                e[5] = pown;
+            }
+        }
+#pragma unroll
+        for (int q = 0; q < 6; ++q) s_e[it * 6 + q] = e[q];
+    }
+    __syncthreads();
+    for (int it = tid; it < CPB * 4 * N; it += 256) {
+        const int c2 = it / (4 * N), a = (it / (2 * N)) % 2, c = (it / N) % 2, tt = it % N;
+        const int cl = cell0 + c2;
+        if (cl >= g.Nc) continue;
+        const int own = g.level[cl];
+        const double sc = 1.0 / (double)(1 << own);
+        const double h = g.H[a] * sc, ht = g.H[1 - a] * sc;
+        const double Wt = t.W[tt] * ht;
+        const bool gw = ea.p && c == a;
+        double pp[N], wa[N], pu[N];
+#pragma unroll
+        for (int m = 0; m < N; ++m) {
+            const int q = c2 * NB + nd2<N>(a, m, tt);
+            pp[m] = s_u[c][q];
+            wa[m] = s_w[a][q];
+            pu[m] = s_pu[q];
+        }
+        const double sig = g.csig_u / h;
+        double pn[2];
+        int kind[2];
+        const double* ee[2];
+#pragma unroll
+        for (int s = 0; s < 2; ++s) {
+            const double nu = s ? 1.0 : -1.0;
+            pn[s] = 0.0;
+#pragma unroll
+            for (int j = 0; j < N; ++j) pn[s] += t.dL[s][j] * pp[j];
+            pn[s] *= nu / h;
+            kind[s] = g.meta[cl * 4 + 2 * a + s] & 15;
+            ee[s] = s_e + ((c2 * 4 + 2 * a + s) * N + tt) * 6;
+        }
+#pragma unroll
+        for (int i = 0; i < N; ++i) {
+            double rl = 0.0, ra = 0.0, rg = 0.0, rd = 0.0;
+#pragma unroll
+            for (int j = 0; j < N; ++j) {
+                rl += t.S[i * N + j] * pp[j];
+                ra += t.W[j] * t.D[j * N + i] * pp[j] * wa[j];
+                rg += t.W[j] * t.D[j * N + i] * pu[j];
+            }
+            rl *= Wt / h;
+            ra *= Wt;
+            rg *= Wt;
+#pragma unroll
+            for (int s = 0; s < 2; ++s) {
+                const double nu = s ? 1.0 : -1.0;
+                const double Li = t.L[s][i];
+                const double* E = ee[s];
+                if (kind[s] == FACE_BOUNDARY) {
+                    rl += Wt * (-pn[s] * Li);
+                    ra -= Wt * Li * E[2 + c];
+                    rg -= Wt * nu * E[5] * Li;
+                    if (ea.uD) {
+                        const double udc = E[c];
+                        rd += Wt * (ea.thd * ea.visc * (-udc * nu * t.dL[s][i] / h + 2.0 * sig * udc * Li)
+                                    + udc * Li * E[4]);
+                    }
+                } else {
+                    rl += Wt * (-0.5 * (pn[s] + nu * E[c]) * Li);
+                    ra -= Wt * Li * E[2 + c];
+                    rg -= Wt * 0.5 * nu * (E[5] + E[4]) * Li;
+                }
+            }
+            double r = ea.cl * rl + ea.ca * ra + rd;
+            if (gw) r += ea.cg * rg;
+            s_y[c][a][c2 * NB + nd2<N>(a, i, tt)] = r;
+        }
+    }
+    __syncthreads();
+    if (active) {
+        const double sc = 1.0 / (double)(1 << g.level[cell]);
+        const double m = ea.mcoef * t.W[nd % N] * t.W[nd / N] * g.H[0] * g.H[1] * sc * sc;
+#pragma unroll
+        for (int c = 0; c < 2; ++c) {
+            const size_t gi = ((size_t)cell * 2 + c) * NB + nd;
+            double v = s_y[c][0][tid] + s_y[c][1][tid];
+            if (ea.uprev) v += m * ea.uprev[gi];
+            if (ea.acc) v += y[gi];
+            y[gi] = v;
+        }
+    }
+}
+
+// b = alpha M^p p + fcoef D u, D u the bracket of F_p:
+// sum_K int u.grad q - sum_E int {{u}}.[[q]] (walls: -int (u.n) q), taken at
+// the velocity Gauss points; exterior velocity traces per face node as in
+// the momentum kernels (projected onto the tangential velocity basis on
+// coarse sides, which integrates the pressure test functions exactly).
+template <int N>
+__global__ __launch_bounds__(256) void k_amr_rhs_p(Geo g, Tab1 t, MixTab x, double alpha,
+                                                   const double* __restrict__ p, double fcoef,
+                                                   const double* __restrict__ u, double* __restrict__ b) {
+    constexpr int NB = N * N;
+    constexpr int NP = N - 1;
+    constexpr int NBP = NP * NP;
+    constexpr int CPB = 256 / NB;
+    __shared__ double s_u[2][CPB * NB];
+    __shared__ double s_e[CPB * 4 * N * 2];   // own and exterior normal-component traces
+    const int tid = threadIdx.x;
+    const int lc = tid / NB, nd = tid % NB;
+    const int cell0 = blockIdx.x * CPB;
+    const int cell = cell0 + lc;
+    if (lc < CPB) {
+        const bool act = cell < g.Nc;
+#pragma unroll
+        for (int c = 0; c < 2; ++c) s_u[c][tid] = act ? u[((size_t)cell * 2 + c) * NB + nd] : 0.0;
+    }
+    __syncthreads();
+    for (int it = tid; it < CPB * 4 * N; it += 256) {
+        const int c2 = it / (4 * N), f = (it / N) % 4, tt = it % N;
+        const int cl = cell0 + c2;
+        double uo = 0.0, ue = 0.0;
+        if (cl < g.Nc) {
+            const int meta = g.meta[cl * 4 + f];
+            const int kind = meta & 15, half = meta >> 4;
+            const int a = f >> 1, s = f & 1, so = 1 - s;
+#pragma unroll
+            for (int j = 0; j < N; ++j) uo += t.L[s][j] * s_u[a][c2 * NB + nd2<N>(a, j, tt)];
+            auto nbr_trace = [&](int nb, int m) {
+                double v = 0.0;
+#pragma unroll
+                for (int j = 0; j < N; ++j) v += t.L[so][j] * u[((size_t)nb * 2 + a) * NB + nd2<N>(a, j, m)];
+                return v;
+            };
+            if (kind == FACE_SAME) {
+                ue = nbr_trace(g.nbr[cl * 8 + f * 2], tt);
+            } else if (kind == FACE_COARSER) {
+                const int nb = g.nbr[cl * 8 + f * 2];
+#pragma unroll
+                for (int m = 0; m < N; ++m) ue += t.T[half][tt * N + m] * nbr_trace(nb, m);
+            } else if (kind == FACE_FINER) {
+                for (int h = 0; h < 2; ++h) {
+                    const int nb = g.nbr[cl * 8 + f * 2 + h];
+#pragma unroll
+                    for (int q = 0; q < N; ++q) ue += 0.5 * t.W[q] * t.T[h][q * N + tt] * nbr_trace(nb, q);
+                }
+                ue /= t.W[tt];
+            }
+        }
+        s_e[it * 2] = uo;
+        s_e[it * 2 + 1] = ue;
+    }
+    __syncthreads();
+    if (tid < CPB * NBP) {
+        const int c2 = tid / NBP, pnode = tid % NBP;
+        const int cl = cell0 + c2;
+        if (cl < g.Nc) {
+            const int own = g.level[cl];
+            const double sc = 1.0 / (double)(1 << own);
+            const int px = pnode % NP, py = pnode / NP;
+            double r = 0.0;
+#pragma unroll
+            for (int a = 0; a < 2; ++a) {
+                const int ia = a == 0 ? px : py, itp = a == 0 ? py : px;
+                const double ht = g.H[1 - a] * sc;
+                for (int tt = 0; tt < N; ++tt) {
+                    const double wt = t.W[tt] * ht * x.I[tt * NP + itp];
+                    double v = 0.0;
+#pragma unroll
+                    for (int m = 0; m < N; ++m)
+                        v += t.W[m] * x.DI[m * NP + ia] * s_u[a][c2 * NB + nd2<N>(a, m, tt)];
+                    double fsum = 0.0;
+#pragma unroll
+                    for (int s = 0; s < 2; ++s) {
+                        const int f = 2 * a + s;
+                        const double nu = s ? 1.0 : -1.0;
+                        const int kind = g.meta[cl * 4 + f] & 15;
+                        const double* E = s_e + ((c2 * 4 + f) * N + tt) * 2;
+                        const double tr = kind == FACE_BOUNDARY ? E[0] : 0.5 * (E[0] + E[1]);
+                        fsum -= nu * tr * x.Lp[s][ia];
+                    }
+                    r += wt * (v + fsum);
+                }
+            }
+            const double hx = g.H[0] * sc, hy = g.H[1] * sc;
+            // the pressure Gauss weights are those of the np-point rule: rebuild
+            // them from the interpolation identity sum_q W_q l^p_m(z_q) = w^p_m
+            double wpx = 0.0, wpy = 0.0;
+            for (int q = 0; q < N; ++q) {
+                wpx += t.W[q] * x.I[q * NP + px];
+                wpy += t.W[q] * x.I[q * NP + py];
+            }
+            const size_t gi = (size_t)cl * NBP + pnode;
+            b[gi] = alpha * wpx * wpy * hx * hy * p[gi] + fcoef * r;
+        }
+    }
+}
+
+// y = x + a grad p at the velocity nodes (M^{-1} P p with the collocated
+// velocity mass)
+template <int N>
+__global__ __launch_bounds__(256) void k_amr_grad(Geo g, MixTab x, const double* __restrict__ xin,
+                                                  double a, const double* __restrict__ p,
+                                                  double* __restrict__ y) {
+    constexpr int NB = N * N;
+    constexpr int NP = N - 1;
+    constexpr int NBP = NP * NP;
+    const int64_t gid = (int64_t)blockIdx.x * 256 + threadIdx.x;
+    if (gid >= (int64_t)g.Nc * NB) return;
+    const int cell = (int)(gid / NB), nd = (int)(gid % NB);
+    const int ix = nd % N, iy = nd / N;
+    const double sc = 1.0 / (double)(1 << g.level[cell]);
+    double gx = 0.0, gy = 0.0;
+    for (int my = 0; my < NP; ++my) {
+        double rx = 0.0, ry = 0.0;
+        for (int mx = 0; mx < NP; ++mx) {
+            const double pv = p[(size_t)cell * NBP + mx + NP * my];
+            rx += x.DI[ix * NP + mx] * pv;
+            ry += x.I[ix * NP + mx] * pv;
+        }
+        gx += x.I[iy * NP + my] * rx;
+        gy += x.DI[iy * NP + my] * ry;
+    }
+    gx /= g.H[0] * sc;
+    gy /= g.H[1] * sc;
+    const size_t b0 = ((size_t)cell * 2) * NB + nd, b1 = b0 + NB;
+    y[b0] = xin[b0] + a * gx;
+    y[b1] = xin[b1] + a * gy;
+}
+
 // Diagonal of mc M + tnu A (the momentum operator without its advection),
 // in the velocity layout [cell][component][node]: the Jacobi scaling of the
 // momentum GMRES on adapted meshes.
@@ -636,6 +1038,77 @@ void launch_amr_momentum(hipStream_t st, const Geo& g, const Tab1& t, double mc,
         default: throw Error(TBDG_EUNSUPPORTED, "velocity nodes per direction must be 2..8");
     }
 #undef TBDG_AMR_M
+    TBDG_HIP(hipGetLastError());
+}
+
+void launch_amr_explicit(hipStream_t st, const Geo& g, const Tab1& t, const MixTab& x,
+                         const ExplicitArgs& e, double* y) {
+    if (g.Nc == 0) return;
+#define TBDG_AMR_E(NV)                                                                        \
+    case NV: {                                                                                \
+        constexpr int CPB = 256 / (NV * NV);                                                  \
+        hipLaunchKernelGGL((k_amr_explicit<NV>), dim3((g.Nc + CPB - 1) / CPB), dim3(256), 0, st, \
+                           g, t, x, e, y);                                                    \
+        break;                                                                                \
+    }
+    switch (t.n) {
+        TBDG_AMR_E(2)
+        TBDG_AMR_E(3)
+        TBDG_AMR_E(4)
+        TBDG_AMR_E(5)
+        TBDG_AMR_E(6)
+        TBDG_AMR_E(7)
+        TBDG_AMR_E(8)
+        default: throw Error(TBDG_EUNSUPPORTED, "velocity nodes per direction must be 2..8");
+    }
+#undef TBDG_AMR_E
+    TBDG_HIP(hipGetLastError());
+}
+
+void launch_amr_rhs_p(hipStream_t st, const Geo& g, const Tab1& t, const MixTab& x, double alpha,
+                      const double* p, double fcoef, const double* u, double* b) {
+    if (g.Nc == 0) return;
+#define TBDG_AMR_R(NV)                                                                        \
+    case NV: {                                                                                \
+        constexpr int CPB = 256 / (NV * NV);                                                  \
+        hipLaunchKernelGGL((k_amr_rhs_p<NV>), dim3((g.Nc + CPB - 1) / CPB), dim3(256), 0, st, g, \
+                           t, x, alpha, p, fcoef, u, b);                                      \
+        break;                                                                                \
+    }
+    switch (t.n) {
+        TBDG_AMR_R(2)
+        TBDG_AMR_R(3)
+        TBDG_AMR_R(4)
+        TBDG_AMR_R(5)
+        TBDG_AMR_R(6)
+        TBDG_AMR_R(7)
+        TBDG_AMR_R(8)
+        default: throw Error(TBDG_EUNSUPPORTED, "velocity nodes per direction must be 2..8");
+    }
+#undef TBDG_AMR_R
+    TBDG_HIP(hipGetLastError());
+}
+
+void launch_amr_grad(hipStream_t st, const Geo& g, const Tab1& t, const MixTab& x, const double* xin,
+                     double a, const double* p, double* y) {
+    const int64_t total = (int64_t)g.Nc * t.n * t.n;
+    if (total == 0) return;
+#define TBDG_AMR_G(NV)                                                                        \
+    case NV:                                                                                  \
+        hipLaunchKernelGGL((k_amr_grad<NV>), dim3(blocks(total)), dim3(256), 0, st, g, x, xin, a, \
+                           p, y);                                                             \
+        break;
+    switch (t.n) {
+        TBDG_AMR_G(2)
+        TBDG_AMR_G(3)
+        TBDG_AMR_G(4)
+        TBDG_AMR_G(5)
+        TBDG_AMR_G(6)
+        TBDG_AMR_G(7)
+        TBDG_AMR_G(8)
+        default: throw Error(TBDG_EUNSUPPORTED, "velocity nodes per direction must be 2..8");
+    }
+#undef TBDG_AMR_G
     TBDG_HIP(hipGetLastError());
 }
 

@@ -26,6 +26,15 @@ struct Tab1 {
     double T[2][MAXN * MAXN];     // T[h][q n + m] = l_m((h + z_q) / 2)
 };
 
+// Pressure basis (np = n - 1 nodes) at the velocity Gauss points.
+struct MixTab {
+    int n, np;
+    double I[MAXN * MAXN];        // I[q np + m] = l^p_m(z_q)
+    double DI[MAXN * MAXN];       // DI[q np + m] = (l^p_m)'(z_q)
+    double Ih[2][MAXN * MAXN];    // Ih[h][q np + m] = l^p_m((h + z_q) / 2)
+    double Lp[2][MAXN];           // l^p_m(0), l^p_m(1)
+};
+
 // Cells in the order of the forest; face f = 2 a + s (direction a, side s).
 struct Geo {
     const int* level;     // [Nc]
@@ -53,6 +62,24 @@ void launch_amr_pressure(hipStream_t st, const Geo& g, const Tab1& t, double alp
 // velocity Gauss points of the boundary faces (face number bface, n points)
 void launch_amr_momentum(hipStream_t st, const Geo& g, const Tab1& t, double mc, double tnu, double th,
                          const double* w, const double* u, const double* uD, double* y);
+// Momentum right-hand side pieces, both components:
+//   y_c (+)= mcoef M uprev_c + cl L0 ue_c + ca A0_we(ue)_c + cg (Gw p)_c
+//            + wall-data terms (thd, visc, wd, uD) of the stage functional
+// L0, A0 the explicit diffusion and advection of eq. rhs1 over the whole
+// skeleton, Gw the weak gradient; p, uD, wd may be null when unused.
+struct ExplicitArgs {
+    double mcoef, cl, ca, cg, thd, visc;
+    const double *uprev, *ue, *we, *p, *wd, *uD;
+    bool acc;
+};
+void launch_amr_explicit(hipStream_t st, const Geo& g, const Tab1& t, const MixTab& x,
+                         const ExplicitArgs& e, double* y);
+// b = alpha M^p p + fcoef D u (the Helmholtz right-hand side of a stage)
+void launch_amr_rhs_p(hipStream_t st, const Geo& g, const Tab1& t, const MixTab& x, double alpha,
+                      const double* p, double fcoef, const double* u, double* b);
+// y = x + a M^{-1} P p (the nodal gradient of p at the velocity nodes)
+void launch_amr_grad(hipStream_t st, const Geo& g, const Tab1& t, const MixTab& x, const double* xin,
+                     double a, const double* p, double* y);
 // diag(mc M + tnu A) in the velocity layout (both components)
 void launch_amr_momentum_diag(hipStream_t st, const Geo& g, const Tab1& t, double mc, double tnu,
                               double* d);

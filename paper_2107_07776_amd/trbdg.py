@@ -41,7 +41,8 @@ EXPORTED = [
     "tbdg_amr_sizes", "tbdg_amr_leaves", "tbdg_amr_apply_pressure", "tbdg_amr_diag_pressure",
     "tbdg_amr_solve_pressure", "tbdg_amr_indicator", "tbdg_amr_mark", "tbdg_amr_plan",
     "tbdg_amr_transfer", "tbdg_amr_commit", "tbdg_amr_face_qpoints", "tbdg_amr_apply_momentum",
-    "tbdg_amr_solve_momentum",
+    "tbdg_amr_solve_momentum", "tbdg_amr_set_flow", "tbdg_amr_rhs_momentum", "tbdg_amr_rhs_pressure",
+    "tbdg_amr_add_grad_p", "tbdg_amr_step",
 ]
 
 GUESS = {"given": 0, "previous": 1, "learned": 2, "extrap2": 3, "extrap3": 4}
@@ -62,6 +63,11 @@ class AmrDesc(ctypes.Structure):
     _fields_ = [("n_cells", ctypes.c_int * 2), ("lo", ctypes.c_double * 2),
                 ("hi", ctypes.c_double * 2), ("periodic", ctypes.c_int * 2), ("k", ctypes.c_int),
                 ("max_level", ctypes.c_int), ("pen_p", ctypes.c_double), ("pen_u", ctypes.c_double)]
+
+
+class AmrStepOpts(ctypes.Structure):
+    _fields_ = [("nonlinear", ctypes.c_int), ("mom_tol", ctypes.c_double), ("prs_tol", ctypes.c_double),
+                ("mom_maxiter", ctypes.c_int), ("prs_maxiter", ctypes.c_int), ("restart", ctypes.c_int)]
 
 
 class TrbdgError(RuntimeError):
@@ -196,6 +202,11 @@ def load_library(path=LIB_PATH):
         "tbdg_amr_face_qpoints": ([vp, P(i64), vp], i),
         "tbdg_amr_apply_momentum": ([vp, d, d, d, vp, vp, vp, vp], i),
         "tbdg_amr_solve_momentum": ([vp, d, d, d, vp, vp, vp, vp, d, i, i, P(SolveInfo)], i),
+        "tbdg_amr_set_flow": ([vp, d, d, d], i),
+        "tbdg_amr_rhs_momentum": ([vp, i, vp, vp, vp, vp, vp, vp, vp], i),
+        "tbdg_amr_rhs_pressure": ([vp, i, vp, vp, vp], i),
+        "tbdg_amr_add_grad_p": ([vp, vp, d, vp, vp], i),
+        "tbdg_amr_step": ([vp, P(AmrStepOpts), vp, vp, vp, vp, P(SolveInfo)], i),
     }
     for name, (args, res) in sig.items():
         fn = getattr(lib, name)
@@ -754,6 +765,44 @@ class Adaptive:
         if check:
             self._check(st)
         return info.as_dict() | {"status": st}
+
+    def set_flow(self, nu, dt, c=1.0e3):
+        self._check(self.lib.tbdg_amr_set_flow(self.h, float(nu), float(dt), float(c)))
+
+    def rhs_momentum(self, stage, u_n, u_g, w, p_prev, uD=None, w_explicit=None):
+        out = torch.empty(self.N_u, dtype=torch.float64, device=self.device)
+        self._check(self.lib.tbdg_amr_rhs_momentum(
+            self.h, int(stage), _ptr(self._vec(u_n, self.N_u, "u_n")),
+            _ptr(self._vec(u_g, self.N_u, "u_g") if u_g is not None else None),
+            _ptr(self._vec(w, self.N_u, "w")),
+            _ptr(self._vec(w_explicit, self.N_u, "w_explicit") if w_explicit is not None else None),
+            _ptr(self._vec(p_prev, self.N_p, "p_prev")), _ptr(uD), _ptr(out)))
+        return out
+
+    def rhs_pressure(self, stage, u_ss, p_prev):
+        out = torch.empty(self.N_p, dtype=torch.float64, device=self.device)
+        self._check(self.lib.tbdg_amr_rhs_pressure(self.h, int(stage), _ptr(self._vec(u_ss, self.N_u, "u_ss")),
+                                                   _ptr(self._vec(p_prev, self.N_p, "p_prev")), _ptr(out)))
+        return out
+
+    def add_grad_p(self, x, a, p, out=None):
+        y = out if out is not None else torch.empty(self.N_u, dtype=torch.float64, device=self.device)
+        self._check(self.lib.tbdg_amr_add_grad_p(self.h, _ptr(self._vec(x, self.N_u, "x")), float(a),
+                                                 _ptr(self._vec(p, self.N_p, "p")),
+                                                 _ptr(self._vec(y, self.N_u, "out"))))
+        return y
+
+    def step(self, u, u_hist, p, uD=None, nonlinear=1, mom_tol=1e-10, prs_tol=1e-10, mom_maxiter=5000,
+             prs_maxiter=20000, restart=30, check=True):
+        o = AmrStepOpts(int(nonlinear), float(mom_tol), float(prs_tol), int(mom_maxiter), int(prs_maxiter),
+                        int(restart))
+        info = (SolveInfo * 4)()
+        st = self.lib.tbdg_amr_step(self.h, ctypes.byref(o), _ptr(self._vec(u, self.N_u, "u")),
+                                    _ptr(self._vec(u_hist, self.N_u, "u_hist")),
+                                    _ptr(self._vec(p, self.N_p, "p")), _ptr(uD), info)
+        if check:
+            self._check(st)
+        return [info[q].as_dict() for q in range(4)], st
 
     def diag_pressure(self, alpha):
         y = torch.empty(self.N_p, dtype=torch.float64, device=self.device)

@@ -265,3 +265,78 @@ def test_momentum_gmres_reaches_tolerance_and_direct_solution(seed, nc, per, k):
             assert np.abs(xc - xd).max() <= 1e-9 * np.abs(xd).max()
     finally:
         g.close()
+
+
+# ---------------------------------------------------------------------------
+# stage functionals and the TR-BDF2 step on adapted meshes
+# ---------------------------------------------------------------------------
+STEP_CASES = [(8, (3, 2), (0, 0), 2), (9, (4, 3), (1, 0), 3), (10, (3, 3), (1, 1), 3)]
+
+
+def _kov(x, t=0.0):
+    return synthetic.kovasznay(x - 0.5, 40.0)[0]
+
+
+@pytest.mark.parametrize("seed,nc,per,k", STEP_CASES)
+def test_stage_functionals_match_oracle(seed, nc, per, k):
+    from oracle import TRBDF2
+    g, f = _pair(seed, nc, per, k, lo=(0.0, 0.0), hi=(1.5, 1.0))
+    try:
+        nu, dt = 0.02, 0.01
+        g.set_flow(nu, dt)
+        ad = AdaptiveDisc(f, k, nu=nu)
+        ora = TRBDF2(ad, dt, uD=_kov)
+        xb = g.face_qpoints().cpu().numpy()
+        uD = _t(_kov(xb)) if len(xb) else None
+        rv = lambda n, sd: synthetic.random_vector(n, sd)
+        u_n, u_g, w, wex = (rv(ad.N_u, 900 + seed + 10 * q) for q in range(4))
+        p = rv(ad.N_p, 950 + seed)
+        for s in (1, 2):
+            for we in (None, wex):
+                if s == 2 and we is not None:
+                    continue
+                y = g.rhs_momentum(s, _t(u_n), _t(u_g), _t(w), _t(p), uD,
+                                   _t(we) if we is not None else None).cpu().numpy()
+                ref = ora.rhs_momentum(s, u_n, u_g, w, p, 0.0, w_explicit=we)
+                assert np.abs(y - ref).max() <= 1e-12 * np.abs(ref).max(), (s, we is None)
+            b = g.rhs_pressure(s, _t(u_n), _t(p)).cpu().numpy()
+            ref = ora.rhs_pressure(s, u_n, p)
+            assert np.abs(b - ref).max() <= 1e-12 * np.abs(ref).max(), s
+        y = g.add_grad_p(_t(u_g), -0.3, _t(p)).cpu().numpy()
+        ref = u_g - 0.3 * ora.grad_p(p)
+        assert np.abs(y - ref).max() <= 1e-12 * np.abs(ref).max()
+    finally:
+        g.close()
+
+
+@pytest.mark.parametrize("seed,nc,per,k", STEP_CASES)
+@pytest.mark.parametrize("nonlinear", [1, 2])
+def test_trbdf2_steps_match_oracle(seed, nc, per, k, nonlinear):
+    """Three steps of a Kovasznay field (walls where not periodic) on a mesh
+    with hanging nodes, tight solves, against the oracle's sparse-LU steps."""
+    from oracle import TRBDF2
+    g, f = _pair(seed, nc, per, k, lo=(0.0, 0.0), hi=(1.5, 1.0))
+    try:
+        nu, dt = 0.025, 0.01
+        g.set_flow(nu, dt)
+        ad = AdaptiveDisc(f, k, nu=nu)
+        ora = TRBDF2(ad, dt, uD=_kov, nonlinear_iters=nonlinear)
+        xb = g.face_qpoints().cpu().numpy()
+        uD = _t(_kov(xb)) if len(xb) else None
+        xu = ad.node_coords("u")
+        u = synthetic.nodal_velocity(_kov(xu), 2, ad.nbu)
+        p = np.cos(xu[::ad.nbu, 0].repeat(ad.nbp))   # a cellwise-constant start
+        U, H, P = _t(u), _t(u), _t(p)
+        uo, ho, po = u.copy(), u.copy(), p.copy()
+        t = 0.0
+        for n in range(3):
+            info, st = g.step(U, H, P, uD, nonlinear=nonlinear, mom_tol=1e-13, prs_tol=1e-13)
+            assert st == 0, info
+            uo, ho, po, _ = ora.step(uo, ho, po, t)
+            t += dt
+        du = np.linalg.norm(U.cpu().numpy() - uo) / np.linalg.norm(uo)
+        dp = np.linalg.norm(P.cpu().numpy() - po) / np.linalg.norm(po)
+        print(f"adaptive step: u {du:.2e}, p {dp:.2e}")
+        assert du < 1e-9 and dp < 1e-8
+    finally:
+        g.close()
