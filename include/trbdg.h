@@ -665,10 +665,12 @@ typedef struct {
  * value, the pressure CG of tbdg_amr_solve_pressure from the previous
  * pressure, time-independent wall data uD).  On success u, u_hist, p hold
  * u^{n+1}, u^{n+gamma}, p^{n+1}; on failure they are unchanged.  info: the
- * four solves (stage-1 momentum, pressure, stage-2 momentum, pressure).    */
+ * four solves (stage-1 momentum, pressure, stage-2 momentum, pressure);
+ * max_du (host, may be NULL): max over all velocity DoFs of
+ * |u^{n+1} - u^n|, the quantity of the early remeshing check of Sec. 4.    */
 TBDG_API tbdg_status tbdg_amr_step(tbdg_amr* amr, const tbdg_amr_step_opts* opts, double* u,
                                    double* u_hist, double* p, const double* uD,
-                                   tbdg_solve_info info[4]);
+                                   tbdg_solve_info info[4], double* max_du);
 /* d = diag(alpha M^p + K).                                                 */
 TBDG_API tbdg_status tbdg_amr_diag_pressure(tbdg_amr* amr, double alpha, double* d);
 /* Jacobi-preconditioned CG for (alpha M^p + K) x = b from the given x

@@ -806,7 +806,7 @@ tbdg_status tbdg_amr_add_grad_p(tbdg_amr* m, const double* x, double a, const do
 }
 
 tbdg_status tbdg_amr_step(tbdg_amr* m, const tbdg_amr_step_opts* o, double* u, double* u_hist,
-                          double* p, const double* uD, tbdg_solve_info info[4]) {
+                          double* p, const double* uD, tbdg_solve_info info[4], double* max_du) {
     if (!m || !o) return TBDG_EINVAL;
     return aguard(m, [&]() {
         need(m->flow, "tbdg_amr_set_flow first");
@@ -874,6 +874,12 @@ tbdg_status tbdg_amr_step(tbdg_amr* m, const tbdg_amr_step_opts* o, double* u, d
         if (info)
             for (int q = 0; q < 4; ++q) info[q] = loc[q];
         if (rc != TBDG_OK) return rc;
+        if (max_du) {
+            A::launch_amr_maxdiff(st, nu_, un, u, m->part, DOT_BLOCKS, m->scal + 5);
+            TBDG_HIP(hipMemcpyAsync(m->host, m->scal + 5, sizeof(double), hipMemcpyDeviceToHost, st));
+            TBDG_HIP(hipStreamSynchronize(st));
+            *max_du = m->host[0];
+        }
         TBDG_HIP(hipMemcpyAsync(u_hist, ug, bu, hipMemcpyDeviceToDevice, st));
         TBDG_HIP(hipMemcpyAsync(u, un, bu, hipMemcpyDeviceToDevice, st));
         TBDG_HIP(hipMemcpyAsync(p, pn, bp, hipMemcpyDeviceToDevice, st));

@@ -986,6 +986,34 @@ __global__ __launch_bounds__(256) void k_amr_div(int64_t n, const double* r, con
     z[i] = r[i] / d[i];
 }
 
+__global__ __launch_bounds__(256) void k_amr_maxdiff(int64_t n, const double* __restrict__ a,
+                                                     const double* __restrict__ b, double* part) {
+    double m = 0.0;
+    for (int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x; i < n; i += (int64_t)gridDim.x * 256)
+        m = fmax(m, fabs(a[i] - b[i]));
+    __shared__ double s_m[256];
+    s_m[threadIdx.x] = m;
+    __syncthreads();
+    for (int w = 128; w > 0; w >>= 1) {
+        if ((int)threadIdx.x < w) s_m[threadIdx.x] = fmax(s_m[threadIdx.x], s_m[threadIdx.x + w]);
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) part[blockIdx.x] = s_m[0];
+}
+
+__global__ __launch_bounds__(256) void k_amr_max_finish(const double* part, int G, double* out) {
+    __shared__ double s_m[256];
+    double m = 0.0;
+    for (int i = threadIdx.x; i < G; i += 256) m = fmax(m, part[i]);
+    s_m[threadIdx.x] = m;
+    __syncthreads();
+    for (int w = 128; w > 0; w >>= 1) {
+        if ((int)threadIdx.x < w) s_m[threadIdx.x] = fmax(s_m[threadIdx.x], s_m[threadIdx.x + w]);
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) *out = s_m[0];
+}
+
 inline int blocks(int64_t n) { return (int)((n + 255) / 256); }
 
 }  // namespace
@@ -1186,6 +1214,13 @@ void launch_amr_dot(hipStream_t st, int64_t n, const double* a, const double* b,
                     double* out) {
     hipLaunchKernelGGL(k_amr_dot, dim3(G), dim3(256), 0, st, n, a, b, part);
     hipLaunchKernelGGL(k_amr_dot_finish, dim3(1), dim3(256), 0, st, part, G, out);
+    TBDG_HIP(hipGetLastError());
+}
+
+void launch_amr_maxdiff(hipStream_t st, int64_t n, const double* a, const double* b, double* part, int G,
+                       double* out) {
+    hipLaunchKernelGGL(k_amr_maxdiff, dim3(G), dim3(256), 0, st, n, a, b, part);
+    hipLaunchKernelGGL(k_amr_max_finish, dim3(1), dim3(256), 0, st, part, G, out);
     TBDG_HIP(hipGetLastError());
 }
 

@@ -89,6 +89,9 @@ void launch_amr_transfer(hipStream_t st, const XferMap& m, const Tab1& t, int nc
 // partial sums of a.b over G blocks into part, then the sum into *out
 void launch_amr_dot(hipStream_t st, int64_t n, const double* a, const double* b, double* part, int G,
                     double* out);
+// max |a - b| over G block partials in part, then into *out
+void launch_amr_maxdiff(hipStream_t st, int64_t n, const double* a, const double* b, double* part, int G,
+                       double* out);
 // Jacobi PCG glue on device scalars: x += al p, r -= al q, z = r / d with
 // al = *rz / *pq; then p = z + (*rz_new / *rz_old) p
 void launch_amr_cg_update(hipStream_t st, int64_t n, const double* rz, const double* pq,

@@ -206,7 +206,7 @@ def load_library(path=LIB_PATH):
         "tbdg_amr_rhs_momentum": ([vp, i, vp, vp, vp, vp, vp, vp, vp], i),
         "tbdg_amr_rhs_pressure": ([vp, i, vp, vp, vp], i),
         "tbdg_amr_add_grad_p": ([vp, vp, d, vp, vp], i),
-        "tbdg_amr_step": ([vp, P(AmrStepOpts), vp, vp, vp, vp, P(SolveInfo)], i),
+        "tbdg_amr_step": ([vp, P(AmrStepOpts), vp, vp, vp, vp, P(SolveInfo), P(d)], i),
     }
     for name, (args, res) in sig.items():
         fn = getattr(lib, name)
@@ -797,12 +797,41 @@ class Adaptive:
         o = AmrStepOpts(int(nonlinear), float(mom_tol), float(prs_tol), int(mom_maxiter), int(prs_maxiter),
                         int(restart))
         info = (SolveInfo * 4)()
+        mdu = ctypes.c_double(0.0)
         st = self.lib.tbdg_amr_step(self.h, ctypes.byref(o), _ptr(self._vec(u, self.N_u, "u")),
                                     _ptr(self._vec(u_hist, self.N_u, "u_hist")),
-                                    _ptr(self._vec(p, self.N_p, "p")), _ptr(uD), info)
+                                    _ptr(self._vec(p, self.N_p, "p")), _ptr(uD), info, ctypes.byref(mdu))
         if check:
             self._check(st)
+        self.last_max_du = mdu.value
         return [info[q].as_dict() for q in range(4)], st
+
+    def simulate(self, u, u_hist, p, wall_data, steps, remesh_every=1000, check_every=50,
+                 check_tol=1e-2, refine_frac=0.1, coarsen_frac=0.3, h_min=0.0, h_max=float("inf"),
+                 **step_kw):
+        """The adaptive schedule of Sec. 4: TR-BDF2 steps; after every
+        ``remesh_every`` steps, and after every ``check_every`` steps while the
+        last step changed the velocity by more than ``check_tol`` (max norm),
+        the indicator marks ``refine_frac`` / ``coarsen_frac`` of the cells and
+        the mesh is adapted with u, u_hist and p transferred.  ``wall_data(x)``
+        returns the wall velocity at the (n, 2) host points (None on a fully
+        periodic mesh).  Returns the fields and a log of (step, cells)."""
+        def walls():
+            x = self.face_qpoints()
+            if x.shape[0] == 0 or wall_data is None:
+                return None
+            return torch.tensor(np.asarray(wall_data(x.cpu().numpy()), dtype=np.float64),
+                                device=self.device).contiguous()
+        uD = walls()
+        log = [(0, self.N_c)]
+        for n in range(1, steps + 1):
+            self.step(u, u_hist, p, uD, **step_kw)
+            if n % remesh_every == 0 or (n % check_every == 0 and self.last_max_du > check_tol):
+                flags = self.mark(self.indicator(u), refine_frac, coarsen_frac, h_min, h_max)
+                u, u_hist, p = self.adapt(flags, [("u", u), ("u", u_hist), ("p", p)])
+                uD = walls()
+                log.append((n, self.N_c))
+        return u, u_hist, p, log
 
     def diag_pressure(self, alpha):
         y = torch.empty(self.N_p, dtype=torch.float64, device=self.device)

@@ -277,6 +277,10 @@ def _kov(x, t=0.0):
     return synthetic.kovasznay(x - 0.5, 40.0)[0]
 
 
+def _kov_shifted(x, t=0.0):
+    return synthetic.kovasznay(x - np.array([0.5, 0.13]), 40.0)[0]
+
+
 @pytest.mark.parametrize("seed,nc,per,k", STEP_CASES)
 def test_stage_functionals_match_oracle(seed, nc, per, k):
     from oracle import TRBDF2
@@ -338,5 +342,50 @@ def test_trbdf2_steps_match_oracle(seed, nc, per, k, nonlinear):
         dp = np.linalg.norm(P.cpu().numpy() - po) / np.linalg.norm(po)
         print(f"adaptive step: u {du:.2e}, p {dp:.2e}")
         assert du < 1e-9 and dp < 1e-8
+    finally:
+        g.close()
+
+
+@pytest.mark.parametrize("check_tol", [0.0, 1e9])
+def test_adaptive_schedule_matches_oracle(check_tol):
+    """The schedule of Sec. 4 on a walled Kovasznay field: six steps,
+    remeshing after step 4 and, while the last step changed the velocity by
+    more than check_tol, after every second step (check_tol 0: steps 2, 4,
+    6; 1e9: step 4 only); the oracle repeats it with its own indicator,
+    marking, forest and transfer.  The field is shifted off the mesh's
+    mirror line y = 1/2 (the Kovasznay flow is even in y there), so that no
+    two cells tie in the indicator and both sides mark the same cells."""
+    from oracle import TRBDF2
+    from paper_2107_07776_amd import Adaptive
+    k, nu, dt = 2, 0.025, 0.01
+    lo, hi = (0.0, 0.0), (1.5, 1.0)
+    g = Adaptive((3, 2), lo, hi, k, 3)
+    f = QuadForest((3, 2), lo, hi, (0, 0), 3)
+    try:
+        g.set_flow(nu, dt)
+        ad = AdaptiveDisc(f, k, nu=nu)
+        xu = ad.node_coords("u")
+        u = synthetic.nodal_velocity(_kov_shifted(xu), 2, ad.nbu)
+        p = np.zeros(ad.N_p)
+        U, H, P = _t(u), _t(u), _t(p)
+        U, H, P, log = g.simulate(U, H, P, _kov_shifted, 6, remesh_every=4, check_every=2, check_tol=check_tol,
+                                  refine_frac=0.2, coarsen_frac=0.2, mom_tol=1e-13, prs_tol=1e-13)
+        want = [2, 4, 6] if check_tol == 0.0 else [4]
+        assert [s for s, _ in log[1:]] == want
+        uh = u.copy()
+        t = 0.0
+        for n in range(1, 7):
+            ad = AdaptiveDisc(f, k, nu=nu)
+            u, uh, p, _ = TRBDF2(ad, dt, uD=_kov_shifted).step(u, uh, p, t)
+            t += dt
+            if n in want:
+                fl = mark(ad.indicator(u), f, 0.2, 0.2)
+                f2 = f.adapt(fl)
+                u, uh = transfer(f, f2, u, k + 1, 2), transfer(f, f2, uh, k + 1, 2)
+                p = transfer(f, f2, p, k, 1)
+                f = f2
+        assert [tuple(r) for r in g.leaves().tolist()] == f.leaves
+        assert np.linalg.norm(U.cpu().numpy() - u) <= 1e-9 * np.linalg.norm(u)
+        assert np.linalg.norm(P.cpu().numpy() - p) <= 1e-8 * np.linalg.norm(p)
     finally:
         g.close()
