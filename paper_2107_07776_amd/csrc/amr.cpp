@@ -303,6 +303,8 @@ struct tbdg_amr {
     double* gm = nullptr;   // momentum GMRES: basis, z, diagonal
     int64_t gm_cap = 0;
     double* part = nullptr;
+    double* ppart = nullptr;     // block partials of the operator kernel
+    int64_t ppart_cap = 0;
     double* scal = nullptr;      // device scalars: rz[2], pq, rr, bb
     double* host = nullptr;      // pinned
     std::string last_error;
@@ -375,6 +377,7 @@ struct tbdg_amr {
         devfree(gm);
         devfree(sv);
         devfree(part);
+        devfree(ppart);
         devfree(scal);
         if (host) (void)hipHostFree(host);
         host = nullptr;
@@ -931,6 +934,18 @@ tbdg_status tbdg_amr_solve_pressure(tbdg_amr* m, double alpha, const double* b, 
         A::launch_amr_div(st, n, r, d, z);
         TBDG_HIP(hipMemcpyAsync(p, z, sizeof(double) * n, hipMemcpyDeviceToDevice, st));
         A::launch_amr_dot(st, n, r, z, m->part, DOT_BLOCKS, rz[0]);
+        // per iteration: the operator with its p.q block sums, one fused
+        // update with the r.z and r.r block sums, the direction; all scalars
+        // stay on the device and the host reads p.q and r.r every kCheck
+        // iterations
+        constexpr int kCheck = 8;
+        const int Gp = A::amr_pressure_blocks(g, m->tp);
+        if (Gp > m->ppart_cap) {
+            devfree(m->ppart);
+            m->ppart = devalloc<double>(Gp);
+            m->ppart_cap = Gp;
+        }
+        double* rr = m->scal + 3;
         tbdg_status status = TBDG_ENOTCONV;
         int it = 0, cur = 0;
         for (;;) {
@@ -943,18 +958,23 @@ tbdg_status tbdg_amr_solve_pressure(tbdg_amr* m, double alpha, const double* b, 
                 break;
             }
             if (it >= maxiter) break;
-            ++it;
-            A::launch_amr_pressure(st, g, m->tp, alpha, p, q, false);
-            const double pqv = dot(m, n, p, q, 2);
+            const int stop = std::min(maxiter, it + kCheck);
+            for (; it < stop; ++it) {
+                A::launch_amr_pressure(st, g, m->tp, alpha, p, q, false, m->ppart);
+                A::launch_amr_finish(st, m->ppart, Gp, 1, pq, nullptr);
+                A::launch_amr_cg_step(st, n, rz[cur], pq, p, q, d, x, r, z, m->part, DOT_BLOCKS / 2);
+                A::launch_amr_finish(st, m->part, DOT_BLOCKS / 2, 2, rz[1 - cur], rr);
+                A::launch_amr_cg_dir(st, n, rz[1 - cur], rz[cur], z, p);
+                cur = 1 - cur;
+            }
+            TBDG_HIP(hipMemcpyAsync(m->host, pq, 2 * sizeof(double), hipMemcpyDeviceToHost, st));
+            TBDG_HIP(hipStreamSynchronize(st));
+            const double pqv = m->host[0];
             if (!(pqv > 0.0)) {
                 status = std::isfinite(pqv) ? TBDG_EBREAKDOWN : TBDG_ENAN;
                 break;
             }
-            A::launch_amr_cg_update(st, n, rz[cur], pq, p, q, d, x, r, z);
-            A::launch_amr_dot(st, n, r, z, m->part, DOT_BLOCKS, rz[1 - cur]);
-            res = std::sqrt(dot(m, n, r, r, 3)) / bnorm;
-            A::launch_amr_cg_dir(st, n, rz[1 - cur], rz[cur], z, p);
-            cur = 1 - cur;
+            res = std::sqrt(m->host[1]) / bnorm;
         }
         inf.iters = it;
         inf.res_final = res;

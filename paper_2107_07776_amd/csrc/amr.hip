@@ -52,7 +52,7 @@ __device__ inline void trace(const double* __restrict__ p, const Tab1& t, int ce
 template <int NP, bool DIAG>
 __global__ __launch_bounds__(256) void k_amr_pressure(Geo g, Tab1 t, double alpha,
                                                       const double* __restrict__ p,
-                                                      double* __restrict__ y) {
+                                                      double* __restrict__ y, double* part) {
     constexpr int NB = NP * NP;
     constexpr int CPB = 256 / NB;
     __shared__ double s_p[CPB * NB];
@@ -169,11 +169,19 @@ __global__ __launch_bounds__(256) void k_amr_pressure(Geo g, Tab1 t, double alph
         }
     }
     __syncthreads();
+    double py = 0.0;
     if (active) {
         const double sc = 1.0 / (double)(1 << g.level[cell]);
         const double m = alpha * t.W[nd % NP] * t.W[nd / NP] * g.H[0] * g.H[1] * sc * sc;
         const double own = DIAG ? 1.0 : s_p[tid];
-        y[(size_t)cell * NB + nd] = m * own + s_y[0][tid] + s_y[1][tid];
+        const double v = m * own + s_y[0][tid] + s_y[1][tid];
+        y[(size_t)cell * NB + nd] = v;
+        py = own * v;
+    }
+    // optional per-block partial sum of p . y (the CG step length)
+    if (!DIAG && part) {
+        py = red::block_sum(py);
+        if (threadIdx.x == 0) part[blockIdx.x] = py;
     }
 }
 
@@ -953,20 +961,47 @@ __global__ __launch_bounds__(256) void k_amr_dot_finish(const double* part, int 
     if (threadIdx.x == 0) *out = s;
 }
 
-__global__ __launch_bounds__(256) void k_amr_cg_update(int64_t n, const double* rz,
-                                                       const double* pq,
-                                                       const double* __restrict__ p,
-                                                       const double* __restrict__ q,
-                                                       const double* __restrict__ d,
-                                                       double* __restrict__ x, double* __restrict__ r,
-                                                       double* __restrict__ z) {
-    const int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
-    if (i >= n) return;
+// x += al p, r -= al q, z = r / d, al = *rz / *pq; per-block partial sums
+// of r.z and r.r (grid-stride over a fixed grid)
+__global__ __launch_bounds__(256) void k_amr_cg_step(int64_t n, const double* rz, const double* pq,
+                                                     const double* __restrict__ p,
+                                                     const double* __restrict__ q,
+                                                     const double* __restrict__ d,
+                                                     double* __restrict__ x, double* __restrict__ r,
+                                                     double* __restrict__ z, double* part) {
     const double al = *rz / *pq;
-    x[i] += al * p[i];
-    const double ri = r[i] - al * q[i];
-    r[i] = ri;
-    z[i] = ri / d[i];
+    double a = 0.0, b = 0.0;
+    for (int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x; i < n; i += (int64_t)gridDim.x * 256) {
+        x[i] += al * p[i];
+        const double ri = r[i] - al * q[i];
+        const double zi = ri / d[i];
+        r[i] = ri;
+        z[i] = zi;
+        a += ri * zi;
+        b += ri * ri;
+    }
+    a = red::block_sum(a);
+    b = red::block_sum(b);
+    if (threadIdx.x == 0) {
+        part[blockIdx.x] = a;
+        part[gridDim.x + blockIdx.x] = b;
+    }
+}
+
+// sums of two rows of G partials into out[0], out[1] (second row optional)
+__global__ __launch_bounds__(256) void k_amr_finish2(const double* part, int G, int rows, double* out0,
+                                                     double* out1) {
+    double a = 0.0, b = 0.0;
+    for (int i = threadIdx.x; i < G; i += 256) {
+        a += part[i];
+        if (rows > 1) b += part[G + i];
+    }
+    a = red::block_sum(a);
+    b = red::block_sum(b);
+    if (threadIdx.x == 0) {
+        *out0 = a;
+        if (rows > 1) *out1 = b;
+    }
 }
 
 __global__ __launch_bounds__(256) void k_amr_cg_dir(int64_t n, const double* rz_new,
@@ -1018,17 +1053,22 @@ inline int blocks(int64_t n) { return (int)((n + 255) / 256); }
 
 }  // namespace
 
+int amr_pressure_blocks(const Geo& g, const Tab1& t) {
+    const int cpb = 256 / (t.n * t.n);
+    return (g.Nc + cpb - 1) / cpb;
+}
+
 void launch_amr_pressure(hipStream_t st, const Geo& g, const Tab1& t, double alpha, const double* p,
-                         double* y, bool diag) {
+                         double* y, bool diag, double* part) {
     if (g.Nc == 0) return;
 #define TBDG_AMR_P(NPV)                                                                       \
     case NPV: {                                                                               \
         constexpr int CPB = 256 / (NPV * NPV);                                                \
         const int G = (g.Nc + CPB - 1) / CPB;                                                 \
         if (diag) hipLaunchKernelGGL((k_amr_pressure<NPV, true>), dim3(G), dim3(256), 0, st, g, t, \
-                                     alpha, p, y);                                           \
+                                     alpha, p, y, nullptr);                                  \
         else hipLaunchKernelGGL((k_amr_pressure<NPV, false>), dim3(G), dim3(256), 0, st, g, t,  \
-                                alpha, p, y);                                                \
+                                alpha, p, y, part);                                          \
         break;                                                                                \
     }
     switch (t.n) {
@@ -1224,12 +1264,15 @@ void launch_amr_maxdiff(hipStream_t st, int64_t n, const double* a, const double
     TBDG_HIP(hipGetLastError());
 }
 
-void launch_amr_cg_update(hipStream_t st, int64_t n, const double* rz, const double* pq,
-                          const double* p, const double* q, const double* d, double* x, double* r,
-                          double* z) {
-    if (n == 0) return;
-    hipLaunchKernelGGL(k_amr_cg_update, dim3(blocks(n)), dim3(256), 0, st, n, rz, pq, p, q, d, x, r,
-                       z);
+void launch_amr_cg_step(hipStream_t st, int64_t n, const double* rz, const double* pq, const double* p,
+                        const double* q, const double* d, double* x, double* r, double* z, double* part,
+                        int G) {
+    hipLaunchKernelGGL(k_amr_cg_step, dim3(G), dim3(256), 0, st, n, rz, pq, p, q, d, x, r, z, part);
+    TBDG_HIP(hipGetLastError());
+}
+
+void launch_amr_finish(hipStream_t st, const double* part, int G, int rows, double* out0, double* out1) {
+    hipLaunchKernelGGL(k_amr_finish2, dim3(1), dim3(256), 0, st, part, G, rows, out0, out1);
     TBDG_HIP(hipGetLastError());
 }
 

@@ -56,8 +56,18 @@ struct XferMap {
     int Nnew;
 };
 
+// part (may be null): per-block partial sums of p . y, amr_pressure_blocks
+// of them
 void launch_amr_pressure(hipStream_t st, const Geo& g, const Tab1& t, double alpha, const double* p,
-                         double* y, bool diag);
+                         double* y, bool diag, double* part = nullptr);
+int amr_pressure_blocks(const Geo& g, const Tab1& t);
+// x += al p, r -= al q, z = r / d (al = *rz / *pq), block partials of r.z and
+// r.r in part[0..G), part[G..2G)
+void launch_amr_cg_step(hipStream_t st, int64_t n, const double* rz, const double* pq, const double* p,
+                        const double* q, const double* d, double* x, double* r, double* z, double* part,
+                        int G);
+// out0 = sum of part[0..G), out1 = sum of part[G..2G) when rows == 2
+void launch_amr_finish(hipStream_t st, const double* part, int G, int rows, double* out0, double* out1);
 // y_c = mc M u_c + tnu A u_c + th C(w) u_c, c = 0, 1; uD: wall data at the
 // velocity Gauss points of the boundary faces (face number bface, n points)
 void launch_amr_momentum(hipStream_t st, const Geo& g, const Tab1& t, double mc, double tnu, double th,
@@ -92,11 +102,7 @@ void launch_amr_dot(hipStream_t st, int64_t n, const double* a, const double* b,
 // max |a - b| over G block partials in part, then into *out
 void launch_amr_maxdiff(hipStream_t st, int64_t n, const double* a, const double* b, double* part, int G,
                        double* out);
-// Jacobi PCG glue on device scalars: x += al p, r -= al q, z = r / d with
-// al = *rz / *pq; then p = z + (*rz_new / *rz_old) p
-void launch_amr_cg_update(hipStream_t st, int64_t n, const double* rz, const double* pq,
-                          const double* p, const double* q, const double* d, double* x, double* r,
-                          double* z);
+// Jacobi PCG direction on device scalars: p = z + (*rz_new / *rz_old) p
 void launch_amr_cg_dir(hipStream_t st, int64_t n, const double* rz_new, const double* rz_old,
                        const double* z, double* p);
 void launch_amr_div(hipStream_t st, int64_t n, const double* r, const double* d, double* z);
