@@ -110,6 +110,7 @@ struct MomFuse {
     int ndot;
     double* part;
     const double* shv;   // without invd: the shift is - shift gsc[0] shv (the Krylov vector)
+    const double* rb = nullptr;   // residual mode: y = rb - (operator result)
 };
 constexpr int MOM_FUSE_MAX_DOTS = 8;
 
@@ -391,6 +392,9 @@ void launch_apply_pressure(const tbdg_ctx* c, double alpha, const double* p, dou
 void launch_diag_pressure(const tbdg_ctx* c, double alpha, double* d);
 // momentum operator / diagonal of stage s (Dirichlet data of that stage)
 void launch_apply_momentum(const tbdg_ctx* c, int s, const double* w, const double* u, double* y);
+// r = b - V_s(w) u in one pass where the kernel supports it
+void launch_residual_momentum(const tbdg_ctx* c, int s, const double* w, const double* u,
+                              const double* b, double* r);
 // the same with fused GMRES work; returns the grid size (partials per dot)
 int launch_apply_momentum_fused(const tbdg_ctx* c, int s, const double* w, const double* u,
                                 double* y, const MomFuse& fz);

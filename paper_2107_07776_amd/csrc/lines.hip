@@ -437,6 +437,10 @@ __global__ __launch_bounds__(256) void k_momentum_face(Geom g, LineGeom lg, Line
     }
 #pragma unroll
     for (int c = 0; c < DIM; ++c) yv[c] = active ? s_y[c][pi] - ysh * uraw[c] : 0.0;
+    if (fz.rb && active) {
+#pragma unroll
+        for (int c = 0; c < DIM; ++c) yv[c] = fz.rb[((size_t)cell * DIM + c) * NB + nd] - yv[c];
+    }
     if (active) {
 #pragma unroll
         for (int c = 0; c < DIM; ++c) y[((size_t)cell * DIM + c) * NB + nd] = yv[c];
@@ -1306,6 +1310,7 @@ int launch_apply_momentum_fused(const tbdg_ctx* c, int st, const double* w, cons
     if (fz.invd) bytes += 8.0 * (double)c->Ns;
     if (fz.shv) bytes += 8.0 * (double)c->Nu;
     bytes += 8.0 * fz.ndot * (double)c->Nu;
+    if (fz.rb) bytes += 8.0 * (double)c->Nu;
 #define L_(D, N)                                                                           \
     {                                                                                      \
         using FL = FaceLay<D, N>;                                                          \
@@ -1328,6 +1333,19 @@ int launch_apply_momentum_fused(const tbdg_ctx* c, int st, const double* w, cons
 void launch_apply_momentum(const tbdg_ctx* c, int st, const double* w, const double* u, double* y) {
     launch_apply_momentum_fused(c, st, w, u, y,
                                 MomFuse{nullptr, nullptr, 0.0, nullptr, 0, 0, nullptr, nullptr});
+}
+
+void launch_residual_momentum(const tbdg_ctx* c, int st, const double* w, const double* u,
+                              const double* b, double* r) {
+    if (c->mapped) {
+        // the mapped kernels have no residual mode: apply, then subtract
+        launch_apply_momentum(c, st, w, u, r);
+        vec_axpby(c->stream, c->Nu, 1.0, b, -1.0, r, r);
+        return;
+    }
+    MomFuse fz{nullptr, nullptr, 0.0, nullptr, 0, 0, nullptr, nullptr};
+    fz.rb = b;
+    launch_apply_momentum_fused(c, st, w, u, r, fz);
 }
 
 void launch_rhs_lines(const tbdg_ctx* c, double mcoef, const double* u_prev, const double* u1,

@@ -72,23 +72,11 @@ const double* build_mom_lineprec(tbdg_ctx* c, int s, const double* w) {
     return d;
 }
 
-namespace {
-
-struct MomentumOp {
-    tbdg_ctx* c;
-    int s;
-    const double* w;
-    void operator()(const double* x, double* y) const { launch_apply_momentum(c, s, w, x, y); }
-};
-
-}  // namespace
-
 // ---------------------------------------------------------------------------
 tbdg_status solve_momentum(tbdg_ctx* c, int s, const double* w, const double* b, double* x,
                            const tbdg_solver_opts& o, tbdg_solve_info* info, bool reuse_prec) {
     const int64_t n = c->Nu;
     const int m = std::min(o.restart > 0 ? o.restart : 30, c->gm_m);
-    MomentumOp A{c, s, w};
     const bool line = o.precond == TBDG_PRECOND_LINE;
     const bool mgp = o.precond == TBDG_PRECOND_MG_FP32;
     // line blocks and multigrid are applied by their own kernels into gz;
@@ -134,8 +122,7 @@ tbdg_status solve_momentum(tbdg_ctx* c, int s, const double* w, const double* b,
     // initial residual r = b - A x into V_0; the Krylov vectors stay
     // unnormalised, their inverse norms live in c->gsc on the device
     double* gsc = c->gsc;
-    A(x, c->gv);
-    vec_axpby(c->stream, n, 1.0, b, -1.0, c->gv, V);
+    launch_residual_momentum(c, s, w, x, b, V);
     gm_norm_inv(c, n, V, c->red_out + 63, gsc);
     double beta = std::sqrt(mirrored(c, c->red_out + 63));
     inf.res0 = beta / bnorm;
@@ -143,8 +130,7 @@ tbdg_status solve_momentum(tbdg_ctx* c, int s, const double* w, const double* b,
     // restart; convergence and the final residual always use a true one
     bool true_res = true;
     auto true_residual = [&]() {
-        A(x, c->gv);
-        vec_axpby(c->stream, n, 1.0, b, -1.0, c->gv, V);
+        launch_residual_momentum(c, s, w, x, b, V);
         gm_norm_inv(c, n, V, c->red_out + 63, gsc);
         beta = std::sqrt(mirrored(c, c->red_out + 63));
         true_res = true;
