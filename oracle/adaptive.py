@@ -294,8 +294,10 @@ class AdaptiveDisc:
         return self.k ** 2 * self.pen_p / float(self.f.size(c)[a])
 
     def mass_p(self, cells=None):
+        """Pressure mass matrix; with ``cells`` only those cells' rows (as in
+        every form taking ``cells``: the other rows may be incomplete)."""
         rows, cols, vals = [], [], []
-        for c in range(self.Nc):
+        for c in (range(self.Nc) if cells is None else cells):
             h = self.f.size(c)
             W = np.kron(self.wp, self.wp) * h[0] * h[1]
             xr = np.tile(self.zp, self.n_p)
@@ -330,41 +332,34 @@ class AdaptiveDisc:
 
         xr = np.tile(self.zp, self.n_p)
         yr = np.repeat(self.zp, self.n_p)
-        for c in range(self.Nc):
+        for c in (range(self.Nc) if cells is None else cells):
             h = self.f.size(c)
             W = np.kron(self.wp, self.wp) * h[0] * h[1]
             _, G = self._tab(self.zp, xr, yr, h)
             add(c, c, sum(G[:, :, d].T @ (W[:, None] * G[:, :, d]) for d in range(2)))
-        for c in range(self.Nc):
-            for a in range(2):
-                for s in (0, 1):
-                    nbr = self.f.neighbours(c, a, s)
-                    if nbr[0] == "B" or nbr[0] == "f":
-                        continue   # no pressure boundary term; fine faces visit themselves
-                    if nbr[0] == "C" and s == 0:
-                        continue   # conforming faces once, from side 1
-                    other = nbr[1]
-                    sub = nbr[2] if nbr[0] == "c" else None
-                    h = self.f.size(c)
-                    ho = self.f.size(other)
-                    pc = self._face_points(c, a, s)
-                    po = self._face_points(other, a, 1 - s, sub)
-                    Vc, Gc = self._tab(self.zp, pc[:, 0], pc[:, 1], h)
-                    Vo, Go = self._tab(self.zp, po[:, 0], po[:, 1], ho)
-                    dS = self.wp * float(h[1 - a])       # the (smaller or equal) face of c
-                    nvec = np.zeros(2)
-                    nvec[a] = 1.0 if s == 1 else -1.0
-                    C = 0.5 * (self._sigma(c, a) + self._sigma(other, a))
-                    tabs = [(c, Vc, Gc, nvec), (other, Vo, Go, -nvec)]
-                    for (ct, Vt, Gt, nt) in tabs:
-                        for (cs, Vs, Gs, ns) in tabs:
-                            avg_trial = 0.5 * np.einsum("qjd,d->qj", Gs, nt)
-                            avg_test = 0.5 * np.einsum("qid,d->qi", Gt, ns)
-                            nn = float(ns @ nt)
-                            blk = (-(Vt * dS[:, None]).T @ avg_trial
-                                   - (avg_test * dS[:, None]).T @ Vs
-                                   + (Vt * (C * nn * dS)[:, None]).T @ Vs)
-                            add(ct, cs, blk)
+        # interior faces once (a coarse-fine face from its fine side); no
+        # pressure boundary term
+        for a, c, s, other, sub in self._interfaces(cells):
+            h = self.f.size(c)
+            ho = self.f.size(other)
+            pc = self._face_points(c, a, s)
+            po = self._face_points(other, a, 1 - s, sub)
+            Vc, Gc = self._tab(self.zp, pc[:, 0], pc[:, 1], h)
+            Vo, Go = self._tab(self.zp, po[:, 0], po[:, 1], ho)
+            dS = self.wp * float(h[1 - a])       # the (smaller or equal) face of c
+            nvec = np.zeros(2)
+            nvec[a] = 1.0 if s == 1 else -1.0
+            C = 0.5 * (self._sigma(c, a) + self._sigma(other, a))
+            tabs = [(c, Vc, Gc, nvec), (other, Vo, Go, -nvec)]
+            for (ct, Vt, Gt, nt) in tabs:
+                for (cs, Vs, Gs, ns) in tabs:
+                    avg_trial = 0.5 * np.einsum("qjd,d->qj", Gs, nt)
+                    avg_test = 0.5 * np.einsum("qid,d->qi", Gt, ns)
+                    nn = float(ns @ nt)
+                    blk = (-(Vt * dS[:, None]).T @ avg_trial
+                           - (avg_test * dS[:, None]).T @ Vs
+                           + (Vt * (C * nn * dS)[:, None]).T @ Vs)
+                    add(ct, cs, blk)
         return sp.coo_matrix((np.concatenate(vals), (np.concatenate(rows), np.concatenate(cols))),
                              shape=(self.N_p, self.N_p)).tocsr()
 
@@ -385,11 +380,35 @@ class AdaptiveDisc:
         V, G = self._tab(self.zu, xr, yr, h)
         return V, G, np.kron(self.wu, self.wu) * h[0] * h[1]
 
-    def _interfaces(self):
+    def _interfaces(self, cells=None):
         """Every interior face once: (a, c, s, other, sub) with c the cell
         whose face (a, s) carries the quadrature (the finer or, on a
         same-level face, the side-0 cell) and sub the half of the other
-        cell's face (None when conforming)."""
+        cell's face (None when conforming).  With ``cells``: only the faces
+        touching those cells."""
+        if cells is not None:
+            seen = set()
+            for c in cells:
+                for a in range(2):
+                    for s in (0, 1):
+                        nbr = self.f.neighbours(c, a, s)
+                        if nbr[0] == "C":
+                            key = (a, c, 1, nbr[1], None) if s == 1 else (a, nbr[1], 1, c, None)
+                        elif nbr[0] == "c":
+                            key = (a, c, s, nbr[1], nbr[2])
+                        elif nbr[0] == "f":
+                            for h, o in enumerate(nbr[1]):
+                                key = (a, o, 1 - s, c, h)
+                                if key not in seen:
+                                    seen.add(key)
+                                    yield key
+                            continue
+                        else:
+                            continue
+                        if key not in seen:
+                            seen.add(key)
+                            yield key
+            return
         for c in range(self.Nc):
             for a in range(2):
                 for s in (0, 1):
@@ -414,7 +433,7 @@ class AdaptiveDisc:
 
     def mass_u(self, cells=None):
         blocks = []
-        for c in range(self.Nc):
+        for c in (range(self.Nc) if cells is None else cells):
             V, _, W = self._cell_tab_u(c)
             blocks.append((c, c, V.T @ (W[:, None] * V)))
         return self._assemble(blocks, self.nbu, self.Nc * self.nbu)
@@ -424,10 +443,10 @@ class AdaptiveDisc:
         in a_p (penalty (k+1)^2 pen_u |Gamma_K|/|K| averaged), boundary faces
         of a non-periodic direction -grad u.n v - u n.grad v + 2 C u v."""
         blocks = []
-        for c in range(self.Nc):
+        for c in (range(self.Nc) if cells is None else cells):
             V, G, W = self._cell_tab_u(c)
             blocks.append((c, c, sum(G[:, :, d].T @ (W[:, None] * G[:, :, d]) for d in range(2))))
-        for a, c, s, other, sub in self._interfaces():
+        for a, c, s, other, sub in self._interfaces(cells):
             Vc, Gc, Vo, Go, nvec, dS = self._face_pair_u(a, c, s, other, sub)
             C = 0.5 * (self._sigma_u(c, a) + self._sigma_u(other, a))
             tabs = [(c, Vc, Gc, nvec), (other, Vo, Go, -nvec)]
@@ -438,7 +457,7 @@ class AdaptiveDisc:
                     blk = (-(Vt * dS[:, None]).T @ avg_trial - (avg_test * dS[:, None]).T @ Vs
                            + (Vt * (C * float(ns @ nt) * dS)[:, None]).T @ Vs)
                     blocks.append((ct, cs, blk))
-        for c, a, s in self._boundary_faces():
+        for c, a, s in self._boundary_faces(cells):
             h = self.f.size(c)
             pc = np.zeros((self.n, 2)); pc[:, a] = float(s); pc[:, 1 - a] = self.zu
             V, G = self._tab(self.zu, pc[:, 0], pc[:, 1], h)
@@ -450,8 +469,8 @@ class AdaptiveDisc:
                            + (V * (2.0 * C * dS)[:, None]).T @ V))
         return self._assemble(blocks, self.nbu, self.Nc * self.nbu)
 
-    def _boundary_faces(self):
-        for c in range(self.Nc):
+    def _boundary_faces(self, cells=None):
+        for c in (range(self.Nc) if cells is None else cells):
             for a in range(2):
                 for s in (0, 1):
                     if self.f.neighbours(c, a, s)[0] == "B":
@@ -660,12 +679,12 @@ class AdaptiveDisc:
         coarse and two fine cells: the fine faces' Gauss points.  uD: (n_b, 2)
         at boundary_points()."""
         blocks = []
-        for c in range(self.Nc):
+        for c in (range(self.Nc) if cells is None else cells):
             V, G, W = self._cell_tab_u(c)
             wq = V @ self._w_cell(w, c).T
             wgv = np.einsum("qd,qid->qi", wq, G)
             blocks.append((c, c, -(wgv * W[:, None]).T @ V))
-        for a, c, s, other, sub in self._interfaces():
+        for a, c, s, other, sub in self._interfaces(cells):
             Vc, _, Vo, _, nvec, dS = self._face_pair_u(a, c, s, other, sub)
             wc = Vc @ self._w_cell(w, c).T
             wo = Vo @ self._w_cell(w, other).T
@@ -675,7 +694,10 @@ class AdaptiveDisc:
                 for (cs, Vs, ns, ws) in tabs:
                     coef = 0.5 * (ws @ nt) + 0.5 * lam * float(ns @ nt)
                     blocks.append((ct, cs, (Vt * (coef * dS)[:, None]).T @ Vs))
-        for b, (c, a, s) in enumerate(self._boundary_faces()):
+        bnum = {f: b for b, f in enumerate(self._boundary_faces())} if cells is not None else None
+        for b, (c, a, s) in enumerate(self._boundary_faces(cells)):
+            if bnum is not None:
+                b = bnum[(c, a, s)]
             V, _, _, _, nvec, dS, x = self._bnd_face(c, a, s)
             wq = V @ self._w_cell(w, c).T
             wext = 2.0 * self._uD_at(uD, b, c, a, s, x) - wq
@@ -683,19 +705,20 @@ class AdaptiveDisc:
             blocks.append((c, c, (V * (lam * dS)[:, None]).T @ V))
         return self._assemble(blocks, self.nbu, self.Nc * self.nbu)
 
-    def apply_momentum(self, mc, tnu, th, w, u, uD=None):
+    def apply_momentum(self, mc, tnu, th, w, u, uD=None, cells=None):
         """y_c = (mc M + tnu A + th C(w)) u_c for both components of u
-        ([cell][component][node])."""
-        A = (mc * self.mass_u() + tnu * self.sip_u() + th * self.lf_advection(w, uD)).tocsr()
+        ([cell][component][node]); with ``cells`` valid on those cells only."""
+        A = (mc * self.mass_u(cells) + tnu * self.sip_u(cells)
+             + th * self.lf_advection(w, uD, cells)).tocsr()
         U = u.reshape(self.Nc, 2, self.nbu)
         out = np.empty_like(U)
         for comp in range(2):
             out[:, comp, :] = (A @ U[:, comp, :].reshape(-1)).reshape(self.Nc, self.nbu)
         return out.reshape(-1)
 
-    def helmholtz_p(self, alpha):
+    def helmholtz_p(self, alpha, cells=None):
         """alpha M^p + K: the stage pressure operator of Sec. 3."""
-        return (alpha * self.mass_p() + self.sip_p()).tocsr()
+        return (alpha * self.mass_p(cells) + self.sip_p(cells)).tocsr()
 
     def indicator(self, u):
         """eta_K = diam(K)^2 ||omega||^2_K, u in [cell][component][node]

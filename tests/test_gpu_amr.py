@@ -389,3 +389,52 @@ def test_adaptive_schedule_matches_oracle(check_tol):
         assert np.linalg.norm(P.cpu().numpy() - p) <= 1e-8 * np.linalg.norm(p)
     finally:
         g.close()
+
+
+def test_full_size_adaptive_operators_sampled():
+    """The adaptive workload's mesh (512^2 base cells, Q3-Q2, two levels of
+    hanging nodes, refined by the vortex field's indicator as the benchmark
+    does): sampled rows of the pressure Helmholtz and momentum operators,
+    coarse-fine cells included, against the oracle's row-restricted forms."""
+    import bench
+    from paper_2107_07776_amd import Adaptive
+    k, base, maxl = 3, 512, 2
+    L = 2 * np.pi
+    H = L / base
+    print(f"[case] amr full size base={base} k={k}", flush=True)
+    g = Adaptive((base, base), (0.0, 0.0), (L, L), k, maxl, periodic=(1, 1))
+    try:
+        x = bench.amr_nodes(g.leaves(), H, k)
+        uv = bench.amr_vortices(x)
+        n = (k + 1) ** 2
+        u = np.empty(g.N_u)
+        u.reshape(-1, 2, n)[:, 0, :] = uv[:, 0].reshape(-1, n)
+        u.reshape(-1, 2, n)[:, 1, :] = uv[:, 1].reshape(-1, n)
+        U = _t(u)
+        for _ in range(3):
+            flags = g.mark(g.indicator(U), 0.1, 0.3, H / 4, H)
+            (U,) = g.adapt(flags, [("u", U)])
+        lv = g.leaves()
+        assert (lv[:, 0] == 2).sum() > 0 and (lv[:, 0] == 0).sum() > 0
+        f = QuadForest((base, base), (0.0, 0.0), (L, L), (1, 1), maxl, leaves=[tuple(r) for r in lv.tolist()])
+        assert f.leaves == [tuple(r) for r in lv.tolist()]
+        rng = np.random.default_rng(17)
+        hang = [c for c in rng.choice(f.N, size=4000, replace=False).tolist()
+                if any(f.neighbours(c, a, s)[0] in ("c", "f") for a in range(2) for s in (0, 1))]
+        cells = sorted(set(hang[:24] + rng.choice(f.N, size=16, replace=False).tolist()))
+        assert len(hang) >= 24
+        ad = AdaptiveDisc(f, k)
+        alpha = 3.0
+        p = synthetic.random_vector(ad.N_p, 71)
+        y = g.apply_pressure(alpha, _t(p)).cpu().numpy()
+        ref = ad.helmholtz_p(alpha, cells) @ p
+        rp = np.concatenate([np.arange(c * ad.nbp, (c + 1) * ad.nbp) for c in cells])
+        assert np.abs(y[rp] - ref[rp]).max() <= 1e-12 * np.abs(ref[rp]).max()
+        w = U.cpu().numpy()
+        uu = synthetic.random_vector(ad.N_u, 72)
+        ym = g.apply_momentum(40.0, 0.002, 0.5, U, _t(uu)).cpu().numpy()
+        refm = ad.apply_momentum(40.0, 0.002, 0.5, w, uu, None, cells)
+        rv = np.concatenate([np.arange(c * 2 * ad.nbu, (c + 1) * 2 * ad.nbu) for c in cells])
+        assert np.abs(ym[rv] - refm[rv]).max() <= 1e-12 * np.abs(refm[rv]).max()
+    finally:
+        g.close()

@@ -490,3 +490,27 @@ def test_trbdf2_step_on_a_one_level_forest_equals_the_box_oracle(walls):
     uad, ha, pad, _ = sa.step(ua, ua, pa, 0.0)
     assert np.abs(to_box(uad, disc.nbu, 2) - ub).max() < 1e-11 * np.abs(ub).max()
     assert np.abs(to_box(pad, disc.nbp, 1) - pb).max() < 1e-10 * np.abs(pb).max()
+
+
+def test_row_restricted_assembly_equals_full_rows():
+    """The forms assembled for a few cells give those cells' rows of the
+    full matrices (used for sampled comparisons on large meshes)."""
+    k = 3
+    f = _random_forest(12, max_level=3, rounds=3)
+    ad = AdaptiveDisc(f, k)
+    rng = np.random.default_rng(5)
+    cells = sorted(rng.choice(f.N, size=min(7, f.N), replace=False).tolist())
+    rp = np.concatenate([np.arange(c * ad.nbp, (c + 1) * ad.nbp) for c in cells])
+    ru = np.concatenate([np.arange(c * ad.nbu, (c + 1) * ad.nbu) for c in cells])
+    A, Ar = ad.helmholtz_p(2.0), ad.helmholtz_p(2.0, cells)
+    assert abs(A[rp] - Ar[rp]).max() < 1e-14 * abs(A).max()   # summation order only
+    w = rng.standard_normal(ad.N_u)
+    uD = rng.standard_normal((len(ad.boundary_points()), 2))
+    for full, part in ((ad.sip_u(), ad.sip_u(cells)), (ad.mass_u(), ad.mass_u(cells)),
+                       (ad.lf_advection(w, uD), ad.lf_advection(w, uD, cells))):
+        assert abs(full[ru] - part[ru]).max() < 1e-14 * abs(full).max()
+    u = rng.standard_normal(ad.N_u)
+    yf = ad.apply_momentum(1.0, 0.1, 0.5, w, u, uD)
+    yr = ad.apply_momentum(1.0, 0.1, 0.5, w, u, uD, cells)
+    rv = np.concatenate([np.arange(c * 2 * ad.nbu, (c + 1) * 2 * ad.nbu) for c in cells])
+    assert np.abs(yf[rv] - yr[rv]).max() < 1e-13 * np.abs(yf).max()
