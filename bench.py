@@ -165,7 +165,12 @@ def kovasznay_errors(ctx, W, U, P):
 LAUNCH_SAMPLE_STRIDE = 3
 
 TRAFFIC_FILES = {("momentum_apply", "tgv32"): "momentum_face_tgv32_q3_traffic.txt",
-                 ("momentum_apply", "tgv64"): "momentum_face_tgv64_q3_traffic.txt"}
+                 ("momentum_apply", "tgv64"): "momentum_face_tgv64_q3_traffic.txt",
+                 ("amr_pressure", "amr2d"): "amr_pressure_amr2d_q3_traffic.txt"}
+
+# the kernel sources each byte-counter summary depends on
+TRAFFIC_SOURCES = {"momentum_apply": ("lines.hip", "lines.hpp", "internal.hpp"),
+                   "amr_pressure": ("amr.hip", "amr.hpp")}
 
 
 def measured_traffic(kernel, workload):
@@ -186,16 +191,19 @@ def measured_traffic(kernel, workload):
             k, v = line.split("=", 1)
             vals[k.strip()] = v.strip()
     src = vals.get("kernel_source_sha256")
-    if src is None or src != kernel_source_digest():
+    if src is None or src != kernel_source_digest(TRAFFIC_SOURCES[kernel]):
         return None
-    return {"bytes_per_launch": float(vals["traffic_bytes_per_launch"]), "source": f"profiles/{name}"}
+    out = {"bytes_per_launch": float(vals["traffic_bytes_per_launch"]), "source": f"profiles/{name}"}
+    if "traffic_bytes_per_pressure_dof" in vals:
+        out["bytes_per_dof"] = float(vals["traffic_bytes_per_pressure_dof"])
+    return out
 
 
-def kernel_source_digest():
-    """SHA-256 over the HIP sources of the operator kernels."""
+def kernel_source_digest(files=("lines.hip", "lines.hpp", "internal.hpp")):
+    """SHA-256 over the HIP sources of an operator kernel."""
     import hashlib
     h = hashlib.sha256()
-    for f in ("lines.hip", "lines.hpp", "internal.hpp"):
+    for f in files:
         h.update(open(os.path.join(ROOT, "paper_2107_07776_amd", "csrc", f), "rb").read())
     return h.hexdigest()
 
@@ -581,6 +589,12 @@ def run_amr(args, applies=50):
                         "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": gbs / HBM_PEAK_GBS,
                         "traffic": None, "algorithmic_bytes_per_launch": bytes_launch,
                         "avg_launch_us": avg_s * 1e6, "launches_timed": reps}}
+    traffic = measured_traffic("amr_pressure", "amr2d")
+    if traffic and traffic.get("bytes_per_dof"):
+        # the mesh changes from cycle to cycle: the counted bytes per pressure
+        # DoF of the summary's mesh, times this mesh's DoFs
+        out["roofline"]["traffic"] = traffic["bytes_per_dof"] * g.N_p
+        out["roofline"]["traffic_source"] = traffic["source"] + " (bytes per pressure DoF x DoFs)"
     g.close()
     if not args.no_amr_steps:
         out["adaptive_trbdf2"] = amr_steps(args)
@@ -700,9 +714,6 @@ def main():
 
     import torch
 
-    if args.workload == "amr2d":
-        run_amr(args)
-        return
     if args.copy_calibration > 0:
         n = args.copy_calibration * (1 << 20) // 8
         src = torch.ones(n, dtype=torch.float64, device="cuda")
@@ -712,6 +723,9 @@ def main():
         torch.cuda.synchronize()
         log(f"[bench] copied {args.copy_calibration} MiB five times")
         del src, dst
+    if args.workload == "amr2d":
+        run_amr(args)
+        return
     W = workload(args.workload)
     log(f"[bench] setting up {W['label']}")
     if args.nonlinear > 0:

@@ -21,6 +21,7 @@
 
 #include "amr.hpp"
 #include "internal.hpp"
+#include "lines.hpp"
 #include "reduce.hpp"
 
 namespace trbdg {
@@ -60,7 +61,8 @@ __global__ __launch_bounds__(256) void k_amr_pressure(Geo g, Tab1 t, double alph
     __shared__ double s_y[2][CPB * NB];
     const int tid = threadIdx.x;
     const int lc = tid / NB, nd = tid % NB;
-    const int cell0 = blockIdx.x * CPB;
+    // consecutive cells (and so the neighbours a block gathers) on one XCD
+    const int cell0 = lines::xcd_block(blockIdx.x, gridDim.x) * CPB;
     const int cell = cell0 + lc;
     const bool active = lc < CPB && cell < g.Nc;
     if (lc < CPB) s_p[tid] = (active && !DIAG) ? p[(size_t)cell * NB + nd] : 0.0;
@@ -209,7 +211,8 @@ __global__ __launch_bounds__(256) void k_amr_momentum(Geo g, Tab1 t, double mc, 
     __shared__ double s_y[2][2][CPB * NB];
     const int tid = threadIdx.x;
     const int lc = tid / NB, nd = tid % NB;
-    const int cell0 = blockIdx.x * CPB;
+    // consecutive cells (and so the neighbours a block gathers) on one XCD
+    const int cell0 = lines::xcd_block(blockIdx.x, gridDim.x) * CPB;
     const int cell = cell0 + lc;
     const bool active = lc < CPB && cell < g.Nc;
     if (lc < CPB) {
@@ -433,7 +436,8 @@ __global__ __launch_bounds__(256) void k_amr_explicit(Geo g, Tab1 t, MixTab x, E
     __shared__ double s_y[2][2][CPB * NB];
     const int tid = threadIdx.x;
     const int lc = tid / NB, nd = tid % NB;
-    const int cell0 = blockIdx.x * CPB;
+    // consecutive cells (and so the neighbours a block gathers) on one XCD
+    const int cell0 = lines::xcd_block(blockIdx.x, gridDim.x) * CPB;
     const int cell = cell0 + lc;
     const bool active = lc < CPB && cell < g.Nc;
     if (lc < CPB) {
@@ -694,7 +698,8 @@ __global__ __launch_bounds__(256) void k_amr_rhs_p(Geo g, Tab1 t, MixTab x, doub
     __shared__ double s_e[CPB * 4 * N * 2];   // own and exterior normal-component traces
     const int tid = threadIdx.x;
     const int lc = tid / NB, nd = tid % NB;
-    const int cell0 = blockIdx.x * CPB;
+    // consecutive cells (and so the neighbours a block gathers) on one XCD
+    const int cell0 = lines::xcd_block(blockIdx.x, gridDim.x) * CPB;
     const int cell = cell0 + lc;
     if (lc < CPB) {
         const bool act = cell < g.Nc;
