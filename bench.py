@@ -607,7 +607,8 @@ def run_amr(args, applies=50):
 def amr_steps(args, base=64, k=3, maxl=2, nu=5e-3, dt=5e-4, remesh_every=5):
     """TR-BDF2 steps on an adaptive mesh with the remeshing schedule of
     Sec. 4 (every remesh_every steps: indicator, 10 % / 30 % marking,
-    transfer of u, u_hist and p): Jacobi GMRES(30) and Jacobi CG to 1e-8."""
+    transfer of u, u_hist and p): Jacobi GMRES(30) and cell-block-Jacobi CG
+    to 1e-8."""
     import numpy as np
     import torch
 
@@ -658,7 +659,7 @@ def amr_steps(args, base=64, k=3, maxl=2, nu=5e-3, dt=5e-4, remesh_every=5):
            "config": f"(0, 2pi)^2 periodic, {base}^2 base cells, Q{k}-Q{k - 1}, <= {maxl} refinement "
                      f"levels, nu = {nu}, dt = {dt}, the twelve-vortex velocity at rest pressure; "
                      "remeshing (timed) every " + str(remesh_every) + " steps; Jacobi GMRES(30) and "
-                     "Jacobi CG to 1e-8"}
+                     "cell-block-Jacobi CG to 1e-8"}
     g.close()
     return out
 

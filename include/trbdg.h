@@ -673,9 +673,12 @@ TBDG_API tbdg_status tbdg_amr_step(tbdg_amr* amr, const tbdg_amr_step_opts* opts
                                    tbdg_solve_info info[4], double* max_du);
 /* d = diag(alpha M^p + K).                                                 */
 TBDG_API tbdg_status tbdg_amr_diag_pressure(tbdg_amr* amr, double alpha, double* d);
-/* Jacobi-preconditioned CG for (alpha M^p + K) x = b from the given x
- * (alpha > 0), FP64 throughout, to ||b - A x|| <= tol ||b||.  Errors:
- * TBDG_ENOTCONV, TBDG_EBREAKDOWN, TBDG_ENAN; x holds the last iterate.      */
+/* Preconditioned CG for (alpha M^p + K) x = b from the given x (alpha > 0),
+ * FP64 vectors and recurrences, to ||b - A x|| <= tol ||b|| (the recurrence
+ * residual, read every 8 iterations).  Preconditioner: the inverses of the
+ * cells' diagonal blocks (stored FP32) for k <= 4, else the Jacobi
+ * diagonal.  Errors: TBDG_ENOTCONV, TBDG_EBREAKDOWN, TBDG_ENAN; x holds
+ * the last iterate.                                                          */
 TBDG_API tbdg_status tbdg_amr_solve_pressure(tbdg_amr* amr, double alpha, const double* b, double* x,
                                              double tol, int maxiter, tbdg_solve_info* info);
 /* eta[c] = (h_x^2 + h_y^2) int_K (d_x u_y - d_y u_x)^2 (the diagonal as

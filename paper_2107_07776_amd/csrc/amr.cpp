@@ -305,6 +305,11 @@ struct tbdg_amr {
     double* part = nullptr;
     double* ppart = nullptr;     // block partials of the operator kernel
     int64_t ppart_cap = 0;
+    double* blk = nullptr;       // cell blocks of the pressure operator (FP64)
+    float* blkinv = nullptr;     // their inverses (FP32)
+    int64_t blk_cap = 0;
+    double* bpart = nullptr;     // block partials of the block-Jacobi apply
+    int64_t bpart_cap = 0;
     double* scal = nullptr;      // device scalars: rz[2], pq, rr, bb
     double* host = nullptr;      // pinned
     std::string last_error;
@@ -378,6 +383,9 @@ struct tbdg_amr {
         devfree(sv);
         devfree(part);
         devfree(ppart);
+        devfree(blk);
+        devfree(blkinv);
+        devfree(bpart);
         devfree(scal);
         if (host) (void)hipHostFree(host);
         host = nullptr;
@@ -919,7 +927,30 @@ tbdg_status tbdg_amr_solve_pressure(tbdg_amr* m, double alpha, const double* b, 
         const hipStream_t st = m->stream;
         const A::Geo g = m->geo();
         tbdg_solve_info inf{0, 0.0, 0.0, 0, 0};
-        A::launch_amr_pressure(st, g, m->tp, alpha, nullptr, d, true);
+        // cell-block Jacobi (the inverse of every cell's diagonal block) where
+        // the blocks are small, else the point Jacobi diagonal
+        const int nbp = m->k * m->k;
+        const bool blk = A::amr_block_ok(nbp);
+        const int64_t nc = m->Nc();
+        if (blk) {
+            const int64_t nbb = nc * nbp * nbp;
+            if (nbb > m->blk_cap) {
+                devfree(m->blk);
+                devfree(m->blkinv);
+                m->blk = devalloc<double>(nbb);
+                m->blkinv = devalloc<float>(nbb);
+                m->blk_cap = nbb;
+            }
+            A::launch_amr_block_build(st, g, m->tp, alpha, z, q, m->blk, m->blkinv);
+            const int64_t gb = 2 * ((nc + 256 / nbp - 1) / (256 / nbp));
+            if (gb > m->bpart_cap) {
+                devfree(m->bpart);
+                m->bpart = devalloc<double>(gb);
+                m->bpart_cap = gb;
+            }
+        } else {
+            A::launch_amr_pressure(st, g, m->tp, alpha, nullptr, d, true);
+        }
         A::launch_amr_pressure(st, g, m->tp, alpha, x, q, false);
         trbdg::vec_axpby(st, n, 1.0, b, -1.0, q, r);
         const double bnorm = std::sqrt(dot(m, n, b, b, 4));
@@ -931,9 +962,14 @@ tbdg_status tbdg_amr_solve_pressure(tbdg_amr* m, double alpha, const double* b, 
         if (!std::isfinite(bnorm)) return TBDG_ENAN;
         double res = std::sqrt(dot(m, n, r, r, 3)) / bnorm;
         inf.res0 = res;
-        A::launch_amr_div(st, n, r, d, z);
+        if (blk) {
+            const int gb = A::launch_amr_block_apply(st, nc, nbp, m->blkinv, r, z, m->bpart);
+            A::launch_amr_finish(st, m->bpart, gb, 1, rz[0], nullptr);
+        } else {
+            A::launch_amr_div(st, n, r, d, z);
+            A::launch_amr_dot(st, n, r, z, m->part, DOT_BLOCKS, rz[0]);
+        }
         TBDG_HIP(hipMemcpyAsync(p, z, sizeof(double) * n, hipMemcpyDeviceToDevice, st));
-        A::launch_amr_dot(st, n, r, z, m->part, DOT_BLOCKS, rz[0]);
         // per iteration: the operator with its p.q block sums, one fused
         // update with the r.z and r.r block sums, the direction; all scalars
         // stay on the device and the host reads p.q and r.r every kCheck
@@ -962,8 +998,14 @@ tbdg_status tbdg_amr_solve_pressure(tbdg_amr* m, double alpha, const double* b, 
             for (; it < stop; ++it) {
                 A::launch_amr_pressure(st, g, m->tp, alpha, p, q, false, m->ppart);
                 A::launch_amr_finish(st, m->ppart, Gp, 1, pq, nullptr);
-                A::launch_amr_cg_step(st, n, rz[cur], pq, p, q, d, x, r, z, m->part, DOT_BLOCKS / 2);
-                A::launch_amr_finish(st, m->part, DOT_BLOCKS / 2, 2, rz[1 - cur], rr);
+                if (blk) {
+                    A::launch_amr_cg_xr(st, n, rz[cur], pq, p, q, x, r);
+                    const int gb = A::launch_amr_block_apply(st, nc, nbp, m->blkinv, r, z, m->bpart);
+                    A::launch_amr_finish(st, m->bpart, gb, 2, rz[1 - cur], rr);
+                } else {
+                    A::launch_amr_cg_step(st, n, rz[cur], pq, p, q, d, x, r, z, m->part, DOT_BLOCKS / 2);
+                    A::launch_amr_finish(st, m->part, DOT_BLOCKS / 2, 2, rz[1 - cur], rr);
+                }
                 A::launch_amr_cg_dir(st, n, rz[1 - cur], rz[cur], z, p);
                 cur = 1 - cur;
             }

@@ -50,10 +50,14 @@ __device__ inline void trace(const double* __restrict__ p, const Tab1& t, int ce
 }
 
 // y = (alpha M + K) p, or its diagonal (DIAG)
-template <int NP, bool DIAG>
+// MODE 0: y = H p; 1: y = diag(H); 2: y = H_own p, the cell-local part of
+// H (the exterior traces set to zero): applied to a field that is one unit
+// node per cell it returns one column of every cell's diagonal block
+template <int NP, int MODE>
 __global__ __launch_bounds__(256) void k_amr_pressure(Geo g, Tab1 t, double alpha,
                                                       const double* __restrict__ p,
                                                       double* __restrict__ y, double* part) {
+    constexpr bool DIAG = MODE == 1;
     constexpr int NB = NP * NP;
     constexpr int CPB = 256 / NB;
     __shared__ double s_p[CPB * NB];
@@ -71,7 +75,7 @@ __global__ __launch_bounds__(256) void k_amr_pressure(Geo g, Tab1 t, double alph
         const int c2 = it / (4 * NP), f = (it / NP) % 4, tt = it % NP;
         const int cl = cell0 + c2;
         double ve = 0.0, de = 0.0;
-        if (!DIAG && cl < g.Nc) {
+        if (MODE == 0 && cl < g.Nc) {
             const int meta = g.meta[cl * 4 + f];
             const int kind = meta & 15, half = meta >> 4;
             const int a = f >> 1, s = f & 1, so = 1 - s;
@@ -181,7 +185,7 @@ __global__ __launch_bounds__(256) void k_amr_pressure(Geo g, Tab1 t, double alph
         py = own * v;
     }
     // optional per-block partial sum of p . y (the CG step length)
-    if (!DIAG && part) {
+    if (MODE == 0 && part) {
         py = red::block_sum(py);
         if (threadIdx.x == 0) part[blockIdx.x] = py;
     }
@@ -966,6 +970,96 @@ __global__ __launch_bounds__(256) void k_amr_dot_finish(const double* part, int 
     if (threadIdx.x == 0) *out = s;
 }
 
+// one unit node per cell: u[c NB + j] = (j == i)
+__global__ __launch_bounds__(256) void k_amr_unit(int64_t nc, int nb, int i, double* u) {
+    const int64_t gid = (int64_t)blockIdx.x * 256 + threadIdx.x;
+    if (gid < nc * nb) u[gid] = (int)(gid % nb) == i ? 1.0 : 0.0;
+}
+
+// column i of every cell's block: B[c][row][i] = y[c NB + row] (FP64 scratch)
+__global__ __launch_bounds__(256) void k_amr_block_col(int64_t nc, int nb, int i, const double* y,
+                                                       double* B) {
+    const int64_t gid = (int64_t)blockIdx.x * 256 + threadIdx.x;
+    if (gid >= nc * nb) return;
+    const int64_t c = gid / nb;
+    const int row = (int)(gid % nb);
+    B[(c * nb + row) * nb + i] = y[gid];
+}
+
+// in-place inverse of every cell's SPD block by Gauss-Jordan elimination
+// without pivoting (the diagonal block of an SPD matrix is SPD), stored FP32
+template <int NBK>
+__global__ __launch_bounds__(64) void k_amr_block_inv(int64_t nc, const double* __restrict__ B,
+                                                      float* __restrict__ Binv) {
+    const int64_t c = (int64_t)blockIdx.x * 64 + threadIdx.x;
+    if (c >= nc) return;
+    double a[NBK * NBK], v[NBK * NBK];
+    for (int q = 0; q < NBK * NBK; ++q) {
+        a[q] = B[c * NBK * NBK + q];
+        v[q] = (q / NBK == q % NBK) ? 1.0 : 0.0;
+    }
+    for (int k = 0; k < NBK; ++k) {
+        const double ip = 1.0 / a[k * NBK + k];
+        for (int j = 0; j < NBK; ++j) {
+            a[k * NBK + j] *= ip;
+            v[k * NBK + j] *= ip;
+        }
+        for (int r = 0; r < NBK; ++r) {
+            if (r == k) continue;
+            const double fct = a[r * NBK + k];
+            for (int j = 0; j < NBK; ++j) {
+                a[r * NBK + j] -= fct * a[k * NBK + j];
+                v[r * NBK + j] -= fct * v[k * NBK + j];
+            }
+        }
+    }
+    for (int q = 0; q < NBK * NBK; ++q) Binv[c * NBK * NBK + q] = (float)v[q];
+}
+
+// z = B^{-1} r per cell (FP32 blocks, FP64 vectors and sums); block partial
+// sums of r.z and r.r in part[b], part[G + b]
+template <int NBK>
+__global__ __launch_bounds__(256) void k_amr_block_apply(int64_t nc, const float* __restrict__ Binv,
+                                                         const double* __restrict__ r,
+                                                         double* __restrict__ z, double* part) {
+    constexpr int CPB = 256 / NBK;
+    __shared__ double s_r[CPB * NBK];
+    const int tid = threadIdx.x;
+    const int lc = tid / NBK, i = tid % NBK;
+    const int64_t c = (int64_t)blockIdx.x * CPB + lc;
+    const bool act = lc < CPB && c < nc;
+    if (lc < CPB) s_r[tid] = act ? r[c * NBK + i] : 0.0;
+    __syncthreads();
+    double rz = 0.0, rr = 0.0;
+    if (act) {
+        double zi = 0.0;
+        const float* row = Binv + (c * NBK + i) * NBK;
+#pragma unroll
+        for (int j = 0; j < NBK; ++j) zi += (double)row[j] * s_r[lc * NBK + j];
+        z[c * NBK + i] = zi;
+        rz = s_r[tid] * zi;
+        rr = s_r[tid] * s_r[tid];
+    }
+    rz = red::block_sum(rz);
+    rr = red::block_sum(rr);
+    if (threadIdx.x == 0) {
+        part[blockIdx.x] = rz;
+        part[gridDim.x + blockIdx.x] = rr;
+    }
+}
+
+// x += al p, r -= al q (al = *rz / *pq)
+__global__ __launch_bounds__(256) void k_amr_cg_xr(int64_t n, const double* rz, const double* pq,
+                                                   const double* __restrict__ p,
+                                                   const double* __restrict__ q,
+                                                   double* __restrict__ x, double* __restrict__ r) {
+    const int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
+    if (i >= n) return;
+    const double al = *rz / *pq;
+    x[i] += al * p[i];
+    r[i] -= al * q[i];
+}
+
 // x += al p, r -= al q, z = r / d, al = *rz / *pq; per-block partial sums
 // of r.z and r.r (grid-stride over a fixed grid)
 __global__ __launch_bounds__(256) void k_amr_cg_step(int64_t n, const double* rz, const double* pq,
@@ -1065,15 +1159,22 @@ int amr_pressure_blocks(const Geo& g, const Tab1& t) {
 
 void launch_amr_pressure(hipStream_t st, const Geo& g, const Tab1& t, double alpha, const double* p,
                          double* y, bool diag, double* part) {
+    launch_amr_pressure_mode(st, g, t, alpha, p, y, diag ? 1 : 0, part);
+}
+
+void launch_amr_pressure_mode(hipStream_t st, const Geo& g, const Tab1& t, double alpha,
+                              const double* p, double* y, int mode, double* part) {
     if (g.Nc == 0) return;
 #define TBDG_AMR_P(NPV)                                                                       \
     case NPV: {                                                                               \
         constexpr int CPB = 256 / (NPV * NPV);                                                \
         const int G = (g.Nc + CPB - 1) / CPB;                                                 \
-        if (diag) hipLaunchKernelGGL((k_amr_pressure<NPV, true>), dim3(G), dim3(256), 0, st, g, t, \
-                                     alpha, p, y, nullptr);                                  \
-        else hipLaunchKernelGGL((k_amr_pressure<NPV, false>), dim3(G), dim3(256), 0, st, g, t,  \
-                                alpha, p, y, part);                                          \
+        if (mode == 1) hipLaunchKernelGGL((k_amr_pressure<NPV, 1>), dim3(G), dim3(256), 0, st, g, \
+                                          t, alpha, p, y, nullptr);                          \
+        else if (mode == 2) hipLaunchKernelGGL((k_amr_pressure<NPV, 2>), dim3(G), dim3(256), 0, st, \
+                                               g, t, alpha, p, y, nullptr);                  \
+        else hipLaunchKernelGGL((k_amr_pressure<NPV, 0>), dim3(G), dim3(256), 0, st, g, t, alpha, \
+                                p, y, part);                                                 \
         break;                                                                                \
     }
     switch (t.n) {
@@ -1266,6 +1367,53 @@ void launch_amr_maxdiff(hipStream_t st, int64_t n, const double* a, const double
                        double* out) {
     hipLaunchKernelGGL(k_amr_maxdiff, dim3(G), dim3(256), 0, st, n, a, b, part);
     hipLaunchKernelGGL(k_amr_max_finish, dim3(1), dim3(256), 0, st, part, G, out);
+    TBDG_HIP(hipGetLastError());
+}
+
+bool amr_block_ok(int nb) { return nb == 1 || nb == 4 || nb == 9 || nb == 16; }
+
+void launch_amr_block_build(hipStream_t st, const Geo& g, const Tab1& t, double alpha, double* u,
+                            double* y, double* B, float* Binv) {
+    const int nb = t.n * t.n;
+    const int64_t nc = g.Nc;
+    if (nc == 0) return;
+    const int G = blocks(nc * nb);
+    for (int i = 0; i < nb; ++i) {
+        hipLaunchKernelGGL(k_amr_unit, dim3(G), dim3(256), 0, st, nc, nb, i, u);
+        launch_amr_pressure_mode(st, g, t, alpha, u, y, 2, nullptr);
+        hipLaunchKernelGGL(k_amr_block_col, dim3(G), dim3(256), 0, st, nc, nb, i, y, B);
+    }
+    const int Gi = (int)((nc + 63) / 64);
+    switch (nb) {
+        case 1: hipLaunchKernelGGL((k_amr_block_inv<1>), dim3(Gi), dim3(64), 0, st, nc, B, Binv); break;
+        case 4: hipLaunchKernelGGL((k_amr_block_inv<4>), dim3(Gi), dim3(64), 0, st, nc, B, Binv); break;
+        case 9: hipLaunchKernelGGL((k_amr_block_inv<9>), dim3(Gi), dim3(64), 0, st, nc, B, Binv); break;
+        case 16: hipLaunchKernelGGL((k_amr_block_inv<16>), dim3(Gi), dim3(64), 0, st, nc, B, Binv); break;
+        default: throw Error(TBDG_EUNSUPPORTED, "cell blocks up to 16 pressure nodes");
+    }
+    TBDG_HIP(hipGetLastError());
+}
+
+int launch_amr_block_apply(hipStream_t st, int64_t nc, int nb, const float* Binv, const double* r,
+                           double* z, double* part) {
+    if (nc == 0) return 0;
+    const int cpb = 256 / nb;
+    const int G = (int)((nc + cpb - 1) / cpb);
+    switch (nb) {
+        case 1: hipLaunchKernelGGL((k_amr_block_apply<1>), dim3(G), dim3(256), 0, st, nc, Binv, r, z, part); break;
+        case 4: hipLaunchKernelGGL((k_amr_block_apply<4>), dim3(G), dim3(256), 0, st, nc, Binv, r, z, part); break;
+        case 9: hipLaunchKernelGGL((k_amr_block_apply<9>), dim3(G), dim3(256), 0, st, nc, Binv, r, z, part); break;
+        case 16: hipLaunchKernelGGL((k_amr_block_apply<16>), dim3(G), dim3(256), 0, st, nc, Binv, r, z, part); break;
+        default: throw Error(TBDG_EUNSUPPORTED, "cell blocks up to 16 pressure nodes");
+    }
+    TBDG_HIP(hipGetLastError());
+    return G;
+}
+
+void launch_amr_cg_xr(hipStream_t st, int64_t n, const double* rz, const double* pq, const double* p,
+                      const double* q, double* x, double* r) {
+    if (n == 0) return;
+    hipLaunchKernelGGL(k_amr_cg_xr, dim3(blocks(n)), dim3(256), 0, st, n, rz, pq, p, q, x, r);
     TBDG_HIP(hipGetLastError());
 }
 

@@ -61,6 +61,19 @@ struct XferMap {
 void launch_amr_pressure(hipStream_t st, const Geo& g, const Tab1& t, double alpha, const double* p,
                          double* y, bool diag, double* part = nullptr);
 int amr_pressure_blocks(const Geo& g, const Tab1& t);
+// mode 0 apply, 1 diagonal, 2 the cell-local part (exterior traces zero)
+void launch_amr_pressure_mode(hipStream_t st, const Geo& g, const Tab1& t, double alpha,
+                              const double* p, double* y, int mode, double* part);
+// cell-block Jacobi of the pressure operator (blocks of 1, 4, 9 or 16 nodes):
+// build FP32 block inverses (u, y: pressure-size scratch, B: FP64 blocks),
+// apply z = B^{-1} r with block partials of r.z and r.r (returns the grid)
+bool amr_block_ok(int nb);
+void launch_amr_block_build(hipStream_t st, const Geo& g, const Tab1& t, double alpha, double* u,
+                            double* y, double* B, float* Binv);
+int launch_amr_block_apply(hipStream_t st, int64_t nc, int nb, const float* Binv, const double* r,
+                           double* z, double* part);
+void launch_amr_cg_xr(hipStream_t st, int64_t n, const double* rz, const double* pq, const double* p,
+                      const double* q, double* x, double* r);
 // x += al p, r -= al q, z = r / d (al = *rz / *pq), block partials of r.z and
 // r.r in part[0..G), part[G..2G)
 void launch_amr_cg_step(hipStream_t st, int64_t n, const double* rz, const double* pq, const double* p,
