@@ -170,29 +170,76 @@ template <int DIM, int N>
 __global__ __launch_bounds__(256) void k_add_grad_p(Geom g, Tables t, const double* x, double a,
                                                      const double* __restrict__ p, double* y,
                                                      int64_t Nc) {
+    // y = x + a grad p at the velocity nodes, sum-factorised: each thread
+    // takes its node's rows of the 1D pressure basis (values I, derivatives
+    // D) once and contracts the cell's pressure direction by direction
     constexpr int NP = N - 1;
     constexpr int NB = ipow(N, DIM);
     constexpr int NBP = ipow(NP, DIM);
     using Lay = Layout<DIM, N>;
-    using LayP = Layout<DIM, NP>;
     const int64_t gid = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (gid >= Nc * NB) return;
     const int64_t cell = gid / NB;
     const int nd = (int)(gid % NB);
     const double* pc = p + cell * NBP;
-    for (int c = 0; c < DIM; ++c) {
-        double v = 0.0;
-        for (int j = 0; j < NBP; ++j) {
-            double b = 1.0;
-            for (int e = 0; e < DIM; ++e) {
-                const int ie = Lay::coord(nd, e), je = LayP::coord(j, e);
-                b *= (e == c) ? t.Dpu[ie * NMAX + je] : t.Ip[ie * NMAX + je];
-            }
-            v += b * pc[j];
+    double I[DIM][NP], D[DIM][NP];
+#pragma unroll
+    for (int e = 0; e < DIM; ++e) {
+        const int ie = Lay::coord(nd, e);
+#pragma unroll
+        for (int j = 0; j < NP; ++j) {
+            I[e][j] = t.Ip[ie * NMAX + j];
+            D[e][j] = t.Dpu[ie * NMAX + j];
         }
+    }
+    double gr[DIM];
+    if (DIM == 2) {
+        double gx = 0.0, gy = 0.0;
+#pragma unroll
+        for (int jy = 0; jy < NP; ++jy) {
+            double sd = 0.0, si = 0.0;
+#pragma unroll
+            for (int jx = 0; jx < NP; ++jx) {
+                const double pv = pc[jx + NP * jy];
+                sd += D[0][jx] * pv;
+                si += I[0][jx] * pv;
+            }
+            gx += I[1][jy] * sd;
+            gy += D[1][jy] * si;
+        }
+        gr[0] = gx;
+        gr[1] = gy;
+    } else {
+        double gx = 0.0, gy = 0.0, gz = 0.0;
+#pragma unroll
+        for (int jz = 0; jz < NP; ++jz) {
+            double tx = 0.0, ty = 0.0, ti = 0.0;
+#pragma unroll
+            for (int jy = 0; jy < NP; ++jy) {
+                double sd = 0.0, si = 0.0;
+#pragma unroll
+                for (int jx = 0; jx < NP; ++jx) {
+                    const double pv = pc[jx + NP * (jy + NP * jz)];
+                    sd += D[0][jx] * pv;
+                    si += I[0][jx] * pv;
+                }
+                tx += I[1][jy] * sd;
+                ty += D[1][jy] * si;
+                ti += I[1][jy] * si;
+            }
+            gx += I[DIM - 1][jz] * tx;
+            gy += I[DIM - 1][jz] * ty;
+            gz += D[DIM - 1][jz] * ti;
+        }
+        gr[0] = gx;
+        gr[1] = gy;
+        gr[DIM - 1] = gz;
+    }
+#pragma unroll
+    for (int c = 0; c < DIM; ++c) {
         const int64_t idx = (cell * DIM + c) * NB + nd;
         const double xv = x ? x[idx] : 0.0;
-        y[idx] = xv + a * v / g.h[c];
+        y[idx] = xv + a * gr[c] / g.h[c];
     }
 }
 
