@@ -243,7 +243,7 @@ tbdg_status tbdg_create(const tbdg_mesh_desc* mesh, const tbdg_disc_desc* disc, 
         c->invd_p[1] = dalloc(c->Np);
         c->invd_p[2] = dalloc(c->Np);
         void* h = nullptr;
-        TBDG_HIP(hipHostMalloc(&h, sizeof(double) * 512, hipHostMallocCoherent | hipHostMallocMapped));
+        TBDG_HIP(hipHostMalloc(&h, sizeof(double) * 2048, hipHostMallocCoherent | hipHostMallocMapped));
         c->host_out = static_cast<double*>(h);
         void* hd = nullptr;
         TBDG_HIP(hipHostGetDevicePointer(&hd, h, 0));

@@ -518,7 +518,7 @@ void mg_build(tbdg_ctx* c, MGData& M, const tbdg_mg_desc* desc) {
         // (K 1 = 0) of the BF16 cycle's correction
         M.z = mg_alloc<double>(&M, M.n0);
         M.zpart = mg_alloc<double>(&M, 2 * (int64_t)level_blocks(c->dim, M.lv[0]));
-        M.rpart = mg_alloc<double>(&M, 1024);
+        M.rpart = mg_alloc<double>(&M, 2048);
         M.mones = mg_alloc<double>(&M, M.n0);
         M.dsum = mg_alloc<double>(&M, 3 * 256);
         double* ones = mg_alloc<double>(&M, M.n0);

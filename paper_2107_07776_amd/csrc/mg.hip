@@ -897,8 +897,9 @@ template <typename S>
 int launch_mg_prep(hipStream_t st, int64_t n, int update, const double* pa, int Ga, double* sc,
                    int slot, double* x, double* r, const double* p, const double* q, S* b0, S* d0,
                    const float* invd, float c2, double* partial) {
-    // at most 256 partials: the host adds them from a 512-entry pinned buffer
-    const unsigned G = gs_grid(n) < 256u ? gs_grid(n) : 256u;
+    // at most 1024 partials (gs_grid's cap): the host adds them from its
+    // 2048-entry pinned buffer; 1024 blocks keep four per CU streaming
+    const unsigned G = gs_grid(n);
     hipLaunchKernelGGL((k_mg_prep<S>), dim3(G), dim3(256), 0, st, n, update, pa, Ga, sc, slot, x,
                        r, p, q, b0, d0, invd, c2, partial);
     TBDG_HIP(hipGetLastError());
