@@ -918,10 +918,13 @@ tbdg_status tbdg_amr_solve_pressure(tbdg_amr* m, double alpha, const double* b, 
         const int64_t n = m->Np();
         if (n > m->cg_cap) {
             devfree(m->cg);
-            m->cg = devalloc<double>(5 * n);
+            m->cg = devalloc<double>(6 * n);
             m->cg_cap = n;
         }
-        double *r = m->cg, *z = r + n, *p = z + n, *q = p + n, *d = q + n;
+        // two direction buffers: the operator forms the new direction from
+        // the old one while other blocks still read the old one
+        double *r = m->cg, *z = r + n, *q = z + n, *d = q + n;
+        double* P[2] = {d + n, d + 2 * n};
         double* rz[2] = {m->scal, m->scal + 1};
         double* pq = m->scal + 2;
         const hipStream_t st = m->stream;
@@ -942,7 +945,7 @@ tbdg_status tbdg_amr_solve_pressure(tbdg_amr* m, double alpha, const double* b, 
                 m->blk_cap = nbb;
             }
             A::launch_amr_block_build(st, g, m->tp, alpha, z, q, m->blk, m->blkinv);
-            const int64_t gb = 2 * ((nc + 256 / nbp - 1) / (256 / nbp));
+            const int64_t gb = 2 * (int64_t)A::amr_block_grid(nc, nbp);
             if (gb > m->bpart_cap) {
                 devfree(m->bpart);
                 m->bpart = devalloc<double>(gb);
@@ -969,11 +972,12 @@ tbdg_status tbdg_amr_solve_pressure(tbdg_amr* m, double alpha, const double* b, 
             A::launch_amr_div(st, n, r, d, z);
             A::launch_amr_dot(st, n, r, z, m->part, DOT_BLOCKS, rz[0]);
         }
-        TBDG_HIP(hipMemcpyAsync(p, z, sizeof(double) * n, hipMemcpyDeviceToDevice, st));
-        // per iteration: the operator with its p.q block sums, one fused
-        // update with the r.z and r.r block sums, the direction; all scalars
-        // stay on the device and the host reads p.q and r.r every kCheck
-        // iterations
+        // per iteration: the operator fused with the new direction, then the
+        // update of x and r fused with the preconditioner.  Each writes block
+        // partials of its dot products; when they are few, the next kernel
+        // sums them itself (the operator stores r.z for the update), else a
+        // one-block kernel sums them in between.  All scalars stay on the
+        // device and the host reads p.q and r.r every kCheck iterations.
         constexpr int kCheck = 8;
         const int Gp = A::amr_pressure_blocks(g, m->tp);
         if (Gp > m->ppart_cap) {
@@ -982,8 +986,12 @@ tbdg_status tbdg_amr_solve_pressure(tbdg_amr* m, double alpha, const double* b, 
             m->ppart_cap = Gp;
         }
         double* rr = m->scal + 3;
+        constexpr int kFusedSums = 1024;
+        const int Grz = blk ? A::amr_block_grid(nc, nbp) : DOT_BLOCKS / 2;
+        double* rzpart = blk ? m->bpart : m->part;
+        const bool fused = Gp <= kFusedSums && Grz <= kFusedSums;
         tbdg_status status = TBDG_ENOTCONV;
-        int it = 0, cur = 0;
+        int it = 0, cur = 0, pb = 0;
         for (;;) {
             if (!std::isfinite(res)) {
                 status = TBDG_ENAN;
@@ -996,18 +1004,34 @@ tbdg_status tbdg_amr_solve_pressure(tbdg_amr* m, double alpha, const double* b, 
             if (it >= maxiter) break;
             const int stop = std::min(maxiter, it + kCheck);
             for (; it < stop; ++it) {
-                A::launch_amr_pressure(st, g, m->tp, alpha, p, q, false, m->ppart);
-                A::launch_amr_finish(st, m->ppart, Gp, 1, pq, nullptr);
-                if (blk) {
-                    A::launch_amr_cg_xr(st, n, rz[cur], pq, p, q, x, r);
-                    const int gb = A::launch_amr_block_apply(st, nc, nbp, m->blkinv, r, z, m->bpart);
-                    A::launch_amr_finish(st, m->bpart, gb, 2, rz[1 - cur], rr);
-                } else {
-                    A::launch_amr_cg_step(st, n, rz[cur], pq, p, q, d, x, r, z, m->part, DOT_BLOCKS / 2);
-                    A::launch_amr_finish(st, m->part, DOT_BLOCKS / 2, 2, rz[1 - cur], rr);
+                // p_it = z + (rz_it / rz_{it-1}) p_{it-1}, the first one z
+                // rz[cur] holds r.z of this iteration (or receives it from the
+                // operator kernel), rz[1 - cur] that of the previous one
+                const bool first = it == 0;
+                A::CgDir dir{first ? z : P[pb], P[1 - pb], rz[cur], nullptr, 0,
+                             first ? nullptr : rz[1 - cur], nullptr};
+                if (fused && !first) {
+                    dir.rz_part = rzpart;
+                    dir.rz_G = Grz;
+                    dir.rz_store = rz[cur];
                 }
-                A::launch_amr_cg_dir(st, n, rz[1 - cur], rz[cur], z, p);
+                A::launch_amr_pressure_dir(st, g, m->tp, alpha, z, dir, q, m->ppart);
+                pb = 1 - pb;
+                A::CgUpdate up{rz[cur], pq, nullptr, 0, P[pb], q, x};
+                if (fused) {
+                    up.pq_part = m->ppart;
+                    up.pq_G = Gp;
+                } else {
+                    A::launch_amr_finish(st, m->ppart, Gp, 1, pq, nullptr);
+                }
+                if (blk) A::launch_amr_block_xr(st, nc, nbp, m->blkinv, up, r, z, m->bpart);
+                else A::launch_amr_cg_step(st, n, up, d, r, z, m->part, DOT_BLOCKS / 2);
+                if (!fused) A::launch_amr_finish(st, rzpart, Grz, 2, rz[1 - cur], rr);
                 cur = 1 - cur;
+            }
+            if (fused) {
+                A::launch_amr_finish(st, m->ppart, Gp, 1, pq, nullptr);
+                A::launch_amr_finish(st, rzpart + Grz, Grz, 1, rr, nullptr);
             }
             TBDG_HIP(hipMemcpyAsync(m->host, pq, 2 * sizeof(double), hipMemcpyDeviceToHost, st));
             TBDG_HIP(hipStreamSynchronize(st));

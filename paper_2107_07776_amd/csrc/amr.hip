@@ -33,17 +33,44 @@ __device__ inline int nd2(int a, int m, int t) {
     return a == 0 ? m + NP * t : t + NP * m;
 }
 
+// The sum of part[0..G) in every thread of the block, in the order of
+// k_amr_finish2 (so bitwise its result): a kernel that consumes a reduction
+// of few partials sums them itself instead of waiting for a one-block
+// kernel.  Every thread of the block must call it.
+__device__ inline double sum_all(const double* part, int G) {
+    __shared__ double s_v;
+    double a = 0.0;
+    for (int i = threadIdx.x; i < G; i += 256) a += part[i];
+    a = red::block_sum(a);
+    if (threadIdx.x == 0) s_v = a;
+    __syncthreads();
+    return s_v;
+}
+
+// The operand of the pressure kernel at entry i: p itself, or, for the
+// fused CG direction, p_new = z + beta p_old formed on the fly
+template <bool DIR>
+struct Operand {
+    const double* __restrict__ z;
+    const double* __restrict__ pold;
+    double beta;
+    __device__ double operator()(size_t i) const {
+        if constexpr (DIR) return z[i] + beta * pold[i];
+        return z[i];
+    }
+};
+
 // value and reference normal derivative of cell's trace at side `side` of
 // direction a, on the grid line through tangential node tt
-template <int NP>
-__device__ inline void trace(const double* __restrict__ p, const Tab1& t, int cell, int a, int side,
-                             int tt, double& v, double& d) {
+template <int NP, class S>
+__device__ inline void trace(const S& p, const Tab1& t, int cell, int a, int side, int tt, double& v,
+                             double& d) {
     constexpr int NB = NP * NP;
     v = 0.0;
     d = 0.0;
 #pragma unroll
     for (int m = 0; m < NP; ++m) {
-        const double pv = p[(size_t)cell * NB + nd2<NP>(a, m, tt)];
+        const double pv = p((size_t)cell * NB + nd2<NP>(a, m, tt));
         v += t.L[side][m] * pv;
         d += t.dL[side][m] * pv;
     }
@@ -52,12 +79,27 @@ __device__ inline void trace(const double* __restrict__ p, const Tab1& t, int ce
 // y = (alpha M + K) p, or its diagonal (DIAG)
 // MODE 0: y = H p; 1: y = diag(H); 2: y = H_own p, the cell-local part of
 // H (the exterior traces set to zero): applied to a field that is one unit
-// node per cell it returns one column of every cell's diagonal block
+// node per cell it returns one column of every cell's diagonal block;
+// 3: the CG direction and its product in one pass: p holds z, the new
+// direction z + beta p_old (beta = r.z / rz_old, 0 when rz_old is null;
+// r.z the scalar *rz_new or the sum of the partials rz_part, which block 0
+// then stores in rz_store) is formed for the cell's own nodes, written to
+// dir.pnew, and formed again wherever a neighbour's trace reads it;
+// y = H p_new.  MODE 0 and 3 write the per-block partial sums of p . y into
+// part when it is not null.
 template <int NP, int MODE>
 __global__ __launch_bounds__(256) void k_amr_pressure(Geo g, Tab1 t, double alpha,
                                                       const double* __restrict__ p,
-                                                      double* __restrict__ y, double* part) {
+                                                      double* __restrict__ y, double* part, CgDir dir) {
     constexpr bool DIAG = MODE == 1;
+    constexpr bool EXT = MODE == 0 || MODE == 3;
+    double beta = 0.0;
+    if (MODE == 3) {
+        const double rz = dir.rz_part ? sum_all(dir.rz_part, dir.rz_G) : (dir.rz_old ? *dir.rz_new : 0.0);
+        if (dir.rz_old) beta = rz / *dir.rz_old;
+        if (dir.rz_store && blockIdx.x == 0 && threadIdx.x == 0) *dir.rz_store = rz;
+    }
+    const Operand<MODE == 3> src{p, (MODE == 3 && dir.rz_old) ? dir.pold : p, beta};
     constexpr int NB = NP * NP;
     constexpr int CPB = 256 / NB;
     __shared__ double s_p[CPB * NB];
@@ -69,27 +111,28 @@ __global__ __launch_bounds__(256) void k_amr_pressure(Geo g, Tab1 t, double alph
     const int cell0 = lines::xcd_block(blockIdx.x, gridDim.x) * CPB;
     const int cell = cell0 + lc;
     const bool active = lc < CPB && cell < g.Nc;
-    if (lc < CPB) s_p[tid] = (active && !DIAG) ? p[(size_t)cell * NB + nd] : 0.0;
+    if (lc < CPB) s_p[tid] = (active && !DIAG) ? src((size_t)cell * NB + nd) : 0.0;
+    if (MODE == 3 && active) dir.pnew[(size_t)cell * NB + nd] = s_p[tid];
     // exterior traces at every face node of the block's cells
     for (int it = tid; it < CPB * 4 * NP; it += 256) {
         const int c2 = it / (4 * NP), f = (it / NP) % 4, tt = it % NP;
         const int cl = cell0 + c2;
         double ve = 0.0, de = 0.0;
-        if (MODE == 0 && cl < g.Nc) {
+        if (EXT && cl < g.Nc) {
             const int meta = g.meta[cl * 4 + f];
             const int kind = meta & 15, half = meta >> 4;
             const int a = f >> 1, s = f & 1, so = 1 - s;
             const int own = g.level[cl];
             if (kind == FACE_SAME) {
                 const int nb = g.nbr[cl * 8 + f * 2];
-                trace<NP>(p, t, nb, a, so, tt, ve, de);
+                trace<NP>(src, t, nb, a, so, tt, ve, de);
                 de *= (double)(1 << own) / g.H[a];
             } else if (kind == FACE_COARSER) {
                 const int nb = g.nbr[cl * 8 + f * 2];
 #pragma unroll
                 for (int m = 0; m < NP; ++m) {
                     double v, d;
-                    trace<NP>(p, t, nb, a, so, m, v, d);
+                    trace<NP>(src, t, nb, a, so, m, v, d);
                     ve += t.T[half][tt * NP + m] * v;
                     de += t.T[half][tt * NP + m] * d;
                 }
@@ -100,7 +143,7 @@ __global__ __launch_bounds__(256) void k_amr_pressure(Geo g, Tab1 t, double alph
 #pragma unroll
                     for (int q = 0; q < NP; ++q) {
                         double v, d;
-                        trace<NP>(p, t, nb, a, so, q, v, d);
+                        trace<NP>(src, t, nb, a, so, q, v, d);
                         const double wq = 0.5 * t.W[q] * t.T[h][q * NP + tt];
                         ve += wq * v;
                         de += wq * d;
@@ -185,7 +228,7 @@ __global__ __launch_bounds__(256) void k_amr_pressure(Geo g, Tab1 t, double alph
         py = own * v;
     }
     // optional per-block partial sum of p . y (the CG step length)
-    if (MODE == 0 && part) {
+    if (EXT && part) {
         py = red::block_sum(py);
         if (threadIdx.x == 0) part[blockIdx.x] = py;
     }
@@ -1017,18 +1060,33 @@ __global__ __launch_bounds__(64) void k_amr_block_inv(int64_t nc, const double* 
 }
 
 // z = B^{-1} r per cell (FP32 blocks, FP64 vectors and sums); block partial
-// sums of r.z and r.r in part[b], part[G + b]
-template <int NBK>
+// sums of r.z and r.r in part[b], part[G + b].  XR: the CG update comes
+// first, x += al p and r -= al q with al = *xr.rz / p.q (the scalar *xr.pq
+// or the sum of the partials xr.pq_part), and z is formed from the updated r
+template <int NBK, bool XR>
 __global__ __launch_bounds__(256) void k_amr_block_apply(int64_t nc, const float* __restrict__ Binv,
-                                                         const double* __restrict__ r,
-                                                         double* __restrict__ z, double* part) {
+                                                         double* __restrict__ r,
+                                                         double* __restrict__ z, double* part,
+                                                         CgUpdate xr) {
     constexpr int CPB = 256 / NBK;
     __shared__ double s_r[CPB * NBK];
     const int tid = threadIdx.x;
     const int lc = tid / NBK, i = tid % NBK;
     const int64_t c = (int64_t)blockIdx.x * CPB + lc;
     const bool act = lc < CPB && c < nc;
-    if (lc < CPB) s_r[tid] = act ? r[c * NBK + i] : 0.0;
+    double al = 0.0;
+    if (XR) al = *xr.rz / (xr.pq_part ? sum_all(xr.pq_part, xr.pq_G) : *xr.pq);
+    double rv = 0.0;
+    if (act) {
+        const int64_t k = c * NBK + i;
+        rv = r[k];
+        if (XR) {
+            xr.x[k] += al * xr.p[k];
+            rv -= al * xr.q[k];
+            r[k] = rv;
+        }
+    }
+    if (lc < CPB) s_r[tid] = rv;
     __syncthreads();
     double rz = 0.0, rr = 0.0;
     if (act) {
@@ -1048,31 +1106,18 @@ __global__ __launch_bounds__(256) void k_amr_block_apply(int64_t nc, const float
     }
 }
 
-// x += al p, r -= al q (al = *rz / *pq)
-__global__ __launch_bounds__(256) void k_amr_cg_xr(int64_t n, const double* rz, const double* pq,
-                                                   const double* __restrict__ p,
-                                                   const double* __restrict__ q,
-                                                   double* __restrict__ x, double* __restrict__ r) {
-    const int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
-    if (i >= n) return;
-    const double al = *rz / *pq;
-    x[i] += al * p[i];
-    r[i] -= al * q[i];
-}
-
-// x += al p, r -= al q, z = r / d, al = *rz / *pq; per-block partial sums
-// of r.z and r.r (grid-stride over a fixed grid)
-__global__ __launch_bounds__(256) void k_amr_cg_step(int64_t n, const double* rz, const double* pq,
-                                                     const double* __restrict__ p,
-                                                     const double* __restrict__ q,
+// x += al p, r -= al q, z = r / d, al = *u.rz / p.q (the scalar *u.pq or
+// the sum of the partials u.pq_part); per-block partial sums of r.z and r.r
+// (grid-stride over a fixed grid)
+__global__ __launch_bounds__(256) void k_amr_cg_step(int64_t n, CgUpdate u,
                                                      const double* __restrict__ d,
-                                                     double* __restrict__ x, double* __restrict__ r,
+                                                     double* __restrict__ r,
                                                      double* __restrict__ z, double* part) {
-    const double al = *rz / *pq;
+    const double al = *u.rz / (u.pq_part ? sum_all(u.pq_part, u.pq_G) : *u.pq);
     double a = 0.0, b = 0.0;
     for (int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x; i < n; i += (int64_t)gridDim.x * 256) {
-        x[i] += al * p[i];
-        const double ri = r[i] - al * q[i];
+        u.x[i] += al * u.p[i];
+        const double ri = r[i] - al * u.q[i];
         const double zi = ri / d[i];
         r[i] = ri;
         z[i] = zi;
@@ -1101,15 +1146,6 @@ __global__ __launch_bounds__(256) void k_amr_finish2(const double* part, int G, 
         *out0 = a;
         if (rows > 1) *out1 = b;
     }
-}
-
-__global__ __launch_bounds__(256) void k_amr_cg_dir(int64_t n, const double* rz_new,
-                                                    const double* rz_old,
-                                                    const double* __restrict__ z,
-                                                    double* __restrict__ p) {
-    const int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
-    if (i >= n) return;
-    p[i] = z[i] + (*rz_new / *rz_old) * p[i];
 }
 
 // z = r / d elementwise; z may alias r
@@ -1164,17 +1200,29 @@ void launch_amr_pressure(hipStream_t st, const Geo& g, const Tab1& t, double alp
 
 void launch_amr_pressure_mode(hipStream_t st, const Geo& g, const Tab1& t, double alpha,
                               const double* p, double* y, int mode, double* part) {
+    launch_amr_pressure_any(st, g, t, alpha, p, y, mode, part, CgDir{});
+}
+
+void launch_amr_pressure_dir(hipStream_t st, const Geo& g, const Tab1& t, double alpha, const double* z,
+                             const CgDir& dir, double* q, double* part) {
+    launch_amr_pressure_any(st, g, t, alpha, z, q, 3, part, dir);
+}
+
+void launch_amr_pressure_any(hipStream_t st, const Geo& g, const Tab1& t, double alpha, const double* p,
+                             double* y, int mode, double* part, const CgDir& dir) {
     if (g.Nc == 0) return;
 #define TBDG_AMR_P(NPV)                                                                       \
     case NPV: {                                                                               \
         constexpr int CPB = 256 / (NPV * NPV);                                                \
         const int G = (g.Nc + CPB - 1) / CPB;                                                 \
         if (mode == 1) hipLaunchKernelGGL((k_amr_pressure<NPV, 1>), dim3(G), dim3(256), 0, st, g, \
-                                          t, alpha, p, y, nullptr);                          \
+                                          t, alpha, p, y, nullptr, dir);                     \
         else if (mode == 2) hipLaunchKernelGGL((k_amr_pressure<NPV, 2>), dim3(G), dim3(256), 0, st, \
-                                               g, t, alpha, p, y, nullptr);                  \
+                                               g, t, alpha, p, y, nullptr, dir);             \
+        else if (mode == 3) hipLaunchKernelGGL((k_amr_pressure<NPV, 3>), dim3(G), dim3(256), 0, st, \
+                                               g, t, alpha, p, y, part, dir);                \
         else hipLaunchKernelGGL((k_amr_pressure<NPV, 0>), dim3(G), dim3(256), 0, st, g, t, alpha, \
-                                p, y, part);                                                 \
+                                p, y, part, dir);                                            \
         break;                                                                                \
     }
     switch (t.n) {
@@ -1394,45 +1442,58 @@ void launch_amr_block_build(hipStream_t st, const Geo& g, const Tab1& t, double 
     TBDG_HIP(hipGetLastError());
 }
 
-int launch_amr_block_apply(hipStream_t st, int64_t nc, int nb, const float* Binv, const double* r,
-                           double* z, double* part) {
-    if (nc == 0) return 0;
+int amr_block_grid(int64_t nc, int nb) {
     const int cpb = 256 / nb;
-    const int G = (int)((nc + cpb - 1) / cpb);
+    return (int)((nc + cpb - 1) / cpb);
+}
+
+namespace {
+
+int block_apply(hipStream_t st, int64_t nc, int nb, const float* Binv, double* r, double* z, double* part,
+                const CgUpdate* xr) {
+    if (nc == 0) return 0;
+    const int G = amr_block_grid(nc, nb);
+    const CgUpdate u = xr ? *xr : CgUpdate{};
+#define TBDG_AMR_B(NBV)                                                                       \
+    case NBV:                                                                                 \
+        if (xr) hipLaunchKernelGGL((k_amr_block_apply<NBV, true>), dim3(G), dim3(256), 0, st, nc, Binv, \
+                                   r, z, part, u);                                           \
+        else hipLaunchKernelGGL((k_amr_block_apply<NBV, false>), dim3(G), dim3(256), 0, st, nc, Binv, \
+                                r, z, part, u);                                              \
+        break;
     switch (nb) {
-        case 1: hipLaunchKernelGGL((k_amr_block_apply<1>), dim3(G), dim3(256), 0, st, nc, Binv, r, z, part); break;
-        case 4: hipLaunchKernelGGL((k_amr_block_apply<4>), dim3(G), dim3(256), 0, st, nc, Binv, r, z, part); break;
-        case 9: hipLaunchKernelGGL((k_amr_block_apply<9>), dim3(G), dim3(256), 0, st, nc, Binv, r, z, part); break;
-        case 16: hipLaunchKernelGGL((k_amr_block_apply<16>), dim3(G), dim3(256), 0, st, nc, Binv, r, z, part); break;
+        TBDG_AMR_B(1)
+        TBDG_AMR_B(4)
+        TBDG_AMR_B(9)
+        TBDG_AMR_B(16)
         default: throw Error(TBDG_EUNSUPPORTED, "cell blocks up to 16 pressure nodes");
     }
+#undef TBDG_AMR_B
     TBDG_HIP(hipGetLastError());
     return G;
 }
 
-void launch_amr_cg_xr(hipStream_t st, int64_t n, const double* rz, const double* pq, const double* p,
-                      const double* q, double* x, double* r) {
-    if (n == 0) return;
-    hipLaunchKernelGGL(k_amr_cg_xr, dim3(blocks(n)), dim3(256), 0, st, n, rz, pq, p, q, x, r);
-    TBDG_HIP(hipGetLastError());
+}  // namespace
+
+int launch_amr_block_apply(hipStream_t st, int64_t nc, int nb, const float* Binv, const double* r,
+                           double* z, double* part) {
+    // without the update the kernel only reads r
+    return block_apply(st, nc, nb, Binv, const_cast<double*>(r), z, part, nullptr);
 }
 
-void launch_amr_cg_step(hipStream_t st, int64_t n, const double* rz, const double* pq, const double* p,
-                        const double* q, const double* d, double* x, double* r, double* z, double* part,
-                        int G) {
-    hipLaunchKernelGGL(k_amr_cg_step, dim3(G), dim3(256), 0, st, n, rz, pq, p, q, d, x, r, z, part);
+int launch_amr_block_xr(hipStream_t st, int64_t nc, int nb, const float* Binv, const CgUpdate& xr,
+                        double* r, double* z, double* part) {
+    return block_apply(st, nc, nb, Binv, r, z, part, &xr);
+}
+
+void launch_amr_cg_step(hipStream_t st, int64_t n, const CgUpdate& u, const double* d, double* r,
+                        double* z, double* part, int G) {
+    hipLaunchKernelGGL(k_amr_cg_step, dim3(G), dim3(256), 0, st, n, u, d, r, z, part);
     TBDG_HIP(hipGetLastError());
 }
 
 void launch_amr_finish(hipStream_t st, const double* part, int G, int rows, double* out0, double* out1) {
     hipLaunchKernelGGL(k_amr_finish2, dim3(1), dim3(256), 0, st, part, G, rows, out0, out1);
-    TBDG_HIP(hipGetLastError());
-}
-
-void launch_amr_cg_dir(hipStream_t st, int64_t n, const double* rz_new, const double* rz_old,
-                       const double* z, double* p) {
-    if (n == 0) return;
-    hipLaunchKernelGGL(k_amr_cg_dir, dim3(blocks(n)), dim3(256), 0, st, n, rz_new, rz_old, z, p);
     TBDG_HIP(hipGetLastError());
 }
 

@@ -56,6 +56,35 @@ struct XferMap {
     int Nnew;
 };
 
+// The fused CG direction of the pressure operator: the operand is
+// p_new = z + beta p_old, beta = r.z / *rz_old (0 and p_old unread when
+// rz_old is null), written to pnew (which must not alias z or pold).  r.z
+// is *rz_new, or, when rz_part is not null, the sum of its rz_G partials,
+// which block 0 then stores in rz_store (if not null; rz_store must differ
+// from rz_old).
+struct CgDir {
+    const double* pold;
+    double* pnew;
+    const double* rz_new;
+    const double* rz_part;
+    int rz_G;
+    const double* rz_old;
+    double* rz_store;
+};
+
+// The CG update fused into the preconditioner: x += al p, r -= al q,
+// al = *rz / p.q with p.q the scalar *pq or, when pq_part is not null, the
+// sum of its pq_G partials
+struct CgUpdate {
+    const double* rz;
+    const double* pq;
+    const double* pq_part;
+    int pq_G;
+    const double* p;
+    const double* q;
+    double* x;
+};
+
 // part (may be null): per-block partial sums of p . y, amr_pressure_blocks
 // of them
 void launch_amr_pressure(hipStream_t st, const Geo& g, const Tab1& t, double alpha, const double* p,
@@ -64,6 +93,12 @@ int amr_pressure_blocks(const Geo& g, const Tab1& t);
 // mode 0 apply, 1 diagonal, 2 the cell-local part (exterior traces zero)
 void launch_amr_pressure_mode(hipStream_t st, const Geo& g, const Tab1& t, double alpha,
                               const double* p, double* y, int mode, double* part);
+// q = H p_new with p_new = z + beta p_old formed and stored on the way, and
+// the per-block partials of p_new . q in part
+void launch_amr_pressure_dir(hipStream_t st, const Geo& g, const Tab1& t, double alpha, const double* z,
+                             const CgDir& dir, double* q, double* part);
+void launch_amr_pressure_any(hipStream_t st, const Geo& g, const Tab1& t, double alpha, const double* p,
+                             double* y, int mode, double* part, const CgDir& dir);
 // cell-block Jacobi of the pressure operator (blocks of 1, 4, 9 or 16 nodes):
 // build FP32 block inverses (u, y: pressure-size scratch, B: FP64 blocks),
 // apply z = B^{-1} r with block partials of r.z and r.r (returns the grid)
@@ -72,13 +107,15 @@ void launch_amr_block_build(hipStream_t st, const Geo& g, const Tab1& t, double 
                             double* y, double* B, float* Binv);
 int launch_amr_block_apply(hipStream_t st, int64_t nc, int nb, const float* Binv, const double* r,
                            double* z, double* part);
-void launch_amr_cg_xr(hipStream_t st, int64_t n, const double* rz, const double* pq, const double* p,
-                      const double* q, double* x, double* r);
-// x += al p, r -= al q, z = r / d (al = *rz / *pq), block partials of r.z and
+// the grid of the block preconditioner (cells / (256 / nb) blocks)
+int amr_block_grid(int64_t nc, int nb);
+// the same after the CG update of x and r (returns the grid)
+int launch_amr_block_xr(hipStream_t st, int64_t nc, int nb, const float* Binv, const CgUpdate& xr,
+                        double* r, double* z, double* part);
+// the update u of x and r, then z = r / d, with block partials of r.z and
 // r.r in part[0..G), part[G..2G)
-void launch_amr_cg_step(hipStream_t st, int64_t n, const double* rz, const double* pq, const double* p,
-                        const double* q, const double* d, double* x, double* r, double* z, double* part,
-                        int G);
+void launch_amr_cg_step(hipStream_t st, int64_t n, const CgUpdate& u, const double* d, double* r,
+                        double* z, double* part, int G);
 // out0 = sum of part[0..G), out1 = sum of part[G..2G) when rows == 2
 void launch_amr_finish(hipStream_t st, const double* part, int G, int rows, double* out0, double* out1);
 // y_c = mc M u_c + tnu A u_c + th C(w) u_c, c = 0, 1; uD: wall data at the
@@ -115,9 +152,6 @@ void launch_amr_dot(hipStream_t st, int64_t n, const double* a, const double* b,
 // max |a - b| over G block partials in part, then into *out
 void launch_amr_maxdiff(hipStream_t st, int64_t n, const double* a, const double* b, double* part, int G,
                        double* out);
-// Jacobi PCG direction on device scalars: p = z + (*rz_new / *rz_old) p
-void launch_amr_cg_dir(hipStream_t st, int64_t n, const double* rz_new, const double* rz_old,
-                       const double* z, double* p);
 void launch_amr_div(hipStream_t st, int64_t n, const double* r, const double* d, double* z);
 
 }  // namespace amr

@@ -2,8 +2,8 @@
 oracle (oracle/adaptive.py): the same flags give the same forest cell for
 cell; the pressure Helmholtz operator, its diagonal, the indicator and the
 field transfer agree to FP64 rounding; the marking agrees flag for flag on
-the same indicator; the Jacobi CG solve reaches its tolerance and the
-oracle's direct solution."""
+the same indicator; the block- and point-Jacobi CG solves reach their
+tolerance and the oracle's direct solution."""
 import numpy as np
 import pytest
 import scipy.sparse.linalg as spla
@@ -72,7 +72,8 @@ def test_penalty_multiplier_and_alpha_zero():
         g.close()
 
 
-@pytest.mark.parametrize("seed,nc,per,k", CASES[:3])
+# k <= 4: cell-block Jacobi; k = 5 (25 nodes per cell): point Jacobi
+@pytest.mark.parametrize("seed,nc,per,k", CASES[:3] + [(4, (3, 2), (1, 0), 5)])
 def test_cg_solve_reaches_tolerance_and_direct_solution(seed, nc, per, k):
     g, f = _pair(seed, nc, per, k)
     try:
@@ -89,6 +90,29 @@ def test_cg_solve_reaches_tolerance_and_direct_solution(seed, nc, per, k):
         # a converged start returns at once
         info2 = g.solve_pressure(alpha, _t(b), x, tol=1e-9)
         assert info2["iters"] == 0
+    finally:
+        g.close()
+
+
+@pytest.mark.parametrize("k,base", [(3, (192, 160)), (5, (120, 96))])
+def test_cg_solve_above_the_in_kernel_reduction_size(k, base):
+    """Past 1024 blocks of partial sums the CG sums them with one-block
+    kernels between its two fused kernels instead of in the consumer; the
+    solve must still reach its tolerance in the true residual (the operator
+    itself is pinned at large sizes by the sampled-rows test)."""
+    from paper_2107_07776_amd import Adaptive
+    print(f"[case] amr large CG k={k} base={base}", flush=True)
+    g = Adaptive(base, (0.0, 0.0), (1.5, 1.0), k, 2, periodic=(1, 0))
+    try:
+        rng = np.random.default_rng(k)
+        g.adapt(rng.choice([0, 1], size=g.N_c, p=[0.85, 0.15]).astype(np.int8))
+        assert g.N_c * k * k > 1024 * 256       # more than 1024 operator blocks
+        b = _t(rng.standard_normal(g.N_p))
+        x = torch.zeros_like(b)
+        info = g.solve_pressure(3.0, b, x, tol=1e-10, maxiter=50000)
+        y = torch.empty_like(b)
+        g.apply_pressure(3.0, x, y)
+        assert (b - y).norm().item() <= 2e-10 * b.norm().item(), info
     finally:
         g.close()
 
