@@ -374,6 +374,11 @@ struct tbdg_ctx {
     double* map_gr = nullptr;
     trbdg::MGData* mg = nullptr;    // multigrid hierarchy (built on first use)
     trbdg::MGData* mgu = nullptr;   // velocity-component hierarchy (momentum solves, lazy)
+    // copies of it for components 1 and 2, whose V-cycles replay on their own
+    // streams beside component 0's (fork and join by events; lazy)
+    trbdg::MGData* mgu_side[2] = {nullptr, nullptr};
+    hipStream_t side_stream[2] = {nullptr, nullptr};
+    hipEvent_t ev_fork = nullptr, ev_join[2] = {nullptr, nullptr};
     bool mg_graphs = true;          // replay the solvers' V-cycles as captured HIP graphs
     int lineprec_stage = 0;         // stage the momentum line blocks were last built for
     bool reuse_lineprec = true;     // later fixed-point solves of a stage keep them

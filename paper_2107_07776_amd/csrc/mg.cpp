@@ -380,7 +380,7 @@ constexpr size_t kMaxGraphs = 16;   // captures kept per hierarchy
 // the host issues one call instead of one per kernel.  The cycle has no
 // memset, copy or host synchronisation, only kernels on the hierarchy's
 // own buffers and the outputs of the key.
-void vcycle_graph(tbdg_ctx* c, MGData& M, int s, int precision, const ZOut& zo) {
+void vcycle_graph(tbdg_ctx* c, MGData& M, int s, int precision, const ZOut& zo, hipStream_t launch) {
     VGraph* hit = nullptr;
     for (VGraph& g : M.graphs)
         if (g.s == s && g.prec == precision && g.z == zo.z && g.r64 == zo.r64 && g.q64 == zo.q64)
@@ -409,11 +409,11 @@ void vcycle_graph(tbdg_ctx* c, MGData& M, int s, int precision, const ZOut& zo) 
         M.graphs.push_back(VGraph{s, precision, zo.z, zo.r64, zo.q64, exec});
         hit = &M.graphs.back();
     }
-    TBDG_HIP(hipGraphLaunch(hit->exec, c->stream));
+    TBDG_HIP(hipGraphLaunch(hit->exec, launch));
 }
 
 void run_cycle(tbdg_ctx* c, MGData& M, int s, int precision, const ZOut& zo, bool graph) {
-    if (graph && c->mg_graphs) vcycle_graph(c, M, s, precision, zo);
+    if (graph && c->mg_graphs) vcycle_graph(c, M, s, precision, zo, c->stream);
     else vcycle_eager(c, M, s, precision, zo);
 }
 
@@ -447,11 +447,21 @@ void mg_free(tbdg_ctx* c) {
 }
 
 void mgu_free(tbdg_ctx* c) {
-    if (!c->mgu) return;
-    destroy_graphs(*c->mgu);
-    for (void* p : c->mgu->allocs) (void)hipFree(p);
-    delete c->mgu;
-    c->mgu = nullptr;
+    for (MGData** pm : {&c->mgu, &c->mgu_side[0], &c->mgu_side[1]}) {
+        if (!*pm) continue;
+        destroy_graphs(**pm);
+        for (void* p : (*pm)->allocs) (void)hipFree(p);
+        delete *pm;
+        *pm = nullptr;
+    }
+    for (int i = 0; i < 2; ++i) {
+        if (c->side_stream[i]) (void)hipStreamDestroy(c->side_stream[i]);
+        if (c->ev_join[i]) (void)hipEventDestroy(c->ev_join[i]);
+        c->side_stream[i] = nullptr;
+        c->ev_join[i] = nullptr;
+    }
+    if (c->ev_fork) (void)hipEventDestroy(c->ev_fork);
+    c->ev_fork = nullptr;
 }
 
 namespace {
@@ -665,9 +675,42 @@ void mg_apply_velocity(tbdg_ctx* c, int s, const double* v, const double* sc_dev
     const int nb = (int)(L.N / L.Nc);
     const float c2 = (float)(1.0 / L.theta[s]);
     const double scale = 1.0 / (c->theta[s] * c->nu);
-    for (int d = 0; d < c->dim; ++d) {
-        launch_vel_prep(c->stream, L.Nc, nb, c->dim, d, v, sc_dev, scale, L.b, L.d[0], L.invd[s], c2);
-        run_cycle(c, M, s, 1, ZOut{M.z + (int64_t)d * nb, c->dim * nb, nullptr, nullptr, nullptr}, true);
+    if (!c->mg_graphs) {
+        for (int d = 0; d < c->dim; ++d) {
+            launch_vel_prep(c->stream, L.Nc, nb, c->dim, d, v, sc_dev, scale, L.b, L.d[0], L.invd[s], c2);
+            run_cycle(c, M, s, 1, ZOut{M.z + (int64_t)d * nb, c->dim * nb, nullptr, nullptr, nullptr}, false);
+        }
+    } else {
+        // Each component has its own copy of the hierarchy (the same levels,
+        // coefficients and eigenvalue bounds, so bitwise the same cycle), and
+        // the cycles of components 1 and 2 replay on side streams beside
+        // component 0's: their coarse levels, a few workgroups each, overlap
+        // instead of queueing.  Every cycle writes its own interleaved slice
+        // of M.z.
+        for (int d = 1; d < c->dim; ++d) {
+            if (!c->mgu_side[d - 1]) c->mgu_side[d - 1] = mg_new(c, 1, &c->mg_desc);
+            if (!c->side_stream[d - 1])
+                TBDG_HIP(hipStreamCreateWithFlags(&c->side_stream[d - 1], hipStreamNonBlocking));
+            if (!c->ev_join[d - 1])
+                TBDG_HIP(hipEventCreateWithFlags(&c->ev_join[d - 1], hipEventDisableTiming));
+        }
+        if (!c->ev_fork) TBDG_HIP(hipEventCreateWithFlags(&c->ev_fork, hipEventDisableTiming));
+        MGData* H[3] = {&M, c->mgu_side[0], c->mgu_side[1]};
+        for (int d = 0; d < c->dim; ++d) {
+            MGLevel& Ld = H[d]->lv[0];
+            launch_vel_prep(c->stream, Ld.Nc, nb, c->dim, d, v, sc_dev, scale, Ld.b, Ld.d[0], Ld.invd[s], c2);
+        }
+        TBDG_HIP(hipEventRecord(c->ev_fork, c->stream));
+        for (int d = 0; d < c->dim; ++d) {
+            hipStream_t st = d == 0 ? c->stream : c->side_stream[d - 1];
+            if (d > 0) TBDG_HIP(hipStreamWaitEvent(st, c->ev_fork, 0));
+            vcycle_graph(c, *H[d], s, 1, ZOut{M.z + (int64_t)d * nb, c->dim * nb, nullptr, nullptr, nullptr},
+                         st);
+        }
+        for (int d = 1; d < c->dim; ++d) {
+            TBDG_HIP(hipEventRecord(c->ev_join[d - 1], c->side_stream[d - 1]));
+            TBDG_HIP(hipStreamWaitEvent(c->stream, c->ev_join[d - 1], 0));
+        }
     }
     if (accumulate) vec_axpby(c->stream, M.n0 * c->dim, 1.0, z, 1.0, M.z, z);
     else TBDG_HIP(hipMemcpyAsync(z, M.z, sizeof(double) * M.n0 * c->dim, hipMemcpyDeviceToDevice, c->stream));

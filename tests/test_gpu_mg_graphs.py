@@ -4,7 +4,9 @@ same kernels launched one by one.
 Each check replays the captured graphs several times, with other eager
 library work and host synchronisations between the replays, and compares
 every replay bit for bit with the kernel-by-kernel result of the same call:
-the momentum V-cycles (tbdg_mg_apply_momentum), the pressure flexible CG,
+the momentum V-cycles (tbdg_mg_apply_momentum; with graphs the components'
+cycles run side by side on their own streams, in 2D and 3D), the pressure
+flexible CG,
 the multigrid-preconditioned momentum GMRES and whole TR-BDF2 steps of the
 Kovasznay flow on Q1-mapped cells.
 """
@@ -48,6 +50,32 @@ def test_momentum_vcycles_replay_equals_eager():
         for rep in range(4):
             for stage in (1, 2):
                 v = torch.tensor(synthetic.random_vector(ctx.N_u, 10 + 3 * rep + stage), device="cuda")
+                ctx.set_mg_graphs(False)
+                ze = ctx.mg_apply_momentum(stage, v).clone()
+                _eager_work(ctx, u, p)
+                ctx.set_mg_graphs(True)
+                zg = ctx.mg_apply_momentum(stage, v)
+                torch.cuda.synchronize()
+                assert torch.equal(ze, zg), (rep, stage)
+                _eager_work(ctx, u, p)
+    finally:
+        ctx.close()
+
+
+def test_momentum_vcycles_replay_equals_eager_3d():
+    """In 3D the graphs of components 1 and 2 replay on two side streams
+    beside component 0's, each on its own copy of the hierarchy."""
+    from paper_2107_07776_amd import Context
+    print("[case] graphs 3D periodic cells=(8, 8, 8) k=2", flush=True)
+    ctx = Context(3, (8, 8, 8), (0.0, 0.0, 0.0), (1.0, 1.0, 1.0), k=2, nu=0.05, dt=0.05,
+                  periodic=(1, 1, 1))
+    try:
+        ctx.mg_setup(degree=4)
+        u = torch.tensor(synthetic.random_vector(ctx.N_u, 3), device="cuda")
+        p = torch.tensor(synthetic.random_vector(ctx.N_p, 4), device="cuda")
+        for rep in range(3):
+            for stage in (1, 2):
+                v = torch.tensor(synthetic.random_vector(ctx.N_u, 40 + 3 * rep + stage), device="cuda")
                 ctx.set_mg_graphs(False)
                 ze = ctx.mg_apply_momentum(stage, v).clone()
                 _eager_work(ctx, u, p)
