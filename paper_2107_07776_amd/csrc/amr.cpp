@@ -872,7 +872,10 @@ tbdg_status tbdg_amr_step(tbdg_amr* m, const tbdg_amr_step_opts* o, double* u, d
             const double bdt = T.beta(s) * m->dt;
             A::launch_amr_grad(st, m->geo(), m->tu, m->mx, us, bdt, p_prev, uss);
             rhs_pressure_amr(m, s, uss, p_prev, b);
-            TBDG_HIP(hipMemcpyAsync(p_out, p_prev, bp, hipMemcpyDeviceToDevice, st));
+            // initial guess: stage 1 starts from p^n; stage 2 from the line
+            // through p^n and p^{n+gamma}, evaluated at t^{n+1}
+            if (s == 1) TBDG_HIP(hipMemcpyAsync(p_out, p_prev, bp, hipMemcpyDeviceToDevice, st));
+            else trbdg::vec_axpby(st, np_, 1.0 / T.g, p_prev, -(1.0 - T.g) / T.g, p, p_out);
             const double alpha = std::isinf(m->c) ? 0.0 : 1.0 / (m->c * m->c * bdt * bdt);
             const tbdg_status rc = tbdg_amr_solve_pressure(m, alpha, b, p_out, o->prs_tol, o->prs_maxiter,
                                                            &loc[2 * (s - 1) + 1]);
