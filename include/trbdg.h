@@ -624,10 +624,11 @@ TBDG_API tbdg_status tbdg_amr_face_qpoints(const tbdg_amr* amr, int64_t* n_point
 TBDG_API tbdg_status tbdg_amr_apply_momentum(tbdg_amr* amr, double mc, double tnu, double th,
                                              const double* w, const double* u, const double* uD,
                                              double* y);
-/* Restarted GMRES(restart) for (mc M + tnu A + th C(w)) x = b (both
- * components in one Krylov space), right-preconditioned by the diagonal of
- * mc M + tnu A, modified Gram-Schmidt, FP64 throughout, from the given x to
- * a true residual ||b - A x|| <= tol ||b|| (checked at every restart).
+/* Restarted GMRES(restart), restart 1..60, for (mc M + tnu A + th C(w)) x = b
+ * (both components in one Krylov space), right-preconditioned by the
+ * diagonal of mc M + tnu A, classical Gram-Schmidt repeated once where
+ * cancellation is large, FP64 throughout, from the given x to a true
+ * residual ||b - A x|| <= tol ||b|| (checked at every restart).
  * Errors: TBDG_ENOTCONV, TBDG_EBREAKDOWN, TBDG_ENAN; x holds the last
  * iterate.                                                                  */
 TBDG_API tbdg_status tbdg_amr_solve_momentum(tbdg_amr* amr, double mc, double tnu, double th,
@@ -657,7 +658,7 @@ TBDG_API tbdg_status tbdg_amr_add_grad_p(tbdg_amr* amr, const double* x, double 
 typedef struct {
     int nonlinear;      /* momentum solves per stage (>= 1): fixed point      */
     double mom_tol, prs_tol;
-    int mom_maxiter, prs_maxiter, restart;   /* restart <= 0: 30            */
+    int mom_maxiter, prs_maxiter, restart;   /* restart <= 0: 30; max 60    */
 } tbdg_amr_step_opts;
 /* One TR-BDF2 step on the adapted mesh (the stages of tbdg_step: the
  * advecting velocity extrapolated from u and u_hist = u^{n-1+gamma}, the

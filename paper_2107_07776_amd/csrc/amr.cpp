@@ -19,6 +19,7 @@
 
 #include "amr.hpp"
 #include "internal.hpp"
+#include "krylov.hpp"
 
 using trbdg::Error;
 namespace A = trbdg::amr;
@@ -311,6 +312,8 @@ struct tbdg_amr {
     double* bpart = nullptr;     // block partials of the block-Jacobi apply
     int64_t bpart_cap = 0;
     double* scal = nullptr;      // device scalars: rz[2], pq, rr, bb
+    double* gdev = nullptr;      // GMRES: the Gram-Schmidt coefficients, w.w, |w'|^2, 1/|w'|
+    double* gpart = nullptr;     // GMRES: block partials of the multi-dots
     double* host = nullptr;      // pinned
     std::string last_error;
 
@@ -387,6 +390,8 @@ struct tbdg_amr {
         devfree(blkinv);
         devfree(bpart);
         devfree(scal);
+        devfree(gdev);
+        devfree(gpart);
         if (host) (void)hipHostFree(host);
         host = nullptr;
     }
@@ -395,6 +400,9 @@ struct tbdg_amr {
 namespace {
 
 constexpr int DOT_BLOCKS = 1024;
+constexpr int kGmMaxRestart = 60;   // the adaptive GMRES's largest basis
+constexpr int kGmBlocks = 256;      // blocks per vector of its multi-dots
+constexpr int kGmScalars = 72;      // device / pinned scalars (>= kGmMaxRestart + 4)
 
 template <class F>
 tbdg_status aguard(tbdg_amr* m, F&& f) {
@@ -538,7 +546,9 @@ tbdg_status tbdg_amr_create(const tbdg_amr_desc* d, void* hip_stream, tbdg_amr**
         mixtab(m->tu, m->tp, m->mx);
         m->part = devalloc<double>(DOT_BLOCKS);
         m->scal = devalloc<double>(8);
-        TBDG_HIP(hipHostMalloc((void**)&m->host, 8 * sizeof(double), hipHostMallocDefault));
+        m->gdev = devalloc<double>(kGmScalars);
+        m->gpart = devalloc<double>((int64_t)(kGmMaxRestart + 1) * kGmBlocks);
+        TBDG_HIP(hipHostMalloc((void**)&m->host, kGmScalars * sizeof(double), hipHostMallocDefault));
         m->upload();
         return TBDG_OK;
     });
@@ -646,7 +656,8 @@ tbdg_status tbdg_amr_solve_momentum(tbdg_amr* m, double mc, double tnu, double t
     if (!m) return TBDG_EINVAL;
     return aguard(m, [&]() {
         need(std::isfinite(mc) && std::isfinite(tnu) && std::isfinite(th), "coefficients must be finite");
-        need(tol > 0.0 && maxiter >= 0 && restart >= 1 && restart <= 200, "need tol > 0, restart 1..200");
+        need(tol > 0.0 && maxiter >= 0 && restart >= 1 && restart <= kGmMaxRestart,
+             "need tol > 0, restart 1..60");
         need(w && b && x, "null vector");
         need(m->n_bfaces == 0 || uD, "the mesh has walls: wall data uD needed");
         need(x != w && b != w && x != b, "x, b and w must be distinct");
@@ -668,6 +679,7 @@ tbdg_status tbdg_amr_solve_momentum(tbdg_amr* m, double mc, double tnu, double t
             A::launch_amr_momentum(st, g, m->tu, mc, tnu, th, w, in, uD, out);
         };
         A::launch_amr_momentum_diag(st, g, m->tu, mc, tnu, dg);
+        const int Gd = (int)std::min<int64_t>(kGmBlocks, std::max<int64_t>(1, (n + 255) / 256));
         tbdg_solve_info inf{0, 0.0, 0.0, 0, 0};
         const double bnorm = std::sqrt(dot(m, n, b, b, 4));
         if (bnorm == 0.0) {
@@ -707,13 +719,25 @@ tbdg_status tbdg_amr_solve_momentum(tbdg_amr* m, double mc, double tnu, double t
                 double* vn = V + (int64_t)(j + 1) * n;
                 A::launch_amr_div(st, n, vj, dg, z);
                 op(z, vn);
-                // modified Gram-Schmidt
-                for (int i = 0; i <= j; ++i) {
-                    const double hij = dot(m, n, vn, V + (int64_t)i * n, 2);
-                    H[(size_t)i * mr + j] = hij;
-                    trbdg::vec_axpby(st, n, 1.0, vn, -hij, V + (int64_t)i * n, vn);
+                // classical Gram-Schmidt: the dots with V_0..V_j and w.w in one
+                // pass, the update and |w'|^2 in another, one host read; a
+                // second pass when the norm fell below 1/sqrt(10) of its value
+                // (cancellation large enough to cost orthogonality)
+                double nn = 0.0;
+                for (int i = 0; i <= j; ++i) H[(size_t)i * mr + j] = 0.0;
+                for (int pass = 0; pass < 2; ++pass) {
+                    trbdg::kr_dots(st, n, j + 1, V, n, vn, m->gpart, Gd, m->gdev);
+                    trbdg::kr_update_norm(st, n, j + 1, V, n, m->gdev, vn, m->gpart, Gd, m->gdev + j + 2,
+                                          m->gdev + kGmScalars - 1);
+                    TBDG_HIP(hipMemcpyAsync(m->host, m->gdev, sizeof(double) * (j + 3), hipMemcpyDeviceToHost,
+                                            st));
+                    TBDG_HIP(hipStreamSynchronize(st));
+                    for (int i = 0; i <= j; ++i) H[(size_t)i * mr + j] += m->host[i];
+                    const double ww = m->host[j + 1];
+                    nn = m->host[j + 2];
+                    if (!(nn < 0.1 * ww)) break;
                 }
-                const double hn = std::sqrt(dot(m, n, vn, vn, 2));
+                const double hn = std::sqrt(nn);
                 H[(size_t)(j + 1) * mr + j] = hn;
                 for (int i = 0; i < j; ++i) {
                     const double t1 = cs[i] * H[(size_t)i * mr + j] + sn[i] * H[(size_t)(i + 1) * mr + j];

@@ -5,6 +5,7 @@
 // work-group adds the partials in a fixed order.  The grid size does not
 // depend on timing, so results are bitwise reproducible run to run.
 #include "internal.hpp"
+#include "krylov.hpp"
 #include "reduce.hpp"
 
 namespace trbdg {
@@ -289,7 +290,7 @@ __global__ __launch_bounds__(BS) void k_update_norm(int64_t n, int k, const doub
                                                     const double* h, const double* gsc, double* w,
                                                     double* partial) {
     __shared__ double s_cf[64];
-    for (int j = threadIdx.x; j < k; j += BS) s_cf[j] = h[j] * gsc[j];
+    for (int j = threadIdx.x; j < k; j += BS) s_cf[j] = gsc ? h[j] * gsc[j] : h[j];
     __syncthreads();
     double nn = 0.0;
     for (int64_t i = (int64_t)blockIdx.x * BS + threadIdx.x; i < n; i += (int64_t)gridDim.x * BS) {
@@ -341,7 +342,7 @@ __global__ __launch_bounds__(BS) void k_finish_gs(const double* partial, int G, 
     double acc = thread_sum(partial + (int64_t)j * G, G);
     acc = block_sum(acc);
     if (threadIdx.x == 0) {
-        const double v = j < k ? gsc[j] * acc : acc;
+        const double v = j < k && gsc ? gsc[j] * acc : acc;
         out[j] = v;
         if (hout) {
             hout[j] = v;
@@ -503,6 +504,20 @@ void gm_restart(tbdg_ctx* c, int64_t n, int k, double* V, int64_t ldv, const dou
                        y, cr, gsc, invd, x, part, xcomb);
     hipLaunchKernelGGL(k_finish_inv_norm, dim3(1), dim3(BS), 0, c->stream, part, G, dev_nn, gsc0,
                        host_mirror(c, dev_nn));
+    TBDG_HIP(hipGetLastError());
+}
+
+void kr_dots(hipStream_t st, int64_t n, int k, const double* V, int64_t ldv, const double* w,
+             double* part, int G, double* out) {
+    hipLaunchKernelGGL(k_mdot8, dim3(G, (k + 7) / 8), dim3(BS), 0, st, n, k, V, ldv, w, part);
+    hipLaunchKernelGGL(k_finish_gs, dim3(k + 1), dim3(BS), 0, st, part, G, k, nullptr, out, nullptr);
+    TBDG_HIP(hipGetLastError());
+}
+
+void kr_update_norm(hipStream_t st, int64_t n, int k, const double* V, int64_t ldv, const double* h,
+                    double* w, double* part, int G, double* nn, double* inv) {
+    hipLaunchKernelGGL(k_update_norm, dim3(G), dim3(BS), 0, st, n, k, V, ldv, h, nullptr, w, part);
+    hipLaunchKernelGGL(k_finish_inv_norm, dim3(1), dim3(BS), 0, st, part, G, nn, inv, nullptr);
     TBDG_HIP(hipGetLastError());
 }
 

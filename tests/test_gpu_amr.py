@@ -276,6 +276,9 @@ def test_momentum_gmres_reaches_tolerance_and_direct_solution(seed, nc, per, k):
         b = synthetic.random_vector(ad.N_u, 800 + seed)
         mc, tnu, th = 1.0 / (0.5858 * 0.02), 0.005, 0.5
         x = torch.zeros(ad.N_u, dtype=torch.float64, device="cuda")
+        with pytest.raises(RuntimeError):     # the basis holds at most 60 vectors
+            g.solve_momentum(mc, tnu, th, _t(w), _t(b), x, _t(uD) if len(xb) else None, tol=1e-12,
+                             maxiter=4000, restart=61)
         info = g.solve_momentum(mc, tnu, th, _t(w), _t(b), x, _t(uD) if len(xb) else None, tol=1e-12,
                                 maxiter=4000, restart=20)
         xs = x.cpu().numpy()
